@@ -1,0 +1,244 @@
+"""Benchmark of the EBIC fitness evaluation on one MI355X.
+
+One step = one evaluation of an 800-individual population (one EBIC
+generation's fitness pass) against the resident 436,444 x 64 methylation-
+shaped matrix: output initialisation and the evaluation kernel, counts left
+on the device. The matrix and the population are resident in HBM before the
+timed region starts.
+
+Prints ONE JSON line: the metric (nominal row-trend checks per second, a
+check being one (individual, row, column-of-that-individual) triple), the
+dominant kernel against its roofline, per-evaluation latency percentiles and
+the CPU oracle timed on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("row-trend checks/sec (pop×rows×cols) at 436,444 rows; % HBM peak; "
+          "p50/p99 eval latency")
+HBM_PEAK_GBS = 8000.0
+# v_cmp_*_f32 issue: 256 CUs x 64 lanes per clock x 2.4 GHz.
+CMP_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1807_09932_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(launch_units):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_eval_config3_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_sources_sha") != kernel_sources_sha():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, offs, cols, threads):
+    import oracle
+    rows = w.X.shape[0]
+    t0 = time.perf_counter()
+    oracle.eval_population(w.X, offs, cols, include=False, negative=True, masks=False,
+                           threads=threads)
+    dt = time.perf_counter() - t0
+    checks = rows * int(offs[-1])
+    return {"value": checks / dt, "unit": "checks/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole workload: {offs.size - 1} individuals x {rows} rows "
+                      f"({checks:.3e} nominal checks) in {dt:.2f} s",
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--rows", type=int, default=436444, help="(testing only) smaller matrix")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(row or population sharding across GPUs is described in DESIGN.md, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1807_09932_amd import ebic, gen
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    log("generating the methylation-shaped workload")
+    w, pop = gen.config3(rows=args.rows)
+    offs, cols = gen.csr(pop)
+    rows, ncols = w.X.shape
+    n = offs.size - 1
+    checks = gen.nominal_checks(rows, offs)
+
+    ctx = ebic.Context(0)
+    mat = ctx.upload(w.X)
+    p = ctx.population(offsets=offs, cols=cols)
+    out = ctx.outputs(mat, n, masks=False)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ctx.eval(mat, p, include=False, negative=True, masks=False, out=out)
+
+    # Spot check against the oracle on a sample of individuals.
+    import oracle
+    sample = np.arange(0, n, max(1, n // 16))
+    step()
+    torch.cuda.synchronize()
+    m_gpu = out[0].cpu().numpy()
+    g_gpu = out[1].cpu().numpy()
+    so, sc = gen.csr([cols[offs[i]:offs[i + 1]] for i in sample])
+    om, on, _, _ = oracle.eval_population(w.X, so, sc, negative=True,
+                                          threads=max(1, min(16, os.cpu_count() or 1)))
+    if not (np.array_equal(m_gpu[sample], om) and np.array_equal(g_gpu[sample], on)):
+        print("bench.py: GPU counts differ from the oracle", file=sys.stderr)
+        sys.exit(3)
+    log("spot check vs oracle: ok")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # Untimed: executed predicate steps (counting kernel variant).
+    ebic.ebic_set_profiling(ctx.handle, 2)
+    step()
+    _, _, executed_steps = ebic.ebic_read_profile(ctx.handle)
+    ebic.ebic_set_profiling(ctx.handle, 0)
+    log(f"executed steps per launch: {executed_steps}")
+
+    # Timed region: K steps; HIP events around the evaluation kernel (inside
+    # the library, on this stream) and around each whole step.
+    ebic.ebic_set_profiling(ctx.handle, 1)
+    ebic.ebic_read_profile(ctx.handle)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        step()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, kernel_ms, _ = ebic.ebic_read_profile(ctx.handle)
+    ebic.ebic_set_profiling(ctx.handle, 0)
+    step_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+
+    ms_per_step = wall * 1e3 / args.steps
+    value = checks / (wall / args.steps)
+    k_ms = kernel_ms / max(1, launches)
+    achieved = executed_steps * 64 * 2 / (k_ms * 1e-3) / 1e12
+
+    # End-to-end latency of one generation's evaluation as the host EA sees
+    # it: CSR to the device, evaluation, counts back to the host.
+    e2e = []
+    for i in range(min(50, args.steps)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pp = ctx.population(offsets=offs, cols=cols)
+        ctx.eval(mat, pp, include=False, negative=True, masks=False, out=out)
+        _ = out[0].cpu(), out[1].cpu()
+        e2e.append(time.perf_counter() - t1)
+    e2e = np.array(e2e) * 1e3
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "checks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "methylation-shaped plain eval: %d x %d FP32 Beta(0.5,0.5), 10 planted "
+                        "trend biclusters, %d individuals of 2-30 columns" % (rows, ncols, n),
+            "rows": rows, "cols": ncols, "population": n, "nominal_checks": checks,
+            "check": "one (individual, row, column of that individual) triple",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": CMP_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved / CMP_PEAK_TOPS,
+            "traffic": traffic_from_profile(1),
+            "kernel": "k_eval",
+            "kernel_ms": k_ms,
+            "ops": "FP32 compares executed: 2 per (column step, row), %d steps x 64 rows "
+                   "per launch (early exit at 64-row granularity)" % executed_steps,
+        },
+        "hbm_view": {
+            "effective_gbs": 4.0 * checks / (k_ms * 1e-3) / 1e9,
+            "effective_frac_of_peak": 4.0 * checks / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "note": "gather-equivalent: 4 B per nominal check; the staged kernel reads the "
+                    "matrix once, so this is not physical traffic",
+            "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9,
+        },
+        "latency_ms": {
+            "eval_p50": float(np.percentile(step_ms, 50)),
+            "eval_p99": float(np.percentile(step_ms, 99)),
+            "end_to_end_p50": float(np.percentile(e2e, 50)),
+            "end_to_end_p99": float(np.percentile(e2e, 99)),
+            "end_to_end": "CSR host->device, evaluation, counts device->host, synchronous",
+        },
+    }
+    ctx.release(mat)
+    ctx.close()
+
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
+        log(f"timing the CPU oracle with {threads} threads")
+        result["cpu_baseline"] = cpu_baseline(w, offs, cols, threads)
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * ebic.h -- C ABI of the EBIC fitness evaluation on MI355X (gfx950).
+ *
+ * EBIC (Orzechowski & Moore, "EBIC: an open source software for
+ * high-dimensional and big data biclustering analyses") is an evolutionary
+ * biclustering method whose search is driven by counting rows (Methods,
+ * "Handling missing values"). An individual of its population is an ordered
+ * list of column indices c_0 .. c_{k-1}. A row supports the individual when
+ * its values along that order stand in the greater-or-equal relation:
+ *
+ *   P(row) = AND_{j=1..k-1} X[row, c_j] >= X[row, c_{j-1}]   (positive trend)
+ *   N(row) = AND_{j=1..k-1} X[row, c_j] <= X[row, c_{j-1}]   (negative trend,
+ *                                                  only with EBIC_NEG_TRENDS)
+ *   matched  = #rows with P or N
+ *   negative = #rows with N and not P  (a row on both trends -- constant along
+ *                                       the individual -- counts as positive)
+ *
+ * Comparisons are IEEE-754 single precision, ordered, exact: -0 == +0,
+ * denormals are ordinary values, +-inf are ordinary values, NaN is missing.
+ *
+ * Missing values (Methods, "Handling missing values"), two modes:
+ *   EBIC_NAN_EXCLUDE: a row with a missing value in any of the individual's
+ *                     columns is not counted.
+ *   EBIC_NAN_INCLUDE: the legacy behaviour; a missing value takes the
+ *                     matrix's fill value and joins the ordinary comparison.
+ * A cell is missing when it is NaN, or, if a sentinel was given at upload,
+ * when it compares equal to that sentinel (the paper's "predefined value",
+ * e.g. 0 or 999).
+ *
+ * Rows: up to 2^31-1 per matrix on one GPU (Methods, "Support for Big
+ * Data"); there is no cap on the population size beyond int32.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an ebic_status (0 = EBIC_OK, < 0 = error) except
+ *     ebic_last_error and ebic_mask_words. On error, ebic_last_error() returns
+ *     a message (thread-local, valid until the calling thread's next call).
+ *     No C++ exception crosses this boundary.
+ *   - Host-checkable errors (NULL required pointer, unknown handle, bad
+ *     flags, bad sizes) return before anything is enqueued.
+ *   - `hip_stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Device pointers (d_*) are caller-owned device memory of the context's
+ *     device; they are borrowed until the work enqueued on `hip_stream`
+ *     completes.
+ *   - The context is thread-safe. Evaluations on different streams may run
+ *     concurrently; matrix upload and release are serialised internally.
+ */
+#ifndef EBIC_H
+#define EBIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ebic_ctx ebic_ctx;  /* opaque; one per HIP device */
+typedef int32_t ebic_status;
+
+enum {
+    EBIC_OK = 0,
+    EBIC_EINVAL = -1,   /* bad argument */
+    EBIC_ENOMEM = -2,   /* device or host allocation failed */
+    EBIC_EHIP = -3,     /* a HIP runtime call failed */
+    EBIC_ENOENT = -4,   /* unknown matrix handle */
+    EBIC_EBUSY = -5,    /* resource in use */
+    EBIC_EBUDGET = -6   /* request exceeds a memory budget */
+};
+
+/* Evaluation flags. */
+#define EBIC_NAN_EXCLUDE 0u   /* bit 0 clear: exclude rows with missing values */
+#define EBIC_NAN_INCLUDE 1u   /* bit 0 set: missing values take the fill value */
+#define EBIC_NEG_TRENDS 2u    /* also count rows on the reversed (<=) chain */
+
+/* Upload-only flags. */
+#define EBIC_SRC_DEVICE 4u       /* `src` is device memory (default: host) */
+#define EBIC_SRC_COL_MAJOR 8u    /* `src` is column-major (default: row-major) */
+#define EBIC_KEEP_FILL_COPY 16u  /* also keep a fill-substituted copy resident */
+
+/* Create a context on HIP device `hip_device`. *out receives the handle. */
+ebic_status ebic_create(int32_t hip_device, ebic_ctx **out);
+
+/* Wait for the device, free every resident matrix and the context. */
+ebic_status ebic_destroy(ebic_ctx *ctx);
+
+/*
+ * Route the library's device allocations (resident matrices, descriptor
+ * tables) through `alloc`/`release` (e.g. a framework's caching allocator).
+ * `alloc(bytes, user)` returns device memory of the context's device aligned
+ * to at least 256 bytes, or NULL. Pass NULLs to restore hipMalloc/hipFree.
+ * Only allowed while no matrix is resident (else EBIC_EBUSY).
+ */
+ebic_status ebic_set_allocator(ebic_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
+                               void (*release)(void *ptr, void *user), void *user);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *ebic_last_error(void);
+
+/*
+ * Make a matrix resident on the device (rows x cols, FP32).
+ *   src:      host (default) or device (EBIC_SRC_DEVICE) memory; row-major
+ *             with row stride ld_src >= cols (default) or column-major with
+ *             column stride ld_src >= rows (EBIC_SRC_COL_MAJOR), in elements.
+ *   rows:     1 .. 2^31-1.       cols: >= 1.
+ *   flags:    EBIC_SRC_DEVICE | EBIC_SRC_COL_MAJOR | EBIC_KEEP_FILL_COPY.
+ *   missing_sentinel: cells equal (IEEE ==) to it become missing; NaN = none.
+ *   missing_fill:     value a missing cell takes in EBIC_NAN_INCLUDE mode;
+ *                     must not be NaN.
+ *   out_matrix: receives a handle (>= 0).
+ * The resident copy is column-major with a leading dimension padded to a
+ * multiple of 64 rows (missing cells stored as NaN). Returns after the copy
+ * has completed on `hip_stream`.
+ */
+ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, int32_t cols,
+                               int64_t ld_src, uint32_t flags, float missing_sentinel,
+                               float missing_fill, void *hip_stream, int32_t *out_matrix);
+
+/* Shape and resident bytes of a matrix. Any output pointer may be NULL. */
+ebic_status ebic_matrix_info(ebic_ctx *ctx, int32_t matrix, int64_t *rows, int32_t *cols,
+                             int64_t *device_bytes);
+
+/* Free a resident matrix (waits for the device first). */
+ebic_status ebic_release_matrix(ebic_ctx *ctx, int32_t matrix);
+
+/* Number of uint64 mask words per individual: ceil(rows / 64). */
+int64_t ebic_mask_words(int64_t rows);
+
+/*
+ * Evaluate one population against a resident matrix (the fitness evaluation
+ * of one EBIC generation; Methods, "Handling missing values" and "Support
+ * for Big Data").
+ *   n_ind:     number of individuals (0 is a valid no-op).
+ *   d_offsets: int32[n_ind + 1], non-decreasing; individual i is
+ *              d_cols[d_offsets[i] .. d_offsets[i+1]).
+ *   d_cols:    int32[d_offsets[n_ind]] column indices.
+ *   flags:     EBIC_NAN_EXCLUDE or EBIC_NAN_INCLUDE, | EBIC_NEG_TRENDS.
+ *   d_matched:       int32[n_ind] (required).
+ *   d_negative:      int32[n_ind] or NULL.
+ *   d_matched_mask:  uint64[n_ind * ebic_mask_words(rows)] or NULL; bit
+ *                    (r % 64) of word (r / 64) of individual i's row is set
+ *                    when row r is matched. Bits past `rows` are 0.
+ *   d_negative_mask: same layout for the negative-trend rows, or NULL.
+ * Outputs are fully overwritten. An individual of length < 1 or with a
+ * column outside [0, cols) gets matched = negative = -1 and zero mask words;
+ * the call still returns EBIC_OK. Asynchronous on `hip_stream`.
+ */
+ebic_status ebic_eval_population(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
+                                 const int32_t *d_offsets, const int32_t *d_cols,
+                                 uint32_t flags, int32_t *d_matched, int32_t *d_negative,
+                                 uint64_t *d_matched_mask, uint64_t *d_negative_mask,
+                                 void *hip_stream);
+
+/* One population-evaluation request of a batch (same meaning as above). */
+typedef struct ebic_request {
+    int32_t matrix;
+    int32_t n_ind;
+    const int32_t *d_offsets;
+    const int32_t *d_cols;
+    uint32_t flags;
+    int32_t *d_matched;
+    int32_t *d_negative;
+    uint64_t *d_matched_mask;
+    uint64_t *d_negative_mask;
+} ebic_request;
+
+/*
+ * Evaluate many populations -- of uneven sizes, with individuals of uneven
+ * lengths, from many concurrent EBIC runs, over one or several resident
+ * matrices -- in one persistent launch replayed from a captured HIP graph.
+ * Each request's outputs equal those of ebic_eval_population on the same
+ * inputs. `reqs` is a host array of n_reqs entries (read before the call
+ * returns). Asynchronous on `hip_stream`.
+ */
+ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs,
+                            void *hip_stream);
+
+/*
+ * Time the candidate launch shapes on `sample` (a representative batch whose
+ * outputs are overwritten) and store the fastest for the sample's shape class
+ * in the context; if cache_path is not NULL, also merge it into that JSON
+ * file, which later contexts read at creation when EBIC_TUNE_CACHE names it.
+ * Synchronises the device.
+ */
+ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_reqs,
+                          const char *cache_path);
+
+/*
+ * Force the launch shape of later evaluations on this context (tests and
+ * tuning experiments); waves_per_block = 0 restores the automatic choice.
+ *   tiles_per_wave:        64-row tiles one wave evaluates together (1, 2, 4)
+ *   waves_per_block:       1 .. 16
+ *   individuals_per_group: individuals that share one block's staged tiles
+ *   staging:               0 = column tiles staged in LDS, 1 = direct reads
+ *   blocks:                grid size per group, 0 = from occupancy
+ * Shapes that do not fit the device are reduced at launch (fewer tiles per
+ * wave, then direct reads). Results never depend on the shape.
+ */
+ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t waves_per_block,
+                                  int32_t individuals_per_group, int32_t staging, int32_t blocks);
+
+/*
+ * Measurement diagnostics. `mode` bit 0: record a HIP event pair on the
+ * caller's stream around every evaluation kernel this context launches;
+ * bit 1: count executed predicate steps (one step = one column of one
+ * individual compared on one 64-row tile), using a counting variant of the
+ * kernel that is slower and meant for an untimed run. 0 turns both off.
+ */
+ebic_status ebic_set_profiling(ebic_ctx *ctx, int32_t mode);
+
+/*
+ * Synchronise the device, then report what was recorded since the previous
+ * read and reset it: evaluation kernels timed, their summed duration in
+ * milliseconds, and executed predicate steps. Any output may be NULL.
+ */
+ebic_status ebic_read_profile(ebic_ctx *ctx, int64_t *launches, double *kernel_ms,
+                              int64_t *executed_steps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBIC_H */

@@ -1,0 +1,445 @@
+// ebic_runtime.cpp -- the C ABI declared in include/ebic.h: contexts, the
+// resident-matrix registry, argument validation, launch planning and error
+// reporting. Kernels live in ebic_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/ebic.h"
+#include "ebic_internal.h"
+#include "ebic_runtime_internal.h"
+
+using namespace ebic;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+    ebic_status code;
+    Error(ebic_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(ebic_status code, const std::string &msg) { throw Error(code, msg); }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) fail(EBIC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Makes the context's device current for the duration of a call and
+// restores the caller's device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        hip_check(hipGetDevice(&prev), "hipGetDevice");
+        if (prev != dev) hip_check(hipSetDevice(dev), "hipSetDevice");
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename F>
+ebic_status guarded(F &&f)
+{
+    try {
+        g_last_error.clear();
+        f();
+        return EBIC_OK;
+    } catch (const Error &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return EBIC_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return EBIC_EINVAL;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return EBIC_EINVAL;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context helpers (also used by the batch and tuning code).
+// ---------------------------------------------------------------------------
+namespace ebic {
+
+void *ctx_alloc(ebic_ctx *ctx, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (ctx->alloc) {
+        p = ctx->alloc(bytes, ctx->alloc_user);
+        if (!p) fail(EBIC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {
+            if (ctx->release) ctx->release(p, ctx->alloc_user);
+            fail(EBIC_EINVAL, "allocator returned memory not aligned to 256 bytes");
+        }
+        return p;
+    }
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(EBIC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                              hipGetErrorString(e));
+    }
+    return p;
+}
+
+void ctx_free(ebic_ctx *ctx, void *p)
+{
+    if (!p) return;
+    if (ctx->alloc) {
+        if (ctx->release) ctx->release(p, ctx->alloc_user);
+        return;
+    }
+    (void)hipFree(p);
+}
+
+const Matrix &ctx_matrix(ebic_ctx *ctx, int32_t id)
+{
+    auto it = ctx->matrices.find(id);
+    if (it == ctx->matrices.end()) fail(EBIC_ENOENT, "unknown matrix handle " + std::to_string(id));
+    return it->second;
+}
+
+// Launch shape for one population on one matrix.
+LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint32_t flags)
+{
+    LaunchCfg cfg;
+    if (ctx->override_cfg.W > 0) cfg = ctx->override_cfg;
+    else cfg = tuned_cfg(ctx, m.dev.rows, m.dev.cols, n, nnz);
+    const size_t lds_max = ctx->lds_per_block;
+    cfg.P = std::max(1, std::min(cfg.P, std::max(1, n)));
+    // Fall back to fewer rows per wave, then to direct reads, until the shape fits.
+    while (cfg.staging == STAGE_LDS && cfg.L > 1 && eval_lds_bytes(cfg, m.dev.cols) > lds_max)
+        cfg.L /= 2;
+    if (cfg.staging == STAGE_LDS && eval_lds_bytes(cfg, m.dev.cols) > lds_max) cfg.staging = STAGE_DIRECT;
+    while (eval_lds_bytes(cfg, m.dev.cols) > lds_max && cfg.P > 64) cfg.P /= 2;
+    const int64_t n_tiles = (m.dev.rows + 63) / 64;
+    const int32_t groups = (n + cfg.P - 1) / cfg.P;
+    if (cfg.blocks <= 0) {
+        int occ = eval_occupancy(cfg, m.dev.cols, flags);
+        if (occ <= 0) occ = 1;
+        const int64_t slots = (int64_t)ctx->cu_count * occ;
+        int64_t bx = std::max<int64_t>(1, slots / std::max(1, groups));
+        bx = std::min<int64_t>(bx, (n_tiles + cfg.L - 1) / cfg.L);
+        cfg.blocks = (int32_t)std::max<int64_t>(1, bx);
+    }
+    cfg.blocks = (int32_t)std::min<int64_t>(cfg.blocks, std::max<int64_t>(1, n_tiles));
+    return cfg;
+}
+
+hipError_t ctx_launch_eval(ebic_ctx *ctx, EvalArgs a, const LaunchCfg &cfg, hipStream_t s)
+{
+    int32_t mode;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        mode = ctx->prof_mode;
+        if (mode & 2) a.step_counter = ctx->d_step_counter;
+    }
+    if (!(mode & 1)) return launch_eval(a, cfg, s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return e;
+    }
+    e = launch_eval(a, cfg, s, e0, e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return e;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->prof_events.emplace_back(e0, e1);
+    return hipSuccess;
+}
+
+}  // namespace ebic
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *ebic_last_error(void) { return g_last_error.c_str(); }
+
+int64_t ebic_mask_words(int64_t rows) { return rows <= 0 ? 0 : (rows + 63) / 64; }
+
+ebic_status ebic_create(int32_t hip_device, ebic_ctx **out)
+{
+    return guarded([&] {
+        if (!out) fail(EBIC_EINVAL, "out is NULL");
+        *out = nullptr;
+        int n = 0;
+        hip_check(hipGetDeviceCount(&n), "hipGetDeviceCount");
+        if (hip_device < 0 || hip_device >= n)
+            fail(EBIC_EINVAL, "device " + std::to_string(hip_device) + " out of range (" +
+                                  std::to_string(n) + " devices)");
+        DeviceGuard g(hip_device);
+        hipDeviceProp_t prop;
+        hip_check(hipGetDeviceProperties(&prop, hip_device), "hipGetDeviceProperties");
+        auto *ctx = new ebic_ctx();
+        ctx->device = hip_device;
+        ctx->cu_count = prop.multiProcessorCount;
+        ctx->lds_per_block = std::max<size_t>(prop.sharedMemPerBlock, 65536);
+        ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+        ctx->arch = prop.gcnArchName;
+        const char *cache = std::getenv("EBIC_TUNE_CACHE");
+        if (cache && *cache) load_tune_cache(ctx, cache);
+        *out = ctx;
+    });
+}
+
+ebic_status ebic_destroy(ebic_ctx *ctx)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        {
+            DeviceGuard g(ctx->device);
+            (void)hipDeviceSynchronize();
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            for (auto &kv : ctx->matrices) {
+                ctx_free(ctx, kv.second.X);
+                ctx_free(ctx, kv.second.Xfill);
+            }
+            ctx->matrices.clear();
+            destroy_batch_state(ctx);
+            for (auto &pr : ctx->prof_events) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+            ctx->prof_events.clear();
+            ctx_free(ctx, ctx->d_step_counter);
+            ctx->d_step_counter = nullptr;
+        }
+        delete ctx;
+    });
+}
+
+ebic_status ebic_set_allocator(ebic_ctx *ctx, void *(*alloc)(size_t, void *),
+                               void (*release)(void *, void *), void *user)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        if ((alloc == nullptr) != (release == nullptr))
+            fail(EBIC_EINVAL, "alloc and release must both be set or both be NULL");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!ctx->matrices.empty() || ctx->batch_state_allocated || ctx->d_step_counter)
+            fail(EBIC_EBUSY, "allocator can only change while nothing is resident");
+        ctx->alloc = alloc;
+        ctx->release = release;
+        ctx->alloc_user = user;
+    });
+}
+
+ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, int32_t cols,
+                               int64_t ld_src, uint32_t flags, float missing_sentinel,
+                               float missing_fill, void *hip_stream, int32_t *out_matrix)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        if (!src) fail(EBIC_EINVAL, "src is NULL");
+        if (!out_matrix) fail(EBIC_EINVAL, "out_matrix is NULL");
+        if (rows <= 0 || rows > INT32_MAX) fail(EBIC_EINVAL, "rows must be in 1 .. 2^31-1");
+        if (cols <= 0) fail(EBIC_EINVAL, "cols must be >= 1");
+        const uint32_t known = EBIC_SRC_DEVICE | EBIC_SRC_COL_MAJOR | EBIC_KEEP_FILL_COPY;
+        if (flags & ~known) fail(EBIC_EINVAL, "unknown upload flags");
+        if (std::isnan(missing_fill)) fail(EBIC_EINVAL, "missing_fill must not be NaN");
+        const bool col_major = flags & EBIC_SRC_COL_MAJOR;
+        if (col_major ? ld_src < rows : ld_src < cols)
+            fail(EBIC_EINVAL, "ld_src smaller than the source's inner dimension");
+        const bool on_device = flags & EBIC_SRC_DEVICE;
+        hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+
+        DeviceGuard g(ctx->device);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Matrix m;
+        m.dev.rows = rows;
+        m.dev.cols = cols;
+        m.dev.ld = (rows + 63) / 64 * 64;
+        m.dev.fill = missing_fill;
+        m.sentinel = missing_sentinel;
+        const size_t bytes = (size_t)m.dev.ld * cols * sizeof(float);
+        m.X = static_cast<float *>(ctx_alloc(ctx, bytes));
+        m.bytes = bytes;
+        float *staging = nullptr;
+        try {
+            if (flags & EBIC_KEEP_FILL_COPY) {
+                m.Xfill = static_cast<float *>(ctx_alloc(ctx, bytes));
+                m.bytes += bytes;
+            }
+            // Rows are laid out chunk by chunk through a bounded staging buffer.
+            const int64_t chunk_bytes = 64ll << 20;
+            int64_t chunk = std::max<int64_t>(64, chunk_bytes / ((int64_t)cols * 4) / 64 * 64);
+            chunk = std::min<int64_t>(chunk, (rows + 63) / 64 * 64);
+            if (!on_device) staging = static_cast<float *>(ctx_alloc(ctx, (size_t)chunk * cols * 4));
+            for (int64_t r0 = 0; r0 < rows; r0 += chunk) {
+                const int64_t nr = std::min<int64_t>(chunk, rows - r0);
+                const float *dsrc;
+                int64_t dld;
+                if (on_device) {
+                    dsrc = col_major ? src + r0 : src + r0 * ld_src;
+                    dld = ld_src;
+                } else if (!col_major) {
+                    hip_check(hipMemcpy2DAsync(staging, (size_t)cols * 4, src + r0 * ld_src,
+                                               (size_t)ld_src * 4, (size_t)cols * 4, (size_t)nr,
+                                               hipMemcpyHostToDevice, s),
+                              "hipMemcpy2DAsync");
+                    dsrc = staging;
+                    dld = cols;
+                } else {
+                    hip_check(hipMemcpy2DAsync(staging, (size_t)nr * 4, src + r0, (size_t)ld_src * 4,
+                                               (size_t)nr * 4, (size_t)cols, hipMemcpyHostToDevice, s),
+                              "hipMemcpy2DAsync");
+                    dsrc = staging;
+                    dld = nr;
+                }
+                hip_check(launch_layout(dsrc, dld, col_major, nr, cols, r0, m.X, m.dev.ld,
+                                        missing_sentinel, m.Xfill, missing_fill, s),
+                          "layout kernel");
+                // The staging buffer is reused by the next chunk.
+                if (!on_device) hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+            }
+            hip_check(launch_zero_pad(m.X, rows, m.dev.ld, cols, s), "zero-pad kernel");
+            if (m.Xfill) hip_check(launch_zero_pad(m.Xfill, rows, m.dev.ld, cols, s), "zero-pad kernel");
+            hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        } catch (...) {
+            ctx_free(ctx, staging);
+            ctx_free(ctx, m.X);
+            ctx_free(ctx, m.Xfill);
+            throw;
+        }
+        ctx_free(ctx, staging);
+        m.dev.X = m.X;
+        m.dev.Xfill = m.Xfill;
+        const int32_t id = ctx->next_matrix++;
+        ctx->matrices[id] = m;
+        *out_matrix = id;
+    });
+}
+
+ebic_status ebic_matrix_info(ebic_ctx *ctx, int32_t matrix, int64_t *rows, int32_t *cols,
+                             int64_t *device_bytes)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        const Matrix &m = ctx_matrix(ctx, matrix);
+        if (rows) *rows = m.dev.rows;
+        if (cols) *cols = m.dev.cols;
+        if (device_bytes) *device_bytes = (int64_t)m.bytes;
+    });
+}
+
+ebic_status ebic_release_matrix(ebic_ctx *ctx, int32_t matrix)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        DeviceGuard g(ctx->device);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Matrix m = ctx_matrix(ctx, matrix);
+        hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        ctx_free(ctx, m.X);
+        ctx_free(ctx, m.Xfill);
+        ctx->matrices.erase(matrix);
+    });
+}
+
+ebic_status ebic_eval_population(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
+                                 const int32_t *d_offsets, const int32_t *d_cols, uint32_t flags,
+                                 int32_t *d_matched, int32_t *d_negative,
+                                 uint64_t *d_matched_mask, uint64_t *d_negative_mask,
+                                 void *hip_stream)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        if (n_ind < 0) fail(EBIC_EINVAL, "n_ind < 0");
+        if (flags & ~(EBIC_NAN_INCLUDE | EBIC_NEG_TRENDS)) fail(EBIC_EINVAL, "unknown eval flags");
+        EvalArgs a;
+        LaunchCfg cfg;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            const Matrix &m = ctx_matrix(ctx, matrix);
+            if (n_ind == 0) return;
+            if (!d_offsets || !d_cols || !d_matched)
+                fail(EBIC_EINVAL, "d_offsets, d_cols and d_matched are required");
+            a.m = m.dev;
+            cfg = plan_eval(ctx, m, n_ind, -1, flags);
+        }
+        a.offsets = d_offsets;
+        a.cols = d_cols;
+        a.n = n_ind;
+        a.flags = flags;
+        a.matched = d_matched;
+        a.negative = d_negative;
+        a.mmask = d_matched_mask;
+        a.nmask = d_negative_mask;
+        DeviceGuard g(ctx->device);
+        hip_check(ctx_launch_eval(ctx, a, cfg, reinterpret_cast<hipStream_t>(hip_stream)),
+                  "evaluation launch");
+    });
+}
+
+ebic_status ebic_set_profiling(ebic_ctx *ctx, int32_t mode)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        if (mode & ~3) fail(EBIC_EINVAL, "unknown profiling mode");
+        DeviceGuard g(ctx->device);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if ((mode & 2) && !ctx->d_step_counter) {
+            ctx->d_step_counter = static_cast<unsigned long long *>(ctx_alloc(ctx, 256));
+            hip_check(hipMemset(ctx->d_step_counter, 0, sizeof(unsigned long long)), "hipMemset");
+        }
+        ctx->prof_mode = mode;
+    });
+}
+
+ebic_status ebic_read_profile(ebic_ctx *ctx, int64_t *launches, double *kernel_ms,
+                              int64_t *executed_steps)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        DeviceGuard g(ctx->device);
+        hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        double ms = 0;
+        for (auto &pr : ctx->prof_events) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) ms += t;
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        if (launches) *launches = (int64_t)ctx->prof_events.size();
+        if (kernel_ms) *kernel_ms = ms;
+        ctx->prof_events.clear();
+        unsigned long long steps = 0;
+        if (ctx->d_step_counter) {
+            hip_check(hipMemcpy(&steps, ctx->d_step_counter, sizeof(steps), hipMemcpyDeviceToHost),
+                      "hipMemcpy");
+            hip_check(hipMemset(ctx->d_step_counter, 0, sizeof(steps)), "hipMemset");
+        }
+        if (executed_steps) *executed_steps = (int64_t)steps;
+    });
+}
+
+}  // extern "C"

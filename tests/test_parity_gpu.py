@@ -1,0 +1,251 @@
+"""Parity of the HIP path with the CPU oracle, bit-exact (tolerance 0: the
+outputs are integers decided by exact FP32 compares), through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_1807_09932_amd import gen
+from tests.gpu_common import announce, assert_same, gpu_eval, oracle_eval
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1807_09932_amd.ebic import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _special(rng, shape, nan_frac=0.0):
+    alpha = np.array([-np.inf, -1.0, -0.0, 0.0, 1.4e-45, 2.8e-45, 1.0, 2.0, np.inf],
+                     dtype=np.float32)
+    X = alpha[rng.integers(0, alpha.size, size=shape)]
+    if nan_frac:
+        X[rng.random(shape) < nan_frac] = np.float32(np.nan)
+    return X
+
+
+def _random_pop(rng, ncols, n, kmax, dup=0.0, bad=0.0):
+    inds = []
+    for _ in range(n):
+        k = int(rng.integers(1, kmax + 1))
+        if rng.random() < dup:
+            ind = rng.integers(0, ncols, size=k)
+        else:
+            ind = rng.permutation(ncols)[:min(k, ncols)]
+        if rng.random() < bad:
+            ind = np.append(ind, ncols + int(rng.integers(0, 3)))
+        inds.append(np.asarray(ind, np.int32))
+    return gen.csr(inds)
+
+
+@pytest.mark.parametrize("include", [False, True])
+@pytest.mark.parametrize("negative", [False, True])
+def test_config1_plain(ctx, include, negative):
+    w, pop = gen.config1()
+    offs, cols = gen.csr(pop)
+    mat = ctx.upload(w.X)
+    announce("config1", include, negative)
+    got = gpu_eval(ctx, mat, offs, cols, include=include, negative=negative)
+    want = oracle_eval(w.X, offs, cols, include=include, negative=negative)
+    assert_same(got, want, "config1")
+    ctx.release(mat)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return gen.config2()
+
+
+@pytest.mark.parametrize("include,fill", [(False, 0.0), (True, 0.0), (True, 999.0)])
+def test_config2_missing_values(ctx, cfg2, include, fill):
+    w, pop = cfg2
+    offs, cols = gen.csr(pop)
+    mat = ctx.upload(w.X, fill=fill)
+    announce("config2", include, fill)
+    got = gpu_eval(ctx, mat, offs, cols, include=include)
+    want = oracle_eval(w.X, offs, cols, include=include, fill=fill)
+    assert_same(got, want, f"config2 include={include} fill={fill}")
+    ctx.release(mat)
+
+
+def test_config3_methylation_full(ctx):
+    """436,444 rows x 64 columns, 800 individuals: every count and every mask
+    word against the oracle, in the launch shape the benchmark uses."""
+    w, pop = gen.config3()
+    offs, cols = gen.csr(pop)
+    mat = ctx.upload(w.X)
+    announce("config3 full")
+    got = gpu_eval(ctx, mat, offs, cols, negative=True, masks=True)
+    want = oracle_eval(w.X, offs, cols, negative=True, masks=True)
+    assert_same(got, want, "config3")
+    # planted trends are recovered in full
+    mm = got[2]
+    for i, p in enumerate(w.plants):
+        bits = np.unpackbits(mm[i].view(np.uint8), bitorder="little")[: w.X.shape[0]]
+        assert bits[p.rows].all()
+    announce("config3 positive only")
+    got = gpu_eval(ctx, mat, offs, cols, negative=False, masks=False)
+    want = oracle_eval(w.X, offs, cols, negative=False, masks=False)
+    assert_same(got, want, "config3 pos")
+    ctx.release(mat)
+
+
+SHAPES = [  # tiles_per_wave, waves_per_block, individuals_per_group, staging, blocks
+    (1, 1, 1, 0, 0), (1, 4, 7, 0, 3), (2, 8, 64, 0, 0), (4, 16, 1000, 0, 0), (4, 3, 33, 0, 1),
+    (2, 5, 200, 0, 7), (1, 8, 1000, 1, 0), (2, 4, 13, 1, 2), (4, 8, 300, 1, 0), (4, 1, 5, 1, 0),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "L{}W{}P{}S{}B{}".format(*s))
+def test_launch_shapes_agree(ctx, shape):
+    rng = np.random.default_rng(101)
+    rows, ncols = 5000 + 37, 48
+    X = rng.integers(0, 6, size=(rows, ncols)).astype(np.float32)  # many ties
+    X[rng.random((rows, ncols)) < 0.03] = np.float32(np.nan)
+    offs, cols = _random_pop(rng, ncols, 301, 12, dup=0.05, bad=0.03)
+    mat = ctx.upload(X, fill=2.5)
+    try:
+        ctx.set_launch_shape(*shape)
+        for include in (False, True):
+            announce("shape", shape, include)
+            got = gpu_eval(ctx, mat, offs, cols, include=include)
+            want = oracle_eval(X, offs, cols, include=include, fill=2.5)
+            assert_same(got, want, f"shape {shape} include={include}")
+    finally:
+        ctx.set_launch_shape()
+        ctx.release(mat)
+
+
+@pytest.mark.parametrize("rows", [1, 2, 63, 64, 65, 127, 129, 255, 257, 4095])
+def test_edge_rows(ctx, rows):
+    rng = np.random.default_rng(200 + rows)
+    X = _special(rng, (rows, 9), nan_frac=0.05)
+    offs, cols = _random_pop(rng, 9, 60, 7, dup=0.1)
+    mat = ctx.upload(X, fill=-0.0)
+    for include in (False, True):
+        announce("rows", rows, include)
+        got = gpu_eval(ctx, mat, offs, cols, include=include)
+        want = oracle_eval(X, offs, cols, include=include, fill=-0.0)
+        assert_same(got, want, f"rows={rows}")
+    ctx.release(mat)
+
+
+@pytest.mark.parametrize("ncols", [1, 2, 3, 64, 65, 256, 310, 700])
+def test_edge_cols(ctx, ncols):
+    rng = np.random.default_rng(300 + ncols)
+    rows = 700
+    X = rng.standard_normal((rows, ncols)).astype(np.float32)
+    X[:, ::3] = np.round(X[:, ::3])  # ties
+    X[rng.random((rows, ncols)) < 0.02] = np.float32(np.nan)
+    offs, cols = _random_pop(rng, ncols, 120, min(ncols, 25), dup=0.05)
+    mat = ctx.upload(X, fill=0.0)
+    for include in (False, True):
+        announce("cols", ncols, include)
+        got = gpu_eval(ctx, mat, offs, cols, include=include)
+        want = oracle_eval(X, offs, cols, include=include)
+        assert_same(got, want, f"cols={ncols}")
+    ctx.release(mat)
+
+
+def test_invalid_and_degenerate_individuals(ctx):
+    rng = np.random.default_rng(400)
+    X = rng.standard_normal((1000, 10)).astype(np.float32)
+    inds = [[0, 1], [], [0, 10], [-1, 2], [3], [2, 2, 2], [9, 8, 7, 6, 5, 4, 3, 2, 1, 0],
+            [5, 5], [0], list(range(10)), [4, 11, 2]]
+    offs, cols = gen.csr(inds)
+    mat = ctx.upload(X)
+    announce("invalid individuals")
+    got = gpu_eval(ctx, mat, offs, cols)
+    want = oracle_eval(X, offs, cols)
+    assert_same(got, want, "invalid")
+    assert list(got[0][[1, 2, 3, 10]]) == [-1, -1, -1, -1]
+    assert not got[2][[1, 2, 3, 10]].any()
+    # a population with zero individuals is a no-op
+    import torch
+    from paper_1807_09932_amd.ebic import ebic_eval_population
+    ebic_eval_population(ctx.handle, mat, 0, 0, 0, 2, 0, None, None, None, 0)
+    torch.cuda.synchronize()
+    ctx.release(mat)
+
+
+def test_sentinel_and_fill_copy(ctx):
+    rng = np.random.default_rng(500)
+    X = rng.integers(-3, 4, size=(3000, 12)).astype(np.float32)
+    X[rng.random(X.shape) < 0.05] = np.float32(999.0)
+    X[rng.random(X.shape) < 0.02] = np.float32(np.nan)
+    X[rng.random(X.shape) < 0.02] = np.float32(-0.0)
+    offs, cols = _random_pop(rng, 12, 200, 8)
+    for sentinel in (999.0, 0.0):
+        for keep in (False, True):
+            mat = ctx.upload(X, sentinel=sentinel, fill=7.0, keep_fill_copy=keep)
+            for staging in (0, 1):
+                ctx.set_launch_shape(2, 4, 64, staging, 0)
+                for include in (False, True):
+                    announce("sentinel", sentinel, keep, staging, include)
+                    got = gpu_eval(ctx, mat, offs, cols, include=include)
+                    want = oracle_eval(X, offs, cols, include=include, sentinel=sentinel, fill=7.0)
+                    assert_same(got, want, f"sentinel={sentinel} keep={keep} staging={staging}")
+            ctx.set_launch_shape()
+            ctx.release(mat)
+
+
+def test_upload_layouts(ctx):
+    import torch
+    rng = np.random.default_rng(600)
+    base = rng.standard_normal((900, 40)).astype(np.float32)
+    X = base[:, 3:33]                       # row-major view with row stride 40
+    offs, cols = _random_pop(rng, 30, 80, 10)
+    want = oracle_eval(np.ascontiguousarray(X), offs, cols)
+    variants = {
+        "host_rowmajor_strided": torch.from_numpy(base)[:, 3:33],
+        "host_colmajor": torch.from_numpy(np.asfortranarray(X)).t().contiguous().t(),
+        "device_rowmajor": torch.from_numpy(np.ascontiguousarray(X)).cuda(),
+        "device_colmajor": torch.from_numpy(np.ascontiguousarray(X.T)).cuda().t(),
+    }
+    for name, src in variants.items():
+        mat = ctx.upload(src)
+        announce("upload", name)
+        got = gpu_eval(ctx, mat, offs, cols)
+        assert_same(got, want, name)
+        ctx.release(mat)
+
+
+def test_repeat_is_deterministic(ctx):
+    w, pop = gen.config1()
+    offs, cols = gen.csr(pop)
+    mat = ctx.upload(w.X)
+    announce("repeat")
+    a = gpu_eval(ctx, mat, offs, cols)
+    b = gpu_eval(ctx, mat, offs, cols)
+    assert_same(a, b, "repeat")
+    ctx.release(mat)
+
+
+def test_error_paths(ctx):
+    from paper_1807_09932_amd import ebic
+    X = np.ones((10, 3), np.float32)
+    with pytest.raises(ebic.EbicError) as e:
+        ctx.upload(X, fill=float("nan"))
+    assert e.value.status == ebic.EBIC_EINVAL
+    mat = ctx.upload(X)
+    pop = ctx.population([[0, 1]])
+    out = ctx.outputs(mat, 1)
+    with pytest.raises(ebic.EbicError) as e:
+        ebic.ebic_eval_population(ctx.handle, 12345, 1, pop.offsets.data_ptr(), pop.cols.data_ptr(),
+                                  0, out[0].data_ptr(), None, None, None, 0)
+    assert e.value.status == ebic.EBIC_ENOENT
+    with pytest.raises(ebic.EbicError) as e:
+        ebic.ebic_eval_population(ctx.handle, mat, 1, pop.offsets.data_ptr(), pop.cols.data_ptr(),
+                                  64, out[0].data_ptr(), None, None, None, 0)
+    assert e.value.status == ebic.EBIC_EINVAL
+    with pytest.raises(ebic.EbicError) as e:
+        ebic.ebic_eval_population(ctx.handle, mat, 1, 0, 0, 0, 0, None, None, None, 0)
+    assert e.value.status == ebic.EBIC_EINVAL
+    with pytest.raises(ValueError):
+        ctx.population(offsets=np.array([0, 5], np.int32), cols=np.array([1, 2], np.int32))
+    ctx.release(mat)
+    with pytest.raises(ebic.EbicError) as e:
+        ctx.release(mat)
+    assert e.value.status == ebic.EBIC_ENOENT
