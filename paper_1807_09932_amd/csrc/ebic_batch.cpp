@@ -1,7 +1,25 @@
-// ebic_batch.cpp -- ebic_eval_batch: many populations in one call.
+// ebic_batch.cpp -- ebic_eval_batch: many populations (of uneven sizes, with
+// individuals of uneven lengths, over one or several resident matrices) in
+// one persistent launch, replayed from a captured HIP graph.
+//
+// The host planner turns the requests into work items (individual group x
+// tile range), ordered largest first, and writes a batch arena (header,
+// request descriptors, prefix sums of individuals, items) into pinned host
+// memory. A graph captured once per (stream, launch shape, capacity)
+// copies the arena to the device, runs the prep kernel (validation, output
+// initialisation, individual headers, zeroing the work counter) and the
+// persistent evaluation kernel, whose blocks take items from the counter.
+// The arena's device address is fixed per graph, so one graph serves every
+// batch that fits its capacity; only the copy size is updated per replay.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ebic.h"
@@ -10,13 +28,257 @@
 
 namespace ebic {
 
-struct BatchState {};
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct ArenaLayout {
+    size_t hdr = 0, descs = 0, first = 0, items = 0, bytes = 0;
+    ArenaLayout(int32_t n_req, int32_t n_items)
+    {
+        hdr = 0;
+        descs = align256(sizeof(BatchHeader));
+        first = align256(descs + sizeof(ReqDesc) * (size_t)n_req);
+        items = align256(first + sizeof(int64_t) * (size_t)(n_req + 1));
+        bytes = align256(items + sizeof(Item) * (size_t)n_items);
+    }
+};
+
+// One captured graph with the buffers its nodes point at.
+struct GraphEntry {
+    int32_t cap_req = 0, cap_items = 0;
+    int64_t cap_ind = 0;
+    void *d_arena = nullptr;
+    IndHead *d_heads = nullptr;
+    void *h_arena[2] = {nullptr, nullptr};  // pinned, used alternately
+    hipEvent_t done[2] = {nullptr, nullptr};
+    int next = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy_node = nullptr;
+};
+
+using GraphKey = std::tuple<hipStream_t, int32_t, int32_t, int32_t, int64_t, int32_t, int32_t,
+                            int32_t, int64_t, bool>;
+
+void check(hipError_t e, const char *what) { hip_check(e, what); }
+
+}  // namespace
+
+struct BatchState {
+    hipStream_t capture = nullptr;
+    std::map<GraphKey, std::unique_ptr<GraphEntry>> graphs;
+};
+
+static void free_entry(ebic_ctx *ctx, GraphEntry *g)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (g->done[i]) {
+            (void)hipEventSynchronize(g->done[i]);
+            (void)hipEventDestroy(g->done[i]);
+        }
+        if (g->h_arena[i]) (void)hipHostFree(g->h_arena[i]);
+    }
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    ctx_free(ctx, g->d_arena);
+    ctx_free(ctx, g->d_heads);
+}
 
 void destroy_batch_state(ebic_ctx *ctx)
 {
+    if (!ctx->batch) return;
+    for (auto &kv : ctx->batch->graphs) free_entry(ctx, kv.second.get());
+    ctx->batch->graphs.clear();
+    if (ctx->batch->capture) (void)hipStreamDestroy(ctx->batch->capture);
     delete ctx->batch;
     ctx->batch = nullptr;
     ctx->batch_state_allocated = false;
+}
+
+// Launch shape of a batch: tuned if the context holds an entry for its
+// shape class, else a default.
+static LaunchCfg batch_cfg(ebic_ctx *ctx, int64_t total_ind, int64_t mean_rows, int32_t max_cols,
+                           int64_t nnz)
+{
+    if (ctx->override_cfg.W > 0) return ctx->override_cfg;
+    LaunchCfg c = tuned_batch_cfg(ctx, total_ind, mean_rows, max_cols, nnz);
+    return c;
+}
+
+struct Plan {
+    LaunchCfg cfg;
+    std::vector<ReqDesc> descs;
+    std::vector<int64_t> first;
+    std::vector<Item> items;
+    size_t tile_bytes = 0;
+    int64_t total_ind = 0;
+    int32_t grid = 0;
+};
+
+static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, bool count)
+{
+    Plan p;
+    p.first.push_back(0);
+    int64_t rows_sum = 0, nnz_hint = 0;
+    int32_t max_cols = 1;
+    int32_t live = 0;
+    for (int32_t q = 0; q < n_reqs; ++q) {
+        const ebic_request &r = reqs[q];
+        if (r.n_ind < 0) fail(EBIC_EINVAL, "request " + std::to_string(q) + ": n_ind < 0");
+        if (r.flags & ~(EBIC_NAN_INCLUDE | EBIC_NEG_TRENDS))
+            fail(EBIC_EINVAL, "request " + std::to_string(q) + ": unknown flags");
+        const Matrix &m = ctx_matrix(ctx, r.matrix);
+        if (r.n_ind > 0 && (!r.d_offsets || !r.d_cols || !r.d_matched))
+            fail(EBIC_EINVAL, "request " + std::to_string(q) +
+                                  ": d_offsets, d_cols and d_matched are required");
+        if (r.n_ind > 0) {
+            rows_sum += m.dev.rows;
+            max_cols = std::max(max_cols, m.dev.cols);
+            ++live;
+        }
+    }
+    (void)nnz_hint;
+    const int64_t mean_rows = live ? rows_sum / live : 1;
+    int64_t total = 0;
+    for (int32_t q = 0; q < n_reqs; ++q) total += std::max(0, reqs[q].n_ind);
+    p.cfg = batch_cfg(ctx, total, mean_rows, max_cols, -1);
+    LaunchCfg &c = p.cfg;
+    const size_t lds_max = ctx->lds_per_block - 256;  // room for the kernel's static LDS
+    if (c.L != 1 && c.L != 2 && c.L != 4) c.L = 2;
+    c.W = std::max(1, std::min(16, c.W));
+    c.P = std::max(1, c.P);
+
+    // Staging per request: LDS if the tile fits next to the counts.
+    for (int32_t q = 0; q < n_reqs; ++q) {
+        const ebic_request &r = reqs[q];
+        const Matrix &m = ctx_matrix(ctx, r.matrix);
+        int32_t staging = STAGE_LDS;
+        if (tile_lds_bytes(c.L, m.dev.cols) + count_lds_bytes(c.P) > lds_max) staging = STAGE_DIRECT;
+        ReqDesc d = make_desc(m, std::max(0, r.n_ind), r.d_offsets, r.d_cols, r.flags, r.d_matched,
+                              r.d_negative, r.d_matched_mask, r.d_negative_mask, staging);
+        d.head_base = p.first.back();
+        if (staging == STAGE_LDS) p.tile_bytes = std::max(p.tile_bytes, tile_lds_bytes(c.L, m.dev.cols));
+        p.descs.push_back(d);
+        p.first.push_back(p.first.back() + d.n);
+    }
+    p.total_ind = p.first.back();
+
+    const size_t lds = p.tile_bytes + count_lds_bytes(c.P);
+    int occ = batch_occupancy(c.L, c.W, lds);
+    if (occ <= 0) occ = 1;
+    p.grid = c.blocks > 0 ? c.blocks : ctx->cu_count * occ;
+
+    // Items: each request is cut into groups of <= P individuals and tile
+    // ranges so that the whole batch has about 8 items per resident block,
+    // in proportion to each request's work (individuals x tiles).
+    double units = 0;
+    for (auto &d : p.descs) units += (double)d.n * (double)((d.rows + 63) / 64);
+    const double target = 8.0 * p.grid;
+    struct Est {
+        Item it;
+        double cost;
+    };
+    std::vector<Est> est;
+    for (int32_t q = 0; q < n_reqs; ++q) {
+        const ReqDesc &d = p.descs[q];
+        if (d.n == 0) continue;
+        const int64_t tiles = (d.rows + 63) / 64;
+        const int32_t groups = (d.n + c.P - 1) / c.P;
+        const double share = units > 0 ? target * (double)d.n * (double)tiles / units : 1.0;
+        int64_t ranges = (int64_t)std::max(1.0, share / groups + 0.5);
+        ranges = std::min<int64_t>(ranges, std::max<int64_t>(1, tiles / c.L));
+        for (int32_t g = 0; g < groups; ++g) {
+            const int32_t i0 = g * c.P;
+            const int32_t np = std::min(c.P, d.n - i0);
+            for (int64_t r = 0; r < ranges; ++r) {
+                Item it{};
+                it.req = q;
+                it.i0 = i0;
+                it.np = np;
+                it.t0 = (int32_t)(r * tiles / ranges);
+                it.t1 = (int32_t)((r + 1) * tiles / ranges);
+                if (it.t1 <= it.t0) continue;
+                est.push_back({it, (double)np * (double)(it.t1 - it.t0)});
+            }
+        }
+    }
+    std::stable_sort(est.begin(), est.end(), [](const Est &a, const Est &b) { return a.cost > b.cost; });
+    p.items.reserve(est.size());
+    for (auto &e : est) p.items.push_back(e.it);
+    (void)count;
+    return p;
+}
+
+static GraphEntry *get_graph(ebic_ctx *ctx, hipStream_t s, const Plan &p, bool count)
+{
+    if (!ctx->batch) {
+        ctx->batch = new BatchState();
+        ctx->batch_state_allocated = true;
+        check(hipStreamCreateWithFlags(&ctx->batch->capture, hipStreamNonBlocking), "hipStreamCreate");
+    }
+    // Capacities rounded up to powers of two so that nearby batch sizes share a graph.
+    auto pow2 = [](int64_t x) {
+        int64_t v = 1;
+        while (v < x) v <<= 1;
+        return v;
+    };
+    const int32_t cap_req = (int32_t)pow2(std::max<int64_t>(8, (int64_t)p.descs.size()));
+    const int32_t cap_items = (int32_t)pow2(std::max<int64_t>(64, (int64_t)p.items.size()));
+    const int64_t cap_ind = pow2(std::max<int64_t>(1024, p.total_ind));
+    GraphKey key{s, p.cfg.L, p.cfg.W, p.cfg.P, (int64_t)p.tile_bytes, p.grid, cap_req, cap_items,
+                 cap_ind, count};
+    auto it = ctx->batch->graphs.find(key);
+    if (it != ctx->batch->graphs.end()) return it->second.get();
+
+    auto g = std::make_unique<GraphEntry>();
+    g->cap_req = cap_req;
+    g->cap_items = cap_items;
+    g->cap_ind = cap_ind;
+    const ArenaLayout lay(cap_req, cap_items);
+    try {
+        g->d_arena = ctx_alloc(ctx, lay.bytes);
+        g->d_heads = static_cast<IndHead *>(ctx_alloc(ctx, (size_t)cap_ind * sizeof(IndHead)));
+        for (int i = 0; i < 2; ++i) {
+            check(hipHostMalloc(&g->h_arena[i], lay.bytes, hipHostMallocDefault), "hipHostMalloc");
+            std::memset(g->h_arena[i], 0, lay.bytes);
+            check(hipEventCreateWithFlags(&g->done[i], hipEventDisableTiming), "hipEventCreate");
+        }
+        char *da = static_cast<char *>(g->d_arena);
+        const int prep_blocks = std::max(1, ctx->cu_count * 2);
+        unsigned long long *counter = count ? ctx->d_step_counter : nullptr;
+        hipStream_t cs = ctx->batch->capture;
+        check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        hipError_t e = hipMemcpyAsync(da, g->h_arena[0], lay.bytes, hipMemcpyHostToDevice, cs);
+        if (e == hipSuccess)
+            e = launch_batch(reinterpret_cast<BatchHeader *>(da + lay.hdr),
+                             reinterpret_cast<const ReqDesc *>(da + lay.descs),
+                             reinterpret_cast<const int64_t *>(da + lay.first),
+                             reinterpret_cast<const Item *>(da + lay.items), g->d_heads, p.cfg.L,
+                             p.cfg.W, p.cfg.P, p.tile_bytes, p.grid, prep_blocks, counter, cs);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        check(e, "batch capture");
+        check(e2, "hipStreamEndCapture");
+        g->graph = graph;
+        check(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        size_t nn = 0;
+        check(hipGraphGetNodes(graph, nullptr, &nn), "hipGraphGetNodes");
+        std::vector<hipGraphNode_t> nodes(nn);
+        check(hipGraphGetNodes(graph, nodes.data(), &nn), "hipGraphGetNodes");
+        for (auto n : nodes) {
+            hipGraphNodeType t;
+            check(hipGraphNodeGetType(n, &t), "hipGraphNodeGetType");
+            if (t == hipGraphNodeTypeMemcpy) g->copy_node = n;
+        }
+        if (!g->copy_node) fail(EBIC_EHIP, "captured batch graph has no copy node");
+    } catch (...) {
+        free_entry(ctx, g.get());
+        throw;
+    }
+    GraphEntry *raw = g.get();
+    ctx->batch->graphs.emplace(key, std::move(g));
+    return raw;
 }
 
 }  // namespace ebic
@@ -26,13 +288,57 @@ using namespace ebic;
 extern "C" ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs,
                                        void *hip_stream)
 {
-    if (!ctx || n_reqs < 0 || (n_reqs > 0 && !reqs)) return EBIC_EINVAL;
-    for (int32_t q = 0; q < n_reqs; ++q) {
-        const ebic_request &r = reqs[q];
-        ebic_status st = ebic_eval_population(ctx, r.matrix, r.n_ind, r.d_offsets, r.d_cols, r.flags,
-                                              r.d_matched, r.d_negative, r.d_matched_mask,
-                                              r.d_negative_mask, hip_stream);
-        if (st != EBIC_OK) return st;
-    }
-    return EBIC_OK;
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        if (n_reqs < 0 || (n_reqs > 0 && !reqs)) fail(EBIC_EINVAL, "bad request array");
+        if (n_reqs == 0) return;
+        hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+        DeviceGuard dg(ctx->device);
+        std::lock_guard<std::mutex> lk(ctx->batch_mu);
+        Plan p;
+        int32_t prof_mode;
+        {
+            std::lock_guard<std::mutex> lk2(ctx->mu);
+            p = plan_batch(ctx, reqs, n_reqs, false);
+            prof_mode = ctx->prof_mode;
+        }
+        if (p.items.empty()) return;  // every population is empty
+        const bool count = (prof_mode & 2) != 0;
+        GraphEntry *g;
+        {
+            std::lock_guard<std::mutex> lk2(ctx->mu);
+            g = get_graph(ctx, s, p, count);
+        }
+        const int slot = g->next;
+        g->next ^= 1;
+        // This slot's pinned buffer was last read by the launch two calls ago.
+        check(hipEventSynchronize(g->done[slot]), "hipEventSynchronize");
+        const ArenaLayout cap(g->cap_req, g->cap_items);
+        char *h = static_cast<char *>(g->h_arena[slot]);
+        BatchHeader bh{};
+        bh.n_req = (int32_t)p.descs.size();
+        bh.n_items = (int32_t)p.items.size();
+        bh.total_ind = p.total_ind;
+        std::memcpy(h + cap.hdr, &bh, sizeof(bh));
+        std::memcpy(h + cap.descs, p.descs.data(), sizeof(ReqDesc) * p.descs.size());
+        std::memcpy(h + cap.first, p.first.data(), sizeof(int64_t) * p.first.size());
+        std::memcpy(h + cap.items, p.items.data(), sizeof(Item) * p.items.size());
+        const size_t used = cap.items + sizeof(Item) * p.items.size();
+        check(hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy_node, g->d_arena, h, used,
+                                                hipMemcpyHostToDevice),
+              "hipGraphExecMemcpyNodeSetParams1D");
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (prof_mode & 1) {
+            check(hipEventCreate(&e0), "hipEventCreate");
+            check(hipEventCreate(&e1), "hipEventCreate");
+            check(hipEventRecord(e0, s), "hipEventRecord");
+        }
+        check(hipGraphLaunch(g->exec, s), "hipGraphLaunch");
+        if (prof_mode & 1) {
+            check(hipEventRecord(e1, s), "hipEventRecord");
+            std::lock_guard<std::mutex> lk2(ctx->mu);
+            ctx->prof_events.emplace_back(e0, e1);
+        }
+        check(hipEventRecord(g->done[slot], s), "hipEventRecord");
+    });
 }

@@ -1,5 +1,6 @@
-// ebic_internal.h -- declarations shared by the runtime (ebic_runtime.cpp)
-// and the kernels (ebic_kernels.hip). Not part of the public ABI.
+// ebic_internal.h -- declarations shared by the runtime (ebic_runtime.cpp,
+// ebic_batch.cpp, ebic_tune.cpp) and the kernels (ebic_eval.hip,
+// ebic_layout.hip). Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,11 +8,21 @@
 
 namespace ebic {
 
+constexpr int kWave = 64;  // gfx950 wavefront
+constexpr int kWin = 8;    // leading columns of an individual kept in its header
+
 // How the column tile of a work item reaches the predicate.
 enum Staging : int32_t {
     STAGE_LDS = 0,     // rows x all columns staged into LDS, shared by the block
     STAGE_DIRECT = 1,  // read straight from the column-major matrix (L1/L2)
 };
+
+// Request flags as the kernels see them (the low two bits are the ABI's
+// EBIC_NAN_INCLUDE and EBIC_NEG_TRENDS).
+constexpr uint32_t kFlagInclude = 1u;
+constexpr uint32_t kFlagNeg = 2u;
+constexpr uint32_t kFlagDirect = 1u << 8;  // this request reads the matrix directly
+constexpr uint32_t kFlagSubst = 1u << 9;   // direct reads replace NaN by the fill value
 
 // One launch shape of the evaluation kernels.
 struct LaunchCfg {
@@ -19,12 +30,12 @@ struct LaunchCfg {
     int32_t W = 0;        // waves per block (1..16)
     int32_t P = 0;        // individuals per group (max individuals sharing a block)
     int32_t staging = STAGE_LDS;
-    int32_t blocks = 0;   // grid size (x); 0 = derive from occupancy
+    int32_t blocks = 0;   // plain: tile ranges per group; batch: persistent grid; 0 = derive
 };
 
 // A resident matrix as the kernels see it.
 struct DevMatrix {
-    const float *X = nullptr;      // column-major, leading dimension ld
+    const float *X = nullptr;      // column-major, leading dimension ld, missing = NaN
     const float *Xfill = nullptr;  // fill-substituted copy, or null
     int64_t ld = 0;                // multiple of 64
     int64_t rows = 0;
@@ -32,40 +43,88 @@ struct DevMatrix {
     float fill = 0.f;
 };
 
-// Arguments of one population evaluation.
-struct EvalArgs {
-    DevMatrix m;
-    const int32_t *offsets = nullptr;
-    const int32_t *cols = nullptr;
-    int32_t n = 0;
-    uint32_t flags = 0;
-    int32_t *matched = nullptr;
-    int32_t *negative = nullptr;
-    uint64_t *mmask = nullptr;
-    uint64_t *nmask = nullptr;
-    // Diagnostics: when not null, every wave adds the number of (column,
-    // 64-row sub-tile) predicate steps it executed (selects a counting
-    // variant of the kernel).
-    unsigned long long *step_counter = nullptr;
+// One population evaluation as the kernels read it.
+struct ReqDesc {
+    const float *X;            // the matrix to read (the fill copy when it serves include mode)
+    int64_t ld;
+    int64_t rows;
+    int32_t cols;
+    float fill;
+    uint32_t flags;            // kFlag*
+    int32_t n;                 // individuals
+    const int32_t *offsets;    // CSR, n + 1 entries
+    const int32_t *colidx;
+    int32_t *matched;
+    int32_t *negative;         // may be null
+    uint64_t *mmask;           // may be null
+    uint64_t *nmask;           // may be null
+    int64_t head_base;         // first row of this request in the header table
 };
 
-// Bytes of dynamic LDS a launch shape needs.
-size_t eval_lds_bytes(const LaunchCfg &cfg, int32_t cols);
+// Per-individual header written by the prep kernel (64 bytes, one scalar
+// load): k = length (0 for an invalid individual), the CSR start of its
+// columns, and its first kWin columns (clamped to the last one).
+struct IndHead {
+    int32_t k;
+    int32_t begin;
+    int32_t pad[6];
+    int32_t win[kWin];
+};
+static_assert(sizeof(IndHead) == 64, "IndHead is one 64-byte scalar load");
 
-// Blocks per CU the evaluation kernel reaches with this shape (0 = cannot run).
+// A work item of the batched kernel: individuals [i0, i0 + np) of request
+// `req`, on 64-row tiles [t0, t1).
+struct Item {
+    int32_t req;
+    int32_t i0;
+    int32_t np;
+    int32_t t0;
+    int32_t t1;
+    int32_t pad[3];
+};
+static_assert(sizeof(Item) == 32, "Item is 32 bytes");
+
+// Device-side header of a batch: counts and the dynamic work counter.
+struct BatchHeader {
+    int32_t n_req;
+    int32_t n_items;
+    int64_t total_ind;     // individuals over all requests
+    uint32_t counter;      // next item to take (zeroed by the prep kernel)
+    uint32_t pad[3];
+};
+
+// Bytes of dynamic LDS one work item needs: the staged tile (if staged) and
+// the per-individual counts of a group of P.
+size_t tile_lds_bytes(int32_t L, int32_t cols);
+size_t count_lds_bytes(int32_t P);
+
+// Blocks per CU the plain evaluation kernel reaches with this shape (0 = cannot run).
 int eval_occupancy(const LaunchCfg &cfg, int32_t cols, uint32_t flags);
+int batch_occupancy(int32_t L, int32_t W, size_t lds_bytes);
 
-// Enqueue: validation/zeroing of the outputs, then the evaluation kernel.
-// If ev0/ev1 are not null they are recorded on `s` right before and right
-// after the evaluation kernel.
-hipError_t launch_eval(const EvalArgs &a, const LaunchCfg &cfg, hipStream_t s,
+// Plain evaluation: prep (validation, output initialisation, headers) then
+// the evaluation kernel over G groups x cfg.blocks tile ranges. ev0/ev1, if
+// not null, are recorded right before and after the evaluation kernel.
+hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
+                       unsigned long long *step_counter, hipStream_t s,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
-// Enqueue the layout kernel: src (device, row-major with row stride ld_src,
-// or column-major with column stride ld_src) -> dst column-major with
-// leading dimension ld; rows [r0, r0 + nr) of the matrix; cells equal to the
-// sentinel become NaN; if dst_fill is not null it receives the same values
-// with every missing cell replaced by `fill`.
+// Batched evaluation over a device-resident batch arena:
+//   hdr (BatchHeader) | descs (ReqDesc[n_req]) | first (int64[n_req + 1],
+//   prefix sums of individuals) | items (Item[n_items])
+// prep_blocks x 256 threads validate every individual of every request;
+// then `grid` persistent blocks of W waves take items from the counter.
+hipError_t launch_batch(BatchHeader *hdr, const ReqDesc *descs, const int64_t *first,
+                        const Item *items, IndHead *heads, int32_t L, int32_t W, int32_t P,
+                        size_t tile_bytes, int32_t grid, int32_t prep_blocks,
+                        unsigned long long *step_counter, hipStream_t s,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// Layout kernel: src (device, row-major with row stride ld_src, or
+// column-major with column stride ld_src), rows [r0, r0 + nr) of the matrix
+// -> dst column-major with leading dimension ld; cells equal to the sentinel
+// become NaN; if dst_fill is not null it receives the same values with every
+// missing cell replaced by `fill`.
 hipError_t launch_layout(const float *src, int64_t ld_src, bool src_col_major, int64_t nr,
                          int32_t cols, int64_t r0, float *dst, int64_t ld, float sentinel,
                          float *dst_fill, float fill, hipStream_t s);

@@ -1,0 +1,93 @@
+// ebic_layout.hip -- upload kernels: the resident matrix layout.
+//
+// The matrix is kept column-major (one column of 64 consecutive rows is one
+// coalesced 256-byte segment for a wave) with a leading dimension padded to
+// a multiple of 64 rows; padding rows hold 0. Missing cells are stored as
+// NaN: the paper lets the user mark missing values with a predefined value
+// (Methods, "Handling missing values"), so cells equal to that sentinel are
+// converted here. An optional second copy holds the fill value in place of
+// every missing cell, for the mode in which missing values take part in the
+// comparison.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ebic_internal.h"
+
+namespace ebic {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Layout: 64x64 tiles through LDS. Row-major source -> column-major
+// destination with coalesced reads (along a source row) and coalesced writes
+// (along a destination column). Sentinel cells become NaN.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_layout(const float *__restrict__ src, int64_t ld_src, int32_t src_col_major, int64_t nr,
+         int32_t cols, int64_t r0, float *__restrict__ dst, int64_t ld, float sentinel,
+         float *__restrict__ dst_fill, float fill)
+{
+    __shared__ float t[64][65];
+    const int64_t rb = (int64_t)blockIdx.x * 64;  // first source row of the tile
+    const int32_t cb = blockIdx.y * 64;            // first column of the tile
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+    if (!src_col_major) {
+        for (int y = ty; y < 64; y += 4) {
+            const int64_t r = rb + y;
+            const int32_t c = cb + tx;
+            t[y][tx] = (r < nr && c < cols) ? src[r * ld_src + c] : 0.f;
+        }
+    } else {
+        for (int y = ty; y < 64; y += 4) {
+            const int64_t r = rb + tx;
+            const int32_t c = cb + y;
+            t[tx][y] = (r < nr && c < cols) ? src[(int64_t)c * ld_src + r] : 0.f;
+        }
+    }
+    __syncthreads();
+    for (int y = ty; y < 64; y += 4) {
+        const int32_t c = cb + y;
+        const int64_t r = rb + tx;
+        if (c < cols && r < nr) {
+            float v = t[tx][y];
+            const bool missing = v != v || v == sentinel;
+            if (missing) v = __builtin_nanf("");
+            dst[(int64_t)c * ld + r0 + r] = v;
+            if (dst_fill) dst_fill[(int64_t)c * ld + r0 + r] = missing ? fill : v;
+        }
+    }
+}
+
+__global__ void k_zero_pad(float *__restrict__ dst, int64_t rows, int64_t ld, int32_t cols)
+{
+    const int64_t pad = ld - rows;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= pad * cols) return;
+    const int64_t c = idx / pad, r = rows + idx % pad;
+    dst[c * ld + r] = 0.f;
+}
+
+}  // namespace
+
+hipError_t launch_layout(const float *src, int64_t ld_src, bool src_col_major, int64_t nr,
+                         int32_t cols, int64_t r0, float *dst, int64_t ld, float sentinel,
+                         float *dst_fill, float fill, hipStream_t s)
+{
+    if (nr <= 0) return hipSuccess;
+    dim3 grid((unsigned)((nr + 63) / 64), (unsigned)((cols + 63) / 64));
+    hipLaunchKernelGGL(k_layout, grid, dim3(256), 0, s, src, ld_src, (int32_t)src_col_major, nr,
+                       cols, r0, dst, ld, sentinel, dst_fill, fill);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_pad(float *dst, int64_t rows, int64_t ld, int32_t cols, hipStream_t s)
+{
+    const int64_t total = (ld - rows) * cols;
+    if (total <= 0) return hipSuccess;
+    const int threads = 256;
+    hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads),
+                       0, s, dst, rows, ld, cols);
+    return hipGetLastError();
+}
+
+}  // namespace ebic

@@ -20,60 +20,12 @@
 using namespace ebic;
 
 namespace {
-
 thread_local std::string g_last_error;
-
-struct Error : std::runtime_error {
-    ebic_status code;
-    Error(ebic_status c, const std::string &m) : std::runtime_error(m), code(c) {}
-};
-
-[[noreturn]] void fail(ebic_status code, const std::string &msg) { throw Error(code, msg); }
-
-void hip_check(hipError_t e, const char *what)
-{
-    if (e != hipSuccess) fail(EBIC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-// Makes the context's device current for the duration of a call and
-// restores the caller's device afterwards.
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        hip_check(hipGetDevice(&prev), "hipGetDevice");
-        if (prev != dev) hip_check(hipSetDevice(dev), "hipSetDevice");
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-template <typename F>
-ebic_status guarded(F &&f)
-{
-    try {
-        g_last_error.clear();
-        f();
-        return EBIC_OK;
-    } catch (const Error &e) {
-        g_last_error = e.what();
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        g_last_error = "host allocation failed";
-        return EBIC_ENOMEM;
-    } catch (const std::exception &e) {
-        g_last_error = e.what();
-        return EBIC_EINVAL;
-    } catch (...) {
-        g_last_error = "unknown error";
-        return EBIC_EINVAL;
-    }
-}
-
 }  // namespace
+
+namespace ebic {
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace ebic
 
 // ---------------------------------------------------------------------------
 // Context helpers (also used by the batch and tuning code).
@@ -127,11 +79,13 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
     else cfg = tuned_cfg(ctx, m.dev.rows, m.dev.cols, n, nnz);
     const size_t lds_max = ctx->lds_per_block;
     cfg.P = std::max(1, std::min(cfg.P, std::max(1, n)));
+    auto lds = [&](const LaunchCfg &c) {
+        return (c.staging == STAGE_LDS ? tile_lds_bytes(c.L, m.dev.cols) : 0) + count_lds_bytes(c.P);
+    };
     // Fall back to fewer rows per wave, then to direct reads, until the shape fits.
-    while (cfg.staging == STAGE_LDS && cfg.L > 1 && eval_lds_bytes(cfg, m.dev.cols) > lds_max)
-        cfg.L /= 2;
-    if (cfg.staging == STAGE_LDS && eval_lds_bytes(cfg, m.dev.cols) > lds_max) cfg.staging = STAGE_DIRECT;
-    while (eval_lds_bytes(cfg, m.dev.cols) > lds_max && cfg.P > 64) cfg.P /= 2;
+    while (cfg.staging == STAGE_LDS && cfg.L > 1 && lds(cfg) > lds_max) cfg.L /= 2;
+    if (cfg.staging == STAGE_LDS && lds(cfg) > lds_max) cfg.staging = STAGE_DIRECT;
+    while (lds(cfg) > lds_max && cfg.P > 64) cfg.P /= 2;
     const int64_t n_tiles = (m.dev.rows + 63) / 64;
     const int32_t groups = (n + cfg.P - 1) / cfg.P;
     if (cfg.blocks <= 0) {
@@ -146,15 +100,66 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
     return cfg;
 }
 
-hipError_t ctx_launch_eval(ebic_ctx *ctx, EvalArgs a, const LaunchCfg &cfg, hipStream_t s)
+ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int32_t *cols,
+                  uint32_t flags, int32_t *matched, int32_t *negative, uint64_t *mmask,
+                  uint64_t *nmask, int32_t staging)
+{
+    ReqDesc d{};
+    const bool include = (flags & EBIC_NAN_INCLUDE) != 0;
+    d.X = m.dev.X;
+    d.flags = flags & (kFlagInclude | kFlagNeg);
+    if (staging == STAGE_DIRECT) {
+        d.flags |= kFlagDirect;
+        if (include) {
+            if (m.dev.Xfill) d.X = m.dev.Xfill;
+            else d.flags |= kFlagSubst;
+        }
+    }
+    d.ld = m.dev.ld;
+    d.rows = m.dev.rows;
+    d.cols = m.dev.cols;
+    d.fill = m.dev.fill;
+    d.n = n;
+    d.offsets = offsets;
+    d.colidx = cols;
+    d.matched = matched;
+    d.negative = negative;
+    d.mmask = mmask;
+    d.nmask = nmask;
+    d.head_base = 0;
+    return d;
+}
+
+void *stream_scratch(ebic_ctx *ctx, hipStream_t s, size_t bytes)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scratch &sc = ctx->scratch[s];
+    if (sc.bytes >= bytes && sc.ptr) return sc.ptr;
+    size_t want = std::max<size_t>(bytes, 64 << 10);
+    want = std::max(want, sc.bytes * 2);
+    if (sc.ptr) {
+        // Work already enqueued on this stream may still read the old buffer.
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        ctx_free(ctx, sc.ptr);
+        sc.ptr = nullptr;
+        sc.bytes = 0;
+    }
+    sc.ptr = ctx_alloc(ctx, want);
+    sc.bytes = want;
+    return sc.ptr;
+}
+
+hipError_t ctx_launch_eval(ebic_ctx *ctx, const ReqDesc &d, const LaunchCfg &cfg, hipStream_t s)
 {
     int32_t mode;
+    unsigned long long *counter = nullptr;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         mode = ctx->prof_mode;
-        if (mode & 2) a.step_counter = ctx->d_step_counter;
+        if (mode & 2) counter = ctx->d_step_counter;
     }
-    if (!(mode & 1)) return launch_eval(a, cfg, s);
+    IndHead *heads = static_cast<IndHead *>(stream_scratch(ctx, s, (size_t)d.n * sizeof(IndHead)));
+    if (!(mode & 1)) return launch_eval(d, heads, cfg, counter, s);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e != hipSuccess) return e;
@@ -162,7 +167,7 @@ hipError_t ctx_launch_eval(ebic_ctx *ctx, EvalArgs a, const LaunchCfg &cfg, hipS
         (void)hipEventDestroy(e0);
         return e;
     }
-    e = launch_eval(a, cfg, s, e0, e1);
+    e = launch_eval(d, heads, cfg, counter, s, e0, e1);
     if (e != hipSuccess) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -230,6 +235,8 @@ ebic_status ebic_destroy(ebic_ctx *ctx)
             ctx->prof_events.clear();
             ctx_free(ctx, ctx->d_step_counter);
             ctx->d_step_counter = nullptr;
+            for (auto &kv : ctx->scratch) ctx_free(ctx, kv.second.ptr);
+            ctx->scratch.clear();
         }
         delete ctx;
     });
@@ -243,7 +250,8 @@ ebic_status ebic_set_allocator(ebic_ctx *ctx, void *(*alloc)(size_t, void *),
         if ((alloc == nullptr) != (release == nullptr))
             fail(EBIC_EINVAL, "alloc and release must both be set or both be NULL");
         std::lock_guard<std::mutex> lk(ctx->mu);
-        if (!ctx->matrices.empty() || ctx->batch_state_allocated || ctx->d_step_counter)
+        if (!ctx->matrices.empty() || ctx->batch_state_allocated || ctx->d_step_counter ||
+            !ctx->scratch.empty())
             fail(EBIC_EBUSY, "allocator can only change while nothing is resident");
         ctx->alloc = alloc;
         ctx->release = release;
@@ -374,7 +382,7 @@ ebic_status ebic_eval_population(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
         if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
         if (n_ind < 0) fail(EBIC_EINVAL, "n_ind < 0");
         if (flags & ~(EBIC_NAN_INCLUDE | EBIC_NEG_TRENDS)) fail(EBIC_EINVAL, "unknown eval flags");
-        EvalArgs a;
+        ReqDesc d;
         LaunchCfg cfg;
         {
             std::lock_guard<std::mutex> lk(ctx->mu);
@@ -382,19 +390,12 @@ ebic_status ebic_eval_population(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
             if (n_ind == 0) return;
             if (!d_offsets || !d_cols || !d_matched)
                 fail(EBIC_EINVAL, "d_offsets, d_cols and d_matched are required");
-            a.m = m.dev;
             cfg = plan_eval(ctx, m, n_ind, -1, flags);
+            d = make_desc(m, n_ind, d_offsets, d_cols, flags, d_matched, d_negative, d_matched_mask,
+                          d_negative_mask, cfg.staging);
         }
-        a.offsets = d_offsets;
-        a.cols = d_cols;
-        a.n = n_ind;
-        a.flags = flags;
-        a.matched = d_matched;
-        a.negative = d_negative;
-        a.mmask = d_matched_mask;
-        a.nmask = d_negative_mask;
         DeviceGuard g(ctx->device);
-        hip_check(ctx_launch_eval(ctx, a, cfg, reinterpret_cast<hipStream_t>(hip_stream)),
+        hip_check(ctx_launch_eval(ctx, d, cfg, reinterpret_cast<hipStream_t>(hip_stream)),
                   "evaluation launch");
     });
 }

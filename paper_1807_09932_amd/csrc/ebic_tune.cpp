@@ -1,5 +1,7 @@
 // ebic_tune.cpp -- launch-shape selection: defaults, the per-context tuning
-// table, its JSON cache file, and the autotuner (ebic_autotune).
+// table, its JSON cache file, the forced-shape override, and the autotuner
+// (ebic_autotune), which times candidate shapes on a sample and keeps the
+// fastest per shape class.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -7,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <set>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -30,7 +33,12 @@ static int32_t log2_bucket(int64_t v)
 TuneKey tune_key(int64_t rows, int32_t cols, int32_t n, int64_t nnz)
 {
     const int64_t kmean = (nnz > 0 && n > 0) ? (nnz + n - 1) / n : 0;
-    return TuneKey{log2_bucket(rows), log2_bucket(cols), log2_bucket(n), log2_bucket(kmean)};
+    return TuneKey{0, log2_bucket(rows), log2_bucket(cols), log2_bucket(n), log2_bucket(kmean)};
+}
+
+static TuneKey batch_key(int64_t total_ind, int64_t mean_rows, int32_t max_cols)
+{
+    return TuneKey{1, log2_bucket(mean_rows), log2_bucket(max_cols), log2_bucket(total_ind), 0};
 }
 
 LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
@@ -45,20 +53,40 @@ LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
     return c;
 }
 
+LaunchCfg default_batch_cfg(int32_t max_cols)
+{
+    LaunchCfg c;
+    c.W = 8;
+    c.P = 512;
+    c.L = max_cols <= 96 ? 2 : 1;
+    c.staging = STAGE_LDS;
+    c.blocks = 0;
+    return c;
+}
+
 LaunchCfg tuned_cfg(ebic_ctx *ctx, int64_t rows, int32_t cols, int32_t n, int64_t nnz)
 {
     if (nnz >= 0) {
         auto it = ctx->tuned.find(tune_key(rows, cols, n, nnz));
         if (it != ctx->tuned.end()) return it->second;
-    } else {
-        // Population length unknown on the host: any entry of the same
-        // rows/cols/n class will do.
-        const TuneKey k = tune_key(rows, cols, n, 0);
-        for (auto &kv : ctx->tuned)
-            if (kv.first.rows_b == k.rows_b && kv.first.cols_b == k.cols_b && kv.first.n_b == k.n_b)
-                return kv.second;
     }
+    // Mean length unknown on the host (it lives in device memory): any entry
+    // of the same rows/cols/population class will do.
+    const TuneKey k = tune_key(rows, cols, n, 0);
+    for (auto &kv : ctx->tuned)
+        if (kv.first.kind == 0 && kv.first.rows_b == k.rows_b && kv.first.cols_b == k.cols_b &&
+            kv.first.n_b == k.n_b)
+            return kv.second;
     return default_cfg(rows, cols, n);
+}
+
+LaunchCfg tuned_batch_cfg(ebic_ctx *ctx, int64_t total_ind, int64_t mean_rows, int32_t max_cols,
+                          int64_t nnz)
+{
+    (void)nnz;
+    auto it = ctx->tuned.find(batch_key(total_ind, mean_rows, max_cols));
+    if (it != ctx->tuned.end()) return it->second;
+    return default_batch_cfg(max_cols);
 }
 
 // Minimal reader of the cache written by save_tune_cache: one JSON object
@@ -76,7 +104,7 @@ static bool read_int(const std::string &obj, const char *key, int32_t *out)
     return true;
 }
 
-void load_tune_cache(ebic_ctx *ctx, const std::string &path)
+static void read_cache(std::map<TuneKey, LaunchCfg> &out, const std::string &path)
 {
     std::ifstream f(path);
     if (!f) return;
@@ -94,185 +122,224 @@ void load_tune_cache(ebic_ctx *ctx, const std::string &path)
         pos = b + 1;
         TuneKey k{};
         LaunchCfg c;
-        if (read_int(obj, "rows_b", &k.rows_b) && read_int(obj, "cols_b", &k.cols_b) &&
-            read_int(obj, "n_b", &k.n_b) && read_int(obj, "k_b", &k.k_b) &&
-            read_int(obj, "L", &c.L) && read_int(obj, "W", &c.W) && read_int(obj, "P", &c.P) &&
-            read_int(obj, "staging", &c.staging)) {
-            if ((c.L == 1 || c.L == 2 || c.L == 4) && c.W >= 1 && c.W <= 16 && c.P >= 1 &&
-                (c.staging == STAGE_LDS || c.staging == STAGE_DIRECT))
-                ctx->tuned[k] = c;
+        if (read_int(obj, "kind", &k.kind) && read_int(obj, "rows_b", &k.rows_b) &&
+            read_int(obj, "cols_b", &k.cols_b) && read_int(obj, "n_b", &k.n_b) &&
+            read_int(obj, "k_b", &k.k_b) && read_int(obj, "L", &c.L) && read_int(obj, "W", &c.W) &&
+            read_int(obj, "P", &c.P) && read_int(obj, "staging", &c.staging)) {
+            if ((k.kind == 0 || k.kind == 1) && (c.L == 1 || c.L == 2 || c.L == 4) && c.W >= 1 &&
+                c.W <= 16 && c.P >= 1 && (c.staging == STAGE_LDS || c.staging == STAGE_DIRECT))
+                out[k] = c;
         }
     }
 }
 
+void load_tune_cache(ebic_ctx *ctx, const std::string &path) { read_cache(ctx->tuned, path); }
+
 static void save_tune_cache(ebic_ctx *ctx, const std::string &path)
 {
-    // Merge: entries already in the file keep their place unless re-tuned.
+    // Merge: entries already in the file stay unless re-tuned here.
     std::map<TuneKey, LaunchCfg> merged;
-    {
-        ebic_ctx tmp;
-        load_tune_cache(&tmp, path);
-        merged = tmp.tuned;
-    }
+    read_cache(merged, path);
     for (auto &kv : ctx->tuned) merged[kv.first] = kv.second;
     const std::string tmp_path = path + ".tmp";
     FILE *f = std::fopen(tmp_path.c_str(), "w");
-    if (!f) return;
+    if (!f) fail(EBIC_EINVAL, "cannot write " + tmp_path);
     std::fprintf(f, "{\"arch\": \"%s\", \"entries\": [\n", ctx->arch.c_str());
     size_t i = 0;
     for (auto &kv : merged) {
         std::fprintf(f,
-                     "  {\"rows_b\": %d, \"cols_b\": %d, \"n_b\": %d, \"k_b\": %d, \"L\": %d, "
-                     "\"W\": %d, \"P\": %d, \"staging\": %d}%s\n",
-                     kv.first.rows_b, kv.first.cols_b, kv.first.n_b, kv.first.k_b, kv.second.L,
-                     kv.second.W, kv.second.P, kv.second.staging, ++i < merged.size() ? "," : "");
+                     "  {\"kind\": %d, \"rows_b\": %d, \"cols_b\": %d, \"n_b\": %d, \"k_b\": %d, "
+                     "\"L\": %d, \"W\": %d, \"P\": %d, \"staging\": %d}%s\n",
+                     kv.first.kind, kv.first.rows_b, kv.first.cols_b, kv.first.n_b, kv.first.k_b,
+                     kv.second.L, kv.second.W, kv.second.P, kv.second.staging,
+                     ++i < merged.size() ? "," : "");
     }
     std::fprintf(f, "]}\n");
     std::fclose(f);
-    std::rename(tmp_path.c_str(), path.c_str());
+    if (std::rename(tmp_path.c_str(), path.c_str()) != 0) fail(EBIC_EINVAL, "cannot write " + path);
 }
 
-}  // namespace ebic
-
-using namespace ebic;
-
-namespace {
-thread_local std::string t_err;
-}
-
-extern "C" {
-
-ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t waves_per_block,
-                                  int32_t individuals_per_group, int32_t staging, int32_t blocks)
+// Median of `reps` timed runs of `fn` (after one warm-up), in ms.
+template <typename F>
+static float time_ms(F &&fn, int reps, hipStream_t s)
 {
-    if (!ctx) return EBIC_EINVAL;
-    if (waves_per_block == 0) {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->override_cfg = LaunchCfg();
-        return EBIC_OK;
-    }
-    if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 4) || waves_per_block < 1 ||
-        waves_per_block > 16 || individuals_per_group < 1 ||
-        !(staging == STAGE_LDS || staging == STAGE_DIRECT) || blocks < 0)
-        return EBIC_EINVAL;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    LaunchCfg c;
-    c.L = tiles_per_wave;
-    c.W = waves_per_block;
-    c.P = individuals_per_group;
-    c.staging = staging;
-    c.blocks = blocks;
-    ctx->override_cfg = c;
-    return EBIC_OK;
-}
-
-}  // extern "C"
-
-namespace ebic {
-
-// Time one request under one launch shape: median of `reps` runs, in ms.
-static float time_request(ebic_ctx *ctx, const ebic_request &r, const LaunchCfg &cfg, int reps,
-                          hipStream_t s)
-{
-    const Matrix &m = ctx_matrix(ctx, r.matrix);
-    EvalArgs a;
-    a.m = m.dev;
-    a.offsets = r.d_offsets;
-    a.cols = r.d_cols;
-    a.n = r.n_ind;
-    a.flags = r.flags;
-    a.matched = r.d_matched;
-    a.negative = r.d_negative;
-    a.mmask = r.d_matched_mask;
-    a.nmask = r.d_negative_mask;
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return INFINITY;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return INFINITY;
-    }
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
     std::vector<float> t;
-    for (int i = 0; i < reps + 1; ++i) {
+    bool ok = true;
+    for (int i = 0; i < reps + 1 && ok; ++i) {
         (void)hipEventRecord(e0, s);
-        if (launch_eval(a, cfg, s) != hipSuccess) {
-            (void)hipGetLastError();
-            t.clear();
-            break;
-        }
+        ok = fn();
         (void)hipEventRecord(e1, s);
         (void)hipEventSynchronize(e1);
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (i > 0) t.push_back(ms);  // the first run is a warm-up
+        if (i > 0) t.push_back(ms);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (t.empty()) return INFINITY;
+    if (!ok || t.empty()) return INFINITY;
     std::sort(t.begin(), t.end());
     return t[t.size() / 2];
 }
 
 }  // namespace ebic
 
-extern "C" ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_reqs,
-                                     const char *cache_path)
+using namespace ebic;
+
+extern "C" {
+
+ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t waves_per_block,
+                                  int32_t individuals_per_group, int32_t staging, int32_t blocks)
 {
-    if (!ctx || (!sample && n_reqs > 0) || n_reqs < 0) return EBIC_EINVAL;
-    int prev = -1;
-    (void)hipGetDevice(&prev);
-    (void)hipSetDevice(ctx->device);
-    hipStream_t s = nullptr;
-    ebic_status st = EBIC_OK;
-    try {
-        for (int32_t q = 0; q < n_reqs; ++q) {
-            const ebic_request &r = sample[q];
-            if (r.n_ind <= 0) continue;
-            // The host knows the population's size only through d_offsets.
-            int32_t nnz = 0;
-            if (hipMemcpy(&nnz, r.d_offsets + r.n_ind, sizeof(int32_t), hipMemcpyDeviceToHost) !=
-                hipSuccess)
-                return EBIC_EHIP;
-            int32_t first = 0;
-            (void)hipMemcpy(&first, r.d_offsets, sizeof(int32_t), hipMemcpyDeviceToHost);
-            std::lock_guard<std::mutex> lk(ctx->mu);
-            const Matrix &m = ctx_matrix(ctx, r.matrix);
-            const TuneKey key = tune_key(m.dev.rows, m.dev.cols, r.n_ind, (int64_t)nnz - first);
-            LaunchCfg best;
-            float best_ms = INFINITY;
-            for (int L : {1, 2, 4})
-                for (int W : {4, 8, 16})
-                    for (int P : {256, 1024, 4096})
-                        for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT}) {
-                            LaunchCfg c;
-                            c.L = L;
-                            c.W = W;
-                            c.P = std::min(P, r.n_ind);
-                            c.staging = stg;
-                            if (stg == STAGE_LDS && eval_lds_bytes(c, m.dev.cols) > ctx->lds_per_block)
-                                continue;
-                            if (eval_lds_bytes(c, m.dev.cols) > ctx->lds_per_block) continue;
-                            int occ = eval_occupancy(c, m.dev.cols, r.flags);
-                            if (occ <= 0) continue;
-                            const int64_t n_tiles = (m.dev.rows + 63) / 64;
-                            const int32_t groups = (r.n_ind + c.P - 1) / c.P;
-                            int64_t bx = std::max<int64_t>(1, (int64_t)ctx->cu_count * occ / groups);
-                            bx = std::min<int64_t>(bx, (n_tiles + L - 1) / L);
-                            c.blocks = (int32_t)bx;
-                            const float ms = time_request(ctx, r, c, 3, s);
-                            if (ms < best_ms) {
-                                best_ms = ms;
-                                best = c;
-                            }
-                        }
-            if (best.W > 0) {
-                best.blocks = 0;  // re-derived from occupancy at launch
-                ctx->tuned[key] = best;
-            }
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (waves_per_block == 0) {
+            ctx->override_cfg = LaunchCfg();
+            return;
         }
-        if (cache_path && *cache_path) save_tune_cache(ctx, cache_path);
-    } catch (...) {
-        st = EBIC_EINVAL;
-    }
-    if (prev >= 0) (void)hipSetDevice(prev);
-    return st;
+        if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 4) ||
+            waves_per_block < 1 || waves_per_block > 16 || individuals_per_group < 1 ||
+            !(staging == STAGE_LDS || staging == STAGE_DIRECT) || blocks < 0)
+            fail(EBIC_EINVAL, "launch shape out of range");
+        LaunchCfg c;
+        c.L = tiles_per_wave;
+        c.W = waves_per_block;
+        c.P = individuals_per_group;
+        c.staging = staging;
+        c.blocks = blocks;
+        ctx->override_cfg = c;
+    });
 }
+
+ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_reqs,
+                          const char *cache_path)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        if (n_reqs < 0 || (n_reqs > 0 && !sample)) fail(EBIC_EINVAL, "bad request array");
+        DeviceGuard dg(ctx->device);
+        hipStream_t s = nullptr;
+        hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        LaunchCfg saved;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            saved = ctx->override_cfg;
+        }
+        auto set_override = [&](const LaunchCfg &c) {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->override_cfg = c;
+        };
+        try {
+            // One population at a time: one entry per distinct shape class.
+            std::set<TuneKey> done;
+            for (int32_t q = 0; q < n_reqs; ++q) {
+                const ebic_request &r = sample[q];
+                if (r.n_ind <= 0) continue;
+                int32_t ends[2] = {0, 0};
+                hip_check(hipMemcpy(&ends[0], r.d_offsets, sizeof(int32_t), hipMemcpyDeviceToHost),
+                          "hipMemcpy");
+                hip_check(hipMemcpy(&ends[1], r.d_offsets + r.n_ind, sizeof(int32_t),
+                                    hipMemcpyDeviceToHost),
+                          "hipMemcpy");
+                int64_t rows;
+                int32_t cols;
+                {
+                    std::lock_guard<std::mutex> lk(ctx->mu);
+                    const Matrix &m = ctx_matrix(ctx, r.matrix);
+                    rows = m.dev.rows;
+                    cols = m.dev.cols;
+                }
+                const TuneKey key = tune_key(rows, cols, r.n_ind, (int64_t)ends[1] - ends[0]);
+                if (!done.insert(key).second) continue;
+                LaunchCfg best;
+                float best_ms = INFINITY;
+                for (int L : {1, 2, 4})
+                    for (int W : {4, 8, 16})
+                        for (int P : {200, 400, 800, 1600})
+                            for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT}) {
+                                LaunchCfg c;
+                                c.L = L;
+                                c.W = W;
+                                c.P = std::min(P, r.n_ind);
+                                c.staging = stg;
+                                if (stg == STAGE_LDS &&
+                                    tile_lds_bytes(L, cols) + count_lds_bytes(c.P) > ctx->lds_per_block)
+                                    continue;
+                                set_override(c);
+                                const float ms = time_ms(
+                                    [&] {
+                                        return ebic_eval_population(
+                                                   ctx, r.matrix, r.n_ind, r.d_offsets, r.d_cols,
+                                                   r.flags, r.d_matched, r.d_negative,
+                                                   r.d_matched_mask, r.d_negative_mask, s) == EBIC_OK;
+                                    },
+                                    3, s);
+                                if (ms < best_ms) {
+                                    best_ms = ms;
+                                    best = c;
+                                }
+                            }
+                if (best.W > 0) {
+                    best.blocks = 0;  // re-derived from occupancy at launch
+                    std::lock_guard<std::mutex> lk(ctx->mu);
+                    ctx->tuned[key] = best;
+                }
+            }
+            // The whole sample as one batch: tile width, waves and
+            // individuals per work item for its shape class.
+            if (n_reqs > 1) {
+                int64_t total = 0, rows_sum = 0;
+                int32_t max_cols = 1, live = 0;
+                for (int32_t q = 0; q < n_reqs; ++q) {
+                    if (sample[q].n_ind <= 0) continue;
+                    std::lock_guard<std::mutex> lk(ctx->mu);
+                    const Matrix &m = ctx_matrix(ctx, sample[q].matrix);
+                    total += sample[q].n_ind;
+                    rows_sum += m.dev.rows;
+                    max_cols = std::max(max_cols, m.dev.cols);
+                    ++live;
+                }
+                if (live > 0) {
+                    const TuneKey key = batch_key(total, rows_sum / live, max_cols);
+                    LaunchCfg best;
+                    float best_ms = INFINITY;
+                    for (int L : {1, 2, 4})
+                        for (int W : {4, 8, 16})
+                            for (int P : {128, 256, 512, 1024}) {
+                                LaunchCfg c;
+                                c.L = L;
+                                c.W = W;
+                                c.P = P;
+                                c.staging = STAGE_LDS;
+                                set_override(c);
+                                const float ms = time_ms(
+                                    [&] { return ebic_eval_batch(ctx, sample, n_reqs, s) == EBIC_OK; }, 3,
+                                    s);
+                                if (ms < best_ms) {
+                                    best_ms = ms;
+                                    best = c;
+                                }
+                            }
+                    if (best.W > 0) {
+                        best.blocks = 0;
+                        std::lock_guard<std::mutex> lk(ctx->mu);
+                        ctx->tuned[key] = best;
+                    }
+                }
+            }
+        } catch (...) {
+            set_override(saved);
+            throw;
+        }
+        set_override(saved);
+        if (cache_path && *cache_path) {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            save_tune_cache(ctx, cache_path);
+        }
+    });
+}
+
+}  // extern "C"

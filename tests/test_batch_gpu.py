@@ -1,0 +1,149 @@
+"""The batched path (one persistent launch replayed from a HIP graph) against
+the CPU oracle, per request, bit-exact; and against the plain path."""
+import numpy as np
+import pytest
+
+from paper_1807_09932_amd import gen
+from tests.gpu_common import announce, assert_same, oracle_eval, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1807_09932_amd.ebic import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _pops(seed, ncols, n_pops, n_range, length_fn):
+    rng = np.random.default_rng(seed)
+    pops = []
+    for _ in range(n_pops):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        inds = [rng.choice(ncols, max(1, min(ncols, length_fn(rng))), replace=False).astype(np.int32)
+                for _ in range(n)]
+        pops.append(gen.csr(inds))
+    return pops
+
+
+def _run_batch(ctx, jobs, stream=None):
+    """jobs: list of (matrix handle, (offs, cols), include, negative, masks)."""
+    import torch
+    reqs, outs = [], []
+    for mat, (offs, cols), include, negative, masks in jobs:
+        pop = ctx.population(offsets=offs, cols=cols)
+        out = ctx.outputs(mat, pop.n, masks=masks, negative=True)
+        outs.append((pop, out))
+        reqs.append(ctx.request(mat, pop, out, include=include, negative=negative))
+    ctx.eval_batch(reqs, stream=stream)
+    torch.cuda.synchronize()
+    return [tuple(to_np(t) for t in out) for _, out in outs]
+
+
+def test_batched_skewed_populations(ctx):
+    """Config-4 shape, reduced: uneven population sizes, lengths 2..40
+    skewed toward short, one N(0,1) matrix with planted trends."""
+    w = gen.make_matrix(4, 20000, 256, "normal", 8, (100, 1000), (4, 12))
+    pops = _pops(41, 256, 24, (5, 400), gen.skewed_length)
+    mat = ctx.upload(w.X)
+    jobs = [(mat, p, False, True, i % 3 == 0) for i, p in enumerate(pops)]
+    announce("batch skewed")
+    got = _run_batch(ctx, jobs)
+    for i, (p, g) in enumerate(zip(pops, got)):
+        want = oracle_eval(w.X, *p, negative=True, masks=jobs[i][4])
+        assert_same(g, want, f"request {i}")
+    # the plain path gives the same numbers
+    for i in (0, 5, 17):
+        pop = ctx.population(offsets=pops[i][0], cols=pops[i][1])
+        out = ctx.eval(mat, pop, negative=True, masks=jobs[i][4])
+        import torch
+        torch.cuda.synchronize()
+        assert_same(tuple(to_np(t) for t in out), got[i], f"plain vs batch {i}")
+    ctx.release(mat)
+
+
+def test_batched_many_matrices_and_modes(ctx):
+    rng = np.random.default_rng(42)
+    mats, Xs = [], []
+    for rows, ncols in [(3000, 40), (700, 310), (1500, 700), (64, 5)]:
+        X = rng.standard_normal((rows, ncols)).astype(np.float32)
+        X[:, ::4] = np.round(X[:, ::4])
+        X[rng.random(X.shape) < 0.03] = np.float32(np.nan)
+        Xs.append(X)
+        mats.append(ctx.upload(X, fill=0.5))
+    jobs, want = [], []
+    for q in range(20):
+        m = q % len(mats)
+        ncols = Xs[m].shape[1]
+        (offs, cols), = _pops(100 + q, ncols, 1, (0 if q == 7 else 3, 150),
+                              lambda r: int(r.integers(1, 26)))
+        include, negative, masks = bool(q & 1), bool(q & 2), bool(q & 4)
+        jobs.append((mats[m], (offs, cols), include, negative, masks))
+        want.append(oracle_eval(Xs[m], offs, cols, include=include, negative=negative,
+                                masks=masks, fill=0.5))
+    announce("batch many matrices")
+    got = _run_batch(ctx, jobs)
+    for q in range(len(jobs)):
+        assert_same(got[q], want[q], f"request {q}")
+    # the same batch in another order gives the same per-request results
+    order = np.random.default_rng(5).permutation(len(jobs))
+    announce("batch shuffled")
+    got2 = _run_batch(ctx, [jobs[i] for i in order])
+    for k, i in enumerate(order):
+        assert np.array_equal(got2[k][0], got[i][0])
+        assert np.array_equal(got2[k][1], got[i][1])
+    for m in mats:
+        ctx.release(m)
+
+
+def test_batch_graph_replays_with_eager_work_between(ctx):
+    """One captured graph replayed for batches of different contents, with
+    plain evaluations and synchronisations between the replays; every
+    replay is checked against the oracle."""
+    import torch
+    rng = np.random.default_rng(43)
+    X = rng.random((5000, 64)).astype(np.float32)
+    mat = ctx.upload(X)
+    for rep in range(4):
+        pops = _pops(200 + rep, 64, 6 + rep, (20, 200), lambda r: int(r.integers(2, 31)))
+        jobs = [(mat, p, False, True, rep % 2 == 0) for p in pops]
+        announce("graph replay", rep)
+        got = _run_batch(ctx, jobs)
+        for i, p in enumerate(pops):
+            assert_same(got[i], oracle_eval(X, *p, masks=rep % 2 == 0), f"replay {rep} req {i}")
+        # eager work between replays
+        pop = ctx.population(offsets=pops[0][0], cols=pops[0][1])
+        out = ctx.eval(mat, pop)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(out[0]), got[0][0])
+    ctx.release(mat)
+
+
+def test_batch_invalid_and_empty(ctx):
+    X = np.arange(600, dtype=np.float32).reshape(100, 6)[::-1].copy()
+    mat = ctx.upload(X)
+    p1 = gen.csr([[0, 1], [], [0, 6], [5, 4, 3], [2]])
+    p2 = gen.csr([])
+    p3 = gen.csr([[3, 3], [-2]])
+    jobs = [(mat, p1, False, True, True), (mat, p2, False, True, True), (mat, p3, True, True, True)]
+    announce("batch invalid/empty")
+    got = _run_batch(ctx, jobs)
+    assert_same(got[0], oracle_eval(X, *p1), "p1")
+    assert got[1][0].size == 0
+    assert_same(got[2], oracle_eval(X, *p3, include=True), "p3")
+    ctx.release(mat)
+
+
+def test_batch_matches_plain_on_config4_sample(ctx):
+    """Three populations of the full config-4 workload (100,000 x 256)."""
+    w, pops = gen.config4(n_pops=3)
+    mat = ctx.upload(w.X)
+    packed = [gen.csr(p) for p in pops]
+    jobs = [(mat, p, False, True, False) for p in packed]
+    announce("config4 sample batch")
+    got = _run_batch(ctx, jobs)
+    for i, p in enumerate(packed):
+        assert_same(got[i], oracle_eval(w.X, *p, masks=False), f"config4 pop {i}")
+    ctx.release(mat)
