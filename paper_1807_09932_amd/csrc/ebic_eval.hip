@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ebic_internal.h"
 
 namespace ebic {
@@ -44,6 +46,7 @@ __host__ __device__ inline size_t tile_bytes_of(int32_t L, int32_t cols)
     return (size_t)L * kWave * cols * sizeof(float);
 }
 
+// Per-individual [matched, negative] counts of a group of P.
 __host__ __device__ inline size_t count_bytes_of(int32_t P)
 {
     return (size_t)((P + 1) & ~1) * 2 * sizeof(int32_t);
@@ -101,94 +104,334 @@ __global__ void k_prep_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs
 // The predicate.
 // ---------------------------------------------------------------------------
 
-// All-ones if x > y (both wave-uniform), else zero. Produced by scalar
-// instructions the compiler cannot see through, so that an exit test
-// `(live & mask) == 0` stays a single 64-bit AND instead of being split
-// into a second, boolean condition.
-__device__ __forceinline__ uint64_t ones_if_greater(int32_t x, int32_t y)
+// ---------------------------------------------------------------------------
+// The predicate on LDS-staged tiles, as one oriented chain per row.
+//
+// After the first pair (c_0, c_1) every row that can still match follows
+// one direction: rows with v_1 > v_0 can only be on the >= chain, rows with
+// v_1 < v_0 only on the <= chain. Flipping the sign bit of every value of a
+// falling row (an exact negation, also for +-0, +-inf and NaN) turns its
+// <= chain into a >= chain, so from the second pair on every row runs the
+// same test, (v_j ^ flip) >= (v_{j-1} ^ flip), and the wave carries one
+// alive mask: the execution mask. Each column step is an XOR and a compare
+// (VALU) and one AND into the execution mask (SALU); the chain stops for
+// the wave as soon as no row is left (s_cbranch_execz). Rows tied on the
+// first pair (v_1 == v_0) follow the >= chain here and get a second chain
+// for the <= direction. NaN compares false, so a missing value anywhere
+// along the chain removes the row (exclude mode); in include mode the tile
+// holds no NaN.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSign = 0x80000000u;
+
+typedef __attribute__((address_space(3))) const unsigned char lds_uchar;
+
+// Byte offset of an LDS pointer in the LDS address space.
+__device__ __forceinline__ uint32_t lds_addr(const void *p)
 {
-    uint64_t m;
-    asm volatile("s_cmp_gt_i32 %1, %2\n\ts_cselect_b64 %0, -1, 0" : "=s"(m) : "s"(x), "s"(y) : "scc");
-    return m;
+    return (uint32_t)(uintptr_t)(lds_uchar *)p;
 }
 
-// One individual on L LDS-staged sub-tiles of 64 rows, evaluated together
-// (independent loads and compares overlap their latency); the individual
-// stops once no row of any sub-tile can still match. The first kWin - 1
-// column steps come from the header's window, unrolled, with an exit test
-// every two steps; longer individuals continue in a loop. Window entries
-// past the end repeat the last column, whose self-comparison changes
-// nothing (a NaN there has already cleared the row).
+__device__ __forceinline__ float flipped(float v, uint32_t flip)
+{
+    return __uint_as_float(__float_as_uint(v) ^ flip);
+}
+
+// The window's column steps 2..min(last, 7), as assembly text shared by the
+// sequences below: three pairs of columns; for each column an XOR (omitted
+// when every row runs the >= chain), a compare into VCC and an AND of VCC
+// into EXEC; after each pair the chain ends if no row is left
+// (s_cbranch_execz) or if the individual has no more columns. The loads of
+// the next pair are issued before the current pair is compared, so LDS
+// latency overlaps the compares. The sequence starts with lgkmcnt(0) (no
+// scalar load of the surrounding code in flight, so LDS loads complete in
+// issue order and lgkmcnt(2) names the older pair) and ends with it (no
+// load left in flight when control returns). `prev` holds the (flipped)
+// value of column 1; the first pair's loads are issued by the caller's text.
+#define EBIC_XOR(r) "v_xor_b32 %[" r "], %[" r "], %[flip]\n\t"
+#define EBIC_CMP2(ra, rb, rp, XORA, XORB)                                      \
+    XORA                                                                       \
+    "v_cmp_ge_f32 vcc, %[" ra "], %[" rp "]\n\t"                               \
+    XORB                                                                       \
+    "s_and_b64 exec, exec, vcc\n\t"                                            \
+    "v_cmp_ge_f32 vcc, %[" rb "], %[" ra "]\n\t"                               \
+    "s_and_b64 exec, exec, vcc\n\t"
+#define EBIC_LOAD2(ra, rb, aa, ab)                                             \
+    "ds_read_b32 %[" ra "], %[" aa "] offset:%[off]\n\t"                       \
+    "ds_read_b32 %[" rb "], %[" ab "] offset:%[off]\n\t"
+#define EBIC_LOAD_FIRST EBIC_LOAD2("r0", "r1", "a2", "a3")
+#define EBIC_WINDOW(X0, X1, X2, X3, X4, X5)                                    \
+    EBIC_LOAD2("r2", "r3", "a4", "a5")                                         \
+    "s_waitcnt lgkmcnt(2)\n\t"                                                 \
+    EBIC_CMP2("r0", "r1", "prev", X0, X1)                                      \
+    "s_cbranch_execz 1f\n\t"                                                   \
+    "s_cmp_le_i32 %[last], 3\n\t"                                              \
+    "s_cbranch_scc1 1f\n\t"                                                    \
+    EBIC_LOAD2("r4", "r5", "a6", "a7")                                         \
+    "s_waitcnt lgkmcnt(2)\n\t"                                                 \
+    EBIC_CMP2("r2", "r3", "r1", X2, X3)                                        \
+    "s_cbranch_execz 1f\n\t"                                                   \
+    "s_cmp_le_i32 %[last], 5\n\t"                                              \
+    "s_cbranch_scc1 1f\n\t"                                                    \
+    "s_waitcnt lgkmcnt(0)\n\t"                                                 \
+    EBIC_CMP2("r4", "r5", "r3", X4, X5)                                        \
+    "1:\n\t"                                                                   \
+    "s_waitcnt lgkmcnt(0)\n\t"
+#define EBIC_WINDOW_FLIP                                                       \
+    EBIC_WINDOW(EBIC_XOR("r0"), EBIC_XOR("r1"), EBIC_XOR("r2"), EBIC_XOR("r3"), \
+                EBIC_XOR("r4"), EBIC_XOR("r5"))
+#define EBIC_WINDOW_PLAIN EBIC_WINDOW("", "", "", "", "", "")
+#define EBIC_SCRATCH_OUTPUTS                                                   \
+    [r0] "=&v"(r[0]), [r1] "=&v"(r[1]), [r2] "=&v"(r[2]), [r3] "=&v"(r[3]),    \
+        [r4] "=&v"(r[4]), [r5] "=&v"(r[5])
+#define EBIC_WINDOW_INPUTS                                                     \
+    [last] "s"(last), [a2] "v"(a[2]), [a3] "v"(a[3]), [a4] "v"(a[4]),          \
+        [a5] "v"(a[5]), [a6] "v"(a[6]), [a7] "v"(a[7]), [off] "i"(OFF)
+
+// First pair of both chains (values v0, v1 of columns 0 and 1, loaded by
+// the caller) and the window, on one 64-row sub-tile; rows outside `valid`
+// take no part. Returns the rows still on their chain after column
+// min(last, 7); `fall` receives the rows with v1 < v0 (on the <= chain),
+// `tie` those with v1 == v0 (still on both), `flip` the per-row sign flip,
+// `lastf` the flipped value of column 7 (meaningful when the window ran to
+// its end).
+template <int OFF>
+__device__ __forceinline__ uint64_t subtile_neg(uint64_t valid, int32_t last, const uint32_t (&a)[kWin],
+                                                uint32_t sign, float v0, float v1, uint64_t &fall,
+                                                uint64_t &tie, uint32_t &flip, float &lastf)
+{
+    uint64_t out, save, f, t;
+    float prev, r[6];
+    uint32_t fl;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_mov_b64 %[save], exec\n\t"
+        "s_and_b64 exec, exec, %[valid]\n\t"
+        EBIC_LOAD_FIRST
+        "v_cmp_lt_f32_e64 %[f], %[v1], %[v0]\n\t"
+        "v_cmp_eq_f32_e64 %[t], %[v1], %[v0]\n\t"
+        "v_cmp_o_f32 vcc, %[v1], %[v0]\n\t"
+        "s_nop 4\n\t"  // wait states before a VALU reads an SGPR mask a VALU wrote
+        "v_cndmask_b32_e64 %[flip], 0, %[sign], %[f]\n\t"
+        "s_and_b64 exec, exec, vcc\n\t"
+        "v_xor_b32 %[prev], %[v1], %[flip]\n\t"
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 1f\n\t"
+        EBIC_WINDOW_FLIP
+        "1:\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_mov_b64 %[out], exec\n\t"
+        "s_mov_b64 exec, %[save]"
+        : [out] "=&s"(out), [save] "=&s"(save), [f] "=&s"(f), [t] "=&s"(t), [flip] "=&v"(fl),
+          [prev] "=&v"(prev), EBIC_SCRATCH_OUTPUTS
+        : [valid] "s"(valid), [v0] "v"(v0), [v1] "v"(v1), [sign] "v"(sign), EBIC_WINDOW_INPUTS
+        : "vcc", "scc", "memory");
+    fall = f;
+    tie = t;
+    flip = fl;
+    lastf = r[5];
+    return out;
+}
+
+// The same for the >= chain alone (negative trends not requested).
+template <int OFF>
+__device__ __forceinline__ uint64_t subtile_pos(uint64_t valid, int32_t last, const uint32_t (&a)[kWin],
+                                                float v0, float v1, float &lastf)
+{
+    uint64_t out, save;
+    float r[6];
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_mov_b64 %[save], exec\n\t"
+        "s_and_b64 exec, exec, %[valid]\n\t"
+        EBIC_LOAD_FIRST
+        "v_cmp_ge_f32 vcc, %[prev], %[v0]\n\t"
+        "s_and_b64 exec, exec, vcc\n\t"
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 1f\n\t"
+        EBIC_WINDOW_PLAIN
+        "1:\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_mov_b64 %[out], exec\n\t"
+        "s_mov_b64 exec, %[save]"
+        : [out] "=&s"(out), [save] "=&s"(save), EBIC_SCRATCH_OUTPUTS
+        : [valid] "s"(valid), [v0] "v"(v0), [prev] "v"(v1), EBIC_WINDOW_INPUTS
+        : "vcc", "scc", "memory");
+    lastf = r[5];
+    return out;
+}
+
+// The <= chain of the rows tied on the first pair: every value flipped.
+template <int OFF>
+__device__ __forceinline__ uint64_t subtile_tie(uint64_t tie, int32_t last, const uint32_t (&a)[kWin],
+                                                uint32_t sign, float v1, float &lastf)
+{
+    uint64_t out, save;
+    float r[6];
+    const float prev = flipped(v1, kSign);
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_mov_b64 %[save], exec\n\t"
+        "s_and_b64 exec, exec, %[tie]\n\t"
+        "s_cbranch_execz 1f\n\t"
+        EBIC_LOAD_FIRST
+        EBIC_WINDOW_FLIP
+        "1:\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_mov_b64 %[out], exec\n\t"
+        "s_mov_b64 exec, %[save]"
+        : [out] "=&s"(out), [save] "=&s"(save), EBIC_SCRATCH_OUTPUTS
+        : [tie] "s"(tie), [prev] "v"(prev), [flip] "v"(sign), EBIC_WINDOW_INPUTS
+        : "vcc", "scc", "memory");
+    lastf = r[5];
+    return out;
+}
+
+// Plain-code twin of the three sequences above, with the same exit points;
+// it counts the compare instructions it executes (the measurement variant).
+struct SubtileRef {
+    const unsigned char *tile;
+    uint32_t tile_lds;
+    int off;
+    const uint32_t *a;
+    uint64_t *steps;
+    __device__ float ld(int u) const
+    {
+        return *reinterpret_cast<const float *>(tile + (a[u] - tile_lds) + off);
+    }
+    // Window steps 2..min(last, 7) of a chain whose rows are `alive`.
+    __device__ uint64_t window(uint64_t alive, int32_t last, uint32_t flip, float prev, float &lastf) const
+    {
+#pragma unroll
+        for (int u = 2; u < kWin; u += 2) {
+            if (alive == 0) break;
+            const float x = flipped(ld(u), flip), y = flipped(ld(u + 1), flip);
+            alive &= __ballot(x >= prev);
+            alive &= __ballot(y >= x);
+            *steps += 2;
+            prev = y;
+            if (alive == 0 || last <= u + 1) break;
+        }
+        lastf = prev;
+        return alive;
+    }
+};
+
+// Columns kWin..last of a chain (long individuals; rarely any row is left).
+__device__ __forceinline__ uint64_t chain_tail(uint64_t alive, int32_t last,
+                                               const unsigned char *__restrict__ tile, int off,
+                                               const int32_t *__restrict__ c, int cb, int lane4,
+                                               uint32_t flip, float prevf, uint64_t &steps,
+                                               bool count)
+{
+    float prev = prevf;
+    for (int32_t u = kWin; u <= last && alive; ++u) {
+        const float v = flipped(*reinterpret_cast<const float *>(tile + c[u] * cb + lane4 + off), flip);
+        alive &= __ballot(v >= prev);
+        prev = v;
+        if (count) steps += 1;
+    }
+    return alive;
+}
+
+// One individual on one LDS-staged 64-row sub-tile S (v0, v1: this lane's
+// values of columns 0 and 1): its matched rows M and negative-only rows G.
+template <int L, int S, bool NEG, bool COUNT>
+__device__ __forceinline__ void eval_subtile(const unsigned char *__restrict__ tile, uint32_t tile_lds,
+                                             const uint32_t (&a)[kWin], const int32_t *__restrict__ c,
+                                             int32_t last, int lane4, uint64_t valid, float v0,
+                                             float v1, uint64_t &M, uint64_t &G, uint64_t &steps)
+{
+    constexpr int CB = L * kWave * 4;
+    constexpr int OFF = S * kWave * 4;
+    if (last == 0) {  // one column: the row counts unless its value is missing
+        M = __ballot(v0 == v0) & valid;
+        G = 0;
+        if (COUNT) steps += 1;
+        return;
+    }
+    if constexpr (NEG) {
+        uint64_t fall, tie, out;
+        float lastf;
+        uint32_t flip;
+        if constexpr (COUNT) {
+            const SubtileRef r{tile, tile_lds, OFF, a, &steps};
+            fall = __ballot(v1 < v0) & valid;
+            tie = __ballot(v1 == v0) & valid;
+            flip = v1 < v0 ? kSign : 0u;
+            steps += 3;
+            out = __ballot(v1 == v1 && v0 == v0) & valid;
+            lastf = flipped(v1, flip);
+            if (last >= 2) out = r.window(out, last, flip, lastf, lastf);
+        } else {
+            out = subtile_neg<OFF>(valid, last, a, kSign, v0, v1, fall, tie, flip, lastf);
+        }
+        if (last >= kWin && out) out = chain_tail(out, last, tile, OFF, c, CB, lane4, flip, lastf, steps, COUNT);
+        uint64_t m = out, g = out & fall;
+        if (tie) {
+            uint64_t tout = tie;
+            if (last >= 2) {
+                float tl;
+                if constexpr (COUNT) {
+                    const SubtileRef r{tile, tile_lds, OFF, a, &steps};
+                    tout = r.window(tie, last, kSign, flipped(v1, kSign), tl);
+                } else {
+                    tout = subtile_tie<OFF>(tie, last, a, kSign, v1, tl);
+                }
+                if (last >= kWin && tout)
+                    tout = chain_tail(tout, last, tile, OFF, c, CB, lane4, kSign, tl, steps, COUNT);
+            }
+            m |= tout;
+            g |= tout & ~out;
+        }
+        M = m;
+        G = g;
+    } else {
+        uint64_t out;
+        float lastf;
+        if constexpr (COUNT) {
+            const SubtileRef r{tile, tile_lds, OFF, a, &steps};
+            out = __ballot(v1 >= v0) & valid;
+            steps += 1;
+            lastf = v1;
+            if (last >= 2) out = r.window(out, last, 0u, lastf, lastf);
+        } else {
+            out = subtile_pos<OFF>(valid, last, a, v0, v1, lastf);
+        }
+        if (last >= kWin && out) out = chain_tail(out, last, tile, OFF, c, CB, lane4, 0u, lastf, steps, COUNT);
+        M = out;
+        G = 0;
+    }
+}
+
+// One individual on the L LDS-staged sub-tiles of a chunk, one sub-tile at a
+// time (each with its own early exit).
 template <int L, bool NEG, bool COUNT>
-__device__ __forceinline__ void eval_lds(const unsigned char *__restrict__ tile, const IndHead &h,
-                                         const int32_t *__restrict__ colidx, int lane4,
-                                         const uint64_t (&valid)[L], uint64_t (&M)[L],
-                                         uint64_t (&G)[L], uint64_t &steps)
+__device__ __forceinline__ void eval_lds(const unsigned char *__restrict__ tile, int32_t last,
+                                         const int32_t *__restrict__ c, const int4 &w03,
+                                         const int4 &w47, int lane4, const uint64_t (&valid)[L],
+                                         uint64_t (&M)[L], uint64_t (&G)[L], uint64_t &steps)
 {
     constexpr int CB = L * kWave * 4;  // bytes of one staged column
-    const int32_t last = h.k - 1;
-    const uint64_t more2 = ones_if_greater(last, 2);
-    const uint64_t more4 = ones_if_greater(last, 4);
-    const uint64_t more6 = ones_if_greater(last, 6);
-    const uint64_t more7 = ones_if_greater(last, 7);
-
-    uint64_t P[L], N[L];
-    float prev[L];
-    {
-        const unsigned char *b = tile + h.win[0] * CB + lane4;
+    const uint32_t tile_lds = lds_addr(tile);
+    const uint32_t base = tile_lds + lane4;
+    const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
+    uint32_t a[kWin];
 #pragma unroll
-        for (int s = 0; s < L; ++s) {
-            prev[s] = *reinterpret_cast<const float *>(b + s * kWave * 4);
-            // A missing first value removes the row (exclude mode); in include
-            // mode no NaN is staged, so this only drops rows past the end.
-            P[s] = __ballot(prev[s] == prev[s]) & valid[s];
-            N[s] = NEG ? P[s] : 0ull;
-        }
-        if (COUNT) steps += L;
-    }
-    auto live = [&]() {
-        uint64_t x = 0;
-#pragma unroll
-        for (int s = 0; s < L; ++s) x |= P[s] | N[s];
-        return x;
-    };
-#define EBIC_STEP(col)                                                             \
-    {                                                                              \
-        const unsigned char *b_ = tile + (col) * CB + lane4;                       \
-        _Pragma("unroll") for (int s = 0; s < L; ++s)                              \
-        {                                                                          \
-            const float v_ = *reinterpret_cast<const float *>(b_ + s * kWave * 4); \
-            /* Ordered compares: false when either side is NaN, so a missing */   \
-            /* value anywhere along the chain removes the row from both trends. */ \
-            P[s] &= __ballot(v_ >= prev[s]);                                       \
-            if (NEG) N[s] &= __ballot(v_ <= prev[s]);                              \
-            prev[s] = v_;                                                          \
-        }                                                                          \
-        if (COUNT) steps += L;                                                     \
-    }
-    if (last == 0) goto done;
-    EBIC_STEP(h.win[1]);
-    EBIC_STEP(h.win[2]);
-    if ((live() & more2) == 0) goto done;
-    EBIC_STEP(h.win[3]);
-    EBIC_STEP(h.win[4]);
-    if ((live() & more4) == 0) goto done;
-    EBIC_STEP(h.win[5]);
-    EBIC_STEP(h.win[6]);
-    if ((live() & more6) == 0) goto done;
-    EBIC_STEP(h.win[7]);
-    if ((live() & more7) == 0) goto done;
-    for (int32_t u = kWin; u <= last; u += 2) {
-        EBIC_STEP(colidx[h.begin + u]);
-        EBIC_STEP(colidx[h.begin + min(u + 1, last)]);
-        if (live() == 0) break;
-    }
-#undef EBIC_STEP
-done:
+    for (int u = 0; u < kWin; ++u) a[u] = base + w[u] * CB;
+    // The first pair of every sub-tile is loaded up front, so only the first
+    // sub-tile waits for it.
+    float v0[L], v1[L];
 #pragma unroll
     for (int s = 0; s < L; ++s) {
-        M[s] = P[s] | N[s];
-        G[s] = N[s] & ~P[s];
+        v0[s] = *reinterpret_cast<const float *>(tile + (a[0] - tile_lds) + s * kWave * 4);
+        v1[s] = *reinterpret_cast<const float *>(tile + (a[1] - tile_lds) + s * kWave * 4);
+    }
+    eval_subtile<L, 0, NEG, COUNT>(tile, tile_lds, a, c, last, lane4, valid[0], v0[0], v1[0], M[0], G[0], steps);
+    if constexpr (L > 1)
+        eval_subtile<L, 1, NEG, COUNT>(tile, tile_lds, a, c, last, lane4, valid[1], v0[1], v1[1], M[1], G[1], steps);
+    if constexpr (L > 2) {
+        eval_subtile<L, 2, NEG, COUNT>(tile, tile_lds, a, c, last, lane4, valid[2], v0[2], v1[2], M[2], G[2], steps);
+        eval_subtile<L, 3, NEG, COUNT>(tile, tile_lds, a, c, last, lane4, valid[3], v0[3], v1[3], M[3], G[3], steps);
     }
 }
 
@@ -198,13 +441,11 @@ done:
 // that every read stays inside the matrix).
 template <int L, bool NEG, bool COUNT>
 __device__ __forceinline__ void eval_direct(const float *__restrict__ xr, int64_t ld,
-                                            const int64_t (&sub)[L], const IndHead &h,
-                                            const int32_t *__restrict__ colidx, float fill,
+                                            const int64_t (&sub)[L], int32_t last,
+                                            const int32_t *__restrict__ c, float fill,
                                             bool subst, const uint64_t (&valid)[L],
                                             uint64_t (&M)[L], uint64_t (&G)[L], uint64_t &steps)
 {
-    const int32_t last = h.k - 1;
-    const int32_t *c = colidx + h.begin;
     auto load = [&](int32_t col, int s) {
         float v = xr[(int64_t)col * ld + sub[s]];
         if (subst) v = v != v ? fill : v;
@@ -254,9 +495,26 @@ __device__ __forceinline__ void store_words(uint64_t *__restrict__ dst, const ui
 }
 
 // ---------------------------------------------------------------------------
+// The header fields the evaluation uses (length, CSR start, window), read
+// with scalar loads and materialised together: one scalar-memory round trip
+// instead of a dependent load per field on the early-exit path.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void load_head(const IndHead *__restrict__ hb, int32_t ii, int4 (&hv)[3])
+{
+    const int4 *p = reinterpret_cast<const int4 *>(hb + ii);
+    hv[0] = p[0];  // k, begin
+    hv[1] = p[2];  // win[0..3]
+    hv[2] = p[3];  // win[4..7]
+    asm volatile("" ::"s"(hv[0].x), "s"(hv[0].y), "s"(hv[1].x), "s"(hv[1].y), "s"(hv[1].z),
+                 "s"(hv[1].w), "s"(hv[2].x), "s"(hv[2].y), "s"(hv[2].z), "s"(hv[2].w));
+}
+
+// ---------------------------------------------------------------------------
 // One work item: individuals [i0, i0 + np) of request d on tiles [t0, t1).
-// `tile` and `cnt` are this block's LDS areas. Ends with a barrier, so a
-// persistent block can start its next item right away.
+// `tile` and `cnt` are this block's LDS areas; wave w takes the group's
+// individuals w, w + W, w + 2W, ... on every chunk, so each count has a
+// single writer. Ends with a barrier, so a persistent block can start its
+// next item right away.
 // ---------------------------------------------------------------------------
 template <int L, bool NEG, int STAGE, bool COUNT>
 __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__restrict__ heads,
@@ -266,7 +524,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
     constexpr int T = L * kWave;
     const int lane = threadIdx.x & (kWave - 1);
     // Wave index as a scalar: every per-individual quantity derived from it
-    // (headers, column indices, masks) then lives in scalar registers.
+    // (lengths, column indices, masks) then lives in scalar registers.
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int W = blockDim.x / kWave;
     const int64_t words = (d.rows + 63) / 64;
@@ -304,19 +562,18 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         }
 
         for (int32_t ii = wave; ii < np; ii += W) {
-            const IndHead h = hb[ii];
-            // Materialise the whole header at once: one scalar-memory round
-            // trip instead of a dependent load per field on the early-exit path.
-            asm volatile("" ::"s"(h.k), "s"(h.begin), "s"(h.win[0]), "s"(h.win[1]), "s"(h.win[2]),
-                         "s"(h.win[3]), "s"(h.win[4]), "s"(h.win[5]), "s"(h.win[6]), "s"(h.win[7]));
+            int4 hv[3];
+            load_head(hb, ii, hv);
+            const int32_t k = hv[0].x;
             uint64_t M[L], G[L];
-            if (h.k == 0) {
+            if (k == 0) {
 #pragma unroll
                 for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
             } else {
+                const int32_t *c = d.colidx + hv[0].y;
                 if constexpr (STAGE == STAGE_LDS) {
-                    eval_lds<L, NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), h, d.colidx,
-                                            lane * 4, valid, M, G, steps);
+                    eval_lds<L, NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1, c,
+                                            hv[1], hv[2], lane * 4, valid, M, G, steps);
                 } else {
                     // Sub-tiles past the last tile are clamped onto it (their
                     // rows are masked out by `valid`).
@@ -324,7 +581,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                     int64_t sub[L];
 #pragma unroll
                     for (int s = 0; s < L; ++s) sub[s] = min<int64_t>(row0 + s * kWave, last_row0) - row0;
-                    eval_direct<L, NEG, COUNT>(d.X + row0 + lane, d.ld, sub, h, d.colidx, d.fill,
+                    eval_direct<L, NEG, COUNT>(d.X + row0 + lane, d.ld, sub, k - 1, c, d.fill,
                                                (d.flags & kFlagSubst) != 0, valid, M, G, steps);
                 }
                 int32_t pm = 0, pg = 0;
@@ -357,7 +614,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
 // Plain evaluation: block (x, y) = tile range x of individual group y.
 // ---------------------------------------------------------------------------
 template <int L, bool NEG, int STAGE, bool COUNT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 k_eval(ReqDesc d, const IndHead *__restrict__ heads, int32_t P, int32_t n_tiles,
        unsigned long long *step_counter)
 {
@@ -382,15 +639,16 @@ k_eval(ReqDesc d, const IndHead *__restrict__ heads, int32_t P, int32_t n_tiles,
 // (matrix, population, flags, outputs).
 // ---------------------------------------------------------------------------
 template <int L, bool COUNT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 k_eval_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs, const Item *__restrict__ items,
-             const IndHead *__restrict__ heads, int32_t tile_bytes,
+             const IndHead *__restrict__ heads, int32_t tile_bytes, int32_t P,
              unsigned long long *step_counter)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t s_item;
     float *tile = reinterpret_cast<float *>(smem);
     int32_t *cnt = reinterpret_cast<int32_t *>(smem + tile_bytes);
+    (void)P;
     const int32_t n_items = __builtin_amdgcn_readfirstlane(hdr->n_items);
     uint64_t steps = 0;
     while (true) {
@@ -539,8 +797,9 @@ hipError_t launch_batch(BatchHeader *hdr, const ReqDesc *descs, const int64_t *f
     const Item *it = items;
     const IndHead *hh = heads;
     int32_t tb = (int32_t)tile_bytes;
+    int32_t PP = P;
     unsigned long long *sc = step_counter;
-    void *params[] = {&h, &dd, &it, &hh, &tb, &sc};
+    void *params[] = {&h, &dd, &it, &hh, &tb, &PP, &sc};
     if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
     e = hipLaunchKernel(k, dim3(grid), dim3(W * kWave), params, lds, s);
     if (e != hipSuccess) return e;

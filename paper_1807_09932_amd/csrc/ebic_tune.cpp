@@ -41,13 +41,18 @@ static TuneKey batch_key(int64_t total_ind, int64_t mean_rows, int32_t max_cols)
     return TuneKey{1, log2_bucket(mean_rows), log2_bucket(max_cols), log2_bucket(total_ind), 0};
 }
 
+// Defaults measured on MI355X for the 436,444 x 64 workload: four 64-row
+// tiles per chunk while the tile fits twice in LDS, sixteen waves per block
+// (two blocks, 32 waves per CU), groups of 400 individuals.
+static int32_t default_L(int32_t cols) { return cols <= 64 ? 4 : (cols <= 128 ? 2 : 1); }
+
 LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
 {
     (void)rows;
     LaunchCfg c;
-    c.W = 8;
-    c.P = std::max(1, std::min(n, 1024));
-    c.L = cols <= 96 ? 2 : 1;
+    c.W = 16;
+    c.P = std::max(1, std::min(n, 400));
+    c.L = default_L(cols);
     c.staging = STAGE_LDS;
     c.blocks = 0;
     return c;
@@ -56,9 +61,9 @@ LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
 LaunchCfg default_batch_cfg(int32_t max_cols)
 {
     LaunchCfg c;
-    c.W = 8;
-    c.P = 512;
-    c.L = max_cols <= 96 ? 2 : 1;
+    c.W = 16;
+    c.P = 400;
+    c.L = default_L(max_cols);
     c.staging = STAGE_LDS;
     c.blocks = 0;
     return c;

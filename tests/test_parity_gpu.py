@@ -249,3 +249,30 @@ def test_error_paths(ctx):
     with pytest.raises(ebic.EbicError) as e:
         ctx.release(mat)
     assert e.value.status == ebic.EBIC_ENOENT
+
+
+@pytest.mark.parametrize("tiles_per_wave", [1, 2, 4])
+def test_measurement_variant_agrees(ctx, tiles_per_wave):
+    """The step-counting kernel variant (profiling mode 2) computes the same
+    outputs as the timed one, and counts a positive number of steps."""
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(700 + tiles_per_wave)
+    X = rng.integers(0, 5, size=(3000, 30)).astype(np.float32)
+    X[rng.random(X.shape) < 0.02] = np.float32(np.nan)
+    offs, cols = _random_pop(rng, 30, 150, 20, dup=0.05, bad=0.02)
+    mat = ctx.upload(X)
+    try:
+        ctx.set_launch_shape(tiles_per_wave, 4, 50, 0, 0)
+        ebic.ebic_set_profiling(ctx.handle, 3)
+        for include in (False, True):
+            for negative in (False, True):
+                announce("counting variant", tiles_per_wave, include, negative)
+                got = gpu_eval(ctx, mat, offs, cols, include=include, negative=negative)
+                want = oracle_eval(X, offs, cols, include=include, negative=negative)
+                assert_same(got, want, f"counting L={tiles_per_wave}")
+        launches, ms, steps = ebic.ebic_read_profile(ctx.handle)
+        assert launches == 4 and ms > 0 and steps > 0
+    finally:
+        ebic.ebic_set_profiling(ctx.handle, 0)
+        ctx.set_launch_shape()
+        ctx.release(mat)
