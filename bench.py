@@ -36,10 +36,15 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("ebic_eval.hip", "ebic_internal.h")
+
+
 def kernel_sources_sha():
+    """Digest of the evaluation kernel's sources (the counters in profiles/
+    are valid only for the kernel they were taken on)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1807_09932_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -145,7 +150,8 @@ def main():
     else:
         # The library's autotuner picks the launch shape for this shape class.
         ctx.autotune([ctx.request(mat, p, out, include=False, negative=True)])
-        shape_note = "autotuned"
+        L, W, P, stg, blocks = ebic.ebic_plan_shape(ctx.handle, mat, n, int(offs[-1]))
+        shape_note = f"autotuned: L={L} W={W} P={P} staging={stg} blocks={blocks}"
     log(f"launch shape: {shape_note}")
 
     # Spot check against the oracle on a sample of individuals.

@@ -199,6 +199,16 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
                                   int32_t individuals_per_group, int32_t staging, int32_t blocks);
 
 /*
+ * The launch shape an evaluation of n_ind individuals (nnz columns in all,
+ * or -1 if unknown) on `matrix` would use now: the forced shape if one is
+ * set, else the tuned one for its shape class, else the default, reduced to
+ * what the device fits. Any output may be NULL. Staging: 0 = LDS, 1 = direct.
+ */
+ebic_status ebic_plan_shape(ebic_ctx *ctx, int32_t matrix, int32_t n_ind, int64_t nnz,
+                            int32_t *tiles_per_wave, int32_t *waves_per_block,
+                            int32_t *individuals_per_group, int32_t *staging, int32_t *blocks);
+
+/*
  * Measurement diagnostics. `mode` bit 0: record a HIP event pair on the
  * caller's stream around every evaluation kernel this context launches;
  * bit 1: count executed predicate steps (one step = one column of one

@@ -400,6 +400,25 @@ ebic_status ebic_eval_population(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
     });
 }
 
+ebic_status ebic_plan_shape(ebic_ctx *ctx, int32_t matrix, int32_t n_ind, int64_t nnz,
+                            int32_t *tiles_per_wave, int32_t *waves_per_block,
+                            int32_t *individuals_per_group, int32_t *staging, int32_t *blocks)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        if (n_ind <= 0) fail(EBIC_EINVAL, "n_ind must be >= 1");
+        DeviceGuard g(ctx->device);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        const Matrix &m = ctx_matrix(ctx, matrix);
+        const LaunchCfg c = plan_eval(ctx, m, n_ind, nnz, EBIC_NEG_TRENDS);
+        if (tiles_per_wave) *tiles_per_wave = c.L;
+        if (waves_per_block) *waves_per_block = c.W;
+        if (individuals_per_group) *individuals_per_group = c.P;
+        if (staging) *staging = c.staging;
+        if (blocks) *blocks = c.blocks;
+    });
+}
+
 ebic_status ebic_set_profiling(ebic_ctx *ctx, int32_t mode)
 {
     return guarded([&] {

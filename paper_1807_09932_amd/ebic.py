@@ -42,7 +42,8 @@ STAGE_DIRECT = 1
 EXPORTED = ["ebic_create", "ebic_destroy", "ebic_set_allocator", "ebic_last_error",
             "ebic_upload_matrix", "ebic_matrix_info", "ebic_release_matrix",
             "ebic_mask_words", "ebic_eval_population", "ebic_eval_batch", "ebic_autotune",
-            "ebic_set_launch_shape", "ebic_set_profiling", "ebic_read_profile"]
+            "ebic_set_launch_shape", "ebic_set_profiling", "ebic_read_profile",
+            "ebic_plan_shape"]
 
 
 class EbicError(RuntimeError):
@@ -89,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "ebic_autotune": (I32, [P, ctypes.POINTER(ebic_request), I32, ctypes.c_char_p]),
         "ebic_set_launch_shape": (I32, [P, I32, I32, I32, I32, I32]),
         "ebic_set_profiling": (I32, [P, I32]),
+        "ebic_plan_shape": (I32, [P, I32, I32, I64] + [ctypes.POINTER(I32)] * 5),
         "ebic_read_profile": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(I64)]),
     }
@@ -175,6 +177,13 @@ def ebic_set_launch_shape(ctx: int, tiles_per_wave: int, waves_per_block: int,
                           individuals_per_group: int, staging: int, blocks: int) -> None:
     _check(load_library().ebic_set_launch_shape(ctx, tiles_per_wave, waves_per_block,
                                                 individuals_per_group, staging, blocks))
+
+
+def ebic_plan_shape(ctx: int, matrix: int, n_ind: int, nnz: int = -1) -> Tuple[int, int, int, int, int]:
+    """(tiles_per_wave, waves_per_block, individuals_per_group, staging, blocks)."""
+    v = [ctypes.c_int32() for _ in range(5)]
+    _check(load_library().ebic_plan_shape(ctx, matrix, n_ind, nnz, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
 
 
 def ebic_set_profiling(ctx: int, mode: int) -> None:

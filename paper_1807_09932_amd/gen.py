@@ -183,34 +183,51 @@ def config5_matrices(scale: float = 1.0):
     return out
 
 
+def population_fast(rng: np.random.Generator, ncols: int, n: int, k_range=(2, 30)):
+    """CSR population of n individuals, lengths uniform in k_range, distinct
+    columns per individual (vectorised: the first k entries of a random
+    permutation per row)."""
+    kmax = min(k_range[1], ncols)
+    k = rng.integers(k_range[0], kmax + 1, size=n)
+    perm = np.argsort(rng.random((n, ncols)), axis=1)[:, :kmax].astype(np.int32)
+    offs = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(k, out=offs[1:])
+    take = np.arange(kmax)[None, :] < k[:, None]
+    return offs.astype(np.int32), perm[take]
+
+
 @dataclasses.dataclass
 class Request:
     t_arrival: float          # seconds from the start of the stream
-    run: int                  # EBIC run id (0..15)
+    run: int                  # EBIC run id (0..n_runs-1)
     matrix: int               # resident matrix index (run mod 4)
-    individuals: List[np.ndarray]
+    pool_index: int           # population in that matrix's pool
+
+
+def config5_pools(pool_size: int = 32, n_range=(100, 800), k_range=(2, 30)):
+    """Per resident matrix, `pool_size` seeded populations (CSR): the
+    generations the served runs submit are drawn from these."""
+    pools = []
+    for m, (_, c, _) in enumerate(CONFIG5_SHAPES):
+        rng = rng_for(5, 100 + m)
+        pools.append([population_fast(rng, c, int(rng.integers(n_range[0], n_range[1] + 1)), k_range)
+                      for _ in range(pool_size)])
+    return pools
 
 
 def config5_requests(duration_s: float, rate_hz: float = 2000.0, n_runs: int = 16,
-                     cols: Sequence[int] = tuple(c for _, c, _ in CONFIG5_SHAPES),
-                     n_range=(100, 800), k_range=(2, 30), max_requests: int | None = None):
-    """Poisson arrivals from ``n_runs`` concurrent runs; run j uses matrix j mod 4."""
+                     pool_size: int = 32):
+    """Poisson arrivals (mean rate_hz) from n_runs concurrent runs; run j
+    uses matrix j mod 4 and submits populations from that matrix's pool."""
     rng = rng_for(5, 7)
-    t = 0.0
-    reqs: List[Request] = []
-    while True:
-        t += rng.exponential(1.0 / rate_hz)
-        if t >= duration_s or (max_requests is not None and len(reqs) >= max_requests):
-            break
-        run = int(rng.integers(0, n_runs))
-        m = run % len(cols)
-        n = int(rng.integers(n_range[0], n_range[1] + 1))
-        inds = []
-        for _ in range(n):
-            k = int(rng.integers(k_range[0], min(k_range[1], cols[m]) + 1))
-            inds.append(rng.choice(cols[m], k, replace=False).astype(np.int32))
-        reqs.append(Request(t, run, m, inds))
-    return reqs
+    n = int(rng.poisson(rate_hz * duration_s * 1.2)) + 16
+    gaps = rng.exponential(1.0 / rate_hz, size=n)
+    t = np.cumsum(gaps)
+    t = t[t < duration_s]
+    runs = rng.integers(0, n_runs, size=t.size)
+    picks = rng.integers(0, pool_size, size=t.size)
+    return [Request(float(t[i]), int(runs[i]), int(runs[i]) % len(CONFIG5_SHAPES), int(picks[i]))
+            for i in range(t.size)]
 
 
 def nominal_checks(rows: int, offsets: np.ndarray) -> int:
