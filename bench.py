@@ -87,6 +87,211 @@ def _cpu_model():
     return "unknown"
 
 
+def _timed(fn, reps, stream):
+    """Median wall-clock ms of fn() over reps calls, synchronised each time."""
+    import torch
+    out = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        stream.synchronize()
+        out.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(out))
+
+
+def bench_batched(ctx, args):
+    """64 populations of uneven size (100..1,600 individuals) and skewed
+    lengths against one resident 100,000 x 256 matrix: one batched launch
+    (a replayed HIP graph) against 64 plain launches, both tuned."""
+    import torch
+    from paper_1807_09932_amd import ebic, gen
+    log("batched: generating 64 populations over a 100,000 x 256 matrix")
+    w, pops = gen.config4()
+    mat = ctx.upload(w.X)
+    packed = [gen.csr(p) for p in pops]
+    dev = [ctx.population(offsets=o, cols=c) for o, c in packed]
+    outs_b = [ctx.outputs(mat, p.n) for p in dev]
+    outs_p = [ctx.outputs(mat, p.n) for p in dev]
+    reqs = [ctx.request(mat, p, o) for p, o in zip(dev, outs_b)]
+    rows = w.X.shape[0]
+    checks = sum(gen.nominal_checks(rows, o) for o, _ in packed)
+    n_total = sum(p.n for p in dev)
+    log("batched: autotuning plain and batched shapes")
+    ctx.set_launch_shape(0, 0, 0, ebic.STAGE_LDS, 0)
+    ctx.autotune(reqs)
+    stream = torch.cuda.current_stream()
+
+    def batched():
+        ctx.eval_batch(reqs)
+
+    def plain():
+        for p, o in zip(dev, outs_p):
+            ctx.eval(mat, p, out=o)
+
+    batched()
+    plain()
+    torch.cuda.synchronize()
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+               for a, b in zip(outs_b, outs_p))
+    if not same:
+        print("bench.py: batched and plain counts differ", file=sys.stderr)
+        sys.exit(3)
+    # Oracle spot check on two populations.
+    import oracle
+    for q in (0, len(pops) - 1):
+        o, c = packed[q]
+        om, on, _, _ = oracle.eval_population(w.X, o, c, negative=True,
+                                              threads=max(1, min(16, os.cpu_count() or 1)))
+        if not (np.array_equal(outs_b[q][0].cpu().numpy(), om) and
+                np.array_equal(outs_b[q][1].cpu().numpy(), on)):
+            print("bench.py: batched counts differ from the oracle", file=sys.stderr)
+            sys.exit(3)
+    for _ in range(3):
+        batched()
+        plain()
+    reps = 20
+    b_ms = _timed(batched, reps, stream)
+    p_ms = _timed(plain, reps, stream)
+    ctx.release(mat)
+    return {
+        "workload": "64 populations (%d individuals, lengths 2 + min(38, Exp(mean 5)), "
+                    "%.3e nominal checks) over one 100,000 x 256 N(0,1) matrix" % (n_total, checks),
+        "batched_ms": b_ms, "plain_ms": p_ms,
+        "batched_checks_per_s": checks / (b_ms * 1e-3),
+        "plain_checks_per_s": checks / (p_ms * 1e-3),
+        "speedup": p_ms / b_ms,
+        "equal_results": True,
+        "timing": "median of %d synchronised calls; batched = one ebic_eval_batch (descriptor "
+                  "copy + graph replay), plain = 64 ebic_eval_population calls" % reps,
+    }
+
+
+def bench_served(ctx, args):
+    """Continuous batching of Poisson requests (mean 2,000 req/s) from 16
+    EBIC runs over 4 resident matrices; then a closed-loop saturation run and
+    the same requests served one plain launch at a time."""
+    import torch
+    from paper_1807_09932_amd import gen
+    from paper_1807_09932_amd.serve import Server
+    log("served: uploading 4 matrices, generating request pools")
+    ws = gen.config5_matrices()
+    mats = [ctx.upload(x.X) for x in ws]
+    pools = gen.config5_pools()
+    rows = [x.X.shape[0] for x in ws]
+    resident = sum(x.X.nbytes for x in ws)
+    budget = 1 << 30
+    dur = args.serve_warmup + args.serve_seconds
+    reqs = gen.config5_requests(dur)
+    out = {"workload": "4 resident matrices (10,000 x 100, 50,000 x 200 N(0,1); 200,000 x 64, "
+                       "436,444 x 64 Beta(0.5,0.5); %.0f MB); 16 runs, run j on matrix j mod 4; "
+                       "populations of 100-800 individuals of 2-30 columns" % (resident / 1e6),
+           "hbm_budget_bytes": budget}
+
+    def req_checks(r):
+        o, _ = pools[r.matrix][r.pool_index]
+        return gen.nominal_checks(rows[r.matrix], o)
+
+    # Open loop: Poisson arrivals at the scheduled times.
+    with Server(ctx, hbm_budget_bytes=budget, slots=4) as srv:
+        # warm the graphs / allocator with a few requests first
+        for f in [srv.submit(0, mats[m], *pools[m][0]) for m in range(4)]:
+            f.result(timeout=60)
+        log(f"served: open loop, {len(reqs)} requests over {dur:.1f} s")
+        t0 = time.perf_counter()
+        futs = []
+        for r in reqs:
+            due = t0 + r.t_arrival
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                time.sleep(min(2e-4, due - now))
+            lag = time.perf_counter() - due
+            o, c = pools[r.matrix][r.pool_index]
+            futs.append((r, lag, srv.submit(r.run, mats[r.matrix], o, c)))
+        lat, done_checks = [], 0
+        t_end = 0.0
+        for r, lag, f in futs:
+            res = f.result(timeout=120)
+            if r.t_arrival >= args.serve_warmup:
+                lat.append(res.latency_s + lag)
+                done_checks += req_checks(r)
+        t_end = time.perf_counter() - t0
+        st = srv.stats()
+    lat = np.array(lat) * 1e3
+    offered = done_checks / args.serve_seconds
+    out["open_loop"] = {
+        "rate_hz": 2000.0, "requests": int(lat.size), "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)), "offered_checks_per_s": offered,
+        "drain_s_after_last_arrival": max(0.0, t_end - dur),
+        "mean_batch": st["mean_batch"], "admitted_bytes_high_water": st["admitted_bytes_high_water"],
+        "latency": "scheduled arrival to result on the host",
+    }
+    log(f"served: open loop p50 {out['open_loop']['p50_ms']:.2f} ms "
+        f"p99 {out['open_loop']['p99_ms']:.2f} ms")
+
+    # Closed loop: a fixed number of requests always outstanding.
+    seq = reqs[: min(len(reqs), 6000)]
+    for depth in (16, 256):
+        with Server(ctx, hbm_budget_bytes=budget, slots=4) as srv:
+            it = iter(seq)
+            pending = []
+            done_checks = 0
+            t0 = time.perf_counter()
+            lat = []
+            import collections
+            q = collections.deque()
+            for _ in range(depth):
+                r = next(it, None)
+                if r is None:
+                    break
+                o, c = pools[r.matrix][r.pool_index]
+                q.append((r, srv.submit(r.run, mats[r.matrix], o, c)))
+            while q:
+                r, f = q.popleft()
+                res = f.result(timeout=120)
+                lat.append(res.latency_s)
+                done_checks += req_checks(r)
+                nr = next(it, None)
+                if nr is not None:
+                    o, c = pools[nr.matrix][nr.pool_index]
+                    q.append((nr, srv.submit(nr.run, mats[nr.matrix], o, c)))
+            el = time.perf_counter() - t0
+            st = srv.stats()
+        lat = np.array(lat) * 1e3
+        out[f"closed_loop_{depth}"] = {
+            "outstanding": depth, "requests": len(seq), "checks_per_s": done_checks / el,
+            "requests_per_s": len(seq) / el, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_batch": st["mean_batch"],
+            "admitted_bytes_high_water": st["admitted_bytes_high_water"]}
+        log(f"served: closed loop depth {depth}: {done_checks / el:.3e} checks/s")
+
+    # The same requests, one plain launch each, synchronously.
+    seq = reqs[: min(len(reqs), 2000)]
+    lat = []
+    done_checks = 0
+    t0 = time.perf_counter()
+    for r in seq:
+        t1 = time.perf_counter()
+        o, c = pools[r.matrix][r.pool_index]
+        p = ctx.population(offsets=o, cols=c)
+        m, g, _, _ = ctx.eval(mats[r.matrix], p)
+        m.cpu(), g.cpu()
+        lat.append(time.perf_counter() - t1)
+        done_checks += req_checks(r)
+    el = time.perf_counter() - t0
+    lat = np.array(lat) * 1e3
+    out["plain_per_request"] = {
+        "requests": len(seq), "checks_per_s": done_checks / el, "requests_per_s": len(seq) / el,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "how": "one ebic_eval_population per request, population copied in and counts copied "
+               "back synchronously, one request at a time"}
+    for m in mats:
+        ctx.release(m)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +306,12 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times), to scale "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
+    ap.add_argument("--extras", type=str, default="batch,serve",
+                    help="comma list of extra measurements: 'batch' (64 populations in one "
+                         "batched launch vs 64 plain launches), 'serve' (Poisson requests from "
+                         "16 runs over 4 resident matrices); '' for none")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -266,12 +477,21 @@ def main():
         },
     }
     ctx.release(mat)
+    extras = {x for x in args.extras.split(",") if x}
+    if "batch" in extras:
+        result["batched"] = bench_batched(ctx, args)
+    if "serve" in extras:
+        result["served"] = bench_served(ctx, args)
     ctx.close()
 
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
         log(f"timing the CPU oracle with {threads} threads")
         result["cpu_baseline"] = cpu_baseline(w, offs, cols, threads)
+        if threads > 1:
+            log("timing the CPU oracle on one thread")
+            one = cpu_baseline(w, offs, cols, 1)
+            result["cpu_baseline"]["single_thread_value"] = one["value"]
     else:
         result["cpu_baseline"] = None
     print(json.dumps(result))
