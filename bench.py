@@ -167,6 +167,49 @@ def bench_batched(ctx, args):
     }
 
 
+def bench_ea(ctx, args, w=None):
+    """The stand-in evolutionary loop around the evaluation on the 436,444 x 64
+    matrix: 800 individuals per generation; per generation the host driver
+    breeds, the population goes to the device, is evaluated, and its counts
+    come back."""
+    import torch
+    from paper_1807_09932_amd import ebic, gen
+    if w is None:
+        w, _ = gen.config3()
+    rows, ncols = w.X.shape
+    mat = ctx.upload(w.X)
+    ea = ebic.EA(ncols, 800, 2, 30, seed=180709932)
+    gens = 40
+    t_host = t_dev = 0.0
+    checks = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(gens):
+        t1 = time.perf_counter()
+        offs, cols, _ = ea.population()
+        t2 = time.perf_counter()
+        pop = ctx.population(offsets=offs, cols=cols)
+        m, _, _, _ = ctx.eval(mat, pop, negative=True)
+        counts = m.cpu().numpy()
+        t3 = time.perf_counter()
+        ea.step(counts)
+        t4 = time.perf_counter()
+        t_host += (t2 - t1) + (t4 - t3)
+        t_dev += t3 - t2
+        checks += gen.nominal_checks(rows, offs)
+    el = time.perf_counter() - t0
+    ctx.release(mat)
+    ea.close()
+    return {"workload": "stand-in evolutionary loop, 800 individuals of 2-30 columns per "
+                        "generation, %d x %d matrix, %d generations" % (rows, ncols, gens),
+            "generations_per_s": gens / el, "ms_per_generation": el * 1e3 / gens,
+            "host_driver_ms_per_generation": t_host * 1e3 / gens,
+            "evaluation_ms_per_generation": t_dev * 1e3 / gens,
+            "checks_per_s": checks / el,
+            "evaluation": "population to the device, ebic_eval_population, matched counts back "
+                          "(synchronous)"}
+
+
 def bench_served(ctx, args):
     """Continuous batching of Poisson requests (mean 2,000 req/s) from 16
     EBIC runs over 4 resident matrices; then a closed-loop saturation run and
@@ -306,10 +349,11 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times), to scale "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
-    ap.add_argument("--extras", type=str, default="batch,serve",
+    ap.add_argument("--extras", type=str, default="batch,serve,ea",
                     help="comma list of extra measurements: 'batch' (64 populations in one "
                          "batched launch vs 64 plain launches), 'serve' (Poisson requests from "
-                         "16 runs over 4 resident matrices); '' for none")
+                         "16 runs over 4 resident matrices), 'ea' (the stand-in evolutionary "
+                         "loop around the evaluation); '' for none")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     args = ap.parse_args()
@@ -482,6 +526,8 @@ def main():
         result["batched"] = bench_batched(ctx, args)
     if "serve" in extras:
         result["served"] = bench_served(ctx, args)
+    if "ea" in extras:
+        result["evolutionary_loop"] = bench_ea(ctx, args, w)
     ctx.close()
 
     if not args.no_cpu_baseline:

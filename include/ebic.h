@@ -225,6 +225,180 @@ ebic_status ebic_set_profiling(ebic_ctx *ctx, int32_t mode);
 ebic_status ebic_read_profile(ebic_ctx *ctx, int64_t *launches, double *kernel_ms,
                               int64_t *executed_steps);
 
+/* ------------------------------------------------------------------------
+ * Serving: evaluations submitted by many concurrent EBIC runs (each run's
+ * evolutionary loop on the host asks for the counts of one population per
+ * generation, EBIC paper, Introduction and Methods), batched continuously
+ * onto one GPU. Host buffers in, host buffers out.
+ * ------------------------------------------------------------------------ */
+typedef struct ebic_server ebic_server;
+
+typedef struct ebic_server_stats {
+    int64_t submitted;        /* requests accepted (after the last reset) */
+    int64_t completed;        /* requests completed */
+    int64_t batches;          /* batched launches */
+    int64_t pending;          /* requests waiting for a slot or memory */
+    int64_t reserved_bytes;   /* device bytes held by batches in flight */
+    int64_t high_water_bytes; /* largest reserved_bytes seen */
+    int64_t budget_bytes;     /* the HBM budget */
+    int64_t nominal_checks;   /* rows x sum of lengths over completed requests */
+    double latency_p50_ms;    /* submission to completion */
+    double latency_p99_ms;
+    double mean_batch;        /* requests per batched launch */
+} ebic_server_stats;
+
+/*
+ * Device bytes one request holds while in flight (its CSR and outputs,
+ * 256-byte aligned): the quantity admission compares with the budget.
+ * masks != 0: both mask arrays (the negative one only with
+ * EBIC_NEG_TRENDS) are returned.
+ */
+ebic_status ebic_server_request_bytes(ebic_ctx *ctx, int32_t matrix, int32_t n_ind, int64_t nnz,
+                                      uint32_t flags, int32_t masks, int64_t *out_bytes);
+
+/*
+ * Start a server on `ctx`: a device arena of hbm_budget_bytes (from the
+ * context's allocator; it bounds the bytes of all batches in flight),
+ * `slots` streams (1..16, each with a pinned staging buffer and a completion
+ * thread) and a scheduler thread that launches up to max_batch waiting
+ * requests per slot as one ebic_eval_batch. The matrices stay owned by the
+ * context and must outlive the requests that use them.
+ */
+ebic_status ebic_server_create(ebic_ctx *ctx, int64_t hbm_budget_bytes, int32_t slots,
+                               int32_t max_batch, ebic_server **out);
+
+/*
+ * Complete every submitted request (their outputs are written), stop the
+ * threads and free the server's memory. Tags not yet polled are dropped.
+ */
+ebic_status ebic_server_destroy(ebic_server *srv);
+
+/*
+ * Queue one population evaluation. offsets (n_ind + 1 entries) and cols
+ * (max(offsets) entries) are host arrays, copied before the call returns.
+ * matched (n_ind), negative (n_ind, or NULL), matched_mask and
+ * negative_mask (n_ind * ebic_mask_words(rows) words each, or NULL; the
+ * negative mask needs `negative`) are host buffers that the server writes
+ * when the request completes: they must stay valid until ebic_server_poll
+ * returns `tag`. flags: EBIC_NAN_INCLUDE, EBIC_NEG_TRENDS. Results equal
+ * those of ebic_eval_population on the same inputs. Errors: EBIC_EINVAL
+ * (arguments, negative offsets), EBIC_ENOENT (unknown matrix), EBIC_EBUDGET
+ * (the request alone exceeds the budget), EBIC_EBUSY (shutting down).
+ */
+ebic_status ebic_server_submit(ebic_server *srv, int32_t matrix, int32_t n_ind,
+                               const int32_t *offsets, const int32_t *cols, uint32_t flags,
+                               int32_t *matched, int32_t *negative, uint64_t *matched_mask,
+                               uint64_t *negative_mask, uint64_t tag);
+
+/*
+ * Wait up to timeout_us microseconds for completed requests and return up to
+ * max_tags of their tags (and, if `statuses` is not NULL, each request's
+ * status: EBIC_OK, or the error of its batch's launch) in completion order.
+ */
+ebic_status ebic_server_poll(ebic_server *srv, uint64_t *tags, ebic_status *statuses,
+                             int32_t max_tags, int32_t timeout_us, int32_t *n_done);
+
+/* Counters and latency percentiles; reset != 0 starts a new window. */
+ebic_status ebic_server_get_stats(ebic_server *srv, ebic_server_stats *out, int32_t reset);
+
+/* ------------------------------------------------------------------------
+ * A stand-in evolutionary driver (host code). The paper gives EBIC's search
+ * only as evolutionary and driven by row counts (Introduction; Methods,
+ * "Handling missing values"), not its operators or fitness formula, so these
+ * are a stand-in of the same shape: tournament selection with elitism on
+ * fitness = matched * 2^(k-2) (invalid individuals last), one-point
+ * crossover, and one mutation (insert, delete, swap or substitute a column).
+ * Every random choice comes from SplitMix64 seeded with `seed`, so a run is
+ * a function of its parameters and the counts it is given.
+ * ------------------------------------------------------------------------ */
+typedef struct ebic_ea ebic_ea;
+
+typedef struct ebic_ea_params {
+    int32_t n_cols;      /* columns of the matrix the individuals index */
+    int32_t pop_size;    /* individuals per generation (>= 2) */
+    int32_t k_min;       /* individual length bounds, 1 <= k_min <= k_max <= n_cols */
+    int32_t k_max;
+    int32_t elite;       /* best individuals carried over unchanged, [0, pop_size) */
+    double p_crossover;  /* probability that a child comes from crossover */
+    double p_mutation;   /* probability that a child is mutated once */
+    uint64_t seed;
+} ebic_ea_params;
+
+/* A driver with a random first generation (distinct columns per individual). */
+ebic_status ebic_ea_create(const ebic_ea_params *params, ebic_ea **out);
+
+ebic_status ebic_ea_destroy(ebic_ea *ea);
+
+/*
+ * The current generation as host CSR (pop_size + 1 offsets, then the
+ * columns), owned by the driver and valid until the next ebic_ea_step or
+ * ebic_ea_destroy; any output may be NULL.
+ */
+ebic_status ebic_ea_population(ebic_ea *ea, const int32_t **offsets, const int32_t **cols,
+                               int32_t *n_ind, int64_t *generation);
+
+/*
+ * Score the current generation from its matched counts (pop_size entries,
+ * as returned by an evaluation of the CSR above; -1 marks an invalid
+ * individual), report its best individual, and replace it by the next
+ * generation.
+ */
+ebic_status ebic_ea_step(ebic_ea *ea, const int32_t *matched, int32_t *best_index,
+                         double *best_fitness);
+
+/* ------------------------------------------------------------------------
+ * Ingest and export (host code).
+ * ------------------------------------------------------------------------ */
+typedef struct ebic_text_matrix {
+    int64_t rows;
+    int32_t cols;
+    char delimiter;     /* the one used (given or detected) */
+    float *values;      /* column-major: values[c * rows + r]; missing = NaN */
+    char **row_names;   /* rows entries, or NULL when the file has none */
+    char **col_names;   /* cols entries, or NULL when the file has no header */
+} ebic_text_matrix;
+
+/*
+ * Read a delimited text matrix, genes in rows and samples in columns (EBIC
+ * paper, Methods, "Different input file formats support"): values separated
+ * by ',', '\t' or ';' (delimiter 0: the one of those most frequent on the
+ * first line); an optional header row (header -1: detected, a non-numeric
+ * field past the first; 0: none; 1: present) whose upper-left cell may be
+ * absent; optional row names in the first field (row_names -1: detected,
+ * 0, 1). Empty fields and NA, NaN, nan, na, ? are missing (NaN); other
+ * fields are decimal numbers, read as double and rounded to float. Blank
+ * lines are skipped; CR LF is accepted. `threads` (>= 1) parse lines in
+ * parallel. The result is ready for ebic_upload_matrix(src = values,
+ * ld_src = rows, flags = EBIC_SRC_COL_MAJOR); free it with
+ * ebic_free_text_matrix. Errors: EBIC_ENOENT (cannot open), EBIC_EINVAL
+ * (ragged lines, non-numeric values, with the line and field in
+ * ebic_last_error()).
+ */
+ebic_status ebic_read_delimited(const char *path, char delimiter, int32_t header,
+                                int32_t row_names, int32_t threads, ebic_text_matrix *out);
+
+/* Free what ebic_read_delimited allocated and zero the struct. */
+ebic_status ebic_free_text_matrix(ebic_text_matrix *m);
+
+/*
+ * Write the biclusters of the chosen individuals (EBIC paper, Methods,
+ * "Compatibility with R and Bioconductor") as text: a comment line, then
+ * per bicluster three tab-separated lines,
+ *   bicluster <b> <number of rows> <number of columns>
+ *   rows <row> <row> ...      (the set bits of its matched mask)
+ *   cols <col> <col> ...      (its columns in the individual's order)
+ * with 1-based indices, or the names when row_names / col_names are given.
+ *   offsets, cols: the population's host CSR (n_ind individuals).
+ *   matched_mask:  host copy of the evaluation's matched mask,
+ *                  n_ind x ebic_mask_words(rows) words.
+ *   which:         n_out individual indices in [0, n_ind).
+ */
+ebic_status ebic_write_biclusters(const char *path, int64_t rows, int32_t n_ind,
+                                  const int32_t *offsets, const int32_t *cols,
+                                  const uint64_t *matched_mask, int32_t n_out,
+                                  const int32_t *which, const char *const *row_names,
+                                  const char *const *col_names);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libebic.so")
 
-SOURCES = ["ebic_eval.hip", "ebic_layout.hip", "ebic_runtime.cpp", "ebic_tune.cpp", "ebic_batch.cpp"]
+SOURCES = ["ebic_eval.hip", "ebic_layout.hip", "ebic_runtime.cpp", "ebic_tune.cpp", "ebic_batch.cpp",
+           "ebic_serve.cpp", "ebic_ea.cpp", "ebic_io.cpp"]
 
 ARCH = os.environ.get("EBIC_OFFLOAD_ARCH", "gfx950")
 
@@ -53,7 +54,7 @@ def build(verbose: bool = False) -> str:
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-lpthread", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -184,10 +184,11 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
         const ReqDesc &d = p.descs[q];
         if (d.n == 0) continue;
         const int64_t tiles = (d.rows + 63) / 64;
+        const int64_t chunks = (tiles + c.L - 1) / c.L;  // ranges start on a multiple of L tiles
         const int32_t groups = (d.n + c.P - 1) / c.P;
         const double share = units > 0 ? target * (double)d.n * (double)tiles / units : 1.0;
         int64_t ranges = (int64_t)std::max(1.0, share / groups + 0.5);
-        ranges = std::min<int64_t>(ranges, std::max<int64_t>(1, tiles / c.L));
+        ranges = std::min<int64_t>(ranges, chunks);
         for (int32_t g = 0; g < groups; ++g) {
             const int32_t i0 = g * c.P;
             const int32_t np = std::min(c.P, d.n - i0);
@@ -196,8 +197,8 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
                 it.req = q;
                 it.i0 = i0;
                 it.np = np;
-                it.t0 = (int32_t)(r * tiles / ranges);
-                it.t1 = (int32_t)((r + 1) * tiles / ranges);
+                it.t0 = (int32_t)(r * chunks / ranges * c.L);
+                it.t1 = (int32_t)std::min<int64_t>(tiles, (r + 1) * chunks / ranges * c.L);
                 if (it.t1 <= it.t0) continue;
                 est.push_back({it, (double)np * (double)(it.t1 - it.t0)});
             }

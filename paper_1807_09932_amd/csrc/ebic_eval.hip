@@ -7,18 +7,21 @@
 // Data"). All outputs are integers decided by exact FP32 compares.
 //
 // Work decomposition. A work item is (a group of up to P individuals of one
-// population, a contiguous range of 64-row tiles of its matrix). The block
-// that owns an item walks the range L tiles at a time: it stages those
-// L*64 rows of every column into LDS (column-major, so lane l of a wave
-// reads bank l), then each wave takes every W-th individual of the group and
-// evaluates it on the L sub-tiles together: lane l holds row l of each
-// sub-tile; for each column step a pair of compares is reduced across the
-// wave with a ballot, so the running positive and negative masks of 64 rows
-// live in scalar registers; the individual stops as soon as no row of its
-// L sub-tiles can still match (a wave-uniform early exit). Counts are
-// popcounts of the masks, accumulated per block in LDS and added to global
-// memory once per item with integer atomics (order-independent, so results
-// are deterministic).
+// population, a contiguous range of 64-row tiles of its matrix, starting on
+// a multiple of L tiles). The block that owns an item walks the range L
+// tiles at a time: it stages those L*64 rows of every column into LDS
+// (column-major, so lane l of a wave reads bank l; rows outside the item or
+// the matrix hold NaN), then each wave takes every W-th individual of the
+// group and evaluates it on the L sub-tiles: lane l holds row l of each
+// sub-tile. After the first pair of columns each row follows one oriented
+// chain (falling rows are sign-flipped), so every further column is one XOR
+// and one compare per sub-tile, reduced across the wave into a 64-bit alive
+// mask in scalar registers. With L = 2 or 4 the sub-tiles run interleaved in
+// one instruction stream (independent compares hide each other's latency);
+// the individual stops as soon as no row of its L sub-tiles can still match
+// (a wave-uniform early exit). Counts are popcounts of the masks,
+// accumulated per block in LDS and added to global memory once per item with
+// integer atomics (order-independent, so results are deterministic).
 //
 // The plain kernel (one population) launches one block per item on a 2-D
 // grid. The batched kernel (many populations, many matrices) is persistent:
@@ -435,6 +438,343 @@ __device__ __forceinline__ void eval_lds(const unsigned char *__restrict__ tile,
     }
 }
 
+// ---------------------------------------------------------------------------
+// L sub-tiles interleaved (L = 2 or 4): one instruction stream evaluates the
+// same individual on all L sub-tiles of the chunk, each with its own alive
+// mask in scalar registers, so the compares of different sub-tiles are
+// independent and hide each other's latency. Column u of sub-tile s of this
+// lane sits at base + u*CB + s*256 bytes, one address per column.
+//
+// Register rotation: column u is loaded into set u mod 3; while column u is
+// compared (against set (u-1) mod 3) the loads of column u+1 are in flight.
+// Window columns past the last one repeat the last column (the header clamps
+// them), and a repeated column never removes a row (x >= x for every non-NaN
+// x; NaN rows are already gone), so the window may run past `last` without
+// changing the result; the exits after columns 3 and 5 only save work.
+// ---------------------------------------------------------------------------
+#define IL_LOAD4(r, w)                                                         \
+    "v_lshl_add_u32 %[ad], %[" w "], 10, %[base]\n\t"                          \
+    "ds_read_b32 %[R" r "0], %[ad]\n\t"                                        \
+    "ds_read_b32 %[R" r "1], %[ad] offset:256\n\t"                             \
+    "ds_read_b32 %[R" r "2], %[ad] offset:512\n\t"                             \
+    "ds_read_b32 %[R" r "3], %[ad] offset:768\n\t"
+#define IL_LOAD2(r, w)                                                         \
+    "v_lshl_add_u32 %[ad], %[" w "], 9, %[base]\n\t"                           \
+    "ds_read_b32 %[R" r "0], %[ad]\n\t"                                        \
+    "ds_read_b32 %[R" r "1], %[ad] offset:256\n\t"
+#define IL_XORF(c, s) "v_xor_b32 %[R" c s "], %[R" c s "], %[f" s "]\n\t"
+#define IL_XORN(c, s) ""
+#define IL_CMP2(c, p, s0, s1)                                                  \
+    "v_cmp_ge_f32_e32 vcc, %[R" c s0 "], %[R" p s0 "]\n\t"                     \
+    "v_cmp_ge_f32_e64 %[tmp], %[R" c s1 "], %[R" p s1 "]\n\t"                  \
+    "s_and_b64 %[A" s0 "], %[A" s0 "], vcc\n\t"                                \
+    "s_and_b64 %[A" s1 "], %[A" s1 "], %[tmp]\n\t"
+#define IL_STEP4(c, p, X)                                                      \
+    X(c, "0") X(c, "1") X(c, "2") X(c, "3")                                    \
+    IL_CMP2(c, p, "0", "1") IL_CMP2(c, p, "2", "3")
+#define IL_STEP2(c, p, X) X(c, "0") X(c, "1") IL_CMP2(c, p, "0", "1")
+#define IL_EXIT4(u)                                                            \
+    "s_or_b64 %[tmp], %[A0], %[A1]\n\t"                                        \
+    "s_or_b64 %[tmp], %[tmp], %[A2]\n\t"                                       \
+    "s_or_b64 %[tmp], %[tmp], %[A3]\n\t"                                       \
+    "s_cbranch_scc0 2f\n\t"                                                    \
+    "s_cmp_le_i32 %[last], " u "\n\t"                                          \
+    "s_cbranch_scc1 2f\n\t"
+#define IL_EXIT2(u)                                                            \
+    "s_or_b64 %[tmp], %[A0], %[A1]\n\t"                                        \
+    "s_cbranch_scc0 2f\n\t"                                                    \
+    "s_cmp_le_i32 %[last], " u "\n\t"                                          \
+    "s_cbranch_scc1 2f\n\t"
+// Window columns 2..7, after the first pair (sets 0 and 1 hold columns 0
+// and 1, set 2 is loading column 2).
+#define IL_WINDOW(LOAD, STEP, EXIT, X)                                         \
+    LOAD("0", "w3") "s_waitcnt lgkmcnt(%[nl])\n\t" STEP("2", "1", X)           \
+    LOAD("1", "w4") "s_waitcnt lgkmcnt(%[nl])\n\t" STEP("0", "2", X) EXIT("3") \
+    LOAD("2", "w5") "s_waitcnt lgkmcnt(%[nl])\n\t" STEP("1", "0", X)           \
+    LOAD("0", "w6") "s_waitcnt lgkmcnt(%[nl])\n\t" STEP("2", "1", X) EXIT("5") \
+    LOAD("1", "w7") "s_waitcnt lgkmcnt(%[nl])\n\t" STEP("0", "2", X)           \
+    "s_waitcnt lgkmcnt(0)\n\t" STEP("1", "0", X)
+#define IL_FIRST_NEG(s)                                                        \
+    "v_cmp_lt_f32_e64 %[F" s "], %[R1" s "], %[R0" s "]\n\t"
+#define IL_ORD(s) "v_cmp_o_f32_e64 %[A" s "], %[R1" s "], %[R0" s "]\n\t"
+#define IL_TIE(s)                                                              \
+    "v_cmp_eq_f32_e64 %[tmp], %[R1" s "], %[R0" s "]\n\t"                      \
+    "s_or_b64 %[T], %[T], %[tmp]\n\t"
+#define IL_FLIP(s) "v_cndmask_b32_e64 %[f" s "], 0, %[sign], %[F" s "]\n\t"
+#define IL_PREV(s) "v_xor_b32 %[R1" s "], %[R1" s "], %[f" s "]\n\t"
+#define IL_POS(s) "v_cmp_ge_f32_e64 %[A" s "], %[R1" s "], %[R0" s "]\n\t"
+
+#define IL_COMMON_IN                                                           \
+    [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), \
+        [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last)
+
+// Interleaved chain with negative trends: A = rows on their oriented chain
+// after column min(last, 7) (or earlier exit), F = rows falling on the first
+// pair, T = union of the rows tied on the first pair, f = per-row sign flip.
+__device__ __forceinline__ void il_neg4(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t sign,
+                                        uint64_t (&A)[4], uint64_t (&F)[4], uint64_t &T, uint32_t (&f)[4])
+{
+    float R00, R01, R02, R03, R10, R11, R12, R13, R20, R21, R22, R23;
+    uint32_t ad;
+    uint64_t tmp;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        IL_LOAD4("0", "w0") IL_LOAD4("1", "w1") IL_LOAD4("2", "w2")
+        "s_waitcnt lgkmcnt(%[nl])\n\t"
+        IL_FIRST_NEG("0") IL_FIRST_NEG("1") IL_FIRST_NEG("2") IL_FIRST_NEG("3")
+        IL_ORD("0") IL_ORD("1") IL_ORD("2") IL_ORD("3")
+        "v_cmp_eq_f32_e64 %[T], %[R10], %[R00]\n\t"
+        IL_TIE("1") IL_TIE("2") IL_TIE("3")
+        IL_FLIP("0") IL_FLIP("1") IL_FLIP("2") IL_FLIP("3")
+        IL_PREV("0") IL_PREV("1") IL_PREV("2") IL_PREV("3")
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        IL_WINDOW(IL_LOAD4, IL_STEP4, IL_EXIT4, IL_XORF)
+        "2:\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [A0] "=&s"(A[0]), [A1] "=&s"(A[1]), [A2] "=&s"(A[2]), [A3] "=&s"(A[3]),
+          [F0] "=&s"(F[0]), [F1] "=&s"(F[1]), [F2] "=&s"(F[2]), [F3] "=&s"(F[3]),
+          [T] "=&s"(T), [tmp] "=&s"(tmp), [f0] "=&v"(f[0]), [f1] "=&v"(f[1]), [f2] "=&v"(f[2]),
+          [f3] "=&v"(f[3]), [ad] "=&v"(ad), [R00] "=&v"(R00), [R01] "=&v"(R01), [R02] "=&v"(R02),
+          [R03] "=&v"(R03), [R10] "=&v"(R10), [R11] "=&v"(R11), [R12] "=&v"(R12), [R13] "=&v"(R13),
+          [R20] "=&v"(R20), [R21] "=&v"(R21), [R22] "=&v"(R22), [R23] "=&v"(R23)
+        : IL_COMMON_IN, [sign] "v"(sign), [nl] "i"(4)
+        : "vcc", "scc", "memory");
+}
+
+__device__ __forceinline__ void il_neg2(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t sign,
+                                        uint64_t (&A)[2], uint64_t (&F)[2], uint64_t &T, uint32_t (&f)[2])
+{
+    float R00, R01, R10, R11, R20, R21;
+    uint32_t ad;
+    uint64_t tmp;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        IL_LOAD2("0", "w0") IL_LOAD2("1", "w1") IL_LOAD2("2", "w2")
+        "s_waitcnt lgkmcnt(%[nl])\n\t"
+        IL_FIRST_NEG("0") IL_FIRST_NEG("1")
+        IL_ORD("0") IL_ORD("1")
+        "v_cmp_eq_f32_e64 %[T], %[R10], %[R00]\n\t"
+        IL_TIE("1")
+        "s_nop 4\n\t"  // wait states before a VALU reads an SGPR mask a VALU wrote
+        IL_FLIP("0") IL_FLIP("1")
+        IL_PREV("0") IL_PREV("1")
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        IL_WINDOW(IL_LOAD2, IL_STEP2, IL_EXIT2, IL_XORF)
+        "2:\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [A0] "=&s"(A[0]), [A1] "=&s"(A[1]), [F0] "=&s"(F[0]), [F1] "=&s"(F[1]), [T] "=&s"(T),
+          [tmp] "=&s"(tmp), [f0] "=&v"(f[0]), [f1] "=&v"(f[1]), [ad] "=&v"(ad), [R00] "=&v"(R00),
+          [R01] "=&v"(R01), [R10] "=&v"(R10), [R11] "=&v"(R11), [R20] "=&v"(R20), [R21] "=&v"(R21)
+        : IL_COMMON_IN, [sign] "v"(sign), [nl] "i"(2)
+        : "vcc", "scc", "memory");
+}
+
+// The >= chain alone (negative trends not requested).
+__device__ __forceinline__ void il_pos4(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint64_t (&A)[4])
+{
+    float R00, R01, R02, R03, R10, R11, R12, R13, R20, R21, R22, R23;
+    uint32_t ad;
+    uint64_t tmp;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        IL_LOAD4("0", "w0") IL_LOAD4("1", "w1") IL_LOAD4("2", "w2")
+        "s_waitcnt lgkmcnt(%[nl])\n\t"
+        IL_POS("0") IL_POS("1") IL_POS("2") IL_POS("3")
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        IL_WINDOW(IL_LOAD4, IL_STEP4, IL_EXIT4, IL_XORN)
+        "2:\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [A0] "=&s"(A[0]), [A1] "=&s"(A[1]), [A2] "=&s"(A[2]), [A3] "=&s"(A[3]),
+          [tmp] "=&s"(tmp), [ad] "=&v"(ad), [R00] "=&v"(R00), [R01] "=&v"(R01), [R02] "=&v"(R02),
+          [R03] "=&v"(R03), [R10] "=&v"(R10), [R11] "=&v"(R11), [R12] "=&v"(R12), [R13] "=&v"(R13),
+          [R20] "=&v"(R20), [R21] "=&v"(R21), [R22] "=&v"(R22), [R23] "=&v"(R23)
+        : IL_COMMON_IN, [nl] "i"(4)
+        : "vcc", "scc", "memory");
+}
+
+__device__ __forceinline__ void il_pos2(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint64_t (&A)[2])
+{
+    float R00, R01, R10, R11, R20, R21;
+    uint32_t ad;
+    uint64_t tmp;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        IL_LOAD2("0", "w0") IL_LOAD2("1", "w1") IL_LOAD2("2", "w2")
+        "s_waitcnt lgkmcnt(%[nl])\n\t"
+        IL_POS("0") IL_POS("1")
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        IL_WINDOW(IL_LOAD2, IL_STEP2, IL_EXIT2, IL_XORN)
+        "2:\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [A0] "=&s"(A[0]), [A1] "=&s"(A[1]), [tmp] "=&s"(tmp), [ad] "=&v"(ad), [R00] "=&v"(R00),
+          [R01] "=&v"(R01), [R10] "=&v"(R10), [R11] "=&v"(R11), [R20] "=&v"(R20), [R21] "=&v"(R21)
+        : IL_COMMON_IN, [nl] "i"(2)
+        : "vcc", "scc", "memory");
+}
+
+// Plain-code twin of the interleaved window (the measurement variant and the
+// rare paths): same exit points as the sequences above. `prev` holds the
+// flipped values of column 1; counts executed compare instructions.
+template <int L, bool COUNT>
+__device__ __forceinline__ void il_window_ref(const unsigned char *__restrict__ base, const int32_t (&w)[kWin],
+                                              int32_t last, const uint32_t (&flip)[L], float (&prev)[L],
+                                              uint64_t (&alive)[L], uint64_t &steps)
+{
+    constexpr int CB = L * kWave * 4;
+#pragma unroll
+    for (int u = 2; u < kWin; ++u) {
+#pragma unroll
+        for (int s = 0; s < L; ++s) {
+            const float y = flipped(*reinterpret_cast<const float *>(base + w[u] * CB + s * kWave * 4), flip[s]);
+            alive[s] &= __ballot(y >= prev[s]);
+            prev[s] = y;
+        }
+        if (COUNT) steps += L;
+        if (u == 3 || u == 5) {
+            uint64_t any = 0;
+#pragma unroll
+            for (int s = 0; s < L; ++s) any |= alive[s];
+            if (any == 0 || last <= u) return;
+        }
+    }
+}
+
+// Columns kWin..last (long individuals; rarely any row is left).
+template <int L, bool COUNT>
+__device__ __forceinline__ void il_tail(const unsigned char *__restrict__ base, const int32_t *__restrict__ c,
+                                        int32_t last, const uint32_t (&flip)[L], float (&prev)[L],
+                                        uint64_t (&alive)[L], uint64_t &steps)
+{
+    constexpr int CB = L * kWave * 4;
+    for (int32_t u = kWin; u <= last; ++u) {
+        const int32_t col = c[u];
+        uint64_t any = 0;
+#pragma unroll
+        for (int s = 0; s < L; ++s) {
+            const float y = flipped(*reinterpret_cast<const float *>(base + col * CB + s * kWave * 4), flip[s]);
+            alive[s] &= __ballot(y >= prev[s]);
+            prev[s] = y;
+            any |= alive[s];
+        }
+        if (COUNT) steps += L;
+        if (any == 0) return;
+    }
+}
+
+// One individual on the L (2 or 4) sub-tiles of a chunk. Rows outside the
+// matrix hold NaN in the tile, so they never match.
+template <int L, bool NEG, bool COUNT>
+__device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ tile, int32_t last,
+                                            const int32_t *__restrict__ c, const int4 &w03,
+                                            const int4 &w47, int lane4, uint64_t (&M)[L],
+                                            uint64_t (&G)[L], uint64_t &steps)
+{
+    static_assert(L == 2 || L == 4, "interleaved evaluation takes 2 or 4 sub-tiles");
+    constexpr int CB = L * kWave * 4;
+    const unsigned char *base = tile + lane4;
+    const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
+    auto ld = [&](int32_t col, int s) -> float {
+        return *reinterpret_cast<const float *>(base + col * CB + s * kWave * 4);
+    };
+    if (last == 0) {  // one column: the row counts unless its value is missing
+#pragma unroll
+        for (int s = 0; s < L; ++s) {
+            const float v = ld(w[0], s);
+            M[s] = __ballot(v == v);
+            G[s] = 0;
+        }
+        if (COUNT) steps += L;
+        return;
+    }
+    uint64_t A[L], F[L], T = 0;
+    uint32_t f[L];
+    if constexpr (COUNT || !NEG) {
+        float prev[L];
+#pragma unroll
+        for (int s = 0; s < L; ++s) {
+            const float v0 = ld(w[0], s), v1 = ld(w[1], s);
+            if constexpr (NEG) {
+                F[s] = __ballot(v1 < v0);
+                A[s] = __ballot(!__builtin_isunordered(v1, v0));
+                T |= __ballot(v1 == v0);
+                f[s] = v1 < v0 ? kSign : 0u;
+            } else {
+                F[s] = 0;
+                A[s] = __ballot(v1 >= v0);
+                f[s] = 0u;
+            }
+            prev[s] = flipped(v1, f[s]);
+        }
+        if (COUNT) steps += (NEG ? 3 : 1) * L;
+        if constexpr (COUNT) {
+            if (last >= 2) il_window_ref<L, COUNT>(base, w, last, f, prev, A, steps);
+        } else {
+            const uint32_t b = lds_addr(base);
+            if constexpr (L == 4) il_pos4(b, w, last, A);
+            else il_pos2(b, w, last, A);
+        }
+    } else {
+        const uint32_t b = lds_addr(base);
+        if constexpr (L == 4) il_neg4(b, w, last, kSign, A, F, T, f);
+        else il_neg2(b, w, last, kSign, A, F, T, f);
+    }
+    if (last >= kWin) {
+        uint64_t any = 0;
+#pragma unroll
+        for (int s = 0; s < L; ++s) any |= A[s];
+        if (any) {
+            float prev[L];
+#pragma unroll
+            for (int s = 0; s < L; ++s) prev[s] = flipped(ld(w[kWin - 1], s), f[s]);
+            il_tail<L, COUNT>(base, c, last, f, prev, A, steps);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < L; ++s) {
+        M[s] = A[s];
+        if constexpr (NEG && !COUNT)  // on the scalar unit (wave-uniform masks)
+            asm("s_and_b64 %0, %1, %2" : "=s"(G[s]) : "s"(A[s]), "s"(F[s]) : "scc");
+        else
+            G[s] = A[s] & F[s];
+    }
+    if constexpr (NEG) {
+        if (T && last >= 2) {
+            // Rows tied on the first pair also try the <= chain.
+            uint64_t ta[L];
+            uint32_t fl[L];
+            float prev[L];
+#pragma unroll
+            for (int s = 0; s < L; ++s) {
+                const float v0 = ld(w[0], s), v1 = ld(w[1], s);
+                ta[s] = __ballot(v1 == v0);
+                fl[s] = kSign;
+                prev[s] = flipped(v1, kSign);
+            }
+            if (COUNT) steps += L;
+            if (last >= 2) il_window_ref<L, COUNT>(base, w, last, fl, prev, ta, steps);
+            if (last >= kWin) {
+                uint64_t any = 0;
+#pragma unroll
+                for (int s = 0; s < L; ++s) any |= ta[s];
+                if (any) {
+#pragma unroll
+                    for (int s = 0; s < L; ++s) prev[s] = flipped(ld(w[kWin - 1], s), kSign);
+                    il_tail<L, COUNT>(base, c, last, fl, prev, ta, steps);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < L; ++s) {
+                M[s] |= ta[s];
+                G[s] |= ta[s] & ~A[s];
+            }
+        }
+    }
+}
+
 // One individual read straight from the column-major matrix (matrices too
 // wide to stage). `xr` points at row (row0 + lane) of column 0; `sub`
 // holds the element offsets of the L sub-tiles (clamped by the caller so
@@ -509,6 +849,20 @@ __device__ __forceinline__ void load_head(const IndHead *__restrict__ hb, int32_
                  "s"(hv[1].w), "s"(hv[2].x), "s"(hv[2].y), "s"(hv[2].z), "s"(hv[2].w));
 }
 
+__device__ __forceinline__ void load_head_async(const IndHead *__restrict__ hb, int32_t ii, int4 (&hv)[3])
+{
+    const int4 *p = reinterpret_cast<const int4 *>(hb + ii);
+    hv[0] = p[0];
+    hv[1] = p[2];
+    hv[2] = p[3];
+}
+
+__device__ __forceinline__ void head_ready(int4 (&hv)[3])
+{
+    asm volatile("" : "+s"(hv[0].x), "+s"(hv[0].y), "+s"(hv[1].x), "+s"(hv[1].y), "+s"(hv[1].z),
+                 "+s"(hv[1].w), "+s"(hv[2].x), "+s"(hv[2].y), "+s"(hv[2].z), "+s"(hv[2].w));
+}
+
 // ---------------------------------------------------------------------------
 // One work item: individuals [i0, i0 + np) of request d on tiles [t0, t1).
 // `tile` and `cnt` are this block's LDS areas; wave w takes the group's
@@ -558,6 +912,18 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                 }
                 *reinterpret_cast<float4 *>(tile + (size_t)c * T + 4 * q) = v;
             }
+            if (L >= 2 && (nl < L || row0 + T > d.rows)) {
+                // The interleaved evaluation reads all L sub-tiles and takes
+                // no row mask: rows outside this item's range or past the end
+                // of the matrix hold NaN, so they never match.
+                __syncthreads();
+                const int64_t first = min<int64_t>(d.rows - row0, (int64_t)nl * kWave);
+                const int tail = T * d.cols;
+                for (int idx = threadIdx.x; idx < tail; idx += blockDim.x) {
+                    const int r = idx % T;
+                    if (r >= first) tile[idx] = __builtin_nanf("");
+                }
+            }
             __syncthreads();
         }
 
@@ -572,8 +938,12 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             } else {
                 const int32_t *c = d.colidx + hv[0].y;
                 if constexpr (STAGE == STAGE_LDS) {
-                    eval_lds<L, NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1, c,
-                                            hv[1], hv[2], lane * 4, valid, M, G, steps);
+                    if constexpr (L >= 2)
+                        eval_lds_il<L, NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1, c,
+                                                   hv[1], hv[2], lane * 4, M, G, steps);
+                    else
+                        eval_lds<L, NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1, c,
+                                                hv[1], hv[2], lane * 4, valid, M, G, steps);
                 } else {
                     // Sub-tiles past the last tile are clamped onto it (their
                     // rows are masked out by `valid`).
@@ -625,8 +995,11 @@ k_eval(ReqDesc d, const IndHead *__restrict__ heads, int32_t P, int32_t n_tiles,
     const int32_t i0 = blockIdx.y * P;
     const int32_t np = min(P, d.n - i0);
     if (np <= 0) return;
-    const int64_t t0 = (int64_t)blockIdx.x * n_tiles / gridDim.x;
-    const int64_t t1 = (int64_t)(blockIdx.x + 1) * n_tiles / gridDim.x;
+    // Tile ranges start on a multiple of L, so only the matrix's last chunk
+    // can be partial.
+    const int64_t n_chunks = (n_tiles + L - 1) / L;
+    const int64_t t0 = (int64_t)blockIdx.x * n_chunks / gridDim.x * L;
+    const int64_t t1 = min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * n_chunks / gridDim.x * L);
     uint64_t steps = 0;
     run_item<L, NEG, STAGE, COUNT>(d, heads, i0, np, t0, t1, tile, cnt, steps);
     if (COUNT && (threadIdx.x & (kWave - 1)) == 0 && steps)

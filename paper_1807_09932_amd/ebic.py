@@ -43,7 +43,11 @@ EXPORTED = ["ebic_create", "ebic_destroy", "ebic_set_allocator", "ebic_last_erro
             "ebic_upload_matrix", "ebic_matrix_info", "ebic_release_matrix",
             "ebic_mask_words", "ebic_eval_population", "ebic_eval_batch", "ebic_autotune",
             "ebic_set_launch_shape", "ebic_set_profiling", "ebic_read_profile",
-            "ebic_plan_shape"]
+            "ebic_plan_shape", "ebic_server_request_bytes", "ebic_server_create",
+            "ebic_server_destroy", "ebic_server_submit", "ebic_server_poll",
+            "ebic_server_get_stats", "ebic_ea_create", "ebic_ea_destroy", "ebic_ea_population",
+            "ebic_ea_step", "ebic_read_delimited", "ebic_free_text_matrix",
+            "ebic_write_biclusters"]
 
 
 class EbicError(RuntimeError):
@@ -58,6 +62,29 @@ class ebic_request(ctypes.Structure):
                 ("flags", ctypes.c_uint32),
                 ("d_matched", ctypes.c_void_p), ("d_negative", ctypes.c_void_p),
                 ("d_matched_mask", ctypes.c_void_p), ("d_negative_mask", ctypes.c_void_p)]
+
+
+class ebic_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("pending", ctypes.c_int64),
+                ("reserved_bytes", ctypes.c_int64), ("high_water_bytes", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_int64), ("nominal_checks", ctypes.c_int64),
+                ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("mean_batch", ctypes.c_double)]
+
+
+class ebic_ea_params(ctypes.Structure):
+    _fields_ = [("n_cols", ctypes.c_int32), ("pop_size", ctypes.c_int32),
+                ("k_min", ctypes.c_int32), ("k_max", ctypes.c_int32), ("elite", ctypes.c_int32),
+                ("p_crossover", ctypes.c_double), ("p_mutation", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class ebic_text_matrix(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int32), ("delimiter", ctypes.c_char),
+                ("values", ctypes.POINTER(ctypes.c_float)),
+                ("row_names", ctypes.POINTER(ctypes.c_char_p)),
+                ("col_names", ctypes.POINTER(ctypes.c_char_p))]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -93,6 +120,23 @@ def load_library(path: str = LIB_PATH):
         "ebic_plan_shape": (I32, [P, I32, I32, I64] + [ctypes.POINTER(I32)] * 5),
         "ebic_read_profile": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(I64)]),
+        "ebic_server_request_bytes": (I32, [P, I32, I32, I64, U32, I32, ctypes.POINTER(I64)]),
+        "ebic_server_create": (I32, [P, I64, I32, I32, ctypes.POINTER(P)]),
+        "ebic_server_destroy": (I32, [P]),
+        "ebic_server_submit": (I32, [P, I32, I32, P, P, U32, P, P, P, P, ctypes.c_uint64]),
+        "ebic_server_poll": (I32, [P, P, P, I32, I32, ctypes.POINTER(I32)]),
+        "ebic_server_get_stats": (I32, [P, ctypes.POINTER(ebic_server_stats), I32]),
+        "ebic_ea_create": (I32, [ctypes.POINTER(ebic_ea_params), ctypes.POINTER(P)]),
+        "ebic_ea_destroy": (I32, [P]),
+        "ebic_ea_population": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I32),
+                                     ctypes.POINTER(I64)]),
+        "ebic_ea_step": (I32, [P, P, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]),
+        "ebic_read_delimited": (I32, [ctypes.c_char_p, ctypes.c_char, I32, I32, I32,
+                                      ctypes.POINTER(ebic_text_matrix)]),
+        "ebic_free_text_matrix": (I32, [ctypes.POINTER(ebic_text_matrix)]),
+        "ebic_write_biclusters": (I32, [ctypes.c_char_p, I64, I32, P, P, P, I32, P,
+                                        ctypes.POINTER(ctypes.c_char_p),
+                                        ctypes.POINTER(ctypes.c_char_p)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -196,6 +240,179 @@ def ebic_read_profile(ctx: int) -> Tuple[int, float, int]:
     _check(load_library().ebic_read_profile(ctx, ctypes.byref(n), ctypes.byref(ms),
                                             ctypes.byref(steps)))
     return n.value, ms.value, steps.value
+
+
+def ebic_server_request_bytes(ctx: int, matrix: int, n_ind: int, nnz: int, flags: int,
+                              masks: bool) -> int:
+    out = ctypes.c_int64()
+    _check(load_library().ebic_server_request_bytes(ctx, matrix, n_ind, nnz, flags, int(masks),
+                                                    ctypes.byref(out)))
+    return out.value
+
+
+def ebic_server_create(ctx: int, hbm_budget_bytes: int, slots: int, max_batch: int) -> int:
+    h = ctypes.c_void_p()
+    _check(load_library().ebic_server_create(ctx, int(hbm_budget_bytes), slots, max_batch,
+                                             ctypes.byref(h)))
+    return h.value
+
+
+def ebic_server_destroy(srv: int) -> None:
+    _check(load_library().ebic_server_destroy(srv))
+
+
+def ebic_server_submit(srv: int, matrix: int, n_ind: int, offsets: int, cols: Optional[int],
+                       flags: int, matched: int, negative: Optional[int],
+                       matched_mask: Optional[int], negative_mask: Optional[int], tag: int) -> None:
+    """Host pointers; the output buffers must stay alive until `tag` is polled."""
+    _check(load_library().ebic_server_submit(srv, matrix, n_ind, offsets, cols, flags, matched,
+                                             negative, matched_mask, negative_mask, tag))
+
+
+def ebic_server_poll(srv: int, tags: np.ndarray, statuses: np.ndarray, timeout_us: int) -> int:
+    """Fill tags (uint64) / statuses (int32) with completed requests; returns their number."""
+    n = ctypes.c_int32()
+    _check(load_library().ebic_server_poll(srv, tags.ctypes.data, statuses.ctypes.data,
+                                           min(tags.size, statuses.size), int(timeout_us),
+                                           ctypes.byref(n)))
+    return n.value
+
+
+def ebic_server_get_stats(srv: int, reset: bool = False) -> ebic_server_stats:
+    st = ebic_server_stats()
+    _check(load_library().ebic_server_get_stats(srv, ctypes.byref(st), int(reset)))
+    return st
+
+
+def ebic_ea_create(params: "ebic_ea_params") -> int:
+    h = ctypes.c_void_p()
+    _check(load_library().ebic_ea_create(ctypes.byref(params), ctypes.byref(h)))
+    return h.value
+
+
+def ebic_ea_destroy(ea: int) -> None:
+    _check(load_library().ebic_ea_destroy(ea))
+
+
+def ebic_ea_population(ea: int) -> Tuple[int, int, int, int]:
+    """(offsets pointer, cols pointer, n_ind, generation) of the driver's host CSR."""
+    o, c, n, g = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int32(), ctypes.c_int64()
+    _check(load_library().ebic_ea_population(ea, ctypes.byref(o), ctypes.byref(c),
+                                             ctypes.byref(n), ctypes.byref(g)))
+    return o.value, c.value, n.value, g.value
+
+
+def ebic_ea_step(ea: int, matched: int) -> Tuple[int, float]:
+    """`matched`: host pointer to pop_size int32 counts; returns (best index, fitness)."""
+    bi, bf = ctypes.c_int32(), ctypes.c_double()
+    _check(load_library().ebic_ea_step(ea, matched, ctypes.byref(bi), ctypes.byref(bf)))
+    return bi.value, bf.value
+
+
+def ebic_read_delimited(path: str, delimiter: bytes, header: int, row_names: int,
+                        threads: int) -> "ebic_text_matrix":
+    m = ebic_text_matrix()
+    _check(load_library().ebic_read_delimited(os.fsencode(path), delimiter, header, row_names,
+                                              threads, ctypes.byref(m)))
+    return m
+
+
+def ebic_free_text_matrix(m: "ebic_text_matrix") -> None:
+    _check(load_library().ebic_free_text_matrix(ctypes.byref(m)))
+
+
+def ebic_write_biclusters(path: str, rows: int, n_ind: int, offsets: int, cols: Optional[int],
+                          matched_mask: int, n_out: int, which: Optional[int],
+                          row_names, col_names) -> None:
+    _check(load_library().ebic_write_biclusters(os.fsencode(path), rows, n_ind, offsets, cols,
+                                                matched_mask, n_out, which, row_names, col_names))
+
+
+def read_delimited(path: str, delimiter: str = "", header: int = -1, row_names: int = -1,
+                   threads: int = 8):
+    """Parse a delimited text matrix with the library's reader.
+
+    Returns (X, row_names, col_names): X is a float32 (rows x cols) array in
+    column-major (Fortran) order, ready for Context.upload; the name lists
+    are None when the file has none."""
+    d = delimiter.encode()[:1] if delimiter else b"\0"
+    m = ebic_read_delimited(path, d, header, row_names, max(1, threads))
+    try:
+        n = m.rows * m.cols
+        flat = np.ctypeslib.as_array(m.values, shape=(n,)).copy() if n else np.zeros(0, np.float32)
+        X = flat.reshape(m.cols, m.rows).T  # column-major view of (rows, cols)
+        rn = [m.row_names[i].decode() for i in range(m.rows)] if m.row_names else None
+        cn = [m.col_names[i].decode() for i in range(m.cols)] if m.col_names else None
+    finally:
+        ebic_free_text_matrix(m)
+    return X, rn, cn
+
+
+def write_biclusters(path: str, rows: int, offsets: np.ndarray, cols: np.ndarray,
+                     matched_mask: np.ndarray, which: Sequence[int],
+                     row_names: Optional[Sequence[str]] = None,
+                     col_names: Optional[Sequence[str]] = None) -> None:
+    """Write the biclusters of individuals `which` (text, see include/ebic.h)."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    mask = np.ascontiguousarray(matched_mask).view(np.uint64)
+    n = offsets.size - 1
+    if mask.size != n * ebic_mask_words(rows):
+        raise ValueError("matched_mask must hold n x ebic_mask_words(rows) words")
+    w = np.ascontiguousarray(which, dtype=np.int32)
+
+    def names(v):
+        if v is None:
+            return None
+        arr = (ctypes.c_char_p * len(v))(*[str(x).encode() for x in v])
+        return ctypes.cast(arr, ctypes.POINTER(ctypes.c_char_p)), arr
+    rn, cn = names(row_names), names(col_names)
+    ebic_write_biclusters(path, rows, n, offsets.ctypes.data, cols.ctypes.data if cols.size else None,
+                          mask.ctypes.data, w.size, w.ctypes.data if w.size else None,
+                          rn[0] if rn else None, cn[0] if cn else None)
+
+
+class EA:
+    """The library's stand-in evolutionary driver (host code, include/ebic.h):
+    ``population()`` gives the current generation as CSR, ``step(matched)``
+    scores it from its matched counts and breeds the next one."""
+
+    def __init__(self, n_cols: int, pop_size: int, k_min: int = 2, k_max: int = 30,
+                 elite: int = -1, p_crossover: float = 0.5, p_mutation: float = 0.9,
+                 seed: int = 0):
+        if elite < 0:
+            elite = max(1, pop_size // 20)
+        self.params = ebic_ea_params(n_cols, pop_size, k_min, min(k_max, n_cols), elite,
+                                     p_crossover, p_mutation, seed & (2**64 - 1))
+        self.handle = ebic_ea_create(self.params)
+
+    def population(self) -> Tuple[np.ndarray, np.ndarray, int]:
+        """(offsets, cols, generation): copies of the current generation's CSR."""
+        o, c, n, g = ebic_ea_population(self.handle)
+        offs = np.ctypeslib.as_array(ctypes.cast(o, ctypes.POINTER(ctypes.c_int32)),
+                                     shape=(n + 1,)).copy()
+        nnz = int(offs[-1])
+        cols = (np.ctypeslib.as_array(ctypes.cast(c, ctypes.POINTER(ctypes.c_int32)),
+                                      shape=(nnz,)).copy() if nnz else np.zeros(0, np.int32))
+        return offs, cols, g
+
+    def step(self, matched: np.ndarray) -> Tuple[int, float]:
+        """Score the current generation; returns (best index, best fitness)."""
+        m = np.ascontiguousarray(matched, dtype=np.int32)
+        if m.size != self.params.pop_size:
+            raise ValueError("one matched count per individual is required")
+        return ebic_ea_step(self.handle, m.ctypes.data)
+
+    def close(self):
+        if self.handle:
+            ebic_ea_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

@@ -5,21 +5,14 @@ submits one population evaluation per generation and waits for its counts
 (the host-side evolutionary loop of the EBIC paper's Introduction; the
 evaluation of Methods, "Handling missing values").
 
-The server does continuous batching:
-
-* Admission. A request reserves the device bytes it will hold: its CSR
-  population, its outputs, and its masks if asked for. It is admitted only
-  while the reserved total stays within the HBM budget. A request larger than
-  the whole budget is refused at submission with EBIC_EBUDGET.
-* Launch. Each admitted request's population is copied to the device on a
-  free stream slot. Whenever a slot is free, every admitted request waiting
-  for one is launched there as one batch: one ebic_eval_batch call, one HIP
-  graph replay. Requests that arrive while other batches run on other slots
-  are admitted and launched as soon as a slot and memory free up, so their
-  work overlaps on the device.
-* Completion. When a slot's batch has finished (its event has completed), its
-  results go back to the host, each request's future is completed, its latency
-  is recorded, and its reservation and slot are released.
+The scheduling runs in the library's native serving engine
+(``ebic_server_*`` in include/ebic.h): admission against an HBM budget
+(a device arena of exactly that size), continuous batching of waiting
+requests onto stream slots (one ``ebic_eval_batch`` graph replay per batch,
+one copy in and one copy out), a completion thread per slot and latency
+accounting. This module only marshals arguments: ``submit`` hands the host
+CSR and host output arrays to the engine and returns a future; one poller
+thread turns completed tags into results.
 
 Each request's counts and masks are exactly those of an evaluation of the
 same population alone: the batched kernel runs the same per-item code, and
@@ -29,13 +22,12 @@ from __future__ import annotations
 
 import concurrent.futures
 import dataclasses
+import itertools
 import threading
 import time
-from collections import deque
-from typing import Deque, Dict, List, Optional
+from typing import Dict, Optional
 
 import numpy as np
-import torch
 
 from . import ebic
 
@@ -50,33 +42,10 @@ class Result:
 
 
 @dataclasses.dataclass
-class _Req:
-    run: int
-    matrix: int
-    offsets: np.ndarray
-    cols: np.ndarray
-    include: bool
-    negative: bool
-    masks: bool
-    bytes: int
+class _Pending:
     future: concurrent.futures.Future
+    keep: tuple                  # the arrays the engine reads or writes
     t_submit: float
-    n: int = 0
-    checks: int = 0
-    # device state once admitted
-    pop: Optional[ebic.Population] = None
-    out: Optional[tuple] = None
-
-
-class _Slot:
-    def __init__(self, device):
-        self.stream = torch.cuda.Stream(device=device)  # default priority
-        self.event: Optional[torch.cuda.Event] = None
-        self.batch: List[_Req] = []
-
-    @property
-    def busy(self) -> bool:
-        return bool(self.batch)
 
 
 class Server:
@@ -86,60 +55,89 @@ class Server:
                  max_batch: int = 256):
         self.ctx = ctx
         self.budget = int(hbm_budget_bytes)
-        self.reserved = 0
-        self.high_water = 0
-        self.max_batch = max_batch
-        self.slots = [_Slot(ctx.device) for _ in range(max(1, slots))]
-        self._waiting: Deque[_Req] = deque()     # submitted, not yet admitted
-        self._admitted: Deque[_Req] = deque()    # on the device, not yet launched
-        self._cv = threading.Condition()
-        self._stop = False
-        self._thread = threading.Thread(target=self._loop, name="ebic-server", daemon=True)
-        self.latencies: List[float] = []
-        self.completed = 0
-        self.checks_done = 0
-        self.batches = 0
-        self._thread.start()
+        self.handle = ebic.ebic_server_create(ctx.handle, self.budget, slots, max_batch)
+        self._tags = itertools.count(1)
+        self._pending: Dict[int, _Pending] = {}
+        self._mu = threading.Lock()
+        self._closing = False
+        self._final_stats = None
+        self._poller = threading.Thread(target=self._poll_loop, name="ebic-server-poll", daemon=True)
+        self._poller.start()
 
     # -- client side ----------------------------------------------------------
     def request_bytes(self, matrix: int, n: int, nnz: int, masks: bool) -> int:
-        rows, _ = self.ctx.matrices[matrix]
-        words = ebic.ebic_mask_words(rows)
-        b = 4 * (n + 1) + 4 * max(1, nnz) + 8 * n
-        if masks:
-            b += 2 * 8 * n * words
-        return b
+        """Device bytes a request holds while in flight (what admission counts):
+        its CSR, both count arrays and, with masks, both mask arrays."""
+        flags = ebic.Context.flags(False, True)
+        return ebic.ebic_server_request_bytes(self.ctx.handle, matrix, n, nnz, flags, masks)
 
     def submit(self, run: int, matrix: int, offsets: np.ndarray, cols: np.ndarray,
                include: bool = False, negative: bool = True,
                masks: bool = False) -> concurrent.futures.Future:
-        """Queue one population evaluation; the future yields a Result."""
+        """Queue one population evaluation; the future yields a Result.
+        Raises EbicError(EBIC_EBUDGET) for a request larger than the budget."""
+        del run  # requests of all runs share the queue (FIFO)
         offsets = np.ascontiguousarray(offsets, dtype=np.int32)
         cols = np.ascontiguousarray(cols, dtype=np.int32)
         n = offsets.size - 1
-        if offsets.size < 1 or int(offsets.min()) < 0 or int(offsets.max()) > cols.size:
+        if n < 0:
+            raise ValueError("offsets must have n + 1 entries")
+        if n and (int(offsets.min()) < 0 or int(offsets.max()) > cols.size):
             raise ValueError("offsets reach outside the column array")
-        nbytes = self.request_bytes(matrix, n, cols.size, masks)
-        if nbytes > self.budget:
-            raise ebic.EbicError(ebic.EBIC_EBUDGET,
-                                 f"request needs {nbytes} bytes, budget is {self.budget}")
         rows, _ = self.ctx.matrices[matrix]
+        words = ebic.ebic_mask_words(rows)
+        # Like Context.eval: both count arrays, and both masks when asked for
+        # (the negative ones are zero when negative trends are not counted).
+        m = np.empty(n, np.int32)
+        g = np.empty(n, np.int32)
+        mm = np.empty((n, words), np.uint64) if masks else None
+        nm = np.empty((n, words), np.uint64) if masks else None
+        flags = ebic.Context.flags(include, negative)
         fut: concurrent.futures.Future = concurrent.futures.Future()
-        r = _Req(run, matrix, offsets, cols, include, negative, masks, nbytes, fut,
-                 time.perf_counter(), n=n, checks=rows * int(offsets[-1]))
-        with self._cv:
-            if self._stop:
+        tag = next(self._tags)
+        ptr = lambda a: None if a is None else a.ctypes.data
+        with self._mu:
+            if self._closing:
                 raise RuntimeError("server is closed")
-            self._waiting.append(r)
-            self._cv.notify()
+            self._pending[tag] = _Pending(fut, (offsets, cols, m, g, mm, nm), time.perf_counter())
+        try:
+            ebic.ebic_server_submit(self.handle, matrix, n, offsets.ctypes.data,
+                                    cols.ctypes.data if cols.size else None, flags, m.ctypes.data,
+                                    ptr(g), ptr(mm), ptr(nm), tag)
+        except Exception:
+            with self._mu:
+                self._pending.pop(tag, None)
+            raise
         return fut
 
-    def close(self, wait: bool = True):
-        with self._cv:
-            self._stop = True
-            self._cv.notify()
-        if wait:
-            self._thread.join()
+    def _poll_loop(self):
+        tags = np.zeros(256, np.uint64)
+        sts = np.zeros(256, np.int32)
+        while True:
+            k = ebic.ebic_server_poll(self.handle, tags, sts, 20000)
+            now = time.perf_counter()
+            for i in range(k):
+                with self._mu:
+                    p = self._pending.pop(int(tags[i]))
+                _, _, m, g, mm, nm = p.keep
+                if sts[i] != ebic.EBIC_OK:
+                    p.future.set_exception(ebic.EbicError(int(sts[i]), "batch launch failed"))
+                else:
+                    p.future.set_result(Result(m, g, mm, nm, now - p.t_submit))
+            with self._mu:
+                if self._closing and not self._pending:
+                    return
+
+    def close(self):
+        """Complete every submitted request, then stop the engine."""
+        if self.handle is None:
+            return
+        with self._mu:
+            self._closing = True
+        self._poller.join()
+        self._final_stats = self._raw_stats()
+        ebic.ebic_server_destroy(self.handle)
+        self.handle = None
 
     def __enter__(self):
         return self
@@ -147,84 +145,22 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
-    def stats(self) -> Dict[str, float]:
-        lat = np.array(self.latencies) if self.latencies else np.zeros(1)
-        return {"completed": self.completed, "batches": self.batches,
-                "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                "mean_batch": self.completed / max(1, self.batches),
-                "admitted_bytes_high_water": self.high_water,
-                "checks": self.checks_done}
+    def _raw_stats(self, reset: bool = False):
+        st = ebic.ebic_server_get_stats(self.handle, reset)
+        return {"completed": st.completed, "batches": st.batches, "pending": st.pending,
+                "p50_ms": st.latency_p50_ms, "p99_ms": st.latency_p99_ms,
+                "mean_batch": st.mean_batch,
+                "admitted_bytes_high_water": st.high_water_bytes,
+                "reserved_bytes": st.reserved_bytes, "budget_bytes": st.budget_bytes,
+                "checks": st.nominal_checks}
 
-    # -- scheduler ------------------------------------------------------------
-    def _admit(self) -> bool:
-        """Move waiting requests onto the device while the budget allows."""
-        moved = False
-        while self._waiting and self.reserved + self._waiting[0].bytes <= self.budget:
-            r = self._waiting.popleft()
-            self.reserved += r.bytes
-            self.high_water = max(self.high_water, self.reserved)
-            self._admitted.append(r)
-            moved = True
-        return moved
+    def stats(self, reset: bool = False) -> Dict[str, float]:
+        """Engine counters (latency from submission to completion in the
+        engine); reset=True starts a new measurement window."""
+        if self.handle is None:
+            return dict(self._final_stats or {})
+        return self._raw_stats(reset)
 
-    def _launch(self, slot: _Slot):
-        batch = []
-        while self._admitted and len(batch) < self.max_batch:
-            batch.append(self._admitted.popleft())
-        if not batch:
-            return
-        with torch.cuda.stream(slot.stream):
-            reqs = []
-            for r in batch:
-                r.pop = self.ctx.population(offsets=r.offsets, cols=r.cols)
-                r.out = self.ctx.outputs(r.matrix, r.n, masks=r.masks, negative=True)
-                reqs.append(self.ctx.request(r.matrix, r.pop, r.out, include=r.include,
-                                             negative=r.negative))
-            self.ctx.eval_batch(reqs, stream=slot.stream)
-            ev = torch.cuda.Event()
-            ev.record(slot.stream)
-        slot.event = ev
-        slot.batch = batch
-        self.batches += 1
-
-    def _complete(self, slot: _Slot):
-        now = time.perf_counter()
-        for r in slot.batch:
-            m, g, mm, nm = r.out
-            res = Result(m.cpu().numpy(), g.cpu().numpy(),
-                         None if mm is None else mm.cpu().numpy().view(np.uint64),
-                         None if nm is None else nm.cpu().numpy().view(np.uint64),
-                         now - r.t_submit)
-            self.reserved -= r.bytes
-            self.latencies.append(res.latency_s)
-            self.completed += 1
-            self.checks_done += r.checks
-            r.pop = r.out = None
-            r.future.set_result(res)
-        slot.batch = []
-        slot.event = None
-
-    def _loop(self):
-        torch.cuda.set_device(self.ctx.device)
-        while True:
-            with self._cv:
-                progressed = self._admit()
-                free = [s for s in self.slots if not s.busy]
-                if self._admitted and free:
-                    self._launch(free[0])
-                    progressed = True
-                for s in self.slots:
-                    if s.busy and s.event.query():
-                        self._complete(s)
-                        progressed = True
-                        self._admit()
-                idle = not self._waiting and not self._admitted and \
-                    not any(s.busy for s in self.slots)
-                if self._stop and idle:
-                    return
-                if not progressed:
-                    if idle:
-                        self._cv.wait(timeout=0.05)
-                    else:
-                        self._cv.wait(timeout=50e-6)
+    @property
+    def high_water(self) -> int:
+        return int(self.stats()["admitted_bytes_high_water"])
