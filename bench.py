@@ -153,6 +153,20 @@ def bench_batched(ctx, args):
     reps = 20
     b_ms = _timed(batched, reps, stream)
     p_ms = _timed(plain, reps, stream)
+    # The batched launch against the compare-issue roofline: executed compare
+    # instructions (measurement variant, untimed) over the graph's duration
+    # (HIP events around the replay: descriptor copy, prep, evaluation).
+    ebic.ebic_set_profiling(ctx.handle, 2)
+    batched()
+    _, _, b_steps = ebic.ebic_read_profile(ctx.handle)
+    ebic.ebic_set_profiling(ctx.handle, 1)
+    ebic.ebic_read_profile(ctx.handle)
+    for _ in range(reps):
+        batched()
+    n_l, l_ms, _ = ebic.ebic_read_profile(ctx.handle)
+    ebic.ebic_set_profiling(ctx.handle, 0)
+    g_ms = l_ms / max(1, n_l)
+    b_achieved = b_steps * 64 / (g_ms * 1e-3) / 1e12
     ctx.release(mat)
     return {
         "workload": "64 populations (%d individuals, lengths 2 + min(38, Exp(mean 5)), "
@@ -162,6 +176,10 @@ def bench_batched(ctx, args):
         "plain_checks_per_s": checks / (p_ms * 1e-3),
         "speedup": p_ms / b_ms,
         "equal_results": True,
+        "graph_ms": g_ms,
+        "executed_compares": b_steps,
+        "roofline": {"bound": "alu", "achieved": b_achieved, "peak": CMP_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": b_achieved / CMP_PEAK_TOPS},
         "timing": "median of %d synchronised calls; batched = one ebic_eval_batch (descriptor "
                   "copy + graph replay), plain = 64 ebic_eval_population calls" % reps,
     }
@@ -277,8 +295,10 @@ def bench_served(ctx, args):
         "client_latency": "Python load generator: scheduled arrival to the future's result",
         "served_checks_per_s": done_checks / args.serve_seconds,
         "drain_s_after_last_arrival": max(0.0, t_end - dur),
+        "max_ms": st["max_ms"], "queue_p99_ms": st["queue_p99_ms"],
         "batches": st["batches"], "mean_batch": st["mean_batch"],
         "admitted_bytes_high_water": st["admitted_bytes_high_water"],
+        "graph_captures_total": st["graph_captures"], "staging_grows": st["staging_grows"],
     }
     log(f"served: open loop p50 {out['open_loop']['p50_ms']:.2f} ms "
         f"p99 {out['open_loop']['p99_ms']:.2f} ms")

@@ -245,6 +245,10 @@ typedef struct ebic_server_stats {
     double latency_p50_ms;    /* submission to completion */
     double latency_p99_ms;
     double mean_batch;        /* requests per batched launch */
+    double latency_max_ms;
+    int64_t graph_captures;   /* batch graphs the context has captured in all */
+    int64_t staging_grows;    /* pinned staging buffers enlarged */
+    double queue_p99_ms;      /* submission to the enqueue of the request's batch */
 } ebic_server_stats;
 
 /*

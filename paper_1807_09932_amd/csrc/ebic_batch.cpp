@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <tuple>
@@ -56,6 +57,7 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t copy_node = nullptr;
+    std::mutex mu;  // one replay at a time per graph (its pinned buffers alternate)
 };
 
 using GraphKey = std::tuple<hipStream_t, int32_t, int32_t, int32_t, int64_t, int32_t, int32_t,
@@ -66,7 +68,6 @@ void check(hipError_t e, const char *what) { hip_check(e, what); }
 }  // namespace
 
 struct BatchState {
-    hipStream_t capture = nullptr;
     std::map<GraphKey, std::unique_ptr<GraphEntry>> graphs;
 };
 
@@ -90,7 +91,6 @@ void destroy_batch_state(ebic_ctx *ctx)
     if (!ctx->batch) return;
     for (auto &kv : ctx->batch->graphs) free_entry(ctx, kv.second.get());
     ctx->batch->graphs.clear();
-    if (ctx->batch->capture) (void)hipStreamDestroy(ctx->batch->capture);
     delete ctx->batch;
     ctx->batch = nullptr;
     ctx->batch_state_allocated = false;
@@ -211,35 +211,46 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     return p;
 }
 
-static GraphEntry *get_graph(ebic_ctx *ctx, hipStream_t s, const Plan &p, bool count)
+struct GraphSpec {
+    GraphKey key;
+    int32_t cap_req, cap_items;
+    int64_t cap_ind;
+};
+
+static GraphSpec graph_spec(hipStream_t s, const Plan &p, bool count)
 {
-    if (!ctx->batch) {
-        ctx->batch = new BatchState();
-        ctx->batch_state_allocated = true;
-        check(hipStreamCreateWithFlags(&ctx->batch->capture, hipStreamNonBlocking), "hipStreamCreate");
-    }
-    // Capacities rounded up to powers of two so that nearby batch sizes share a graph.
+    // Capacities rounded up to powers of two, with floors that cover typical
+    // batches, so that batches of different sizes share a graph (a capture
+    // costs milliseconds; the floors cost about 1.3 MB per graph).
     auto pow2 = [](int64_t x) {
         int64_t v = 1;
         while (v < x) v <<= 1;
         return v;
     };
-    const int32_t cap_req = (int32_t)pow2(std::max<int64_t>(8, (int64_t)p.descs.size()));
-    const int32_t cap_items = (int32_t)pow2(std::max<int64_t>(64, (int64_t)p.items.size()));
-    const int64_t cap_ind = pow2(std::max<int64_t>(1024, p.total_ind));
-    GraphKey key{s, p.cfg.L, p.cfg.W, p.cfg.P, (int64_t)p.tile_bytes, p.grid, cap_req, cap_items,
-                 cap_ind, count};
-    auto it = ctx->batch->graphs.find(key);
-    if (it != ctx->batch->graphs.end()) return it->second.get();
+    GraphSpec g;
+    g.cap_req = (int32_t)pow2(std::max<int64_t>(64, (int64_t)p.descs.size()));
+    g.cap_items = (int32_t)pow2(std::max<int64_t>(8192, (int64_t)p.items.size()));
+    g.cap_ind = pow2(std::max<int64_t>(16384, p.total_ind));
+    g.key = GraphKey{s, p.cfg.L, p.cfg.W, p.cfg.P, (int64_t)p.tile_bytes, p.grid, g.cap_req, g.cap_items,
+                     g.cap_ind, count};
+    return g;
+}
 
+// Capture a new graph for `spec`. Holds no context lock: the capture runs on
+// a stream of its own in thread-local capture mode, so evaluations on other
+// streams proceed meanwhile.
+static std::unique_ptr<GraphEntry> capture_graph(ebic_ctx *ctx, const GraphSpec &spec, const Plan &p,
+                                                 bool count)
+{
     auto g = std::make_unique<GraphEntry>();
-    g->cap_req = cap_req;
-    g->cap_items = cap_items;
-    g->cap_ind = cap_ind;
-    const ArenaLayout lay(cap_req, cap_items);
+    g->cap_req = spec.cap_req;
+    g->cap_items = spec.cap_items;
+    g->cap_ind = spec.cap_ind;
+    const ArenaLayout lay(spec.cap_req, spec.cap_items);
+    hipStream_t cs = nullptr;
     try {
         g->d_arena = ctx_alloc(ctx, lay.bytes);
-        g->d_heads = static_cast<IndHead *>(ctx_alloc(ctx, (size_t)cap_ind * sizeof(IndHead)));
+        g->d_heads = static_cast<IndHead *>(ctx_alloc(ctx, (size_t)spec.cap_ind * sizeof(IndHead)));
         for (int i = 0; i < 2; ++i) {
             check(hipHostMalloc(&g->h_arena[i], lay.bytes, hipHostMallocDefault), "hipHostMalloc");
             std::memset(g->h_arena[i], 0, lay.bytes);
@@ -248,7 +259,7 @@ static GraphEntry *get_graph(ebic_ctx *ctx, hipStream_t s, const Plan &p, bool c
         char *da = static_cast<char *>(g->d_arena);
         const int prep_blocks = std::max(1, ctx->cu_count * 2);
         unsigned long long *counter = count ? ctx->d_step_counter : nullptr;
-        hipStream_t cs = ctx->batch->capture;
+        check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
         check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
         hipError_t e = hipMemcpyAsync(da, g->h_arena[0], lay.bytes, hipMemcpyHostToDevice, cs);
         if (e == hipSuccess)
@@ -273,13 +284,14 @@ static GraphEntry *get_graph(ebic_ctx *ctx, hipStream_t s, const Plan &p, bool c
             if (t == hipGraphNodeTypeMemcpy) g->copy_node = n;
         }
         if (!g->copy_node) fail(EBIC_EHIP, "captured batch graph has no copy node");
+        check(hipStreamDestroy(cs), "hipStreamDestroy");
+        cs = nullptr;
     } catch (...) {
+        if (cs) (void)hipStreamDestroy(cs);
         free_entry(ctx, g.get());
         throw;
     }
-    GraphEntry *raw = g.get();
-    ctx->batch->graphs.emplace(key, std::move(g));
-    return raw;
+    return g;
 }
 
 }  // namespace ebic
@@ -295,7 +307,6 @@ extern "C" ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, 
         if (n_reqs == 0) return;
         hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
         DeviceGuard dg(ctx->device);
-        std::lock_guard<std::mutex> lk(ctx->batch_mu);
         Plan p;
         int32_t prof_mode;
         {
@@ -305,11 +316,32 @@ extern "C" ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, 
         }
         if (p.items.empty()) return;  // every population is empty
         const bool count = (prof_mode & 2) != 0;
-        GraphEntry *g;
+        const GraphSpec spec = graph_spec(s, p, count);
+        GraphEntry *g = nullptr;
         {
-            std::lock_guard<std::mutex> lk2(ctx->mu);
-            g = get_graph(ctx, s, p, count);
+            std::lock_guard<std::mutex> lk(ctx->batch_mu);
+            if (!ctx->batch) {
+                ctx->batch = new BatchState();
+                ctx->batch_state_allocated = true;
+            }
+            auto it = ctx->batch->graphs.find(spec.key);
+            if (it != ctx->batch->graphs.end()) g = it->second.get();
         }
+        if (!g) {
+            std::unique_ptr<GraphEntry> fresh = capture_graph(ctx, spec, p, count);
+            std::lock_guard<std::mutex> lk(ctx->batch_mu);
+            auto it = ctx->batch->graphs.find(spec.key);
+            if (it != ctx->batch->graphs.end()) {  // another thread captured it meanwhile
+                free_entry(ctx, fresh.get());
+                g = it->second.get();
+            } else {
+                g = fresh.get();
+                ctx->batch->graphs.emplace(spec.key, std::move(fresh));
+                std::lock_guard<std::mutex> lk2(ctx->mu);
+                ++ctx->graph_captures;
+            }
+        }
+        std::lock_guard<std::mutex> lkg(g->mu);
         const int slot = g->next;
         g->next ^= 1;
         // This slot's pinned buffer was last read by the launch two calls ago.

@@ -65,7 +65,8 @@ struct ebic_ctx {
     ebic::LaunchCfg override_cfg;              // W > 0: forced launch shape
     std::map<ebic::TuneKey, ebic::LaunchCfg> tuned;
     ebic::BatchState *batch = nullptr;
-    std::mutex batch_mu;  // serialises batch planning and graph reuse
+    int64_t graph_captures = 0;  // batch graphs captured so far (under mu)
+    std::mutex batch_mu;  // guards the batch graph cache (captures run outside it)
     bool batch_state_allocated = false;
     std::map<hipStream_t, ebic::Scratch> scratch;
     // Diagnostics (ebic_set_profiling / ebic_read_profile).

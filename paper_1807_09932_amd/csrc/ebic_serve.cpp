@@ -76,7 +76,7 @@ struct Req {
     int32_t *matched = nullptr, *negative = nullptr;
     uint64_t *mmask = nullptr, *nmask = nullptr;
     Sizes sz;
-    double t_submit = 0;
+    double t_submit = 0, t_launched = 0;
     int64_t checks = 0;
     // placement inside the batch region
     size_t in_off = 0, out_off = 0;
@@ -162,8 +162,9 @@ struct ebic_server {
     std::thread scheduler;
     // statistics
     int64_t submitted = 0, completed = 0, batches = 0, batched_requests = 0;
-    int64_t reserved = 0, high_water = 0, checks = 0;
+    int64_t reserved = 0, high_water = 0, checks = 0, staging_grows = 0;
     std::vector<double> latencies_ms;
+    std::vector<double> queue_ms;  // submission to the batch's enqueue on its slot
 };
 
 namespace ebic {
@@ -172,6 +173,7 @@ namespace {
 void complete_locked(ebic_server *srv, std::unique_ptr<Req> r, ebic_status st, double t_done)
 {
     srv->latencies_ms.push_back((t_done - r->t_submit) * 1e3);
+    srv->queue_ms.push_back(((r->t_launched > 0 ? r->t_launched : t_done) - r->t_submit) * 1e3);
     ++srv->completed;
     srv->checks += r->checks;
     srv->done.emplace_back(r->tag, st);
@@ -194,10 +196,14 @@ ebic_status launch_batch_on(ebic_server *srv, Slot &sl)
         }
         const size_t total = in_total + out_total;
         if (sl.h_cap < total) {
+            const size_t cap = std::max<size_t>(total, 2 * sl.h_cap);
             if (sl.h_buf) hip_check(hipHostFree(sl.h_buf), "hipHostFree");
             sl.h_buf = nullptr;
             sl.h_cap = 0;
-            const size_t cap = std::max<size_t>(total, 1 << 20);
+            {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                ++srv->staging_grows;
+            }
             hip_check(hipHostMalloc(reinterpret_cast<void **>(&sl.h_buf), cap, hipHostMallocDefault),
                       "hipHostMalloc");
             sl.h_cap = cap;
@@ -298,6 +304,8 @@ void scheduler_main(ebic_server *srv)
         srv->batched_requests += (int64_t)take;
         lk.unlock();
         const ebic_status st = launch_batch_on(srv, sl);
+        const double t_l = now_s();
+        for (auto &r : sl.batch) r->t_launched = t_l;
         lk.lock();
         sl.launch_status = st;
         sl.launched = true;
@@ -415,10 +423,16 @@ ebic_status ebic_server_create(ebic_ctx *ctx, int64_t hbm_budget_bytes, int32_t 
         srv->d_arena = static_cast<char *>(ctx_alloc(ctx, (size_t)srv->budget));
         srv->free_list = std::make_unique<FreeList>((size_t)srv->budget);
         try {
+            // Pinned staging per slot, sized for a full batch of typical
+            // requests up front (grown by doubling if a batch needs more).
+            const size_t stage0 = (size_t)std::min<int64_t>(srv->budget, (int64_t)16 << 20);
             for (int32_t i = 0; i < slots; ++i) {
                 auto s = std::make_unique<Slot>();
                 hip_check(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
                 hip_check(hipEventCreateWithFlags(&s->done, hipEventDisableTiming), "hipEventCreate");
+                hip_check(hipHostMalloc(reinterpret_cast<void **>(&s->h_buf), stage0, hipHostMallocDefault),
+                          "hipHostMalloc");
+                s->h_cap = stage0;
                 srv->slots.push_back(std::move(s));
             }
             srv->scheduler = std::thread(scheduler_main, srv.get());
@@ -531,7 +545,21 @@ ebic_status ebic_server_get_stats(ebic_server *srv, ebic_server_stats *out, int3
         s.budget_bytes = srv->budget;
         s.nominal_checks = srv->checks;
         s.mean_batch = srv->batches ? (double)srv->batched_requests / (double)srv->batches : 0.0;
+        s.staging_grows = srv->staging_grows;
+        {
+            std::lock_guard<std::mutex> lk2(srv->ctx->mu);
+            s.graph_captures = srv->ctx->graph_captures;
+        }
         std::vector<double> v = srv->latencies_ms;
+        if (!v.empty()) s.latency_max_ms = *std::max_element(v.begin(), v.end());
+        {
+            std::vector<double> q = srv->queue_ms;
+            if (!q.empty()) {
+                const size_t i = std::min(q.size() - 1, (size_t)(0.99 * (double)(q.size() - 1) + 0.5));
+                std::nth_element(q.begin(), q.begin() + (ptrdiff_t)i, q.end());
+                s.queue_p99_ms = q[i];
+            }
+        }
         if (!v.empty()) {
             auto pct = [&](double q) {
                 const size_t i = std::min(v.size() - 1, (size_t)(q * (double)(v.size() - 1) + 0.5));
@@ -550,6 +578,7 @@ ebic_status ebic_server_get_stats(ebic_server *srv, ebic_server_stats *out, int3
             srv->checks = 0;
             srv->high_water = srv->reserved;
             srv->latencies_ms.clear();
+            srv->queue_ms.clear();
         }
     });
 }

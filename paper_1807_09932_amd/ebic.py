@@ -70,7 +70,9 @@ class ebic_server_stats(ctypes.Structure):
                 ("reserved_bytes", ctypes.c_int64), ("high_water_bytes", ctypes.c_int64),
                 ("budget_bytes", ctypes.c_int64), ("nominal_checks", ctypes.c_int64),
                 ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
-                ("mean_batch", ctypes.c_double)]
+                ("mean_batch", ctypes.c_double), ("latency_max_ms", ctypes.c_double),
+                ("graph_captures", ctypes.c_int64), ("staging_grows", ctypes.c_int64),
+                ("queue_p99_ms", ctypes.c_double)]
 
 
 class ebic_ea_params(ctypes.Structure):

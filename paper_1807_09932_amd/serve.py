@@ -149,6 +149,8 @@ class Server:
         st = ebic.ebic_server_get_stats(self.handle, reset)
         return {"completed": st.completed, "batches": st.batches, "pending": st.pending,
                 "p50_ms": st.latency_p50_ms, "p99_ms": st.latency_p99_ms,
+                "max_ms": st.latency_max_ms, "graph_captures": st.graph_captures,
+                "staging_grows": st.staging_grows, "queue_p99_ms": st.queue_p99_ms,
                 "mean_batch": st.mean_batch,
                 "admitted_bytes_high_water": st.high_water_bytes,
                 "reserved_bytes": st.reserved_bytes, "budget_bytes": st.budget_bytes,
