@@ -927,6 +927,10 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             __syncthreads();
         }
 
+        // The individuals of this wave on the staged chunk; the loop is
+        // compiled twice, with and without the mask stores.
+        auto individuals = [&](auto masks_tag) {
+        constexpr bool MASKS = decltype(masks_tag)::value;
         for (int32_t ii = wave; ii < np; ii += W) {
             int4 hv[3];
             load_head(hb, ii, hv);
@@ -960,15 +964,36 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                     pm += __popcll(M[s]);
                     pg += __popcll(G[s]);
                 }
-                if (lane == 0) {
-                    cnt[2 * ii] += pm;
-                    cnt[2 * ii + 1] += pg;
+                if (pm | pg) {
+                    // Lane 0 adds both counts to the block's LDS accumulators;
+                    // no result is returned, so nothing waits for it.
+                    const uint32_t a = lds_addr(cnt + 2 * ii);
+                    uint64_t save;
+                    uint32_t va, vm, vg;
+                    asm volatile(
+                        "s_mov_b64 %[save], exec\n\t"
+                        "s_mov_b64 exec, 1\n\t"
+                        "v_mov_b32 %[va], %[a]\n\t"
+                        "v_mov_b32 %[vm], %[pm]\n\t"
+                        "v_mov_b32 %[vg], %[pg]\n\t"
+                        "ds_add_u32 %[va], %[vm]\n\t"
+                        "ds_add_u32 %[va], %[vg] offset:4\n\t"
+                        "s_mov_b64 exec, %[save]"
+                        : [save] "=&s"(save), [va] "=&v"(va), [vm] "=&v"(vm), [vg] "=&v"(vg)
+                        : [a] "s"(a), [pm] "s"(pm), [pg] "s"(pg)
+                        : "memory");
                 }
             }
-            const int64_t i = i0 + ii;
-            if (d.mmask) store_words<L>(d.mmask + i * words + tb, M, nl, lane);
-            if (d.nmask) store_words<L>(d.nmask + i * words + tb, G, nl, lane);
+            if constexpr (MASKS) {
+                const int64_t i = i0 + ii;
+                if (d.mmask) store_words<L>(d.mmask + i * words + tb, M, nl, lane);
+                if (d.nmask) store_words<L>(d.nmask + i * words + tb, G, nl, lane);
+            }
         }
+        };
+        if (d.mmask || d.nmask) individuals(std::true_type{});
+        else individuals(std::false_type{});
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the count adds, before the barrier
     }
 
     __syncthreads();
