@@ -161,6 +161,16 @@ def config3(rows: int = 436444):
     return w, pop
 
 
+def config3_wide(rows: int = 436444, cols: int = 310):
+    """The methylation workload at the paper's own dataset width (Results,
+    Table 1: 436,444 x 310, 541 MB): Beta(0.5,0.5), 10 planted trends,
+    800 individuals of 2-30 columns."""
+    lo, hi = (1000, 20000) if rows >= 436444 else (max(1, rows // 400), max(1, rows // 25))
+    w = make_matrix(30, rows, cols, "beta", 10, (lo, hi), (4, 12), directions="alternate")
+    pop = make_population(30, 0, cols, 800, (2, 30), w.plants)
+    return w, pop
+
+
 def config4(rows: int = 100000, n_pops: int = 64):
     lo, hi = (500, 5000) if rows >= 100000 else (max(1, rows // 200), max(1, rows // 20))
     w = make_matrix(4, rows, 256, "normal", 8, (lo, hi), (4, 12))
