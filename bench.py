@@ -36,7 +36,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("ebic_eval.hip", "ebic_internal.h")
+KERNEL_SOURCES = ("ebic_eval.hip", "ebic_chain.inc", "ebic_internal.h")
 
 
 def kernel_sources_sha():
@@ -434,8 +434,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--rows", type=int, default=436444, help="(testing only) smaller matrix")
     ap.add_argument("--shape", type=str, default="",
-                    help="force the launch shape 'L,W,P' (64-row tiles per wave, waves per "
-                         "block, individuals per group) instead of autotuning")
+                    help="force the launch shape 'L,W,P[,S]' (64-row tiles per wave, waves per "
+                         "block, individuals per group, staging: 0 FP32 tile, 1 direct, "
+                         "2 rank codes) instead of autotuning")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times), to scale "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
@@ -489,9 +490,11 @@ def main():
         ctx.eval(mat, p, include=False, negative=True, masks=False, out=out)
 
     if args.shape:
-        L, W, P = (int(x) for x in args.shape.split(","))
-        ctx.set_launch_shape(L, W, P, ebic.STAGE_LDS, 0)
-        shape_note = f"forced L={L} W={W} P={P}"
+        parts = [int(x) for x in args.shape.split(",")]
+        L, W, P = parts[:3]
+        S = parts[3] if len(parts) > 3 else ebic.STAGE_LDS
+        ctx.set_launch_shape(L, W, P, S, 0)
+        shape_note = f"forced L={L} W={W} P={P} staging={S}"
     else:
         # The library's autotuner picks the launch shape for this shape class.
         ctx.autotune([ctx.request(mat, p, out, include=False, negative=True)])

@@ -108,8 +108,11 @@ const char *ebic_last_error(void);
  *                     must not be NaN.
  *   out_matrix: receives a handle (>= 0).
  * The resident copy is column-major with a leading dimension padded to a
- * multiple of 64 rows (missing cells stored as NaN). Returns after the copy
- * has completed on `hip_stream`.
+ * multiple of 64 rows (missing cells stored as NaN). A matrix of at most 384
+ * columns also keeps its rank codes (per cell, the number of smaller cells
+ * of its row, as FP16; half the bytes of the values, and of the fill copy
+ * if kept), which stage twice the rows in LDS and compare exactly as the
+ * values do. Returns after the copy has completed on `hip_stream`.
  */
 ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, int32_t cols,
                                int64_t ld_src, uint32_t flags, float missing_sentinel,
@@ -190,7 +193,9 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
  *   tiles_per_wave:        64-row tiles one wave evaluates together (1, 2, 4)
  *   waves_per_block:       1 .. 16
  *   individuals_per_group: individuals that share one block's staged tiles
- *   staging:               0 = column tiles staged in LDS, 1 = direct reads
+ *   staging:               0 = column tiles staged in LDS, 1 = direct reads,
+ *                          2 = the rank codes staged in LDS (2 or 4 sub-tiles;
+ *                              include mode needs EBIC_KEEP_FILL_COPY)
  *   blocks:                grid size per group, 0 = from occupancy
  * Shapes that do not fit the device are reduced at launch (fewer tiles per
  * wave, then direct reads). Results never depend on the shape.
@@ -202,7 +207,8 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
  * The launch shape an evaluation of n_ind individuals (nnz columns in all,
  * or -1 if unknown) on `matrix` would use now: the forced shape if one is
  * set, else the tuned one for its shape class, else the default, reduced to
- * what the device fits. Any output may be NULL. Staging: 0 = LDS, 1 = direct.
+ * what the device fits. Any output may be NULL. Staging: 0 = LDS, 1 = direct,
+ * 2 = rank codes in LDS.
  */
 ebic_status ebic_plan_shape(ebic_ctx *ctx, int32_t matrix, int32_t n_ind, int64_t nnz,
                             int32_t *tiles_per_wave, int32_t *waves_per_block,

@@ -149,16 +149,24 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     c.W = std::max(1, std::min(16, c.W));
     c.P = std::max(1, c.P);
 
-    // Staging per request: LDS if the tile fits next to the counts.
+    // Staging per request: the rank codes when the shape asks for them (or
+    // the FP32 tile does not fit) and they exist and fit, else the FP32 tile
+    // if it fits next to the counts, else direct reads.
     for (int32_t q = 0; q < n_reqs; ++q) {
         const ebic_request &r = reqs[q];
         const Matrix &m = ctx_matrix(ctx, r.matrix);
-        int32_t staging = STAGE_LDS;
-        if (tile_lds_bytes(c.L, m.dev.cols) + count_lds_bytes(c.P) > lds_max) staging = STAGE_DIRECT;
+        const bool have_codes = ((r.flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
+        auto fits = [&](int32_t stg) {
+            return tile_lds_bytes(c.L, m.dev.cols, stg) + count_lds_bytes(c.P) <= lds_max;
+        };
+        int32_t staging = STAGE_DIRECT;
+        const bool codes_ok = have_codes && c.L >= 2 && fits(STAGE_CODES);
+        if (codes_ok && (c.staging == STAGE_CODES || !fits(STAGE_LDS))) staging = STAGE_CODES;
+        else if (fits(STAGE_LDS)) staging = STAGE_LDS;
         ReqDesc d = make_desc(m, std::max(0, r.n_ind), r.d_offsets, r.d_cols, r.flags, r.d_matched,
                               r.d_negative, r.d_matched_mask, r.d_negative_mask, staging);
         d.head_base = p.first.back();
-        if (staging == STAGE_LDS) p.tile_bytes = std::max(p.tile_bytes, tile_lds_bytes(c.L, m.dev.cols));
+        p.tile_bytes = std::max(p.tile_bytes, tile_lds_bytes(c.L, m.dev.cols, staging));
         p.descs.push_back(d);
         p.first.push_back(p.first.back() + d.n);
     }

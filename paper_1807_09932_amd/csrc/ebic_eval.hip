@@ -31,6 +31,7 @@
 // outputs (0, or -1 for an invalid individual) and writes its 64-byte header
 // (length, CSR start, first kWin columns clamped to the last one), which the
 // evaluation reads with one scalar load per individual.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,9 +45,10 @@ namespace {
 
 constexpr int32_t kInvalid = -1;
 
-__host__ __device__ inline size_t tile_bytes_of(int32_t L, int32_t cols)
+__host__ __device__ inline size_t tile_bytes_of(int32_t L, int32_t cols, int32_t staging)
 {
-    return (size_t)L * kWave * cols * sizeof(float);
+    if (staging == STAGE_DIRECT) return 0;
+    return (size_t)L * kWave * cols * (staging == STAGE_CODES ? sizeof(uint16_t) : sizeof(float));
 }
 
 // Per-individual [matched, negative] counts of a group of P.
@@ -452,184 +454,66 @@ __device__ __forceinline__ void eval_lds(const unsigned char *__restrict__ tile,
 // x; NaN rows are already gone), so the window may run past `last` without
 // changing the result; the exits after columns 3 and 5 only save work.
 // ---------------------------------------------------------------------------
-#define IL_LOAD4(r, w)                                                         \
-    "v_lshl_add_u32 %[ad], %[" w "], 10, %[base]\n\t"                          \
-    "ds_read_b32 %[R" r "0], %[ad]\n\t"                                        \
-    "ds_read_b32 %[R" r "1], %[ad] offset:256\n\t"                             \
-    "ds_read_b32 %[R" r "2], %[ad] offset:512\n\t"                             \
-    "ds_read_b32 %[R" r "3], %[ad] offset:768\n\t"
-#define IL_LOAD2(r, w)                                                         \
-    "v_lshl_add_u32 %[ad], %[" w "], 9, %[base]\n\t"                           \
-    "ds_read_b32 %[R" r "0], %[ad]\n\t"                                        \
-    "ds_read_b32 %[R" r "1], %[ad] offset:256\n\t"
-#define IL_XORF(c, s) "v_xor_b32 %[R" c s "], %[R" c s "], %[f" s "]\n\t"
-#define IL_XORN(c, s) ""
-#define IL_CMP2(c, p, s0, s1)                                                  \
-    "v_cmp_ge_f32_e32 vcc, %[R" c s0 "], %[R" p s0 "]\n\t"                     \
-    "v_cmp_ge_f32_e64 %[tmp], %[R" c s1 "], %[R" p s1 "]\n\t"                  \
-    "s_and_b64 %[A" s0 "], %[A" s0 "], vcc\n\t"                                \
-    "s_and_b64 %[A" s1 "], %[A" s1 "], %[tmp]\n\t"
-#define IL_STEP4(c, p, X)                                                      \
-    X(c, "0") X(c, "1") X(c, "2") X(c, "3")                                    \
-    IL_CMP2(c, p, "0", "1") IL_CMP2(c, p, "2", "3")
-#define IL_STEP2(c, p, X) X(c, "0") X(c, "1") IL_CMP2(c, p, "0", "1")
-#define IL_EXIT4(u)                                                            \
-    "s_or_b64 %[tmp], %[A0], %[A1]\n\t"                                        \
-    "s_or_b64 %[tmp], %[tmp], %[A2]\n\t"                                       \
-    "s_or_b64 %[tmp], %[tmp], %[A3]\n\t"                                       \
-    "s_cbranch_scc0 2f\n\t"                                                    \
-    "s_cmp_le_i32 %[last], " u "\n\t"                                          \
-    "s_cbranch_scc1 2f\n\t"
-#define IL_EXIT2(u)                                                            \
-    "s_or_b64 %[tmp], %[A0], %[A1]\n\t"                                        \
-    "s_cbranch_scc0 2f\n\t"                                                    \
-    "s_cmp_le_i32 %[last], " u "\n\t"                                          \
-    "s_cbranch_scc1 2f\n\t"
-// Window columns 2..7, after the first pair (sets 0 and 1 hold columns 0
-// and 1, set 2 is loading column 2).
-#define IL_WINDOW(LOAD, STEP, EXIT, X)                                         \
-    LOAD("0", "w3") "s_waitcnt lgkmcnt(%[nl])\n\t" STEP("2", "1", X)           \
-    LOAD("1", "w4") "s_waitcnt lgkmcnt(%[nl])\n\t" STEP("0", "2", X) EXIT("3") \
-    LOAD("2", "w5") "s_waitcnt lgkmcnt(%[nl])\n\t" STEP("1", "0", X)           \
-    LOAD("0", "w6") "s_waitcnt lgkmcnt(%[nl])\n\t" STEP("2", "1", X) EXIT("5") \
-    LOAD("1", "w7") "s_waitcnt lgkmcnt(%[nl])\n\t" STEP("0", "2", X)           \
-    "s_waitcnt lgkmcnt(0)\n\t" STEP("1", "0", X)
-#define IL_FIRST_NEG(s)                                                        \
-    "v_cmp_lt_f32_e64 %[F" s "], %[R1" s "], %[R0" s "]\n\t"
-#define IL_ORD(s) "v_cmp_o_f32_e64 %[A" s "], %[R1" s "], %[R0" s "]\n\t"
-#define IL_TIE(s)                                                              \
-    "v_cmp_eq_f32_e64 %[tmp], %[R1" s "], %[R0" s "]\n\t"                      \
-    "s_or_b64 %[T], %[T], %[tmp]\n\t"
-#define IL_FLIP(s) "v_cndmask_b32_e64 %[f" s "], 0, %[sign], %[F" s "]\n\t"
-#define IL_PREV(s) "v_xor_b32 %[R1" s "], %[R1" s "], %[f" s "]\n\t"
-#define IL_POS(s) "v_cmp_ge_f32_e64 %[A" s "], %[R1" s "], %[R0" s "]\n\t"
+#define IL_T "f32"
+#define IL_LD "ds_read_b32"
+#define IL_O1 "256"
+#define IL_O2 "512"
+#define IL_O3 "768"
+#define IL_SH4 "10"
+#define IL_SH2 "9"
+#define IL_NAME(f) f##_f32
+#include "ebic_chain.inc"
+#undef IL_T
+#undef IL_LD
+#undef IL_O1
+#undef IL_O2
+#undef IL_O3
+#undef IL_SH4
+#undef IL_SH2
+#undef IL_NAME
 
-#define IL_COMMON_IN                                                           \
-    [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), \
-        [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last)
+#define IL_T "f16"
+#define IL_LD "ds_read_u16"
+#define IL_O1 "128"
+#define IL_O2 "256"
+#define IL_O3 "384"
+#define IL_SH4 "9"
+#define IL_SH2 "8"
+#define IL_NAME(f) f##_f16
+#include "ebic_chain.inc"
+#undef IL_T
+#undef IL_LD
+#undef IL_O1
+#undef IL_O2
+#undef IL_O3
+#undef IL_SH4
+#undef IL_SH2
+#undef IL_NAME
 
-// Interleaved chain with negative trends: A = rows on their oriented chain
-// after column min(last, 7) (or earlier exit), F = rows falling on the first
-// pair, T = union of the rows tied on the first pair, f = per-row sign flip.
-__device__ __forceinline__ void il_neg4(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t sign,
-                                        uint64_t (&A)[4], uint64_t (&F)[4], uint64_t &T, uint32_t (&f)[4])
+// One staged element as a float: an FP32 value, or an FP16 rank code
+// (converted exactly; NaN stays NaN).
+template <typename E>
+__device__ __forceinline__ float lds_val(const unsigned char *p)
 {
-    float R00, R01, R02, R03, R10, R11, R12, R13, R20, R21, R22, R23;
-    uint32_t ad;
-    uint64_t tmp;
-    asm volatile(
-        "s_waitcnt lgkmcnt(0)\n\t"
-        IL_LOAD4("0", "w0") IL_LOAD4("1", "w1") IL_LOAD4("2", "w2")
-        "s_waitcnt lgkmcnt(%[nl])\n\t"
-        IL_FIRST_NEG("0") IL_FIRST_NEG("1") IL_FIRST_NEG("2") IL_FIRST_NEG("3")
-        IL_ORD("0") IL_ORD("1") IL_ORD("2") IL_ORD("3")
-        "v_cmp_eq_f32_e64 %[T], %[R10], %[R00]\n\t"
-        IL_TIE("1") IL_TIE("2") IL_TIE("3")
-        IL_FLIP("0") IL_FLIP("1") IL_FLIP("2") IL_FLIP("3")
-        IL_PREV("0") IL_PREV("1") IL_PREV("2") IL_PREV("3")
-        "s_cmp_lt_i32 %[last], 2\n\t"
-        "s_cbranch_scc1 2f\n\t"
-        IL_WINDOW(IL_LOAD4, IL_STEP4, IL_EXIT4, IL_XORF)
-        "2:\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : [A0] "=&s"(A[0]), [A1] "=&s"(A[1]), [A2] "=&s"(A[2]), [A3] "=&s"(A[3]),
-          [F0] "=&s"(F[0]), [F1] "=&s"(F[1]), [F2] "=&s"(F[2]), [F3] "=&s"(F[3]),
-          [T] "=&s"(T), [tmp] "=&s"(tmp), [f0] "=&v"(f[0]), [f1] "=&v"(f[1]), [f2] "=&v"(f[2]),
-          [f3] "=&v"(f[3]), [ad] "=&v"(ad), [R00] "=&v"(R00), [R01] "=&v"(R01), [R02] "=&v"(R02),
-          [R03] "=&v"(R03), [R10] "=&v"(R10), [R11] "=&v"(R11), [R12] "=&v"(R12), [R13] "=&v"(R13),
-          [R20] "=&v"(R20), [R21] "=&v"(R21), [R22] "=&v"(R22), [R23] "=&v"(R23)
-        : IL_COMMON_IN, [sign] "v"(sign), [nl] "i"(4)
-        : "vcc", "scc", "memory");
-}
-
-__device__ __forceinline__ void il_neg2(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t sign,
-                                        uint64_t (&A)[2], uint64_t (&F)[2], uint64_t &T, uint32_t (&f)[2])
-{
-    float R00, R01, R10, R11, R20, R21;
-    uint32_t ad;
-    uint64_t tmp;
-    asm volatile(
-        "s_waitcnt lgkmcnt(0)\n\t"
-        IL_LOAD2("0", "w0") IL_LOAD2("1", "w1") IL_LOAD2("2", "w2")
-        "s_waitcnt lgkmcnt(%[nl])\n\t"
-        IL_FIRST_NEG("0") IL_FIRST_NEG("1")
-        IL_ORD("0") IL_ORD("1")
-        "v_cmp_eq_f32_e64 %[T], %[R10], %[R00]\n\t"
-        IL_TIE("1")
-        "s_nop 4\n\t"  // wait states before a VALU reads an SGPR mask a VALU wrote
-        IL_FLIP("0") IL_FLIP("1")
-        IL_PREV("0") IL_PREV("1")
-        "s_cmp_lt_i32 %[last], 2\n\t"
-        "s_cbranch_scc1 2f\n\t"
-        IL_WINDOW(IL_LOAD2, IL_STEP2, IL_EXIT2, IL_XORF)
-        "2:\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : [A0] "=&s"(A[0]), [A1] "=&s"(A[1]), [F0] "=&s"(F[0]), [F1] "=&s"(F[1]), [T] "=&s"(T),
-          [tmp] "=&s"(tmp), [f0] "=&v"(f[0]), [f1] "=&v"(f[1]), [ad] "=&v"(ad), [R00] "=&v"(R00),
-          [R01] "=&v"(R01), [R10] "=&v"(R10), [R11] "=&v"(R11), [R20] "=&v"(R20), [R21] "=&v"(R21)
-        : IL_COMMON_IN, [sign] "v"(sign), [nl] "i"(2)
-        : "vcc", "scc", "memory");
-}
-
-// The >= chain alone (negative trends not requested).
-__device__ __forceinline__ void il_pos4(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint64_t (&A)[4])
-{
-    float R00, R01, R02, R03, R10, R11, R12, R13, R20, R21, R22, R23;
-    uint32_t ad;
-    uint64_t tmp;
-    asm volatile(
-        "s_waitcnt lgkmcnt(0)\n\t"
-        IL_LOAD4("0", "w0") IL_LOAD4("1", "w1") IL_LOAD4("2", "w2")
-        "s_waitcnt lgkmcnt(%[nl])\n\t"
-        IL_POS("0") IL_POS("1") IL_POS("2") IL_POS("3")
-        "s_cmp_lt_i32 %[last], 2\n\t"
-        "s_cbranch_scc1 2f\n\t"
-        IL_WINDOW(IL_LOAD4, IL_STEP4, IL_EXIT4, IL_XORN)
-        "2:\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : [A0] "=&s"(A[0]), [A1] "=&s"(A[1]), [A2] "=&s"(A[2]), [A3] "=&s"(A[3]),
-          [tmp] "=&s"(tmp), [ad] "=&v"(ad), [R00] "=&v"(R00), [R01] "=&v"(R01), [R02] "=&v"(R02),
-          [R03] "=&v"(R03), [R10] "=&v"(R10), [R11] "=&v"(R11), [R12] "=&v"(R12), [R13] "=&v"(R13),
-          [R20] "=&v"(R20), [R21] "=&v"(R21), [R22] "=&v"(R22), [R23] "=&v"(R23)
-        : IL_COMMON_IN, [nl] "i"(4)
-        : "vcc", "scc", "memory");
-}
-
-__device__ __forceinline__ void il_pos2(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint64_t (&A)[2])
-{
-    float R00, R01, R10, R11, R20, R21;
-    uint32_t ad;
-    uint64_t tmp;
-    asm volatile(
-        "s_waitcnt lgkmcnt(0)\n\t"
-        IL_LOAD2("0", "w0") IL_LOAD2("1", "w1") IL_LOAD2("2", "w2")
-        "s_waitcnt lgkmcnt(%[nl])\n\t"
-        IL_POS("0") IL_POS("1")
-        "s_cmp_lt_i32 %[last], 2\n\t"
-        "s_cbranch_scc1 2f\n\t"
-        IL_WINDOW(IL_LOAD2, IL_STEP2, IL_EXIT2, IL_XORN)
-        "2:\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : [A0] "=&s"(A[0]), [A1] "=&s"(A[1]), [tmp] "=&s"(tmp), [ad] "=&v"(ad), [R00] "=&v"(R00),
-          [R01] "=&v"(R01), [R10] "=&v"(R10), [R11] "=&v"(R11), [R20] "=&v"(R20), [R21] "=&v"(R21)
-        : IL_COMMON_IN, [nl] "i"(2)
-        : "vcc", "scc", "memory");
+    if constexpr (std::is_same<E, float>::value) return *reinterpret_cast<const float *>(p);
+    else return __half2float(__ushort_as_half(*reinterpret_cast<const uint16_t *>(p)));
 }
 
 // Plain-code twin of the interleaved window (the measurement variant and the
 // rare paths): same exit points as the sequences above. `prev` holds the
-// flipped values of column 1; counts executed compare instructions.
-template <int L, bool COUNT>
+// flipped values of column 1; counts executed compare instructions. `flip`
+// is the FP32 sign bit or 0 (values are compared as floats here).
+template <int L, bool COUNT, typename E>
 __device__ __forceinline__ void il_window_ref(const unsigned char *__restrict__ base, const int32_t (&w)[kWin],
                                               int32_t last, const uint32_t (&flip)[L], float (&prev)[L],
                                               uint64_t (&alive)[L], uint64_t &steps)
 {
-    constexpr int CB = L * kWave * 4;
+    constexpr int SB = kWave * (int)sizeof(E), CB = L * SB;
 #pragma unroll
     for (int u = 2; u < kWin; ++u) {
 #pragma unroll
         for (int s = 0; s < L; ++s) {
-            const float y = flipped(*reinterpret_cast<const float *>(base + w[u] * CB + s * kWave * 4), flip[s]);
+            const float y = flipped(lds_val<E>(base + w[u] * CB + s * SB), flip[s]);
             alive[s] &= __ballot(y >= prev[s]);
             prev[s] = y;
         }
@@ -644,18 +528,18 @@ __device__ __forceinline__ void il_window_ref(const unsigned char *__restrict__ 
 }
 
 // Columns kWin..last (long individuals; rarely any row is left).
-template <int L, bool COUNT>
+template <int L, bool COUNT, typename E>
 __device__ __forceinline__ void il_tail(const unsigned char *__restrict__ base, const int32_t *__restrict__ c,
                                         int32_t last, const uint32_t (&flip)[L], float (&prev)[L],
                                         uint64_t (&alive)[L], uint64_t &steps)
 {
-    constexpr int CB = L * kWave * 4;
+    constexpr int SB = kWave * (int)sizeof(E), CB = L * SB;
     for (int32_t u = kWin; u <= last; ++u) {
         const int32_t col = c[u];
         uint64_t any = 0;
 #pragma unroll
         for (int s = 0; s < L; ++s) {
-            const float y = flipped(*reinterpret_cast<const float *>(base + col * CB + s * kWave * 4), flip[s]);
+            const float y = flipped(lds_val<E>(base + col * CB + s * SB), flip[s]);
             alive[s] &= __ballot(y >= prev[s]);
             prev[s] = y;
             any |= alive[s];
@@ -665,21 +549,21 @@ __device__ __forceinline__ void il_tail(const unsigned char *__restrict__ base, 
     }
 }
 
-// One individual on the L (2 or 4) sub-tiles of a chunk. Rows outside the
+// One individual on the L (2 or 4) sub-tiles of a chunk, staged as FP32
+// values (E = float) or FP16 rank codes (E = uint16_t). Rows outside the
 // matrix hold NaN in the tile, so they never match.
-template <int L, bool NEG, bool COUNT>
+template <int L, bool NEG, bool COUNT, typename E>
 __device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ tile, int32_t last,
                                             const int32_t *__restrict__ c, const int4 &w03,
-                                            const int4 &w47, int lane4, uint64_t (&M)[L],
+                                            const int4 &w47, int lane, uint64_t (&M)[L],
                                             uint64_t (&G)[L], uint64_t &steps)
 {
     static_assert(L == 2 || L == 4, "interleaved evaluation takes 2 or 4 sub-tiles");
-    constexpr int CB = L * kWave * 4;
-    const unsigned char *base = tile + lane4;
+    constexpr bool H = !std::is_same<E, float>::value;
+    constexpr int SB = kWave * (int)sizeof(E), CB = L * SB;
+    const unsigned char *base = tile + lane * (int)sizeof(E);
     const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
-    auto ld = [&](int32_t col, int s) -> float {
-        return *reinterpret_cast<const float *>(base + col * CB + s * kWave * 4);
-    };
+    auto ld = [&](int32_t col, int s) -> float { return lds_val<E>(base + col * CB + s * SB); };
     if (last == 0) {  // one column: the row counts unless its value is missing
 #pragma unroll
         for (int s = 0; s < L; ++s) {
@@ -711,16 +595,30 @@ __device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ ti
         }
         if (COUNT) steps += (NEG ? 3 : 1) * L;
         if constexpr (COUNT) {
-            if (last >= 2) il_window_ref<L, COUNT>(base, w, last, f, prev, A, steps);
+            if (last >= 2) il_window_ref<L, COUNT, E>(base, w, last, f, prev, A, steps);
         } else {
             const uint32_t b = lds_addr(base);
-            if constexpr (L == 4) il_pos4(b, w, last, A);
-            else il_pos2(b, w, last, A);
+            if constexpr (H) {
+                if constexpr (L == 4) il_pos4_f16(b, w, last, A);
+                else il_pos2_f16(b, w, last, A);
+            } else {
+                if constexpr (L == 4) il_pos4_f32(b, w, last, A);
+                else il_pos2_f32(b, w, last, A);
+            }
         }
     } else {
         const uint32_t b = lds_addr(base);
-        if constexpr (L == 4) il_neg4(b, w, last, kSign, A, F, T, f);
-        else il_neg2(b, w, last, kSign, A, F, T, f);
+        if constexpr (H) {
+            // The FP16 sign bit flips a code; the plain code below compares
+            // converted floats, so the flips are widened afterwards.
+            if constexpr (L == 4) il_neg4_f16(b, w, last, kSign >> 16, A, F, T, f);
+            else il_neg2_f16(b, w, last, kSign >> 16, A, F, T, f);
+#pragma unroll
+            for (int s = 0; s < L; ++s) f[s] <<= 16;
+        } else {
+            if constexpr (L == 4) il_neg4_f32(b, w, last, kSign, A, F, T, f);
+            else il_neg2_f32(b, w, last, kSign, A, F, T, f);
+        }
     }
     if (last >= kWin) {
         uint64_t any = 0;
@@ -730,7 +628,7 @@ __device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ ti
             float prev[L];
 #pragma unroll
             for (int s = 0; s < L; ++s) prev[s] = flipped(ld(w[kWin - 1], s), f[s]);
-            il_tail<L, COUNT>(base, c, last, f, prev, A, steps);
+            il_tail<L, COUNT, E>(base, c, last, f, prev, A, steps);
         }
     }
 #pragma unroll
@@ -755,7 +653,7 @@ __device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ ti
                 prev[s] = flipped(v1, kSign);
             }
             if (COUNT) steps += L;
-            if (last >= 2) il_window_ref<L, COUNT>(base, w, last, fl, prev, ta, steps);
+            if (last >= 2) il_window_ref<L, COUNT, E>(base, w, last, fl, prev, ta, steps);
             if (last >= kWin) {
                 uint64_t any = 0;
 #pragma unroll
@@ -763,7 +661,7 @@ __device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ ti
                 if (any) {
 #pragma unroll
                     for (int s = 0; s < L; ++s) prev[s] = flipped(ld(w[kWin - 1], s), kSign);
-                    il_tail<L, COUNT>(base, c, last, fl, prev, ta, steps);
+                    il_tail<L, COUNT, E>(base, c, last, fl, prev, ta, steps);
                 }
             }
 #pragma unroll
@@ -849,20 +747,6 @@ __device__ __forceinline__ void load_head(const IndHead *__restrict__ hb, int32_
                  "s"(hv[1].w), "s"(hv[2].x), "s"(hv[2].y), "s"(hv[2].z), "s"(hv[2].w));
 }
 
-__device__ __forceinline__ void load_head_async(const IndHead *__restrict__ hb, int32_t ii, int4 (&hv)[3])
-{
-    const int4 *p = reinterpret_cast<const int4 *>(hb + ii);
-    hv[0] = p[0];
-    hv[1] = p[2];
-    hv[2] = p[3];
-}
-
-__device__ __forceinline__ void head_ready(int4 (&hv)[3])
-{
-    asm volatile("" : "+s"(hv[0].x), "+s"(hv[0].y), "+s"(hv[1].x), "+s"(hv[1].y), "+s"(hv[1].z),
-                 "+s"(hv[1].w), "+s"(hv[2].x), "+s"(hv[2].y), "+s"(hv[2].z), "+s"(hv[2].w));
-}
-
 // ---------------------------------------------------------------------------
 // One work item: individuals [i0, i0 + np) of request d on tiles [t0, t1).
 // `tile` and `cnt` are this block's LDS areas; wave w takes the group's
@@ -895,6 +779,30 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         for (int s = 0; s < L; ++s) valid[s] = __ballot(s < nl && row0 + s * kWave + lane < d.rows);
 
         __syncthreads();  // counts initialised; the previous chunk's readers are done
+        if constexpr (STAGE == STAGE_CODES) {
+            // Rows [row0, row0 + nl*64) of every column's rank codes, 4 rows
+            // (8 bytes) per thread; codes of include mode already encode the
+            // fill value.
+            uint16_t *tile16 = reinterpret_cast<uint16_t *>(tile);
+            const int q_per_col = nl * (kWave / 4);
+            const int total = q_per_col * d.cols;
+            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+                const int c = idx / q_per_col;
+                const int q = idx - c * q_per_col;
+                *reinterpret_cast<uint2 *>(tile16 + (size_t)c * T + 4 * q) =
+                    *reinterpret_cast<const uint2 *>(d.C + (int64_t)c * d.ld + row0 + 4 * q);
+            }
+            if (nl < L || row0 + T > d.rows) {  // as below: outside rows never match
+                __syncthreads();
+                const int64_t first = min<int64_t>(d.rows - row0, (int64_t)nl * kWave);
+                const int tail = T * d.cols;
+                for (int idx = threadIdx.x; idx < tail; idx += blockDim.x) {
+                    const int r = idx % T;
+                    if (r >= first) tile16[idx] = kCodeNaN;
+                }
+            }
+            __syncthreads();
+        }
         if constexpr (STAGE == STAGE_LDS) {
             // Rows [row0, row0 + nl*64) of every column, 4 rows per thread.
             const int q_per_col = nl * (kWave / 4);
@@ -941,10 +849,14 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                 for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
             } else {
                 const int32_t *c = d.colidx + hv[0].y;
-                if constexpr (STAGE == STAGE_LDS) {
+                if constexpr (STAGE == STAGE_CODES) {
+                    static_assert(L >= 2, "rank codes are staged for 2 or 4 sub-tiles");
+                    eval_lds_il<L, NEG, COUNT, uint16_t>(reinterpret_cast<const unsigned char *>(tile), k - 1,
+                                                         c, hv[1], hv[2], lane, M, G, steps);
+                } else if constexpr (STAGE == STAGE_LDS) {
                     if constexpr (L >= 2)
-                        eval_lds_il<L, NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1, c,
-                                                   hv[1], hv[2], lane * 4, M, G, steps);
+                        eval_lds_il<L, NEG, COUNT, float>(reinterpret_cast<const unsigned char *>(tile), k - 1, c,
+                                                          hv[1], hv[2], lane, M, G, steps);
                     else
                         eval_lds<L, NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1, c,
                                                 hv[1], hv[2], lane * 4, valid, M, G, steps);
@@ -1014,7 +926,7 @@ k_eval(ReqDesc d, const IndHead *__restrict__ heads, int32_t P, int32_t n_tiles,
        unsigned long long *step_counter)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const size_t tb = STAGE == STAGE_LDS ? tile_bytes_of(L, d.cols) : 0;
+    const size_t tb = tile_bytes_of(L, d.cols, STAGE);
     float *tile = reinterpret_cast<float *>(smem);
     int32_t *cnt = reinterpret_cast<int32_t *>(smem + tb);
     const int32_t i0 = blockIdx.y * P;
@@ -1058,6 +970,13 @@ k_eval_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs, const Item *__
         const Item it = items[id];
         const ReqDesc d = descs[it.req];
         const bool neg = (d.flags & kFlagNeg) != 0;
+        if constexpr (L >= 2) {
+            if (d.flags & kFlagCodes) {
+                if (neg) run_item<L, true, STAGE_CODES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                else run_item<L, false, STAGE_CODES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                continue;
+            }
+        }
         if ((d.flags & kFlagDirect) == 0) {
             if (neg) run_item<L, true, STAGE_LDS, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
             else run_item<L, false, STAGE_LDS, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
@@ -1090,9 +1009,20 @@ const void *eval_pick_L(int L)
     }
 }
 
+template <bool NEG, bool COUNT>
+const void *eval_pick_codes(int L)
+{
+    switch (L) {
+    case 2: return eval_ptr<2, NEG, STAGE_CODES, COUNT>();
+    case 4: return eval_ptr<4, NEG, STAGE_CODES, COUNT>();
+    default: return nullptr;  // codes are staged for 2 or 4 sub-tiles only
+    }
+}
+
 template <bool COUNT>
 const void *eval_pick(int L, bool neg, int staging)
 {
+    if (staging == STAGE_CODES) return neg ? eval_pick_codes<true, COUNT>(L) : eval_pick_codes<false, COUNT>(L);
     if (staging == STAGE_LDS)
         return neg ? eval_pick_L<true, STAGE_LDS, COUNT>(L) : eval_pick_L<false, STAGE_LDS, COUNT>(L);
     return neg ? eval_pick_L<true, STAGE_DIRECT, COUNT>(L) : eval_pick_L<false, STAGE_DIRECT, COUNT>(L);
@@ -1121,7 +1051,7 @@ hipError_t set_lds(const void *k, size_t lds)
 
 }  // namespace
 
-size_t tile_lds_bytes(int32_t L, int32_t cols) { return tile_bytes_of(L, cols); }
+size_t tile_lds_bytes(int32_t L, int32_t cols, int32_t staging) { return tile_bytes_of(L, cols, staging); }
 
 size_t count_lds_bytes(int32_t P) { return count_bytes_of(P); }
 
@@ -1129,7 +1059,7 @@ int eval_occupancy(const LaunchCfg &cfg, int32_t cols, uint32_t flags)
 {
     const void *k = eval_kernel(cfg.L, flags, cfg.staging, false);
     if (!k) return 0;
-    const size_t lds = (cfg.staging == STAGE_LDS ? tile_bytes_of(cfg.L, cols) : 0) + count_bytes_of(cfg.P);
+    const size_t lds = tile_bytes_of(cfg.L, cols, cfg.staging) + count_bytes_of(cfg.P);
     int blocks = 0;
     if (set_lds(k, lds) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, cfg.W * kWave, lds) != hipSuccess)
@@ -1162,7 +1092,7 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
     if (!k) return hipErrorInvalidValue;
     const int32_t n_tiles = (int32_t)((d.rows + 63) / 64);
     const int32_t groups = (d.n + cfg.P - 1) / cfg.P;
-    const size_t lds = (cfg.staging == STAGE_LDS ? tile_bytes_of(cfg.L, d.cols) : 0) + count_bytes_of(cfg.P);
+    const size_t lds = tile_bytes_of(cfg.L, d.cols, cfg.staging) + count_bytes_of(cfg.P);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     ReqDesc dd = d;

@@ -15,7 +15,16 @@ constexpr int kWin = 8;    // leading columns of an individual kept in its heade
 enum Staging : int32_t {
     STAGE_LDS = 0,     // rows x all columns staged into LDS, shared by the block
     STAGE_DIRECT = 1,  // read straight from the column-major matrix (L1/L2)
+    STAGE_CODES = 2,   // the matrix's 16-bit rank codes staged into LDS (half the bytes)
 };
+
+// Rank codes are kept for matrices of at most this many columns: a cell's
+// code is the number of cells of its row that are smaller, stored as an
+// FP16 integer (exact up to 2048), NaN for a missing cell. Codes compare
+// exactly as the values do (a >= b iff code(a) >= code(b)), so the
+// predicate on codes gives the same rows.
+constexpr int32_t kMaxCodeCols = 384;
+constexpr uint16_t kCodeNaN = 0x7E00;
 
 // Request flags as the kernels see them (the low two bits are the ABI's
 // EBIC_NAN_INCLUDE and EBIC_NEG_TRENDS).
@@ -23,10 +32,11 @@ constexpr uint32_t kFlagInclude = 1u;
 constexpr uint32_t kFlagNeg = 2u;
 constexpr uint32_t kFlagDirect = 1u << 8;  // this request reads the matrix directly
 constexpr uint32_t kFlagSubst = 1u << 9;   // direct reads replace NaN by the fill value
+constexpr uint32_t kFlagCodes = 1u << 10;  // this request stages the rank codes
 
 // One launch shape of the evaluation kernels.
 struct LaunchCfg {
-    int32_t L = 0;        // 64-row sub-tiles evaluated together per wave (1, 2, 4)
+    int32_t L = 0;        // 64-row sub-tiles evaluated together per wave (1, 2, 4; codes: 2, 4)
     int32_t W = 0;        // waves per block (1..16)
     int32_t P = 0;        // individuals per group (max individuals sharing a block)
     int32_t staging = STAGE_LDS;
@@ -37,6 +47,8 @@ struct LaunchCfg {
 struct DevMatrix {
     const float *X = nullptr;      // column-major, leading dimension ld, missing = NaN
     const float *Xfill = nullptr;  // fill-substituted copy, or null
+    const uint16_t *C = nullptr;   // rank codes of X (same layout), or null
+    const uint16_t *Cfill = nullptr;  // rank codes of Xfill, or null
     int64_t ld = 0;                // multiple of 64
     int64_t rows = 0;
     int32_t cols = 0;
@@ -46,6 +58,7 @@ struct DevMatrix {
 // One population evaluation as the kernels read it.
 struct ReqDesc {
     const float *X;            // the matrix to read (the fill copy when it serves include mode)
+    const uint16_t *C;         // the rank codes to stage (kFlagCodes), or null
     int64_t ld;
     int64_t rows;
     int32_t cols;
@@ -95,7 +108,7 @@ struct BatchHeader {
 
 // Bytes of dynamic LDS one work item needs: the staged tile (if staged) and
 // the per-individual counts of a group of P.
-size_t tile_lds_bytes(int32_t L, int32_t cols);
+size_t tile_lds_bytes(int32_t L, int32_t cols, int32_t staging);
 size_t count_lds_bytes(int32_t P);
 
 // Blocks per CU the plain evaluation kernel reaches with this shape (0 = cannot run).
@@ -128,6 +141,11 @@ hipError_t launch_batch(BatchHeader *hdr, const ReqDesc *descs, const int64_t *f
 hipError_t launch_layout(const float *src, int64_t ld_src, bool src_col_major, int64_t nr,
                          int32_t cols, int64_t r0, float *dst, int64_t ld, float sentinel,
                          float *dst_fill, float fill, hipStream_t s);
+
+// Rank codes of rows [0, rows) of a column-major matrix (cols <= kMaxCodeCols),
+// written column-major with the same leading dimension; padding rows get 0.
+hipError_t launch_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, uint16_t *C,
+                        hipStream_t s);
 
 // Zero rows [rows, ld) of every column of a column-major matrix.
 hipError_t launch_zero_pad(float *dst, int64_t rows, int64_t ld, int32_t cols, hipStream_t s);

@@ -8,6 +8,7 @@
 // converted here. An optional second copy holds the fill value in place of
 // every missing cell, for the mode in which missing values take part in the
 // comparison.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -58,6 +59,32 @@ k_layout(const float *__restrict__ src, int64_t ld_src, int32_t src_col_major, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// Rank codes: for every cell, the number of cells of its row that are
+// smaller (IEEE <, so NaN is never smaller and -0 is not smaller than +0),
+// as an FP16 integer; a missing cell gets NaN. A block stages 64 rows of all
+// columns in LDS; thread (lane, wave) counts, for its row, the columns wave,
+// wave + 4, ... Padding rows get code 0.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols, uint16_t *__restrict__ C)
+{
+    extern __shared__ float t[];  // [cols][64]
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int32_t c = wave; c < cols; c += 4) t[c * 64 + lane] = X[(int64_t)c * ld + r0 + lane];
+    __syncthreads();
+    const bool live = r0 + lane < rows;
+    for (int32_t c = wave; c < cols; c += 4) {
+        const float v = t[c * 64 + lane];
+        int32_t n = 0;
+        for (int32_t j = 0; j < cols; ++j) n += t[j * 64 + lane] < v ? 1 : 0;
+        uint16_t code = __half_as_ushort(__int2half_rn(n));  // exact: n < 2048
+        if (v != v) code = kCodeNaN;
+        C[(int64_t)c * ld + r0 + lane] = live ? code : (uint16_t)0;
+    }
+}
+
 __global__ void k_zero_pad(float *__restrict__ dst, int64_t rows, int64_t ld, int32_t cols)
 {
     const int64_t pad = ld - rows;
@@ -68,6 +95,18 @@ __global__ void k_zero_pad(float *__restrict__ dst, int64_t rows, int64_t ld, in
 }
 
 }  // namespace
+
+hipError_t launch_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, uint16_t *C,
+                        hipStream_t s)
+{
+    if (cols > kMaxCodeCols) return hipErrorInvalidValue;
+    const size_t lds = (size_t)cols * 64 * sizeof(float);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_codes),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_codes, dim3((unsigned)(ld / 64)), dim3(256), lds, s, X, rows, ld, cols, C);
+    return hipGetLastError();
+}
 
 hipError_t launch_layout(const float *src, int64_t ld_src, bool src_col_major, int64_t nr,
                          int32_t cols, int64_t r0, float *dst, int64_t ld, float sentinel,

@@ -79,13 +79,24 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
     else cfg = tuned_cfg(ctx, m.dev.rows, m.dev.cols, n, nnz);
     const size_t lds_max = ctx->lds_per_block;
     cfg.P = std::max(1, std::min(cfg.P, std::max(1, n)));
-    auto lds = [&](const LaunchCfg &c) {
-        return (c.staging == STAGE_LDS ? tile_lds_bytes(c.L, m.dev.cols) : 0) + count_lds_bytes(c.P);
-    };
-    // Fall back to fewer rows per wave, then to direct reads, until the shape fits.
-    while (cfg.staging == STAGE_LDS && cfg.L > 1 && lds(cfg) > lds_max) cfg.L /= 2;
-    if (cfg.staging == STAGE_LDS && lds(cfg) > lds_max) cfg.staging = STAGE_DIRECT;
-    while (lds(cfg) > lds_max && cfg.P > 64) cfg.P /= 2;
+    auto lds = [&](const LaunchCfg &c) { return tile_lds_bytes(c.L, m.dev.cols, c.staging) + count_lds_bytes(c.P); };
+    auto fits = [&](const LaunchCfg &c) { return lds(c) <= lds_max; };
+    const bool have_codes = ((flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
+    // Rank codes need codes for this mode and at least two sub-tiles.
+    if (cfg.staging == STAGE_CODES && (!have_codes || cfg.L < 2)) cfg.staging = STAGE_LDS;
+    // An FP32 tile that does not fit: the codes' tile (half the bytes) at the
+    // same number of sub-tiles, if there are codes.
+    if (cfg.staging == STAGE_LDS && !fits(cfg) && have_codes && cfg.L >= 2) {
+        LaunchCfg c2 = cfg;
+        c2.staging = STAGE_CODES;
+        if (fits(c2)) cfg = c2;
+    }
+    // Then fewer rows per wave, FP32 staging, direct reads, until the shape fits.
+    while (cfg.staging == STAGE_CODES && cfg.L > 2 && !fits(cfg)) cfg.L /= 2;
+    if (cfg.staging == STAGE_CODES && !fits(cfg)) cfg.staging = STAGE_LDS;
+    while (cfg.staging == STAGE_LDS && cfg.L > 1 && !fits(cfg)) cfg.L /= 2;
+    if (cfg.staging == STAGE_LDS && !fits(cfg)) cfg.staging = STAGE_DIRECT;
+    while (!fits(cfg) && cfg.P > 64) cfg.P /= 2;
     const int64_t n_tiles = (m.dev.rows + 63) / 64;
     const int32_t groups = (n + cfg.P - 1) / cfg.P;
     if (cfg.blocks <= 0) {
@@ -107,7 +118,13 @@ ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int3
     ReqDesc d{};
     const bool include = (flags & EBIC_NAN_INCLUDE) != 0;
     d.X = m.dev.X;
+    d.C = nullptr;
     d.flags = flags & (kFlagInclude | kFlagNeg);
+    if (staging == STAGE_CODES) {
+        d.C = include ? m.dev.Cfill : m.dev.C;
+        if (!d.C) fail(EBIC_EINVAL, "no rank codes for this matrix and mode");
+        d.flags |= kFlagCodes;
+    }
     if (staging == STAGE_DIRECT) {
         d.flags |= kFlagDirect;
         if (include) {
@@ -225,6 +242,8 @@ ebic_status ebic_destroy(ebic_ctx *ctx)
             for (auto &kv : ctx->matrices) {
                 ctx_free(ctx, kv.second.X);
                 ctx_free(ctx, kv.second.Xfill);
+                ctx_free(ctx, kv.second.C);
+                ctx_free(ctx, kv.second.Cfill);
             }
             ctx->matrices.clear();
             destroy_batch_state(ctx);
@@ -329,16 +348,33 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             }
             hip_check(launch_zero_pad(m.X, rows, m.dev.ld, cols, s), "zero-pad kernel");
             if (m.Xfill) hip_check(launch_zero_pad(m.Xfill, rows, m.dev.ld, cols, s), "zero-pad kernel");
+            // Rank codes for matrices narrow enough: half the bytes of a
+            // staged tile, so wide matrices fit twice the rows in LDS.
+            if (cols <= kMaxCodeCols) {
+                const size_t cbytes = (size_t)m.dev.ld * cols * sizeof(uint16_t);
+                m.C = static_cast<uint16_t *>(ctx_alloc(ctx, cbytes));
+                m.bytes += cbytes;
+                hip_check(launch_codes(m.X, rows, m.dev.ld, cols, m.C, s), "codes kernel");
+                if (m.Xfill) {
+                    m.Cfill = static_cast<uint16_t *>(ctx_alloc(ctx, cbytes));
+                    m.bytes += cbytes;
+                    hip_check(launch_codes(m.Xfill, rows, m.dev.ld, cols, m.Cfill, s), "codes kernel");
+                }
+            }
             hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
         } catch (...) {
             ctx_free(ctx, staging);
             ctx_free(ctx, m.X);
             ctx_free(ctx, m.Xfill);
+            ctx_free(ctx, m.C);
+            ctx_free(ctx, m.Cfill);
             throw;
         }
         ctx_free(ctx, staging);
         m.dev.X = m.X;
         m.dev.Xfill = m.Xfill;
+        m.dev.C = m.C;
+        m.dev.Cfill = m.Cfill;
         const int32_t id = ctx->next_matrix++;
         ctx->matrices[id] = m;
         *out_matrix = id;
@@ -368,6 +404,8 @@ ebic_status ebic_release_matrix(ebic_ctx *ctx, int32_t matrix)
         hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
         ctx_free(ctx, m.X);
         ctx_free(ctx, m.Xfill);
+        ctx_free(ctx, m.C);
+        ctx_free(ctx, m.Cfill);
         ctx->matrices.erase(matrix);
     });
 }

@@ -20,6 +20,8 @@ struct Matrix {
     DevMatrix dev;
     float *X = nullptr;
     float *Xfill = nullptr;
+    uint16_t *C = nullptr;      // rank codes of X (cols <= kMaxCodeCols)
+    uint16_t *Cfill = nullptr;  // rank codes of Xfill
     size_t bytes = 0;
     float sentinel = 0.f;
 };

@@ -54,6 +54,12 @@ LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
     c.P = std::max(1, std::min(n, 400));
     c.L = default_L(cols);
     c.staging = STAGE_LDS;
+    // Wider than 64 columns: the rank codes' tile keeps two sub-tiles (or
+    // four up to 128 columns) in LDS; without codes the launch falls back.
+    if (cols > 64 && cols <= kMaxCodeCols) {
+        c.staging = STAGE_CODES;
+        c.L = cols <= 128 ? 4 : 2;
+    }
     c.blocks = 0;
     return c;
 }
@@ -65,6 +71,10 @@ LaunchCfg default_batch_cfg(int32_t max_cols)
     c.P = 400;
     c.L = default_L(max_cols);
     c.staging = STAGE_LDS;
+    if (max_cols > 64 && max_cols <= kMaxCodeCols) {
+        c.staging = STAGE_CODES;
+        c.L = max_cols <= 128 ? 4 : 2;
+    }
     c.blocks = 0;
     return c;
 }
@@ -207,7 +217,7 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
         }
         if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 4) ||
             waves_per_block < 1 || waves_per_block > 16 || individuals_per_group < 1 ||
-            !(staging == STAGE_LDS || staging == STAGE_DIRECT) || blocks < 0)
+            !(staging == STAGE_LDS || staging == STAGE_DIRECT || staging == STAGE_CODES) || blocks < 0)
             fail(EBIC_EINVAL, "launch shape out of range");
         LaunchCfg c;
         c.L = tiles_per_wave;
@@ -251,11 +261,13 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                           "hipMemcpy");
                 int64_t rows;
                 int32_t cols;
+                bool have_codes;
                 {
                     std::lock_guard<std::mutex> lk(ctx->mu);
                     const Matrix &m = ctx_matrix(ctx, r.matrix);
                     rows = m.dev.rows;
                     cols = m.dev.cols;
+                    have_codes = ((r.flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
                 }
                 const TuneKey key = tune_key(rows, cols, r.n_ind, (int64_t)ends[1] - ends[0]);
                 if (!done.insert(key).second) continue;
@@ -264,15 +276,16 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                 for (int L : {1, 2, 4})
                     for (int W : {4, 8, 16})
                         for (int P : {200, 400, 800, 1600})
-                            for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT}) {
+                            for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT, (int)STAGE_CODES}) {
                                 LaunchCfg c;
                                 c.L = L;
                                 c.W = W;
                                 c.P = std::min(P, r.n_ind);
                                 c.staging = stg;
-                                if (stg == STAGE_LDS &&
-                                    tile_lds_bytes(L, cols) + count_lds_bytes(c.P) > ctx->lds_per_block)
+                                if (stg != STAGE_DIRECT &&
+                                    tile_lds_bytes(L, cols, stg) + count_lds_bytes(c.P) > ctx->lds_per_block)
                                     continue;
+                                if (stg == STAGE_CODES && (L < 2 || !have_codes)) continue;
                                 set_override(c);
                                 const float ms = time_ms(
                                     [&] {
@@ -313,12 +326,14 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                     float best_ms = INFINITY;
                     for (int L : {1, 2, 4})
                         for (int W : {4, 8, 16})
-                            for (int P : {128, 256, 512, 1024}) {
+                            for (int P : {128, 256, 512, 1024})
+                                for (int stg : {(int)STAGE_LDS, (int)STAGE_CODES}) {
+                                if (stg == STAGE_CODES && L < 2) continue;
                                 LaunchCfg c;
                                 c.L = L;
                                 c.W = W;
                                 c.P = P;
-                                c.staging = STAGE_LDS;
+                                c.staging = stg;
                                 set_override(c);
                                 const float ms = time_ms(
                                     [&] { return ebic_eval_batch(ctx, sample, n_reqs, s) == EBIC_OK; }, 3,

@@ -38,6 +38,7 @@ EBIC_KEEP_FILL_COPY = 16
 
 STAGE_LDS = 0
 STAGE_DIRECT = 1
+STAGE_CODES = 2   # FP16 rank codes staged in LDS (matrices of <= 384 columns)
 
 EXPORTED = ["ebic_create", "ebic_destroy", "ebic_set_allocator", "ebic_last_error",
             "ebic_upload_matrix", "ebic_matrix_info", "ebic_release_matrix",

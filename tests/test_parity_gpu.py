@@ -95,6 +95,8 @@ def test_config3_methylation_full(ctx):
 SHAPES = [  # tiles_per_wave, waves_per_block, individuals_per_group, staging, blocks
     (1, 1, 1, 0, 0), (1, 4, 7, 0, 3), (2, 8, 64, 0, 0), (4, 16, 1000, 0, 0), (4, 3, 33, 0, 1),
     (2, 5, 200, 0, 7), (1, 8, 1000, 1, 0), (2, 4, 13, 1, 2), (4, 8, 300, 1, 0), (4, 1, 5, 1, 0),
+    # staging 2: the FP16 rank codes
+    (2, 8, 64, 2, 0), (4, 16, 1000, 2, 0), (4, 3, 33, 2, 1), (2, 5, 200, 2, 7), (1, 8, 100, 2, 0),
 ]
 
 
@@ -105,7 +107,8 @@ def test_launch_shapes_agree(ctx, shape):
     X = rng.integers(0, 6, size=(rows, ncols)).astype(np.float32)  # many ties
     X[rng.random((rows, ncols)) < 0.03] = np.float32(np.nan)
     offs, cols = _random_pop(rng, ncols, 301, 12, dup=0.05, bad=0.03)
-    mat = ctx.upload(X, fill=2.5)
+    # (the fill copy also gives include mode its rank codes)
+    mat = ctx.upload(X, fill=2.5, keep_fill_copy=shape[3] == 2)
     try:
         ctx.set_launch_shape(*shape)
         for include in (False, True):
@@ -147,6 +150,26 @@ def test_edge_cols(ctx, ncols):
         want = oracle_eval(X, offs, cols, include=include)
         assert_same(got, want, f"cols={ncols}")
     ctx.release(mat)
+
+
+@pytest.mark.parametrize("ncols,L", [(9, 2), (9, 4), (100, 4), (310, 2), (384, 2)])
+def test_rank_codes_special_values(ctx, ncols, L):
+    """FP16 rank-code staging on the special values (+-inf, +-0, denormals,
+    ties, NaN), in both modes, at widths up to the largest with codes."""
+    rng = np.random.default_rng(900 + ncols)
+    X = _special(rng, (777, ncols), nan_frac=0.04)
+    offs, cols = _random_pop(rng, ncols, 150, min(ncols, 14), dup=0.1, bad=0.02)
+    mat = ctx.upload(X, fill=-0.0, keep_fill_copy=True)
+    try:
+        ctx.set_launch_shape(L, 8, 64, 2, 0)
+        for include in (False, True):
+            announce("rank codes", ncols, L, include)
+            got = gpu_eval(ctx, mat, offs, cols, include=include)
+            want = oracle_eval(X, offs, cols, include=include, fill=-0.0)
+            assert_same(got, want, f"codes cols={ncols} L={L} include={include}")
+    finally:
+        ctx.set_launch_shape()
+        ctx.release(mat)
 
 
 def test_invalid_and_degenerate_individuals(ctx):
@@ -251,8 +274,8 @@ def test_error_paths(ctx):
     assert e.value.status == ebic.EBIC_ENOENT
 
 
-@pytest.mark.parametrize("tiles_per_wave", [1, 2, 4])
-def test_measurement_variant_agrees(ctx, tiles_per_wave):
+@pytest.mark.parametrize("tiles_per_wave,staging", [(1, 0), (2, 0), (4, 0), (2, 2), (4, 2)])
+def test_measurement_variant_agrees(ctx, tiles_per_wave, staging):
     """The step-counting kernel variant (profiling mode 2) computes the same
     outputs as the timed one, and counts a positive number of steps."""
     from paper_1807_09932_amd import ebic
@@ -260,9 +283,9 @@ def test_measurement_variant_agrees(ctx, tiles_per_wave):
     X = rng.integers(0, 5, size=(3000, 30)).astype(np.float32)
     X[rng.random(X.shape) < 0.02] = np.float32(np.nan)
     offs, cols = _random_pop(rng, 30, 150, 20, dup=0.05, bad=0.02)
-    mat = ctx.upload(X)
+    mat = ctx.upload(X, keep_fill_copy=True)
     try:
-        ctx.set_launch_shape(tiles_per_wave, 4, 50, 0, 0)
+        ctx.set_launch_shape(tiles_per_wave, 4, 50, staging, 0)
         ebic.ebic_set_profiling(ctx.handle, 3)
         for include in (False, True):
             for negative in (False, True):
