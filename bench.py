@@ -437,6 +437,8 @@ def main():
                     help="force the launch shape 'L,W,P[,S]' (64-row tiles per wave, waves per "
                          "block, individuals per group, staging: 0 FP32 tile, 1 direct, "
                          "2 rank codes) instead of autotuning")
+    ap.add_argument("--cold-cache-evals", type=int, default=20,
+                    help="evaluations timed after streaming a 1 GiB buffer (0 = none)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times), to scale "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
@@ -549,9 +551,9 @@ def main():
     # Cold cache: a 1 GiB buffer is streamed (read and written) before each
     # evaluation, so the matrix comes from HBM rather than the 256 MB
     # Infinity Cache; median kernel time over 20 such evaluations.
-    flush = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+    flush = torch.zeros(1 << 28, dtype=torch.float32, device="cuda") if args.cold_cache_evals else None
     cold = []
-    for _ in range(20):
+    for _ in range(args.cold_cache_evals):
         flush.add_(1.0)
         ebic.ebic_set_profiling(ctx.handle, 1)
         step()
@@ -559,7 +561,7 @@ def main():
         cold.append(ms_c / max(1, n_c))
     ebic.ebic_set_profiling(ctx.handle, 0)
     del flush
-    cold_ms = float(np.median(cold))
+    cold_ms = float(np.median(cold)) if cold else None
 
     ms_per_step = wall * 1e3 / args.steps
     value = checks / (wall / args.steps)
