@@ -563,6 +563,20 @@ def main():
     del flush
     cold_ms = float(np.median(cold)) if cold else None
 
+    # The measured copy ceiling: a 1 GiB device-to-device copy (read + write).
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        b.copy_(a)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * a.numel() * 4 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del a, b
+
     ms_per_step = wall * 1e3 / args.steps
     value = checks / (wall / args.steps)
     k_ms = kernel_ms / max(1, launches)
@@ -622,6 +636,12 @@ def main():
             "note": "gather-equivalent: 4 B per nominal check; the staged kernel reads the "
                     "matrix once, so this is not physical traffic",
             "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9,
+            "physical_gbs": (traffic_from_profile(1) / (k_ms * 1e-3) / 1e9
+                             if traffic_from_profile(1) else None),
+            "copy_ceiling_gbs": copy_gbs,
+            "physical_note": "HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE "
+                             "summary over the measured kernel time; copy ceiling = a 1 GiB "
+                             "device copy (bytes read + written per second)",
         },
         "latency_ms": {
             "eval_p50": float(np.percentile(step_ms, 50)),
