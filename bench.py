@@ -53,7 +53,7 @@ def kernel_sources_sha():
 def traffic_from_profile(launch_units):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_eval_config3_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_eval_methylation_436444x64_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -110,7 +110,7 @@ def bench_batched(ctx, args):
     import torch
     from paper_1807_09932_amd import ebic, gen
     log("batched: generating 64 populations over a 100,000 x 256 matrix")
-    w, pops = gen.config4()
+    w, pops = gen.batched_100000x256()
     mat = ctx.upload(w.X)
     packed = [gen.csr(p) for p in pops]
     dev = [ctx.population(offsets=o, cols=c) for o, c in packed]
@@ -196,7 +196,7 @@ def bench_ea(ctx, args, w=None):
     import torch
     from paper_1807_09932_amd import ebic, gen
     if w is None:
-        w, _ = gen.config3()
+        w, _ = gen.methylation_436444x64()
     rows, ncols = w.X.shape
     mat = ctx.upload(w.X)
     ea = ebic.EA(ncols, 800, 2, 30, seed=180709932)
@@ -238,7 +238,7 @@ def bench_paper_shape(ctx, args):
     import torch
     from paper_1807_09932_amd import ebic, gen
     log("paper shape: generating 436,444 x 310")
-    w, pop = gen.config3_wide()
+    w, pop = gen.methylation_wide()
     offs, cols = gen.csr(pop)
     rows, ncols = w.X.shape
     mat = ctx.upload(w.X)
@@ -288,14 +288,14 @@ def bench_served(ctx, args):
     from paper_1807_09932_amd import gen
     from paper_1807_09932_amd.serve import Server
     log("served: uploading 4 matrices, generating request pools")
-    ws = gen.config5_matrices()
+    ws = gen.served_matrices()
     mats = [ctx.upload(x.X) for x in ws]
-    pools = gen.config5_pools()
+    pools = gen.served_pools()
     rows = [x.X.shape[0] for x in ws]
     resident = sum(x.X.nbytes for x in ws)
     budget = 1 << 30
     dur = args.serve_warmup + args.serve_seconds
-    reqs = gen.config5_requests(dur)
+    reqs = gen.served_requests(dur)
     out = {"workload": "4 resident matrices (10,000 x 100, 50,000 x 200 N(0,1); 200,000 x 64, "
                        "436,444 x 64 Beta(0.5,0.5); %.0f MB); 16 runs, run j on matrix j mod 4; "
                        "populations of 100-800 individuals of 2-30 columns" % (resident / 1e6),
@@ -452,8 +452,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(row or population sharding across GPUs is described in DESIGN.md, not built)",
+        print(f"bench.py: the evaluation runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding rows or populations across GPUs is designed, not built)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -476,7 +476,7 @@ def main():
         return
 
     log("generating the methylation-shaped workload")
-    w, pop = gen.config3(rows=args.rows)
+    w, pop = gen.methylation_436444x64(rows=args.rows)
     offs, cols = gen.csr(pop)
     rows, ncols = w.X.shape
     n = offs.size - 1

@@ -7,7 +7,7 @@ the CPU oracle and the HIP path can take their inputs from it without sharing
 any of the method's arithmetic.
 
 Every draw goes through ``numpy.random.default_rng`` (PCG64) seeded with
-``SEED_BASE + config_index`` (``+ 1000 * sub_stream`` for populations and
+``SEED_BASE + stream`` (``+ 1000 * sub_stream`` for populations and
 request streams). Values are drawn in float64 and rounded to float32 (round
 to nearest even).
 
@@ -26,8 +26,8 @@ import numpy as np
 SEED_BASE = 180709932
 
 
-def rng_for(config_index: int, sub: int = 0) -> np.random.Generator:
-    return np.random.default_rng(SEED_BASE + int(config_index) + 1000 * int(sub))
+def rng_for(stream: int, sub: int = 0) -> np.random.Generator:
+    return np.random.default_rng(SEED_BASE + int(stream) + 1000 * int(sub))
 
 
 def draw_values(rng: np.random.Generator, dist: str, shape) -> np.ndarray:
@@ -71,7 +71,7 @@ def _distinct_sorted_rows(rng, dist, m, k, increasing):
     return out
 
 
-def make_matrix(config_index: int, rows: int, cols: int, dist: str,
+def make_matrix(stream: int, rows: int, cols: int, dist: str,
                 n_plants: int, plant_rows: Tuple[int, int], plant_cols: Tuple[int, int],
                 directions: str = "increasing", nan_fraction: float = 0.0) -> Workload:
     """Matrix + planted trend biclusters (+ missing cells after planting).
@@ -82,7 +82,7 @@ def make_matrix(config_index: int, rows: int, cols: int, dist: str,
     ``directions``: "increasing", or "alternate" (even plants increasing,
     odd plants decreasing).
     """
-    rng = rng_for(config_index)
+    rng = rng_for(stream)
     X = draw_values(rng, dist, (rows, cols))
     plants: List[Plant] = []
     sizes = [int(rng.integers(plant_rows[0], plant_rows[1] + 1)) for _ in range(n_plants)]
@@ -117,14 +117,14 @@ def csr(individuals: Sequence[Sequence[int]]) -> Tuple[np.ndarray, np.ndarray]:
     return offs.astype(np.int32), cols
 
 
-def make_population(config_index: int, sub: int, cols: int, n: int,
+def make_population(stream: int, sub: int, cols: int, n: int,
                     lengths, plants: Sequence[Plant] = ()) -> List[np.ndarray]:
     """Planted orders first, then random individuals.
 
     ``lengths`` is (lo, hi) for a uniform integer length, or a callable
     ``f(rng) -> int``. Columns are distinct, ``choice(cols, k)`` in draw order.
     """
-    rng = rng_for(config_index, sub + 1)
+    rng = rng_for(stream, sub + 1)
     inds: List[np.ndarray] = [p.cols.copy() for p in plants][:n]
     while len(inds) < n:
         k = int(lengths(rng)) if callable(lengths) else int(rng.integers(lengths[0], lengths[1] + 1))
@@ -142,26 +142,26 @@ def skewed_length(rng: np.random.Generator) -> int:
 # The five workloads. ``scale`` < 1 shrinks the row count (tests only).
 # --------------------------------------------------------------------------
 
-def config1():
+def uniform_1000x50():
     w = make_matrix(1, 1000, 50, "uniform", 3, (50, 50), (8, 8))
     pop = make_population(1, 0, 50, 100, (3, 8), w.plants)
     return w, pop
 
 
-def config2():
+def normal_missing_20000x200():
     w = make_matrix(2, 20000, 200, "normal", 8, (200, 1000), (5, 15), nan_fraction=0.05)
     pop = make_population(2, 0, 200, 800, (3, 20), w.plants)
     return w, pop
 
 
-def config3(rows: int = 436444):
+def methylation_436444x64(rows: int = 436444):
     lo, hi = (1000, 20000) if rows >= 436444 else (max(1, rows // 400), max(1, rows // 25))
     w = make_matrix(3, rows, 64, "beta", 10, (lo, hi), (4, 12), directions="alternate")
     pop = make_population(3, 0, 64, 800, (2, 30), w.plants)
     return w, pop
 
 
-def config3_wide(rows: int = 436444, cols: int = 310):
+def methylation_wide(rows: int = 436444, cols: int = 310):
     """The methylation workload at the paper's own dataset width (Results,
     Table 1: 436,444 x 310, 541 MB): Beta(0.5,0.5), 10 planted trends,
     800 individuals of 2-30 columns."""
@@ -171,7 +171,7 @@ def config3_wide(rows: int = 436444, cols: int = 310):
     return w, pop
 
 
-def config4(rows: int = 100000, n_pops: int = 64):
+def batched_100000x256(rows: int = 100000, n_pops: int = 64):
     lo, hi = (500, 5000) if rows >= 100000 else (max(1, rows // 200), max(1, rows // 20))
     w = make_matrix(4, rows, 256, "normal", 8, (lo, hi), (4, 12))
     rng = rng_for(4, 999)
@@ -180,13 +180,13 @@ def config4(rows: int = 100000, n_pops: int = 64):
     return w, pops
 
 
-CONFIG5_SHAPES = [(10000, 100, "normal"), (50000, 200, "normal"),
+SERVED_SHAPES = [(10000, 100, "normal"), (50000, 200, "normal"),
                   (200000, 64, "beta"), (436444, 64, "beta")]
 
 
-def config5_matrices(scale: float = 1.0):
+def served_matrices(scale: float = 1.0):
     out = []
-    for m, (r, c, dist) in enumerate(CONFIG5_SHAPES):
+    for m, (r, c, dist) in enumerate(SERVED_SHAPES):
         rr = max(64, int(r * scale))
         out.append(make_matrix(50 + m, rr, c, dist, 4,
                                (max(1, rr // 200), max(1, rr // 50)), (4, 12)))
@@ -214,18 +214,18 @@ class Request:
     pool_index: int           # population in that matrix's pool
 
 
-def config5_pools(pool_size: int = 32, n_range=(100, 800), k_range=(2, 30)):
+def served_pools(pool_size: int = 32, n_range=(100, 800), k_range=(2, 30)):
     """Per resident matrix, `pool_size` seeded populations (CSR): the
     generations the served runs submit are drawn from these."""
     pools = []
-    for m, (_, c, _) in enumerate(CONFIG5_SHAPES):
+    for m, (_, c, _) in enumerate(SERVED_SHAPES):
         rng = rng_for(5, 100 + m)
         pools.append([population_fast(rng, c, int(rng.integers(n_range[0], n_range[1] + 1)), k_range)
                       for _ in range(pool_size)])
     return pools
 
 
-def config5_requests(duration_s: float, rate_hz: float = 2000.0, n_runs: int = 16,
+def served_requests(duration_s: float, rate_hz: float = 2000.0, n_runs: int = 16,
                      pool_size: int = 32):
     """Poisson arrivals (mean rate_hz) from n_runs concurrent runs; run j
     uses matrix j mod 4 and submits populations from that matrix's pool."""
@@ -236,7 +236,7 @@ def config5_requests(duration_s: float, rate_hz: float = 2000.0, n_runs: int = 1
     t = t[t < duration_s]
     runs = rng.integers(0, n_runs, size=t.size)
     picks = rng.integers(0, pool_size, size=t.size)
-    return [Request(float(t[i]), int(runs[i]), int(runs[i]) % len(CONFIG5_SHAPES), int(picks[i]))
+    return [Request(float(t[i]), int(runs[i]), int(runs[i]) % len(SERVED_SHAPES), int(picks[i]))
             for i in range(t.size)]
 
 

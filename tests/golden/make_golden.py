@@ -1,4 +1,4 @@
-"""Writes tests/golden/config1_counts.json from the CPU oracle alone.
+"""Writes tests/golden/uniform_1000x50_counts.json from the CPU oracle alone.
 
 Regression fixture: the counts of the 1,000 x 50 plain-evaluation workload
 (seeded generator) in both missing-value modes, with and without the
@@ -26,7 +26,7 @@ def digest(*arrays):
 
 
 def main():
-    w, pop = gen.config1()
+    w, pop = gen.uniform_1000x50()
     offs, cols = gen.csr(pop)
     out = {"workload": "1000x50 U[0,1), 3 planted 50x8, 100 individuals of 3-8 columns",
            "inputs_sha256": digest(w.X, offs, cols), "runs": {}}
@@ -37,7 +37,7 @@ def main():
             key = f"{'include' if include else 'exclude'}_{'neg' if negative else 'pos'}"
             out["runs"][key] = {"matched": m.tolist(), "negative": n.tolist(),
                                 "masks_sha256": digest(mm, nm)}
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "config1_counts.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "uniform_1000x50_counts.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path)

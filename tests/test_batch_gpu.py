@@ -43,7 +43,7 @@ def _run_batch(ctx, jobs, stream=None):
 
 
 def test_batched_skewed_populations(ctx):
-    """Config-4 shape, reduced: uneven population sizes, lengths 2..40
+    """The batched 100,000 x 256 workload, reduced: uneven population sizes, lengths 2..40
     skewed toward short, one N(0,1) matrix with planted trends."""
     w = gen.make_matrix(4, 20000, 256, "normal", 8, (100, 1000), (4, 12))
     pops = _pops(41, 256, 24, (5, 400), gen.skewed_length)
@@ -136,14 +136,14 @@ def test_batch_invalid_and_empty(ctx):
     ctx.release(mat)
 
 
-def test_batch_matches_plain_on_config4_sample(ctx):
-    """Three populations of the full config-4 workload (100,000 x 256)."""
-    w, pops = gen.config4(n_pops=3)
+def test_batch_matches_plain_on_batched_100000x256_sample(ctx):
+    """Three populations of the full batched workload (100,000 x 256)."""
+    w, pops = gen.batched_100000x256(n_pops=3)
     mat = ctx.upload(w.X)
     packed = [gen.csr(p) for p in pops]
     jobs = [(mat, p, False, True, False) for p in packed]
-    announce("config4 sample batch")
+    announce("batched_100000x256 sample batch")
     got = _run_batch(ctx, jobs)
     for i, p in enumerate(packed):
-        assert_same(got[i], oracle_eval(w.X, *p, masks=False), f"config4 pop {i}")
+        assert_same(got[i], oracle_eval(w.X, *p, masks=False), f"batched_100000x256 pop {i}")
     ctx.release(mat)

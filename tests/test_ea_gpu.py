@@ -10,17 +10,19 @@ from tests.gpu_common import announce, oracle_eval, to_np
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("config,include", [(3, False), (2, False), (2, True)])
-def test_ea_trajectory_gpu_equals_oracle(config, include):
+@pytest.mark.parametrize("workload,include", [("methylation", False), ("missing", False),
+                                              ("missing", True)])
+def test_ea_trajectory_gpu_equals_oracle(workload, include):
     from paper_1807_09932_amd.ebic import Context
-    w = gen.config3()[0] if config == 3 else gen.config2()[0]
+    w = (gen.methylation_436444x64()[0] if workload == "methylation"
+         else gen.normal_missing_20000x200()[0])
     rows, n_cols = w.X.shape
     ctx = Context(0)
     mat = ctx.upload(w.X)
-    ea = ebic.EA(n_cols, 400, 2, 30 if n_cols >= 30 else n_cols, seed=1000 + config)
+    ea = ebic.EA(n_cols, 400, 2, 30 if n_cols >= 30 else n_cols, seed=1000 + len(workload))
     for g in range(6):
         offs, cols, gno = ea.population()
-        announce("ea generation", config, include, gno)
+        announce("ea generation", workload, include, gno)
         pop = ctx.population(offsets=offs, cols=cols)
         m, neg, _, _ = ctx.eval(mat, pop, include=include, negative=True)
         gm, gn = to_np(m), to_np(neg)

@@ -11,9 +11,9 @@ from tests.golden.make_golden import digest
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def test_config1_golden():
-    ref = json.load(open(os.path.join(HERE, "golden", "config1_counts.json")))
-    w, pop = gen.config1()
+def test_uniform_1000x50_golden():
+    ref = json.load(open(os.path.join(HERE, "golden", "uniform_1000x50_counts.json")))
+    w, pop = gen.uniform_1000x50()
     offs, cols = gen.csr(pop)
     assert digest(w.X, offs, cols) == ref["inputs_sha256"]
     for key, run in ref["runs"].items():

@@ -106,7 +106,7 @@ def _parse_export(path):
 
 
 def test_export_matches_masks(tmp_path):
-    w, pop = gen.config1()
+    w, pop = gen.uniform_1000x50()
     offs, cols = gen.csr(pop)
     rows = w.X.shape[0]
     m, _, mm, _ = oracle.eval_population(w.X, offs, cols, negative=True, masks=True, threads=4)

@@ -13,7 +13,7 @@ def test_oracle_pin(pin):
 
 def test_oracle_threads_agree():
     from paper_1807_09932_amd import gen
-    w, pop = gen.config1()
+    w, pop = gen.uniform_1000x50()
     offs, cols = gen.csr(pop)
     a = oracle.eval_population(w.X, offs, cols, masks=True, threads=1)
     b = oracle.eval_population(w.X, offs, cols, masks=True, threads=4)

@@ -42,53 +42,53 @@ def _random_pop(rng, ncols, n, kmax, dup=0.0, bad=0.0):
 
 @pytest.mark.parametrize("include", [False, True])
 @pytest.mark.parametrize("negative", [False, True])
-def test_config1_plain(ctx, include, negative):
-    w, pop = gen.config1()
+def test_uniform_1000x50_plain(ctx, include, negative):
+    w, pop = gen.uniform_1000x50()
     offs, cols = gen.csr(pop)
     mat = ctx.upload(w.X)
-    announce("config1", include, negative)
+    announce("uniform_1000x50", include, negative)
     got = gpu_eval(ctx, mat, offs, cols, include=include, negative=negative)
     want = oracle_eval(w.X, offs, cols, include=include, negative=negative)
-    assert_same(got, want, "config1")
+    assert_same(got, want, "uniform_1000x50")
     ctx.release(mat)
 
 
 @pytest.fixture(scope="module")
 def cfg2():
-    return gen.config2()
+    return gen.normal_missing_20000x200()
 
 
 @pytest.mark.parametrize("include,fill", [(False, 0.0), (True, 0.0), (True, 999.0)])
-def test_config2_missing_values(ctx, cfg2, include, fill):
+def test_normal_missing_values(ctx, cfg2, include, fill):
     w, pop = cfg2
     offs, cols = gen.csr(pop)
     mat = ctx.upload(w.X, fill=fill)
-    announce("config2", include, fill)
+    announce("normal_missing_20000x200", include, fill)
     got = gpu_eval(ctx, mat, offs, cols, include=include)
     want = oracle_eval(w.X, offs, cols, include=include, fill=fill)
-    assert_same(got, want, f"config2 include={include} fill={fill}")
+    assert_same(got, want, f"normal_missing_20000x200 include={include} fill={fill}")
     ctx.release(mat)
 
 
-def test_config3_methylation_full(ctx):
+def test_methylation_436444x64_full(ctx):
     """436,444 rows x 64 columns, 800 individuals: every count and every mask
     word against the oracle, in the launch shape the benchmark uses."""
-    w, pop = gen.config3()
+    w, pop = gen.methylation_436444x64()
     offs, cols = gen.csr(pop)
     mat = ctx.upload(w.X)
-    announce("config3 full")
+    announce("methylation_436444x64 full")
     got = gpu_eval(ctx, mat, offs, cols, negative=True, masks=True)
     want = oracle_eval(w.X, offs, cols, negative=True, masks=True)
-    assert_same(got, want, "config3")
+    assert_same(got, want, "methylation_436444x64")
     # planted trends are recovered in full
     mm = got[2]
     for i, p in enumerate(w.plants):
         bits = np.unpackbits(mm[i].view(np.uint8), bitorder="little")[: w.X.shape[0]]
         assert bits[p.rows].all()
-    announce("config3 positive only")
+    announce("methylation_436444x64 positive only")
     got = gpu_eval(ctx, mat, offs, cols, negative=False, masks=False)
     want = oracle_eval(w.X, offs, cols, negative=False, masks=False)
-    assert_same(got, want, "config3 pos")
+    assert_same(got, want, "methylation_436444x64 pos")
     ctx.release(mat)
 
 
@@ -236,7 +236,7 @@ def test_upload_layouts(ctx):
 
 
 def test_repeat_is_deterministic(ctx):
-    w, pop = gen.config1()
+    w, pop = gen.uniform_1000x50()
     offs, cols = gen.csr(pop)
     mat = ctx.upload(w.X)
     announce("repeat")

@@ -15,9 +15,9 @@ pytestmark = pytest.mark.gpu
 def served():
     from paper_1807_09932_amd.ebic import Context
     ctx = Context(0)
-    ws = gen.config5_matrices(scale=0.05)
+    ws = gen.served_matrices(scale=0.05)
     mats = [ctx.upload(w.X) for w in ws]
-    pools = gen.config5_pools(pool_size=6, n_range=(20, 200))
+    pools = gen.served_pools(pool_size=6, n_range=(20, 200))
     yield ctx, ws, mats, pools
     ctx.close()
 
@@ -33,7 +33,7 @@ def _alone(ctx, mat, offs, cols, negative=True, masks=False, include=False):
 def test_results_in_the_mix_equal_results_alone(served):
     from paper_1807_09932_amd.serve import Server
     ctx, ws, mats, pools = served
-    reqs = gen.config5_requests(0.2, rate_hz=1000.0, pool_size=6)[:150]
+    reqs = gen.served_requests(0.2, rate_hz=1000.0, pool_size=6)[:150]
     announce("serve mix", len(reqs))
     with Server(ctx, hbm_budget_bytes=64 << 20, slots=3) as srv:
         t0 = time.perf_counter()
