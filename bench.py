@@ -280,6 +280,55 @@ def bench_paper_shape(ctx, args):
             "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9}
 
 
+def bench_shard(ctx, args, w, offs, cols):
+    """One GPU's share under row sharding across 8 GPUs (Methods, "Support for
+    Big Data"): the first slice of ceil(rows/8) rows rounded up to a multiple
+    of 64, with the whole population, autotuned and timed; the 8 partial
+    counts would then be summed (a 2 x n int32 reduction per generation)."""
+    import torch
+    from paper_1807_09932_amd import ebic, gen
+    rows, ncols = w.X.shape
+    per_gpu = -(-rows // 8)
+    step = -(-per_gpu // 64) * 64      # slice starts on 64-row mask words
+    X = w.X[:step]
+    mat = ctx.upload(X)
+    p = ctx.population(offsets=offs, cols=cols)
+    out = ctx.outputs(mat, p.n)
+    ctx.set_launch_shape(0, 0, 0, ebic.STAGE_LDS, 0)
+    ctx.autotune([ctx.request(mat, p, out)])
+    L, W, P, stg, blocks = ebic.ebic_plan_shape(ctx.handle, mat, p.n, int(offs[-1]))
+    ctx.eval(mat, p, out=out)
+    torch.cuda.synchronize()
+    import oracle
+    sample = np.arange(0, p.n, max(1, p.n // 8))
+    so, sc = gen.csr([cols[offs[i]:offs[i + 1]] for i in sample])
+    om, on, _, _ = oracle.eval_population(X, so, sc, negative=True,
+                                          threads=max(1, min(16, os.cpu_count() or 1)))
+    if not (np.array_equal(out[0].cpu().numpy()[sample], om) and
+            np.array_equal(out[1].cpu().numpy()[sample], on)):
+        print("bench.py: GPU counts differ from the oracle (row slice)", file=sys.stderr)
+        sys.exit(3)
+    ebic.ebic_set_profiling(ctx.handle, 2)
+    ctx.eval(mat, p, out=out)
+    _, _, steps = ebic.ebic_read_profile(ctx.handle)
+    ebic.ebic_set_profiling(ctx.handle, 1)
+    ebic.ebic_read_profile(ctx.handle)
+    for _ in range(20):
+        ctx.eval(mat, p, out=out)
+    n_l, ms, _ = ebic.ebic_read_profile(ctx.handle)
+    ebic.ebic_set_profiling(ctx.handle, 0)
+    k_ms = ms / max(1, n_l)
+    checks = gen.nominal_checks(step, offs)
+    ach = steps * 64 / (k_ms * 1e-3) / 1e12
+    ctx.release(mat)
+    return {"workload": "rows 0-%d of the %d x %d methylation matrix (one of 8 row slices), "
+                        "%d individuals" % (step, rows, ncols, p.n),
+            "launch_shape": f"L={L} W={W} P={P} staging={stg} blocks={blocks}",
+            "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
+            "roofline": {"bound": "alu", "achieved": ach, "peak": CMP_PEAK_TOPS, "unit": "TOP/s",
+                         "frac": ach / CMP_PEAK_TOPS}}
+
+
 def bench_served(ctx, args):
     """Continuous batching of Poisson requests (mean 2,000 req/s) from 16
     EBIC runs over 4 resident matrices; then a closed-loop saturation run and
@@ -442,11 +491,12 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times), to scale "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
-    ap.add_argument("--extras", type=str, default="batch,serve,ea,paper",
+    ap.add_argument("--extras", type=str, default="batch,serve,ea,paper,shard",
                     help="comma list of extra measurements: 'batch' (64 populations in one "
                          "batched launch vs 64 plain launches), 'serve' (Poisson requests from "
                          "16 runs over 4 resident matrices), 'ea' (the stand-in evolutionary "
-                         "loop around the evaluation), 'paper' (436,444 x 310); '' for none")
+                         "loop around the evaluation), 'paper' (436,444 x 310), 'shard' (one of 8 "
+                         "row slices of the matrix); '' for none")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     args = ap.parse_args()
@@ -661,6 +711,8 @@ def main():
         result["evolutionary_loop"] = bench_ea(ctx, args, w)
     if "paper" in extras:
         result["paper_shape"] = bench_paper_shape(ctx, args)
+    if "shard" in extras:
+        result["row_shard_of_8"] = bench_shard(ctx, args, w, offs, cols)
     ctx.close()
 
     if not args.no_cpu_baseline:
