@@ -112,7 +112,11 @@ const char *ebic_last_error(void);
  * columns also keeps its rank codes (per cell, the number of smaller cells
  * of its row, as FP16; half the bytes of the values, and of the fill copy
  * if kept), which stage twice the rows in LDS and compare exactly as the
- * values do. Returns after the copy has completed on `hip_stream`.
+ * values do. A matrix of at most 128 columns also keeps byte rank codes of
+ * its fill-substituted values (one byte per cell, rows padded to a multiple
+ * of 256), which let one 32-bit lane word hold four rows; exclude mode uses
+ * them only if the matrix has no missing cell. Returns after the copy has
+ * completed on `hip_stream`.
  */
 ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, int32_t cols,
                                int64_t ld_src, uint32_t flags, float missing_sentinel,
@@ -195,7 +199,11 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
  *   individuals_per_group: individuals that share one block's staged tiles
  *   staging:               0 = column tiles staged in LDS, 1 = direct reads,
  *                          2 = the rank codes staged in LDS (2 or 4 sub-tiles;
- *                              include mode needs EBIC_KEEP_FILL_COPY)
+ *                              include mode needs EBIC_KEEP_FILL_COPY),
+ *                          3 = the byte rank codes staged in LDS (4 sub-tiles;
+ *                              exclude mode needs a matrix without missing
+ *                              cells); without codes for the request's mode
+ *                              the launch takes another staging
  *   blocks:                grid size per group, 0 = from occupancy
  * Shapes that do not fit the device are reduced at launch (fewer tiles per
  * wave, then direct reads). Results never depend on the shape.
@@ -208,7 +216,8 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
  * or -1 if unknown) on `matrix` would use now: the forced shape if one is
  * set, else the tuned one for its shape class, else the default, reduced to
  * what the device fits. Any output may be NULL. Staging: 0 = LDS, 1 = direct,
- * 2 = rank codes in LDS.
+ * 2 = rank codes in LDS, 3 = byte rank codes in LDS (the staging planned
+ * for exclude mode).
  */
 ebic_status ebic_plan_shape(ebic_ctx *ctx, int32_t matrix, int32_t n_ind, int64_t nnz,
                             int32_t *tiles_per_wave, int32_t *waves_per_block,

@@ -48,6 +48,7 @@ constexpr int32_t kInvalid = -1;
 __host__ __device__ inline size_t tile_bytes_of(int32_t L, int32_t cols, int32_t staging)
 {
     if (staging == STAGE_DIRECT) return 0;
+    if (staging == STAGE_BYTES) return (size_t)cols * 4 * kWave;  // four sub-tiles, one byte per row
     return (size_t)L * kWave * cols * (staging == STAGE_CODES ? sizeof(uint16_t) : sizeof(float));
 }
 
@@ -673,6 +674,275 @@ __device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ ti
     }
 }
 
+// ---------------------------------------------------------------------------
+// Byte rank codes: four sub-tiles in one 32-bit word per lane.
+//
+// Byte b of lane l's word is the code (0..127) of row 64*b + l of the staged
+// 256-row chunk, and codes order exactly as the values do. For codes x and
+// y below 128, the 32-bit difference (x | 0x80808080) - y never borrows
+// across bytes (every byte of it lies in [1, 255]), and bit 7 of a byte is
+// set exactly when that byte's x >= y: one subtraction compares four rows.
+// A row that falls on the first pair has its codes mirrored (t ^ 0x7F
+// reverses their order), so every row again follows one >= chain, of
+// oriented codes x_j = t_j ^ fm. With fH = fm | 0x80808080, nf = ~fm and
+// nx = -x_{j-1}, one column is
+//   D = (t_j ^ fH) + nx      = (x_j | 0x80808080) - x_{j-1}
+//   nx = (t_j ^ nf) + 1      = -x_j
+//   alive &= D
+// two v_xad_u32 and one AND for 256 rows; `alive` keeps bit 7 of the bytes
+// of the rows still on their chain (it starts from the in-range rows).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kByteHi = 0x80808080u;
+
+#define BY_LOAD(t, w)                                                          \
+    "v_lshl_add_u32 %[ad], %[" w "], 8, %[base]\n\t"                           \
+    "ds_read_b32 %[" t "], %[ad]\n\t"
+#define BY_STEP(t)                                                             \
+    "v_xad_u32 %[D], %[" t "], %[fH], %[nx]\n\t"                               \
+    "v_xad_u32 %[nx], %[" t "], %[nf], 1\n\t"                                  \
+    "v_and_b32_e32 %[alive], %[alive], %[D]\n\t"
+#define BY_EXIT(u)                                                             \
+    "v_cmp_ne_u32_e64 %[tmp], 0, %[alive]\n\t"                                 \
+    "s_cmp_lg_u64 %[tmp], 0\n\t"                                               \
+    "s_cbranch_scc0 2f\n\t"                                                    \
+    "s_cmp_le_i32 %[last], " u "\n\t"                                          \
+    "s_cbranch_scc1 2f\n\t"
+// Columns 2..7: t2 and t3 hold (or are loading) columns 2 and 3; each load
+// is issued two columns ahead. The chain ends after column 3 or 5 when no
+// row is left or the individual has no more columns (window columns past
+// the last one repeat it, which changes nothing).
+#define BY_WINDOW                                                              \
+    BY_LOAD("t0", "w4") "s_waitcnt lgkmcnt(2)\n\t" BY_STEP("t2")               \
+    BY_LOAD("t1", "w5") "s_waitcnt lgkmcnt(2)\n\t" BY_STEP("t3") BY_EXIT("3")  \
+    BY_LOAD("t2", "w6") "s_waitcnt lgkmcnt(2)\n\t" BY_STEP("t0")               \
+    BY_LOAD("t3", "w7") "s_waitcnt lgkmcnt(2)\n\t" BY_STEP("t1") BY_EXIT("5")  \
+    "s_waitcnt lgkmcnt(1)\n\t" BY_STEP("t2")                                   \
+    "s_waitcnt lgkmcnt(0)\n\t" BY_STEP("t3")
+#define BY_SCRATCH                                                             \
+    [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3), [ad] "=&v"(ad), \
+        [D] "=&v"(D), [tmp] "=&s"(tmp)
+#define BY_COLS                                                                \
+    [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), \
+        [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last)
+
+// First pair and window, both chains. Outputs: alive, fall (bit 7 of the
+// in-range rows with t1 < t0), tie (of those with t1 == t0), the
+// orientation words fH and nf, and tany (a wave-wide "some row is tied").
+// The sequence starts with lgkmcnt(0) (no scalar load in flight, so LDS
+// loads complete in issue order) and ends with it.
+__device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
+                                       uint32_t &alive, uint32_t &fall, uint32_t &tie, uint64_t &tany)
+{
+    uint32_t t0, t1, t2, t3, ad, D, E, fm, fH, nf, nx;
+    uint64_t tmp;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        BY_LOAD("t0", "w0") BY_LOAD("t1", "w1") BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
+        "s_waitcnt lgkmcnt(2)\n\t"
+        "v_or_b32_e32 %[D], 0x80808080, %[t1]\n\t"
+        "v_sub_u32_e32 %[D], %[D], %[t0]\n\t"       // bit 7: t1 >= t0
+        "v_or_b32_e32 %[E], 0x80808080, %[t0]\n\t"
+        "v_sub_u32_e32 %[E], %[E], %[t1]\n\t"       // bit 7: t0 >= t1
+        "v_and_b32_e32 %[tie], %[D], %[E]\n\t"
+        "v_and_b32_e32 %[tie], %[tie], %[hv]\n\t"
+        "v_bfi_b32 %[fall], %[D], 0, %[E]\n\t"      // E & ~D
+        "v_and_b32_e32 %[fall], %[fall], %[hv]\n\t"
+        "v_lshrrev_b32_e32 %[fm], 7, %[fall]\n\t"
+        "v_sub_u32_e32 %[fm], %[fall], %[fm]\n\t"   // 0x7F in each falling byte
+        "v_or_b32_e32 %[fH], 0x80808080, %[fm]\n\t"
+        "v_not_b32_e32 %[nf], %[fm]\n\t"
+        "v_xad_u32 %[nx], %[t1], %[nf], 1\n\t"
+        "v_mov_b32_e32 %[alive], %[hv]\n\t"
+        "v_cmp_ne_u32_e64 %[tany], 0, %[tie]\n\t"
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        BY_WINDOW
+        "2:\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : BY_SCRATCH, [E] "=&v"(E), [fm] "=&v"(fm), [fH] "=&v"(fH), [nf] "=&v"(nf), [nx] "=&v"(nx),
+          [alive] "=&v"(alive), [fall] "=&v"(fall), [tie] "=&v"(tie), [tany] "=&s"(tany)
+        : BY_COLS, [hv] "v"(hv)
+        : "scc", "memory");
+}
+
+// First pair and window of the >= chain alone.
+__device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
+                                       uint32_t &alive)
+{
+    uint32_t t0, t1, t2, t3, ad, D, nx;
+    uint64_t tmp;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        BY_LOAD("t0", "w0") BY_LOAD("t1", "w1") BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
+        "s_waitcnt lgkmcnt(2)\n\t"
+        "v_or_b32_e32 %[D], 0x80808080, %[t1]\n\t"
+        "v_sub_u32_e32 %[D], %[D], %[t0]\n\t"
+        "v_and_b32_e32 %[alive], %[D], %[hv]\n\t"
+        "v_sub_u32_e32 %[nx], 0, %[t1]\n\t"
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        BY_WINDOW
+        "2:\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : BY_SCRATCH, [nx] "=&v"(nx), [alive] "=&v"(alive)
+        : BY_COLS, [hv] "v"(hv), [fH] "s"(kByteHi), [nf] "i"(-1)
+        : "scc", "memory");
+}
+
+// The window of the <= chain for the rows tied on the first pair (alive =
+// their bits on entry; last >= 2): every code mirrored, fm = 0x7F7F7F7F.
+__device__ __forceinline__ void by_tie(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t nx,
+                                       uint32_t &alive)
+{
+    uint32_t t0, t1, t2, t3, ad, D;
+    uint64_t tmp;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
+        BY_WINDOW
+        "2:\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : BY_SCRATCH, [nx] "+v"(nx), [alive] "+v"(alive)
+        : BY_COLS, [fH] "i"(-1), [nf] "s"(kByteHi)
+        : "scc", "memory");
+}
+
+#undef BY_LOAD
+#undef BY_STEP
+#undef BY_EXIT
+#undef BY_WINDOW
+#undef BY_SCRATCH
+#undef BY_COLS
+
+// Wave-wide masks of the four sub-tiles: bit l of m[b] is bit 7 of byte b
+// of lane l's word (one SDWA compare per byte). The trailing wait states
+// let any following VALU read the masks.
+__device__ __forceinline__ void byte_masks(uint32_t x, uint64_t (&m)[4])
+{
+    asm volatile(
+        "v_cmp_ne_u32_sdwa %[m0], %[x], 0 src0_sel:BYTE_0 src1_sel:DWORD\n\t"
+        "v_cmp_ne_u32_sdwa %[m1], %[x], 0 src0_sel:BYTE_1 src1_sel:DWORD\n\t"
+        "v_cmp_ne_u32_sdwa %[m2], %[x], 0 src0_sel:BYTE_2 src1_sel:DWORD\n\t"
+        "v_cmp_ne_u32_sdwa %[m3], %[x], 0 src0_sel:BYTE_3 src1_sel:DWORD\n\t"
+        "s_nop 1"
+        : [m0] "=s"(m[0]), [m1] "=s"(m[1]), [m2] "=s"(m[2]), [m3] "=s"(m[3])
+        : [x] "v"(x));
+}
+
+// Plain-code twin of the window (the measurement variant): the same exit
+// points; counts one step per 64-row sub-tile and column.
+template <bool COUNT>
+__device__ __forceinline__ void by_window_ref(const unsigned char *__restrict__ base, const int32_t (&w)[kWin],
+                                              int32_t last, uint32_t fH, uint32_t nf, uint32_t &nx,
+                                              uint32_t &alive, uint64_t &steps)
+{
+#pragma unroll
+    for (int u = 2; u < kWin; ++u) {
+        const uint32_t t = *reinterpret_cast<const uint32_t *>(base + w[u] * 256);
+        alive &= (t ^ fH) + nx;
+        nx = (t ^ nf) + 1u;
+        if (COUNT) steps += 4;
+        if ((u == 3 || u == 5) && (__ballot(alive != 0) == 0 || last <= u)) return;
+    }
+}
+
+// Columns kWin..last (long individuals), while any row is left.
+template <bool COUNT>
+__device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, const int32_t *__restrict__ c,
+                                        int32_t last, uint32_t fH, uint32_t nf, uint32_t nx, uint32_t &alive,
+                                        uint64_t &steps)
+{
+    for (int32_t u = kWin; u <= last; ++u) {
+        if (__ballot(alive != 0) == 0) return;
+        const uint32_t t = *reinterpret_cast<const uint32_t *>(base + c[u] * 256);
+        alive &= (t ^ fH) + nx;
+        nx = (t ^ nf) + 1u;
+        if (COUNT) steps += 4;
+    }
+}
+
+// One individual on a chunk of byte rank codes (four 64-row sub-tiles).
+// `hv` holds bit 7 of the bytes of the rows inside the item and the matrix.
+// The byte codes have no missing value (exclude mode uses them only on a
+// matrix without missing cells; include mode's codes encode the fill).
+template <bool NEG, bool COUNT>
+__device__ __forceinline__ void eval_bytes(const unsigned char *__restrict__ tile, int32_t last,
+                                           const int32_t *__restrict__ c, const int4 &w03, const int4 &w47,
+                                           int lane, uint32_t hv, uint64_t (&M)[4], uint64_t (&G)[4],
+                                           uint64_t &steps)
+{
+    const unsigned char *base = tile + 4 * lane;
+    const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
+    auto rd = [&](int32_t col) { return *reinterpret_cast<const uint32_t *>(base + col * 256); };
+    if (last == 0) {  // one column: every row in range counts
+        byte_masks(hv, M);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) G[s] = 0;
+        if (COUNT) steps += 4;
+        return;
+    }
+    uint32_t alive, fall = 0, tie = 0, fH = kByteHi, nf = ~0u, nx;
+    uint64_t tany = 0;
+    if constexpr (COUNT) {
+        const uint32_t t0 = rd(w[0]), t1 = rd(w[1]);
+        const uint32_t D = (t1 | kByteHi) - t0, E = (t0 | kByteHi) - t1;
+        if constexpr (NEG) {
+            tie = D & E & hv;
+            fall = E & ~D & hv;
+            const uint32_t fm = fall - (fall >> 7);
+            fH = fm | kByteHi;
+            nf = ~fm;
+            alive = hv;
+            tany = __ballot(tie != 0);
+        } else {
+            alive = D & hv;
+        }
+        nx = (t1 ^ nf) + 1u;
+        steps += 4;
+        if (last >= 2) by_window_ref<COUNT>(base, w, last, fH, nf, nx, alive, steps);
+    } else {
+        const uint32_t b = lds_addr(base);
+        if constexpr (NEG) by_neg(b, w, last, hv, alive, fall, tie, tany);
+        else by_pos(b, w, last, hv, alive);
+    }
+    if (last >= kWin) {
+        if constexpr (NEG && !COUNT) {  // the orientation words, from the falling rows
+            const uint32_t fm = fall - (fall >> 7);
+            fH = fm | kByteHi;
+            nf = ~fm;
+        }
+        // The tail starts from -x_7, the oriented code of window column 7
+        // (with a row left, the window ran through column 7).
+        nx = (rd(w[kWin - 1]) ^ nf) + 1u;
+        by_tail<COUNT>(base, c, last, fH, nf, nx, alive, steps);
+    }
+    uint32_t mw = alive, gw = alive & fall;
+    if constexpr (NEG) {
+        if (tany && last >= 2) {
+            // Rows tied on the first pair also try the <= chain.
+            uint32_t a2 = tie, nx2 = (rd(w[1]) ^ kByteHi) + 1u;
+            if constexpr (COUNT) {
+                steps += 4;
+                by_window_ref<COUNT>(base, w, last, ~0u, kByteHi, nx2, a2, steps);
+            } else {
+                by_tie(lds_addr(base), w, last, nx2, a2);
+            }
+            if (last >= kWin) {
+                nx2 = (rd(w[kWin - 1]) ^ kByteHi) + 1u;
+                by_tail<COUNT>(base, c, last, ~0u, kByteHi, nx2, a2, steps);
+            }
+            mw |= a2;
+            gw |= a2 & ~alive;
+        }
+    }
+    byte_masks(mw, M);
+    if constexpr (NEG) byte_masks(gw, G);
+    else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) G[s] = 0;
+    }
+}
+
 // One individual read straight from the column-major matrix (matrices too
 // wide to stage). `xr` points at row (row0 + lane) of column 0; `sub`
 // holds the element offsets of the L sub-tiles (clamped by the caller so
@@ -803,6 +1073,23 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             }
             __syncthreads();
         }
+        uint32_t hvalid = 0;  // byte codes: bit 7 of the bytes of the rows in range
+        if constexpr (STAGE == STAGE_BYTES) {
+            static_assert(L == 4, "byte codes hold four sub-tiles per lane word");
+            // The 256 bytes of every column for rows [row0, row0 + 256), in
+            // their interleaved order; rows outside the item or the matrix
+            // are left out of `hvalid` instead.
+            const int total = d.cols * 16;
+            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+                const int c = idx >> 4, q = idx & 15;
+                reinterpret_cast<uint4 *>(tile)[idx] =
+                    *reinterpret_cast<const uint4 *>(d.B + (int64_t)c * d.ldb + row0 + 16 * q);
+            }
+#pragma unroll
+            for (int s = 0; s < L; ++s)
+                if (s < nl && row0 + s * kWave + lane < d.rows) hvalid |= 0x80u << (8 * s);
+            __syncthreads();
+        }
         if constexpr (STAGE == STAGE_LDS) {
             // Rows [row0, row0 + nl*64) of every column, 4 rows per thread.
             const int q_per_col = nl * (kWave / 4);
@@ -849,7 +1136,10 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                 for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
             } else {
                 const int32_t *c = d.colidx + hv[0].y;
-                if constexpr (STAGE == STAGE_CODES) {
+                if constexpr (STAGE == STAGE_BYTES) {
+                    eval_bytes<NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1, c, hv[1],
+                                           hv[2], lane, hvalid, M, G, steps);
+                } else if constexpr (STAGE == STAGE_CODES) {
                     static_assert(L >= 2, "rank codes are staged for 2 or 4 sub-tiles");
                     eval_lds_il<L, NEG, COUNT, uint16_t>(reinterpret_cast<const unsigned char *>(tile), k - 1,
                                                          c, hv[1], hv[2], lane, M, G, steps);
@@ -970,6 +1260,13 @@ k_eval_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs, const Item *__
         const Item it = items[id];
         const ReqDesc d = descs[it.req];
         const bool neg = (d.flags & kFlagNeg) != 0;
+        if constexpr (L == 4) {
+            if (d.flags & kFlagBytes) {
+                if (neg) run_item<L, true, STAGE_BYTES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                else run_item<L, false, STAGE_BYTES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                continue;
+            }
+        }
         if constexpr (L >= 2) {
             if (d.flags & kFlagCodes) {
                 if (neg) run_item<L, true, STAGE_CODES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
@@ -1022,6 +1319,10 @@ const void *eval_pick_codes(int L)
 template <bool COUNT>
 const void *eval_pick(int L, bool neg, int staging)
 {
+    if (staging == STAGE_BYTES) {
+        if (L != 4) return nullptr;  // byte codes hold four sub-tiles per lane word
+        return neg ? eval_ptr<4, true, STAGE_BYTES, COUNT>() : eval_ptr<4, false, STAGE_BYTES, COUNT>();
+    }
     if (staging == STAGE_CODES) return neg ? eval_pick_codes<true, COUNT>(L) : eval_pick_codes<false, COUNT>(L);
     if (staging == STAGE_LDS)
         return neg ? eval_pick_L<true, STAGE_LDS, COUNT>(L) : eval_pick_L<false, STAGE_LDS, COUNT>(L);

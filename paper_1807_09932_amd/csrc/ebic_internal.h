@@ -16,6 +16,7 @@ enum Staging : int32_t {
     STAGE_LDS = 0,     // rows x all columns staged into LDS, shared by the block
     STAGE_DIRECT = 1,  // read straight from the column-major matrix (L1/L2)
     STAGE_CODES = 2,   // the matrix's 16-bit rank codes staged into LDS (half the bytes)
+    STAGE_BYTES = 3,   // 8-bit rank codes, four rows per 32-bit lane word (4 sub-tiles only)
 };
 
 // Rank codes are kept for matrices of at most this many columns: a cell's
@@ -26,6 +27,16 @@ enum Staging : int32_t {
 constexpr int32_t kMaxCodeCols = 384;
 constexpr uint16_t kCodeNaN = 0x7E00;
 
+// Byte rank codes, for matrices of at most 128 columns: the same count of
+// smaller cells, of the fill-substituted values (so there is no missing
+// code), as one byte. Within each group of 256 rows the bytes are ordered
+// so that the 32-bit word of lane l holds rows l, 64 + l, 128 + l and
+// 192 + l (bytes 0..3): one word per lane covers four 64-row sub-tiles, and
+// byte b of all lanes is sub-tile b. A column occupies ldb bytes, ldb =
+// rows rounded up to a multiple of 256; padding rows hold 0. Exclude mode
+// may use them only when the matrix has no missing cell.
+constexpr int32_t kMaxByteCols = 128;
+
 // Request flags as the kernels see them (the low two bits are the ABI's
 // EBIC_NAN_INCLUDE and EBIC_NEG_TRENDS).
 constexpr uint32_t kFlagInclude = 1u;
@@ -33,10 +44,11 @@ constexpr uint32_t kFlagNeg = 2u;
 constexpr uint32_t kFlagDirect = 1u << 8;  // this request reads the matrix directly
 constexpr uint32_t kFlagSubst = 1u << 9;   // direct reads replace NaN by the fill value
 constexpr uint32_t kFlagCodes = 1u << 10;  // this request stages the rank codes
+constexpr uint32_t kFlagBytes = 1u << 11;  // this request stages the byte rank codes
 
 // One launch shape of the evaluation kernels.
 struct LaunchCfg {
-    int32_t L = 0;        // 64-row sub-tiles evaluated together per wave (1, 2, 4; codes: 2, 4)
+    int32_t L = 0;        // 64-row sub-tiles evaluated together per wave (1, 2, 4; codes: 2, 4; bytes: 4)
     int32_t W = 0;        // waves per block (1..16)
     int32_t P = 0;        // individuals per group (max individuals sharing a block)
     int32_t staging = STAGE_LDS;
@@ -49,6 +61,9 @@ struct DevMatrix {
     const float *Xfill = nullptr;  // fill-substituted copy, or null
     const uint16_t *C = nullptr;   // rank codes of X (same layout), or null
     const uint16_t *Cfill = nullptr;  // rank codes of Xfill, or null
+    const uint8_t *B = nullptr;    // byte rank codes of the fill-substituted values, or null
+    bool b_exclude = false;        // B also serves exclude mode (no missing cell)
+    int64_t ldb = 0;               // bytes per column of B (multiple of 256)
     int64_t ld = 0;                // multiple of 64
     int64_t rows = 0;
     int32_t cols = 0;
@@ -59,6 +74,8 @@ struct DevMatrix {
 struct ReqDesc {
     const float *X;            // the matrix to read (the fill copy when it serves include mode)
     const uint16_t *C;         // the rank codes to stage (kFlagCodes), or null
+    const uint8_t *B;          // the byte rank codes to stage (kFlagBytes), or null
+    int64_t ldb;               // bytes per column of B
     int64_t ld;
     int64_t rows;
     int32_t cols;
@@ -146,6 +163,13 @@ hipError_t launch_layout(const float *src, int64_t ld_src, bool src_col_major, i
 // written column-major with the same leading dimension; padding rows get 0.
 hipError_t launch_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, uint16_t *C,
                         hipStream_t s);
+
+// Byte rank codes of rows [0, rows) of a column-major matrix (cols <=
+// kMaxByteCols), with missing cells replaced by `fill`, into B (ldb bytes
+// per column, the interleaved order above; padding rows get 0). *has_nan
+// (device int, zeroed by the caller) is set to 1 if any cell is missing.
+hipError_t launch_byte_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
+                             uint8_t *B, int64_t ldb, int32_t *has_nan, hipStream_t s);
 
 // Zero rows [rows, ld) of every column of a column-major matrix.
 hipError_t launch_zero_pad(float *dst, int64_t rows, int64_t ld, int32_t cols, hipStream_t s);

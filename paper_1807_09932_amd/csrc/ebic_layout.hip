@@ -85,6 +85,41 @@ k_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols, uin
     }
 }
 
+// ---------------------------------------------------------------------------
+// Byte rank codes: as above, of the fill-substituted values, one byte per
+// cell, written in the interleaved order of each 256-row group (lane l's
+// word holds rows l, 64 + l, 128 + l, 192 + l). Rows past the matrix get 0.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_byte_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols, float fill,
+             uint8_t *__restrict__ B, int64_t ldb, int32_t *__restrict__ has_nan)
+{
+    extern __shared__ float t[];  // [cols][64]
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r = r0 + lane;
+    const bool live = r < rows;
+    bool missing = false;
+    for (int32_t c = wave; c < cols; c += 4) {
+        float v = live ? X[(int64_t)c * ld + r] : 0.f;
+        if (v != v) {
+            missing = true;
+            v = fill;
+        }
+        t[c * 64 + lane] = v;
+    }
+    if (missing) *has_nan = 1;
+    __syncthreads();
+    // Position of row r inside its 256-row group.
+    const int64_t pos = (r & ~(int64_t)255) + 4 * (r & 63) + ((r >> 6) & 3);
+    for (int32_t c = wave; c < cols; c += 4) {
+        const float v = t[c * 64 + lane];
+        int32_t n = 0;
+        for (int32_t j = 0; j < cols; ++j) n += t[j * 64 + lane] < v ? 1 : 0;
+        B[(int64_t)c * ldb + pos] = live ? (uint8_t)n : (uint8_t)0;
+    }
+}
+
 __global__ void k_zero_pad(float *__restrict__ dst, int64_t rows, int64_t ld, int32_t cols)
 {
     const int64_t pad = ld - rows;
@@ -105,6 +140,19 @@ hipError_t launch_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, 
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_codes, dim3((unsigned)(ld / 64)), dim3(256), lds, s, X, rows, ld, cols, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_byte_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
+                             uint8_t *B, int64_t ldb, int32_t *has_nan, hipStream_t s)
+{
+    if (cols > kMaxByteCols || ldb % 256 != 0 || ldb < rows) return hipErrorInvalidValue;
+    const size_t lds = (size_t)cols * 64 * sizeof(float);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_byte_codes),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_byte_codes, dim3((unsigned)(ldb / 64)), dim3(256), lds, s, X, rows, ld,
+                       cols, fill, B, ldb, has_nan);
     return hipGetLastError();
 }
 

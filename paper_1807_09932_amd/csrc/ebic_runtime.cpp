@@ -82,6 +82,14 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
     auto lds = [&](const LaunchCfg &c) { return tile_lds_bytes(c.L, m.dev.cols, c.staging) + count_lds_bytes(c.P); };
     auto fits = [&](const LaunchCfg &c) { return lds(c) <= lds_max; };
     const bool have_codes = ((flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
+    const bool have_bytes = m.dev.B && ((flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
+    // Byte codes hold four sub-tiles per lane word; without them for this
+    // mode, the 16-bit codes (or the FP32 tile) at the same shape.
+    if (cfg.staging == STAGE_BYTES) {
+        if (have_bytes) cfg.L = 4;
+        else cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
+    }
+    if (cfg.staging == STAGE_BYTES && !fits(cfg)) cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
     // Rank codes need codes for this mode and at least two sub-tiles.
     if (cfg.staging == STAGE_CODES && (!have_codes || cfg.L < 2)) cfg.staging = STAGE_LDS;
     // An FP32 tile that does not fit: the codes' tile (half the bytes) at the
@@ -124,6 +132,14 @@ ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int3
         d.C = include ? m.dev.Cfill : m.dev.C;
         if (!d.C) fail(EBIC_EINVAL, "no rank codes for this matrix and mode");
         d.flags |= kFlagCodes;
+    }
+    d.B = nullptr;
+    d.ldb = m.dev.ldb;
+    if (staging == STAGE_BYTES) {
+        if (!m.dev.B || !(include || m.dev.b_exclude))
+            fail(EBIC_EINVAL, "no byte rank codes for this matrix and mode");
+        d.B = m.dev.B;
+        d.flags |= kFlagBytes;
     }
     if (staging == STAGE_DIRECT) {
         d.flags |= kFlagDirect;
@@ -244,6 +260,7 @@ ebic_status ebic_destroy(ebic_ctx *ctx)
                 ctx_free(ctx, kv.second.Xfill);
                 ctx_free(ctx, kv.second.C);
                 ctx_free(ctx, kv.second.Cfill);
+                ctx_free(ctx, kv.second.B);
             }
             ctx->matrices.clear();
             destroy_batch_state(ctx);
@@ -361,13 +378,31 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
                     hip_check(launch_codes(m.Xfill, rows, m.dev.ld, cols, m.Cfill, s), "codes kernel");
                 }
             }
+            // Byte rank codes for matrices of at most 128 columns: four rows
+            // per 32-bit word. They encode the fill-substituted values, so
+            // exclude mode may use them only if no cell is missing.
+            int32_t has_nan = 1;
+            if (cols <= kMaxByteCols) {
+                m.dev.ldb = (rows + 255) / 256 * 256;
+                const size_t bbytes = (size_t)m.dev.ldb * cols;
+                m.B = static_cast<uint8_t *>(ctx_alloc(ctx, bbytes + 256));
+                m.bytes += bbytes + 256;
+                int32_t *flag = reinterpret_cast<int32_t *>(m.B + bbytes);
+                hip_check(hipMemsetAsync(flag, 0, sizeof(int32_t), s), "hipMemsetAsync");
+                hip_check(launch_byte_codes(m.X, rows, m.dev.ld, cols, missing_fill, m.B, m.dev.ldb, flag, s),
+                          "byte codes kernel");
+                hip_check(hipMemcpyAsync(&has_nan, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s),
+                          "hipMemcpyAsync");
+            }
             hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+            m.dev.b_exclude = m.B && has_nan == 0;
         } catch (...) {
             ctx_free(ctx, staging);
             ctx_free(ctx, m.X);
             ctx_free(ctx, m.Xfill);
             ctx_free(ctx, m.C);
             ctx_free(ctx, m.Cfill);
+            ctx_free(ctx, m.B);
             throw;
         }
         ctx_free(ctx, staging);
@@ -375,6 +410,7 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
         m.dev.Xfill = m.Xfill;
         m.dev.C = m.C;
         m.dev.Cfill = m.Cfill;
+        m.dev.B = m.B;
         const int32_t id = ctx->next_matrix++;
         ctx->matrices[id] = m;
         *out_matrix = id;
@@ -406,6 +442,7 @@ ebic_status ebic_release_matrix(ebic_ctx *ctx, int32_t matrix)
         ctx_free(ctx, m.Xfill);
         ctx_free(ctx, m.C);
         ctx_free(ctx, m.Cfill);
+        ctx_free(ctx, m.B);
         ctx->matrices.erase(matrix);
     });
 }

@@ -22,6 +22,7 @@ struct Matrix {
     float *Xfill = nullptr;
     uint16_t *C = nullptr;      // rank codes of X (cols <= kMaxCodeCols)
     uint16_t *Cfill = nullptr;  // rank codes of Xfill
+    uint8_t *B = nullptr;       // byte rank codes (cols <= kMaxByteCols)
     size_t bytes = 0;
     float sentinel = 0.f;
 };

@@ -217,7 +217,9 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
         }
         if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 4) ||
             waves_per_block < 1 || waves_per_block > 16 || individuals_per_group < 1 ||
-            !(staging == STAGE_LDS || staging == STAGE_DIRECT || staging == STAGE_CODES) || blocks < 0)
+            !(staging == STAGE_LDS || staging == STAGE_DIRECT || staging == STAGE_CODES ||
+              staging == STAGE_BYTES) ||
+            blocks < 0)
             fail(EBIC_EINVAL, "launch shape out of range");
         LaunchCfg c;
         c.L = tiles_per_wave;
@@ -261,13 +263,14 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                           "hipMemcpy");
                 int64_t rows;
                 int32_t cols;
-                bool have_codes;
+                bool have_codes, have_bytes;
                 {
                     std::lock_guard<std::mutex> lk(ctx->mu);
                     const Matrix &m = ctx_matrix(ctx, r.matrix);
                     rows = m.dev.rows;
                     cols = m.dev.cols;
                     have_codes = ((r.flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
+                    have_bytes = m.dev.B && ((r.flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
                 }
                 const TuneKey key = tune_key(rows, cols, r.n_ind, (int64_t)ends[1] - ends[0]);
                 if (!done.insert(key).second) continue;
@@ -276,7 +279,8 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                 for (int L : {1, 2, 4})
                     for (int W : {4, 8, 16})
                         for (int P : {200, 400, 800, 1600})
-                            for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT, (int)STAGE_CODES}) {
+                            for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT, (int)STAGE_CODES,
+                                            (int)STAGE_BYTES}) {
                                 LaunchCfg c;
                                 c.L = L;
                                 c.W = W;
@@ -286,6 +290,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                                     tile_lds_bytes(L, cols, stg) + count_lds_bytes(c.P) > ctx->lds_per_block)
                                     continue;
                                 if (stg == STAGE_CODES && (L < 2 || !have_codes)) continue;
+                                if (stg == STAGE_BYTES && (L != 4 || !have_bytes)) continue;
                                 set_override(c);
                                 const float ms = time_ms(
                                     [&] {
@@ -327,8 +332,9 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                     for (int L : {1, 2, 4})
                         for (int W : {4, 8, 16})
                             for (int P : {128, 256, 512, 1024})
-                                for (int stg : {(int)STAGE_LDS, (int)STAGE_CODES}) {
+                                for (int stg : {(int)STAGE_LDS, (int)STAGE_CODES, (int)STAGE_BYTES}) {
                                 if (stg == STAGE_CODES && L < 2) continue;
+                                if (stg == STAGE_BYTES && L != 4) continue;
                                 LaunchCfg c;
                                 c.L = L;
                                 c.W = W;

@@ -98,6 +98,37 @@ def test_batched_many_matrices_and_modes(ctx):
         ctx.release(m)
 
 
+def test_batch_byte_codes(ctx):
+    """The batched kernel with the byte rank codes forced: requests on a
+    matrix without missing cells (byte codes in both modes) and on one with
+    them (byte codes in include mode only), masks on and off."""
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(44)
+    Xa = rng.integers(0, 7, size=(4099, 64)).astype(np.float32)
+    Xb = rng.standard_normal((1030, 100)).astype(np.float32)
+    Xb[rng.random(Xb.shape) < 0.03] = np.float32(np.nan)
+    mats = [ctx.upload(Xa), ctx.upload(Xb, fill=0.25)]
+    Xs = [Xa, Xb]
+    jobs, want = [], []
+    for q in range(12):
+        m = q % 2
+        (offs, cols), = _pops(300 + q, Xs[m].shape[1], 1, (1, 220), lambda r: int(r.integers(1, 31)))
+        include, negative, masks = bool(q & 2), bool(q & 4), bool(q & 1)
+        jobs.append((mats[m], (offs, cols), include, negative, masks))
+        want.append(oracle_eval(Xs[m], offs, cols, include=include, negative=negative, masks=masks,
+                                fill=0.25))
+    try:
+        ctx.set_launch_shape(4, 8, 128, ebic.STAGE_BYTES, 0)
+        announce("batch byte codes")
+        got = _run_batch(ctx, jobs)
+        for q in range(len(jobs)):
+            assert_same(got[q], want[q], f"request {q}")
+    finally:
+        ctx.set_launch_shape()
+        for m in mats:
+            ctx.release(m)
+
+
 def test_batch_graph_replays_with_eager_work_between(ctx):
     """One captured graph replayed for batches of different contents, with
     plain evaluations and synchronisations between the replays; every

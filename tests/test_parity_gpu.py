@@ -97,6 +97,9 @@ SHAPES = [  # tiles_per_wave, waves_per_block, individuals_per_group, staging, b
     (2, 5, 200, 0, 7), (1, 8, 1000, 1, 0), (2, 4, 13, 1, 2), (4, 8, 300, 1, 0), (4, 1, 5, 1, 0),
     # staging 2: the FP16 rank codes
     (2, 8, 64, 2, 0), (4, 16, 1000, 2, 0), (4, 3, 33, 2, 1), (2, 5, 200, 2, 7), (1, 8, 100, 2, 0),
+    # staging 3: the byte rank codes (include mode here; exclude mode falls
+    # back, the matrix has missing cells)
+    (4, 8, 64, 3, 0), (4, 16, 1000, 3, 0), (4, 3, 33, 3, 1), (4, 5, 200, 3, 7), (2, 8, 100, 3, 0),
 ]
 
 
@@ -170,6 +173,39 @@ def test_rank_codes_special_values(ctx, ncols, L):
     finally:
         ctx.set_launch_shape()
         ctx.release(mat)
+
+
+@pytest.mark.parametrize("ncols", [2, 9, 64, 128])
+@pytest.mark.parametrize("rows", [1, 255, 257, 777, 3001])
+def test_byte_codes_special_values(ctx, ncols, rows):
+    """Byte rank-code staging (four rows per 32-bit lane word) on the special
+    values (+-inf, +-0, denormals, ties): both modes and both trend settings
+    on a matrix without missing cells, where both modes stage the byte
+    codes; with missing cells, include mode stages them and exclude mode
+    falls back to another staging. Individuals of up to 30 columns reach
+    past the 8-column window."""
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(1100 + 7 * ncols + rows)
+    X = _special(rng, (rows, ncols))
+    Xn = X.copy()
+    Xn[rng.random(X.shape) < 0.04] = np.float32(np.nan)
+    offs, cols = _random_pop(rng, ncols, 150, min(ncols, 30), dup=0.1, bad=0.02)
+    for name, A in (("no missing", X), ("missing", Xn)):
+        mat = ctx.upload(A, fill=-0.0)
+        try:
+            ctx.set_launch_shape(4, 8, 64, ebic.STAGE_BYTES, 0)
+            planned = ebic.ebic_plan_shape(ctx.handle, mat, offs.size - 1, int(offs[-1]))[3]
+            assert (planned == ebic.STAGE_BYTES) == (not np.isnan(A).any())
+            for include in (False, True):
+                for negative in (False, True):
+                    announce("byte codes", rows, ncols, name, include, negative)
+                    got = gpu_eval(ctx, mat, offs, cols, include=include, negative=negative)
+                    want = oracle_eval(A, offs, cols, include=include, negative=negative, fill=-0.0)
+                    assert_same(got, want, f"bytes {rows}x{ncols} {name} include={include} "
+                                           f"negative={negative}")
+        finally:
+            ctx.set_launch_shape()
+            ctx.release(mat)
 
 
 def test_invalid_and_degenerate_individuals(ctx):
@@ -274,14 +310,15 @@ def test_error_paths(ctx):
     assert e.value.status == ebic.EBIC_ENOENT
 
 
-@pytest.mark.parametrize("tiles_per_wave,staging", [(1, 0), (2, 0), (4, 0), (2, 2), (4, 2)])
+@pytest.mark.parametrize("tiles_per_wave,staging", [(1, 0), (2, 0), (4, 0), (2, 2), (4, 2), (4, 3)])
 def test_measurement_variant_agrees(ctx, tiles_per_wave, staging):
     """The step-counting kernel variant (profiling mode 2) computes the same
     outputs as the timed one, and counts a positive number of steps."""
     from paper_1807_09932_amd import ebic
     rng = np.random.default_rng(700 + tiles_per_wave)
     X = rng.integers(0, 5, size=(3000, 30)).astype(np.float32)
-    X[rng.random(X.shape) < 0.02] = np.float32(np.nan)
+    if staging != ebic.STAGE_BYTES:  # (byte codes serve exclude mode without missing cells)
+        X[rng.random(X.shape) < 0.02] = np.float32(np.nan)
     offs, cols = _random_pop(rng, 30, 150, 20, dup=0.05, bad=0.02)
     mat = ctx.upload(X, keep_fill_copy=True)
     try:
