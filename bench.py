@@ -28,8 +28,28 @@ sys.path.insert(0, ROOT)
 METRIC = ("row-trend checks/sec (pop×rows×cols) at 436,444 rows; % HBM peak; "
           "p50/p99 eval latency")
 HBM_PEAK_GBS = 8000.0
-# v_cmp_*_f32 issue: 256 CUs x 64 lanes per clock x 2.4 GHz.
+# The VALU lane rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12
+# 32-bit lane operations per second.
+# FP32 / FP16 staging: one 64-lane compare instruction per sub-tile and
+# column, counted as 64 compare lane-ops: peak 39.3 T/s.
 CMP_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Byte rank codes: one 32-bit lane op covers four rows, and a column step
+# costs three ops (two v_xad_u32 and an AND): peak 4/3 x 39.3 = 52.4 T
+# row-checks/s.
+BYTE_PEAK_TOPS = CMP_PEAK_TOPS * 4 / 3
+STAGE_BYTES = 3
+
+
+def alu_roofline(steps, k_ms, staging):
+    """The ALU roofline of one launch: `steps` counted by the measurement
+    variant (compare instructions, or 64-row sub-tile column steps with byte
+    codes) x 64 rows over the kernel time, against the peak of that staging."""
+    ach = steps * 64 / (k_ms * 1e-3) / 1e12
+    if staging == STAGE_BYTES:
+        return {"bound": "alu", "achieved": ach, "peak": BYTE_PEAK_TOPS, "unit": "T row-checks/s",
+                "frac": ach / BYTE_PEAK_TOPS}
+    return {"bound": "alu", "achieved": ach, "peak": CMP_PEAK_TOPS, "unit": "T compare lane-ops/s",
+            "frac": ach / CMP_PEAK_TOPS}
 
 
 def log(*a):
@@ -169,7 +189,6 @@ def bench_batched(ctx, args):
     n_l, l_ms, _ = ebic.ebic_read_profile(ctx.handle)
     ebic.ebic_set_profiling(ctx.handle, 0)
     g_ms = l_ms / max(1, n_l)
-    b_achieved = b_steps * 64 / (g_ms * 1e-3) / 1e12
     ctx.release(mat)
     return {
         "workload": "64 populations (%d individuals, lengths 2 + min(38, Exp(mean 5)), "
@@ -181,8 +200,7 @@ def bench_batched(ctx, args):
         "equal_results": True,
         "graph_ms": g_ms,
         "executed_compares": b_steps,
-        "roofline": {"bound": "alu", "achieved": b_achieved, "peak": CMP_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": b_achieved / CMP_PEAK_TOPS},
+        "roofline": alu_roofline(b_steps, g_ms, None),
         "timing": "median of %d synchronised calls; batched = one ebic_eval_batch (descriptor "
                   "copy + graph replay), plain = 64 ebic_eval_population calls" % reps,
     }
@@ -269,14 +287,12 @@ def bench_paper_shape(ctx, args):
     ebic.ebic_set_profiling(ctx.handle, 0)
     k_ms = ms / max(1, n_l)
     checks = gen.nominal_checks(rows, offs)
-    ach = steps * 64 / (k_ms * 1e-3) / 1e12
     ctx.release(mat)
     return {"workload": "%d x %d FP32 Beta(0.5,0.5), 10 planted trends, %d individuals of "
                         "2-30 columns" % (rows, ncols, p.n),
             "launch_shape": f"L={L} W={W} P={P} staging={stg} blocks={blocks}",
             "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
-            "roofline": {"bound": "alu", "achieved": ach, "peak": CMP_PEAK_TOPS, "unit": "TOP/s",
-                         "frac": ach / CMP_PEAK_TOPS},
+            "roofline": alu_roofline(steps, k_ms, stg),
             "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9}
 
 
@@ -319,14 +335,12 @@ def bench_shard(ctx, args, w, offs, cols):
     ebic.ebic_set_profiling(ctx.handle, 0)
     k_ms = ms / max(1, n_l)
     checks = gen.nominal_checks(step, offs)
-    ach = steps * 64 / (k_ms * 1e-3) / 1e12
     ctx.release(mat)
     return {"workload": "rows 0-%d of the %d x %d methylation matrix (one of 8 row slices), "
                         "%d individuals" % (step, rows, ncols, p.n),
             "launch_shape": f"L={L} W={W} P={P} staging={stg} blocks={blocks}",
             "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
-            "roofline": {"bound": "alu", "achieved": ach, "peak": CMP_PEAK_TOPS, "unit": "TOP/s",
-                         "frac": ach / CMP_PEAK_TOPS}}
+            "roofline": alu_roofline(steps, k_ms, stg)}
 
 
 def bench_served(ctx, args):
@@ -546,12 +560,14 @@ def main():
         L, W, P = parts[:3]
         S = parts[3] if len(parts) > 3 else ebic.STAGE_LDS
         ctx.set_launch_shape(L, W, P, S, 0)
-        shape_note = f"forced L={L} W={W} P={P} staging={S}"
+        how = "forced"
     else:
         # The library's autotuner picks the launch shape for this shape class.
         ctx.autotune([ctx.request(mat, p, out, include=False, negative=True)])
-        L, W, P, stg, blocks = ebic.ebic_plan_shape(ctx.handle, mat, n, int(offs[-1]))
-        shape_note = f"autotuned: L={L} W={W} P={P} staging={stg} blocks={blocks}"
+        how = "autotuned"
+    # The shape the launches take (a forced one may be reduced to what fits).
+    L, W, P, stg, blocks = ebic.ebic_plan_shape(ctx.handle, mat, n, int(offs[-1]))
+    shape_note = f"{how}: L={L} W={W} P={P} staging={stg} blocks={blocks}"
     log(f"launch shape: {shape_note}")
 
     # Spot check against the oracle on a sample of individuals.
@@ -630,8 +646,7 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = checks / (wall / args.steps)
     k_ms = kernel_ms / max(1, launches)
-    # Each counted step is one 64-lane FP32 compare instruction.
-    achieved = executed_steps * 64 / (k_ms * 1e-3) / 1e12
+    roof = alu_roofline(executed_steps, k_ms, stg)
 
     # End-to-end latency of one generation's evaluation as the host EA sees
     # it: CSR to the device, evaluation, counts back to the host.
@@ -665,20 +680,21 @@ def main():
             "check": "one (individual, row, column of that individual) triple",
         },
         "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": CMP_PEAK_TOPS,
-            "unit": "TOP/s",
-            "frac": achieved / CMP_PEAK_TOPS,
+            **roof,
             "traffic": traffic_from_profile(1),
             "kernel": "k_eval",
             "launch_shape": shape_note,
             "kernel_ms": k_ms,
             "kernel_ms_cold_cache": cold_ms,
-            "ops": "FP32 compares executed per launch: %d wave-wide compare instructions x 64 "
-                   "rows (first pair: 3 per 64-row tile, then 1 per column step of each row's "
-                   "oriented chain; early exit per 64-row tile), counted by the measurement "
-                   "variant of the kernel" % executed_steps,
+            "ops": (("row checks executed per launch: %d steps x 64 rows (one step = one column "
+                     "of one 64-row sub-tile; the first pair counts one step; early exit per "
+                     "256-row chunk), counted by the measurement variant of the kernel; peak = "
+                     "39.3e12 32-bit VALU lane ops/s x 4 rows per lane op / 3 ops per column "
+                     "step" % executed_steps) if stg == STAGE_BYTES else
+                    ("FP32 compares executed per launch: %d wave-wide compare instructions x 64 "
+                     "rows (first pair: 3 per 64-row tile, then 1 per column step of each row's "
+                     "oriented chain; early exit per group of tiles), counted by the measurement "
+                     "variant of the kernel" % executed_steps)),
         },
         "hbm_view": {
             "effective_gbs": 4.0 * checks / (k_ms * 1e-3) / 1e9,

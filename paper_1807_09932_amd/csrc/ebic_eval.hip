@@ -688,88 +688,101 @@ __device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ ti
 // nx = -x_{j-1}, one column is
 //   D = (t_j ^ fH) + nx      = (x_j | 0x80808080) - x_{j-1}
 //   nx = (t_j ^ nf) + 1      = -x_j
-//   alive &= D
-// two v_xad_u32 and one AND for 256 rows; `alive` keeps bit 7 of the bytes
-// of the rows still on their chain (it starts from the in-range rows).
+// and every two columns alive &= D_j & D_{j+1} (one three-input AND):
+// five VALU operations per two columns of 256 rows. `alive` keeps bit 7 of
+// the bytes of the rows still on their chain (it starts from the in-range
+// rows). Rows tied on the first pair then run the <= chain on their own:
+// every code mirrored, fH = 0xFFFFFFFF, nf = 0x80808080.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kByteHi = 0x80808080u;
 
 #define BY_LOAD(t, w)                                                          \
     "v_lshl_add_u32 %[ad], %[" w "], 8, %[base]\n\t"                           \
     "ds_read_b32 %[" t "], %[ad]\n\t"
-#define BY_STEP(t)                                                             \
-    "v_xad_u32 %[D], %[" t "], %[fH], %[nx]\n\t"                               \
-    "v_xad_u32 %[nx], %[" t "], %[nf], 1\n\t"                                  \
-    "v_and_b32_e32 %[alive], %[alive], %[D]\n\t"
-#define BY_EXIT(u)                                                             \
-    "v_cmp_ne_u32_e64 %[tmp], 0, %[alive]\n\t"                                 \
+#define BY_PAIR(ta, tb, FH, NF, NX, AL)                                        \
+    "v_xad_u32 %[D], %[" ta "], " FH ", %[" NX "]\n\t"                         \
+    "v_xad_u32 %[" NX "], %[" ta "], " NF ", 1\n\t"                            \
+    "v_xad_u32 %[D2], %[" tb "], " FH ", %[" NX "]\n\t"                        \
+    "v_xad_u32 %[" NX "], %[" tb "], " NF ", 1\n\t"                            \
+    "v_bitop3_b32 %[" AL "], %[" AL "], %[D], %[D2] bitop3:0x80\n\t"
+// After column 3 only the length ends the chain (256 rows rarely all fail
+// within four columns); after column 5 also the rows left.
+#define BY_EXIT_LAST(u, L) "s_cmp_le_i32 %[last], " u "\n\t" "s_cbranch_scc1 " L "\n\t"
+#define BY_EXIT(u, AL, L)                                                      \
+    "v_cmp_ne_u32_e64 %[tmp], 0, %[" AL "]\n\t"                                \
     "s_cmp_lg_u64 %[tmp], 0\n\t"                                               \
-    "s_cbranch_scc0 2f\n\t"                                                    \
-    "s_cmp_le_i32 %[last], " u "\n\t"                                          \
-    "s_cbranch_scc1 2f\n\t"
-// Columns 2..7: t2 and t3 hold (or are loading) columns 2 and 3; each load
-// is issued two columns ahead. The chain ends after column 3 or 5 when no
-// row is left or the individual has no more columns (window columns past
-// the last one repeat it, which changes nothing).
-#define BY_WINDOW                                                              \
-    BY_LOAD("t0", "w4") "s_waitcnt lgkmcnt(2)\n\t" BY_STEP("t2")               \
-    BY_LOAD("t1", "w5") "s_waitcnt lgkmcnt(2)\n\t" BY_STEP("t3") BY_EXIT("3")  \
-    BY_LOAD("t2", "w6") "s_waitcnt lgkmcnt(2)\n\t" BY_STEP("t0")               \
-    BY_LOAD("t3", "w7") "s_waitcnt lgkmcnt(2)\n\t" BY_STEP("t1") BY_EXIT("5")  \
-    "s_waitcnt lgkmcnt(1)\n\t" BY_STEP("t2")                                   \
-    "s_waitcnt lgkmcnt(0)\n\t" BY_STEP("t3")
+    "s_cbranch_scc0 " L "\n\t" BY_EXIT_LAST(u, L)
+// Columns 2..7: t2 and t3 hold (or are loading) columns 2 and 3; loads run
+// two columns ahead. Window columns past the last one repeat it, which
+// changes nothing.
+#define BY_WINDOW(FH, NF, NX, AL, L)                                           \
+    BY_LOAD("t0", "w4") BY_LOAD("t1", "w5") "s_waitcnt lgkmcnt(2)\n\t"         \
+    BY_PAIR("t2", "t3", FH, NF, NX, AL) BY_EXIT_LAST("3", L)                   \
+    BY_LOAD("t2", "w6") BY_LOAD("t3", "w7") "s_waitcnt lgkmcnt(2)\n\t"         \
+    BY_PAIR("t0", "t1", FH, NF, NX, AL) BY_EXIT("5", AL, L)                    \
+    "s_waitcnt lgkmcnt(0)\n\t" BY_PAIR("t2", "t3", FH, NF, NX, AL)
 #define BY_SCRATCH                                                             \
     [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3), [ad] "=&v"(ad), \
-        [D] "=&v"(D), [tmp] "=&s"(tmp)
+        [D] "=&v"(D), [D2] "=&v"(D2), [tmp] "=&s"(tmp)
 #define BY_COLS                                                                \
     [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), \
         [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last)
 
-// First pair and window, both chains. Outputs: alive, fall (bit 7 of the
-// in-range rows with t1 < t0), tie (of those with t1 == t0), the
-// orientation words fH and nf, and tany (a wave-wide "some row is tied").
-// The sequence starts with lgkmcnt(0) (no scalar load in flight, so LDS
-// loads complete in issue order) and ends with it.
+// Both chains through column min(last, 7): alive (rows on their oriented
+// chain), fall (bit 7 of the in-range rows with t1 < t0) and tied (the
+// rows tied on the first pair that also follow the <= chain; 0 unless
+// last >= 2). The sequence starts with lgkmcnt(0) (no scalar load in
+// flight, so LDS loads complete in issue order) and ends with it.
 __device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
-                                       uint32_t &alive, uint32_t &fall, uint32_t &tie, uint64_t &tany)
+                                       uint32_t &alive, uint32_t &fall, uint32_t &tied)
 {
-    uint32_t t0, t1, t2, t3, ad, D, E, fm, fH, nf, nx;
-    uint64_t tmp;
+    uint32_t t0, t1, t2, t3, ad, D, D2, fm, fH, nf, nx;
+    uint64_t tmp, tany;
     asm volatile(
         "s_waitcnt lgkmcnt(0)\n\t"
         BY_LOAD("t0", "w0") BY_LOAD("t1", "w1") BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
         "s_waitcnt lgkmcnt(2)\n\t"
         "v_or_b32_e32 %[D], 0x80808080, %[t1]\n\t"
-        "v_sub_u32_e32 %[D], %[D], %[t0]\n\t"       // bit 7: t1 >= t0
-        "v_or_b32_e32 %[E], 0x80808080, %[t0]\n\t"
-        "v_sub_u32_e32 %[E], %[E], %[t1]\n\t"       // bit 7: t0 >= t1
-        "v_and_b32_e32 %[tie], %[D], %[E]\n\t"
-        "v_and_b32_e32 %[tie], %[tie], %[hv]\n\t"
-        "v_bfi_b32 %[fall], %[D], 0, %[E]\n\t"      // E & ~D
-        "v_and_b32_e32 %[fall], %[fall], %[hv]\n\t"
+        "v_sub_u32_e32 %[D], %[D], %[t0]\n\t"           // bit 7: t1 >= t0
+        "v_sub_u32_e32 %[D2], 0x1010100, %[D]\n\t"      // = (t0 | 0x80..) - t1, bit 7: t0 >= t1
+        "v_bitop3_b32 %[tied], %[D], %[D2], %[hv] bitop3:0x80\n\t"  // tied, in range
+        "v_bitop3_b32 %[fall], %[D], %[D2], %[hv] bitop3:0x08\n\t"  // ~D & D2 & hv: falling
         "v_lshrrev_b32_e32 %[fm], 7, %[fall]\n\t"
-        "v_sub_u32_e32 %[fm], %[fall], %[fm]\n\t"   // 0x7F in each falling byte
+        "v_sub_u32_e32 %[fm], %[fall], %[fm]\n\t"       // 0x7F in each falling byte
         "v_or_b32_e32 %[fH], 0x80808080, %[fm]\n\t"
         "v_not_b32_e32 %[nf], %[fm]\n\t"
         "v_xad_u32 %[nx], %[t1], %[nf], 1\n\t"
         "v_mov_b32_e32 %[alive], %[hv]\n\t"
-        "v_cmp_ne_u32_e64 %[tany], 0, %[tie]\n\t"
+        "v_cmp_ne_u32_e64 %[tany], 0, %[tied]\n\t"
         "s_cmp_lt_i32 %[last], 2\n\t"
-        "s_cbranch_scc1 2f\n\t"
-        BY_WINDOW
+        "s_cbranch_scc1 4f\n\t"
+        BY_WINDOW("%[fH]", "%[nf]", "nx", "alive", "2f")
         "2:\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : BY_SCRATCH, [E] "=&v"(E), [fm] "=&v"(fm), [fH] "=&v"(fH), [nf] "=&v"(nf), [nx] "=&v"(nx),
-          [alive] "=&v"(alive), [fall] "=&v"(fall), [tie] "=&v"(tie), [tany] "=&s"(tany)
-        : BY_COLS, [hv] "v"(hv)
+        "s_waitcnt lgkmcnt(0)\n\t"
+        // The rows tied on the first pair: the <= chain from column 1.
+        "s_cmp_lg_u64 %[tany], 0\n\t"
+        "s_cbranch_scc0 4f\n\t"
+        BY_LOAD("t1", "w1") BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
+        "s_waitcnt lgkmcnt(2)\n\t"
+        "v_xad_u32 %[nx], %[t1], %[hi], 1\n\t"
+        BY_WINDOW("-1", "%[hi]", "nx", "tied", "3f")
+        "3:\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_branch 5f\n\t"
+        "4:\n\t"
+        "v_mov_b32_e32 %[tied], 0\n\t"
+        "5:"
+        : BY_SCRATCH, [fm] "=&v"(fm), [fH] "=&v"(fH), [nf] "=&v"(nf), [nx] "=&v"(nx),
+          [alive] "=&v"(alive), [fall] "=&v"(fall), [tied] "=&v"(tied), [tany] "=&s"(tany)
+        : BY_COLS, [hv] "v"(hv), [hi] "s"(kByteHi)
         : "scc", "memory");
 }
 
-// First pair and window of the >= chain alone.
+// The >= chain alone through column min(last, 7).
 __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
                                        uint32_t &alive)
 {
-    uint32_t t0, t1, t2, t3, ad, D, nx;
+    uint32_t t0, t1, t2, t3, ad, D, D2, nx;
     uint64_t tmp;
     asm volatile(
         "s_waitcnt lgkmcnt(0)\n\t"
@@ -781,34 +794,17 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
         "v_sub_u32_e32 %[nx], 0, %[t1]\n\t"
         "s_cmp_lt_i32 %[last], 2\n\t"
         "s_cbranch_scc1 2f\n\t"
-        BY_WINDOW
+        BY_WINDOW("%[hi]", "-1", "nx", "alive", "2f")
         "2:\n\t"
         "s_waitcnt lgkmcnt(0)"
         : BY_SCRATCH, [nx] "=&v"(nx), [alive] "=&v"(alive)
-        : BY_COLS, [hv] "v"(hv), [fH] "s"(kByteHi), [nf] "i"(-1)
-        : "scc", "memory");
-}
-
-// The window of the <= chain for the rows tied on the first pair (alive =
-// their bits on entry; last >= 2): every code mirrored, fm = 0x7F7F7F7F.
-__device__ __forceinline__ void by_tie(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t nx,
-                                       uint32_t &alive)
-{
-    uint32_t t0, t1, t2, t3, ad, D;
-    uint64_t tmp;
-    asm volatile(
-        "s_waitcnt lgkmcnt(0)\n\t"
-        BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
-        BY_WINDOW
-        "2:\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : BY_SCRATCH, [nx] "+v"(nx), [alive] "+v"(alive)
-        : BY_COLS, [fH] "i"(-1), [nf] "s"(kByteHi)
+        : BY_COLS, [hv] "v"(hv), [hi] "s"(kByteHi)
         : "scc", "memory");
 }
 
 #undef BY_LOAD
-#undef BY_STEP
+#undef BY_PAIR
+#undef BY_EXIT_LAST
 #undef BY_EXIT
 #undef BY_WINDOW
 #undef BY_SCRATCH
@@ -833,7 +829,7 @@ __device__ __forceinline__ void byte_masks(uint32_t x, uint64_t (&m)[4])
 // points; counts one step per 64-row sub-tile and column.
 template <bool COUNT>
 __device__ __forceinline__ void by_window_ref(const unsigned char *__restrict__ base, const int32_t (&w)[kWin],
-                                              int32_t last, uint32_t fH, uint32_t nf, uint32_t &nx,
+                                              int32_t last, uint32_t fH, uint32_t nf, uint32_t nx,
                                               uint32_t &alive, uint64_t &steps)
 {
 #pragma unroll
@@ -842,16 +838,19 @@ __device__ __forceinline__ void by_window_ref(const unsigned char *__restrict__ 
         alive &= (t ^ fH) + nx;
         nx = (t ^ nf) + 1u;
         if (COUNT) steps += 4;
-        if ((u == 3 || u == 5) && (__ballot(alive != 0) == 0 || last <= u)) return;
+        if (u == 3 && last <= 3) return;
+        if (u == 5 && (__ballot(alive != 0) == 0 || last <= 5)) return;
     }
 }
 
-// Columns kWin..last (long individuals), while any row is left.
+// Columns kWin..last (long individuals), while any row is left; nx is -x
+// of window column 7 (with a row left, the window ran through column 7).
 template <bool COUNT>
 __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, const int32_t *__restrict__ c,
-                                        int32_t last, uint32_t fH, uint32_t nf, uint32_t nx, uint32_t &alive,
-                                        uint64_t &steps)
+                                        const int32_t (&w)[kWin], int32_t last, uint32_t fH, uint32_t nf,
+                                        uint32_t &alive, uint64_t &steps)
 {
+    uint32_t nx = (*reinterpret_cast<const uint32_t *>(base + w[kWin - 1] * 256) ^ nf) + 1u;
     for (int32_t u = kWin; u <= last; ++u) {
         if (__ballot(alive != 0) == 0) return;
         const uint32_t t = *reinterpret_cast<const uint32_t *>(base + c[u] * 256);
@@ -865,8 +864,9 @@ __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, 
 // `hv` holds bit 7 of the bytes of the rows inside the item and the matrix.
 // The byte codes have no missing value (exclude mode uses them only on a
 // matrix without missing cells; include mode's codes encode the fill).
+// Returns false, and leaves M and G unset, when no row matches.
 template <bool NEG, bool COUNT>
-__device__ __forceinline__ void eval_bytes(const unsigned char *__restrict__ tile, int32_t last,
+__device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ tile, int32_t last,
                                            const int32_t *__restrict__ c, const int4 &w03, const int4 &w47,
                                            int lane, uint32_t hv, uint64_t (&M)[4], uint64_t (&G)[4],
                                            uint64_t &steps)
@@ -879,68 +879,53 @@ __device__ __forceinline__ void eval_bytes(const unsigned char *__restrict__ til
 #pragma unroll
         for (int s = 0; s < 4; ++s) G[s] = 0;
         if (COUNT) steps += 4;
-        return;
+        return true;
     }
-    uint32_t alive, fall = 0, tie = 0, fH = kByteHi, nf = ~0u, nx;
-    uint64_t tany = 0;
+    uint32_t alive, fall = 0, tied = 0;
     if constexpr (COUNT) {
         const uint32_t t0 = rd(w[0]), t1 = rd(w[1]);
         const uint32_t D = (t1 | kByteHi) - t0, E = (t0 | kByteHi) - t1;
+        uint32_t fH = kByteHi, nf = ~0u;
+        alive = D & hv;
         if constexpr (NEG) {
-            tie = D & E & hv;
+            tied = D & E & hv;
             fall = E & ~D & hv;
             const uint32_t fm = fall - (fall >> 7);
             fH = fm | kByteHi;
             nf = ~fm;
             alive = hv;
-            tany = __ballot(tie != 0);
-        } else {
-            alive = D & hv;
         }
-        nx = (t1 ^ nf) + 1u;
         steps += 4;
-        if (last >= 2) by_window_ref<COUNT>(base, w, last, fH, nf, nx, alive, steps);
+        if (last >= 2) by_window_ref<COUNT>(base, w, last, fH, nf, (t1 ^ nf) + 1u, alive, steps);
+        if (NEG && last >= 2 && __ballot(tied != 0) != 0) {
+            steps += 4;
+            by_window_ref<COUNT>(base, w, last, ~0u, kByteHi, (t1 ^ kByteHi) + 1u, tied, steps);
+        } else {
+            tied = 0;
+        }
     } else {
         const uint32_t b = lds_addr(base);
-        if constexpr (NEG) by_neg(b, w, last, hv, alive, fall, tie, tany);
+        if constexpr (NEG) by_neg(b, w, last, hv, alive, fall, tied);
         else by_pos(b, w, last, hv, alive);
     }
     if (last >= kWin) {
-        if constexpr (NEG && !COUNT) {  // the orientation words, from the falling rows
+        if constexpr (NEG) {
             const uint32_t fm = fall - (fall >> 7);
-            fH = fm | kByteHi;
-            nf = ~fm;
-        }
-        // The tail starts from -x_7, the oriented code of window column 7
-        // (with a row left, the window ran through column 7).
-        nx = (rd(w[kWin - 1]) ^ nf) + 1u;
-        by_tail<COUNT>(base, c, last, fH, nf, nx, alive, steps);
-    }
-    uint32_t mw = alive, gw = alive & fall;
-    if constexpr (NEG) {
-        if (tany && last >= 2) {
-            // Rows tied on the first pair also try the <= chain.
-            uint32_t a2 = tie, nx2 = (rd(w[1]) ^ kByteHi) + 1u;
-            if constexpr (COUNT) {
-                steps += 4;
-                by_window_ref<COUNT>(base, w, last, ~0u, kByteHi, nx2, a2, steps);
-            } else {
-                by_tie(lds_addr(base), w, last, nx2, a2);
-            }
-            if (last >= kWin) {
-                nx2 = (rd(w[kWin - 1]) ^ kByteHi) + 1u;
-                by_tail<COUNT>(base, c, last, ~0u, kByteHi, nx2, a2, steps);
-            }
-            mw |= a2;
-            gw |= a2 & ~alive;
+            by_tail<COUNT>(base, c, w, last, fm | kByteHi, ~fm, alive, steps);
+            by_tail<COUNT>(base, c, w, last, ~0u, kByteHi, tied, steps);
+        } else {
+            by_tail<COUNT>(base, c, w, last, kByteHi, ~0u, alive, steps);
         }
     }
+    const uint32_t mw = alive | tied;
+    if (__ballot(mw != 0) == 0) return false;
     byte_masks(mw, M);
-    if constexpr (NEG) byte_masks(gw, G);
+    if constexpr (NEG) byte_masks((alive & fall) | (tied & ~alive), G);
     else {
 #pragma unroll
         for (int s = 0; s < 4; ++s) G[s] = 0;
     }
+    return true;
 }
 
 // One individual read straight from the column-major matrix (matrices too
@@ -1136,9 +1121,14 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                 for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
             } else {
                 const int32_t *c = d.colidx + hv[0].y;
+                bool live = true;  // (byte codes: some row matches)
                 if constexpr (STAGE == STAGE_BYTES) {
-                    eval_bytes<NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1, c, hv[1],
-                                           hv[2], lane, hvalid, M, G, steps);
+                    live = eval_bytes<NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1, c,
+                                                  hv[1], hv[2], lane, hvalid, M, G, steps);
+                    if (!live) {
+#pragma unroll
+                        for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
+                    }
                 } else if constexpr (STAGE == STAGE_CODES) {
                     static_assert(L >= 2, "rank codes are staged for 2 or 4 sub-tiles");
                     eval_lds_il<L, NEG, COUNT, uint16_t>(reinterpret_cast<const unsigned char *>(tile), k - 1,
@@ -1161,10 +1151,12 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                                                (d.flags & kFlagSubst) != 0, valid, M, G, steps);
                 }
                 int32_t pm = 0, pg = 0;
+                if (live) {
 #pragma unroll
-                for (int s = 0; s < L; ++s) {
-                    pm += __popcll(M[s]);
-                    pg += __popcll(G[s]);
+                    for (int s = 0; s < L; ++s) {
+                        pm += __popcll(M[s]);
+                        pg += __popcll(G[s]);
+                    }
                 }
                 if (pm | pg) {
                     // Lane 0 adds both counts to the block's LDS accumulators;

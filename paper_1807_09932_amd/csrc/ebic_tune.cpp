@@ -41,9 +41,11 @@ static TuneKey batch_key(int64_t total_ind, int64_t mean_rows, int32_t max_cols)
     return TuneKey{1, log2_bucket(mean_rows), log2_bucket(max_cols), log2_bucket(total_ind), 0};
 }
 
-// Defaults measured on MI355X for the 436,444 x 64 workload: four 64-row
-// tiles per chunk while the tile fits twice in LDS, sixteen waves per block
-// (two blocks, 32 waves per CU), groups of 400 individuals.
+// Defaults measured on MI355X for the 436,444 x 64 workload: the byte rank
+// codes (four 64-row sub-tiles per lane word) up to 128 columns, sixteen
+// waves per block, groups of 400 individuals; wider matrices stage the
+// 16-bit rank codes. A request without codes for its mode falls back at
+// launch.
 static int32_t default_L(int32_t cols) { return cols <= 64 ? 4 : (cols <= 128 ? 2 : 1); }
 
 LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
@@ -54,11 +56,13 @@ LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
     c.P = std::max(1, std::min(n, 400));
     c.L = default_L(cols);
     c.staging = STAGE_LDS;
-    // Wider than 64 columns: the rank codes' tile keeps two sub-tiles (or
-    // four up to 128 columns) in LDS; without codes the launch falls back.
-    if (cols > 64 && cols <= kMaxCodeCols) {
+    if (cols <= kMaxByteCols) {
+        c.staging = STAGE_BYTES;
+        c.L = 4;
+    } else if (cols <= kMaxCodeCols) {
+        // The 16-bit rank codes' tile keeps two sub-tiles in LDS.
         c.staging = STAGE_CODES;
-        c.L = cols <= 128 ? 4 : 2;
+        c.L = 2;
     }
     c.blocks = 0;
     return c;
@@ -71,9 +75,12 @@ LaunchCfg default_batch_cfg(int32_t max_cols)
     c.P = 400;
     c.L = default_L(max_cols);
     c.staging = STAGE_LDS;
-    if (max_cols > 64 && max_cols <= kMaxCodeCols) {
+    if (max_cols <= kMaxByteCols) {
+        c.staging = STAGE_BYTES;
+        c.L = 4;
+    } else if (max_cols <= kMaxCodeCols) {
         c.staging = STAGE_CODES;
-        c.L = max_cols <= 128 ? 4 : 2;
+        c.L = 2;
     }
     c.blocks = 0;
     return c;
