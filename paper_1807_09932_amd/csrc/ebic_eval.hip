@@ -699,12 +699,12 @@ constexpr uint32_t kByteHi = 0x80808080u;
 #define BY_LOAD(t, w)                                                          \
     "v_lshl_add_u32 %[ad], %[" w "], 8, %[base]\n\t"                           \
     "ds_read_b32 %[" t "], %[ad]\n\t"
-#define BY_PAIR(ta, tb, FH, NF, NX, AL)                                        \
+#define BY_PAIR(ta, tb, FH, NF, NX, AL, ALIN)                                  \
     "v_xad_u32 %[D], %[" ta "], " FH ", %[" NX "]\n\t"                         \
     "v_xad_u32 %[" NX "], %[" ta "], " NF ", 1\n\t"                            \
     "v_xad_u32 %[D2], %[" tb "], " FH ", %[" NX "]\n\t"                        \
     "v_xad_u32 %[" NX "], %[" tb "], " NF ", 1\n\t"                            \
-    "v_bitop3_b32 %[" AL "], %[" AL "], %[D], %[D2] bitop3:0x80\n\t"
+    "v_bitop3_b32 %[" AL "], %[" ALIN "], %[D], %[D2] bitop3:0x80\n\t"
 // After column 3 only the length ends the chain (256 rows rarely all fail
 // within four columns); after column 5 also the rows left.
 #define BY_EXIT_LAST(u, L) "s_cmp_le_i32 %[last], " u "\n\t" "s_cbranch_scc1 " L "\n\t"
@@ -714,13 +714,13 @@ constexpr uint32_t kByteHi = 0x80808080u;
     "s_cbranch_scc0 " L "\n\t" BY_EXIT_LAST(u, L)
 // Columns 2..7: t2 and t3 hold (or are loading) columns 2 and 3; loads run
 // two columns ahead. Window columns past the last one repeat it, which
-// changes nothing.
-#define BY_WINDOW(FH, NF, NX, AL, L)                                           \
+// changes nothing. The first pair's AND reads the rows from ALIN.
+#define BY_WINDOW(FH, NF, NX, AL, ALIN, L)                                     \
     BY_LOAD("t0", "w4") BY_LOAD("t1", "w5") "s_waitcnt lgkmcnt(2)\n\t"         \
-    BY_PAIR("t2", "t3", FH, NF, NX, AL) BY_EXIT_LAST("3", L)                   \
+    BY_PAIR("t2", "t3", FH, NF, NX, AL, ALIN) BY_EXIT_LAST("3", L)             \
     BY_LOAD("t2", "w6") BY_LOAD("t3", "w7") "s_waitcnt lgkmcnt(2)\n\t"         \
-    BY_PAIR("t0", "t1", FH, NF, NX, AL) BY_EXIT("5", AL, L)                    \
-    "s_waitcnt lgkmcnt(0)\n\t" BY_PAIR("t2", "t3", FH, NF, NX, AL)
+    BY_PAIR("t0", "t1", FH, NF, NX, AL, AL) BY_EXIT("5", AL, L)                \
+    "s_waitcnt lgkmcnt(0)\n\t" BY_PAIR("t2", "t3", FH, NF, NX, AL, AL)
 #define BY_SCRATCH                                                             \
     [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3), [ad] "=&v"(ad), \
         [D] "=&v"(D), [D2] "=&v"(D2), [tmp] "=&s"(tmp)
@@ -732,7 +732,8 @@ constexpr uint32_t kByteHi = 0x80808080u;
 // chain), fall (bit 7 of the in-range rows with t1 < t0) and tied (the
 // rows tied on the first pair that also follow the <= chain; 0 unless
 // last >= 2). The sequence starts with lgkmcnt(0) (no scalar load in
-// flight, so LDS loads complete in issue order) and ends with it.
+// flight, so LDS operations complete in issue order and lgkmcnt(n) means
+// that all but the last n issued are done) and ends with it.
 __device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
                                        uint32_t &alive, uint32_t &fall, uint32_t &tied)
 {
@@ -752,11 +753,10 @@ __device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], 
         "v_or_b32_e32 %[fH], 0x80808080, %[fm]\n\t"
         "v_not_b32_e32 %[nf], %[fm]\n\t"
         "v_xad_u32 %[nx], %[t1], %[nf], 1\n\t"
-        "v_mov_b32_e32 %[alive], %[hv]\n\t"
         "v_cmp_ne_u32_e64 %[tany], 0, %[tied]\n\t"
         "s_cmp_lt_i32 %[last], 2\n\t"
-        "s_cbranch_scc1 4f\n\t"
-        BY_WINDOW("%[fH]", "%[nf]", "nx", "alive", "2f")
+        "s_cbranch_scc1 6f\n\t"
+        BY_WINDOW("%[fH]", "%[nf]", "nx", "alive", "hv", "2f")
         "2:\n\t"
         "s_waitcnt lgkmcnt(0)\n\t"
         // The rows tied on the first pair: the <= chain from column 1.
@@ -765,10 +765,12 @@ __device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], 
         BY_LOAD("t1", "w1") BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
         "s_waitcnt lgkmcnt(2)\n\t"
         "v_xad_u32 %[nx], %[t1], %[hi], 1\n\t"
-        BY_WINDOW("-1", "%[hi]", "nx", "tied", "3f")
+        BY_WINDOW("-1", "%[hi]", "nx", "tied", "tied", "3f")
         "3:\n\t"
         "s_waitcnt lgkmcnt(0)\n\t"
         "s_branch 5f\n\t"
+        "6:\n\t"  // two columns: every row in range is on its chain
+        "v_mov_b32_e32 %[alive], %[hv]\n\t"
         "4:\n\t"
         "v_mov_b32_e32 %[tied], 0\n\t"
         "5:"
@@ -778,7 +780,7 @@ __device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], 
         : "scc", "memory");
 }
 
-// The >= chain alone through column min(last, 7).
+// The >= chain alone through column min(last, 7) (waits as above).
 __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
                                        uint32_t &alive)
 {
@@ -794,7 +796,7 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
         "v_sub_u32_e32 %[nx], 0, %[t1]\n\t"
         "s_cmp_lt_i32 %[last], 2\n\t"
         "s_cbranch_scc1 2f\n\t"
-        BY_WINDOW("%[hi]", "-1", "nx", "alive", "2f")
+        BY_WINDOW("%[hi]", "-1", "nx", "alive", "alive", "2f")
         "2:\n\t"
         "s_waitcnt lgkmcnt(0)"
         : BY_SCRATCH, [nx] "=&v"(nx), [alive] "=&v"(alive)
@@ -867,7 +869,8 @@ __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, 
 // Returns false, and leaves M and G unset, when no row matches.
 template <bool NEG, bool COUNT>
 __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ tile, int32_t last,
-                                           const int32_t *__restrict__ c, const int4 &w03, const int4 &w47,
+                                           const int32_t *__restrict__ colidx,
+                                           const IndHead *__restrict__ hp, const int4 &w03, const int4 &w47,
                                            int lane, uint32_t hv, uint64_t (&M)[4], uint64_t (&G)[4],
                                            uint64_t &steps)
 {
@@ -909,6 +912,8 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
         else by_pos(b, w, last, hv, alive);
     }
     if (last >= kWin) {
+        // The columns past the window (the CSR start is read only here).
+        const int32_t *c = colidx + hp->begin;
         if constexpr (NEG) {
             const uint32_t fm = fall - (fall >> 7);
             by_tail<COUNT>(base, c, w, last, fm | kByteHi, ~fm, alive, steps);
@@ -1002,6 +1007,7 @@ __device__ __forceinline__ void load_head(const IndHead *__restrict__ hb, int32_
                  "s"(hv[1].w), "s"(hv[2].x), "s"(hv[2].y), "s"(hv[2].z), "s"(hv[2].w));
 }
 
+
 // ---------------------------------------------------------------------------
 // One work item: individuals [i0, i0 + np) of request d on tiles [t0, t1).
 // `tile` and `cnt` are this block's LDS areas; wave w takes the group's
@@ -1025,6 +1031,23 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
     const IndHead *hb = heads + d.head_base + i0;
 
     for (int32_t t = threadIdx.x; t < 2 * np; t += blockDim.x) cnt[t] = 0;
+
+    // Byte codes: every thread copies up to two 16-byte pieces of a chunk
+    // (piece idx = 16 bytes of column idx / 16) through registers; the
+    // pieces of the next chunk are loaded while the current one is
+    // evaluated. Pieces past 2 * blockDim are copied directly.
+    const int btotal = STAGE == STAGE_BYTES ? d.cols * 16 : 0;
+    const int idx0 = threadIdx.x, idx1 = threadIdx.x + blockDim.x;
+    const uint8_t *src0 = d.B + (int64_t)(idx0 >> 4) * d.ldb + 16 * (idx0 & 15);
+    const uint8_t *src1 = d.B + (int64_t)(idx1 >> 4) * d.ldb + 16 * (idx1 & 15);
+    uint4 pre0 = {0, 0, 0, 0}, pre1 = {0, 0, 0, 0};
+    if constexpr (STAGE == STAGE_BYTES) {
+        if (t0 < t1) {
+            const int64_t r0 = t0 * kWave;
+            if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r0);
+            if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r0);
+        }
+    }
 
     for (int64_t tb = t0; tb < t1; tb += L) {
         const int nl = (int)min<int64_t>(L, t1 - tb);
@@ -1064,16 +1087,25 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             // The 256 bytes of every column for rows [row0, row0 + 256), in
             // their interleaved order; rows outside the item or the matrix
             // are left out of `hvalid` instead.
-            const int total = d.cols * 16;
-            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-                const int c = idx >> 4, q = idx & 15;
-                reinterpret_cast<uint4 *>(tile)[idx] =
-                    *reinterpret_cast<const uint4 *>(d.B + (int64_t)c * d.ldb + row0 + 16 * q);
-            }
+            uint4 *tile4 = reinterpret_cast<uint4 *>(tile);
+            if (idx0 < btotal) tile4[idx0] = pre0;
+            if (idx1 < btotal) tile4[idx1] = pre1;
+            for (int idx = idx1 + blockDim.x; idx < btotal; idx += blockDim.x)
+                tile4[idx] = *reinterpret_cast<const uint4 *>(d.B + (int64_t)(idx >> 4) * d.ldb + row0 +
+                                                              16 * (idx & 15));
+            if (nl == L && row0 + L * kWave <= d.rows) {
+                hvalid = 0x80808080u;
+            } else {
 #pragma unroll
-            for (int s = 0; s < L; ++s)
-                if (s < nl && row0 + s * kWave + lane < d.rows) hvalid |= 0x80u << (8 * s);
+                for (int s = 0; s < L; ++s)
+                    if (s < nl && row0 + s * kWave + lane < d.rows) hvalid |= 0x80u << (8 * s);
+            }
             __syncthreads();
+            if (tb + L < t1) {
+                const int64_t r1 = row0 + L * kWave;
+                if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r1);
+                if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r1);
+            }
         }
         if constexpr (STAGE == STAGE_LDS) {
             // Rows [row0, row0 + nl*64) of every column, 4 rows per thread.
@@ -1111,29 +1143,29 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         // compiled twice, with and without the mask stores.
         auto individuals = [&](auto masks_tag) {
         constexpr bool MASKS = decltype(masks_tag)::value;
-        for (int32_t ii = wave; ii < np; ii += W) {
-            int4 hv[3];
-            load_head(hb, ii, hv);
+        // One individual (header hv) on the staged chunk.
+        auto one = [&](const int4 (&hv)[3], int32_t ii) {
             const int32_t k = hv[0].x;
             uint64_t M[L], G[L];
             if (k == 0) {
 #pragma unroll
                 for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
             } else {
-                const int32_t *c = d.colidx + hv[0].y;
                 bool live = true;  // (byte codes: some row matches)
                 if constexpr (STAGE == STAGE_BYTES) {
-                    live = eval_bytes<NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1, c,
-                                                  hv[1], hv[2], lane, hvalid, M, G, steps);
+                    live = eval_bytes<NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1,
+                                                  d.colidx, hb + ii, hv[1], hv[2], lane, hvalid, M, G, steps);
                     if (!live) {
 #pragma unroll
                         for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
                     }
                 } else if constexpr (STAGE == STAGE_CODES) {
                     static_assert(L >= 2, "rank codes are staged for 2 or 4 sub-tiles");
+                    const int32_t *c = d.colidx + hv[0].y;
                     eval_lds_il<L, NEG, COUNT, uint16_t>(reinterpret_cast<const unsigned char *>(tile), k - 1,
                                                          c, hv[1], hv[2], lane, M, G, steps);
                 } else if constexpr (STAGE == STAGE_LDS) {
+                    const int32_t *c = d.colidx + hv[0].y;
                     if constexpr (L >= 2)
                         eval_lds_il<L, NEG, COUNT, float>(reinterpret_cast<const unsigned char *>(tile), k - 1, c,
                                                           hv[1], hv[2], lane, M, G, steps);
@@ -1147,6 +1179,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                     int64_t sub[L];
 #pragma unroll
                     for (int s = 0; s < L; ++s) sub[s] = min<int64_t>(row0 + s * kWave, last_row0) - row0;
+                    const int32_t *c = d.colidx + hv[0].y;
                     eval_direct<L, NEG, COUNT>(d.X + row0 + lane, d.ld, sub, k - 1, c, d.fill,
                                                (d.flags & kFlagSubst) != 0, valid, M, G, steps);
                 }
@@ -1183,6 +1216,11 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                 if (d.mmask) store_words<L>(d.mmask + i * words + tb, M, nl, lane);
                 if (d.nmask) store_words<L>(d.nmask + i * words + tb, G, nl, lane);
             }
+        };
+        for (int32_t ii = wave; ii < np; ii += W) {
+            int4 hv[3];
+            load_head(hb, ii, hv);
+            one(hv, ii);
         }
         };
         if (d.mmask || d.nmask) individuals(std::true_type{});
