@@ -33,10 +33,10 @@ HBM_PEAK_GBS = 8000.0
 # FP32 / FP16 staging: one 64-lane compare instruction per sub-tile and
 # column, counted as 64 compare lane-ops: peak 39.3 T/s.
 CMP_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Byte rank codes: one 32-bit lane op covers four rows, and a column step
-# costs three ops (two v_xad_u32 and an AND): peak 4/3 x 39.3 = 52.4 T
-# row-checks/s.
-BYTE_PEAK_TOPS = CMP_PEAK_TOPS * 4 / 3
+# Byte rank codes: one 32-bit lane op covers four rows, and two column
+# steps cost five ops (four v_xad_u32 and one three-input AND): peak
+# 4 / 2.5 x 39.3 = 62.9 T row-checks/s.
+BYTE_PEAK_TOPS = CMP_PEAK_TOPS * 4 / 2.5
 STAGE_BYTES = 3
 
 
@@ -689,7 +689,7 @@ def main():
             "ops": (("row checks executed per launch: %d steps x 64 rows (one step = one column "
                      "of one 64-row sub-tile; the first pair counts one step; early exit per "
                      "256-row chunk), counted by the measurement variant of the kernel; peak = "
-                     "39.3e12 32-bit VALU lane ops/s x 4 rows per lane op / 3 ops per column "
+                     "39.3e12 32-bit VALU lane ops/s x 4 rows per lane op / 2.5 ops per column "
                      "step" % executed_steps) if stg == STAGE_BYTES else
                     ("FP32 compares executed per launch: %d wave-wide compare instructions x 64 "
                      "rows (first pair: 3 per 64-row tile, then 1 per column step of each row's "

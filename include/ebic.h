@@ -194,7 +194,8 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
 /*
  * Force the launch shape of later evaluations on this context (tests and
  * tuning experiments); waves_per_block = 0 restores the automatic choice.
- *   tiles_per_wave:        64-row tiles one wave evaluates together (1, 2, 4)
+ *   tiles_per_wave:        64-row tiles one wave evaluates together (1, 2, 4;
+ *                          8 with the byte rank codes, plain evaluations only)
  *   waves_per_block:       1 .. 16
  *   individuals_per_group: individuals that share one block's staged tiles
  *   staging:               0 = column tiles staged in LDS, 1 = direct reads,

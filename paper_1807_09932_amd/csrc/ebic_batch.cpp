@@ -145,6 +145,7 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     p.cfg = batch_cfg(ctx, total, mean_rows, max_cols, -1);
     LaunchCfg &c = p.cfg;
     const size_t lds_max = ctx->lds_per_block - 256;  // room for the kernel's static LDS
+    if (c.L == 8) c.L = 4;  // (batches stage at most four sub-tiles per chunk)
     if (c.L != 1 && c.L != 2 && c.L != 4) c.L = 2;
     c.W = std::max(1, std::min(16, c.W));
     c.P = std::max(1, c.P);
@@ -270,7 +271,7 @@ static std::unique_ptr<GraphEntry> capture_graph(ebic_ctx *ctx, const GraphSpec 
             check(hipEventCreateWithFlags(&g->done[i], hipEventDisableTiming), "hipEventCreate");
         }
         char *da = static_cast<char *>(g->d_arena);
-        const int prep_blocks = std::max(1, ctx->cu_count * 2);
+        const int prep_blocks = std::max(1, ctx->cu_count * 8);  // four waves each, one individual per wave
         unsigned long long *counter = count ? ctx->d_step_counter : nullptr;
         check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
         check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");

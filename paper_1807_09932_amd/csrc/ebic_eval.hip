@@ -48,7 +48,7 @@ constexpr int32_t kInvalid = -1;
 __host__ __device__ inline size_t tile_bytes_of(int32_t L, int32_t cols, int32_t staging)
 {
     if (staging == STAGE_DIRECT) return 0;
-    if (staging == STAGE_BYTES) return (size_t)cols * 4 * kWave;  // four sub-tiles, one byte per row
+    if (staging == STAGE_BYTES) return (size_t)cols * L * kWave;  // one byte per row
     return (size_t)L * kWave * cols * (staging == STAGE_CODES ? sizeof(uint16_t) : sizeof(float));
 }
 
@@ -61,48 +61,58 @@ __host__ __device__ inline size_t count_bytes_of(int32_t P)
 // ---------------------------------------------------------------------------
 // Prep: validation, output initialisation and the per-individual header.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void prep_one(const ReqDesc &d, int32_t i, IndHead *__restrict__ heads)
+// One wave per individual: the lanes check its columns together (one round
+// of independent loads for up to 64 columns), lane 0 initialises the
+// outputs, and lanes 0..15 write the 64-byte header word by word.
+__device__ __forceinline__ void prep_wave(const ReqDesc &d, int32_t i, IndHead *__restrict__ heads, int lane)
 {
     const int32_t b = d.offsets[i], e = d.offsets[i + 1];
-    bool ok = b >= 0 && e > b;
-    for (int32_t j = b; ok && j < e; ++j) {
-        const int32_t c = d.colidx[j];
-        ok = c >= 0 && c < d.cols;
+    const bool span = b >= 0 && e > b;
+    bool bad = false;
+    int32_t win = 0;  // lanes 8..15: window column lane - 8 (clamped to the last column)
+    if (span) {
+        if (lane >= 8 && lane < 16) win = d.colidx[b + min(lane - 8, e - b - 1)];
+        for (int32_t j = b + lane; j < e; j += kWave) {
+            const int32_t c = d.colidx[j];
+            bad |= c < 0 || c >= d.cols;
+        }
     }
-    d.matched[i] = ok ? 0 : kInvalid;
-    if (d.negative) d.negative[i] = ok ? 0 : kInvalid;
+    const bool ok = span && __ballot(bad) == 0;
     const int32_t k = ok ? e - b : 0;
-    int32_t w[kWin];
-#pragma unroll
-    for (int u = 0; u < kWin; ++u) w[u] = ok ? d.colidx[b + min(u, k - 1)] : 0;
-    int4 *dst = reinterpret_cast<int4 *>(heads + d.head_base + i);
-    dst[0] = make_int4(k, b, 0, 0);
-    dst[1] = make_int4(0, 0, 0, 0);
-    dst[2] = make_int4(w[0], w[1], w[2], w[3]);
-    dst[3] = make_int4(w[4], w[5], w[6], w[7]);
+    if (lane == 0) {
+        d.matched[i] = ok ? 0 : kInvalid;
+        if (d.negative) d.negative[i] = ok ? 0 : kInvalid;
+    }
+    if (lane < 16) {
+        // words: k, begin, 6 x 0, the window
+        const int32_t v = lane == 0 ? k : lane == 1 ? b : (lane >= 8 && ok) ? win : 0;
+        reinterpret_cast<int32_t *>(heads + d.head_base + i)[lane] = v;
+    }
 }
 
-__global__ void k_prep(ReqDesc d, IndHead *__restrict__ heads)
+__global__ void __launch_bounds__(256) k_prep(ReqDesc d, IndHead *__restrict__ heads)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < d.n) prep_one(d, i, heads);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int32_t i = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (i < d.n) prep_wave(d, i, heads, threadIdx.x & (kWave - 1));
 }
 
-__global__ void k_prep_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs,
-                             const int64_t *__restrict__ first, IndHead *__restrict__ heads)
+__global__ void __launch_bounds__(256) k_prep_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs,
+                                                    const int64_t *__restrict__ first, IndHead *__restrict__ heads)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) hdr->counter = 0;
     const int64_t total = hdr->total_ind;
     const int32_t nreq = hdr->n_req;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave; g < total; g += stride) {
         int32_t lo = 0, hi = nreq - 1;  // the last request with first[q] <= g
         while (lo < hi) {
             const int32_t mid = (lo + hi + 1) >> 1;
             if (first[mid] <= g) lo = mid;
             else hi = mid - 1;
         }
-        prep_one(descs[lo], (int32_t)(g - first[lo]), heads);
+        prep_wave(descs[lo], (int32_t)(g - first[lo]), heads, threadIdx.x & (kWave - 1));
     }
 }
 
@@ -697,7 +707,7 @@ __device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ ti
 constexpr uint32_t kByteHi = 0x80808080u;
 
 #define BY_LOAD(t, w)                                                          \
-    "v_lshl_add_u32 %[ad], %[" w "], 8, %[base]\n\t"                           \
+    "v_lshl_add_u32 %[ad], %[" w "], %[sh], %[base]\n\t"                       \
     "ds_read_b32 %[" t "], %[ad]\n\t"
 #define BY_PAIR(ta, tb, FH, NF, NX, AL, ALIN)                                  \
     "v_xad_u32 %[D], %[" ta "], " FH ", %[" NX "]\n\t"                         \
@@ -726,7 +736,11 @@ constexpr uint32_t kByteHi = 0x80808080u;
         [D] "=&v"(D), [D2] "=&v"(D2), [tmp] "=&s"(tmp)
 #define BY_COLS                                                                \
     [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), \
-        [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last)
+        [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last), \
+        [sh] "i"(SH)
+
+// The sequences below take SH = log2 of the bytes one staged column
+// occupies (8: 256-row chunks, 9: 512-row chunks of two 256-row groups).
 
 // Both chains through column min(last, 7): alive (rows on their oriented
 // chain), fall (bit 7 of the in-range rows with t1 < t0) and tied (the
@@ -734,6 +748,7 @@ constexpr uint32_t kByteHi = 0x80808080u;
 // last >= 2). The sequence starts with lgkmcnt(0) (no scalar load in
 // flight, so LDS operations complete in issue order and lgkmcnt(n) means
 // that all but the last n issued are done) and ends with it.
+template <int SH>
 __device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
                                        uint32_t &alive, uint32_t &fall, uint32_t &tied)
 {
@@ -781,6 +796,7 @@ __device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], 
 }
 
 // The >= chain alone through column min(last, 7) (waits as above).
+template <int SH>
 __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
                                        uint32_t &alive)
 {
@@ -812,10 +828,168 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
 #undef BY_SCRATCH
 #undef BY_COLS
 
+// ---------------------------------------------------------------------------
+// Two 256-row groups per chunk (512 rows; a staged column is 512 bytes, the
+// second group at +256): the same chains for both groups in one instruction
+// stream. A column's two words share one address, the two groups' operations
+// are independent (they hide each other's latency), and the window ends when
+// no row of either group is left.
+// ---------------------------------------------------------------------------
+#define B2_LOAD(t, w)                                                          \
+    "v_lshl_add_u32 %[ad], %[" w "], 9, %[base]\n\t"                           \
+    "ds_read_b32 %[" t "a], %[ad]\n\t"                                         \
+    "ds_read_b32 %[" t "b], %[ad] offset:256\n\t"
+#define B2_PAIR(ta, tb, FHA, FHB, NFA, NFB, NXA, NXB, AOA, AOB, AIA, AIB)      \
+    "v_xad_u32 %[Da], %[" ta "a], " FHA ", %[" NXA "]\n\t"                     \
+    "v_xad_u32 %[Db], %[" ta "b], " FHB ", %[" NXB "]\n\t"                     \
+    "v_xad_u32 %[" NXA "], %[" ta "a], " NFA ", 1\n\t"                         \
+    "v_xad_u32 %[" NXB "], %[" ta "b], " NFB ", 1\n\t"                         \
+    "v_xad_u32 %[Ea], %[" tb "a], " FHA ", %[" NXA "]\n\t"                     \
+    "v_xad_u32 %[Eb], %[" tb "b], " FHB ", %[" NXB "]\n\t"                     \
+    "v_xad_u32 %[" NXA "], %[" tb "a], " NFA ", 1\n\t"                         \
+    "v_xad_u32 %[" NXB "], %[" tb "b], " NFB ", 1\n\t"                         \
+    "v_bitop3_b32 %[" AOA "], %[" AIA "], %[Da], %[Ea] bitop3:0x80\n\t"        \
+    "v_bitop3_b32 %[" AOB "], %[" AIB "], %[Db], %[Eb] bitop3:0x80\n\t"
+#define B2_EXIT_LAST(u, L) "s_cmp_le_i32 %[last], " u "\n\t" "s_cbranch_scc1 " L "\n\t"
+#define B2_EXIT(u, AA, AB, L)                                                  \
+    "v_or_b32_e32 %[Da], %[" AA "], %[" AB "]\n\t"                             \
+    "v_cmp_ne_u32_e64 %[tmp], 0, %[Da]\n\t"                                    \
+    "s_cmp_lg_u64 %[tmp], 0\n\t"                                               \
+    "s_cbranch_scc0 " L "\n\t" B2_EXIT_LAST(u, L)
+// Columns 2..7 (t2, t3 hold or are loading columns 2 and 3; loads run two
+// columns ahead; two loads per column).
+#define B2_WINDOW(FHA, FHB, NFA, NFB, AA, AB, IA, IB, L)                       \
+    B2_LOAD("t0", "w4") B2_LOAD("t1", "w5") "s_waitcnt lgkmcnt(4)\n\t"         \
+    B2_PAIR("t2", "t3", FHA, FHB, NFA, NFB, "nxa", "nxb", AA, AB, IA, IB)      \
+    B2_EXIT_LAST("3", L)                                                       \
+    B2_LOAD("t2", "w6") B2_LOAD("t3", "w7") "s_waitcnt lgkmcnt(4)\n\t"         \
+    B2_PAIR("t0", "t1", FHA, FHB, NFA, NFB, "nxa", "nxb", AA, AB, AA, AB)      \
+    B2_EXIT("5", AA, AB, L)                                                    \
+    "s_waitcnt lgkmcnt(0)\n\t"                                                 \
+    B2_PAIR("t2", "t3", FHA, FHB, NFA, NFB, "nxa", "nxb", AA, AB, AA, AB)
+#define B2_SCRATCH                                                             \
+    [t0a] "=&v"(t0a), [t0b] "=&v"(t0b), [t1a] "=&v"(t1a), [t1b] "=&v"(t1b),    \
+        [t2a] "=&v"(t2a), [t2b] "=&v"(t2b), [t3a] "=&v"(t3a), [t3b] "=&v"(t3b), \
+        [ad] "=&v"(ad), [Da] "=&v"(Da), [Db] "=&v"(Db), [Ea] "=&v"(Ea), [Eb] "=&v"(Eb), \
+        [nxa] "=&v"(nxa), [nxb] "=&v"(nxb), [tmp] "=&s"(tmp)
+#define B2_COLS                                                                \
+    [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), \
+        [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last)
+// First pair of a group (X = a or b): falling, tied and oriented words; the
+// two groups' operations alternate.
+#define B2_F1(X) "v_or_b32_e32 %[D" X "], 0x80808080, %[t1" X "]\n\t"
+#define B2_F2(X) "v_sub_u32_e32 %[D" X "], %[D" X "], %[t0" X "]\n\t"
+#define B2_F3(X) "v_sub_u32_e32 %[E" X "], 0x1010100, %[D" X "]\n\t"
+#define B2_F4(X) "v_bitop3_b32 %[tied" X "], %[D" X "], %[E" X "], %[hv" X "] bitop3:0x80\n\t"
+#define B2_F5(X) "v_bitop3_b32 %[fall" X "], %[D" X "], %[E" X "], %[hv" X "] bitop3:0x08\n\t"
+#define B2_F6(X) "v_lshrrev_b32_e32 %[E" X "], 7, %[fall" X "]\n\t"
+#define B2_F7(X) "v_sub_u32_e32 %[E" X "], %[fall" X "], %[E" X "]\n\t"
+#define B2_F8(X) "v_or_b32_e32 %[fH" X "], 0x80808080, %[E" X "]\n\t"
+#define B2_F9(X) "v_not_b32_e32 %[nf" X "], %[E" X "]\n\t"
+#define B2_F10(X) "v_xad_u32 %[nx" X "], %[t1" X "], %[nf" X "], 1\n\t"
+#define B2_FIRST                                                               \
+    B2_F1("a") B2_F1("b") B2_F2("a") B2_F2("b") B2_F3("a") B2_F3("b")          \
+    B2_F4("a") B2_F4("b") B2_F5("a") B2_F5("b") B2_F6("a") B2_F6("b")          \
+    B2_F7("a") B2_F7("b") B2_F8("a") B2_F8("b") B2_F9("a") B2_F9("b")          \
+    B2_F10("a") B2_F10("b")
+
+// Both chains on both groups through column min(last, 7); outputs per
+// group as in by_neg. (Waits count LDS operations; they start and end with
+// lgkmcnt(0).)
+__device__ __forceinline__ void by2_neg(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hva,
+                                        uint32_t hvb, uint32_t &alivea, uint32_t &aliveb, uint32_t &falla,
+                                        uint32_t &fallb, uint32_t &tieda, uint32_t &tiedb)
+{
+    uint32_t t0a, t0b, t1a, t1b, t2a, t2b, t3a, t3b, ad, Da, Db, Ea, Eb, nxa, nxb, fHa, fHb, nfa, nfb;
+    uint64_t tmp, tany;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        B2_LOAD("t0", "w0") B2_LOAD("t1", "w1") B2_LOAD("t2", "w2") B2_LOAD("t3", "w3")
+        "s_waitcnt lgkmcnt(4)\n\t"
+        B2_FIRST
+        "v_or_b32_e32 %[Da], %[tieda], %[tiedb]\n\t"
+        "v_cmp_ne_u32_e64 %[tany], 0, %[Da]\n\t"
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 6f\n\t"
+        B2_WINDOW("%[fHa]", "%[fHb]", "%[nfa]", "%[nfb]", "alivea", "aliveb", "hva", "hvb", "2f")
+        "2:\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        // The rows tied on the first pair: the <= chain from column 1.
+        "s_cmp_lg_u64 %[tany], 0\n\t"
+        "s_cbranch_scc0 4f\n\t"
+        B2_LOAD("t1", "w1") B2_LOAD("t2", "w2") B2_LOAD("t3", "w3")
+        "s_waitcnt lgkmcnt(4)\n\t"
+        "v_xad_u32 %[nxa], %[t1a], %[hi], 1\n\t"
+        "v_xad_u32 %[nxb], %[t1b], %[hi], 1\n\t"
+        B2_WINDOW("-1", "-1", "%[hi]", "%[hi]", "tieda", "tiedb", "tieda", "tiedb", "3f")
+        "3:\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_branch 5f\n\t"
+        "6:\n\t"  // two columns: every row in range is on its chain
+        "v_mov_b32_e32 %[alivea], %[hva]\n\t"
+        "v_mov_b32_e32 %[aliveb], %[hvb]\n\t"
+        "4:\n\t"
+        "v_mov_b32_e32 %[tieda], 0\n\t"
+        "v_mov_b32_e32 %[tiedb], 0\n\t"
+        "5:"
+        : B2_SCRATCH, [fHa] "=&v"(fHa), [fHb] "=&v"(fHb), [nfa] "=&v"(nfa), [nfb] "=&v"(nfb),
+          [alivea] "=&v"(alivea), [aliveb] "=&v"(aliveb), [falla] "=&v"(falla), [fallb] "=&v"(fallb),
+          [tieda] "=&v"(tieda), [tiedb] "=&v"(tiedb), [tany] "=&s"(tany)
+        : B2_COLS, [hva] "v"(hva), [hvb] "v"(hvb), [hi] "s"(kByteHi)
+        : "scc", "memory");
+}
+
+// The >= chain alone on both groups.
+__device__ __forceinline__ void by2_pos(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hva,
+                                        uint32_t hvb, uint32_t &alivea, uint32_t &aliveb)
+{
+    uint32_t t0a, t0b, t1a, t1b, t2a, t2b, t3a, t3b, ad, Da, Db, Ea, Eb, nxa, nxb;
+    uint64_t tmp;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        B2_LOAD("t0", "w0") B2_LOAD("t1", "w1") B2_LOAD("t2", "w2") B2_LOAD("t3", "w3")
+        "s_waitcnt lgkmcnt(4)\n\t"
+        "v_or_b32_e32 %[Da], 0x80808080, %[t1a]\n\t"
+        "v_or_b32_e32 %[Db], 0x80808080, %[t1b]\n\t"
+        "v_sub_u32_e32 %[Da], %[Da], %[t0a]\n\t"
+        "v_sub_u32_e32 %[Db], %[Db], %[t0b]\n\t"
+        "v_and_b32_e32 %[alivea], %[Da], %[hva]\n\t"
+        "v_and_b32_e32 %[aliveb], %[Db], %[hvb]\n\t"
+        "v_sub_u32_e32 %[nxa], 0, %[t1a]\n\t"
+        "v_sub_u32_e32 %[nxb], 0, %[t1b]\n\t"
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        B2_WINDOW("%[hi]", "%[hi]", "-1", "-1", "alivea", "aliveb", "alivea", "aliveb", "2f")
+        "2:\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : B2_SCRATCH, [alivea] "=&v"(alivea), [aliveb] "=&v"(aliveb)
+        : B2_COLS, [hva] "v"(hva), [hvb] "v"(hvb), [hi] "s"(kByteHi)
+        : "scc", "memory");
+}
+
+#undef B2_LOAD
+#undef B2_PAIR
+#undef B2_EXIT_LAST
+#undef B2_EXIT
+#undef B2_WINDOW
+#undef B2_SCRATCH
+#undef B2_COLS
+#undef B2_FIRST
+#undef B2_F1
+#undef B2_F2
+#undef B2_F3
+#undef B2_F4
+#undef B2_F5
+#undef B2_F6
+#undef B2_F7
+#undef B2_F8
+#undef B2_F9
+#undef B2_F10
+
 // Wave-wide masks of the four sub-tiles: bit l of m[b] is bit 7 of byte b
 // of lane l's word (one SDWA compare per byte). The trailing wait states
 // let any following VALU read the masks.
-__device__ __forceinline__ void byte_masks(uint32_t x, uint64_t (&m)[4])
+__device__ __forceinline__ void byte_masks4(uint32_t x, uint64_t &m0, uint64_t &m1, uint64_t &m2, uint64_t &m3)
 {
     asm volatile(
         "v_cmp_ne_u32_sdwa %[m0], %[x], 0 src0_sel:BYTE_0 src1_sel:DWORD\n\t"
@@ -823,20 +997,22 @@ __device__ __forceinline__ void byte_masks(uint32_t x, uint64_t (&m)[4])
         "v_cmp_ne_u32_sdwa %[m2], %[x], 0 src0_sel:BYTE_2 src1_sel:DWORD\n\t"
         "v_cmp_ne_u32_sdwa %[m3], %[x], 0 src0_sel:BYTE_3 src1_sel:DWORD\n\t"
         "s_nop 1"
-        : [m0] "=s"(m[0]), [m1] "=s"(m[1]), [m2] "=s"(m[2]), [m3] "=s"(m[3])
+        : [m0] "=s"(m0), [m1] "=s"(m1), [m2] "=s"(m2), [m3] "=s"(m3)
         : [x] "v"(x));
 }
 
+__device__ __forceinline__ void byte_masks(uint32_t x, uint64_t (&m)[4]) { byte_masks4(x, m[0], m[1], m[2], m[3]); }
+
 // Plain-code twin of the window (the measurement variant): the same exit
 // points; counts one step per 64-row sub-tile and column.
-template <bool COUNT>
+template <int SH, bool COUNT>
 __device__ __forceinline__ void by_window_ref(const unsigned char *__restrict__ base, const int32_t (&w)[kWin],
                                               int32_t last, uint32_t fH, uint32_t nf, uint32_t nx,
                                               uint32_t &alive, uint64_t &steps)
 {
 #pragma unroll
     for (int u = 2; u < kWin; ++u) {
-        const uint32_t t = *reinterpret_cast<const uint32_t *>(base + w[u] * 256);
+        const uint32_t t = *reinterpret_cast<const uint32_t *>(base + (w[u] << SH));
         alive &= (t ^ fH) + nx;
         nx = (t ^ nf) + 1u;
         if (COUNT) steps += 4;
@@ -847,15 +1023,15 @@ __device__ __forceinline__ void by_window_ref(const unsigned char *__restrict__ 
 
 // Columns kWin..last (long individuals), while any row is left; nx is -x
 // of window column 7 (with a row left, the window ran through column 7).
-template <bool COUNT>
+template <int SH, bool COUNT>
 __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, const int32_t *__restrict__ c,
                                         const int32_t (&w)[kWin], int32_t last, uint32_t fH, uint32_t nf,
                                         uint32_t &alive, uint64_t &steps)
 {
-    uint32_t nx = (*reinterpret_cast<const uint32_t *>(base + w[kWin - 1] * 256) ^ nf) + 1u;
+    uint32_t nx = (*reinterpret_cast<const uint32_t *>(base + (w[kWin - 1] << SH)) ^ nf) + 1u;
     for (int32_t u = kWin; u <= last; ++u) {
         if (__ballot(alive != 0) == 0) return;
-        const uint32_t t = *reinterpret_cast<const uint32_t *>(base + c[u] * 256);
+        const uint32_t t = *reinterpret_cast<const uint32_t *>(base + (c[u] << SH));
         alive &= (t ^ fH) + nx;
         nx = (t ^ nf) + 1u;
         if (COUNT) steps += 4;
@@ -867,7 +1043,7 @@ __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, 
 // The byte codes have no missing value (exclude mode uses them only on a
 // matrix without missing cells; include mode's codes encode the fill).
 // Returns false, and leaves M and G unset, when no row matches.
-template <bool NEG, bool COUNT>
+template <int SH, bool NEG, bool COUNT>
 __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ tile, int32_t last,
                                            const int32_t *__restrict__ colidx,
                                            const IndHead *__restrict__ hp, const int4 &w03, const int4 &w47,
@@ -876,7 +1052,7 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
 {
     const unsigned char *base = tile + 4 * lane;
     const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
-    auto rd = [&](int32_t col) { return *reinterpret_cast<const uint32_t *>(base + col * 256); };
+    auto rd = [&](int32_t col) { return *reinterpret_cast<const uint32_t *>(base + (col << SH)); };
     if (last == 0) {  // one column: every row in range counts
         byte_masks(hv, M);
 #pragma unroll
@@ -899,27 +1075,27 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
             alive = hv;
         }
         steps += 4;
-        if (last >= 2) by_window_ref<COUNT>(base, w, last, fH, nf, (t1 ^ nf) + 1u, alive, steps);
+        if (last >= 2) by_window_ref<SH, COUNT>(base, w, last, fH, nf, (t1 ^ nf) + 1u, alive, steps);
         if (NEG && last >= 2 && __ballot(tied != 0) != 0) {
             steps += 4;
-            by_window_ref<COUNT>(base, w, last, ~0u, kByteHi, (t1 ^ kByteHi) + 1u, tied, steps);
+            by_window_ref<SH, COUNT>(base, w, last, ~0u, kByteHi, (t1 ^ kByteHi) + 1u, tied, steps);
         } else {
             tied = 0;
         }
     } else {
         const uint32_t b = lds_addr(base);
-        if constexpr (NEG) by_neg(b, w, last, hv, alive, fall, tied);
-        else by_pos(b, w, last, hv, alive);
+        if constexpr (NEG) by_neg<SH>(b, w, last, hv, alive, fall, tied);
+        else by_pos<SH>(b, w, last, hv, alive);
     }
     if (last >= kWin) {
         // The columns past the window (the CSR start is read only here).
         const int32_t *c = colidx + hp->begin;
         if constexpr (NEG) {
             const uint32_t fm = fall - (fall >> 7);
-            by_tail<COUNT>(base, c, w, last, fm | kByteHi, ~fm, alive, steps);
-            by_tail<COUNT>(base, c, w, last, ~0u, kByteHi, tied, steps);
+            by_tail<SH, COUNT>(base, c, w, last, fm | kByteHi, ~fm, alive, steps);
+            by_tail<SH, COUNT>(base, c, w, last, ~0u, kByteHi, tied, steps);
         } else {
-            by_tail<COUNT>(base, c, w, last, kByteHi, ~0u, alive, steps);
+            by_tail<SH, COUNT>(base, c, w, last, kByteHi, ~0u, alive, steps);
         }
     }
     const uint32_t mw = alive | tied;
@@ -929,6 +1105,115 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
     else {
 #pragma unroll
         for (int s = 0; s < 4; ++s) G[s] = 0;
+    }
+    return true;
+}
+
+// Plain-code twin of the two-group window (the measurement variant): both
+// groups in lockstep with the same exits; one step per 64-row sub-tile and
+// column.
+template <bool COUNT>
+__device__ __forceinline__ void by2_window_ref(const unsigned char *__restrict__ base, const int32_t (&w)[kWin],
+                                               int32_t last, const uint32_t (&fH)[2], const uint32_t (&nf)[2],
+                                               uint32_t (&nx)[2], uint32_t (&alive)[2], uint64_t &steps)
+{
+#pragma unroll
+    for (int u = 2; u < kWin; ++u) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t t = *reinterpret_cast<const uint32_t *>(base + (w[u] << 9) + 256 * h);
+            alive[h] &= (t ^ fH[h]) + nx[h];
+            nx[h] = (t ^ nf[h]) + 1u;
+        }
+        if (COUNT) steps += 8;
+        if (u == 3 && last <= 3) return;
+        if (u == 5 && (__ballot((alive[0] | alive[1]) != 0) == 0 || last <= 5)) return;
+    }
+}
+
+// One individual on a chunk of two 256-row groups of byte codes (eight
+// 64-row sub-tiles; a column is 512 bytes). hva, hvb: the in-range rows of
+// each group. Returns false, and leaves M and G unset, when no row matches.
+template <bool NEG, bool COUNT>
+__device__ __forceinline__ bool eval_bytes2(const unsigned char *__restrict__ tile, int32_t last,
+                                            const int32_t *__restrict__ colidx,
+                                            const IndHead *__restrict__ hp, const int4 &w03, const int4 &w47,
+                                            int lane, uint32_t hva, uint32_t hvb, uint64_t (&M)[8],
+                                            uint64_t (&G)[8], uint64_t &steps)
+{
+    const unsigned char *base = tile + 4 * lane;
+    const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
+    auto rd = [&](int32_t col, int h) {
+        return *reinterpret_cast<const uint32_t *>(base + (col << 9) + 256 * h);
+    };
+    if (last == 0) {  // one column: every row in range counts
+        byte_masks4(hva, M[0], M[1], M[2], M[3]);
+        byte_masks4(hvb, M[4], M[5], M[6], M[7]);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) G[s] = 0;
+        if (COUNT) steps += 8;
+        return true;
+    }
+    uint32_t alive[2], fall[2] = {0, 0}, tied[2] = {0, 0};
+    if constexpr (COUNT) {
+        uint32_t fH[2], nf[2], nx[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t hv = h ? hvb : hva;
+            const uint32_t t0 = rd(w[0], h), t1 = rd(w[1], h);
+            const uint32_t D = (t1 | kByteHi) - t0, E = (t0 | kByteHi) - t1;
+            fH[h] = kByteHi;
+            nf[h] = ~0u;
+            alive[h] = D & hv;
+            if constexpr (NEG) {
+                tied[h] = D & E & hv;
+                fall[h] = E & ~D & hv;
+                const uint32_t fm = fall[h] - (fall[h] >> 7);
+                fH[h] = fm | kByteHi;
+                nf[h] = ~fm;
+                alive[h] = hv;
+            }
+            nx[h] = (t1 ^ nf[h]) + 1u;
+        }
+        steps += 8;
+        if (last >= 2) by2_window_ref<COUNT>(base, w, last, fH, nf, nx, alive, steps);
+        if (NEG && last >= 2 && __ballot((tied[0] | tied[1]) != 0) != 0) {
+            const uint32_t fH2[2] = {~0u, ~0u}, nf2[2] = {kByteHi, kByteHi};
+            uint32_t nx2[2] = {(rd(w[1], 0) ^ kByteHi) + 1u, (rd(w[1], 1) ^ kByteHi) + 1u};
+            steps += 8;
+            by2_window_ref<COUNT>(base, w, last, fH2, nf2, nx2, tied, steps);
+        } else {
+            tied[0] = tied[1] = 0;
+        }
+    } else {
+        const uint32_t b = lds_addr(base);
+        if constexpr (NEG) by2_neg(b, w, last, hva, hvb, alive[0], alive[1], fall[0], fall[1], tied[0], tied[1]);
+        else by2_pos(b, w, last, hva, hvb, alive[0], alive[1]);
+    }
+    if (last >= kWin) {
+        // The columns past the window (the CSR start is read only here).
+        const int32_t *c = colidx + hp->begin;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if constexpr (NEG) {
+                const uint32_t fm = fall[h] - (fall[h] >> 7);
+                by_tail<9, COUNT>(base + 256 * h, c, w, last, fm | kByteHi, ~fm, alive[h], steps);
+                by_tail<9, COUNT>(base + 256 * h, c, w, last, ~0u, kByteHi, tied[h], steps);
+            } else {
+                by_tail<9, COUNT>(base + 256 * h, c, w, last, kByteHi, ~0u, alive[h], steps);
+            }
+        }
+    }
+    const uint32_t mwa = alive[0] | tied[0], mwb = alive[1] | tied[1];
+    if (__ballot((mwa | mwb) != 0) == 0) return false;
+    byte_masks4(mwa, M[0], M[1], M[2], M[3]);
+    byte_masks4(mwb, M[4], M[5], M[6], M[7]);
+    if constexpr (NEG) {
+        byte_masks4((alive[0] & fall[0]) | (tied[0] & ~alive[0]), G[0], G[1], G[2], G[3]);
+        byte_masks4((alive[1] & fall[1]) | (tied[1] & ~alive[1]), G[4], G[5], G[6], G[7]);
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) G[s] = 0;
     }
     return true;
 }
@@ -1032,14 +1317,16 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
 
     for (int32_t t = threadIdx.x; t < 2 * np; t += blockDim.x) cnt[t] = 0;
 
-    // Byte codes: every thread copies up to two 16-byte pieces of a chunk
-    // (piece idx = 16 bytes of column idx / 16) through registers; the
-    // pieces of the next chunk are loaded while the current one is
-    // evaluated. Pieces past 2 * blockDim are copied directly.
-    const int btotal = STAGE == STAGE_BYTES ? d.cols * 16 : 0;
+    // Byte codes: a chunk holds L * 64 bytes of every column (L / 4 groups
+    // of 256 rows); every thread copies up to two 16-byte pieces of it
+    // (piece idx = bytes 16 * (idx % 4L) of column idx / 4L) through
+    // registers, and the pieces of the next chunk are loaded while the
+    // current one is evaluated. Pieces past 2 * blockDim are copied directly.
+    constexpr int PL = L == 8 ? 5 : 4;  // log2 of the pieces per column
+    const int btotal = STAGE == STAGE_BYTES ? d.cols << PL : 0;
     const int idx0 = threadIdx.x, idx1 = threadIdx.x + blockDim.x;
-    const uint8_t *src0 = d.B + (int64_t)(idx0 >> 4) * d.ldb + 16 * (idx0 & 15);
-    const uint8_t *src1 = d.B + (int64_t)(idx1 >> 4) * d.ldb + 16 * (idx1 & 15);
+    const uint8_t *src0 = d.B + (int64_t)(idx0 >> PL) * d.ldb + 16 * (idx0 & ((1 << PL) - 1));
+    const uint8_t *src1 = d.B + (int64_t)(idx1 >> PL) * d.ldb + 16 * (idx1 & ((1 << PL) - 1));
     uint4 pre0 = {0, 0, 0, 0}, pre1 = {0, 0, 0, 0};
     if constexpr (STAGE == STAGE_BYTES) {
         if (t0 < t1) {
@@ -1081,24 +1368,26 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             }
             __syncthreads();
         }
-        uint32_t hvalid = 0;  // byte codes: bit 7 of the bytes of the rows in range
+        // Byte codes: bit 7 of the bytes of the rows in range, per 256-row group.
+        uint32_t hvalid[L >= 4 ? L / 4 : 1] = {};
         if constexpr (STAGE == STAGE_BYTES) {
-            static_assert(L == 4, "byte codes hold four sub-tiles per lane word");
-            // The 256 bytes of every column for rows [row0, row0 + 256), in
-            // their interleaved order; rows outside the item or the matrix
-            // are left out of `hvalid` instead.
+            static_assert(L == 4 || L == 8, "byte codes hold four sub-tiles per lane word");
+            // The L * 64 bytes of every column for rows [row0, row0 + 64 L),
+            // in their interleaved order; rows outside the item or the
+            // matrix are left out of `hvalid` instead.
             uint4 *tile4 = reinterpret_cast<uint4 *>(tile);
             if (idx0 < btotal) tile4[idx0] = pre0;
             if (idx1 < btotal) tile4[idx1] = pre1;
             for (int idx = idx1 + blockDim.x; idx < btotal; idx += blockDim.x)
-                tile4[idx] = *reinterpret_cast<const uint4 *>(d.B + (int64_t)(idx >> 4) * d.ldb + row0 +
-                                                              16 * (idx & 15));
+                tile4[idx] = *reinterpret_cast<const uint4 *>(d.B + (int64_t)(idx >> PL) * d.ldb + row0 +
+                                                              16 * (idx & ((1 << PL) - 1)));
             if (nl == L && row0 + L * kWave <= d.rows) {
-                hvalid = 0x80808080u;
+#pragma unroll
+                for (int h = 0; h < L / 4; ++h) hvalid[h] = 0x80808080u;
             } else {
 #pragma unroll
                 for (int s = 0; s < L; ++s)
-                    if (s < nl && row0 + s * kWave + lane < d.rows) hvalid |= 0x80u << (8 * s);
+                    if (s < nl && row0 + s * kWave + lane < d.rows) hvalid[s / 4] |= 0x80u << (8 * (s % 4));
             }
             __syncthreads();
             if (tb + L < t1) {
@@ -1151,13 +1440,43 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
 #pragma unroll
                 for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
             } else {
-                bool live = true;  // (byte codes: some row matches)
-                if constexpr (STAGE == STAGE_BYTES) {
-                    live = eval_bytes<NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile), k - 1,
-                                                  d.colidx, hb + ii, hv[1], hv[2], lane, hvalid, M, G, steps);
-                    if (!live) {
+                bool live = true;  // (byte codes: counted per 256-row group below)
+                int32_t pm = 0, pg = 0;
+                if constexpr (STAGE == STAGE_BYTES && L == 8) {
+                    live = false;
+                    const bool any = eval_bytes2<NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile),
+                                                             k - 1, d.colidx, hb + ii, hv[1], hv[2], lane,
+                                                             hvalid[0], hvalid[L / 4 - 1], M, G, steps);
+                    if (any) {
+#pragma unroll
+                        for (int s = 0; s < L; ++s) {
+                            pm += __popcll(M[s]);
+                            pg += __popcll(G[s]);
+                        }
+                    } else {
 #pragma unroll
                         for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
+                    }
+                } else if constexpr (STAGE == STAGE_BYTES) {
+                    live = false;
+#pragma unroll
+                    for (int h = 0; h < L / 4; ++h) {
+                        uint64_t Mh[4], Gh[4];
+                        const bool any = eval_bytes<L == 8 ? 9 : 8, NEG, COUNT>(
+                            reinterpret_cast<const unsigned char *>(tile) + 256 * h, k - 1, d.colidx, hb + ii,
+                            hv[1], hv[2], lane, hvalid[h], Mh, Gh, steps);
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            M[4 * h + s] = any ? Mh[s] : 0;
+                            G[4 * h + s] = any ? Gh[s] : 0;
+                        }
+                        if (any) {
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) {
+                                pm += __popcll(Mh[s]);
+                                pg += __popcll(Gh[s]);
+                            }
+                        }
                     }
                 } else if constexpr (STAGE == STAGE_CODES) {
                     static_assert(L >= 2, "rank codes are staged for 2 or 4 sub-tiles");
@@ -1183,7 +1502,6 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                     eval_direct<L, NEG, COUNT>(d.X + row0 + lane, d.ld, sub, k - 1, c, d.fill,
                                                (d.flags & kFlagSubst) != 0, valid, M, G, steps);
                 }
-                int32_t pm = 0, pg = 0;
                 if (live) {
 #pragma unroll
                     for (int s = 0; s < L; ++s) {
@@ -1290,7 +1608,7 @@ k_eval_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs, const Item *__
         const Item it = items[id];
         const ReqDesc d = descs[it.req];
         const bool neg = (d.flags & kFlagNeg) != 0;
-        if constexpr (L == 4) {
+        if constexpr (L == 4) {  // (byte codes in batches: four sub-tiles)
             if (d.flags & kFlagBytes) {
                 if (neg) run_item<L, true, STAGE_BYTES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
                 else run_item<L, false, STAGE_BYTES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
@@ -1349,9 +1667,10 @@ const void *eval_pick_codes(int L)
 template <bool COUNT>
 const void *eval_pick(int L, bool neg, int staging)
 {
-    if (staging == STAGE_BYTES) {
-        if (L != 4) return nullptr;  // byte codes hold four sub-tiles per lane word
-        return neg ? eval_ptr<4, true, STAGE_BYTES, COUNT>() : eval_ptr<4, false, STAGE_BYTES, COUNT>();
+    if (staging == STAGE_BYTES) {  // one or two 256-row groups per chunk
+        if (L == 4) return neg ? eval_ptr<4, true, STAGE_BYTES, COUNT>() : eval_ptr<4, false, STAGE_BYTES, COUNT>();
+        if (L == 8) return neg ? eval_ptr<8, true, STAGE_BYTES, COUNT>() : eval_ptr<8, false, STAGE_BYTES, COUNT>();
+        return nullptr;
     }
     if (staging == STAGE_CODES) return neg ? eval_pick_codes<true, COUNT>(L) : eval_pick_codes<false, COUNT>(L);
     if (staging == STAGE_LDS)
@@ -1415,7 +1734,8 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
     if (d.n <= 0) return hipSuccess;
     {
         const int threads = 256;
-        hipLaunchKernelGGL(k_prep, dim3((d.n + threads - 1) / threads), dim3(threads), 0, s, d, heads);
+        const int per_block = threads / kWave;  // one wave per individual
+        hipLaunchKernelGGL(k_prep, dim3((d.n + per_block - 1) / per_block), dim3(threads), 0, s, d, heads);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

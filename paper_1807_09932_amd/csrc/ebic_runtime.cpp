@@ -85,11 +85,15 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
     const bool have_bytes = m.dev.B && ((flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
     // Byte codes hold four sub-tiles per lane word; without them for this
     // mode, the 16-bit codes (or the FP32 tile) at the same shape.
+    // (one or two 256-row groups per chunk: L = 4 or 8; other stagings take
+    // at most 4).
     if (cfg.staging == STAGE_BYTES) {
-        if (have_bytes) cfg.L = 4;
+        if (have_bytes) cfg.L = cfg.L >= 8 ? 8 : 4;
         else cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
     }
+    if (cfg.staging == STAGE_BYTES && cfg.L == 8 && !fits(cfg)) cfg.L = 4;
     if (cfg.staging == STAGE_BYTES && !fits(cfg)) cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
+    if (cfg.staging != STAGE_BYTES) cfg.L = std::min(cfg.L, 4);
     // Rank codes need codes for this mode and at least two sub-tiles.
     if (cfg.staging == STAGE_CODES && (!have_codes || cfg.L < 2)) cfg.staging = STAGE_LDS;
     // An FP32 tile that does not fit: the codes' tile (half the bytes) at the
@@ -383,7 +387,7 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             // exclude mode may use them only if no cell is missing.
             int32_t has_nan = 1;
             if (cols <= kMaxByteCols) {
-                m.dev.ldb = (rows + 255) / 256 * 256;
+                m.dev.ldb = (rows + 511) / 512 * 512;  // whole chunks of two 256-row groups
                 const size_t bbytes = (size_t)m.dev.ldb * cols;
                 m.B = static_cast<uint8_t *>(ctx_alloc(ctx, bbytes + 256));
                 m.bytes += bbytes + 256;

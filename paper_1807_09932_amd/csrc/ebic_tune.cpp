@@ -42,10 +42,10 @@ static TuneKey batch_key(int64_t total_ind, int64_t mean_rows, int32_t max_cols)
 }
 
 // Defaults measured on MI355X for the 436,444 x 64 workload: the byte rank
-// codes (four 64-row sub-tiles per lane word) up to 128 columns, sixteen
-// waves per block, groups of 400 individuals; wider matrices stage the
-// 16-bit rank codes. A request without codes for its mode falls back at
-// launch.
+// codes (four 64-row sub-tiles per lane word, two words per chunk) up to
+// 128 columns, sixteen waves per block, groups of 200 individuals; wider
+// matrices stage the 16-bit rank codes. A request without codes for its
+// mode falls back at launch.
 static int32_t default_L(int32_t cols) { return cols <= 64 ? 4 : (cols <= 128 ? 2 : 1); }
 
 LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
@@ -57,8 +57,10 @@ LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
     c.L = default_L(cols);
     c.staging = STAGE_LDS;
     if (cols <= kMaxByteCols) {
+        // Two 256-row groups of byte codes per chunk, groups of 200.
         c.staging = STAGE_BYTES;
-        c.L = 4;
+        c.L = 8;
+        c.P = std::max(1, std::min(n, 200));
     } else if (cols <= kMaxCodeCols) {
         // The 16-bit rank codes' tile keeps two sub-tiles in LDS.
         c.staging = STAGE_CODES;
@@ -222,7 +224,7 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
             ctx->override_cfg = LaunchCfg();
             return;
         }
-        if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 4) ||
+        if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 4 || tiles_per_wave == 8) ||
             waves_per_block < 1 || waves_per_block > 16 || individuals_per_group < 1 ||
             !(staging == STAGE_LDS || staging == STAGE_DIRECT || staging == STAGE_CODES ||
               staging == STAGE_BYTES) ||
@@ -283,7 +285,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                 if (!done.insert(key).second) continue;
                 LaunchCfg best;
                 float best_ms = INFINITY;
-                for (int L : {1, 2, 4})
+                for (int L : {1, 2, 4, 8})
                     for (int W : {4, 8, 16})
                         for (int P : {200, 400, 800, 1600})
                             for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT, (int)STAGE_CODES,
@@ -297,7 +299,8 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                                     tile_lds_bytes(L, cols, stg) + count_lds_bytes(c.P) > ctx->lds_per_block)
                                     continue;
                                 if (stg == STAGE_CODES && (L < 2 || !have_codes)) continue;
-                                if (stg == STAGE_BYTES && (L != 4 || !have_bytes)) continue;
+                                if (stg == STAGE_BYTES && (L < 4 || !have_bytes)) continue;
+                                if (L == 8 && stg != STAGE_BYTES) continue;  // eight sub-tiles: byte codes only
                                 set_override(c);
                                 const float ms = time_ms(
                                     [&] {

@@ -100,6 +100,7 @@ SHAPES = [  # tiles_per_wave, waves_per_block, individuals_per_group, staging, b
     # staging 3: the byte rank codes (include mode here; exclude mode falls
     # back, the matrix has missing cells)
     (4, 8, 64, 3, 0), (4, 16, 1000, 3, 0), (4, 3, 33, 3, 1), (4, 5, 200, 3, 7), (2, 8, 100, 3, 0),
+    (8, 16, 400, 3, 0), (8, 4, 33, 3, 2), (8, 7, 150, 3, 5),
 ]
 
 
@@ -175,17 +176,19 @@ def test_rank_codes_special_values(ctx, ncols, L):
         ctx.release(mat)
 
 
+@pytest.mark.parametrize("tiles", [4, 8])
 @pytest.mark.parametrize("ncols", [2, 9, 64, 128])
 @pytest.mark.parametrize("rows", [1, 255, 257, 777, 3001])
-def test_byte_codes_special_values(ctx, ncols, rows):
+def test_byte_codes_special_values(ctx, ncols, rows, tiles):
     """Byte rank-code staging (four rows per 32-bit lane word) on the special
     values (+-inf, +-0, denormals, ties): both modes and both trend settings
     on a matrix without missing cells, where both modes stage the byte
     codes; with missing cells, include mode stages them and exclude mode
     falls back to another staging. Individuals of up to 30 columns reach
-    past the 8-column window."""
+    past the 8-column window. tiles = 64-row sub-tiles per chunk (one or two
+    256-row groups)."""
     from paper_1807_09932_amd import ebic
-    rng = np.random.default_rng(1100 + 7 * ncols + rows)
+    rng = np.random.default_rng(1100 + 7 * ncols + rows + tiles)
     X = _special(rng, (rows, ncols))
     Xn = X.copy()
     Xn[rng.random(X.shape) < 0.04] = np.float32(np.nan)
@@ -193,12 +196,14 @@ def test_byte_codes_special_values(ctx, ncols, rows):
     for name, A in (("no missing", X), ("missing", Xn)):
         mat = ctx.upload(A, fill=-0.0)
         try:
-            ctx.set_launch_shape(4, 8, 64, ebic.STAGE_BYTES, 0)
-            planned = ebic.ebic_plan_shape(ctx.handle, mat, offs.size - 1, int(offs[-1]))[3]
-            assert (planned == ebic.STAGE_BYTES) == (not np.isnan(A).any())
+            ctx.set_launch_shape(tiles, 8, 64, ebic.STAGE_BYTES, 0)
+            plan = ebic.ebic_plan_shape(ctx.handle, mat, offs.size - 1, int(offs[-1]))
+            assert (plan[3] == ebic.STAGE_BYTES) == (not np.isnan(A).any())
+            if plan[3] == ebic.STAGE_BYTES:
+                assert plan[0] == tiles
             for include in (False, True):
                 for negative in (False, True):
-                    announce("byte codes", rows, ncols, name, include, negative)
+                    announce("byte codes", rows, ncols, tiles, name, include, negative)
                     got = gpu_eval(ctx, mat, offs, cols, include=include, negative=negative)
                     want = oracle_eval(A, offs, cols, include=include, negative=negative, fill=-0.0)
                     assert_same(got, want, f"bytes {rows}x{ncols} {name} include={include} "
@@ -310,7 +315,7 @@ def test_error_paths(ctx):
     assert e.value.status == ebic.EBIC_ENOENT
 
 
-@pytest.mark.parametrize("tiles_per_wave,staging", [(1, 0), (2, 0), (4, 0), (2, 2), (4, 2), (4, 3)])
+@pytest.mark.parametrize("tiles_per_wave,staging", [(1, 0), (2, 0), (4, 0), (2, 2), (4, 2), (4, 3), (8, 3)])
 def test_measurement_variant_agrees(ctx, tiles_per_wave, staging):
     """The step-counting kernel variant (profiling mode 2) computes the same
     outputs as the timed one, and counts a positive number of steps."""
