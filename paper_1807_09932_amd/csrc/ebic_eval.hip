@@ -833,21 +833,29 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
 // second group at +256): the same chains for both groups in one instruction
 // stream. A column's two words share one address, the two groups' operations
 // are independent (they hide each other's latency), and the window ends when
-// no row of either group is left.
+// no row of either group is left. Here the reference carried from column to
+// column is q = 0x80808080 - x_{j-1} (each byte in 1..128, so again no
+// borrow), which needs fm and nf but not fH:
+//   D = (t_j ^ fm) + q       = (x_j | 0x80..) - x_{j-1}
+//   q = (t_j ^ nf) + 0x80808081 = 0x80808080 - x_j
+// Chunks whose rows hold no two equal values (tie flags computed at upload)
+// skip the tie detection and the tie chain.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kByteHiP1 = 0x80808081u;
+
 #define B2_LOAD(t, w)                                                          \
     "v_lshl_add_u32 %[ad], %[" w "], 9, %[base]\n\t"                           \
     "ds_read_b32 %[" t "a], %[ad]\n\t"                                         \
     "ds_read_b32 %[" t "b], %[ad] offset:256\n\t"
-#define B2_PAIR(ta, tb, FHA, FHB, NFA, NFB, NXA, NXB, AOA, AOB, AIA, AIB)      \
-    "v_xad_u32 %[Da], %[" ta "a], " FHA ", %[" NXA "]\n\t"                     \
-    "v_xad_u32 %[Db], %[" ta "b], " FHB ", %[" NXB "]\n\t"                     \
-    "v_xad_u32 %[" NXA "], %[" ta "a], " NFA ", 1\n\t"                         \
-    "v_xad_u32 %[" NXB "], %[" ta "b], " NFB ", 1\n\t"                         \
-    "v_xad_u32 %[Ea], %[" tb "a], " FHA ", %[" NXA "]\n\t"                     \
-    "v_xad_u32 %[Eb], %[" tb "b], " FHB ", %[" NXB "]\n\t"                     \
-    "v_xad_u32 %[" NXA "], %[" tb "a], " NFA ", 1\n\t"                         \
-    "v_xad_u32 %[" NXB "], %[" tb "b], " NFB ", 1\n\t"                         \
+#define B2_PAIR(ta, tb, FMA, FMB, NFA, NFB, AOA, AOB, AIA, AIB)                \
+    "v_xad_u32 %[Da], %[" ta "a], " FMA ", %[qa]\n\t"                          \
+    "v_xad_u32 %[Db], %[" ta "b], " FMB ", %[qb]\n\t"                          \
+    "v_xad_u32 %[qa], %[" ta "a], " NFA ", %[hp]\n\t"                          \
+    "v_xad_u32 %[qb], %[" ta "b], " NFB ", %[hp]\n\t"                          \
+    "v_xad_u32 %[Ea], %[" tb "a], " FMA ", %[qa]\n\t"                          \
+    "v_xad_u32 %[Eb], %[" tb "b], " FMB ", %[qb]\n\t"                          \
+    "v_xad_u32 %[qa], %[" tb "a], " NFA ", %[hp]\n\t"                          \
+    "v_xad_u32 %[qb], %[" tb "b], " NFB ", %[hp]\n\t"                          \
     "v_bitop3_b32 %[" AOA "], %[" AIA "], %[Da], %[Ea] bitop3:0x80\n\t"        \
     "v_bitop3_b32 %[" AOB "], %[" AIB "], %[Db], %[Eb] bitop3:0x80\n\t"
 #define B2_EXIT_LAST(u, L) "s_cmp_le_i32 %[last], " u "\n\t" "s_cbranch_scc1 " L "\n\t"
@@ -858,92 +866,121 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
     "s_cbranch_scc0 " L "\n\t" B2_EXIT_LAST(u, L)
 // Columns 2..7 (t2, t3 hold or are loading columns 2 and 3; loads run two
 // columns ahead; two loads per column).
-#define B2_WINDOW(FHA, FHB, NFA, NFB, AA, AB, IA, IB, L)                       \
+#define B2_WINDOW(FMA, FMB, NFA, NFB, AA, AB, IA, IB, L)                       \
     B2_LOAD("t0", "w4") B2_LOAD("t1", "w5") "s_waitcnt lgkmcnt(4)\n\t"         \
-    B2_PAIR("t2", "t3", FHA, FHB, NFA, NFB, "nxa", "nxb", AA, AB, IA, IB)      \
+    B2_PAIR("t2", "t3", FMA, FMB, NFA, NFB, AA, AB, IA, IB)                    \
     B2_EXIT_LAST("3", L)                                                       \
     B2_LOAD("t2", "w6") B2_LOAD("t3", "w7") "s_waitcnt lgkmcnt(4)\n\t"         \
-    B2_PAIR("t0", "t1", FHA, FHB, NFA, NFB, "nxa", "nxb", AA, AB, AA, AB)      \
+    B2_PAIR("t0", "t1", FMA, FMB, NFA, NFB, AA, AB, AA, AB)                    \
     B2_EXIT("5", AA, AB, L)                                                    \
     "s_waitcnt lgkmcnt(0)\n\t"                                                 \
-    B2_PAIR("t2", "t3", FHA, FHB, NFA, NFB, "nxa", "nxb", AA, AB, AA, AB)
+    B2_PAIR("t2", "t3", FMA, FMB, NFA, NFB, AA, AB, AA, AB)
 #define B2_SCRATCH                                                             \
     [t0a] "=&v"(t0a), [t0b] "=&v"(t0b), [t1a] "=&v"(t1a), [t1b] "=&v"(t1b),    \
         [t2a] "=&v"(t2a), [t2b] "=&v"(t2b), [t3a] "=&v"(t3a), [t3b] "=&v"(t3b), \
         [ad] "=&v"(ad), [Da] "=&v"(Da), [Db] "=&v"(Db), [Ea] "=&v"(Ea), [Eb] "=&v"(Eb), \
-        [nxa] "=&v"(nxa), [nxb] "=&v"(nxb), [tmp] "=&s"(tmp)
+        [qa] "=&v"(qa), [qb] "=&v"(qb), [tmp] "=&s"(tmp)
 #define B2_COLS                                                                \
     [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), \
-        [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last)
-// First pair of a group (X = a or b): falling, tied and oriented words; the
-// two groups' operations alternate.
+        [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last), \
+        [hp] "s"(kByteHiP1)
+// First pair of a group (X = a or b); the two groups' operations alternate.
+// D: bit 7 where t1 >= t0; E: where t0 >= t1 (only for the tie test).
 #define B2_F1(X) "v_or_b32_e32 %[D" X "], 0x80808080, %[t1" X "]\n\t"
 #define B2_F2(X) "v_sub_u32_e32 %[D" X "], %[D" X "], %[t0" X "]\n\t"
 #define B2_F3(X) "v_sub_u32_e32 %[E" X "], 0x1010100, %[D" X "]\n\t"
 #define B2_F4(X) "v_bitop3_b32 %[tied" X "], %[D" X "], %[E" X "], %[hv" X "] bitop3:0x80\n\t"
-#define B2_F5(X) "v_bitop3_b32 %[fall" X "], %[D" X "], %[E" X "], %[hv" X "] bitop3:0x08\n\t"
+#define B2_F5(X) "v_bfi_b32 %[fall" X "], %[D" X "], 0, %[hv" X "]\n\t"
 #define B2_F6(X) "v_lshrrev_b32_e32 %[E" X "], 7, %[fall" X "]\n\t"
-#define B2_F7(X) "v_sub_u32_e32 %[E" X "], %[fall" X "], %[E" X "]\n\t"
-#define B2_F8(X) "v_or_b32_e32 %[fH" X "], 0x80808080, %[E" X "]\n\t"
-#define B2_F9(X) "v_not_b32_e32 %[nf" X "], %[E" X "]\n\t"
-#define B2_F10(X) "v_xad_u32 %[nx" X "], %[t1" X "], %[nf" X "], 1\n\t"
-#define B2_FIRST                                                               \
-    B2_F1("a") B2_F1("b") B2_F2("a") B2_F2("b") B2_F3("a") B2_F3("b")          \
-    B2_F4("a") B2_F4("b") B2_F5("a") B2_F5("b") B2_F6("a") B2_F6("b")          \
-    B2_F7("a") B2_F7("b") B2_F8("a") B2_F8("b") B2_F9("a") B2_F9("b")          \
-    B2_F10("a") B2_F10("b")
+#define B2_F7(X) "v_sub_u32_e32 %[fm" X "], %[fall" X "], %[E" X "]\n\t"
+#define B2_F8(X) "v_not_b32_e32 %[nf" X "], %[fm" X "]\n\t"
+#define B2_F9(X) "v_xad_u32 %[q" X "], %[t1" X "], %[nf" X "], %[hp]\n\t"
+#define B2_AB(F) F("a") F("b")
+#define B2_FIRST_TIES                                                          \
+    B2_AB(B2_F1) B2_AB(B2_F2) B2_AB(B2_F3) B2_AB(B2_F4) B2_AB(B2_F5)           \
+    B2_AB(B2_F6) B2_AB(B2_F7) B2_AB(B2_F8) B2_AB(B2_F9)
+#define B2_FIRST_NOTIES                                                        \
+    B2_AB(B2_F1) B2_AB(B2_F2) B2_AB(B2_F5) B2_AB(B2_F6) B2_AB(B2_F7)           \
+    B2_AB(B2_F8) B2_AB(B2_F9)
 
 // Both chains on both groups through column min(last, 7); outputs per
-// group as in by_neg. (Waits count LDS operations; they start and end with
-// lgkmcnt(0).)
+// group as in by_neg (tied = 0 without TIES). Waits count LDS operations;
+// the sequence starts and ends with lgkmcnt(0).
+template <bool TIES>
 __device__ __forceinline__ void by2_neg(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hva,
                                         uint32_t hvb, uint32_t &alivea, uint32_t &aliveb, uint32_t &falla,
                                         uint32_t &fallb, uint32_t &tieda, uint32_t &tiedb)
 {
-    uint32_t t0a, t0b, t1a, t1b, t2a, t2b, t3a, t3b, ad, Da, Db, Ea, Eb, nxa, nxb, fHa, fHb, nfa, nfb;
+    uint32_t t0a, t0b, t1a, t1b, t2a, t2b, t3a, t3b, ad, Da, Db, Ea, Eb, qa, qb, fma, fmb, nfa, nfb;
     uint64_t tmp, tany;
-    asm volatile(
-        "s_waitcnt lgkmcnt(0)\n\t"
-        B2_LOAD("t0", "w0") B2_LOAD("t1", "w1") B2_LOAD("t2", "w2") B2_LOAD("t3", "w3")
-        "s_waitcnt lgkmcnt(4)\n\t"
-        B2_FIRST
-        "v_or_b32_e32 %[Da], %[tieda], %[tiedb]\n\t"
-        "v_cmp_ne_u32_e64 %[tany], 0, %[Da]\n\t"
-        "s_cmp_lt_i32 %[last], 2\n\t"
-        "s_cbranch_scc1 6f\n\t"
-        B2_WINDOW("%[fHa]", "%[fHb]", "%[nfa]", "%[nfb]", "alivea", "aliveb", "hva", "hvb", "2f")
-        "2:\n\t"
-        "s_waitcnt lgkmcnt(0)\n\t"
-        // The rows tied on the first pair: the <= chain from column 1.
-        "s_cmp_lg_u64 %[tany], 0\n\t"
-        "s_cbranch_scc0 4f\n\t"
-        B2_LOAD("t1", "w1") B2_LOAD("t2", "w2") B2_LOAD("t3", "w3")
-        "s_waitcnt lgkmcnt(4)\n\t"
-        "v_xad_u32 %[nxa], %[t1a], %[hi], 1\n\t"
-        "v_xad_u32 %[nxb], %[t1b], %[hi], 1\n\t"
-        B2_WINDOW("-1", "-1", "%[hi]", "%[hi]", "tieda", "tiedb", "tieda", "tiedb", "3f")
-        "3:\n\t"
-        "s_waitcnt lgkmcnt(0)\n\t"
-        "s_branch 5f\n\t"
-        "6:\n\t"  // two columns: every row in range is on its chain
-        "v_mov_b32_e32 %[alivea], %[hva]\n\t"
-        "v_mov_b32_e32 %[aliveb], %[hvb]\n\t"
-        "4:\n\t"
-        "v_mov_b32_e32 %[tieda], 0\n\t"
-        "v_mov_b32_e32 %[tiedb], 0\n\t"
-        "5:"
-        : B2_SCRATCH, [fHa] "=&v"(fHa), [fHb] "=&v"(fHb), [nfa] "=&v"(nfa), [nfb] "=&v"(nfb),
-          [alivea] "=&v"(alivea), [aliveb] "=&v"(aliveb), [falla] "=&v"(falla), [fallb] "=&v"(fallb),
-          [tieda] "=&v"(tieda), [tiedb] "=&v"(tiedb), [tany] "=&s"(tany)
-        : B2_COLS, [hva] "v"(hva), [hvb] "v"(hvb), [hi] "s"(kByteHi)
-        : "scc", "memory");
+    if constexpr (TIES) {
+        asm volatile(
+            "s_waitcnt lgkmcnt(0)\n\t"
+            B2_LOAD("t0", "w0") B2_LOAD("t1", "w1") B2_LOAD("t2", "w2") B2_LOAD("t3", "w3")
+            "s_waitcnt lgkmcnt(4)\n\t"
+            B2_FIRST_TIES
+            "v_or_b32_e32 %[Da], %[tieda], %[tiedb]\n\t"
+            "v_cmp_ne_u32_e64 %[tany], 0, %[Da]\n\t"
+            "s_cmp_lt_i32 %[last], 2\n\t"
+            "s_cbranch_scc1 6f\n\t"
+            B2_WINDOW("%[fma]", "%[fmb]", "%[nfa]", "%[nfb]", "alivea", "aliveb", "hva", "hvb", "2f")
+            "2:\n\t"
+            "s_waitcnt lgkmcnt(0)\n\t"
+            // The rows tied on the first pair: the <= chain from column 1
+            // (every code mirrored: fm = 0x7F7F7F7F, nf = 0x80808080).
+            "s_cmp_lg_u64 %[tany], 0\n\t"
+            "s_cbranch_scc0 4f\n\t"
+            B2_LOAD("t1", "w1") B2_LOAD("t2", "w2") B2_LOAD("t3", "w3")
+            "v_mov_b32_e32 %[fma], 0x7f7f7f7f\n\t"
+            "v_mov_b32_e32 %[nfa], 0x80808080\n\t"
+            "s_waitcnt lgkmcnt(4)\n\t"
+            "v_xad_u32 %[qa], %[t1a], %[nfa], %[hp]\n\t"
+            "v_xad_u32 %[qb], %[t1b], %[nfa], %[hp]\n\t"
+            B2_WINDOW("%[fma]", "%[fma]", "%[nfa]", "%[nfa]", "tieda", "tiedb", "tieda", "tiedb", "3f")
+            "3:\n\t"
+            "s_waitcnt lgkmcnt(0)\n\t"
+            "s_branch 5f\n\t"
+            "6:\n\t"  // two columns: every row in range is on its chain
+            "v_mov_b32_e32 %[alivea], %[hva]\n\t"
+            "v_mov_b32_e32 %[aliveb], %[hvb]\n\t"
+            "4:\n\t"
+            "v_mov_b32_e32 %[tieda], 0\n\t"
+            "v_mov_b32_e32 %[tiedb], 0\n\t"
+            "5:"
+            : B2_SCRATCH, [fma] "=&v"(fma), [fmb] "=&v"(fmb), [nfa] "=&v"(nfa), [nfb] "=&v"(nfb),
+              [alivea] "=&v"(alivea), [aliveb] "=&v"(aliveb), [falla] "=&v"(falla), [fallb] "=&v"(fallb),
+              [tieda] "=&v"(tieda), [tiedb] "=&v"(tiedb), [tany] "=&s"(tany)
+            : B2_COLS, [hva] "v"(hva), [hvb] "v"(hvb)
+            : "scc", "memory");
+    } else {
+        asm volatile(
+            "s_waitcnt lgkmcnt(0)\n\t"
+            B2_LOAD("t0", "w0") B2_LOAD("t1", "w1") B2_LOAD("t2", "w2") B2_LOAD("t3", "w3")
+            "s_waitcnt lgkmcnt(4)\n\t"
+            B2_FIRST_NOTIES
+            "s_cmp_lt_i32 %[last], 2\n\t"
+            "s_cbranch_scc1 6f\n\t"
+            B2_WINDOW("%[fma]", "%[fmb]", "%[nfa]", "%[nfb]", "alivea", "aliveb", "hva", "hvb", "2f")
+            "2:\n\t"
+            "s_waitcnt lgkmcnt(0)\n\t"
+            "s_branch 5f\n\t"
+            "6:\n\t"
+            "v_mov_b32_e32 %[alivea], %[hva]\n\t"
+            "v_mov_b32_e32 %[aliveb], %[hvb]\n\t"
+            "5:"
+            : B2_SCRATCH, [fma] "=&v"(fma), [fmb] "=&v"(fmb), [nfa] "=&v"(nfa), [nfb] "=&v"(nfb),
+              [alivea] "=&v"(alivea), [aliveb] "=&v"(aliveb), [falla] "=&v"(falla), [fallb] "=&v"(fallb)
+            : B2_COLS, [hva] "v"(hva), [hvb] "v"(hvb)
+            : "scc", "memory");
+        tieda = tiedb = 0;
+    }
 }
 
-// The >= chain alone on both groups.
+// The >= chain alone on both groups (fm = 0, nf = ~0).
 __device__ __forceinline__ void by2_pos(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hva,
                                         uint32_t hvb, uint32_t &alivea, uint32_t &aliveb)
 {
-    uint32_t t0a, t0b, t1a, t1b, t2a, t2b, t3a, t3b, ad, Da, Db, Ea, Eb, nxa, nxb;
+    uint32_t t0a, t0b, t1a, t1b, t2a, t2b, t3a, t3b, ad, Da, Db, Ea, Eb, qa, qb;
     uint64_t tmp;
     asm volatile(
         "s_waitcnt lgkmcnt(0)\n\t"
@@ -955,15 +992,15 @@ __device__ __forceinline__ void by2_pos(uint32_t base, const int32_t (&w)[kWin],
         "v_sub_u32_e32 %[Db], %[Db], %[t0b]\n\t"
         "v_and_b32_e32 %[alivea], %[Da], %[hva]\n\t"
         "v_and_b32_e32 %[aliveb], %[Db], %[hvb]\n\t"
-        "v_sub_u32_e32 %[nxa], 0, %[t1a]\n\t"
-        "v_sub_u32_e32 %[nxb], 0, %[t1b]\n\t"
+        "v_xad_u32 %[qa], %[t1a], -1, %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t1b], -1, %[hp]\n\t"
         "s_cmp_lt_i32 %[last], 2\n\t"
         "s_cbranch_scc1 2f\n\t"
-        B2_WINDOW("%[hi]", "%[hi]", "-1", "-1", "alivea", "aliveb", "alivea", "aliveb", "2f")
+        B2_WINDOW("0", "0", "-1", "-1", "alivea", "aliveb", "alivea", "aliveb", "2f")
         "2:\n\t"
         "s_waitcnt lgkmcnt(0)"
         : B2_SCRATCH, [alivea] "=&v"(alivea), [aliveb] "=&v"(aliveb)
-        : B2_COLS, [hva] "v"(hva), [hvb] "v"(hvb), [hi] "s"(kByteHi)
+        : B2_COLS, [hva] "v"(hva), [hvb] "v"(hvb)
         : "scc", "memory");
 }
 
@@ -974,7 +1011,6 @@ __device__ __forceinline__ void by2_pos(uint32_t base, const int32_t (&w)[kWin],
 #undef B2_WINDOW
 #undef B2_SCRATCH
 #undef B2_COLS
-#undef B2_FIRST
 #undef B2_F1
 #undef B2_F2
 #undef B2_F3
@@ -984,7 +1020,9 @@ __device__ __forceinline__ void by2_pos(uint32_t base, const int32_t (&w)[kWin],
 #undef B2_F7
 #undef B2_F8
 #undef B2_F9
-#undef B2_F10
+#undef B2_AB
+#undef B2_FIRST_TIES
+#undef B2_FIRST_NOTIES
 
 // Wave-wide masks of the four sub-tiles: bit l of m[b] is bit 7 of byte b
 // of lane l's word (one SDWA compare per byte). The trailing wait states
@@ -1046,7 +1084,7 @@ __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, 
 template <int SH, bool NEG, bool COUNT>
 __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ tile, int32_t last,
                                            const int32_t *__restrict__ colidx,
-                                           const IndHead *__restrict__ hp, const int4 &w03, const int4 &w47,
+                                           const int32_t *__restrict__ hbegin, const int4 &w03, const int4 &w47,
                                            int lane, uint32_t hv, uint64_t (&M)[4], uint64_t (&G)[4],
                                            uint64_t &steps)
 {
@@ -1089,7 +1127,7 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
     }
     if (last >= kWin) {
         // The columns past the window (the CSR start is read only here).
-        const int32_t *c = colidx + hp->begin;
+        const int32_t *c = colidx + *hbegin;
         if constexpr (NEG) {
             const uint32_t fm = fall - (fall >> 7);
             by_tail<SH, COUNT>(base, c, w, last, fm | kByteHi, ~fm, alive, steps);
@@ -1134,11 +1172,11 @@ __device__ __forceinline__ void by2_window_ref(const unsigned char *__restrict__
 // One individual on a chunk of two 256-row groups of byte codes (eight
 // 64-row sub-tiles; a column is 512 bytes). hva, hvb: the in-range rows of
 // each group. Returns false, and leaves M and G unset, when no row matches.
-template <bool NEG, bool COUNT>
+template <bool NEG, bool COUNT, bool TIES>
 __device__ __forceinline__ bool eval_bytes2(const unsigned char *__restrict__ tile, int32_t last,
                                             const int32_t *__restrict__ colidx,
-                                            const IndHead *__restrict__ hp, const int4 &w03, const int4 &w47,
-                                            int lane, uint32_t hva, uint32_t hvb, uint64_t (&M)[8],
+                                            const int32_t *__restrict__ hbegin, const int4 &w03,
+                                            const int4 &w47, int lane, uint32_t hva, uint32_t hvb, uint64_t (&M)[8],
                                             uint64_t (&G)[8], uint64_t &steps)
 {
     const unsigned char *base = tile + 4 * lane;
@@ -1187,12 +1225,13 @@ __device__ __forceinline__ bool eval_bytes2(const unsigned char *__restrict__ ti
         }
     } else {
         const uint32_t b = lds_addr(base);
-        if constexpr (NEG) by2_neg(b, w, last, hva, hvb, alive[0], alive[1], fall[0], fall[1], tied[0], tied[1]);
+        if constexpr (NEG)
+            by2_neg<TIES>(b, w, last, hva, hvb, alive[0], alive[1], fall[0], fall[1], tied[0], tied[1]);
         else by2_pos(b, w, last, hva, hvb, alive[0], alive[1]);
     }
     if (last >= kWin) {
         // The columns past the window (the CSR start is read only here).
-        const int32_t *c = colidx + hp->begin;
+        const int32_t *c = colidx + *hbegin;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if constexpr (NEG) {
@@ -1328,11 +1367,13 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
     const uint8_t *src0 = d.B + (int64_t)(idx0 >> PL) * d.ldb + 16 * (idx0 & ((1 << PL) - 1));
     const uint8_t *src1 = d.B + (int64_t)(idx1 >> PL) * d.ldb + 16 * (idx1 & ((1 << PL) - 1));
     uint4 pre0 = {0, 0, 0, 0}, pre1 = {0, 0, 0, 0};
+    int32_t tie_pre = 1;  // the next chunk's tie flag, loaded with its bytes
     if constexpr (STAGE == STAGE_BYTES) {
         if (t0 < t1) {
             const int64_t r0 = t0 * kWave;
             if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r0);
             if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r0);
+            tie_pre = d.T[r0 >> 9];
         }
     }
 
@@ -1368,10 +1409,13 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             }
             __syncthreads();
         }
-        // Byte codes: bit 7 of the bytes of the rows in range, per 256-row group.
+        // Byte codes: bit 7 of the bytes of the rows in range, per 256-row
+        // group, and whether a row of the chunk holds two equal values.
         uint32_t hvalid[L >= 4 ? L / 4 : 1] = {};
+        bool ties = true;
         if constexpr (STAGE == STAGE_BYTES) {
             static_assert(L == 4 || L == 8, "byte codes hold four sub-tiles per lane word");
+            ties = tie_pre != 0;
             // The L * 64 bytes of every column for rows [row0, row0 + 64 L),
             // in their interleaved order; rows outside the item or the
             // matrix are left out of `hvalid` instead.
@@ -1394,6 +1438,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                 const int64_t r1 = row0 + L * kWave;
                 if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r1);
                 if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r1);
+                tie_pre = d.T[r1 >> 9];
             }
         }
         if constexpr (STAGE == STAGE_LDS) {
@@ -1444,9 +1489,12 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                 int32_t pm = 0, pg = 0;
                 if constexpr (STAGE == STAGE_BYTES && L == 8) {
                     live = false;
-                    const bool any = eval_bytes2<NEG, COUNT>(reinterpret_cast<const unsigned char *>(tile),
-                                                             k - 1, d.colidx, hb + ii, hv[1], hv[2], lane,
-                                                             hvalid[0], hvalid[L / 4 - 1], M, G, steps);
+                    const auto *tl = reinterpret_cast<const unsigned char *>(tile);
+                    const bool any =
+                        ties ? eval_bytes2<NEG, COUNT, true>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2], lane,
+                                                             hvalid[0], hvalid[L / 4 - 1], M, G, steps)
+                             : eval_bytes2<NEG, COUNT, false>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2], lane,
+                                                              hvalid[0], hvalid[L / 4 - 1], M, G, steps);
                     if (any) {
 #pragma unroll
                         for (int s = 0; s < L; ++s) {
@@ -1463,7 +1511,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                     for (int h = 0; h < L / 4; ++h) {
                         uint64_t Mh[4], Gh[4];
                         const bool any = eval_bytes<L == 8 ? 9 : 8, NEG, COUNT>(
-                            reinterpret_cast<const unsigned char *>(tile) + 256 * h, k - 1, d.colidx, hb + ii,
+                            reinterpret_cast<const unsigned char *>(tile) + 256 * h, k - 1, d.colidx, &hb[ii].begin,
                             hv[1], hv[2], lane, hvalid[h], Mh, Gh, steps);
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
@@ -1705,11 +1753,16 @@ size_t tile_lds_bytes(int32_t L, int32_t cols, int32_t staging) { return tile_by
 
 size_t count_lds_bytes(int32_t P) { return count_bytes_of(P); }
 
+size_t item_lds_bytes(int32_t L, int32_t cols, int32_t staging, int32_t P)
+{
+    return tile_bytes_of(L, cols, staging) + count_bytes_of(P);
+}
+
 int eval_occupancy(const LaunchCfg &cfg, int32_t cols, uint32_t flags)
 {
     const void *k = eval_kernel(cfg.L, flags, cfg.staging, false);
     if (!k) return 0;
-    const size_t lds = tile_bytes_of(cfg.L, cols, cfg.staging) + count_bytes_of(cfg.P);
+    const size_t lds = item_lds_bytes(cfg.L, cols, cfg.staging, cfg.P);
     int blocks = 0;
     if (set_lds(k, lds) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, cfg.W * kWave, lds) != hipSuccess)
@@ -1743,7 +1796,7 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
     if (!k) return hipErrorInvalidValue;
     const int32_t n_tiles = (int32_t)((d.rows + 63) / 64);
     const int32_t groups = (d.n + cfg.P - 1) / cfg.P;
-    const size_t lds = tile_bytes_of(cfg.L, d.cols, cfg.staging) + count_bytes_of(cfg.P);
+    const size_t lds = item_lds_bytes(cfg.L, d.cols, cfg.staging, cfg.P);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     ReqDesc dd = d;

@@ -62,6 +62,7 @@ struct DevMatrix {
     const uint16_t *C = nullptr;   // rank codes of X (same layout), or null
     const uint16_t *Cfill = nullptr;  // rank codes of Xfill, or null
     const uint8_t *B = nullptr;    // byte rank codes of the fill-substituted values, or null
+    const int32_t *T = nullptr;    // per 512-row group of B: 1 if a row has two equal values
     bool b_exclude = false;        // B also serves exclude mode (no missing cell)
     int64_t ldb = 0;               // bytes per column of B (multiple of 256)
     int64_t ld = 0;                // multiple of 64
@@ -75,6 +76,7 @@ struct ReqDesc {
     const float *X;            // the matrix to read (the fill copy when it serves include mode)
     const uint16_t *C;         // the rank codes to stage (kFlagCodes), or null
     const uint8_t *B;          // the byte rank codes to stage (kFlagBytes), or null
+    const int32_t *T;          // their per-512-row tie flags
     int64_t ldb;               // bytes per column of B
     int64_t ld;
     int64_t rows;
@@ -127,6 +129,8 @@ struct BatchHeader {
 // the per-individual counts of a group of P.
 size_t tile_lds_bytes(int32_t L, int32_t cols, int32_t staging);
 size_t count_lds_bytes(int32_t P);
+// All dynamic LDS of one plain-evaluation item (tile and counts).
+size_t item_lds_bytes(int32_t L, int32_t cols, int32_t staging, int32_t P);
 
 // Blocks per CU the plain evaluation kernel reaches with this shape (0 = cannot run).
 int eval_occupancy(const LaunchCfg &cfg, int32_t cols, uint32_t flags);
@@ -166,10 +170,13 @@ hipError_t launch_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, 
 
 // Byte rank codes of rows [0, rows) of a column-major matrix (cols <=
 // kMaxByteCols), with missing cells replaced by `fill`, into B (ldb bytes
-// per column, the interleaved order above; padding rows get 0). *has_nan
-// (device int, zeroed by the caller) is set to 1 if any cell is missing.
+// per column, ldb a multiple of 512, the interleaved order above; padding
+// rows get 0). *has_nan (device int, zeroed by the caller) is set to 1 if
+// any cell is missing; ties[g] (ldb / 512 device ints, zeroed by the
+// caller) is set to 1 if some row of rows [512 g, 512 g + 512) holds two
+// equal values.
 hipError_t launch_byte_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
-                             uint8_t *B, int64_t ldb, int32_t *has_nan, hipStream_t s);
+                             uint8_t *B, int64_t ldb, int32_t *has_nan, int32_t *ties, hipStream_t s);
 
 // Zero rows [rows, ld) of every column of a column-major matrix.
 hipError_t launch_zero_pad(float *dst, int64_t rows, int64_t ld, int32_t cols, hipStream_t s);

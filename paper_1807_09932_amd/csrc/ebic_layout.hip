@@ -92,7 +92,7 @@ k_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols, uin
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_byte_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols, float fill,
-             uint8_t *__restrict__ B, int64_t ldb, int32_t *__restrict__ has_nan)
+             uint8_t *__restrict__ B, int64_t ldb, int32_t *__restrict__ has_nan, int32_t *__restrict__ ties)
 {
     extern __shared__ float t[];  // [cols][64]
     const int64_t r0 = (int64_t)blockIdx.x * 64;
@@ -112,12 +112,19 @@ k_byte_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols
     __syncthreads();
     // Position of row r inside its 256-row group.
     const int64_t pos = (r & ~(int64_t)255) + 4 * (r & 63) + ((r >> 6) & 3);
+    bool tie = false;
     for (int32_t c = wave; c < cols; c += 4) {
         const float v = t[c * 64 + lane];
-        int32_t n = 0;
-        for (int32_t j = 0; j < cols; ++j) n += t[j * 64 + lane] < v ? 1 : 0;
+        int32_t n = 0, e = 0;
+        for (int32_t j = 0; j < cols; ++j) {
+            const float u = t[j * 64 + lane];
+            n += u < v ? 1 : 0;
+            e += u == v ? 1 : 0;
+        }
+        tie |= e > 1;  // another cell of the row has the same value (and code)
         B[(int64_t)c * ldb + pos] = live ? (uint8_t)n : (uint8_t)0;
     }
+    if (live && tie) ties[r >> 9] = 1;
 }
 
 __global__ void k_zero_pad(float *__restrict__ dst, int64_t rows, int64_t ld, int32_t cols)
@@ -144,15 +151,15 @@ hipError_t launch_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, 
 }
 
 hipError_t launch_byte_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
-                             uint8_t *B, int64_t ldb, int32_t *has_nan, hipStream_t s)
+                             uint8_t *B, int64_t ldb, int32_t *has_nan, int32_t *ties, hipStream_t s)
 {
-    if (cols > kMaxByteCols || ldb % 256 != 0 || ldb < rows) return hipErrorInvalidValue;
+    if (cols > kMaxByteCols || ldb % 512 != 0 || ldb < rows) return hipErrorInvalidValue;
     const size_t lds = (size_t)cols * 64 * sizeof(float);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_byte_codes),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_byte_codes, dim3((unsigned)(ldb / 64)), dim3(256), lds, s, X, rows, ld,
-                       cols, fill, B, ldb, has_nan);
+                       cols, fill, B, ldb, has_nan, ties);
     return hipGetLastError();
 }
 

@@ -79,7 +79,7 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
     else cfg = tuned_cfg(ctx, m.dev.rows, m.dev.cols, n, nnz);
     const size_t lds_max = ctx->lds_per_block;
     cfg.P = std::max(1, std::min(cfg.P, std::max(1, n)));
-    auto lds = [&](const LaunchCfg &c) { return tile_lds_bytes(c.L, m.dev.cols, c.staging) + count_lds_bytes(c.P); };
+    auto lds = [&](const LaunchCfg &c) { return item_lds_bytes(c.L, m.dev.cols, c.staging, c.P); };
     auto fits = [&](const LaunchCfg &c) { return lds(c) <= lds_max; };
     const bool have_codes = ((flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
     const bool have_bytes = m.dev.B && ((flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
@@ -138,11 +138,13 @@ ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int3
         d.flags |= kFlagCodes;
     }
     d.B = nullptr;
+    d.T = nullptr;
     d.ldb = m.dev.ldb;
     if (staging == STAGE_BYTES) {
         if (!m.dev.B || !(include || m.dev.b_exclude))
             fail(EBIC_EINVAL, "no byte rank codes for this matrix and mode");
         d.B = m.dev.B;
+        d.T = m.dev.T;
         d.flags |= kFlagBytes;
     }
     if (staging == STAGE_DIRECT) {
@@ -388,13 +390,18 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             int32_t has_nan = 1;
             if (cols <= kMaxByteCols) {
                 m.dev.ldb = (rows + 511) / 512 * 512;  // whole chunks of two 256-row groups
+                // Layout: codes | missing flag (256 bytes) | tie flags.
                 const size_t bbytes = (size_t)m.dev.ldb * cols;
-                m.B = static_cast<uint8_t *>(ctx_alloc(ctx, bbytes + 256));
-                m.bytes += bbytes + 256;
+                const size_t tbytes = (size_t)(m.dev.ldb / 512) * sizeof(int32_t);
+                m.B = static_cast<uint8_t *>(ctx_alloc(ctx, bbytes + 256 + tbytes));
+                m.bytes += bbytes + 256 + tbytes;
                 int32_t *flag = reinterpret_cast<int32_t *>(m.B + bbytes);
-                hip_check(hipMemsetAsync(flag, 0, sizeof(int32_t), s), "hipMemsetAsync");
-                hip_check(launch_byte_codes(m.X, rows, m.dev.ld, cols, missing_fill, m.B, m.dev.ldb, flag, s),
+                int32_t *ties = reinterpret_cast<int32_t *>(m.B + bbytes + 256);
+                hip_check(hipMemsetAsync(flag, 0, 256 + tbytes, s), "hipMemsetAsync");
+                hip_check(launch_byte_codes(m.X, rows, m.dev.ld, cols, missing_fill, m.B, m.dev.ldb, flag, ties,
+                                            s),
                           "byte codes kernel");
+                m.dev.T = ties;
                 hip_check(hipMemcpyAsync(&has_nan, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s),
                           "hipMemcpyAsync");
             }

@@ -296,7 +296,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                                 c.P = std::min(P, r.n_ind);
                                 c.staging = stg;
                                 if (stg != STAGE_DIRECT &&
-                                    tile_lds_bytes(L, cols, stg) + count_lds_bytes(c.P) > ctx->lds_per_block)
+                                    item_lds_bytes(L, cols, stg, c.P) > ctx->lds_per_block)
                                     continue;
                                 if (stg == STAGE_CODES && (L < 2 || !have_codes)) continue;
                                 if (stg == STAGE_BYTES && (L < 4 || !have_bytes)) continue;
