@@ -150,23 +150,26 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     c.W = std::max(1, std::min(16, c.W));
     c.P = std::max(1, c.P);
 
-    // Staging per request: the byte rank codes when the shape asks for them
-    // and they exist for this mode (four sub-tiles only); the 16-bit rank
-    // codes when the shape asks for codes (or the FP32 tile does not fit)
-    // and they exist and fit; else the FP32 tile if it fits next to the
-    // counts, else direct reads.
+    // Staging per request: the byte or 16-bit SWAR codes when the shape asks
+    // for either and the matrix has them for this mode (four sub-tiles); the
+    // FP16 rank codes when the shape asks for codes (or the FP32 tile does
+    // not fit) and they exist and fit; else the FP32 tile if it fits next to
+    // the counts, else direct reads.
     for (int32_t q = 0; q < n_reqs; ++q) {
         const ebic_request &r = reqs[q];
         const Matrix &m = ctx_matrix(ctx, r.matrix);
         const bool have_codes = ((r.flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
         const bool have_bytes = m.dev.B && ((r.flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
+        const bool have_halves = m.dev.Hc && ((r.flags & EBIC_NAN_INCLUDE) || m.dev.h_exclude);
         auto fits = [&](int32_t stg) {
             return tile_lds_bytes(c.L, m.dev.cols, stg) + count_lds_bytes(c.P) <= lds_max;
         };
         int32_t staging = STAGE_DIRECT;
         const bool codes_ok = have_codes && c.L >= 2 && fits(STAGE_CODES);
-        const bool wants_codes = c.staging == STAGE_CODES || c.staging == STAGE_BYTES;
-        if (have_bytes && c.L == 4 && c.staging == STAGE_BYTES && fits(STAGE_BYTES)) staging = STAGE_BYTES;
+        const bool wants_swar = c.staging == STAGE_BYTES || c.staging == STAGE_HALVES;
+        const bool wants_codes = c.staging == STAGE_CODES || wants_swar;
+        if (wants_swar && c.L == 4 && have_bytes && fits(STAGE_BYTES)) staging = STAGE_BYTES;
+        else if (wants_swar && c.L == 4 && have_halves && fits(STAGE_HALVES)) staging = STAGE_HALVES;
         else if (codes_ok && (wants_codes || !fits(STAGE_LDS))) staging = STAGE_CODES;
         else if (fits(STAGE_LDS)) staging = STAGE_LDS;
         ReqDesc d = make_desc(m, std::max(0, r.n_ind), r.d_offsets, r.d_cols, r.flags, r.d_matched,

@@ -49,6 +49,7 @@ __host__ __device__ inline size_t tile_bytes_of(int32_t L, int32_t cols, int32_t
 {
     if (staging == STAGE_DIRECT) return 0;
     if (staging == STAGE_BYTES) return (size_t)cols * L * kWave;  // one byte per row
+    if (staging == STAGE_HALVES) return (size_t)cols * L * kWave * 2;
     return (size_t)L * kWave * cols * (staging == STAGE_CODES ? sizeof(uint16_t) : sizeof(float));
 }
 
@@ -706,6 +707,25 @@ __device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ ti
 // ---------------------------------------------------------------------------
 constexpr uint32_t kByteHi = 0x80808080u;
 
+// Lane parts of BITS bits (codes below 2^(BITS-1)): the constants of the
+// arithmetic above.
+template <int BITS> struct Lanes;
+template <> struct Lanes<8> {
+    static constexpr uint32_t H = 0x80808080u;    // the top bit of every part
+    static constexpr uint32_t TWO = 0x01010100u;  // D + E, summed over the parts
+    static constexpr uint32_t MIR = 0x7f7f7f7fu;  // mirrors every part
+    static constexpr int SHF = 7;                 // top bit -> bit 0 of its part
+    static constexpr int PARTS = 4;               // rows per word
+};
+template <> struct Lanes<16> {
+    static constexpr uint32_t H = 0x80008000u;
+    static constexpr uint32_t TWO = 0x00010000u;
+    static constexpr uint32_t MIR = 0x7fff7fffu;
+    static constexpr int SHF = 15;
+    static constexpr int PARTS = 2;
+};
+
+
 #define BY_LOAD(t, w)                                                          \
     "v_lshl_add_u32 %[ad], %[" w "], %[sh], %[base]\n\t"                       \
     "ds_read_b32 %[" t "], %[ad]\n\t"
@@ -737,7 +757,7 @@ constexpr uint32_t kByteHi = 0x80808080u;
 #define BY_COLS                                                                \
     [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), \
         [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last), \
-        [sh] "i"(SH)
+        [sh] "i"(SH), [H] "i"(T::H), [TWO] "i"(T::TWO), [SHF] "i"(T::SHF)
 
 // The sequences below take SH = log2 of the bytes one staged column
 // occupies (8: 256-row chunks, 9: 512-row chunks of two 256-row groups).
@@ -748,24 +768,25 @@ constexpr uint32_t kByteHi = 0x80808080u;
 // last >= 2). The sequence starts with lgkmcnt(0) (no scalar load in
 // flight, so LDS operations complete in issue order and lgkmcnt(n) means
 // that all but the last n issued are done) and ends with it.
-template <int SH>
+template <int SH, int BITS = 8>
 __device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
                                        uint32_t &alive, uint32_t &fall, uint32_t &tied)
 {
+    using T = Lanes<BITS>;
     uint32_t t0, t1, t2, t3, ad, D, D2, fm, fH, nf, nx;
     uint64_t tmp, tany;
     asm volatile(
         "s_waitcnt lgkmcnt(0)\n\t"
         BY_LOAD("t0", "w0") BY_LOAD("t1", "w1") BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
         "s_waitcnt lgkmcnt(2)\n\t"
-        "v_or_b32_e32 %[D], 0x80808080, %[t1]\n\t"
-        "v_sub_u32_e32 %[D], %[D], %[t0]\n\t"           // bit 7: t1 >= t0
-        "v_sub_u32_e32 %[D2], 0x1010100, %[D]\n\t"      // = (t0 | 0x80..) - t1, bit 7: t0 >= t1
+        "v_or_b32_e32 %[D], %[H], %[t1]\n\t"
+        "v_sub_u32_e32 %[D], %[D], %[t0]\n\t"           // top bits: t1 >= t0
+        "v_sub_u32_e32 %[D2], %[TWO], %[D]\n\t"         // = (t0 | H) - t1, top bits: t0 >= t1
         "v_bitop3_b32 %[tied], %[D], %[D2], %[hv] bitop3:0x80\n\t"  // tied, in range
         "v_bitop3_b32 %[fall], %[D], %[D2], %[hv] bitop3:0x08\n\t"  // ~D & D2 & hv: falling
-        "v_lshrrev_b32_e32 %[fm], 7, %[fall]\n\t"
-        "v_sub_u32_e32 %[fm], %[fall], %[fm]\n\t"       // 0x7F in each falling byte
-        "v_or_b32_e32 %[fH], 0x80808080, %[fm]\n\t"
+        "v_lshrrev_b32_e32 %[fm], %[SHF], %[fall]\n\t"
+        "v_sub_u32_e32 %[fm], %[fall], %[fm]\n\t"       // all low bits of each falling part
+        "v_or_b32_e32 %[fH], %[H], %[fm]\n\t"
         "v_not_b32_e32 %[nf], %[fm]\n\t"
         "v_xad_u32 %[nx], %[t1], %[nf], 1\n\t"
         "v_cmp_ne_u32_e64 %[tany], 0, %[tied]\n\t"
@@ -791,22 +812,23 @@ __device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], 
         "5:"
         : BY_SCRATCH, [fm] "=&v"(fm), [fH] "=&v"(fH), [nf] "=&v"(nf), [nx] "=&v"(nx),
           [alive] "=&v"(alive), [fall] "=&v"(fall), [tied] "=&v"(tied), [tany] "=&s"(tany)
-        : BY_COLS, [hv] "v"(hv), [hi] "s"(kByteHi)
+        : BY_COLS, [hv] "v"(hv), [hi] "s"(T::H)
         : "scc", "memory");
 }
 
 // The >= chain alone through column min(last, 7) (waits as above).
-template <int SH>
+template <int SH, int BITS = 8>
 __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
                                        uint32_t &alive)
 {
+    using T = Lanes<BITS>;
     uint32_t t0, t1, t2, t3, ad, D, D2, nx;
     uint64_t tmp;
     asm volatile(
         "s_waitcnt lgkmcnt(0)\n\t"
         BY_LOAD("t0", "w0") BY_LOAD("t1", "w1") BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
         "s_waitcnt lgkmcnt(2)\n\t"
-        "v_or_b32_e32 %[D], 0x80808080, %[t1]\n\t"
+        "v_or_b32_e32 %[D], %[H], %[t1]\n\t"
         "v_sub_u32_e32 %[D], %[D], %[t0]\n\t"
         "v_and_b32_e32 %[alive], %[D], %[hv]\n\t"
         "v_sub_u32_e32 %[nx], 0, %[t1]\n\t"
@@ -816,7 +838,7 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
         "2:\n\t"
         "s_waitcnt lgkmcnt(0)"
         : BY_SCRATCH, [nx] "=&v"(nx), [alive] "=&v"(alive)
-        : BY_COLS, [hv] "v"(hv), [hi] "s"(kByteHi)
+        : BY_COLS, [hv] "v"(hv), [hi] "s"(T::H)
         : "scc", "memory");
 }
 
@@ -829,20 +851,22 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
 #undef BY_COLS
 
 // ---------------------------------------------------------------------------
-// Two 256-row groups per chunk (512 rows; a staged column is 512 bytes, the
-// second group at +256): the same chains for both groups in one instruction
-// stream. A column's two words share one address, the two groups' operations
-// are independent (they hide each other's latency), and the window ends when
-// no row of either group is left. Here the reference carried from column to
-// column is q = 0x80808080 - x_{j-1} (each byte in 1..128, so again no
-// borrow), which needs fm and nf but not fH:
-//   D = (t_j ^ fm) + q       = (x_j | 0x80..) - x_{j-1}
-//   q = (t_j ^ nf) + 0x80808081 = 0x80808080 - x_j
+// Two lane words per chunk: byte codes in 512-row chunks (two 256-row groups,
+// four rows per word) or 16-bit codes in 256-row chunks (two 128-row groups,
+// two rows per word: lane l's word holds rows l and 64 + l of its group). A
+// staged column is 512 bytes in both cases, the second word at +256. Both
+// words' chains run in one instruction stream with their operations
+// alternating: a column's two words share one address and hide each other's
+// latency, and the window ends when no row of either word is left. The
+// arithmetic is the byte one above with lane parts of BITS bits (codes below
+// 2^(BITS-1)); the reference carried from column to column is
+// q = H - x_{j-1} (each part in 1..2^(BITS-1), no borrow), which needs fm and
+// nf but not fH:
+//   D = (t_j ^ fm) + q       = (x_j | H) - x_{j-1}
+//   q = (t_j ^ nf) + H + 1   = H - x_j
 // Chunks whose rows hold no two equal values (tie flags computed at upload)
 // skip the tie detection and the tie chain.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kByteHiP1 = 0x80808081u;
-
 #define B2_LOAD(t, w)                                                          \
     "v_lshl_add_u32 %[ad], %[" w "], 9, %[base]\n\t"                           \
     "ds_read_b32 %[" t "a], %[ad]\n\t"                                         \
@@ -883,15 +907,15 @@ constexpr uint32_t kByteHiP1 = 0x80808081u;
 #define B2_COLS                                                                \
     [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), \
         [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last), \
-        [hp] "s"(kByteHiP1)
-// First pair of a group (X = a or b); the two groups' operations alternate.
-// D: bit 7 where t1 >= t0; E: where t0 >= t1 (only for the tie test).
-#define B2_F1(X) "v_or_b32_e32 %[D" X "], 0x80808080, %[t1" X "]\n\t"
+        [hp] "s"(T::H + 1u), [H] "i"(T::H), [TWO] "i"(T::TWO), [SHF] "i"(T::SHF), [MIR] "i"(T::MIR)
+// First pair of a word (X = a or b); the two words' operations alternate.
+// D: top bit of a part where t1 >= t0; E: where t0 >= t1 (tie test only).
+#define B2_F1(X) "v_or_b32_e32 %[D" X "], %[H], %[t1" X "]\n\t"
 #define B2_F2(X) "v_sub_u32_e32 %[D" X "], %[D" X "], %[t0" X "]\n\t"
-#define B2_F3(X) "v_sub_u32_e32 %[E" X "], 0x1010100, %[D" X "]\n\t"
+#define B2_F3(X) "v_sub_u32_e32 %[E" X "], %[TWO], %[D" X "]\n\t"
 #define B2_F4(X) "v_bitop3_b32 %[tied" X "], %[D" X "], %[E" X "], %[hv" X "] bitop3:0x80\n\t"
 #define B2_F5(X) "v_bfi_b32 %[fall" X "], %[D" X "], 0, %[hv" X "]\n\t"
-#define B2_F6(X) "v_lshrrev_b32_e32 %[E" X "], 7, %[fall" X "]\n\t"
+#define B2_F6(X) "v_lshrrev_b32_e32 %[E" X "], %[SHF], %[fall" X "]\n\t"
 #define B2_F7(X) "v_sub_u32_e32 %[fm" X "], %[fall" X "], %[E" X "]\n\t"
 #define B2_F8(X) "v_not_b32_e32 %[nf" X "], %[fm" X "]\n\t"
 #define B2_F9(X) "v_xad_u32 %[q" X "], %[t1" X "], %[nf" X "], %[hp]\n\t"
@@ -903,14 +927,15 @@ constexpr uint32_t kByteHiP1 = 0x80808081u;
     B2_AB(B2_F1) B2_AB(B2_F2) B2_AB(B2_F5) B2_AB(B2_F6) B2_AB(B2_F7)           \
     B2_AB(B2_F8) B2_AB(B2_F9)
 
-// Both chains on both groups through column min(last, 7); outputs per
-// group as in by_neg (tied = 0 without TIES). Waits count LDS operations;
-// the sequence starts and ends with lgkmcnt(0).
-template <bool TIES>
+// Both chains on both words through column min(last, 7); outputs per word
+// as in by_neg (tied = 0 without TIES). Waits count LDS operations; the
+// sequence starts and ends with lgkmcnt(0).
+template <int BITS, bool TIES>
 __device__ __forceinline__ void by2_neg(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hva,
                                         uint32_t hvb, uint32_t &alivea, uint32_t &aliveb, uint32_t &falla,
                                         uint32_t &fallb, uint32_t &tieda, uint32_t &tiedb)
 {
+    using T = Lanes<BITS>;
     uint32_t t0a, t0b, t1a, t1b, t2a, t2b, t3a, t3b, ad, Da, Db, Ea, Eb, qa, qb, fma, fmb, nfa, nfb;
     uint64_t tmp, tany;
     if constexpr (TIES) {
@@ -927,12 +952,12 @@ __device__ __forceinline__ void by2_neg(uint32_t base, const int32_t (&w)[kWin],
             "2:\n\t"
             "s_waitcnt lgkmcnt(0)\n\t"
             // The rows tied on the first pair: the <= chain from column 1
-            // (every code mirrored: fm = 0x7F7F7F7F, nf = 0x80808080).
+            // (every code mirrored: fm = MIR, nf = H).
             "s_cmp_lg_u64 %[tany], 0\n\t"
             "s_cbranch_scc0 4f\n\t"
             B2_LOAD("t1", "w1") B2_LOAD("t2", "w2") B2_LOAD("t3", "w3")
-            "v_mov_b32_e32 %[fma], 0x7f7f7f7f\n\t"
-            "v_mov_b32_e32 %[nfa], 0x80808080\n\t"
+            "v_mov_b32_e32 %[fma], %[MIR]\n\t"
+            "v_mov_b32_e32 %[nfa], %[H]\n\t"
             "s_waitcnt lgkmcnt(4)\n\t"
             "v_xad_u32 %[qa], %[t1a], %[nfa], %[hp]\n\t"
             "v_xad_u32 %[qb], %[t1b], %[nfa], %[hp]\n\t"
@@ -976,18 +1001,20 @@ __device__ __forceinline__ void by2_neg(uint32_t base, const int32_t (&w)[kWin],
     }
 }
 
-// The >= chain alone on both groups (fm = 0, nf = ~0).
+// The >= chain alone on both words (fm = 0, nf = ~0).
+template <int BITS>
 __device__ __forceinline__ void by2_pos(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hva,
                                         uint32_t hvb, uint32_t &alivea, uint32_t &aliveb)
 {
+    using T = Lanes<BITS>;
     uint32_t t0a, t0b, t1a, t1b, t2a, t2b, t3a, t3b, ad, Da, Db, Ea, Eb, qa, qb;
     uint64_t tmp;
     asm volatile(
         "s_waitcnt lgkmcnt(0)\n\t"
         B2_LOAD("t0", "w0") B2_LOAD("t1", "w1") B2_LOAD("t2", "w2") B2_LOAD("t3", "w3")
         "s_waitcnt lgkmcnt(4)\n\t"
-        "v_or_b32_e32 %[Da], 0x80808080, %[t1a]\n\t"
-        "v_or_b32_e32 %[Db], 0x80808080, %[t1b]\n\t"
+        "v_or_b32_e32 %[Da], %[H], %[t1a]\n\t"
+        "v_or_b32_e32 %[Db], %[H], %[t1b]\n\t"
         "v_sub_u32_e32 %[Da], %[Da], %[t0a]\n\t"
         "v_sub_u32_e32 %[Db], %[Db], %[t0b]\n\t"
         "v_and_b32_e32 %[alivea], %[Da], %[hva]\n\t"
@@ -1061,7 +1088,7 @@ __device__ __forceinline__ void by_window_ref(const unsigned char *__restrict__ 
 
 // Columns kWin..last (long individuals), while any row is left; nx is -x
 // of window column 7 (with a row left, the window ran through column 7).
-template <int SH, bool COUNT>
+template <int SH, bool COUNT, int NP = 4>
 __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, const int32_t *__restrict__ c,
                                         const int32_t (&w)[kWin], int32_t last, uint32_t fH, uint32_t nf,
                                         uint32_t &alive, uint64_t &steps)
@@ -1072,7 +1099,7 @@ __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, 
         const uint32_t t = *reinterpret_cast<const uint32_t *>(base + (c[u] << SH));
         alive &= (t ^ fH) + nx;
         nx = (t ^ nf) + 1u;
-        if (COUNT) steps += 4;
+        if (COUNT) steps += NP;
     }
 }
 
@@ -1147,10 +1174,29 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
     return true;
 }
 
-// Plain-code twin of the two-group window (the measurement variant): both
-// groups in lockstep with the same exits; one step per 64-row sub-tile and
+// Wave-wide masks of the two 64-row sub-tiles of a word of 16-bit parts.
+__device__ __forceinline__ void half_masks2(uint32_t x, uint64_t &m0, uint64_t &m1)
+{
+    asm volatile(
+        "v_cmp_ne_u32_sdwa %[m0], %[x], 0 src0_sel:WORD_0 src1_sel:DWORD\n\t"
+        "v_cmp_ne_u32_sdwa %[m1], %[x], 0 src0_sel:WORD_1 src1_sel:DWORD\n\t"
+        "s_nop 1"
+        : [m0] "=s"(m0), [m1] "=s"(m1)
+        : [x] "v"(x));
+}
+
+// The sub-tile masks of a word (BITS-bit parts; the top bit of each part).
+template <int BITS>
+__device__ __forceinline__ void lane_masks(uint32_t x, uint64_t *m)
+{
+    if constexpr (BITS == 8) byte_masks4(x, m[0], m[1], m[2], m[3]);
+    else half_masks2(x, m[0], m[1]);
+}
+
+// Plain-code twin of the two-word window (the measurement variant): both
+// words in lockstep with the same exits; one step per 64-row sub-tile and
 // column.
-template <bool COUNT>
+template <int BITS, bool COUNT>
 __device__ __forceinline__ void by2_window_ref(const unsigned char *__restrict__ base, const int32_t (&w)[kWin],
                                                int32_t last, const uint32_t (&fH)[2], const uint32_t (&nf)[2],
                                                uint32_t (&nx)[2], uint32_t (&alive)[2], uint64_t &steps)
@@ -1163,33 +1209,37 @@ __device__ __forceinline__ void by2_window_ref(const unsigned char *__restrict__
             alive[h] &= (t ^ fH[h]) + nx[h];
             nx[h] = (t ^ nf[h]) + 1u;
         }
-        if (COUNT) steps += 8;
+        if (COUNT) steps += 2 * Lanes<BITS>::PARTS;
         if (u == 3 && last <= 3) return;
         if (u == 5 && (__ballot((alive[0] | alive[1]) != 0) == 0 || last <= 5)) return;
     }
 }
 
-// One individual on a chunk of two 256-row groups of byte codes (eight
-// 64-row sub-tiles; a column is 512 bytes). hva, hvb: the in-range rows of
-// each group. Returns false, and leaves M and G unset, when no row matches.
-template <bool NEG, bool COUNT, bool TIES>
-__device__ __forceinline__ bool eval_bytes2(const unsigned char *__restrict__ tile, int32_t last,
-                                            const int32_t *__restrict__ colidx,
-                                            const int32_t *__restrict__ hbegin, const int4 &w03,
-                                            const int4 &w47, int lane, uint32_t hva, uint32_t hvb, uint64_t (&M)[8],
-                                            uint64_t (&G)[8], uint64_t &steps)
+// One individual on a chunk of two lane words per row group (byte codes:
+// 512 rows, 8 sub-tiles; 16-bit codes: 256 rows, 4 sub-tiles; a column is
+// 512 bytes). hva, hvb: the top bits of the in-range rows of each word.
+// Returns false, and leaves M and G unset, when no row matches. M and G hold
+// 2 * PARTS sub-tile masks.
+template <int BITS, bool NEG, bool COUNT, bool TIES>
+__device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ tile, int32_t last,
+                                           const int32_t *__restrict__ colidx,
+                                           const int32_t *__restrict__ hbegin, const int4 &w03, const int4 &w47,
+                                           int lane, uint32_t hva, uint32_t hvb, uint64_t *M, uint64_t *G,
+                                           uint64_t &steps)
 {
+    using T = Lanes<BITS>;
+    constexpr int NP = T::PARTS;
     const unsigned char *base = tile + 4 * lane;
     const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
     auto rd = [&](int32_t col, int h) {
         return *reinterpret_cast<const uint32_t *>(base + (col << 9) + 256 * h);
     };
     if (last == 0) {  // one column: every row in range counts
-        byte_masks4(hva, M[0], M[1], M[2], M[3]);
-        byte_masks4(hvb, M[4], M[5], M[6], M[7]);
+        lane_masks<BITS>(hva, M);
+        lane_masks<BITS>(hvb, M + NP);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) G[s] = 0;
-        if (COUNT) steps += 8;
+        for (int s = 0; s < 2 * NP; ++s) G[s] = 0;
+        if (COUNT) steps += 2 * NP;
         return true;
     }
     uint32_t alive[2], fall[2] = {0, 0}, tied[2] = {0, 0};
@@ -1199,35 +1249,35 @@ __device__ __forceinline__ bool eval_bytes2(const unsigned char *__restrict__ ti
         for (int h = 0; h < 2; ++h) {
             const uint32_t hv = h ? hvb : hva;
             const uint32_t t0 = rd(w[0], h), t1 = rd(w[1], h);
-            const uint32_t D = (t1 | kByteHi) - t0, E = (t0 | kByteHi) - t1;
-            fH[h] = kByteHi;
+            const uint32_t D = (t1 | T::H) - t0, E = (t0 | T::H) - t1;
+            fH[h] = T::H;
             nf[h] = ~0u;
             alive[h] = D & hv;
             if constexpr (NEG) {
                 tied[h] = D & E & hv;
                 fall[h] = E & ~D & hv;
-                const uint32_t fm = fall[h] - (fall[h] >> 7);
-                fH[h] = fm | kByteHi;
+                const uint32_t fm = fall[h] - (fall[h] >> T::SHF);
+                fH[h] = fm | T::H;
                 nf[h] = ~fm;
                 alive[h] = hv;
             }
             nx[h] = (t1 ^ nf[h]) + 1u;
         }
-        steps += 8;
-        if (last >= 2) by2_window_ref<COUNT>(base, w, last, fH, nf, nx, alive, steps);
+        steps += 2 * NP;
+        if (last >= 2) by2_window_ref<BITS, COUNT>(base, w, last, fH, nf, nx, alive, steps);
         if (NEG && last >= 2 && __ballot((tied[0] | tied[1]) != 0) != 0) {
-            const uint32_t fH2[2] = {~0u, ~0u}, nf2[2] = {kByteHi, kByteHi};
-            uint32_t nx2[2] = {(rd(w[1], 0) ^ kByteHi) + 1u, (rd(w[1], 1) ^ kByteHi) + 1u};
-            steps += 8;
-            by2_window_ref<COUNT>(base, w, last, fH2, nf2, nx2, tied, steps);
+            const uint32_t fH2[2] = {~0u, ~0u}, nf2[2] = {T::H, T::H};
+            uint32_t nx2[2] = {(rd(w[1], 0) ^ T::H) + 1u, (rd(w[1], 1) ^ T::H) + 1u};
+            steps += 2 * NP;
+            by2_window_ref<BITS, COUNT>(base, w, last, fH2, nf2, nx2, tied, steps);
         } else {
             tied[0] = tied[1] = 0;
         }
     } else {
         const uint32_t b = lds_addr(base);
         if constexpr (NEG)
-            by2_neg<TIES>(b, w, last, hva, hvb, alive[0], alive[1], fall[0], fall[1], tied[0], tied[1]);
-        else by2_pos(b, w, last, hva, hvb, alive[0], alive[1]);
+            by2_neg<BITS, TIES>(b, w, last, hva, hvb, alive[0], alive[1], fall[0], fall[1], tied[0], tied[1]);
+        else by2_pos<BITS>(b, w, last, hva, hvb, alive[0], alive[1]);
     }
     if (last >= kWin) {
         // The columns past the window (the CSR start is read only here).
@@ -1235,24 +1285,24 @@ __device__ __forceinline__ bool eval_bytes2(const unsigned char *__restrict__ ti
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if constexpr (NEG) {
-                const uint32_t fm = fall[h] - (fall[h] >> 7);
-                by_tail<9, COUNT>(base + 256 * h, c, w, last, fm | kByteHi, ~fm, alive[h], steps);
-                by_tail<9, COUNT>(base + 256 * h, c, w, last, ~0u, kByteHi, tied[h], steps);
+                const uint32_t fm = fall[h] - (fall[h] >> T::SHF);
+                by_tail<9, COUNT, NP>(base + 256 * h, c, w, last, fm | T::H, ~fm, alive[h], steps);
+                by_tail<9, COUNT, NP>(base + 256 * h, c, w, last, ~0u, T::H, tied[h], steps);
             } else {
-                by_tail<9, COUNT>(base + 256 * h, c, w, last, kByteHi, ~0u, alive[h], steps);
+                by_tail<9, COUNT, NP>(base + 256 * h, c, w, last, T::H, ~0u, alive[h], steps);
             }
         }
     }
     const uint32_t mwa = alive[0] | tied[0], mwb = alive[1] | tied[1];
     if (__ballot((mwa | mwb) != 0) == 0) return false;
-    byte_masks4(mwa, M[0], M[1], M[2], M[3]);
-    byte_masks4(mwb, M[4], M[5], M[6], M[7]);
+    lane_masks<BITS>(mwa, M);
+    lane_masks<BITS>(mwb, M + NP);
     if constexpr (NEG) {
-        byte_masks4((alive[0] & fall[0]) | (tied[0] & ~alive[0]), G[0], G[1], G[2], G[3]);
-        byte_masks4((alive[1] & fall[1]) | (tied[1] & ~alive[1]), G[4], G[5], G[6], G[7]);
+        lane_masks<BITS>((alive[0] & fall[0]) | (tied[0] & ~alive[0]), G);
+        lane_masks<BITS>((alive[1] & fall[1]) | (tied[1] & ~alive[1]), G + NP);
     } else {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) G[s] = 0;
+        for (int s = 0; s < 2 * NP; ++s) G[s] = 0;
     }
     return true;
 }
@@ -1356,24 +1406,30 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
 
     for (int32_t t = threadIdx.x; t < 2 * np; t += blockDim.x) cnt[t] = 0;
 
-    // Byte codes: a chunk holds L * 64 bytes of every column (L / 4 groups
-    // of 256 rows); every thread copies up to two 16-byte pieces of it
-    // (piece idx = bytes 16 * (idx % 4L) of column idx / 4L) through
-    // registers, and the pieces of the next chunk are loaded while the
-    // current one is evaluated. Pieces past 2 * blockDim are copied directly.
-    constexpr int PL = L == 8 ? 5 : 4;  // log2 of the pieces per column
-    const int btotal = STAGE == STAGE_BYTES ? d.cols << PL : 0;
+    // Byte or 16-bit codes (SWAR stagings): a chunk holds L * 64 * RB bytes
+    // of every column (one or two lane words per row); every thread copies
+    // up to two 16-byte pieces of it (piece idx = bytes 16 * (idx % pieces)
+    // of column idx / pieces) through registers, and the pieces of the next
+    // chunk are loaded while the current one is evaluated. Pieces past
+    // 2 * blockDim are copied directly.
+    constexpr bool kSwar = STAGE == STAGE_BYTES || STAGE == STAGE_HALVES;
+    constexpr int BITS = STAGE == STAGE_HALVES ? 16 : 8;
+    constexpr int RB = BITS / 8;                      // bytes per row
+    constexpr int PARTS = 32 / BITS;                  // rows (sub-tiles) per lane word
+    constexpr int NWORDS = L >= PARTS ? L / PARTS : 1;  // lane words per chunk
+    constexpr int PL = L * RB == 8 ? 5 : 4;          // log2 of the pieces per column
+    const int btotal = kSwar ? d.cols << PL : 0;
     const int idx0 = threadIdx.x, idx1 = threadIdx.x + blockDim.x;
     const uint8_t *src0 = d.B + (int64_t)(idx0 >> PL) * d.ldb + 16 * (idx0 & ((1 << PL) - 1));
     const uint8_t *src1 = d.B + (int64_t)(idx1 >> PL) * d.ldb + 16 * (idx1 & ((1 << PL) - 1));
     uint4 pre0 = {0, 0, 0, 0}, pre1 = {0, 0, 0, 0};
     int32_t tie_pre = 1;  // the next chunk's tie flag, loaded with its bytes
-    if constexpr (STAGE == STAGE_BYTES) {
+    if constexpr (kSwar) {
         if (t0 < t1) {
-            const int64_t r0 = t0 * kWave;
+            const int64_t r0 = t0 * kWave * RB;
             if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r0);
             if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r0);
-            tie_pre = d.T[r0 >> 9];
+            tie_pre = d.T[(t0 * kWave) >> 9];
         }
     }
 
@@ -1409,35 +1465,37 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             }
             __syncthreads();
         }
-        // Byte codes: bit 7 of the bytes of the rows in range, per 256-row
-        // group, and whether a row of the chunk holds two equal values.
-        uint32_t hvalid[L >= 4 ? L / 4 : 1] = {};
+        // SWAR codes: per lane word, the top bit of each part whose row is
+        // in range, and whether a row of the chunk holds two equal values.
+        uint32_t hvalid[NWORDS] = {};
         bool ties = true;
-        if constexpr (STAGE == STAGE_BYTES) {
-            static_assert(L == 4 || L == 8, "byte codes hold four sub-tiles per lane word");
+        if constexpr (kSwar) {
+            static_assert(STAGE == STAGE_HALVES ? L == 4 : (L == 4 || L == 8),
+                          "one or two lane words per row of a chunk");
             ties = tie_pre != 0;
-            // The L * 64 bytes of every column for rows [row0, row0 + 64 L),
-            // in their interleaved order; rows outside the item or the
-            // matrix are left out of `hvalid` instead.
+            // The L * 64 rows [row0, row0 + 64 L) of every column, in their
+            // interleaved order; rows outside the item or the matrix are
+            // left out of `hvalid` instead.
             uint4 *tile4 = reinterpret_cast<uint4 *>(tile);
             if (idx0 < btotal) tile4[idx0] = pre0;
             if (idx1 < btotal) tile4[idx1] = pre1;
             for (int idx = idx1 + blockDim.x; idx < btotal; idx += blockDim.x)
-                tile4[idx] = *reinterpret_cast<const uint4 *>(d.B + (int64_t)(idx >> PL) * d.ldb + row0 +
+                tile4[idx] = *reinterpret_cast<const uint4 *>(d.B + (int64_t)(idx >> PL) * d.ldb + row0 * RB +
                                                               16 * (idx & ((1 << PL) - 1)));
             if (nl == L && row0 + L * kWave <= d.rows) {
 #pragma unroll
-                for (int h = 0; h < L / 4; ++h) hvalid[h] = 0x80808080u;
+                for (int h = 0; h < NWORDS; ++h) hvalid[h] = Lanes<BITS>::H;
             } else {
 #pragma unroll
                 for (int s = 0; s < L; ++s)
-                    if (s < nl && row0 + s * kWave + lane < d.rows) hvalid[s / 4] |= 0x80u << (8 * (s % 4));
+                    if (s < nl && row0 + s * kWave + lane < d.rows)
+                        hvalid[s / PARTS] |= 1u << (BITS * (s % PARTS) + BITS - 1);
             }
             __syncthreads();
             if (tb + L < t1) {
                 const int64_t r1 = row0 + L * kWave;
-                if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r1);
-                if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r1);
+                if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r1 * RB);
+                if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r1 * RB);
                 tie_pre = d.T[r1 >> 9];
             }
         }
@@ -1487,14 +1545,14 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             } else {
                 bool live = true;  // (byte codes: counted per 256-row group below)
                 int32_t pm = 0, pg = 0;
-                if constexpr (STAGE == STAGE_BYTES && L == 8) {
+                if constexpr (kSwar && NWORDS == 2) {
                     live = false;
                     const auto *tl = reinterpret_cast<const unsigned char *>(tile);
                     const bool any =
-                        ties ? eval_bytes2<NEG, COUNT, true>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2], lane,
-                                                             hvalid[0], hvalid[L / 4 - 1], M, G, steps)
-                             : eval_bytes2<NEG, COUNT, false>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2], lane,
-                                                              hvalid[0], hvalid[L / 4 - 1], M, G, steps);
+                        ties ? eval_swar2<BITS, NEG, COUNT, true>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2],
+                                                                  lane, hvalid[0], hvalid[NWORDS - 1], M, G, steps)
+                             : eval_swar2<BITS, NEG, COUNT, false>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2],
+                                                                   lane, hvalid[0], hvalid[NWORDS - 1], M, G, steps);
                     if (any) {
 #pragma unroll
                         for (int s = 0; s < L; ++s) {
@@ -1662,6 +1720,11 @@ k_eval_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs, const Item *__
                 else run_item<L, false, STAGE_BYTES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
                 continue;
             }
+            if (d.flags & kFlagHalves) {
+                if (neg) run_item<L, true, STAGE_HALVES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                else run_item<L, false, STAGE_HALVES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                continue;
+            }
         }
         if constexpr (L >= 2) {
             if (d.flags & kFlagCodes) {
@@ -1718,6 +1781,10 @@ const void *eval_pick(int L, bool neg, int staging)
     if (staging == STAGE_BYTES) {  // one or two 256-row groups per chunk
         if (L == 4) return neg ? eval_ptr<4, true, STAGE_BYTES, COUNT>() : eval_ptr<4, false, STAGE_BYTES, COUNT>();
         if (L == 8) return neg ? eval_ptr<8, true, STAGE_BYTES, COUNT>() : eval_ptr<8, false, STAGE_BYTES, COUNT>();
+        return nullptr;
+    }
+    if (staging == STAGE_HALVES) {  // two lane words of two rows per 256-row chunk
+        if (L == 4) return neg ? eval_ptr<4, true, STAGE_HALVES, COUNT>() : eval_ptr<4, false, STAGE_HALVES, COUNT>();
         return nullptr;
     }
     if (staging == STAGE_CODES) return neg ? eval_pick_codes<true, COUNT>(L) : eval_pick_codes<false, COUNT>(L);

@@ -16,7 +16,8 @@ enum Staging : int32_t {
     STAGE_LDS = 0,     // rows x all columns staged into LDS, shared by the block
     STAGE_DIRECT = 1,  // read straight from the column-major matrix (L1/L2)
     STAGE_CODES = 2,   // the matrix's 16-bit rank codes staged into LDS (half the bytes)
-    STAGE_BYTES = 3,   // 8-bit rank codes, four rows per 32-bit lane word (4 sub-tiles only)
+    STAGE_BYTES = 3,   // 8-bit rank codes, four rows per 32-bit lane word (4 or 8 sub-tiles)
+    STAGE_HALVES = 4,  // 16-bit rank codes, two rows per 32-bit lane word (4 sub-tiles)
 };
 
 // Rank codes are kept for matrices of at most this many columns: a cell's
@@ -37,6 +38,12 @@ constexpr uint16_t kCodeNaN = 0x7E00;
 // may use them only when the matrix has no missing cell.
 constexpr int32_t kMaxByteCols = 128;
 
+// 16-bit rank codes, for matrices of at most kMaxCodeCols columns: the same
+// codes of the fill-substituted values in 16 bits. Within each group of 128
+// rows the 32-bit word of lane l holds rows l and 64 + l (low and high
+// half). A column occupies ldh bytes (rows rounded up to a multiple of 256,
+// two bytes each); exclude mode may use them only without missing cells.
+
 // Request flags as the kernels see them (the low two bits are the ABI's
 // EBIC_NAN_INCLUDE and EBIC_NEG_TRENDS).
 constexpr uint32_t kFlagInclude = 1u;
@@ -45,6 +52,7 @@ constexpr uint32_t kFlagDirect = 1u << 8;  // this request reads the matrix dire
 constexpr uint32_t kFlagSubst = 1u << 9;   // direct reads replace NaN by the fill value
 constexpr uint32_t kFlagCodes = 1u << 10;  // this request stages the rank codes
 constexpr uint32_t kFlagBytes = 1u << 11;  // this request stages the byte rank codes
+constexpr uint32_t kFlagHalves = 1u << 12; // this request stages the 16-bit rank codes
 
 // One launch shape of the evaluation kernels.
 struct LaunchCfg {
@@ -63,6 +71,10 @@ struct DevMatrix {
     const uint16_t *Cfill = nullptr;  // rank codes of Xfill, or null
     const uint8_t *B = nullptr;    // byte rank codes of the fill-substituted values, or null
     const int32_t *T = nullptr;    // per 512-row group of B: 1 if a row has two equal values
+    const uint8_t *Hc = nullptr;   // 16-bit rank codes (interleaved, as bytes), or null
+    const int32_t *Th = nullptr;   // their tie flags per 512 rows
+    bool h_exclude = false;        // Hc also serves exclude mode (no missing cell)
+    int64_t ldh = 0;               // bytes per column of Hc (multiple of 512)
     bool b_exclude = false;        // B also serves exclude mode (no missing cell)
     int64_t ldb = 0;               // bytes per column of B (multiple of 256)
     int64_t ld = 0;                // multiple of 64
@@ -75,7 +87,7 @@ struct DevMatrix {
 struct ReqDesc {
     const float *X;            // the matrix to read (the fill copy when it serves include mode)
     const uint16_t *C;         // the rank codes to stage (kFlagCodes), or null
-    const uint8_t *B;          // the byte rank codes to stage (kFlagBytes), or null
+    const uint8_t *B;          // the byte or 16-bit rank codes to stage (kFlagBytes, kFlagHalves)
     const int32_t *T;          // their per-512-row tie flags
     int64_t ldb;               // bytes per column of B
     int64_t ld;
@@ -177,6 +189,11 @@ hipError_t launch_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, 
 // equal values.
 hipError_t launch_byte_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
                              uint8_t *B, int64_t ldb, int32_t *has_nan, int32_t *ties, hipStream_t s);
+
+// The same for 16-bit codes (cols <= kMaxCodeCols) into Hc, ldh bytes per
+// column (a multiple of 512), in their interleaved order.
+hipError_t launch_half_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
+                             uint8_t *Hc, int64_t ldh, int32_t *has_nan, int32_t *ties, hipStream_t s);
 
 // Zero rows [rows, ld) of every column of a column-major matrix.
 hipError_t launch_zero_pad(float *dst, int64_t rows, int64_t ld, int32_t cols, hipStream_t s);

@@ -86,13 +86,17 @@ k_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols, uin
 }
 
 // ---------------------------------------------------------------------------
-// Byte rank codes: as above, of the fill-substituted values, one byte per
-// cell, written in the interleaved order of each 256-row group (lane l's
-// word holds rows l, 64 + l, 128 + l, 192 + l). Rows past the matrix get 0.
+// Byte or 16-bit rank codes: as above, of the fill-substituted values, in
+// the interleaved order of the SWAR evaluation. Bytes: within each 256-row
+// group the word of lane l holds rows l, 64 + l, 128 + l, 192 + l; 16 bits:
+// within each 128-row group it holds rows l and 64 + l. Rows past the
+// matrix get 0. Also flags any missing cell, and each 512-row group with a
+// row that holds two equal values.
 // ---------------------------------------------------------------------------
+template <typename C>
 __global__ void __launch_bounds__(256)
-k_byte_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols, float fill,
-             uint8_t *__restrict__ B, int64_t ldb, int32_t *__restrict__ has_nan, int32_t *__restrict__ ties)
+k_swar_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols, float fill,
+             C *__restrict__ out, int64_t ld_out, int32_t *__restrict__ has_nan, int32_t *__restrict__ ties)
 {
     extern __shared__ float t[];  // [cols][64]
     const int64_t r0 = (int64_t)blockIdx.x * 64;
@@ -110,8 +114,9 @@ k_byte_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols
     }
     if (missing) *has_nan = 1;
     __syncthreads();
-    // Position of row r inside its 256-row group.
-    const int64_t pos = (r & ~(int64_t)255) + 4 * (r & 63) + ((r >> 6) & 3);
+    // Position of row r (in elements of C) inside its interleaved group.
+    const int64_t pos = sizeof(C) == 1 ? (r & ~(int64_t)255) + 4 * (r & 63) + ((r >> 6) & 3)
+                                       : (r & ~(int64_t)127) + 2 * (r & 63) + ((r >> 6) & 1);
     bool tie = false;
     for (int32_t c = wave; c < cols; c += 4) {
         const float v = t[c * 64 + lane];
@@ -122,7 +127,7 @@ k_byte_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols
             e += u == v ? 1 : 0;
         }
         tie |= e > 1;  // another cell of the row has the same value (and code)
-        B[(int64_t)c * ldb + pos] = live ? (uint8_t)n : (uint8_t)0;
+        out[(int64_t)c * ld_out + pos] = live ? (C)n : (C)0;
     }
     if (live && tie) ties[r >> 9] = 1;
 }
@@ -155,11 +160,24 @@ hipError_t launch_byte_codes(const float *X, int64_t rows, int64_t ld, int32_t c
 {
     if (cols > kMaxByteCols || ldb % 512 != 0 || ldb < rows) return hipErrorInvalidValue;
     const size_t lds = (size_t)cols * 64 * sizeof(float);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_byte_codes),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_swar_codes<uint8_t>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_byte_codes, dim3((unsigned)(ldb / 64)), dim3(256), lds, s, X, rows, ld,
+    hipLaunchKernelGGL(k_swar_codes<uint8_t>, dim3((unsigned)(ldb / 64)), dim3(256), lds, s, X, rows, ld,
                        cols, fill, B, ldb, has_nan, ties);
+    return hipGetLastError();
+}
+
+hipError_t launch_half_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
+                             uint8_t *Hc, int64_t ldh, int32_t *has_nan, int32_t *ties, hipStream_t s)
+{
+    if (cols > kMaxCodeCols || ldh % 512 != 0 || ldh / 2 < rows) return hipErrorInvalidValue;
+    const size_t lds = (size_t)cols * 64 * sizeof(float);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_swar_codes<uint16_t>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_swar_codes<uint16_t>, dim3((unsigned)(ldh / 2 / 64)), dim3(256), lds, s, X, rows,
+                       ld, cols, fill, reinterpret_cast<uint16_t *>(Hc), ldh / 2, has_nan, ties);
     return hipGetLastError();
 }
 

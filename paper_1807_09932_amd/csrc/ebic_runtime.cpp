@@ -83,17 +83,22 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
     auto fits = [&](const LaunchCfg &c) { return lds(c) <= lds_max; };
     const bool have_codes = ((flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
     const bool have_bytes = m.dev.B && ((flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
-    // Byte codes hold four sub-tiles per lane word; without them for this
-    // mode, the 16-bit codes (or the FP32 tile) at the same shape.
-    // (one or two 256-row groups per chunk: L = 4 or 8; other stagings take
-    // at most 4).
-    if (cfg.staging == STAGE_BYTES) {
-        if (have_bytes) cfg.L = cfg.L >= 8 ? 8 : 4;
-        else cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
-    }
+    const bool have_halves = m.dev.Hc && ((flags & EBIC_NAN_INCLUDE) || m.dev.h_exclude);
+    // SWAR codes: bytes (up to 128 columns; one or two lane words per row,
+    // L = 4 or 8) or 16-bit codes (wider; two words, L = 4). A request
+    // without the one its shape asks for takes the other if the matrix has
+    // it, else the FP16 codes (or the FP32 tile) at the same shape.
+    if (cfg.staging == STAGE_BYTES && !have_bytes)
+        cfg.staging = have_halves ? STAGE_HALVES : (have_codes ? STAGE_CODES : STAGE_LDS);
+    if (cfg.staging == STAGE_HALVES && !have_halves)
+        cfg.staging = have_bytes ? STAGE_BYTES : (have_codes ? STAGE_CODES : STAGE_LDS);
+    if (cfg.staging == STAGE_BYTES) cfg.L = cfg.L >= 8 ? 8 : 4;
+    if (cfg.staging == STAGE_HALVES) cfg.L = 4;
+    if (cfg.staging == STAGE_HALVES && !fits(cfg)) cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
     if (cfg.staging == STAGE_BYTES && cfg.L == 8 && !fits(cfg)) cfg.L = 4;
     if (cfg.staging == STAGE_BYTES && !fits(cfg)) cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
     if (cfg.staging != STAGE_BYTES) cfg.L = std::min(cfg.L, 4);
+    if (cfg.staging == STAGE_HALVES) cfg.L = 4;
     // Rank codes need codes for this mode and at least two sub-tiles.
     if (cfg.staging == STAGE_CODES && (!have_codes || cfg.L < 2)) cfg.staging = STAGE_LDS;
     // An FP32 tile that does not fit: the codes' tile (half the bytes) at the
@@ -146,6 +151,14 @@ ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int3
         d.B = m.dev.B;
         d.T = m.dev.T;
         d.flags |= kFlagBytes;
+    }
+    if (staging == STAGE_HALVES) {
+        if (!m.dev.Hc || !(include || m.dev.h_exclude))
+            fail(EBIC_EINVAL, "no 16-bit rank codes for this matrix and mode");
+        d.B = m.dev.Hc;
+        d.T = m.dev.Th;
+        d.ldb = m.dev.ldh;
+        d.flags |= kFlagHalves;
     }
     if (staging == STAGE_DIRECT) {
         d.flags |= kFlagDirect;
@@ -267,6 +280,7 @@ ebic_status ebic_destroy(ebic_ctx *ctx)
                 ctx_free(ctx, kv.second.C);
                 ctx_free(ctx, kv.second.Cfill);
                 ctx_free(ctx, kv.second.B);
+                ctx_free(ctx, kv.second.Hc);
             }
             ctx->matrices.clear();
             destroy_batch_state(ctx);
@@ -405,8 +419,27 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
                 hip_check(hipMemcpyAsync(&has_nan, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s),
                           "hipMemcpyAsync");
             }
+            // 16-bit codes for the wider matrices (two rows per 32-bit word).
+            int32_t has_nan_h = 1;
+            if (cols > kMaxByteCols && cols <= kMaxCodeCols) {
+                const int64_t rows_pad = (rows + 255) / 256 * 256;
+                m.dev.ldh = rows_pad * 2;
+                const size_t hbytes = (size_t)m.dev.ldh * cols;
+                const size_t tbytes = (size_t)((rows_pad + 511) / 512) * sizeof(int32_t);
+                m.Hc = static_cast<uint8_t *>(ctx_alloc(ctx, hbytes + 256 + tbytes));
+                m.bytes += hbytes + 256 + tbytes;
+                int32_t *flag = reinterpret_cast<int32_t *>(m.Hc + hbytes);
+                int32_t *ties = reinterpret_cast<int32_t *>(m.Hc + hbytes + 256);
+                hip_check(hipMemsetAsync(flag, 0, 256 + tbytes, s), "hipMemsetAsync");
+                hip_check(launch_half_codes(m.X, rows, m.dev.ld, cols, missing_fill, m.Hc, m.dev.ldh, flag, ties, s),
+                          "16-bit codes kernel");
+                hip_check(hipMemcpyAsync(&has_nan_h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s),
+                          "hipMemcpyAsync");
+                m.dev.Th = ties;
+            }
             hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
             m.dev.b_exclude = m.B && has_nan == 0;
+            m.dev.h_exclude = m.Hc && has_nan_h == 0;
         } catch (...) {
             ctx_free(ctx, staging);
             ctx_free(ctx, m.X);
@@ -414,6 +447,7 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             ctx_free(ctx, m.C);
             ctx_free(ctx, m.Cfill);
             ctx_free(ctx, m.B);
+            ctx_free(ctx, m.Hc);
             throw;
         }
         ctx_free(ctx, staging);
@@ -422,6 +456,7 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
         m.dev.C = m.C;
         m.dev.Cfill = m.Cfill;
         m.dev.B = m.B;
+        m.dev.Hc = m.Hc;
         const int32_t id = ctx->next_matrix++;
         ctx->matrices[id] = m;
         *out_matrix = id;
@@ -454,6 +489,7 @@ ebic_status ebic_release_matrix(ebic_ctx *ctx, int32_t matrix)
         ctx_free(ctx, m.C);
         ctx_free(ctx, m.Cfill);
         ctx_free(ctx, m.B);
+        ctx_free(ctx, m.Hc);
         ctx->matrices.erase(matrix);
     });
 }

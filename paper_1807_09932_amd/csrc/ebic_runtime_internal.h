@@ -23,6 +23,7 @@ struct Matrix {
     uint16_t *C = nullptr;      // rank codes of X (cols <= kMaxCodeCols)
     uint16_t *Cfill = nullptr;  // rank codes of Xfill
     uint8_t *B = nullptr;       // byte rank codes (cols <= kMaxByteCols)
+    uint8_t *Hc = nullptr;      // 16-bit rank codes (kMaxByteCols < cols <= kMaxCodeCols)
     size_t bytes = 0;
     float sentinel = 0.f;
 };

@@ -44,7 +44,7 @@ static TuneKey batch_key(int64_t total_ind, int64_t mean_rows, int32_t max_cols)
 // Defaults measured on MI355X for the 436,444 x 64 workload: the byte rank
 // codes (four 64-row sub-tiles per lane word, two words per chunk) up to
 // 128 columns, sixteen waves per block, groups of 200 individuals; wider
-// matrices stage the 16-bit rank codes. A request without codes for its
+// matrices stage the 16-bit SWAR codes. A request without codes for its
 // mode falls back at launch.
 static int32_t default_L(int32_t cols) { return cols <= 64 ? 4 : (cols <= 128 ? 2 : 1); }
 
@@ -62,9 +62,9 @@ LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
         c.L = 8;
         c.P = std::max(1, std::min(n, 200));
     } else if (cols <= kMaxCodeCols) {
-        // The 16-bit rank codes' tile keeps two sub-tiles in LDS.
-        c.staging = STAGE_CODES;
-        c.L = 2;
+        // 16-bit rank codes, two rows per lane word, 256-row chunks.
+        c.staging = STAGE_HALVES;
+        c.L = 4;
     }
     c.blocks = 0;
     return c;
@@ -81,8 +81,8 @@ LaunchCfg default_batch_cfg(int32_t max_cols)
         c.staging = STAGE_BYTES;
         c.L = 4;
     } else if (max_cols <= kMaxCodeCols) {
-        c.staging = STAGE_CODES;
-        c.L = 2;
+        c.staging = STAGE_HALVES;
+        c.L = 4;
     }
     c.blocks = 0;
     return c;
@@ -227,7 +227,7 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
         if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 4 || tiles_per_wave == 8) ||
             waves_per_block < 1 || waves_per_block > 16 || individuals_per_group < 1 ||
             !(staging == STAGE_LDS || staging == STAGE_DIRECT || staging == STAGE_CODES ||
-              staging == STAGE_BYTES) ||
+              staging == STAGE_BYTES || staging == STAGE_HALVES) ||
             blocks < 0)
             fail(EBIC_EINVAL, "launch shape out of range");
         LaunchCfg c;
@@ -272,7 +272,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                           "hipMemcpy");
                 int64_t rows;
                 int32_t cols;
-                bool have_codes, have_bytes;
+                bool have_codes, have_bytes, have_halves;
                 {
                     std::lock_guard<std::mutex> lk(ctx->mu);
                     const Matrix &m = ctx_matrix(ctx, r.matrix);
@@ -280,6 +280,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                     cols = m.dev.cols;
                     have_codes = ((r.flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
                     have_bytes = m.dev.B && ((r.flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
+                    have_halves = m.dev.Hc && ((r.flags & EBIC_NAN_INCLUDE) || m.dev.h_exclude);
                 }
                 const TuneKey key = tune_key(rows, cols, r.n_ind, (int64_t)ends[1] - ends[0]);
                 if (!done.insert(key).second) continue;
@@ -289,7 +290,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                     for (int W : {4, 8, 16})
                         for (int P : {200, 400, 800, 1600})
                             for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT, (int)STAGE_CODES,
-                                            (int)STAGE_BYTES}) {
+                                            (int)STAGE_BYTES, (int)STAGE_HALVES}) {
                                 LaunchCfg c;
                                 c.L = L;
                                 c.W = W;
@@ -301,6 +302,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                                 if (stg == STAGE_CODES && (L < 2 || !have_codes)) continue;
                                 if (stg == STAGE_BYTES && (L < 4 || !have_bytes)) continue;
                                 if (L == 8 && stg != STAGE_BYTES) continue;  // eight sub-tiles: byte codes only
+                                if (stg == STAGE_HALVES && (L != 4 || !have_halves)) continue;
                                 set_override(c);
                                 const float ms = time_ms(
                                     [&] {
@@ -342,9 +344,10 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                     for (int L : {1, 2, 4})
                         for (int W : {4, 8, 16})
                             for (int P : {128, 256, 512, 1024})
-                                for (int stg : {(int)STAGE_LDS, (int)STAGE_CODES, (int)STAGE_BYTES}) {
+                                for (int stg : {(int)STAGE_LDS, (int)STAGE_CODES, (int)STAGE_BYTES,
+                                                (int)STAGE_HALVES}) {
                                 if (stg == STAGE_CODES && L < 2) continue;
-                                if (stg == STAGE_BYTES && L != 4) continue;
+                                if ((stg == STAGE_BYTES || stg == STAGE_HALVES) && L != 4) continue;
                                 LaunchCfg c;
                                 c.L = L;
                                 c.W = W;

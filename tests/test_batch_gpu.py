@@ -99,19 +99,21 @@ def test_batched_many_matrices_and_modes(ctx):
 
 
 def test_batch_byte_codes(ctx):
-    """The batched kernel with the byte rank codes forced: requests on a
-    matrix without missing cells (byte codes in both modes) and on one with
-    them (byte codes in include mode only), masks on and off."""
+    """The batched kernel with the SWAR codes forced: requests on a matrix
+    without missing cells (byte codes in both modes), on one with them (byte
+    codes in include mode only) and on a 230-column one (16-bit codes),
+    masks on and off."""
     from paper_1807_09932_amd import ebic
     rng = np.random.default_rng(44)
     Xa = rng.integers(0, 7, size=(4099, 64)).astype(np.float32)
     Xb = rng.standard_normal((1030, 100)).astype(np.float32)
     Xb[rng.random(Xb.shape) < 0.03] = np.float32(np.nan)
-    mats = [ctx.upload(Xa), ctx.upload(Xb, fill=0.25)]
-    Xs = [Xa, Xb]
+    Xc = np.round(rng.standard_normal((2050, 230)), 1).astype(np.float32)  # 16-bit codes, ties
+    mats = [ctx.upload(Xa), ctx.upload(Xb, fill=0.25), ctx.upload(Xc)]
+    Xs = [Xa, Xb, Xc]
     jobs, want = [], []
-    for q in range(12):
-        m = q % 2
+    for q in range(18):
+        m = q % 3
         (offs, cols), = _pops(300 + q, Xs[m].shape[1], 1, (1, 220), lambda r: int(r.integers(1, 31)))
         include, negative, masks = bool(q & 2), bool(q & 4), bool(q & 1)
         jobs.append((mats[m], (offs, cols), include, negative, masks))

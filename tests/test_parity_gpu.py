@@ -213,6 +213,64 @@ def test_byte_codes_special_values(ctx, ncols, rows, tiles):
             ctx.release(mat)
 
 
+@pytest.mark.parametrize("ncols", [129, 256, 384])
+@pytest.mark.parametrize("rows", [1, 257, 777, 3001])
+def test_halves_special_values(ctx, ncols, rows):
+    """16-bit SWAR codes (two rows per 32-bit lane word, matrices of 129 to
+    384 columns) on the special values (+-inf, +-0, denormals, ties): both
+    modes and trend settings without missing cells; with them, include mode
+    uses the codes and exclude mode falls back. Individuals of up to 30
+    columns reach past the 8-column window."""
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(1300 + ncols + rows)
+    X = _special(rng, (rows, ncols))
+    Xn = X.copy()
+    Xn[rng.random(X.shape) < 0.04] = np.float32(np.nan)
+    offs, cols = _random_pop(rng, ncols, 120, 30, dup=0.1, bad=0.02)
+    for name, A in (("no missing", X), ("missing", Xn)):
+        mat = ctx.upload(A, fill=-0.0)
+        try:
+            ctx.set_launch_shape(4, 8, 64, ebic.STAGE_HALVES, 0)
+            plan = ebic.ebic_plan_shape(ctx.handle, mat, offs.size - 1, int(offs[-1]))
+            if np.isnan(A).any():
+                assert plan[3] != ebic.STAGE_HALVES
+            elif ncols <= 256:  # (wider tiles do not fit the LDS and fall back)
+                assert plan[3] == ebic.STAGE_HALVES
+            for include in (False, True):
+                for negative in (False, True):
+                    announce("halves", rows, ncols, name, include, negative)
+                    got = gpu_eval(ctx, mat, offs, cols, include=include, negative=negative)
+                    want = oracle_eval(A, offs, cols, include=include, negative=negative, fill=-0.0)
+                    assert_same(got, want, f"halves {rows}x{ncols} {name} include={include} "
+                                           f"negative={negative}")
+        finally:
+            ctx.set_launch_shape()
+            ctx.release(mat)
+
+
+@pytest.mark.parametrize("shape", [(4, 16, 400, 4, 0), (4, 3, 33, 4, 1), (4, 5, 200, 4, 7),
+                                   (2, 8, 64, 4, 0)], ids=lambda s: "L{}W{}P{}S{}B{}".format(*s))
+def test_halves_launch_shapes(ctx, shape):
+    """16-bit SWAR codes on a 200-column matrix with many ties (integers
+    0..5) and missing cells, in several launch shapes."""
+    rng = np.random.default_rng(1400)
+    rows, ncols = 5000 + 37, 200
+    X = rng.integers(0, 6, size=(rows, ncols)).astype(np.float32)
+    X[rng.random((rows, ncols)) < 0.03] = np.float32(np.nan)
+    offs, cols = _random_pop(rng, ncols, 301, 14, dup=0.05, bad=0.03)
+    mat = ctx.upload(X, fill=2.5)
+    try:
+        ctx.set_launch_shape(*shape)
+        for include in (False, True):
+            announce("halves shape", shape, include)
+            got = gpu_eval(ctx, mat, offs, cols, include=include)
+            want = oracle_eval(X, offs, cols, include=include, fill=2.5)
+            assert_same(got, want, f"halves shape {shape} include={include}")
+    finally:
+        ctx.set_launch_shape()
+        ctx.release(mat)
+
+
 def test_invalid_and_degenerate_individuals(ctx):
     rng = np.random.default_rng(400)
     X = rng.standard_normal((1000, 10)).astype(np.float32)
@@ -315,16 +373,18 @@ def test_error_paths(ctx):
     assert e.value.status == ebic.EBIC_ENOENT
 
 
-@pytest.mark.parametrize("tiles_per_wave,staging", [(1, 0), (2, 0), (4, 0), (2, 2), (4, 2), (4, 3), (8, 3)])
+@pytest.mark.parametrize("tiles_per_wave,staging", [(1, 0), (2, 0), (4, 0), (2, 2), (4, 2), (4, 3), (8, 3),
+                                                    (4, 4)])
 def test_measurement_variant_agrees(ctx, tiles_per_wave, staging):
     """The step-counting kernel variant (profiling mode 2) computes the same
     outputs as the timed one, and counts a positive number of steps."""
     from paper_1807_09932_amd import ebic
     rng = np.random.default_rng(700 + tiles_per_wave)
-    X = rng.integers(0, 5, size=(3000, 30)).astype(np.float32)
-    if staging != ebic.STAGE_BYTES:  # (byte codes serve exclude mode without missing cells)
+    ncols = 150 if staging == ebic.STAGE_HALVES else 30  # (16-bit codes: over 128 columns)
+    X = rng.integers(0, 5, size=(3000, ncols)).astype(np.float32)
+    if staging < ebic.STAGE_BYTES:  # (SWAR codes serve exclude mode without missing cells)
         X[rng.random(X.shape) < 0.02] = np.float32(np.nan)
-    offs, cols = _random_pop(rng, 30, 150, 20, dup=0.05, bad=0.02)
+    offs, cols = _random_pop(rng, ncols, 150, 20, dup=0.05, bad=0.02)
     mat = ctx.upload(X, keep_fill_copy=True)
     try:
         ctx.set_launch_shape(tiles_per_wave, 4, 50, staging, 0)
