@@ -37,7 +37,11 @@ CMP_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # steps cost five ops (four v_xad_u32 and one three-input AND): peak
 # 4 / 2.5 x 39.3 = 62.9 T row-checks/s.
 BYTE_PEAK_TOPS = CMP_PEAK_TOPS * 4 / 2.5
+# 16-bit rank codes: the same five ops per two column steps cover two rows
+# per lane op: peak 2 / 2.5 x 39.3 = 31.5 T row-checks/s.
+HALF_PEAK_TOPS = CMP_PEAK_TOPS * 2 / 2.5
 STAGE_BYTES = 3
+STAGE_HALVES = 4
 
 
 def alu_roofline(steps, k_ms, staging):
@@ -45,9 +49,10 @@ def alu_roofline(steps, k_ms, staging):
     variant (compare instructions, or 64-row sub-tile column steps with byte
     codes) x 64 rows over the kernel time, against the peak of that staging."""
     ach = steps * 64 / (k_ms * 1e-3) / 1e12
-    if staging == STAGE_BYTES:
-        return {"bound": "alu", "achieved": ach, "peak": BYTE_PEAK_TOPS, "unit": "T row-checks/s",
-                "frac": ach / BYTE_PEAK_TOPS}
+    if staging in (STAGE_BYTES, STAGE_HALVES):
+        peak = BYTE_PEAK_TOPS if staging == STAGE_BYTES else HALF_PEAK_TOPS
+        return {"bound": "alu", "achieved": ach, "peak": peak, "unit": "T row-checks/s",
+                "frac": ach / peak}
     return {"bound": "alu", "achieved": ach, "peak": CMP_PEAK_TOPS, "unit": "T compare lane-ops/s",
             "frac": ach / CMP_PEAK_TOPS}
 
@@ -189,6 +194,7 @@ def bench_batched(ctx, args):
     n_l, l_ms, _ = ebic.ebic_read_profile(ctx.handle)
     ebic.ebic_set_profiling(ctx.handle, 0)
     g_ms = l_ms / max(1, n_l)
+    bL, bW, bP, b_stg, b_grid = ebic.ebic_plan_batch_shape(ctx.handle, reqs)
     ctx.release(mat)
     return {
         "workload": "64 populations (%d individuals, lengths 2 + min(38, Exp(mean 5)), "
@@ -200,7 +206,9 @@ def bench_batched(ctx, args):
         "equal_results": True,
         "graph_ms": g_ms,
         "executed_compares": b_steps,
-        "roofline": alu_roofline(b_steps, g_ms, None),
+        "launch_shape": "L=%d W=%d P=%d stagings=%s blocks=%d" % (bL, bW, bP, sorted(set(b_stg)),
+                                                                  b_grid),
+        "roofline": alu_roofline(b_steps, g_ms, b_stg[0] if len(set(b_stg)) == 1 else None),
         "timing": "median of %d synchronised calls; batched = one ebic_eval_batch (descriptor "
                   "copy + graph replay), plain = 64 ebic_eval_population calls" % reps,
     }
@@ -688,9 +696,10 @@ def main():
             "kernel_ms_cold_cache": cold_ms,
             "ops": (("row checks executed per launch: %d steps x 64 rows (one step = one column "
                      "of one 64-row sub-tile; the first pair counts one step; early exit per "
-                     "256-row chunk), counted by the measurement variant of the kernel; peak = "
-                     "39.3e12 32-bit VALU lane ops/s x 4 rows per lane op / 2.5 ops per column "
-                     "step" % executed_steps) if stg == STAGE_BYTES else
+                     "chunk of two lane words per lane), counted by the measurement variant of "
+                     "the kernel; peak = 39.3e12 32-bit VALU lane ops/s x %d rows per lane op / "
+                     "2.5 ops per column step" % (executed_steps, 4 if stg == STAGE_BYTES else 2))
+                    if stg in (STAGE_BYTES, STAGE_HALVES) else
                     ("FP32 compares executed per launch: %d wave-wide compare instructions x 64 "
                      "rows (first pair: 3 per 64-row tile, then 1 per column step of each row's "
                      "oriented chain; early exit per group of tiles), counted by the measurement "

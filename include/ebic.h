@@ -201,10 +201,16 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
  *   staging:               0 = column tiles staged in LDS, 1 = direct reads,
  *                          2 = the rank codes staged in LDS (2 or 4 sub-tiles;
  *                              include mode needs EBIC_KEEP_FILL_COPY),
- *                          3 = the byte rank codes staged in LDS (4 sub-tiles;
+ *                          3 = the byte rank codes staged in LDS (4 or 8
+ *                              sub-tiles; matrices of at most 128 columns;
  *                              exclude mode needs a matrix without missing
- *                              cells); without codes for the request's mode
- *                              the launch takes another staging
+ *                              cells),
+ *                          4 = the 16-bit rank codes staged in LDS (4
+ *                              sub-tiles; 129 .. 384 columns; the same
+ *                              condition for exclude mode); 3 and 4 select
+ *                              whichever of the two the matrix has; without
+ *                              codes for the request's mode the launch takes
+ *                              another staging
  *   blocks:                grid size per group, 0 = from occupancy
  * Shapes that do not fit the device are reduced at launch (fewer tiles per
  * wave, then direct reads). Results never depend on the shape.
@@ -217,12 +223,24 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
  * or -1 if unknown) on `matrix` would use now: the forced shape if one is
  * set, else the tuned one for its shape class, else the default, reduced to
  * what the device fits. Any output may be NULL. Staging: 0 = LDS, 1 = direct,
- * 2 = rank codes in LDS, 3 = byte rank codes in LDS (the staging planned
- * for exclude mode).
+ * 2 = rank codes in LDS, 3 = byte rank codes in LDS, 4 = 16-bit rank codes in
+ * LDS (the staging planned for exclude mode).
  */
 ebic_status ebic_plan_shape(ebic_ctx *ctx, int32_t matrix, int32_t n_ind, int64_t nnz,
                             int32_t *tiles_per_wave, int32_t *waves_per_block,
                             int32_t *individuals_per_group, int32_t *staging, int32_t *blocks);
+
+/*
+ * The launch shape ebic_eval_batch would use now for `reqs` (the same
+ * validation, no launch): tiles per wave, waves per block, individuals per
+ * group, the grid size, and, if `stagings` is not NULL, the staging of each
+ * request (n_reqs entries, numbered as for ebic_plan_shape). Any output may
+ * be NULL.
+ */
+ebic_status ebic_plan_batch_shape(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs,
+                                  int32_t *tiles_per_wave, int32_t *waves_per_block,
+                                  int32_t *individuals_per_group, int32_t *stagings,
+                                  int32_t *blocks);
 
 /*
  * Measurement diagnostics. `mode` bit 0: record a HIP event pair on the

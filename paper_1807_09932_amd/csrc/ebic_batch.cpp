@@ -111,6 +111,7 @@ struct Plan {
     std::vector<ReqDesc> descs;
     std::vector<int64_t> first;
     std::vector<Item> items;
+    std::vector<int32_t> stagings;  // per request
     size_t tile_bytes = 0;
     int64_t total_ind = 0;
     int32_t grid = 0;
@@ -175,6 +176,7 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
         ReqDesc d = make_desc(m, std::max(0, r.n_ind), r.d_offsets, r.d_cols, r.flags, r.d_matched,
                               r.d_negative, r.d_matched_mask, r.d_negative_mask, staging);
         d.head_base = p.first.back();
+        p.stagings.push_back(staging);
         p.tile_bytes = std::max(p.tile_bytes, tile_lds_bytes(c.L, m.dev.cols, staging));
         p.descs.push_back(d);
         p.first.push_back(p.first.back() + d.n);
@@ -314,6 +316,26 @@ static std::unique_ptr<GraphEntry> capture_graph(ebic_ctx *ctx, const GraphSpec 
 }  // namespace ebic
 
 using namespace ebic;
+
+extern "C" ebic_status ebic_plan_batch_shape(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs,
+                                             int32_t *tiles_per_wave, int32_t *waves_per_block,
+                                             int32_t *individuals_per_group, int32_t *stagings,
+                                             int32_t *blocks)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        if (n_reqs < 1 || !reqs) fail(EBIC_EINVAL, "need at least one request");
+        DeviceGuard dg(ctx->device);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        const Plan p = plan_batch(ctx, reqs, n_reqs, false);
+        if (tiles_per_wave) *tiles_per_wave = p.cfg.L;
+        if (waves_per_block) *waves_per_block = p.cfg.W;
+        if (individuals_per_group) *individuals_per_group = p.cfg.P;
+        if (blocks) *blocks = p.grid;
+        if (stagings)
+            for (int32_t q = 0; q < n_reqs; ++q) stagings[q] = p.stagings[q];
+    });
+}
 
 extern "C" ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs,
                                        void *hip_stream)

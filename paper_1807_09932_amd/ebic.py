@@ -46,7 +46,7 @@ EXPORTED = ["ebic_create", "ebic_destroy", "ebic_set_allocator", "ebic_last_erro
             "ebic_upload_matrix", "ebic_matrix_info", "ebic_release_matrix",
             "ebic_mask_words", "ebic_eval_population", "ebic_eval_batch", "ebic_autotune",
             "ebic_set_launch_shape", "ebic_set_profiling", "ebic_read_profile",
-            "ebic_plan_shape", "ebic_server_request_bytes", "ebic_server_create",
+            "ebic_plan_shape", "ebic_plan_batch_shape", "ebic_server_request_bytes", "ebic_server_create",
             "ebic_server_destroy", "ebic_server_submit", "ebic_server_poll",
             "ebic_server_get_stats", "ebic_ea_create", "ebic_ea_destroy", "ebic_ea_population",
             "ebic_ea_step", "ebic_read_delimited", "ebic_free_text_matrix",
@@ -123,6 +123,8 @@ def load_library(path: str = LIB_PATH):
         "ebic_set_launch_shape": (I32, [P, I32, I32, I32, I32, I32]),
         "ebic_set_profiling": (I32, [P, I32]),
         "ebic_plan_shape": (I32, [P, I32, I32, I64] + [ctypes.POINTER(I32)] * 5),
+        "ebic_plan_batch_shape": (I32, [P, ctypes.POINTER(ebic_request), I32]
+                                  + [ctypes.POINTER(I32)] * 5),
         "ebic_read_profile": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(I64)]),
         "ebic_server_request_bytes": (I32, [P, I32, I32, I64, U32, I32, ctypes.POINTER(I64)]),
@@ -233,6 +235,18 @@ def ebic_plan_shape(ctx: int, matrix: int, n_ind: int, nnz: int = -1) -> Tuple[i
     v = [ctypes.c_int32() for _ in range(5)]
     _check(load_library().ebic_plan_shape(ctx, matrix, n_ind, nnz, *[ctypes.byref(x) for x in v]))
     return tuple(x.value for x in v)
+
+
+def ebic_plan_batch_shape(ctx: int, reqs: Sequence[ebic_request]) -> Tuple[int, int, int, List[int], int]:
+    """(tiles_per_wave, waves_per_block, individuals_per_group, per-request
+    stagings, blocks) of the batched launch for `reqs`."""
+    arr = (ebic_request * len(reqs))(*reqs)
+    v = [ctypes.c_int32() for _ in range(4)]
+    st = (ctypes.c_int32 * len(reqs))()
+    _check(load_library().ebic_plan_batch_shape(ctx, arr, len(reqs), ctypes.byref(v[0]),
+                                                ctypes.byref(v[1]), ctypes.byref(v[2]), st,
+                                                ctypes.byref(v[3])))
+    return v[0].value, v[1].value, v[2].value, list(st), v[3].value
 
 
 def ebic_set_profiling(ctx: int, mode: int) -> None:

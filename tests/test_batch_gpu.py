@@ -28,15 +28,19 @@ def _pops(seed, ncols, n_pops, n_range, length_fn):
     return pops
 
 
-def _run_batch(ctx, jobs, stream=None):
-    """jobs: list of (matrix handle, (offs, cols), include, negative, masks)."""
+def _run_batch(ctx, jobs, stream=None, plan=None):
+    """jobs: list of (matrix handle, (offs, cols), include, negative, masks).
+    If `plan` is a list, the batch's planned launch shape is appended to it."""
     import torch
+    from paper_1807_09932_amd import ebic
     reqs, outs = [], []
     for mat, (offs, cols), include, negative, masks in jobs:
         pop = ctx.population(offsets=offs, cols=cols)
         out = ctx.outputs(mat, pop.n, masks=masks, negative=True)
         outs.append((pop, out))
         reqs.append(ctx.request(mat, pop, out, include=include, negative=negative))
+    if plan is not None:
+        plan.append(ebic.ebic_plan_batch_shape(ctx.handle, reqs))
     ctx.eval_batch(reqs, stream=stream)
     torch.cuda.synchronize()
     return [tuple(to_np(t) for t in out) for _, out in outs]
@@ -122,9 +126,20 @@ def test_batch_byte_codes(ctx):
     try:
         ctx.set_launch_shape(4, 8, 128, ebic.STAGE_BYTES, 0)
         announce("batch byte codes")
-        got = _run_batch(ctx, jobs)
+        plan = []
+        got = _run_batch(ctx, jobs, plan=plan)
         for q in range(len(jobs)):
             assert_same(got[q], want[q], f"request {q}")
+        L, W, P, stagings, _ = plan[0]
+        assert (L, W, P) == (4, 8, 128)
+        for q, (m, _, include, _, _) in enumerate(jobs):
+            k = mats.index(m)
+            # byte codes on the 64- and 100-column matrices (the latter has
+            # missing cells, so exclude mode takes the FP16 codes there);
+            # 16-bit codes on the 230-column one
+            expect = (ebic.STAGE_HALVES if k == 2 else
+                      ebic.STAGE_BYTES if (k == 0 or include) else ebic.STAGE_CODES)
+            assert stagings[q] == expect, (q, k, include, stagings[q])
     finally:
         ctx.set_launch_shape()
         for m in mats:
