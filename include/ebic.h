@@ -205,7 +205,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
  *                              sub-tiles; matrices of at most 128 columns;
  *                              exclude mode needs a matrix without missing
  *                              cells),
- *                          4 = the 16-bit rank codes staged in LDS (4
+ *                          4 = the 16-bit rank codes staged in LDS (2 or 4
  *                              sub-tiles; 129 .. 384 columns; the same
  *                              condition for exclude mode); 3 and 4 select
  *                              whichever of the two the matrix has; without

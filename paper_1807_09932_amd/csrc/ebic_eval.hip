@@ -703,10 +703,10 @@ __device__ __forceinline__ void eval_lds_il(const unsigned char *__restrict__ ti
 // five VALU operations per two columns of 256 rows. `alive` keeps bit 7 of
 // the bytes of the rows still on their chain (it starts from the in-range
 // rows). Rows tied on the first pair then run the <= chain on their own:
-// every code mirrored, fH = 0xFFFFFFFF, nf = 0x80808080.
+// every code mirrored, fH = 0xFFFFFFFF, nf = 0x80808080. The same sequences
+// run on 16-bit parts (codes below 2^15, two rows per word: rows l and
+// 64 + l of a 128-row group) with the constants of Lanes<16>.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kByteHi = 0x80808080u;
-
 // Lane parts of BITS bits (codes below 2^(BITS-1)): the constants of the
 // arithmetic above.
 template <int BITS> struct Lanes;
@@ -1066,11 +1066,28 @@ __device__ __forceinline__ void byte_masks4(uint32_t x, uint64_t &m0, uint64_t &
         : [x] "v"(x));
 }
 
-__device__ __forceinline__ void byte_masks(uint32_t x, uint64_t (&m)[4]) { byte_masks4(x, m[0], m[1], m[2], m[3]); }
+// Wave-wide masks of the two 64-row sub-tiles of a word of 16-bit parts.
+__device__ __forceinline__ void half_masks2(uint32_t x, uint64_t &m0, uint64_t &m1)
+{
+    asm volatile(
+        "v_cmp_ne_u32_sdwa %[m0], %[x], 0 src0_sel:WORD_0 src1_sel:DWORD\n\t"
+        "v_cmp_ne_u32_sdwa %[m1], %[x], 0 src0_sel:WORD_1 src1_sel:DWORD\n\t"
+        "s_nop 1"
+        : [m0] "=s"(m0), [m1] "=s"(m1)
+        : [x] "v"(x));
+}
+
+// The sub-tile masks of a word (BITS-bit parts; the top bit of each part).
+template <int BITS>
+__device__ __forceinline__ void lane_masks(uint32_t x, uint64_t *m)
+{
+    if constexpr (BITS == 8) byte_masks4(x, m[0], m[1], m[2], m[3]);
+    else half_masks2(x, m[0], m[1]);
+}
 
 // Plain-code twin of the window (the measurement variant): the same exit
-// points; counts one step per 64-row sub-tile and column.
-template <int SH, bool COUNT>
+// points; counts one step per 64-row sub-tile (NP per word) and column.
+template <int SH, bool COUNT, int NP = 4>
 __device__ __forceinline__ void by_window_ref(const unsigned char *__restrict__ base, const int32_t (&w)[kWin],
                                               int32_t last, uint32_t fH, uint32_t nf, uint32_t nx,
                                               uint32_t &alive, uint64_t &steps)
@@ -1080,7 +1097,7 @@ __device__ __forceinline__ void by_window_ref(const unsigned char *__restrict__ 
         const uint32_t t = *reinterpret_cast<const uint32_t *>(base + (w[u] << SH));
         alive &= (t ^ fH) + nx;
         nx = (t ^ nf) + 1u;
-        if (COUNT) steps += 4;
+        if (COUNT) steps += NP;
         if (u == 3 && last <= 3) return;
         if (u == 5 && (__ballot(alive != 0) == 0 || last <= 5)) return;
     }
@@ -1103,94 +1120,78 @@ __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, 
     }
 }
 
-// One individual on a chunk of byte rank codes (four 64-row sub-tiles).
-// `hv` holds bit 7 of the bytes of the rows inside the item and the matrix.
-// The byte codes have no missing value (exclude mode uses them only on a
-// matrix without missing cells; include mode's codes encode the fill).
-// Returns false, and leaves M and G unset, when no row matches.
-template <int SH, bool NEG, bool COUNT>
+// One individual on one lane word of SWAR rank codes per row group: four
+// 64-row sub-tiles of byte codes (BITS = 8) or two of 16-bit codes
+// (BITS = 16). `hv` holds the top bit of the parts whose rows are inside
+// the item and the matrix. The codes have no missing value (exclude mode
+// uses them only on a matrix without missing cells; include mode's codes
+// encode the fill). Returns false, and leaves M and G (one mask per
+// sub-tile) unset, when no row matches.
+template <int SH, bool NEG, bool COUNT, int BITS = 8>
 __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ tile, int32_t last,
                                            const int32_t *__restrict__ colidx,
                                            const int32_t *__restrict__ hbegin, const int4 &w03, const int4 &w47,
-                                           int lane, uint32_t hv, uint64_t (&M)[4], uint64_t (&G)[4],
-                                           uint64_t &steps)
+                                           int lane, uint32_t hv, uint64_t *M, uint64_t *G, uint64_t &steps)
 {
+    using T = Lanes<BITS>;
+    constexpr int NP = T::PARTS;
     const unsigned char *base = tile + 4 * lane;
     const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
     auto rd = [&](int32_t col) { return *reinterpret_cast<const uint32_t *>(base + (col << SH)); };
     if (last == 0) {  // one column: every row in range counts
-        byte_masks(hv, M);
+        lane_masks<BITS>(hv, M);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) G[s] = 0;
-        if (COUNT) steps += 4;
+        for (int s = 0; s < NP; ++s) G[s] = 0;
+        if (COUNT) steps += NP;
         return true;
     }
     uint32_t alive, fall = 0, tied = 0;
     if constexpr (COUNT) {
         const uint32_t t0 = rd(w[0]), t1 = rd(w[1]);
-        const uint32_t D = (t1 | kByteHi) - t0, E = (t0 | kByteHi) - t1;
-        uint32_t fH = kByteHi, nf = ~0u;
+        const uint32_t D = (t1 | T::H) - t0, E = (t0 | T::H) - t1;
+        uint32_t fH = T::H, nf = ~0u;
         alive = D & hv;
         if constexpr (NEG) {
             tied = D & E & hv;
             fall = E & ~D & hv;
-            const uint32_t fm = fall - (fall >> 7);
-            fH = fm | kByteHi;
+            const uint32_t fm = fall - (fall >> T::SHF);
+            fH = fm | T::H;
             nf = ~fm;
             alive = hv;
         }
-        steps += 4;
-        if (last >= 2) by_window_ref<SH, COUNT>(base, w, last, fH, nf, (t1 ^ nf) + 1u, alive, steps);
+        steps += NP;
+        if (last >= 2) by_window_ref<SH, COUNT, NP>(base, w, last, fH, nf, (t1 ^ nf) + 1u, alive, steps);
         if (NEG && last >= 2 && __ballot(tied != 0) != 0) {
-            steps += 4;
-            by_window_ref<SH, COUNT>(base, w, last, ~0u, kByteHi, (t1 ^ kByteHi) + 1u, tied, steps);
+            steps += NP;
+            by_window_ref<SH, COUNT, NP>(base, w, last, ~0u, T::H, (t1 ^ T::H) + 1u, tied, steps);
         } else {
             tied = 0;
         }
     } else {
         const uint32_t b = lds_addr(base);
-        if constexpr (NEG) by_neg<SH>(b, w, last, hv, alive, fall, tied);
-        else by_pos<SH>(b, w, last, hv, alive);
+        if constexpr (NEG) by_neg<SH, BITS>(b, w, last, hv, alive, fall, tied);
+        else by_pos<SH, BITS>(b, w, last, hv, alive);
     }
     if (last >= kWin) {
         // The columns past the window (the CSR start is read only here).
         const int32_t *c = colidx + *hbegin;
         if constexpr (NEG) {
-            const uint32_t fm = fall - (fall >> 7);
-            by_tail<SH, COUNT>(base, c, w, last, fm | kByteHi, ~fm, alive, steps);
-            by_tail<SH, COUNT>(base, c, w, last, ~0u, kByteHi, tied, steps);
+            const uint32_t fm = fall - (fall >> T::SHF);
+            by_tail<SH, COUNT, NP>(base, c, w, last, fm | T::H, ~fm, alive, steps);
+            by_tail<SH, COUNT, NP>(base, c, w, last, ~0u, T::H, tied, steps);
         } else {
-            by_tail<SH, COUNT>(base, c, w, last, kByteHi, ~0u, alive, steps);
+            by_tail<SH, COUNT, NP>(base, c, w, last, T::H, ~0u, alive, steps);
         }
     }
     const uint32_t mw = alive | tied;
     if (__ballot(mw != 0) == 0) return false;
-    byte_masks(mw, M);
-    if constexpr (NEG) byte_masks((alive & fall) | (tied & ~alive), G);
+    lane_masks<BITS>(mw, M);
+    if constexpr (NEG) lane_masks<BITS>((alive & fall) | (tied & ~alive), G);
     else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) G[s] = 0;
+        for (int s = 0; s < NP; ++s) G[s] = 0;
     }
     return true;
-}
-
-// Wave-wide masks of the two 64-row sub-tiles of a word of 16-bit parts.
-__device__ __forceinline__ void half_masks2(uint32_t x, uint64_t &m0, uint64_t &m1)
-{
-    asm volatile(
-        "v_cmp_ne_u32_sdwa %[m0], %[x], 0 src0_sel:WORD_0 src1_sel:DWORD\n\t"
-        "v_cmp_ne_u32_sdwa %[m1], %[x], 0 src0_sel:WORD_1 src1_sel:DWORD\n\t"
-        "s_nop 1"
-        : [m0] "=s"(m0), [m1] "=s"(m1)
-        : [x] "v"(x));
-}
-
-// The sub-tile masks of a word (BITS-bit parts; the top bit of each part).
-template <int BITS>
-__device__ __forceinline__ void lane_masks(uint32_t x, uint64_t *m)
-{
-    if constexpr (BITS == 8) byte_masks4(x, m[0], m[1], m[2], m[3]);
-    else half_masks2(x, m[0], m[1]);
 }
 
 // Plain-code twin of the two-word window (the measurement variant): both
@@ -1470,7 +1471,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         uint32_t hvalid[NWORDS] = {};
         bool ties = true;
         if constexpr (kSwar) {
-            static_assert(STAGE == STAGE_HALVES ? L == 4 : (L == 4 || L == 8),
+            static_assert(STAGE == STAGE_HALVES ? (L == 2 || L == 4) : (L == 4 || L == 8),
                           "one or two lane words per row of a chunk");
             ties = tie_pre != 0;
             // The L * 64 rows [row0, row0 + 64 L) of every column, in their
@@ -1563,26 +1564,22 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
 #pragma unroll
                         for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
                     }
-                } else if constexpr (STAGE == STAGE_BYTES) {
+                } else if constexpr (kSwar) {
+                    // One lane word per row: four byte sub-tiles or two
+                    // 16-bit ones.
                     live = false;
+                    const bool any = eval_bytes<8, NEG, COUNT, BITS>(
+                        reinterpret_cast<const unsigned char *>(tile), k - 1, d.colidx, &hb[ii].begin, hv[1],
+                        hv[2], lane, hvalid[0], M, G, steps);
+                    if (any) {
 #pragma unroll
-                    for (int h = 0; h < L / 4; ++h) {
-                        uint64_t Mh[4], Gh[4];
-                        const bool any = eval_bytes<L == 8 ? 9 : 8, NEG, COUNT>(
-                            reinterpret_cast<const unsigned char *>(tile) + 256 * h, k - 1, d.colidx, &hb[ii].begin,
-                            hv[1], hv[2], lane, hvalid[h], Mh, Gh, steps);
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            M[4 * h + s] = any ? Mh[s] : 0;
-                            G[4 * h + s] = any ? Gh[s] : 0;
+                        for (int s = 0; s < L; ++s) {
+                            pm += __popcll(M[s]);
+                            pg += __popcll(G[s]);
                         }
-                        if (any) {
+                    } else {
 #pragma unroll
-                            for (int s = 0; s < 4; ++s) {
-                                pm += __popcll(Mh[s]);
-                                pg += __popcll(Gh[s]);
-                            }
-                        }
+                        for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
                     }
                 } else if constexpr (STAGE == STAGE_CODES) {
                     static_assert(L >= 2, "rank codes are staged for 2 or 4 sub-tiles");
@@ -1720,6 +1717,8 @@ k_eval_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs, const Item *__
                 else run_item<L, false, STAGE_BYTES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
                 continue;
             }
+        }
+        if constexpr (L == 2 || L == 4) {  // 16-bit codes: one or two lane words
             if (d.flags & kFlagHalves) {
                 if (neg) run_item<L, true, STAGE_HALVES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
                 else run_item<L, false, STAGE_HALVES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
@@ -1783,7 +1782,8 @@ const void *eval_pick(int L, bool neg, int staging)
         if (L == 8) return neg ? eval_ptr<8, true, STAGE_BYTES, COUNT>() : eval_ptr<8, false, STAGE_BYTES, COUNT>();
         return nullptr;
     }
-    if (staging == STAGE_HALVES) {  // two lane words of two rows per 256-row chunk
+    if (staging == STAGE_HALVES) {  // one or two lane words of two rows per chunk
+        if (L == 2) return neg ? eval_ptr<2, true, STAGE_HALVES, COUNT>() : eval_ptr<2, false, STAGE_HALVES, COUNT>();
         if (L == 4) return neg ? eval_ptr<4, true, STAGE_HALVES, COUNT>() : eval_ptr<4, false, STAGE_HALVES, COUNT>();
         return nullptr;
     }

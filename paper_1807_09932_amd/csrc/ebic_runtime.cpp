@@ -85,20 +85,21 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
     const bool have_bytes = m.dev.B && ((flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
     const bool have_halves = m.dev.Hc && ((flags & EBIC_NAN_INCLUDE) || m.dev.h_exclude);
     // SWAR codes: bytes (up to 128 columns; one or two lane words per row,
-    // L = 4 or 8) or 16-bit codes (wider; two words, L = 4). A request
-    // without the one its shape asks for takes the other if the matrix has
-    // it, else the FP16 codes (or the FP32 tile) at the same shape.
+    // L = 4 or 8) or 16-bit codes (wider; one or two words, L = 2 or 4). A
+    // request without the one its shape asks for takes the other if the
+    // matrix has it, else the FP16 codes (or the FP32 tile) at the same
+    // shape; a tile that does not fit takes one word per row first.
     if (cfg.staging == STAGE_BYTES && !have_bytes)
         cfg.staging = have_halves ? STAGE_HALVES : (have_codes ? STAGE_CODES : STAGE_LDS);
     if (cfg.staging == STAGE_HALVES && !have_halves)
         cfg.staging = have_bytes ? STAGE_BYTES : (have_codes ? STAGE_CODES : STAGE_LDS);
     if (cfg.staging == STAGE_BYTES) cfg.L = cfg.L >= 8 ? 8 : 4;
-    if (cfg.staging == STAGE_HALVES) cfg.L = 4;
+    if (cfg.staging == STAGE_HALVES) cfg.L = cfg.L >= 4 ? 4 : 2;
+    if (cfg.staging == STAGE_HALVES && cfg.L == 4 && !fits(cfg)) cfg.L = 2;
     if (cfg.staging == STAGE_HALVES && !fits(cfg)) cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
     if (cfg.staging == STAGE_BYTES && cfg.L == 8 && !fits(cfg)) cfg.L = 4;
     if (cfg.staging == STAGE_BYTES && !fits(cfg)) cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
     if (cfg.staging != STAGE_BYTES) cfg.L = std::min(cfg.L, 4);
-    if (cfg.staging == STAGE_HALVES) cfg.L = 4;
     // Rank codes need codes for this mode and at least two sub-tiles.
     if (cfg.staging == STAGE_CODES && (!have_codes || cfg.L < 2)) cfg.staging = STAGE_LDS;
     // An FP32 tile that does not fit: the codes' tile (half the bytes) at the

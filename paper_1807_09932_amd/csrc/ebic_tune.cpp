@@ -62,9 +62,11 @@ LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
         c.L = 8;
         c.P = std::max(1, std::min(n, 200));
     } else if (cols <= kMaxCodeCols) {
-        // 16-bit rank codes, two rows per lane word, 256-row chunks.
+        // 16-bit rank codes, one lane word of two rows per 128-row chunk
+        // (cols x 256 bytes: two blocks per CU up to about 310 columns).
         c.staging = STAGE_HALVES;
-        c.L = 4;
+        c.L = 2;
+        c.P = std::max(1, std::min(n, 200));
     }
     c.blocks = 0;
     return c;
@@ -81,8 +83,9 @@ LaunchCfg default_batch_cfg(int32_t max_cols)
         c.staging = STAGE_BYTES;
         c.L = 4;
     } else if (max_cols <= kMaxCodeCols) {
-        c.staging = STAGE_HALVES;
-        c.L = 4;
+        c.staging = STAGE_HALVES;  // one lane word per row, large groups
+        c.L = 2;
+        c.P = 1024;
     }
     c.blocks = 0;
     return c;
@@ -302,7 +305,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                                 if (stg == STAGE_CODES && (L < 2 || !have_codes)) continue;
                                 if (stg == STAGE_BYTES && (L < 4 || !have_bytes)) continue;
                                 if (L == 8 && stg != STAGE_BYTES) continue;  // eight sub-tiles: byte codes only
-                                if (stg == STAGE_HALVES && (L != 4 || !have_halves)) continue;
+                                if (stg == STAGE_HALVES && ((L != 2 && L != 4) || !have_halves)) continue;
                                 set_override(c);
                                 const float ms = time_ms(
                                     [&] {
@@ -347,7 +350,8 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                                 for (int stg : {(int)STAGE_LDS, (int)STAGE_CODES, (int)STAGE_BYTES,
                                                 (int)STAGE_HALVES}) {
                                 if (stg == STAGE_CODES && L < 2) continue;
-                                if ((stg == STAGE_BYTES || stg == STAGE_HALVES) && L != 4) continue;
+                                if (stg == STAGE_BYTES && L != 4) continue;
+                                if (stg == STAGE_HALVES && L != 2 && L != 4) continue;
                                 LaunchCfg c;
                                 c.L = L;
                                 c.W = W;

@@ -40,7 +40,7 @@ STAGE_LDS = 0
 STAGE_DIRECT = 1
 STAGE_CODES = 2   # FP16 rank codes staged in LDS (matrices of <= 384 columns)
 STAGE_BYTES = 3   # byte rank codes, four rows per lane word (<= 128 columns; 4 or 8 tiles per wave)
-STAGE_HALVES = 4  # 16-bit rank codes, two rows per lane word (129..384 columns; 4 tiles per wave)
+STAGE_HALVES = 4  # 16-bit rank codes, two rows per lane word (129..384 columns; 2 or 4 tiles per wave)
 
 EXPORTED = ["ebic_create", "ebic_destroy", "ebic_set_allocator", "ebic_last_error",
             "ebic_upload_matrix", "ebic_matrix_info", "ebic_release_matrix",

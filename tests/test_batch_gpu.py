@@ -102,11 +102,13 @@ def test_batched_many_matrices_and_modes(ctx):
         ctx.release(m)
 
 
-def test_batch_byte_codes(ctx):
+@pytest.mark.parametrize("tiles", [4, 2])
+def test_batch_byte_codes(ctx, tiles):
     """The batched kernel with the SWAR codes forced: requests on a matrix
     without missing cells (byte codes in both modes), on one with them (byte
     codes in include mode only) and on a 230-column one (16-bit codes),
-    masks on and off."""
+    masks on and off. With two tiles per wave only the 16-bit codes exist
+    (one word per row); the byte-code requests take the FP16 codes."""
     from paper_1807_09932_amd import ebic
     rng = np.random.default_rng(44)
     Xa = rng.integers(0, 7, size=(4099, 64)).astype(np.float32)
@@ -124,21 +126,24 @@ def test_batch_byte_codes(ctx):
         want.append(oracle_eval(Xs[m], offs, cols, include=include, negative=negative, masks=masks,
                                 fill=0.25))
     try:
-        ctx.set_launch_shape(4, 8, 128, ebic.STAGE_BYTES, 0)
-        announce("batch byte codes")
+        ctx.set_launch_shape(tiles, 8, 128, ebic.STAGE_BYTES, 0)
+        announce("batch byte codes", tiles)
         plan = []
         got = _run_batch(ctx, jobs, plan=plan)
         for q in range(len(jobs)):
             assert_same(got[q], want[q], f"request {q}")
         L, W, P, stagings, _ = plan[0]
-        assert (L, W, P) == (4, 8, 128)
+        assert (L, W, P) == (tiles, 8, 128)
         for q, (m, _, include, _, _) in enumerate(jobs):
             k = mats.index(m)
-            # byte codes on the 64- and 100-column matrices (the latter has
-            # missing cells, so exclude mode takes the FP16 codes there);
-            # 16-bit codes on the 230-column one
-            expect = (ebic.STAGE_HALVES if k == 2 else
-                      ebic.STAGE_BYTES if (k == 0 or include) else ebic.STAGE_CODES)
+            # byte codes (four tiles only) on the 64- and 100-column matrices
+            # (the latter has missing cells, so exclude mode takes the FP16
+            # codes there; include mode has FP16 codes only with the fill
+            # copy kept, so it takes the FP32 tile); 16-bit codes on the
+            # 230-column one
+            bytes_ok = tiles == 4 and (k == 0 or include)
+            expect = (ebic.STAGE_HALVES if k == 2 else ebic.STAGE_BYTES if bytes_ok else
+                      ebic.STAGE_LDS if include else ebic.STAGE_CODES)
             assert stagings[q] == expect, (q, k, include, stagings[q])
     finally:
         ctx.set_launch_shape()

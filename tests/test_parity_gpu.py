@@ -213,14 +213,16 @@ def test_byte_codes_special_values(ctx, ncols, rows, tiles):
             ctx.release(mat)
 
 
+@pytest.mark.parametrize("tiles", [2, 4])
 @pytest.mark.parametrize("ncols", [129, 256, 384])
 @pytest.mark.parametrize("rows", [1, 257, 777, 3001])
-def test_halves_special_values(ctx, ncols, rows):
+def test_halves_special_values(ctx, ncols, rows, tiles):
     """16-bit SWAR codes (two rows per 32-bit lane word, matrices of 129 to
-    384 columns) on the special values (+-inf, +-0, denormals, ties): both
-    modes and trend settings without missing cells; with them, include mode
-    uses the codes and exclude mode falls back. Individuals of up to 30
-    columns reach past the 8-column window."""
+    384 columns; one word per row of a 128-row chunk, or two of a 256-row
+    chunk) on the special values (+-inf, +-0, denormals, ties): both modes
+    and trend settings without missing cells; with them, include mode uses
+    the codes and exclude mode falls back. Individuals of up to 30 columns
+    reach past the 8-column window."""
     from paper_1807_09932_amd import ebic
     rng = np.random.default_rng(1300 + ncols + rows)
     X = _special(rng, (rows, ncols))
@@ -230,15 +232,17 @@ def test_halves_special_values(ctx, ncols, rows):
     for name, A in (("no missing", X), ("missing", Xn)):
         mat = ctx.upload(A, fill=-0.0)
         try:
-            ctx.set_launch_shape(4, 8, 64, ebic.STAGE_HALVES, 0)
+            ctx.set_launch_shape(tiles, 8, 64, ebic.STAGE_HALVES, 0)
             plan = ebic.ebic_plan_shape(ctx.handle, mat, offs.size - 1, int(offs[-1]))
             if np.isnan(A).any():
                 assert plan[3] != ebic.STAGE_HALVES
-            elif ncols <= 256:  # (wider tiles do not fit the LDS and fall back)
+            else:
                 assert plan[3] == ebic.STAGE_HALVES
+                # a four-tile chunk of 384 columns does not fit the LDS: one word per row
+                assert plan[0] == (2 if ncols > 256 else tiles)
             for include in (False, True):
                 for negative in (False, True):
-                    announce("halves", rows, ncols, name, include, negative)
+                    announce("halves", rows, ncols, tiles, name, include, negative)
                     got = gpu_eval(ctx, mat, offs, cols, include=include, negative=negative)
                     want = oracle_eval(A, offs, cols, include=include, negative=negative, fill=-0.0)
                     assert_same(got, want, f"halves {rows}x{ncols} {name} include={include} "
