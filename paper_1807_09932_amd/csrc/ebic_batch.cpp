@@ -153,7 +153,7 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
 
     // Staging per request: the byte or 16-bit SWAR codes when the shape asks
     // for either and the matrix has them for this mode (bytes: four
-    // sub-tiles; 16-bit codes: two or four); the
+    // sub-tiles; 16-bit codes: two); the
     // FP16 rank codes when the shape asks for codes (or the FP32 tile does
     // not fit) and they exist and fit; else the FP32 tile if it fits next to
     // the counts, else direct reads.
@@ -171,7 +171,7 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
         const bool wants_swar = c.staging == STAGE_BYTES || c.staging == STAGE_HALVES;
         const bool wants_codes = c.staging == STAGE_CODES || wants_swar;
         if (wants_swar && c.L == 4 && have_bytes && fits(STAGE_BYTES)) staging = STAGE_BYTES;
-        else if (wants_swar && c.L >= 2 && have_halves && fits(STAGE_HALVES)) staging = STAGE_HALVES;
+        else if (wants_swar && c.L == 2 && have_halves && fits(STAGE_HALVES)) staging = STAGE_HALVES;
         else if (codes_ok && (wants_codes || !fits(STAGE_LDS))) staging = STAGE_CODES;
         else if (fits(STAGE_LDS)) staging = STAGE_LDS;
         ReqDesc d = make_desc(m, std::max(0, r.n_ind), r.d_offsets, r.d_cols, r.flags, r.d_matched,

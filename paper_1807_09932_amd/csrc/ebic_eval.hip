@@ -1718,7 +1718,10 @@ k_eval_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs, const Item *__
                 continue;
             }
         }
-        if constexpr (L == 2 || L == 4) {  // 16-bit codes: one or two lane words
+        // 16-bit codes in batches: one lane word per row (L = 2). The
+        // two-word sequences would push the L = 4 instance, which holds the
+        // byte path, past its register budget into scratch.
+        if constexpr (L == 2) {
             if (d.flags & kFlagHalves) {
                 if (neg) run_item<L, true, STAGE_HALVES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
                 else run_item<L, false, STAGE_HALVES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);

@@ -350,8 +350,8 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                                 for (int stg : {(int)STAGE_LDS, (int)STAGE_CODES, (int)STAGE_BYTES,
                                                 (int)STAGE_HALVES}) {
                                 if (stg == STAGE_CODES && L < 2) continue;
-                                if (stg == STAGE_BYTES && L != 4) continue;
-                                if (stg == STAGE_HALVES && L != 2 && L != 4) continue;
+                                if (stg == STAGE_BYTES && L != 4) continue;  // batches: bytes at 4,
+                                if (stg == STAGE_HALVES && L != 2) continue; // 16-bit codes at 2 sub-tiles
                                 LaunchCfg c;
                                 c.L = L;
                                 c.W = W;

@@ -107,8 +107,9 @@ def test_batch_byte_codes(ctx, tiles):
     """The batched kernel with the SWAR codes forced: requests on a matrix
     without missing cells (byte codes in both modes), on one with them (byte
     codes in include mode only) and on a 230-column one (16-bit codes),
-    masks on and off. With two tiles per wave only the 16-bit codes exist
-    (one word per row); the byte-code requests take the FP16 codes."""
+    masks on and off. Batches stage byte codes at four tiles per wave and
+    16-bit codes at two; other requests take the FP16 codes, the FP32 tile
+    or direct reads."""
     from paper_1807_09932_amd import ebic
     rng = np.random.default_rng(44)
     Xa = rng.integers(0, 7, size=(4099, 64)).astype(np.float32)
@@ -140,10 +141,16 @@ def test_batch_byte_codes(ctx, tiles):
             # (the latter has missing cells, so exclude mode takes the FP16
             # codes there; include mode has FP16 codes only with the fill
             # copy kept, so it takes the FP32 tile); 16-bit codes on the
-            # 230-column one
-            bytes_ok = tiles == 4 and (k == 0 or include)
-            expect = (ebic.STAGE_HALVES if k == 2 else ebic.STAGE_BYTES if bytes_ok else
-                      ebic.STAGE_LDS if include else ebic.STAGE_CODES)
+            # 230-column one at two tiles (at four, exclude mode takes the
+            # FP16 codes and include mode, whose FP32 tile does not fit,
+            # direct reads)
+            if k == 2:
+                expect = (ebic.STAGE_HALVES if tiles == 2 else
+                          ebic.STAGE_DIRECT if include else ebic.STAGE_CODES)
+            elif tiles == 4 and (k == 0 or include):
+                expect = ebic.STAGE_BYTES
+            else:
+                expect = ebic.STAGE_LDS if include else ebic.STAGE_CODES
             assert stagings[q] == expect, (q, k, include, stagings[q])
     finally:
         ctx.set_launch_shape()
