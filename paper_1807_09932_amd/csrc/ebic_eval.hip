@@ -1085,6 +1085,44 @@ __device__ __forceinline__ void lane_masks(uint32_t x, uint64_t *m)
     else half_masks2(x, m[0], m[1]);
 }
 
+// The number of set top bits of all parts of x over the wave: each part's
+// mask is counted as soon as it is made, so two scalar pairs hold all of
+// them (the SALU reads of a mask the VALU wrote are interlocked).
+template <int BITS>
+__device__ __forceinline__ int32_t lane_popc(uint32_t x)
+{
+    uint64_t a, b;
+    int32_t c, d;
+    if constexpr (BITS == 8) {
+        asm volatile(
+            "v_cmp_ne_u32_sdwa %[a], %[x], 0 src0_sel:BYTE_0 src1_sel:DWORD\n\t"
+            "v_cmp_ne_u32_sdwa %[b], %[x], 0 src0_sel:BYTE_1 src1_sel:DWORD\n\t"
+            "s_bcnt1_i32_b64 %[c], %[a]\n\t"
+            "v_cmp_ne_u32_sdwa %[a], %[x], 0 src0_sel:BYTE_2 src1_sel:DWORD\n\t"
+            "s_bcnt1_i32_b64 %[d], %[b]\n\t"
+            "s_add_u32 %[c], %[c], %[d]\n\t"
+            "v_cmp_ne_u32_sdwa %[b], %[x], 0 src0_sel:BYTE_3 src1_sel:DWORD\n\t"
+            "s_bcnt1_i32_b64 %[d], %[a]\n\t"
+            "s_add_u32 %[c], %[c], %[d]\n\t"
+            "s_bcnt1_i32_b64 %[d], %[b]\n\t"
+            "s_add_u32 %[c], %[c], %[d]"
+            : [a] "=&s"(a), [b] "=&s"(b), [c] "=&s"(c), [d] "=&s"(d)
+            : [x] "v"(x)
+            : "scc");
+    } else {
+        asm volatile(
+            "v_cmp_ne_u32_sdwa %[a], %[x], 0 src0_sel:WORD_0 src1_sel:DWORD\n\t"
+            "v_cmp_ne_u32_sdwa %[b], %[x], 0 src0_sel:WORD_1 src1_sel:DWORD\n\t"
+            "s_bcnt1_i32_b64 %[c], %[a]\n\t"
+            "s_bcnt1_i32_b64 %[d], %[b]\n\t"
+            "s_add_u32 %[c], %[c], %[d]"
+            : [a] "=&s"(a), [b] "=&s"(b), [c] "=&s"(c), [d] "=&s"(d)
+            : [x] "v"(x)
+            : "scc");
+    }
+    return c;
+}
+
 // Plain-code twin of the window (the measurement variant): the same exit
 // points; counts one step per 64-row sub-tile (NP per word) and column.
 template <int SH, bool COUNT, int NP = 4>
@@ -1125,13 +1163,14 @@ __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, 
 // (BITS = 16). `hv` holds the top bit of the parts whose rows are inside
 // the item and the matrix. The codes have no missing value (exclude mode
 // uses them only on a matrix without missing cells; include mode's codes
-// encode the fill). Returns false, and leaves M and G (one mask per
-// sub-tile) unset, when no row matches.
+// encode the fill). Sets mw (the top bits of the matching rows' parts) and
+// gw (those that match on their negative trend); returns false, leaving
+// them unset, when no row matches.
 template <int SH, bool NEG, bool COUNT, int BITS = 8>
 __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ tile, int32_t last,
                                            const int32_t *__restrict__ colidx,
                                            const int32_t *__restrict__ hbegin, const int4 &w03, const int4 &w47,
-                                           int lane, uint32_t hv, uint64_t *M, uint64_t *G, uint64_t &steps)
+                                           int lane, uint32_t hv, uint32_t &mw, uint32_t &gw, uint64_t &steps)
 {
     using T = Lanes<BITS>;
     constexpr int NP = T::PARTS;
@@ -1139,9 +1178,8 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
     const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
     auto rd = [&](int32_t col) { return *reinterpret_cast<const uint32_t *>(base + (col << SH)); };
     if (last == 0) {  // one column: every row in range counts
-        lane_masks<BITS>(hv, M);
-#pragma unroll
-        for (int s = 0; s < NP; ++s) G[s] = 0;
+        mw = hv;
+        gw = 0;
         if (COUNT) steps += NP;
         return true;
     }
@@ -1183,14 +1221,9 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
             by_tail<SH, COUNT, NP>(base, c, w, last, T::H, ~0u, alive, steps);
         }
     }
-    const uint32_t mw = alive | tied;
+    mw = alive | tied;
     if (__ballot(mw != 0) == 0) return false;
-    lane_masks<BITS>(mw, M);
-    if constexpr (NEG) lane_masks<BITS>((alive & fall) | (tied & ~alive), G);
-    else {
-#pragma unroll
-        for (int s = 0; s < NP; ++s) G[s] = 0;
-    }
+    gw = NEG ? (alive & fall) | (tied & ~alive) : 0u;
     return true;
 }
 
@@ -1219,14 +1252,15 @@ __device__ __forceinline__ void by2_window_ref(const unsigned char *__restrict__
 // One individual on a chunk of two lane words per row group (byte codes:
 // 512 rows, 8 sub-tiles; 16-bit codes: 256 rows, 4 sub-tiles; a column is
 // 512 bytes). hva, hvb: the top bits of the in-range rows of each word.
-// Returns false, and leaves M and G unset, when no row matches. M and G hold
-// 2 * PARTS sub-tile masks.
+// Sets, per word, mw (the top bits of the matching rows' parts) and gw
+// (those that match on their negative trend); returns false, leaving them
+// unset, when no row matches.
 template <int BITS, bool NEG, bool COUNT, bool TIES>
 __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ tile, int32_t last,
                                            const int32_t *__restrict__ colidx,
                                            const int32_t *__restrict__ hbegin, const int4 &w03, const int4 &w47,
-                                           int lane, uint32_t hva, uint32_t hvb, uint64_t *M, uint64_t *G,
-                                           uint64_t &steps)
+                                           int lane, uint32_t hva, uint32_t hvb, uint32_t (&mw)[2],
+                                           uint32_t (&gw)[2], uint64_t &steps)
 {
     using T = Lanes<BITS>;
     constexpr int NP = T::PARTS;
@@ -1236,10 +1270,9 @@ __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ til
         return *reinterpret_cast<const uint32_t *>(base + (col << 9) + 256 * h);
     };
     if (last == 0) {  // one column: every row in range counts
-        lane_masks<BITS>(hva, M);
-        lane_masks<BITS>(hvb, M + NP);
-#pragma unroll
-        for (int s = 0; s < 2 * NP; ++s) G[s] = 0;
+        mw[0] = hva;
+        mw[1] = hvb;
+        gw[0] = gw[1] = 0;
         if (COUNT) steps += 2 * NP;
         return true;
     }
@@ -1294,17 +1327,11 @@ __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ til
             }
         }
     }
-    const uint32_t mwa = alive[0] | tied[0], mwb = alive[1] | tied[1];
-    if (__ballot((mwa | mwb) != 0) == 0) return false;
-    lane_masks<BITS>(mwa, M);
-    lane_masks<BITS>(mwb, M + NP);
-    if constexpr (NEG) {
-        lane_masks<BITS>((alive[0] & fall[0]) | (tied[0] & ~alive[0]), G);
-        lane_masks<BITS>((alive[1] & fall[1]) | (tied[1] & ~alive[1]), G + NP);
-    } else {
+    mw[0] = alive[0] | tied[0];
+    mw[1] = alive[1] | tied[1];
+    if (__ballot((mw[0] | mw[1]) != 0) == 0) return false;
 #pragma unroll
-        for (int s = 0; s < 2 * NP; ++s) G[s] = 0;
-    }
+    for (int h = 0; h < 2; ++h) gw[h] = NEG ? (alive[h] & fall[h]) | (tied[h] & ~alive[h]) : 0u;
     return true;
 }
 
@@ -1473,7 +1500,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         if constexpr (kSwar) {
             static_assert(STAGE == STAGE_HALVES ? (L == 2 || L == 4) : (L == 4 || L == 8),
                           "one or two lane words per row of a chunk");
-            ties = tie_pre != 0;
+            ties = __builtin_amdgcn_readfirstlane(tie_pre) != 0;  // (uniform: one flag per chunk)
             // The L * 64 rows [row0, row0 + 64 L) of every column, in their
             // interleaved order; rows outside the item or the matrix are
             // left out of `hvalid` instead.
@@ -1546,38 +1573,44 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             } else {
                 bool live = true;  // (byte codes: counted per 256-row group below)
                 int32_t pm = 0, pg = 0;
-                if constexpr (kSwar && NWORDS == 2) {
+                if constexpr (kSwar) {
+                    // One or two lane words per row: the evaluation returns
+                    // the words of matching rows; the masks are made only
+                    // when they are stored, else each word's parts are
+                    // counted directly.
                     live = false;
                     const auto *tl = reinterpret_cast<const unsigned char *>(tile);
-                    const bool any =
-                        ties ? eval_swar2<BITS, NEG, COUNT, true>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2],
-                                                                  lane, hvalid[0], hvalid[NWORDS - 1], M, G, steps)
-                             : eval_swar2<BITS, NEG, COUNT, false>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2],
-                                                                   lane, hvalid[0], hvalid[NWORDS - 1], M, G, steps);
+                    uint32_t mw[2] = {0, 0}, gw[2] = {0, 0};
+                    bool any;
+                    if constexpr (NWORDS == 2)
+                        any = ties ? eval_swar2<BITS, NEG, COUNT, true>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1],
+                                                                        hv[2], lane, hvalid[0], hvalid[NWORDS - 1],
+                                                                        mw, gw, steps)
+                                   : eval_swar2<BITS, NEG, COUNT, false>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1],
+                                                                         hv[2], lane, hvalid[0], hvalid[NWORDS - 1],
+                                                                         mw, gw, steps);
+                    else
+                        any = eval_bytes<8, NEG, COUNT, BITS>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2], lane,
+                                                              hvalid[0], mw[0], gw[0], steps);
                     if (any) {
 #pragma unroll
-                        for (int s = 0; s < L; ++s) {
-                            pm += __popcll(M[s]);
-                            pg += __popcll(G[s]);
+                        for (int h = 0; h < NWORDS; ++h) {
+                            if constexpr (MASKS) {
+                                lane_masks<BITS>(mw[h], M + h * PARTS);
+                                lane_masks<BITS>(gw[h], G + h * PARTS);
+                            } else {
+                                pm += lane_popc<BITS>(mw[h]);
+                                if constexpr (NEG) pg += lane_popc<BITS>(gw[h]);
+                            }
                         }
-                    } else {
+                        if constexpr (MASKS) {
 #pragma unroll
-                        for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
-                    }
-                } else if constexpr (kSwar) {
-                    // One lane word per row: four byte sub-tiles or two
-                    // 16-bit ones.
-                    live = false;
-                    const bool any = eval_bytes<8, NEG, COUNT, BITS>(
-                        reinterpret_cast<const unsigned char *>(tile), k - 1, d.colidx, &hb[ii].begin, hv[1],
-                        hv[2], lane, hvalid[0], M, G, steps);
-                    if (any) {
-#pragma unroll
-                        for (int s = 0; s < L; ++s) {
-                            pm += __popcll(M[s]);
-                            pg += __popcll(G[s]);
+                            for (int s = 0; s < L; ++s) {
+                                pm += __popcll(M[s]);
+                                pg += __popcll(G[s]);
+                            }
                         }
-                    } else {
+                    } else if constexpr (MASKS) {
 #pragma unroll
                         for (int s = 0; s < L; ++s) M[s] = G[s] = 0;
                     }
