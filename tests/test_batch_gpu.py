@@ -207,3 +207,33 @@ def test_batch_matches_plain_on_batched_100000x256_sample(ctx):
     for i, p in enumerate(packed):
         assert_same(got[i], oracle_eval(w.X, *p, masks=False), f"batched_100000x256 pop {i}")
     ctx.release(mat)
+
+
+def test_plan_batch_shape_reports_and_rejects(ctx):
+    """ebic_plan_batch_shape: the planned shape of a valid batch, and the
+    same validation errors as ebic_eval_batch, with nothing launched."""
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(45)
+    X = rng.standard_normal((3000, 64)).astype(np.float32)
+    mat = ctx.upload(X)
+    try:
+        (offs, cols), = _pops(450, 64, 1, (10, 40), lambda r: int(r.integers(2, 20)))
+        pop = ctx.population(offsets=offs, cols=cols)
+        out = ctx.outputs(mat, pop.n)
+        req = ctx.request(mat, pop, out)
+        ctx.set_launch_shape(4, 8, 128, ebic.STAGE_BYTES, 0)
+        L, W, P, stagings, blocks = ebic.ebic_plan_batch_shape(ctx.handle, [req, req])
+        assert (L, W, P) == (4, 8, 128) and stagings == [ebic.STAGE_BYTES] * 2 and blocks >= 1
+        with pytest.raises(ebic.EbicError):
+            ebic.ebic_plan_batch_shape(ctx.handle, [])
+        bad = ctx.request(mat, pop, out)
+        bad.flags = 1 << 7  # not a defined flag
+        with pytest.raises(ebic.EbicError):
+            ebic.ebic_plan_batch_shape(ctx.handle, [req, bad])
+        bad = ctx.request(mat, pop, out)
+        bad.matrix = 987654  # no such matrix
+        with pytest.raises(ebic.EbicError):
+            ebic.ebic_plan_batch_shape(ctx.handle, [bad])
+    finally:
+        ctx.set_launch_shape()
+        ctx.release(mat)
