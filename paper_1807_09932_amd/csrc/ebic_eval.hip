@@ -1148,9 +1148,10 @@ __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, 
                                         const int32_t (&w)[kWin], int32_t last, uint32_t fH, uint32_t nf,
                                         uint32_t &alive, uint64_t &steps)
 {
+    if (__ballot(alive != 0) == 0) return;
     uint32_t nx = (*reinterpret_cast<const uint32_t *>(base + (w[kWin - 1] << SH)) ^ nf) + 1u;
     for (int32_t u = kWin; u <= last; ++u) {
-        if (__ballot(alive != 0) == 0) return;
+        if (u > kWin && __ballot(alive != 0) == 0) return;
         const uint32_t t = *reinterpret_cast<const uint32_t *>(base + (c[u] << SH));
         alive &= (t ^ fH) + nx;
         nx = (t ^ nf) + 1u;
@@ -1210,8 +1211,10 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
         if constexpr (NEG) by_neg<SH, BITS>(b, w, last, hv, alive, fall, tied);
         else by_pos<SH, BITS>(b, w, last, hv, alive);
     }
-    if (last >= kWin) {
-        // The columns past the window (the CSR start is read only here).
+    // The columns past the window, only while a row is left on either chain
+    // (rarely: few rows survive eight columns); the CSR start is read only
+    // here.
+    if (last >= kWin && __ballot((alive | tied) != 0) != 0) {
         const int32_t *c = colidx + *hbegin;
         if constexpr (NEG) {
             const uint32_t fm = fall - (fall >> T::SHF);
@@ -1313,8 +1316,10 @@ __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ til
             by2_neg<BITS, TIES>(b, w, last, hva, hvb, alive[0], alive[1], fall[0], fall[1], tied[0], tied[1]);
         else by2_pos<BITS>(b, w, last, hva, hvb, alive[0], alive[1]);
     }
-    if (last >= kWin) {
-        // The columns past the window (the CSR start is read only here).
+    // The columns past the window, only while a row of either word is left
+    // on either chain (rarely: few rows survive eight columns); the CSR
+    // start is read only here.
+    if (last >= kWin && __ballot((alive[0] | alive[1] | tied[0] | tied[1]) != 0) != 0) {
         const int32_t *c = colidx + *hbegin;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
