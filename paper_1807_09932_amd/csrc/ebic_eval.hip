@@ -1211,10 +1211,11 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
         if constexpr (NEG) by_neg<SH, BITS>(b, w, last, hv, alive, fall, tied);
         else by_pos<SH, BITS>(b, w, last, hv, alive);
     }
-    // The columns past the window, only while a row is left on either chain
-    // (rarely: few rows survive eight columns); the CSR start is read only
-    // here.
-    if (last >= kWin && __ballot((alive | tied) != 0) != 0) {
+    // No row left on either chain: nothing matches, and the columns past the
+    // window (rarely reached: few rows survive eight columns) are skipped.
+    if (__ballot((alive | tied) != 0) == 0) return false;
+    if (last >= kWin) {
+        // The columns past the window (the CSR start is read only here).
         const int32_t *c = colidx + *hbegin;
         if constexpr (NEG) {
             const uint32_t fm = fall - (fall >> T::SHF);
@@ -1223,9 +1224,9 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
         } else {
             by_tail<SH, COUNT, NP>(base, c, w, last, T::H, ~0u, alive, steps);
         }
+        if (__ballot((alive | tied) != 0) == 0) return false;
     }
     mw = alive | tied;
-    if (__ballot(mw != 0) == 0) return false;
     gw = NEG ? (alive & fall) | (tied & ~alive) : 0u;
     return true;
 }
@@ -1316,10 +1317,12 @@ __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ til
             by2_neg<BITS, TIES>(b, w, last, hva, hvb, alive[0], alive[1], fall[0], fall[1], tied[0], tied[1]);
         else by2_pos<BITS>(b, w, last, hva, hvb, alive[0], alive[1]);
     }
-    // The columns past the window, only while a row of either word is left
-    // on either chain (rarely: few rows survive eight columns); the CSR
-    // start is read only here.
-    if (last >= kWin && __ballot((alive[0] | alive[1] | tied[0] | tied[1]) != 0) != 0) {
+    // No row of either word left on either chain: nothing matches, and the
+    // columns past the window (rarely reached: few rows survive eight
+    // columns) are skipped.
+    if (__ballot((alive[0] | alive[1] | tied[0] | tied[1]) != 0) == 0) return false;
+    if (last >= kWin) {
+        // The columns past the window (the CSR start is read only here).
         const int32_t *c = colidx + *hbegin;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -1331,10 +1334,10 @@ __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ til
                 by_tail<9, COUNT, NP>(base + 256 * h, c, w, last, T::H, ~0u, alive[h], steps);
             }
         }
+        if (__ballot((alive[0] | alive[1] | tied[0] | tied[1]) != 0) == 0) return false;
     }
     mw[0] = alive[0] | tied[0];
     mw[1] = alive[1] | tied[1];
-    if (__ballot((mw[0] | mw[1]) != 0) == 0) return false;
 #pragma unroll
     for (int h = 0; h < 2; ++h) gw[h] = NEG ? (alive[h] & fall[h]) | (tied[h] & ~alive[h]) : 0u;
     return true;
@@ -1564,10 +1567,10 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             __syncthreads();
         }
 
-        // The individuals of this wave on the staged chunk; the loop is
-        // compiled twice, with and without the mask stores.
-        auto individuals = [&](auto masks_tag) {
+        // The individuals of this wave on the staged chunk.
+        auto individuals = [&](auto masks_tag, auto ties_tag) {
         constexpr bool MASKS = decltype(masks_tag)::value;
+        constexpr bool TIES = decltype(ties_tag)::value;  // (two-word SWAR chunks only)
         // One individual (header hv) on the staged chunk.
         auto one = [&](const int4 (&hv)[3], int32_t ii) {
             const int32_t k = hv[0].x;
@@ -1588,12 +1591,8 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                     uint32_t mw[2] = {0, 0}, gw[2] = {0, 0};
                     bool any;
                     if constexpr (NWORDS == 2)
-                        any = ties ? eval_swar2<BITS, NEG, COUNT, true>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1],
-                                                                        hv[2], lane, hvalid[0], hvalid[NWORDS - 1],
-                                                                        mw, gw, steps)
-                                   : eval_swar2<BITS, NEG, COUNT, false>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1],
-                                                                         hv[2], lane, hvalid[0], hvalid[NWORDS - 1],
-                                                                         mw, gw, steps);
+                        any = eval_swar2<BITS, NEG, COUNT, TIES>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2],
+                                                                 lane, hvalid[0], hvalid[NWORDS - 1], mw, gw, steps);
                     else
                         any = eval_bytes<8, NEG, COUNT, BITS>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2], lane,
                                                               hvalid[0], mw[0], gw[0], steps);
@@ -1682,8 +1681,21 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             one(hv, ii);
         }
         };
-        if (d.mmask || d.nmask) individuals(std::true_type{});
-        else individuals(std::false_type{});
+        // The loop is compiled with and without the mask stores, and for
+        // two-word SWAR chunks with and without the tie chain (the chunk's
+        // flag, decided once here rather than per individual).
+        if constexpr (kSwar && NWORDS == 2) {
+            if (d.mmask || d.nmask) {
+                if (ties) individuals(std::true_type{}, std::true_type{});
+                else individuals(std::true_type{}, std::false_type{});
+            } else {
+                if (ties) individuals(std::false_type{}, std::true_type{});
+                else individuals(std::false_type{}, std::false_type{});
+            }
+        } else {
+            if (d.mmask || d.nmask) individuals(std::true_type{}, std::true_type{});
+            else individuals(std::false_type{}, std::true_type{});
+        }
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the count adds, before the barrier
     }
 
