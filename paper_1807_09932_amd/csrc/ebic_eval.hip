@@ -768,13 +768,44 @@ template <> struct Lanes<16> {
 // last >= 2). The sequence starts with lgkmcnt(0) (no scalar load in
 // flight, so LDS operations complete in issue order and lgkmcnt(n) means
 // that all but the last n issued are done) and ends with it.
-template <int SH, int BITS = 8>
+template <int SH, int BITS = 8, bool TIES = true>
 __device__ __forceinline__ void by_neg(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hv,
                                        uint32_t &alive, uint32_t &fall, uint32_t &tied)
 {
     using T = Lanes<BITS>;
     uint32_t t0, t1, t2, t3, ad, D, D2, fm, fH, nf, nx;
     uint64_t tmp, tany;
+    if constexpr (!TIES) {
+        // No row of the chunk holds two equal values: a row falls exactly
+        // when it does not rise, and no row is tied.
+        asm volatile(
+            "s_waitcnt lgkmcnt(0)\n\t"
+            BY_LOAD("t0", "w0") BY_LOAD("t1", "w1") BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
+            "s_waitcnt lgkmcnt(2)\n\t"
+            "v_or_b32_e32 %[D], %[H], %[t1]\n\t"
+            "v_sub_u32_e32 %[D], %[D], %[t0]\n\t"           // top bits: t1 >= t0
+            "v_bfi_b32 %[fall], %[D], 0, %[hv]\n\t"         // ~D & hv: falling, in range
+            "v_lshrrev_b32_e32 %[fm], %[SHF], %[fall]\n\t"
+            "v_sub_u32_e32 %[fm], %[fall], %[fm]\n\t"       // all low bits of each falling part
+            "v_or_b32_e32 %[fH], %[H], %[fm]\n\t"
+            "v_not_b32_e32 %[nf], %[fm]\n\t"
+            "v_xad_u32 %[nx], %[t1], %[nf], 1\n\t"
+            "s_cmp_lt_i32 %[last], 2\n\t"
+            "s_cbranch_scc1 6f\n\t"
+            BY_WINDOW("%[fH]", "%[nf]", "nx", "alive", "hv", "2f")
+            "2:\n\t"
+            "s_waitcnt lgkmcnt(0)\n\t"
+            "s_branch 5f\n\t"
+            "6:\n\t"  // two columns: every row in range is on its chain
+            "v_mov_b32_e32 %[alive], %[hv]\n\t"
+            "5:"
+            : BY_SCRATCH, [fm] "=&v"(fm), [fH] "=&v"(fH), [nf] "=&v"(nf), [nx] "=&v"(nx),
+              [alive] "=&v"(alive), [fall] "=&v"(fall)
+            : BY_COLS, [hv] "v"(hv)
+            : "scc", "memory");
+        tied = 0;
+        return;
+    }
     asm volatile(
         "s_waitcnt lgkmcnt(0)\n\t"
         BY_LOAD("t0", "w0") BY_LOAD("t1", "w1") BY_LOAD("t2", "w2") BY_LOAD("t3", "w3")
@@ -1167,7 +1198,7 @@ __device__ __forceinline__ void by_tail(const unsigned char *__restrict__ base, 
 // encode the fill). Sets mw (the top bits of the matching rows' parts) and
 // gw (those that match on their negative trend); returns false, leaving
 // them unset, when no row matches.
-template <int SH, bool NEG, bool COUNT, int BITS = 8>
+template <int SH, bool NEG, bool COUNT, int BITS = 8, bool TIES = true>
 __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ tile, int32_t last,
                                            const int32_t *__restrict__ colidx,
                                            const int32_t *__restrict__ hbegin, const int4 &w03, const int4 &w47,
@@ -1208,7 +1239,7 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
         }
     } else {
         const uint32_t b = lds_addr(base);
-        if constexpr (NEG) by_neg<SH, BITS>(b, w, last, hv, alive, fall, tied);
+        if constexpr (NEG) by_neg<SH, BITS, TIES>(b, w, last, hv, alive, fall, tied);
         else by_pos<SH, BITS>(b, w, last, hv, alive);
     }
     // No row left on either chain: nothing matches, and the columns past the
@@ -1570,7 +1601,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         // The individuals of this wave on the staged chunk.
         auto individuals = [&](auto masks_tag, auto ties_tag) {
         constexpr bool MASKS = decltype(masks_tag)::value;
-        constexpr bool TIES = decltype(ties_tag)::value;  // (two-word SWAR chunks only)
+        constexpr bool TIES = decltype(ties_tag)::value;  // (SWAR chunks only)
         // One individual (header hv) on the staged chunk.
         auto one = [&](const int4 (&hv)[3], int32_t ii) {
             const int32_t k = hv[0].x;
@@ -1594,8 +1625,8 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                         any = eval_swar2<BITS, NEG, COUNT, TIES>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2],
                                                                  lane, hvalid[0], hvalid[NWORDS - 1], mw, gw, steps);
                     else
-                        any = eval_bytes<8, NEG, COUNT, BITS>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2], lane,
-                                                              hvalid[0], mw[0], gw[0], steps);
+                        any = eval_bytes<8, NEG, COUNT, BITS, TIES>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2],
+                                                                    lane, hvalid[0], mw[0], gw[0], steps);
                     if (any) {
 #pragma unroll
                         for (int h = 0; h < NWORDS; ++h) {
@@ -1682,9 +1713,9 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         }
         };
         // The loop is compiled with and without the mask stores, and for
-        // two-word SWAR chunks with and without the tie chain (the chunk's
-        // flag, decided once here rather than per individual).
-        if constexpr (kSwar && NWORDS == 2) {
+        // SWAR chunks with and without the tie chain (the chunk's flag,
+        // decided once here rather than per individual).
+        if constexpr (kSwar) {
             if (d.mmask || d.nmask) {
                 if (ties) individuals(std::true_type{}, std::true_type{});
                 else individuals(std::true_type{}, std::false_type{});
