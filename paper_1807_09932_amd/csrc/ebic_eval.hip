@@ -735,6 +735,13 @@ template <> struct Lanes<16> {
     "v_xad_u32 %[D2], %[" tb "], " FH ", %[" NX "]\n\t"                        \
     "v_xad_u32 %[" NX "], %[" tb "], " NF ", 1\n\t"                            \
     "v_bitop3_b32 %[" AL "], %[" ALIN "], %[D], %[D2] bitop3:0x80\n\t"
+// The window's last pair: no reference is carried past column 7 (the
+// columns after the window start again from column 7).
+#define BY_PAIR_LAST(ta, tb, FH, NF, NX, AL, ALIN)                             \
+    "v_xad_u32 %[D], %[" ta "], " FH ", %[" NX "]\n\t"                         \
+    "v_xad_u32 %[" NX "], %[" ta "], " NF ", 1\n\t"                            \
+    "v_xad_u32 %[D2], %[" tb "], " FH ", %[" NX "]\n\t"                        \
+    "v_bitop3_b32 %[" AL "], %[" ALIN "], %[D], %[D2] bitop3:0x80\n\t"
 // After column 3 only the length ends the chain (256 rows rarely all fail
 // within four columns); after column 5 also the rows left.
 #define BY_EXIT_LAST(u, L) "s_cmp_le_i32 %[last], " u "\n\t" "s_cbranch_scc1 " L "\n\t"
@@ -750,7 +757,7 @@ template <> struct Lanes<16> {
     BY_PAIR("t2", "t3", FH, NF, NX, AL, ALIN) BY_EXIT_LAST("3", L)             \
     BY_LOAD("t2", "w6") BY_LOAD("t3", "w7") "s_waitcnt lgkmcnt(2)\n\t"         \
     BY_PAIR("t0", "t1", FH, NF, NX, AL, AL) BY_EXIT("5", AL, L)                \
-    "s_waitcnt lgkmcnt(0)\n\t" BY_PAIR("t2", "t3", FH, NF, NX, AL, AL)
+    "s_waitcnt lgkmcnt(0)\n\t" BY_PAIR_LAST("t2", "t3", FH, NF, NX, AL, AL)
 #define BY_SCRATCH                                                             \
     [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3), [ad] "=&v"(ad), \
         [D] "=&v"(D), [D2] "=&v"(D2), [tmp] "=&s"(tmp)
@@ -875,6 +882,7 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
 
 #undef BY_LOAD
 #undef BY_PAIR
+#undef BY_PAIR_LAST
 #undef BY_EXIT_LAST
 #undef BY_EXIT
 #undef BY_WINDOW
@@ -913,6 +921,16 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
     "v_xad_u32 %[qb], %[" tb "b], " NFB ", %[hp]\n\t"                          \
     "v_bitop3_b32 %[" AOA "], %[" AIA "], %[Da], %[Ea] bitop3:0x80\n\t"        \
     "v_bitop3_b32 %[" AOB "], %[" AIB "], %[Db], %[Eb] bitop3:0x80\n\t"
+// The window's last pair: no reference is carried past column 7.
+#define B2_PAIR_LAST(ta, tb, FMA, FMB, NFA, NFB, AOA, AOB, AIA, AIB)           \
+    "v_xad_u32 %[Da], %[" ta "a], " FMA ", %[qa]\n\t"                          \
+    "v_xad_u32 %[Db], %[" ta "b], " FMB ", %[qb]\n\t"                          \
+    "v_xad_u32 %[qa], %[" ta "a], " NFA ", %[hp]\n\t"                          \
+    "v_xad_u32 %[qb], %[" ta "b], " NFB ", %[hp]\n\t"                          \
+    "v_xad_u32 %[Ea], %[" tb "a], " FMA ", %[qa]\n\t"                          \
+    "v_xad_u32 %[Eb], %[" tb "b], " FMB ", %[qb]\n\t"                          \
+    "v_bitop3_b32 %[" AOA "], %[" AIA "], %[Da], %[Ea] bitop3:0x80\n\t"        \
+    "v_bitop3_b32 %[" AOB "], %[" AIB "], %[Db], %[Eb] bitop3:0x80\n\t"
 #define B2_EXIT_LAST(u, L) "s_cmp_le_i32 %[last], " u "\n\t" "s_cbranch_scc1 " L "\n\t"
 #define B2_EXIT(u, AA, AB, L)                                                  \
     "v_or_b32_e32 %[Da], %[" AA "], %[" AB "]\n\t"                             \
@@ -929,7 +947,7 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
     B2_PAIR("t0", "t1", FMA, FMB, NFA, NFB, AA, AB, AA, AB)                    \
     B2_EXIT("5", AA, AB, L)                                                    \
     "s_waitcnt lgkmcnt(0)\n\t"                                                 \
-    B2_PAIR("t2", "t3", FMA, FMB, NFA, NFB, AA, AB, AA, AB)
+    B2_PAIR_LAST("t2", "t3", FMA, FMB, NFA, NFB, AA, AB, AA, AB)
 #define B2_SCRATCH                                                             \
     [t0a] "=&v"(t0a), [t0b] "=&v"(t0b), [t1a] "=&v"(t1a), [t1b] "=&v"(t1b),    \
         [t2a] "=&v"(t2a), [t2b] "=&v"(t2b), [t3a] "=&v"(t3a), [t3b] "=&v"(t3b), \
@@ -1063,6 +1081,7 @@ __device__ __forceinline__ void by2_pos(uint32_t base, const int32_t (&w)[kWin],
 }
 
 #undef B2_LOAD
+#undef B2_PAIR_LAST
 #undef B2_PAIR
 #undef B2_EXIT_LAST
 #undef B2_EXIT
