@@ -1759,7 +1759,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Plain evaluation: block (x, y) = tile range x of individual group y.
+// Plain evaluation: one block per (tile range, individual group).
 // ---------------------------------------------------------------------------
 template <int L, bool NEG, int STAGE, bool COUNT>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
@@ -1770,14 +1770,31 @@ k_eval(ReqDesc d, const IndHead *__restrict__ heads, int32_t P, int32_t n_tiles,
     const size_t tb = tile_bytes_of(L, d.cols, STAGE);
     float *tile = reinterpret_cast<float *>(smem);
     int32_t *cnt = reinterpret_cast<int32_t *>(smem + tb);
-    const int32_t i0 = blockIdx.y * P;
+    // Block (x, y) is tile range x of group y: blocks b and b + 256 (in
+    // dispatch order), which share a CU when two are resident, stage the
+    // same rows for two groups, and the second finds them in the CU's L1.
+    // Byte codes (narrow matrices, small chunks) gain more from header
+    // locality: blocks are dispatched round-robin over the 8 XCDs (block b
+    // to XCD b mod 8), so with R ranges a multiple of 8, XCD x takes the
+    // contiguous ranges [x R/8, (x+1) R/8) for every group (the groups
+    // re-reading a range share that XCD's L2) and its k-th block takes group
+    // k mod G (the blocks sharing a CU, k and k + 32, mostly share a group,
+    // whose headers stay in the scalar cache).
+    const uint32_t R = gridDim.x, G = gridDim.y;
+    int32_t grp = (int32_t)blockIdx.y, rng = (int32_t)blockIdx.x;
+    if (STAGE == STAGE_BYTES && R % 8 == 0) {
+        const uint32_t b = blockIdx.y * R + blockIdx.x, k = b / 8;
+        grp = (int32_t)(k % G);
+        rng = (int32_t)((b % 8) * (R / 8) + k / G);
+    }
+    const int32_t i0 = grp * P;
     const int32_t np = min(P, d.n - i0);
     if (np <= 0) return;
     // Tile ranges start on a multiple of L, so only the matrix's last chunk
     // can be partial.
     const int64_t n_chunks = (n_tiles + L - 1) / L;
-    const int64_t t0 = (int64_t)blockIdx.x * n_chunks / gridDim.x * L;
-    const int64_t t1 = min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * n_chunks / gridDim.x * L);
+    const int64_t t0 = (int64_t)rng * n_chunks / gridDim.x * L;
+    const int64_t t1 = min<int64_t>(n_tiles, (int64_t)(rng + 1) * n_chunks / gridDim.x * L);
     uint64_t steps = 0;
     run_item<L, NEG, STAGE, COUNT>(d, heads, i0, np, t0, t1, tile, cnt, steps);
     if (COUNT && (threadIdx.x & (kWave - 1)) == 0 && steps)
