@@ -101,6 +101,9 @@ SHAPES = [  # tiles_per_wave, waves_per_block, individuals_per_group, staging, b
     # back, the matrix has missing cells)
     (4, 8, 64, 3, 0), (4, 16, 1000, 3, 0), (4, 3, 33, 3, 1), (4, 5, 200, 3, 7), (2, 8, 100, 3, 0),
     (8, 16, 400, 3, 0), (8, 4, 33, 3, 2), (8, 7, 150, 3, 5),
+    # byte codes with a multiple of 8 tile ranges per group (the XCD-aware
+    # block placement; 10 and 5 groups, more ranges than chunks)
+    (8, 4, 33, 3, 8), (4, 8, 64, 3, 16),
 ]
 
 
