@@ -210,7 +210,8 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
  *                              condition for exclude mode); 3 and 4 select
  *                              whichever of the two the matrix has; without
  *                              codes for the request's mode the launch takes
- *                              another staging
+ *                              another staging. Batches stage byte codes at
+ *                              4 sub-tiles and 16-bit codes at 2 only.
  *   blocks:                grid size per group, 0 = from occupancy
  * Shapes that do not fit the device are reduced at launch (fewer tiles per
  * wave, then direct reads). Results never depend on the shape.
