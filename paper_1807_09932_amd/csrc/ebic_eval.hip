@@ -53,10 +53,11 @@ __host__ __device__ inline size_t tile_bytes_of(int32_t L, int32_t cols, int32_t
     return (size_t)L * kWave * cols * (staging == STAGE_CODES ? sizeof(uint16_t) : sizeof(float));
 }
 
-// Per-individual [matched, negative] counts of a group of P.
-__host__ __device__ inline size_t count_bytes_of(int32_t P)
+// Per-individual [matched, negative] counts of a group of P: two 32-bit
+// words each, or (cnt16) one word holding both as 16-bit halves.
+__host__ __device__ inline size_t count_bytes_of(int32_t P, bool cnt16 = false)
 {
-    return (size_t)((P + 1) & ~1) * 2 * sizeof(int32_t);
+    return (size_t)((P + 1) & ~1) * (cnt16 ? 1 : 2) * sizeof(int32_t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1475,7 +1476,10 @@ __device__ __forceinline__ void load_head(const IndHead *__restrict__ hb, int32_
 // single writer. Ends with a barrier, so a persistent block can start its
 // next item right away.
 // ---------------------------------------------------------------------------
-template <int L, bool NEG, int STAGE, bool COUNT>
+// C16: the counts as 16-bit halves of one word per individual (the plain
+// kernel with 16-bit codes, whose wide tiles leave little LDS for counts;
+// the planner keeps every range of such a launch below 65,536 rows).
+template <int L, bool NEG, int STAGE, bool COUNT, bool C16 = false>
 __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__restrict__ heads,
                                          int32_t i0, int32_t np, int64_t t0, int64_t t1,
                                          float *tile, int32_t *cnt, uint64_t &steps)
@@ -1490,7 +1494,8 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
     const bool include = (d.flags & kFlagInclude) != 0;
     const IndHead *hb = heads + d.head_base + i0;
 
-    for (int32_t t = threadIdx.x; t < 2 * np; t += blockDim.x) cnt[t] = 0;
+    constexpr bool c16 = C16;
+    for (int32_t t = threadIdx.x; t < (c16 ? np : 2 * np); t += blockDim.x) cnt[t] = 0;
 
     // Byte or 16-bit codes (SWAR stagings): a chunk holds L * 64 * RB bytes
     // of every column (one or two lane words per row); every thread copies
@@ -1702,21 +1707,36 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                 if (pm | pg) {
                     // Lane 0 adds both counts to the block's LDS accumulators;
                     // no result is returned, so nothing waits for it.
-                    const uint32_t a = lds_addr(cnt + 2 * ii);
                     uint64_t save;
                     uint32_t va, vm, vg;
-                    asm volatile(
-                        "s_mov_b64 %[save], exec\n\t"
-                        "s_mov_b64 exec, 1\n\t"
-                        "v_mov_b32 %[va], %[a]\n\t"
-                        "v_mov_b32 %[vm], %[pm]\n\t"
-                        "v_mov_b32 %[vg], %[pg]\n\t"
-                        "ds_add_u32 %[va], %[vm]\n\t"
-                        "ds_add_u32 %[va], %[vg] offset:4\n\t"
-                        "s_mov_b64 exec, %[save]"
-                        : [save] "=&s"(save), [va] "=&v"(va), [vm] "=&v"(vm), [vg] "=&v"(vg)
-                        : [a] "s"(a), [pm] "s"(pm), [pg] "s"(pg)
-                        : "memory");
+                    if constexpr (c16) {
+                        const uint32_t a = lds_addr(cnt + ii);
+                        const uint32_t both = (uint32_t)pm | ((uint32_t)pg << 16);
+                        asm volatile(
+                            "s_mov_b64 %[save], exec\n\t"
+                            "s_mov_b64 exec, 1\n\t"
+                            "v_mov_b32 %[va], %[a]\n\t"
+                            "v_mov_b32 %[vm], %[both]\n\t"
+                            "ds_add_u32 %[va], %[vm]\n\t"
+                            "s_mov_b64 exec, %[save]"
+                            : [save] "=&s"(save), [va] "=&v"(va), [vm] "=&v"(vm)
+                            : [a] "s"(a), [both] "s"(both)
+                            : "memory");
+                    } else {
+                        const uint32_t a = lds_addr(cnt + 2 * ii);
+                        asm volatile(
+                            "s_mov_b64 %[save], exec\n\t"
+                            "s_mov_b64 exec, 1\n\t"
+                            "v_mov_b32 %[va], %[a]\n\t"
+                            "v_mov_b32 %[vm], %[pm]\n\t"
+                            "v_mov_b32 %[vg], %[pg]\n\t"
+                            "ds_add_u32 %[va], %[vm]\n\t"
+                            "ds_add_u32 %[va], %[vg] offset:4\n\t"
+                            "s_mov_b64 exec, %[save]"
+                            : [save] "=&s"(save), [va] "=&v"(va), [vm] "=&v"(vm), [vg] "=&v"(vg)
+                            : [a] "s"(a), [pm] "s"(pm), [pg] "s"(pg)
+                            : "memory");
+                    }
                 }
             }
             if constexpr (MASKS) {
@@ -1751,7 +1771,8 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
 
     __syncthreads();
     for (int32_t t = threadIdx.x; t < np; t += blockDim.x) {
-        const int32_t m = cnt[2 * t], g = cnt[2 * t + 1];
+        const int32_t m = c16 ? (int32_t)((uint32_t)cnt[t] & 0xffffu) : cnt[2 * t];
+        const int32_t g = c16 ? (int32_t)((uint32_t)cnt[t] >> 16) : cnt[2 * t + 1];
         if (m > 0) atomicAdd(d.matched + i0 + t, m);
         if (g > 0 && d.negative) atomicAdd(d.negative + i0 + t, g);
     }
@@ -1796,7 +1817,7 @@ k_eval(ReqDesc d, const IndHead *__restrict__ heads, int32_t P, int32_t n_tiles,
     const int64_t t0 = (int64_t)rng * n_chunks / gridDim.x * L;
     const int64_t t1 = min<int64_t>(n_tiles, (int64_t)(rng + 1) * n_chunks / gridDim.x * L);
     uint64_t steps = 0;
-    run_item<L, NEG, STAGE, COUNT>(d, heads, i0, np, t0, t1, tile, cnt, steps);
+    run_item<L, NEG, STAGE, COUNT, STAGE == STAGE_HALVES>(d, heads, i0, np, t0, t1, tile, cnt, steps);
     if (COUNT && (threadIdx.x & (kWave - 1)) == 0 && steps)
         atomicAdd(step_counter, (unsigned long long)steps);
 }
@@ -1940,16 +1961,16 @@ size_t tile_lds_bytes(int32_t L, int32_t cols, int32_t staging) { return tile_by
 
 size_t count_lds_bytes(int32_t P) { return count_bytes_of(P); }
 
-size_t item_lds_bytes(int32_t L, int32_t cols, int32_t staging, int32_t P)
+size_t item_lds_bytes(int32_t L, int32_t cols, int32_t staging, int32_t P, bool cnt16)
 {
-    return tile_bytes_of(L, cols, staging) + count_bytes_of(P);
+    return tile_bytes_of(L, cols, staging) + count_bytes_of(P, cnt16);
 }
 
 int eval_occupancy(const LaunchCfg &cfg, int32_t cols, uint32_t flags)
 {
     const void *k = eval_kernel(cfg.L, flags, cfg.staging, false);
     if (!k) return 0;
-    const size_t lds = item_lds_bytes(cfg.L, cols, cfg.staging, cfg.P);
+    const size_t lds = item_lds_bytes(cfg.L, cols, cfg.staging, cfg.P, cfg.cnt16);
     int blocks = 0;
     if (set_lds(k, lds) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, cfg.W * kWave, lds) != hipSuccess)
@@ -1983,7 +2004,7 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
     if (!k) return hipErrorInvalidValue;
     const int32_t n_tiles = (int32_t)((d.rows + 63) / 64);
     const int32_t groups = (d.n + cfg.P - 1) / cfg.P;
-    const size_t lds = item_lds_bytes(cfg.L, d.cols, cfg.staging, cfg.P);
+    const size_t lds = item_lds_bytes(cfg.L, d.cols, cfg.staging, cfg.P, cfg.cnt16);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     ReqDesc dd = d;

@@ -61,6 +61,7 @@ struct LaunchCfg {
     int32_t P = 0;        // individuals per group (max individuals sharing a block)
     int32_t staging = STAGE_LDS;
     int32_t blocks = 0;   // plain: tile ranges per group; batch: persistent grid; 0 = derive
+    bool cnt16 = false;   // plain: counts as 16-bit halves (16-bit codes; set by the planner)
 };
 
 // A resident matrix as the kernels see it.
@@ -141,8 +142,9 @@ struct BatchHeader {
 // the per-individual counts of a group of P.
 size_t tile_lds_bytes(int32_t L, int32_t cols, int32_t staging);
 size_t count_lds_bytes(int32_t P);
-// All dynamic LDS of one plain-evaluation item (tile and counts).
-size_t item_lds_bytes(int32_t L, int32_t cols, int32_t staging, int32_t P);
+// All dynamic LDS of one plain-evaluation item (tile and counts; cnt16:
+// both counts of an individual in one 32-bit word).
+size_t item_lds_bytes(int32_t L, int32_t cols, int32_t staging, int32_t P, bool cnt16 = false);
 
 // Blocks per CU the plain evaluation kernel reaches with this shape (0 = cannot run).
 int eval_occupancy(const LaunchCfg &cfg, int32_t cols, uint32_t flags);

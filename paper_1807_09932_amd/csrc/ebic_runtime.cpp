@@ -116,16 +116,37 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
     if (cfg.staging == STAGE_LDS && !fits(cfg)) cfg.staging = STAGE_DIRECT;
     while (!fits(cfg) && cfg.P > 64) cfg.P /= 2;
     const int64_t n_tiles = (m.dev.rows + 63) / 64;
+    const int64_t n_chunks = (n_tiles + cfg.L - 1) / cfg.L;
     const int32_t groups = (n + cfg.P - 1) / cfg.P;
-    if (cfg.blocks <= 0) {
-        int occ = eval_occupancy(cfg, m.dev.cols, flags);
-        if (occ <= 0) occ = 1;
-        const int64_t slots = (int64_t)ctx->cu_count * occ;
-        int64_t bx = std::max<int64_t>(1, slots / std::max(1, groups));
-        bx = std::min<int64_t>(bx, (n_tiles + cfg.L - 1) / cfg.L);
-        cfg.blocks = (int32_t)std::max<int64_t>(1, bx);
+    const int32_t forced_blocks = cfg.blocks;
+    auto derive_blocks = [&] {
+        cfg.blocks = forced_blocks;
+        if (cfg.blocks <= 0) {
+            int occ = eval_occupancy(cfg, m.dev.cols, flags);
+            if (occ <= 0) occ = 1;
+            const int64_t slots = (int64_t)ctx->cu_count * occ;
+            int64_t bx = std::max<int64_t>(1, slots / std::max(1, groups));
+            bx = std::min<int64_t>(bx, n_chunks);
+            cfg.blocks = (int32_t)std::max<int64_t>(1, bx);
+        }
+        cfg.blocks = (int32_t)std::min<int64_t>(cfg.blocks, std::max<int64_t>(1, n_tiles));
+    };
+    // With 16-bit codes the kernel keeps counts as 16-bit halves (half the
+    // LDS beside a wide tile, which can leave room for a second block per
+    // CU); that needs every block's tile range below 65,536 rows, so more
+    // ranges are used where the matrix is taller.
+    cfg.cnt16 = cfg.staging == STAGE_HALVES;
+    derive_blocks();
+    if (cfg.cnt16) {
+        const int64_t min_ranges = (n_chunks * cfg.L * 64 + 65535 - 1) / 65535;
+        const int64_t need = std::max<int64_t>(min_ranges, 1);
+        if ((n_chunks + cfg.blocks - 1) / cfg.blocks * cfg.L * 64 > 65535) {
+            // the smallest range count whose largest range fits
+            int64_t r = std::max<int64_t>(cfg.blocks, need);
+            while ((n_chunks + r - 1) / r * cfg.L * 64 > 65535) ++r;
+            cfg.blocks = (int32_t)std::min<int64_t>(r, std::max<int64_t>(1, n_tiles));
+        }
     }
-    cfg.blocks = (int32_t)std::min<int64_t>(cfg.blocks, std::max<int64_t>(1, n_tiles));
     return cfg;
 }
 

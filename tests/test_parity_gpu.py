@@ -408,3 +408,33 @@ def test_measurement_variant_agrees(ctx, tiles_per_wave, staging):
         ebic.ebic_set_profiling(ctx.handle, 0)
         ctx.set_launch_shape()
         ctx.release(mat)
+
+
+def test_halves_tall_ranges(ctx):
+    """16-bit SWAR codes keep a block's counts in 16 bits, so the planner
+    keeps every tile range below 65,536 rows: a 140,000-row matrix with one
+    range per group forced is split into ranges that fit, and the counts
+    (some individuals match most rows) stay exact."""
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(1500)
+    rows, ncols = 140000, 160
+    X = rng.standard_normal((rows, ncols)).astype(np.float32)
+    X[:, 1] = X[:, 0] + 1.0  # columns 0, 1 rise on every row
+    inds = [np.array([0, 1]), np.array([1, 0]), np.array([0, 1, 5]), np.array([3])] + \
+        [rng.choice(ncols, size=int(rng.integers(2, 12)), replace=False) for _ in range(60)]
+    offs, cols = gen.csr(inds)
+    mat = ctx.upload(X)
+    try:
+        ctx.set_launch_shape(2, 16, 64, ebic.STAGE_HALVES, 1)
+        plan = ebic.ebic_plan_shape(ctx.handle, mat, offs.size - 1, int(offs[-1]))
+        assert plan[3] == ebic.STAGE_HALVES
+        chunks = -(-rows // (plan[0] * 64))
+        assert -(-chunks // plan[4]) * plan[0] * 64 <= 65535, plan
+        announce("halves tall", plan)
+        got = gpu_eval(ctx, mat, offs, cols, negative=True)
+        want = oracle_eval(X, offs, cols, negative=True)
+        assert_same(got, want, "halves 140000 rows")
+        assert got[0][0] == rows and got[0][3] == rows  # every row matches
+    finally:
+        ctx.set_launch_shape()
+        ctx.release(mat)
