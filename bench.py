@@ -694,7 +694,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {STAGE_BYTES: "u8", STAGE_HALVES: "u16", 2: "f16"}.get(stg, "f32"),
+        "dtype_note": "the type the evaluation kernel compares: the rank codes it stages "
+                      "(u8: byte codes, four per 32-bit lane word; u16: two per word; f16: FP16 "
+                      "codes) or the FP32 values; the resident matrix and the code build are "
+                      "FP32, and the counts are exact integers",
         "data": "synthetic",
         "config": {
             "workload": "methylation-shaped plain eval: %d x %d FP32 Beta(0.5,0.5), 10 planted "
