@@ -270,8 +270,14 @@ def bench_paper_shape(ctx, args):
     mat = ctx.upload(w.X)
     p = ctx.population(offsets=offs, cols=cols)
     out = ctx.outputs(mat, p.n)
-    ctx.set_launch_shape(0, 0, 0, ebic.STAGE_LDS, 0)
-    ctx.autotune([ctx.request(mat, p, out)])
+    if args.paper_shape:
+        # a forced launch shape (profiling runs: no autotuning launches)
+        ctx.set_launch_shape(*[int(x) for x in args.paper_shape.split(",")], 0)
+        how = "forced"
+    else:
+        ctx.set_launch_shape(0, 0, 0, ebic.STAGE_LDS, 0)
+        ctx.autotune([ctx.request(mat, p, out)])
+        how = "autotuned"
     L, W, P, stg, blocks = ebic.ebic_plan_shape(ctx.handle, mat, p.n, int(offs[-1]))
     ctx.eval(mat, p, out=out)
     torch.cuda.synchronize()
@@ -298,7 +304,7 @@ def bench_paper_shape(ctx, args):
     ctx.release(mat)
     return {"workload": "%d x %d FP32 Beta(0.5,0.5), 10 planted trends, %d individuals of "
                         "2-30 columns" % (rows, ncols, p.n),
-            "launch_shape": f"L={L} W={W} P={P} staging={stg} blocks={blocks}",
+            "launch_shape": f"{how}: L={L} W={W} P={P} staging={stg} blocks={blocks}",
             "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
             "roofline": alu_roofline(steps, k_ms, stg),
             "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9}
@@ -504,6 +510,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--rows", type=int, default=436444, help="(testing only) smaller matrix")
+    ap.add_argument("--paper-shape", type=str, default="",
+                    help="L,W,P,staging for the 'paper' extra instead of autotuning it")
     ap.add_argument("--shape", type=str, default="",
                     help="force the launch shape 'L,W,P[,S]' (64-row tiles per wave, waves per "
                          "block, individuals per group, staging: 0 FP32 tile, 1 direct, "
