@@ -126,7 +126,49 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
 ebic_status ebic_matrix_info(ebic_ctx *ctx, int32_t matrix, int64_t *rows, int32_t *cols,
                              int64_t *device_bytes);
 
-/* Free a resident matrix (waits for the device first). */
+/* Code sets a resident matrix may hold (ebic_matrix_stats.code_sets, from ebic_matrix_get_stats). */
+enum {
+    EBIC_SET_FILL_COPY = 1u,   /* FP32 copy with missing cells replaced by the fill */
+    EBIC_SET_FP16 = 2u,        /* FP16 rank codes of the values (missing = NaN) */
+    EBIC_SET_FP16_FILL = 4u,   /* FP16 rank codes of the fill copy */
+    EBIC_SET_U8 = 8u,          /* byte rank codes of the fill-substituted values */
+    EBIC_SET_U16 = 16u         /* 16-bit rank codes of the fill-substituted values */
+};
+
+/*
+ * What a resident matrix holds and what its upload cost (for reports and
+ * tests; the values are stated as of this call).
+ *   value_bytes:     the FP32 matrix, plus its fill copy if kept.
+ *   code_bytes:      every rank-code set resident now, with its flags.
+ *   swar_chunks:     512-row chunks of the byte or 16-bit codes (0 without).
+ *   swar_tie_chunks: of those, the chunks in which some row holds two equal
+ *                    (code-equal) cells; the evaluation runs the first
+ *                    pair's tie handling only on these.
+ *   has_missing:     1 if a cell is missing, 0 if none, -1 if not known
+ *                    (no SWAR code set was built).
+ *   upload_ms:       host wall time of the ebic_upload_matrix call.
+ * Copies a few bytes per 512 rows back from the device (synchronous).
+ */
+typedef struct {
+    int64_t rows;
+    int32_t cols;
+    uint32_t code_sets;        /* EBIC_SET_* */
+    int64_t value_bytes;
+    int64_t code_bytes;
+    int64_t swar_chunks;
+    int64_t swar_tie_chunks;
+    int32_t has_missing;
+    int32_t reserved;
+    double upload_ms;
+} ebic_matrix_stats;
+ebic_status ebic_matrix_get_stats(ebic_ctx *ctx, int32_t matrix, ebic_matrix_stats *out);
+
+/*
+ * Free a resident matrix. Waits for the device to finish the work already
+ * enqueued. Returns EBIC_EBUSY, freeing nothing, while a call on another
+ * thread is between reading the matrix and enqueuing its kernels, or while
+ * a serving engine holds requests on it that have not completed.
+ */
 ebic_status ebic_release_matrix(ebic_ctx *ctx, int32_t matrix);
 
 /* Number of uint64 mask words per individual: ceil(rows / 64). */

@@ -66,28 +66,55 @@ __host__ __device__ inline size_t count_bytes_of(int32_t P, bool cnt16 = false)
 // One wave per individual: the lanes check its columns together (one round
 // of independent loads for up to 64 columns), lane 0 initialises the
 // outputs, and lanes 0..15 write the 64-byte header word by word.
+//
+// A leading run of repeats of the first column is dropped from the header
+// (begin moves to the run's last entry, k shrinks by the same amount):
+// comparing a cell with itself always holds (x >= x and x <= x for any
+// present value; a missing one is excluded by the kept copy of the column
+// in exclude mode and takes the fill value in include mode), so
+// c, c, ..., c, rest follows exactly the rows of c, rest, on both chains.
+// The evaluation then never sees a first pair that compares a cell with
+// itself, which is what lets a chunk without two equal values in any row
+// skip the tie handling of the first pair (the SWAR sequences' tie-free
+// variants classify every row as rising or falling there).
 __device__ __forceinline__ void prep_wave(const ReqDesc &d, int32_t i, IndHead *__restrict__ heads, int lane)
 {
     const int32_t b = d.offsets[i], e = d.offsets[i + 1];
     const bool span = b >= 0 && e > b;
     bool bad = false;
-    int32_t win = 0;  // lanes 8..15: window column lane - 8 (clamped to the last column)
+    int32_t first = 0;  // lane l: column l of the individual (first 64)
+    int32_t run = 0;    // entries b .. b + run hold the first column
     if (span) {
-        if (lane >= 8 && lane < 16) win = d.colidx[b + min(lane - 8, e - b - 1)];
-        for (int32_t j = b + lane; j < e; j += kWave) {
-            const int32_t c = d.colidx[j];
-            bad |= c < 0 || c >= d.cols;
+        const int32_t c0 = d.colidx[b];
+        run = e - b - 1;  // unless a different column follows
+        bool found = false;
+        for (int32_t jb = b; jb < e; jb += kWave) {  // (wave-uniform trip count)
+            const int32_t j = jb + lane;
+            const bool in = j < e;
+            const int32_t c = in ? d.colidx[j] : c0;
+            if (jb == b) first = c;
+            bad |= in && (c < 0 || c >= d.cols);
+            const uint64_t differ = __ballot(in && c != c0);
+            if (!found && differ != 0) {
+                found = true;
+                run = (jb - b) + (int32_t)__builtin_ctzll(differ) - 1;
+            }
         }
     }
     const bool ok = span && __ballot(bad) == 0;
-    const int32_t k = ok ? e - b : 0;
+    const int32_t bb = b + run;      // the header's CSR start
+    const int32_t k = ok ? e - bb : 0;
+    // lanes 8..15: window column lane - 8 from bb (clamped to the last column)
+    const int32_t src = run + min(lane - 8, e - bb - 1);
+    int32_t win = __shfl(first, (src >= 0 && src < kWave) ? src : 0);
+    if (span && lane >= 8 && lane < 16 && src >= kWave) win = d.colidx[b + src];
     if (lane == 0) {
         d.matched[i] = ok ? 0 : kInvalid;
         if (d.negative) d.negative[i] = ok ? 0 : kInvalid;
     }
     if (lane < 16) {
         // words: k, begin, 6 x 0, the window
-        const int32_t v = lane == 0 ? k : lane == 1 ? b : (lane >= 8 && ok) ? win : 0;
+        const int32_t v = lane == 0 ? k : lane == 1 ? bb : (lane >= 8 && ok) ? win : 0;
         reinterpret_cast<int32_t *>(heads + d.head_base + i)[lane] = v;
     }
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -356,6 +357,7 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
         const bool on_device = flags & EBIC_SRC_DEVICE;
         hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
 
+        const auto t_start = std::chrono::steady_clock::now();
         DeviceGuard g(ctx->device);
         std::lock_guard<std::mutex> lk(ctx->mu);
         Matrix m;
@@ -373,6 +375,7 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
                 m.Xfill = static_cast<float *>(ctx_alloc(ctx, bytes));
                 m.bytes += bytes;
             }
+            m.value_bytes = m.bytes;
             // Rows are laid out chunk by chunk through a bounded staging buffer.
             const int64_t chunk_bytes = 64ll << 20;
             int64_t chunk = std::max<int64_t>(64, chunk_bytes / ((int64_t)cols * 4) / 64 * 64);
@@ -462,6 +465,8 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
             m.dev.b_exclude = m.B && has_nan == 0;
             m.dev.h_exclude = m.Hc && has_nan_h == 0;
+            if (m.B) m.has_missing = has_nan != 0;
+            if (m.Hc) m.has_missing = has_nan_h != 0;
         } catch (...) {
             ctx_free(ctx, staging);
             ctx_free(ctx, m.X);
@@ -479,9 +484,40 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
         m.dev.Cfill = m.Cfill;
         m.dev.B = m.B;
         m.dev.Hc = m.Hc;
+        m.upload_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         const int32_t id = ctx->next_matrix++;
         ctx->matrices[id] = m;
         *out_matrix = id;
+    });
+}
+
+ebic_status ebic_matrix_get_stats(ebic_ctx *ctx, int32_t matrix, ebic_matrix_stats *out)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        if (!out) fail(EBIC_EINVAL, "out is NULL");
+        DeviceGuard g(ctx->device);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        const Matrix &m = ctx_matrix(ctx, matrix);
+        ebic_matrix_stats st{};
+        st.rows = m.dev.rows;
+        st.cols = m.dev.cols;
+        st.code_sets = (m.Xfill ? EBIC_SET_FILL_COPY : 0u) | (m.C ? EBIC_SET_FP16 : 0u) |
+                       (m.Cfill ? EBIC_SET_FP16_FILL : 0u) | (m.B ? EBIC_SET_U8 : 0u) | (m.Hc ? EBIC_SET_U16 : 0u);
+        st.value_bytes = (int64_t)m.value_bytes;
+        st.code_bytes = (int64_t)(m.bytes - m.value_bytes);
+        st.has_missing = m.has_missing;
+        st.upload_ms = m.upload_ms;
+        const int32_t *ties = m.B ? m.dev.T : m.Hc ? m.dev.Th : nullptr;
+        if (ties) {
+            const int64_t rows_pad = m.B ? m.dev.ldb : (m.dev.rows + 255) / 256 * 256;
+            const int64_t n = (rows_pad + 511) / 512;
+            std::vector<int32_t> h((size_t)n);
+            hip_check(hipMemcpy(h.data(), ties, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy");
+            st.swar_chunks = n;
+            for (int32_t v : h) st.swar_tie_chunks += v != 0;
+        }
+        *out = st;
     });
 }
 

@@ -24,8 +24,11 @@ struct Matrix {
     uint16_t *Cfill = nullptr;  // rank codes of Xfill
     uint8_t *B = nullptr;       // byte rank codes (cols <= kMaxByteCols)
     uint8_t *Hc = nullptr;      // 16-bit rank codes (kMaxByteCols < cols <= kMaxCodeCols)
-    size_t bytes = 0;
+    size_t bytes = 0;        // everything resident for this matrix
+    size_t value_bytes = 0;  // X and Xfill
     float sentinel = 0.f;
+    int32_t has_missing = -1;  // from the SWAR code build (-1: not built)
+    double upload_ms = 0;
 };
 
 // Shape class of a tuning entry: log2 buckets of rows, columns, population

@@ -43,7 +43,7 @@ STAGE_BYTES = 3   # byte rank codes, four rows per lane word (<= 128 columns; 4 
 STAGE_HALVES = 4  # 16-bit rank codes, two rows per lane word (129..384 columns; 2 or 4 tiles per wave)
 
 EXPORTED = ["ebic_create", "ebic_destroy", "ebic_set_allocator", "ebic_last_error",
-            "ebic_upload_matrix", "ebic_matrix_info", "ebic_release_matrix",
+            "ebic_upload_matrix", "ebic_matrix_info", "ebic_matrix_get_stats", "ebic_release_matrix",
             "ebic_mask_words", "ebic_eval_population", "ebic_eval_batch", "ebic_autotune",
             "ebic_set_launch_shape", "ebic_set_profiling", "ebic_read_profile",
             "ebic_plan_shape", "ebic_plan_batch_shape", "ebic_server_request_bytes", "ebic_server_create",
@@ -76,6 +76,17 @@ class ebic_server_stats(ctypes.Structure):
                 ("mean_batch", ctypes.c_double), ("latency_max_ms", ctypes.c_double),
                 ("graph_captures", ctypes.c_int64), ("staging_grows", ctypes.c_int64),
                 ("queue_p99_ms", ctypes.c_double)]
+
+
+class ebic_matrix_stats(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int32), ("code_sets", ctypes.c_uint32),
+                ("value_bytes", ctypes.c_int64), ("code_bytes", ctypes.c_int64),
+                ("swar_chunks", ctypes.c_int64), ("swar_tie_chunks", ctypes.c_int64),
+                ("has_missing", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("upload_ms", ctypes.c_double)]
+
+
+SET_FILL_COPY, SET_FP16, SET_FP16_FILL, SET_U8, SET_U16 = 1, 2, 4, 8, 16
 
 
 class ebic_ea_params(ctypes.Structure):
@@ -115,6 +126,7 @@ def load_library(path: str = LIB_PATH):
         "ebic_upload_matrix": (I32, [P, P, I64, I32, I64, U32, F, F, P, ctypes.POINTER(I32)]),
         "ebic_matrix_info": (I32, [P, I32, ctypes.POINTER(I64), ctypes.POINTER(I32),
                                    ctypes.POINTER(I64)]),
+        "ebic_matrix_get_stats": (I32, [P, I32, ctypes.POINTER(ebic_matrix_stats)]),
         "ebic_release_matrix": (I32, [P, I32]),
         "ebic_mask_words": (I64, [I64]),
         "ebic_eval_population": (I32, [P, I32, I32, P, P, U32, P, P, P, P, P]),
@@ -194,6 +206,12 @@ def ebic_matrix_info(ctx: int, matrix: int) -> Tuple[int, int, int]:
     _check(load_library().ebic_matrix_info(ctx, matrix, ctypes.byref(r), ctypes.byref(c),
                                            ctypes.byref(b)))
     return r.value, c.value, b.value
+
+
+def ebic_matrix_get_stats(ctx: int, matrix: int) -> dict:
+    st = ebic_matrix_stats()
+    _check(load_library().ebic_matrix_get_stats(ctx, matrix, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in st._fields_ if name != "reserved"}
 
 
 def ebic_release_matrix(ctx: int, matrix: int) -> None:
@@ -552,6 +570,9 @@ class Context:
 
     def info(self, matrix: int):
         return ebic_matrix_info(self.handle, matrix)
+
+    def stats(self, matrix: int) -> dict:
+        return ebic_matrix_get_stats(self.handle, matrix)
 
     # -- populations --------------------------------------------------------
     def population(self, individuals=None, offsets=None, cols=None) -> Population:

@@ -25,6 +25,10 @@ missing values are either excluded or take part through a fill value):
 * pin_invariants       -- bounds, prefix nesting, reversal, mode nesting,
   exact scaling, negation, row and column permutations.
 * pin_invalid          -- the -1 convention for invalid individuals.
+* pin_repeated_columns -- reflexivity of the relation (x >= x and x <= x
+  for every present value): repeating a column in place, at the start or
+  anywhere inside an individual, changes no count and no mask bit, in
+  both missing-value modes.
 """
 from __future__ import annotations
 
@@ -284,6 +288,31 @@ def pin_invalid(ev):
     assert int(mm[0][0]) == (1 << 10) - 1
 
 
+def pin_repeated_columns(ev):
+    rng = np.random.default_rng(17)
+    rows, ncols = 600, 12
+    X = rng.standard_normal((rows, ncols)).astype(np.float32)
+    X[rng.random((rows, ncols)) < 0.04] = NAN
+    X[:50, 3] = X[:50, 5]  # some ties between different columns too
+    base = [rng.permutation(ncols)[: int(rng.integers(1, 9))] for _ in range(30)]
+    rep = []
+    for ind in base:
+        ind = list(ind)
+        at = int(rng.integers(0, len(ind)))
+        times = int(rng.integers(1, 4))
+        rep.append(ind[: at + 1] + [ind[at]] * times + ind[at + 1:])
+    lead = [[ind[0]] * int(rng.integers(2, 5)) + list(ind[1:]) for ind in base]
+    for include in (False, True):
+        want = _run(ev, X, base, include=include, fill=0.25)
+        for other in (rep, lead):
+            got = _run(ev, X, other, include=include, fill=0.25)
+            for a, b in zip(got, want):
+                assert np.array_equal(a, b), include
+    # a column repeated throughout: every row with the value present, none negative
+    m, n, _, _ = _run(ev, X, [[4, 4, 4]])
+    assert m[0] == int((~np.isnan(X[:, 4])).sum()) and n[0] == 0
+
+
 ALL_PINS = [pin_multiset_count, pin_permutation_count, pin_sort_reduction,
             pin_closed_forms, pin_constant_and_sorted_rows, pin_planted,
-            pin_invariants, pin_invalid]
+            pin_invariants, pin_invalid, pin_repeated_columns]
