@@ -199,6 +199,30 @@ ebic_status ebic_eval_population(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
                                  uint64_t *d_matched_mask, uint64_t *d_negative_mask,
                                  void *hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * evaluation as ebic_eval_population, with the same arguments, outputs and
+ * errors, that allocates nothing. It calls no hipMalloc or hipFree and no
+ * allocator hook; the per-individual headers that ebic_eval_population keeps
+ * in stream scratch go to a fixed device buffer instead, which each device
+ * holds from ebic_create until the process ends.
+ *   Limit: n_ind <= 65,536 (4 MiB of 64-byte headers per device); a larger
+ *   population returns EBIC_EINVAL and enqueues nothing.
+ *   Sharing: every call on one device uses the same buffer, and it keeps
+ *   the last call's headers (the prep kernel rewrites every header a call
+ *   reads, so nothing has to start at zero). Calls in order on one stream
+ *   are safe; calls that overlap on one device (other streams, other
+ *   threads, other contexts) race on the buffer and must be serialised by
+ *   the caller.
+ *   No profiling events are recorded for these launches.
+ */
+ebic_status ebic_eval_population_noalloc(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
+                                         const int32_t *d_offsets, const int32_t *d_cols, uint32_t flags,
+                                         int32_t *d_matched, int32_t *d_negative,
+                                         uint64_t *d_matched_mask, uint64_t *d_negative_mask,
+                                         void *hip_stream);
+
 /* One population-evaluation request of a batch (same meaning as above). */
 typedef struct ebic_request {
     int32_t matrix;

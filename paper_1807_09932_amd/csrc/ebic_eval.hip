@@ -35,6 +35,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "ebic_internal.h"
@@ -2044,6 +2046,43 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
     if (e != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, s);
     return e;
+}
+
+}  // namespace ebic
+
+// ---------------------------------------------------------------------------
+// The fixed header buffer of ebic_eval_population_noalloc: room for the
+// 64-byte headers of kNoAllocMaxInd individuals, one copy per device (each
+// device that loads this code object holds its own, until the process
+// ends). Host code never passes the array's name to a kernel: it takes the
+// device address from hipGetSymbolAddress once per device and uses that.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) ebic::IndHead scratch[ebic::kNoAllocMaxInd];
+
+namespace ebic {
+
+namespace {
+std::mutex g_noalloc_mu;
+std::map<int, void *> g_noalloc_ptr;  // device -> address of `scratch` there
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr.count(device)) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+IndHead *noalloc_scratch(int device)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc_ptr.find(device);
+    return it == g_noalloc_ptr.end() ? nullptr : static_cast<IndHead *>(it->second);
 }
 
 hipError_t launch_batch(BatchHeader *hdr, const ReqDesc *descs, const int64_t *first,

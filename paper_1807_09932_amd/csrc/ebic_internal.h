@@ -157,6 +157,14 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
                        unsigned long long *step_counter, hipStream_t s,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// The no-allocation evaluation's header buffer: a fixed device array of
+// kNoAllocMaxInd headers per device. noalloc_scratch_init (called with
+// `device` current, once per device, at context creation) looks up its
+// device address; noalloc_scratch returns it (null before the init).
+constexpr int32_t kNoAllocMaxInd = 65536;
+hipError_t noalloc_scratch_init(int device);
+IndHead *noalloc_scratch(int device);
+
 // Batched evaluation over a device-resident batch arena:
 //   hdr (BatchHeader) | descs (ReqDesc[n_req]) | first (int64[n_req + 1],
 //   prefix sums of individuals) | items (Item[n_items])

@@ -275,6 +275,7 @@ ebic_status ebic_create(int32_t hip_device, ebic_ctx **out)
             fail(EBIC_EINVAL, "device " + std::to_string(hip_device) + " out of range (" +
                                   std::to_string(n) + " devices)");
         DeviceGuard g(hip_device);
+        hip_check(noalloc_scratch_init(hip_device), "address of the no-allocation header buffer");
         hipDeviceProp_t prop;
         hip_check(hipGetDeviceProperties(&prop, hip_device), "hipGetDeviceProperties");
         auto *ctx = new ebic_ctx();
@@ -576,6 +577,39 @@ ebic_status ebic_eval_population(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
         }
         DeviceGuard g(ctx->device);
         hip_check(ctx_launch_eval(ctx, d, cfg, reinterpret_cast<hipStream_t>(hip_stream)),
+                  "evaluation launch");
+    });
+}
+
+ebic_status ebic_eval_population_noalloc(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
+                                         const int32_t *d_offsets, const int32_t *d_cols, uint32_t flags,
+                                         int32_t *d_matched, int32_t *d_negative,
+                                         uint64_t *d_matched_mask, uint64_t *d_negative_mask,
+                                         void *hip_stream)
+{
+    return guarded([&] {
+        if (!ctx) fail(EBIC_EINVAL, "ctx is NULL");
+        if (n_ind < 0) fail(EBIC_EINVAL, "n_ind < 0");
+        if (n_ind > kNoAllocMaxInd)
+            fail(EBIC_EINVAL, "n_ind = " + std::to_string(n_ind) + " exceeds the no-allocation limit of " +
+                                  std::to_string(kNoAllocMaxInd) + " individuals");
+        if (flags & ~(EBIC_NAN_INCLUDE | EBIC_NEG_TRENDS)) fail(EBIC_EINVAL, "unknown eval flags");
+        ReqDesc d;
+        LaunchCfg cfg;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            const Matrix &m = ctx_matrix(ctx, matrix);
+            if (n_ind == 0) return;
+            if (!d_offsets || !d_cols || !d_matched)
+                fail(EBIC_EINVAL, "d_offsets, d_cols and d_matched are required");
+            cfg = plan_eval(ctx, m, n_ind, -1, flags);
+            d = make_desc(m, n_ind, d_offsets, d_cols, flags, d_matched, d_negative, d_matched_mask,
+                          d_negative_mask, cfg.staging);
+        }
+        DeviceGuard g(ctx->device);
+        IndHead *heads = noalloc_scratch(ctx->device);
+        if (!heads) fail(EBIC_EHIP, "the no-allocation header buffer is not set up on this device");
+        hip_check(launch_eval(d, heads, cfg, nullptr, reinterpret_cast<hipStream_t>(hip_stream)),
                   "evaluation launch");
     });
 }

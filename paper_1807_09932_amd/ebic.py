@@ -44,7 +44,7 @@ STAGE_HALVES = 4  # 16-bit rank codes, two rows per lane word (129..384 columns;
 
 EXPORTED = ["ebic_create", "ebic_destroy", "ebic_set_allocator", "ebic_last_error",
             "ebic_upload_matrix", "ebic_matrix_info", "ebic_matrix_get_stats", "ebic_release_matrix",
-            "ebic_mask_words", "ebic_eval_population", "ebic_eval_batch", "ebic_autotune",
+            "ebic_mask_words", "ebic_eval_population", "ebic_eval_population_noalloc", "ebic_eval_batch", "ebic_autotune",
             "ebic_set_launch_shape", "ebic_set_profiling", "ebic_read_profile",
             "ebic_plan_shape", "ebic_plan_batch_shape", "ebic_server_request_bytes", "ebic_server_create",
             "ebic_server_destroy", "ebic_server_submit", "ebic_server_poll",
@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH):
         "ebic_release_matrix": (I32, [P, I32]),
         "ebic_mask_words": (I64, [I64]),
         "ebic_eval_population": (I32, [P, I32, I32, P, P, U32, P, P, P, P, P]),
+        "ebic_eval_population_noalloc": (I32, [P, I32, I32, P, P, U32, P, P, P, P, P]),
         "ebic_eval_batch": (I32, [P, ctypes.POINTER(ebic_request), I32, P]),
         "ebic_autotune": (I32, [P, ctypes.POINTER(ebic_request), I32, ctypes.c_char_p]),
         "ebic_set_launch_shape": (I32, [P, I32, I32, I32, I32, I32]),
@@ -229,6 +230,15 @@ def ebic_eval_population(ctx: int, matrix: int, n_ind: int, d_offsets: int, d_co
     _check(load_library().ebic_eval_population(ctx, matrix, n_ind, d_offsets, d_cols, flags,
                                                d_matched, d_negative, d_matched_mask,
                                                d_negative_mask, hip_stream))
+
+
+def ebic_eval_population_noalloc(ctx: int, matrix: int, n_ind: int, d_offsets: int, d_cols: int,
+                                 flags: int, d_matched: int, d_negative: Optional[int],
+                                 d_matched_mask: Optional[int], d_negative_mask: Optional[int],
+                                 hip_stream: int) -> None:
+    _check(load_library().ebic_eval_population_noalloc(ctx, matrix, n_ind, d_offsets, d_cols, flags,
+                                                       d_matched, d_negative, d_matched_mask,
+                                                       d_negative_mask, hip_stream))
 
 
 def ebic_eval_batch(ctx: int, reqs: Sequence[ebic_request], hip_stream: int) -> None:
