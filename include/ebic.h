@@ -64,7 +64,8 @@ enum {
     EBIC_EHIP = -3,     /* a HIP runtime call failed */
     EBIC_ENOENT = -4,   /* unknown matrix handle */
     EBIC_EBUSY = -5,    /* resource in use */
-    EBIC_EBUDGET = -6   /* request exceeds a memory budget */
+    EBIC_EBUDGET = -6,  /* request exceeds a memory budget */
+    EBIC_ECANCELED = -7 /* a serving request was cancelled before it ran */
 };
 
 /* Evaluation flags. */
@@ -350,6 +351,7 @@ typedef struct ebic_server_stats {
     int64_t graph_captures;   /* batch graphs the context has captured in all */
     int64_t staging_grows;    /* pinned staging buffers enlarged */
     double queue_p99_ms;      /* submission to the enqueue of the request's batch */
+    int64_t cancelled;        /* requests cancelled before they ran */
 } ebic_server_stats;
 
 /*
@@ -386,7 +388,9 @@ ebic_status ebic_server_destroy(ebic_server *srv);
  * negative mask needs `negative`) are host buffers that the server writes
  * when the request completes: they must stay valid until ebic_server_poll
  * returns `tag`. flags: EBIC_NAN_INCLUDE, EBIC_NEG_TRENDS. Results equal
- * those of ebic_eval_population on the same inputs. Errors: EBIC_EINVAL
+ * those of ebic_eval_population on the same inputs. From submission until
+ * the request completes (or is cancelled) it holds its matrix:
+ * ebic_release_matrix returns EBIC_EBUSY meanwhile. Errors: EBIC_EINVAL
  * (arguments, negative offsets), EBIC_ENOENT (unknown matrix), EBIC_EBUDGET
  * (the request alone exceeds the budget), EBIC_EBUSY (shutting down).
  */
@@ -402,6 +406,21 @@ ebic_status ebic_server_submit(ebic_server *srv, int32_t matrix, int32_t n_ind,
  */
 ebic_status ebic_server_poll(ebic_server *srv, uint64_t *tags, ebic_status *statuses,
                              int32_t max_tags, int32_t timeout_us, int32_t *n_done);
+
+/*
+ * Cancel a request that has not been launched yet: it leaves the queue, its
+ * outputs are not written, it releases its matrix, and ebic_server_poll
+ * returns its tag with status EBIC_ECANCELED. Returns EBIC_EBUSY if the
+ * request's batch is already on the device (it will complete normally) and
+ * EBIC_ENOENT if no submitted, uncompleted request has this tag.
+ */
+ebic_status ebic_server_cancel(ebic_server *srv, uint64_t tag);
+
+/*
+ * paused != 0: launch no new batch (submissions still queue; batches on the
+ * device complete); 0: resume. For draining and for deterministic tests.
+ */
+ebic_status ebic_server_set_paused(ebic_server *srv, int32_t paused);
 
 /* Counters and latency percentiles; reset != 0 starts a new window. */
 ebic_status ebic_server_get_stats(ebic_server *srv, ebic_server_stats *out, int32_t reset);

@@ -117,7 +117,7 @@ struct Plan {
     int32_t grid = 0;
 };
 
-static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, bool count)
+static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, bool count, CodesMode codes)
 {
     Plan p;
     p.first.push_back(0);
@@ -159,10 +159,14 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     // the counts, else direct reads.
     for (int32_t q = 0; q < n_reqs; ++q) {
         const ebic_request &r = reqs[q];
-        const Matrix &m = ctx_matrix(ctx, r.matrix);
-        const bool have_codes = ((r.flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
-        const bool have_bytes = m.dev.B && ((r.flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
-        const bool have_halves = m.dev.Hc && ((r.flags & EBIC_NAN_INCLUDE) || m.dev.h_exclude);
+        Matrix &m = ctx_matrix_mut(ctx, r.matrix);
+        const bool include = (r.flags & EBIC_NAN_INCLUDE) != 0;
+        // FP16 codes not resident yet count as available when they can be
+        // built; they are built below if this request stages them.
+        const bool built_codes = (include ? m.dev.Cfill : m.dev.C) != nullptr;
+        const bool have_codes = built_codes || (codes != CODES_EXISTING && codes_buildable(m, include));
+        const bool have_bytes = m.dev.B && (include || m.dev.b_exclude);
+        const bool have_halves = m.dev.Hc && (include || m.dev.h_exclude);
         auto fits = [&](int32_t stg) {
             return tile_lds_bytes(c.L, m.dev.cols, stg) + count_lds_bytes(c.P) <= lds_max;
         };
@@ -174,8 +178,14 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
         else if (wants_swar && c.L == 2 && have_halves && fits(STAGE_HALVES)) staging = STAGE_HALVES;
         else if (codes_ok && (wants_codes || !fits(STAGE_LDS))) staging = STAGE_CODES;
         else if (fits(STAGE_LDS)) staging = STAGE_LDS;
+        if (staging == STAGE_CODES && !built_codes && codes == CODES_BUILD && r.n_ind > 0)
+            build_fp16_codes(ctx, m, include);
+        // (a report plans codes that are not built yet: its descriptors are
+        // never launched)
+        const bool unbuilt = staging == STAGE_CODES && (include ? m.dev.Cfill : m.dev.C) == nullptr;
         ReqDesc d = make_desc(m, std::max(0, r.n_ind), r.d_offsets, r.d_cols, r.flags, r.d_matched,
-                              r.d_negative, r.d_matched_mask, r.d_negative_mask, staging);
+                              r.d_negative, r.d_matched_mask, r.d_negative_mask,
+                              unbuilt && (codes == CODES_REPORT || r.n_ind <= 0) ? STAGE_LDS : staging);
         d.head_base = p.first.back();
         p.stagings.push_back(staging);
         p.tile_bytes = std::max(p.tile_bytes, tile_lds_bytes(c.L, m.dev.cols, staging));
@@ -328,7 +338,7 @@ extern "C" ebic_status ebic_plan_batch_shape(ebic_ctx *ctx, const ebic_request *
         if (n_reqs < 1 || !reqs) fail(EBIC_EINVAL, "need at least one request");
         DeviceGuard dg(ctx->device);
         std::lock_guard<std::mutex> lk(ctx->mu);
-        const Plan p = plan_batch(ctx, reqs, n_reqs, false);
+        const Plan p = plan_batch(ctx, reqs, n_reqs, false, CODES_REPORT);
         if (tiles_per_wave) *tiles_per_wave = p.cfg.L;
         if (waves_per_block) *waves_per_block = p.cfg.W;
         if (individuals_per_group) *individuals_per_group = p.cfg.P;
@@ -349,10 +359,13 @@ extern "C" ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, 
         DeviceGuard dg(ctx->device);
         Plan p;
         int32_t prof_mode;
+        MatrixHold hold(ctx);  // until the graph is launched
         {
             std::lock_guard<std::mutex> lk2(ctx->mu);
-            p = plan_batch(ctx, reqs, n_reqs, false);
+            p = plan_batch(ctx, reqs, n_reqs, false, CODES_BUILD);
             prof_mode = ctx->prof_mode;
+            for (int32_t q = 0; q < n_reqs; ++q)
+                if (reqs[q].n_ind > 0) hold.add_locked(reqs[q].matrix);
         }
         if (p.items.empty()) return;  // every population is empty
         const bool count = (prof_mode & 2) != 0;
@@ -381,6 +394,7 @@ extern "C" ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, 
                 ++ctx->graph_captures;
             }
         }
+        fault_point_launch(ctx, "batch launch");
         std::lock_guard<std::mutex> lkg(g->mu);
         const int slot = g->next;
         g->next ^= 1;

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -25,7 +26,82 @@ thread_local std::string g_last_error;
 }  // namespace
 
 namespace ebic {
-void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+int log_level()
+{
+    static const int level = [] {
+        const char *v = std::getenv("EBIC_LOG");
+        return v && *v ? std::max(0, std::min(3, std::atoi(v))) : 0;
+    }();
+    return level;
+}
+
+void log_msg(int level, const std::string &msg)
+{
+    if (level > log_level()) return;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    std::fprintf(stderr, "[ebic] %s\n", msg.c_str());
+    std::fflush(stderr);
+}
+
+void set_last_error(const std::string &msg)
+{
+    g_last_error = msg;
+    if (!msg.empty()) log_msg(1, "error: " + msg);
+}
+
+FaultPlan parse_fault_plan(const char *spec)
+{
+    FaultPlan f;
+    if (!spec) return f;
+    std::string s(spec);
+    size_t at = 0;
+    while (at <= s.size()) {
+        const size_t end = std::min(s.find(',', at), s.size());
+        const std::string item = s.substr(at, end - at);
+        const size_t colon = item.find(':');
+        const std::string kind = item.substr(0, colon);
+        int64_t n = 0;
+        if (colon != std::string::npos) n = std::max<int64_t>(0, std::atoll(item.c_str() + colon + 1));
+        if (kind == "alloc") f.alloc_after = n;
+        else if (kind == "launch") f.launch_after = n;
+        at = end + 1;
+    }
+    return f;
+}
+
+void fault_point_launch(ebic_ctx *ctx, const char *what)
+{
+    bool fire = false;
+    {
+        std::lock_guard<std::mutex> lk(ctx->fault_mu);
+        if (ctx->fault.launch_after >= 0) {
+            if (ctx->launches_done == ctx->fault.launch_after) {
+                fire = true;
+                ctx->fault.launch_after = -1;
+            } else {
+                ++ctx->launches_done;
+            }
+        }
+    }
+    if (fire) fail(EBIC_EHIP, std::string(what) + ": injected launch failure (EBIC_FAULT)");
+}
+
+void matrix_ref_locked(ebic_ctx *ctx, int32_t id)
+{
+    auto it = ctx->matrices.find(id);
+    if (it == ctx->matrices.end()) fail(EBIC_ENOENT, "unknown matrix handle " + std::to_string(id));
+    ++it->second.refs;
+}
+
+void matrix_unref(ebic_ctx *ctx, int32_t id)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->matrices.find(id);
+    if (it != ctx->matrices.end() && it->second.refs > 0) --it->second.refs;
+}
+
 }  // namespace ebic
 
 // ---------------------------------------------------------------------------
@@ -36,6 +112,17 @@ namespace ebic {
 void *ctx_alloc(ebic_ctx *ctx, size_t bytes)
 {
     if (bytes == 0) bytes = 256;
+    {
+        std::lock_guard<std::mutex> lk(ctx->fault_mu);
+        if (ctx->fault.alloc_after >= 0) {
+            if (ctx->allocs_done == ctx->fault.alloc_after) {
+                ctx->fault.alloc_after = -1;
+                fail(EBIC_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                      " bytes: injected failure (EBIC_FAULT)");
+            }
+            ++ctx->allocs_done;
+        }
+    }
     void *p = nullptr;
     if (ctx->alloc) {
         p = ctx->alloc(bytes, ctx->alloc_user);
@@ -72,8 +159,49 @@ const Matrix &ctx_matrix(ebic_ctx *ctx, int32_t id)
     return it->second;
 }
 
+Matrix &ctx_matrix_mut(ebic_ctx *ctx, int32_t id)
+{
+    auto it = ctx->matrices.find(id);
+    if (it == ctx->matrices.end()) fail(EBIC_ENOENT, "unknown matrix handle " + std::to_string(id));
+    return it->second;
+}
+
+bool codes_buildable(const Matrix &m, bool include)
+{
+    return m.dev.cols <= kMaxCodeCols && (!include || m.Xfill != nullptr);
+}
+
+void build_fp16_codes(ebic_ctx *ctx, Matrix &m, bool include)
+{
+    if ((include ? m.Cfill : m.C) != nullptr) return;
+    if (!codes_buildable(m, include)) fail(EBIC_EINVAL, "no rank codes can be built for this matrix and mode");
+    DeviceGuard g(ctx->device);
+    const size_t cbytes = (size_t)m.dev.ld * m.dev.cols * sizeof(uint16_t);
+    uint16_t *C = static_cast<uint16_t *>(ctx_alloc(ctx, cbytes));
+    hipStream_t s = nullptr;
+    try {
+        hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+        hip_check(launch_codes(include ? m.Xfill : m.X, m.dev.rows, m.dev.ld, m.dev.cols, C, s), "codes kernel");
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        hip_check(hipStreamDestroy(s), "hipStreamDestroy");
+        s = nullptr;
+    } catch (...) {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        ctx_free(ctx, C);
+        throw;
+    }
+    if (include) m.Cfill = C, m.dev.Cfill = C;
+    else m.C = C, m.dev.C = C;
+    m.bytes += cbytes;
+    log_msg(2, std::string("built FP16 rank codes") + (include ? " of the fill copy" : "") + ": " +
+                   std::to_string(cbytes) + " bytes");
+}
+
 // Launch shape for one population on one matrix.
-LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint32_t flags)
+LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t flags, CodesMode codes)
 {
     LaunchCfg cfg;
     if (ctx->override_cfg.W > 0) cfg = ctx->override_cfg;
@@ -82,7 +210,11 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
     cfg.P = std::max(1, std::min(cfg.P, std::max(1, n)));
     auto lds = [&](const LaunchCfg &c) { return item_lds_bytes(c.L, m.dev.cols, c.staging, c.P); };
     auto fits = [&](const LaunchCfg &c) { return lds(c) <= lds_max; };
-    const bool have_codes = ((flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
+    const bool include = (flags & EBIC_NAN_INCLUDE) != 0;
+    // FP16 codes that are not resident count as available when they can be
+    // built on first use; they are built below only if the plan stages them.
+    const bool built_codes = (include ? m.dev.Cfill : m.dev.C) != nullptr;
+    const bool have_codes = built_codes || (codes != CODES_EXISTING && codes_buildable(m, include));
     const bool have_bytes = m.dev.B && ((flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
     const bool have_halves = m.dev.Hc && ((flags & EBIC_NAN_INCLUDE) || m.dev.h_exclude);
     // SWAR codes: bytes (up to 128 columns; one or two lane words per row,
@@ -148,6 +280,7 @@ LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint
             cfg.blocks = (int32_t)std::min<int64_t>(r, std::max<int64_t>(1, n_tiles));
         }
     }
+    if (cfg.staging == STAGE_CODES && !built_codes && codes == CODES_BUILD) build_fp16_codes(ctx, m, include);
     return cfg;
 }
 
@@ -234,6 +367,12 @@ hipError_t ctx_launch_eval(ebic_ctx *ctx, const ReqDesc &d, const LaunchCfg &cfg
         if (mode & 2) counter = ctx->d_step_counter;
     }
     IndHead *heads = static_cast<IndHead *>(stream_scratch(ctx, s, (size_t)d.n * sizeof(IndHead)));
+    fault_point_launch(ctx, "evaluation launch");
+    if (log_level() >= 3)
+        log_msg(3, "eval n=" + std::to_string(d.n) + " rows=" + std::to_string(d.rows) + " cols=" +
+                       std::to_string(d.cols) + " L=" + std::to_string(cfg.L) + " W=" + std::to_string(cfg.W) +
+                       " P=" + std::to_string(cfg.P) + " staging=" + std::to_string(cfg.staging) +
+                       " blocks=" + std::to_string(cfg.blocks));
     if (!(mode & 1)) return launch_eval(d, heads, cfg, counter, s);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
@@ -280,6 +419,7 @@ ebic_status ebic_create(int32_t hip_device, ebic_ctx **out)
         hip_check(hipGetDeviceProperties(&prop, hip_device), "hipGetDeviceProperties");
         auto *ctx = new ebic_ctx();
         ctx->device = hip_device;
+        ctx->fault = parse_fault_plan(std::getenv("EBIC_FAULT"));
         ctx->cu_count = prop.multiProcessorCount;
         ctx->lds_per_block = std::max<size_t>(prop.sharedMemPerBlock, 65536);
         ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
@@ -411,19 +551,6 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             }
             hip_check(launch_zero_pad(m.X, rows, m.dev.ld, cols, s), "zero-pad kernel");
             if (m.Xfill) hip_check(launch_zero_pad(m.Xfill, rows, m.dev.ld, cols, s), "zero-pad kernel");
-            // Rank codes for matrices narrow enough: half the bytes of a
-            // staged tile, so wide matrices fit twice the rows in LDS.
-            if (cols <= kMaxCodeCols) {
-                const size_t cbytes = (size_t)m.dev.ld * cols * sizeof(uint16_t);
-                m.C = static_cast<uint16_t *>(ctx_alloc(ctx, cbytes));
-                m.bytes += cbytes;
-                hip_check(launch_codes(m.X, rows, m.dev.ld, cols, m.C, s), "codes kernel");
-                if (m.Xfill) {
-                    m.Cfill = static_cast<uint16_t *>(ctx_alloc(ctx, cbytes));
-                    m.bytes += cbytes;
-                    hip_check(launch_codes(m.Xfill, rows, m.dev.ld, cols, m.Cfill, s), "codes kernel");
-                }
-            }
             // Byte rank codes for matrices of at most 128 columns: four rows
             // per 32-bit word. They encode the fill-substituted values, so
             // exclude mode may use them only if no cell is missing.
@@ -468,6 +595,18 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             m.dev.h_exclude = m.Hc && has_nan_h == 0;
             if (m.B) m.has_missing = has_nan != 0;
             if (m.Hc) m.has_missing = has_nan_h != 0;
+            // FP16 rank codes (half the bytes of a staged FP32 tile, missing
+            // cells kept as NaN) serve exclude mode where the SWAR codes
+            // cannot: on a matrix with missing cells. Other uses (a shape
+            // that stages them, include mode's codes of the fill copy) build
+            // them on first use.
+            if (cols <= kMaxCodeCols && m.has_missing == 1) {
+                const size_t cbytes = (size_t)m.dev.ld * cols * sizeof(uint16_t);
+                m.C = static_cast<uint16_t *>(ctx_alloc(ctx, cbytes));
+                m.bytes += cbytes;
+                hip_check(launch_codes(m.X, rows, m.dev.ld, cols, m.C, s), "codes kernel");
+                hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+            }
         } catch (...) {
             ctx_free(ctx, staging);
             ctx_free(ctx, m.X);
@@ -489,6 +628,9 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
         const int32_t id = ctx->next_matrix++;
         ctx->matrices[id] = m;
         *out_matrix = id;
+        log_msg(2, "uploaded matrix " + std::to_string(id) + ": " + std::to_string(rows) + " x " +
+                       std::to_string(cols) + ", " + std::to_string(m.bytes) + " device bytes, " +
+                       std::to_string(m.upload_ms) + " ms");
     });
 }
 
@@ -542,6 +684,9 @@ ebic_status ebic_release_matrix(ebic_ctx *ctx, int32_t matrix)
         DeviceGuard g(ctx->device);
         std::lock_guard<std::mutex> lk(ctx->mu);
         Matrix m = ctx_matrix(ctx, matrix);
+        if (m.refs > 0)
+            fail(EBIC_EBUSY, "matrix " + std::to_string(matrix) + " is in use (" + std::to_string(m.refs) +
+                                 " calls or serving requests hold it)");
         hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
         ctx_free(ctx, m.X);
         ctx_free(ctx, m.Xfill);
@@ -550,6 +695,7 @@ ebic_status ebic_release_matrix(ebic_ctx *ctx, int32_t matrix)
         ctx_free(ctx, m.B);
         ctx_free(ctx, m.Hc);
         ctx->matrices.erase(matrix);
+        log_msg(2, "released matrix " + std::to_string(matrix));
     });
 }
 
@@ -565,15 +711,17 @@ ebic_status ebic_eval_population(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
         if (flags & ~(EBIC_NAN_INCLUDE | EBIC_NEG_TRENDS)) fail(EBIC_EINVAL, "unknown eval flags");
         ReqDesc d;
         LaunchCfg cfg;
+        MatrixHold hold(ctx);  // until the kernels are enqueued
         {
             std::lock_guard<std::mutex> lk(ctx->mu);
-            const Matrix &m = ctx_matrix(ctx, matrix);
+            Matrix &m = ctx_matrix_mut(ctx, matrix);
             if (n_ind == 0) return;
             if (!d_offsets || !d_cols || !d_matched)
                 fail(EBIC_EINVAL, "d_offsets, d_cols and d_matched are required");
-            cfg = plan_eval(ctx, m, n_ind, -1, flags);
+            cfg = plan_eval(ctx, m, n_ind, -1, flags, CODES_BUILD);
             d = make_desc(m, n_ind, d_offsets, d_cols, flags, d_matched, d_negative, d_matched_mask,
                           d_negative_mask, cfg.staging);
+            hold.add_locked(matrix);
         }
         DeviceGuard g(ctx->device);
         hip_check(ctx_launch_eval(ctx, d, cfg, reinterpret_cast<hipStream_t>(hip_stream)),
@@ -596,17 +744,20 @@ ebic_status ebic_eval_population_noalloc(ebic_ctx *ctx, int32_t matrix, int32_t 
         if (flags & ~(EBIC_NAN_INCLUDE | EBIC_NEG_TRENDS)) fail(EBIC_EINVAL, "unknown eval flags");
         ReqDesc d;
         LaunchCfg cfg;
+        MatrixHold hold(ctx);  // until the kernels are enqueued
         {
             std::lock_guard<std::mutex> lk(ctx->mu);
-            const Matrix &m = ctx_matrix(ctx, matrix);
+            Matrix &m = ctx_matrix_mut(ctx, matrix);
             if (n_ind == 0) return;
             if (!d_offsets || !d_cols || !d_matched)
                 fail(EBIC_EINVAL, "d_offsets, d_cols and d_matched are required");
-            cfg = plan_eval(ctx, m, n_ind, -1, flags);
+            cfg = plan_eval(ctx, m, n_ind, -1, flags, CODES_EXISTING);  // (allocates nothing)
             d = make_desc(m, n_ind, d_offsets, d_cols, flags, d_matched, d_negative, d_matched_mask,
                           d_negative_mask, cfg.staging);
+            hold.add_locked(matrix);
         }
         DeviceGuard g(ctx->device);
+        fault_point_launch(ctx, "evaluation launch");
         IndHead *heads = noalloc_scratch(ctx->device);
         if (!heads) fail(EBIC_EHIP, "the no-allocation header buffer is not set up on this device");
         hip_check(launch_eval(d, heads, cfg, nullptr, reinterpret_cast<hipStream_t>(hip_stream)),
@@ -623,8 +774,8 @@ ebic_status ebic_plan_shape(ebic_ctx *ctx, int32_t matrix, int32_t n_ind, int64_
         if (n_ind <= 0) fail(EBIC_EINVAL, "n_ind must be >= 1");
         DeviceGuard g(ctx->device);
         std::lock_guard<std::mutex> lk(ctx->mu);
-        const Matrix &m = ctx_matrix(ctx, matrix);
-        const LaunchCfg c = plan_eval(ctx, m, n_ind, nnz, EBIC_NEG_TRENDS);
+        Matrix &m = ctx_matrix_mut(ctx, matrix);
+        const LaunchCfg c = plan_eval(ctx, m, n_ind, nnz, EBIC_NEG_TRENDS, CODES_REPORT);
         if (tiles_per_wave) *tiles_per_wave = c.L;
         if (waves_per_block) *waves_per_block = c.W;
         if (individuals_per_group) *individuals_per_group = c.P;

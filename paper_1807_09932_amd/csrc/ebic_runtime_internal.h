@@ -29,6 +29,10 @@ struct Matrix {
     float sentinel = 0.f;
     int32_t has_missing = -1;  // from the SWAR code build (-1: not built)
     double upload_ms = 0;
+    // Holders that keep the matrix from being released (under ctx->mu):
+    // calls between planning and enqueuing, and serving requests from
+    // submission to completion.
+    int32_t refs = 0;
 };
 
 // Shape class of a tuning entry: log2 buckets of rows, columns, population
@@ -47,6 +51,12 @@ struct TuneKey {
 };
 
 struct BatchState;  // ebic_batch.cpp
+
+// Host-side fault injection plan (see parse_fault_plan).
+struct FaultPlan {
+    int64_t alloc_after = -1;   // -1: off
+    int64_t launch_after = -1;
+};
 
 // Device scratch owned by the context, one per stream: work on one stream
 // runs in order, so consecutive calls on it can reuse the same buffer.
@@ -80,6 +90,10 @@ struct ebic_ctx {
     int32_t prof_mode = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
     unsigned long long *d_step_counter = nullptr;
+    // Fault injection (tests of the error paths; see FaultPlan).
+    std::mutex fault_mu;
+    ebic::FaultPlan fault;
+    int64_t allocs_done = 0, launches_done = 0;
 };
 
 namespace ebic {
@@ -140,10 +154,73 @@ struct DeviceGuard {
     DeviceGuard &operator=(const DeviceGuard &) = delete;
 };
 
+// References that keep matrices resident while a call or a serving request
+// uses them. matrix_ref_locked takes one (the caller holds ctx->mu; fails
+// with EBIC_ENOENT for an unknown handle); matrix_unref drops one (takes
+// ctx->mu itself).
+void matrix_ref_locked(ebic_ctx *ctx, int32_t id);
+void matrix_unref(ebic_ctx *ctx, int32_t id);
+
+// The references of one call, dropped when it goes out of scope (after the
+// call's work has been enqueued, or on an error).
+class MatrixHold {
+  public:
+    explicit MatrixHold(ebic_ctx *ctx) : ctx_(ctx) {}
+    ~MatrixHold()
+    {
+        for (int32_t id : ids_) matrix_unref(ctx_, id);
+    }
+    void add_locked(int32_t id)
+    {
+        matrix_ref_locked(ctx_, id);
+        ids_.push_back(id);
+    }
+    MatrixHold(const MatrixHold &) = delete;
+    MatrixHold &operator=(const MatrixHold &) = delete;
+
+  private:
+    ebic_ctx *ctx_;
+    std::vector<int32_t> ids_;
+};
+
+// Host-side fault injection for tests of the error paths (environment
+// variable EBIC_FAULT, read at ebic_create): "alloc" or "alloc:N" makes
+// the device allocation after N successful ones fail with EBIC_ENOMEM,
+// "launch" or "launch:N" makes the kernel launch after N successful ones
+// fail with EBIC_EHIP, both before anything is enqueued; a comma separates
+// both. Each fault fires once.
+FaultPlan parse_fault_plan(const char *spec);
+// Throws the injected launch failure when it is due (the launch wrappers
+// call it before enqueuing).
+void fault_point_launch(ebic_ctx *ctx, const char *what);
+
+// Diagnostics on stderr at the level of EBIC_LOG (read at ebic_create):
+// 0 off (default), 1 errors returned by the ABI, 2 also uploads, releases
+// and serving-engine events, 3 also every launch plan.
+int log_level();
+void log_msg(int level, const std::string &msg);
+
 void *ctx_alloc(ebic_ctx *ctx, size_t bytes);
 void ctx_free(ebic_ctx *ctx, void *p);
 const Matrix &ctx_matrix(ebic_ctx *ctx, int32_t id);
-LaunchCfg plan_eval(ebic_ctx *ctx, const Matrix &m, int32_t n, int64_t nnz, uint32_t flags);
+Matrix &ctx_matrix_mut(ebic_ctx *ctx, int32_t id);
+
+// FP16 rank codes are built on first use (a forced or tuned shape that
+// stages them), except those exclude mode needs on a matrix with missing
+// cells, which the upload builds. What a planner may do about absent codes:
+enum CodesMode {
+    CODES_EXISTING = 0,  // plan with what is resident (no allocation)
+    CODES_BUILD = 1,     // build the codes a plan stages, then plan with them
+    CODES_REPORT = 2,    // plan as if buildable codes existed (build nothing)
+};
+// Whether the FP16 codes of a mode can exist (include mode codes the fill
+// copy, which must be kept).
+bool codes_buildable(const Matrix &m, bool include);
+// Build them now (under ctx->mu): allocation, the codes kernel on a private
+// stream, and a wait for it.
+void build_fp16_codes(ebic_ctx *ctx, Matrix &m, bool include);
+LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t flags,
+                    CodesMode codes = CODES_BUILD);
 // The kernels' view of one request; `staging` decides whether include mode
 // reads the fill copy or substitutes on the fly.
 ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int32_t *cols,

@@ -68,6 +68,12 @@ Sizes request_sizes(int64_t rows, int32_t n, int64_t ncols, bool negative, bool 
 }
 
 struct Req {
+    // The matrix reference taken at submission (dropped with the request).
+    ebic_ctx *held_ctx = nullptr;
+    ~Req()
+    {
+        if (held_ctx) matrix_unref(held_ctx, matrix);
+    }
     uint64_t tag = 0;
     int32_t matrix = 0, n = 0;
     uint32_t flags = 0;
@@ -158,10 +164,11 @@ struct ebic_server {
     std::deque<std::unique_ptr<Req>> pending;
     std::deque<std::pair<uint64_t, ebic_status>> done;
     bool stop = false;
+    bool paused = false;      // launch no new batch
     bool sched_done = false;  // the scheduler has drained every request and exited
     std::thread scheduler;
     // statistics
-    int64_t submitted = 0, completed = 0, batches = 0, batched_requests = 0;
+    int64_t submitted = 0, completed = 0, cancelled = 0, batches = 0, batched_requests = 0;
     int64_t reserved = 0, high_water = 0, checks = 0, staging_grows = 0;
     std::vector<double> latencies_ms;
     std::vector<double> queue_ms;  // submission to the batch's enqueue on its slot
@@ -172,10 +179,14 @@ namespace {
 
 void complete_locked(ebic_server *srv, std::unique_ptr<Req> r, ebic_status st, double t_done)
 {
-    srv->latencies_ms.push_back((t_done - r->t_submit) * 1e3);
-    srv->queue_ms.push_back(((r->t_launched > 0 ? r->t_launched : t_done) - r->t_submit) * 1e3);
-    ++srv->completed;
-    srv->checks += r->checks;
+    if (st == EBIC_ECANCELED) {
+        ++srv->cancelled;
+    } else {
+        srv->latencies_ms.push_back((t_done - r->t_submit) * 1e3);
+        srv->queue_ms.push_back(((r->t_launched > 0 ? r->t_launched : t_done) - r->t_submit) * 1e3);
+        ++srv->completed;
+        srv->checks += r->checks;
+    }
     srv->done.emplace_back(r->tag, st);
 }
 
@@ -267,7 +278,7 @@ void scheduler_main(ebic_server *srv)
             srv->cv_slot.notify_all();
             break;
         }
-        if (!idle || srv->pending.empty()) {
+        if (!idle || srv->pending.empty() || (srv->paused && !srv->stop)) {
             srv->cv_sched.wait(lk);
             continue;
         }
@@ -472,6 +483,8 @@ ebic_status ebic_server_submit(ebic_server *srv, int32_t matrix, int32_t n_ind, 
         {
             std::lock_guard<std::mutex> lk(srv->ctx->mu);
             r->rows = ctx_matrix(srv->ctx, matrix).dev.rows;
+            matrix_ref_locked(srv->ctx, matrix);
+            r->held_ctx = srv->ctx;
         }
         // The column array's length: the largest offset (decreasing offsets
         // mark invalid individuals, which the kernels report as -1).
@@ -530,6 +543,50 @@ ebic_status ebic_server_poll(ebic_server *srv, uint64_t *tags, ebic_status *stat
     });
 }
 
+ebic_status ebic_server_cancel(ebic_server *srv, uint64_t tag)
+{
+    return guarded([&] {
+        if (!srv) fail(EBIC_EINVAL, "server is NULL");
+        std::unique_ptr<Req> r;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            for (auto it = srv->pending.begin(); it != srv->pending.end(); ++it) {
+                if ((*it)->tag == tag) {
+                    r = std::move(*it);
+                    srv->pending.erase(it);
+                    break;
+                }
+            }
+            if (!r) {
+                for (auto &sl : srv->slots)
+                    for (auto &q : sl->batch)
+                        if (q && q->tag == tag) fail(EBIC_EBUSY, "request is already on the device");
+                fail(EBIC_ENOENT, "no queued request has tag " + std::to_string(tag));
+            }
+            // (the matrix reference is dropped after the server lock, with r)
+            const uint64_t t = r->tag;
+            const double t_submit = r->t_submit;
+            auto stub = std::make_unique<Req>();
+            stub->tag = t;
+            stub->t_submit = t_submit;
+            complete_locked(srv, std::move(stub), EBIC_ECANCELED, now_s());
+            srv->cv_done.notify_all();
+            srv->cv_sched.notify_all();
+        }
+        log_msg(2, "cancelled serving request " + std::to_string(tag));
+    });
+}
+
+ebic_status ebic_server_set_paused(ebic_server *srv, int32_t paused)
+{
+    return guarded([&] {
+        if (!srv) fail(EBIC_EINVAL, "server is NULL");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->paused = paused != 0;
+        srv->cv_sched.notify_all();
+    });
+}
+
 ebic_status ebic_server_get_stats(ebic_server *srv, ebic_server_stats *out, int32_t reset)
 {
     return guarded([&] {
@@ -546,6 +603,7 @@ ebic_status ebic_server_get_stats(ebic_server *srv, ebic_server_stats *out, int3
         s.nominal_checks = srv->checks;
         s.mean_batch = srv->batches ? (double)srv->batched_requests / (double)srv->batches : 0.0;
         s.staging_grows = srv->staging_grows;
+        s.cancelled = srv->cancelled;
         {
             std::lock_guard<std::mutex> lk2(srv->ctx->mu);
             s.graph_captures = srv->ctx->graph_captures;
@@ -572,7 +630,9 @@ ebic_status ebic_server_get_stats(ebic_server *srv, ebic_server_stats *out, int3
         *out = s;
         if (reset) {
             srv->submitted -= srv->completed;
+            srv->submitted -= srv->cancelled;
             srv->completed = 0;
+            srv->cancelled = 0;
             srv->batches = 0;
             srv->batched_requests = 0;
             srv->checks = 0;

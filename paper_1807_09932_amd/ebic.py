@@ -28,6 +28,7 @@ EBIC_EHIP = -3
 EBIC_ENOENT = -4
 EBIC_EBUSY = -5
 EBIC_EBUDGET = -6
+EBIC_ECANCELED = -7
 
 EBIC_NAN_EXCLUDE = 0
 EBIC_NAN_INCLUDE = 1
@@ -48,7 +49,7 @@ EXPORTED = ["ebic_create", "ebic_destroy", "ebic_set_allocator", "ebic_last_erro
             "ebic_set_launch_shape", "ebic_set_profiling", "ebic_read_profile",
             "ebic_plan_shape", "ebic_plan_batch_shape", "ebic_server_request_bytes", "ebic_server_create",
             "ebic_server_destroy", "ebic_server_submit", "ebic_server_poll",
-            "ebic_server_get_stats", "ebic_ea_create", "ebic_ea_destroy", "ebic_ea_population",
+            "ebic_server_get_stats", "ebic_server_cancel", "ebic_server_set_paused", "ebic_ea_create", "ebic_ea_destroy", "ebic_ea_population",
             "ebic_ea_step", "ebic_read_delimited", "ebic_free_text_matrix",
             "ebic_write_biclusters"]
 
@@ -75,7 +76,7 @@ class ebic_server_stats(ctypes.Structure):
                 ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
                 ("mean_batch", ctypes.c_double), ("latency_max_ms", ctypes.c_double),
                 ("graph_captures", ctypes.c_int64), ("staging_grows", ctypes.c_int64),
-                ("queue_p99_ms", ctypes.c_double)]
+                ("queue_p99_ms", ctypes.c_double), ("cancelled", ctypes.c_int64)]
 
 
 class ebic_matrix_stats(ctypes.Structure):
@@ -146,6 +147,8 @@ def load_library(path: str = LIB_PATH):
         "ebic_server_submit": (I32, [P, I32, I32, P, P, U32, P, P, P, P, ctypes.c_uint64]),
         "ebic_server_poll": (I32, [P, P, P, I32, I32, ctypes.POINTER(I32)]),
         "ebic_server_get_stats": (I32, [P, ctypes.POINTER(ebic_server_stats), I32]),
+        "ebic_server_cancel": (I32, [P, ctypes.c_uint64]),
+        "ebic_server_set_paused": (I32, [P, I32]),
         "ebic_ea_create": (I32, [ctypes.POINTER(ebic_ea_params), ctypes.POINTER(P)]),
         "ebic_ea_destroy": (I32, [P]),
         "ebic_ea_population": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I32),
@@ -329,6 +332,14 @@ def ebic_server_get_stats(srv: int, reset: bool = False) -> ebic_server_stats:
     st = ebic_server_stats()
     _check(load_library().ebic_server_get_stats(srv, ctypes.byref(st), int(reset)))
     return st
+
+
+def ebic_server_cancel(srv: int, tag: int) -> None:
+    _check(load_library().ebic_server_cancel(srv, tag))
+
+
+def ebic_server_set_paused(srv: int, paused: bool) -> None:
+    _check(load_library().ebic_server_set_paused(srv, 1 if paused else 0))
 
 
 def ebic_ea_create(params: "ebic_ea_params") -> int:

@@ -46,6 +46,7 @@ class _Pending:
     future: concurrent.futures.Future
     keep: tuple                  # the arrays the engine reads or writes
     t_submit: float
+    tag: int = 0
 
 
 class Server:
@@ -99,7 +100,8 @@ class Server:
         with self._mu:
             if self._closing:
                 raise RuntimeError("server is closed")
-            self._pending[tag] = _Pending(fut, (offsets, cols, m, g, mm, nm), time.perf_counter())
+            self._pending[tag] = _Pending(fut, (offsets, cols, m, g, mm, nm), time.perf_counter(), tag)
+        fut.ebic_tag = tag  # (for cancel)
         try:
             ebic.ebic_server_submit(self.handle, matrix, n, offsets.ctypes.data,
                                     cols.ctypes.data if cols.size else None, flags, m.ctypes.data,
@@ -109,6 +111,22 @@ class Server:
                 self._pending.pop(tag, None)
             raise
         return fut
+
+    def cancel(self, fut: concurrent.futures.Future) -> bool:
+        """Cancel a request that has not been launched yet. True if it was
+        (its future ends cancelled), False if it is already on the device
+        or done (it then completes normally)."""
+        try:
+            ebic.ebic_server_cancel(self.handle, fut.ebic_tag)
+            return True
+        except ebic.EbicError as e:
+            if e.status in (ebic.EBIC_EBUSY, ebic.EBIC_ENOENT):
+                return False
+            raise
+
+    def pause(self, paused: bool = True) -> None:
+        """Stop launching new batches (requests keep queueing), or resume."""
+        ebic.ebic_server_set_paused(self.handle, paused)
 
     def _poll_loop(self):
         tags = np.zeros(256, np.uint64)
@@ -120,7 +138,9 @@ class Server:
                 with self._mu:
                     p = self._pending.pop(int(tags[i]))
                 _, _, m, g, mm, nm = p.keep
-                if sts[i] != ebic.EBIC_OK:
+                if sts[i] == ebic.EBIC_ECANCELED:
+                    p.future.cancel()
+                elif sts[i] != ebic.EBIC_OK:
                     p.future.set_exception(ebic.EbicError(int(sts[i]), "batch launch failed"))
                 else:
                     p.future.set_result(Result(m, g, mm, nm, now - p.t_submit))
@@ -154,7 +174,7 @@ class Server:
                 "mean_batch": st.mean_batch,
                 "admitted_bytes_high_water": st.high_water_bytes,
                 "reserved_bytes": st.reserved_bytes, "budget_bytes": st.budget_bytes,
-                "checks": st.nominal_checks}
+                "checks": st.nominal_checks, "cancelled": st.cancelled}
 
     def stats(self, reset: bool = False) -> Dict[str, float]:
         """Engine counters (latency from submission to completion in the
