@@ -102,17 +102,101 @@ def cpu_baseline(w, offs, cols, threads, repeats=3):
     return {"value": checks / dt, "unit": "checks/s", "cores": threads, "kind": "oracle",
             "sample": f"the whole workload: {offs.size - 1} individuals x {rows} rows "
                       f"({checks:.3e} nominal checks) in {dt:.2f} s (median of {repeats})",
-            "cpu": _cpu_model()}
+            **host_cpu_info()}
 
 
 def _cpu_model():
+    """The processor's full model string (/proc/cpuinfo, else lscpu)."""
+    names = []
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+                names.append(line.split(":", 1)[1].strip())
     except OSError:
         pass
-    return "unknown"
+    name = max(names, key=len) if names else ""
+    if len(name) < 12:  # a bare vendor name: ask lscpu
+        try:
+            import subprocess
+            out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+            for line in out.splitlines():
+                if line.strip().startswith("Model name"):
+                    name = max(name, line.split(":", 1)[1].strip(), key=len)
+        except (OSError, subprocess.SubprocessError):
+            pass
+    return name or "unknown"
+
+
+def _cgroup_cpus():
+    """CPUs the cgroup quota grants this process (cpu.max), or None."""
+    try:
+        quota, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if quota != "max":
+            return float(quota) / float(period)
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def host_cpu_info():
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    return {"cpu": _cpu_model(), "nproc": affinity, "os_cpu_count": os.cpu_count(),
+            "cgroup_cpus": _cgroup_cpus(), "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def default_cpu_threads():
+    """Threads for the oracle baseline: every CPU this process may use (its
+    affinity mask), bounded by a cgroup CPU quota when one is set (on a
+    shared GPU host the quota is the process's share of the cores)."""
+    info = host_cpu_info()
+    n = info["nproc"]
+    if info["cgroup_cpus"]:
+        n = min(n, max(1, int(info["cgroup_cpus"])))
+    return max(1, n)
+
+
+def upload_report(ctx, mat):
+    """Resident bytes and upload cost of one matrix (ebic_matrix_get_stats)."""
+    st = ctx.stats(mat)
+    from paper_1807_09932_amd import ebic
+    names = [n for n, b in (("fp32_fill_copy", ebic.SET_FILL_COPY), ("fp16", ebic.SET_FP16),
+                            ("fp16_fill", ebic.SET_FP16_FILL), ("u8", ebic.SET_U8),
+                            ("u16", ebic.SET_U16)) if st["code_sets"] & b]
+    return {"upload_ms": st["upload_ms"], "resident_bytes": st["value_bytes"] + st["code_bytes"],
+            "value_bytes": st["value_bytes"], "code_bytes": st["code_bytes"], "code_sets": names,
+            "swar_tie_chunks": st["swar_tie_chunks"], "swar_chunks": st["swar_chunks"],
+            "upload": "host-to-device copy of the row-major FP32 matrix, layout to column-major, "
+                      "rank-code build; host wall clock of ebic_upload_matrix"}
+
+
+def roofline_views(executed_steps, k_ms, staging, matrix_bytes, n_ind):
+    """The path's two other roofline readings: the HBM roofline of the
+    method's minimum traffic (the matrix once, the counts once), and the
+    compare-issue rate of the FP32 formulation (two 64-lane compares per
+    64-row wave step) against the chip's 32-bit lane rate."""
+    t = k_ms * 1e-3
+    min_bytes = matrix_bytes + 8 * n_ind
+    views = {
+        "hbm_min_bytes": {
+            "bound": "hbm", "achieved": min_bytes / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": min_bytes / t / 1e9 / HBM_PEAK_GBS, "bytes": min_bytes,
+            "note": "the method's minimum traffic (the FP32 matrix read once, two int32 counts "
+                    "per individual written) over the kernel time; the kernel is bound by "
+                    "instruction issue, not by HBM, so this fraction stays small"},
+        "fp32_compare_issue": {
+            "bound": "alu", "achieved": executed_steps * 2 * 64 / t / 1e12, "peak": CMP_PEAK_TOPS,
+            "unit": "T lane-compares/s", "frac": executed_steps * 2 * 64 / t / 1e12 / CMP_PEAK_TOPS,
+            "note": "executed 64-row column steps x 2 compares x 64 lanes, as if each step were "
+                    "two FP32 compares; above 1 for rank codes, whose one 32-bit lane operation "
+                    "compares four (u8) or two (u16) rows"},
+    }
+    if staging not in (STAGE_BYTES, STAGE_HALVES):
+        views["fp32_compare_issue"]["note"] = ("executed 64-row column steps x 2 compares x 64 lanes "
+                                               "over the kernel time")
+    return views
 
 
 def _timed(fn, reps, stream):
@@ -170,7 +254,7 @@ def bench_batched(ctx, args):
     for q in (0, len(pops) - 1):
         o, c = packed[q]
         om, on, _, _ = oracle.eval_population(w.X, o, c, negative=True,
-                                              threads=max(1, min(16, os.cpu_count() or 1)))
+                                              threads=default_cpu_threads())
         if not (np.array_equal(outs_b[q][0].cpu().numpy(), om) and
                 np.array_equal(outs_b[q][1].cpu().numpy(), on)):
             print("bench.py: batched counts differ from the oracle", file=sys.stderr)
@@ -195,6 +279,7 @@ def bench_batched(ctx, args):
     ebic.ebic_set_profiling(ctx.handle, 0)
     g_ms = l_ms / max(1, n_l)
     bL, bW, bP, b_stg, b_grid = ebic.ebic_plan_batch_shape(ctx.handle, reqs)
+    upload = upload_report(ctx, mat)
     ctx.release(mat)
     return {
         "workload": "64 populations (%d individuals, lengths 2 + min(38, Exp(mean 5)), "
@@ -211,7 +296,63 @@ def bench_batched(ctx, args):
         "roofline": alu_roofline(b_steps, g_ms, b_stg[0] if len(set(b_stg)) == 1 else None),
         "timing": "median of %d synchronised calls; batched = one ebic_eval_batch (descriptor "
                   "copy + graph replay), plain = 64 ebic_eval_population calls" % reps,
+        "upload": upload,
     }
+
+
+def bench_fp32(ctx, args, w, offs, cols):
+    """The FP32-tile kernel on the same workload: every row's values staged
+    into LDS as FP32 and compared in FP32 (no rank codes), in the best of a
+    few launch shapes; its compare instructions against the VALU lane rate."""
+    import torch
+    from paper_1807_09932_amd import ebic, gen
+    rows = w.X.shape[0]
+    n = offs.size - 1
+    mat = ctx.upload(w.X)
+    p = ctx.population(offsets=offs, cols=cols)
+    out = ctx.outputs(mat, n)
+    stream = torch.cuda.current_stream()
+    best = None
+    for shape in ((4, 16, 200), (4, 16, 400), (2, 16, 400), (4, 8, 200), (2, 16, 800)):
+        ctx.set_launch_shape(*shape, ebic.STAGE_LDS, 0)
+        if ebic.ebic_plan_shape(ctx.handle, mat, n)[3] != ebic.STAGE_LDS:
+            continue
+        ms = _timed(lambda: ctx.eval(mat, p, out=out), 7, stream)
+        if best is None or ms < best[1]:
+            best = (shape, ms)
+    ctx.set_launch_shape(*best[0], ebic.STAGE_LDS, 0)
+    L, W, P, stg, blocks = ebic.ebic_plan_shape(ctx.handle, mat, n)
+    ctx.eval(mat, p, out=out)
+    torch.cuda.synchronize()
+    import oracle
+    sample = np.arange(0, n, max(1, n // 16))
+    so, sc = gen.csr([cols[offs[i]:offs[i + 1]] for i in sample])
+    om, on, _, _ = oracle.eval_population(w.X, so, sc, negative=True, threads=default_cpu_threads())
+    if not (np.array_equal(out[0].cpu().numpy()[sample], om) and
+            np.array_equal(out[1].cpu().numpy()[sample], on)):
+        print("bench.py: FP32-tile counts differ from the oracle", file=sys.stderr)
+        sys.exit(3)
+    ebic.ebic_set_profiling(ctx.handle, 2)
+    ctx.eval(mat, p, out=out)
+    _, _, steps = ebic.ebic_read_profile(ctx.handle)
+    ebic.ebic_set_profiling(ctx.handle, 1)
+    ebic.ebic_read_profile(ctx.handle)
+    for _ in range(args.steps):
+        ctx.eval(mat, p, out=out)
+    n_l, ms, _ = ebic.ebic_read_profile(ctx.handle)
+    ebic.ebic_set_profiling(ctx.handle, 0)
+    ctx.set_launch_shape()
+    k_ms = ms / max(1, n_l)
+    checks = gen.nominal_checks(rows, offs)
+    ctx.release(mat)
+    return {"workload": "the same %d x %d matrix and %d individuals" % (rows, w.X.shape[1], n),
+            "dtype": "f32",
+            "launch_shape": f"best of 5 FP32-tile shapes: L={L} W={W} P={P} staging={stg} blocks={blocks}",
+            "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
+            "roofline": alu_roofline(steps, k_ms, stg),
+            "ops": "FP32 compares executed per launch: %d wave-wide compare instructions x 64 rows "
+                   "(first pair: 3 per 64-row tile, then 1 per column step of each row's oriented "
+                   "chain), counted by the measurement variant of the kernel" % steps}
 
 
 def bench_ea(ctx, args, w=None):
@@ -285,7 +426,7 @@ def bench_paper_shape(ctx, args):
     sample = np.arange(0, p.n, max(1, p.n // 8))
     so, sc = gen.csr([cols[offs[i]:offs[i + 1]] for i in sample])
     om, on, _, _ = oracle.eval_population(w.X, so, sc, negative=True,
-                                          threads=max(1, min(16, os.cpu_count() or 1)))
+                                          threads=default_cpu_threads())
     if not (np.array_equal(out[0].cpu().numpy()[sample], om) and
             np.array_equal(out[1].cpu().numpy()[sample], on)):
         print("bench.py: GPU counts differ from the oracle (paper shape)", file=sys.stderr)
@@ -301,9 +442,12 @@ def bench_paper_shape(ctx, args):
     ebic.ebic_set_profiling(ctx.handle, 0)
     k_ms = ms / max(1, n_l)
     checks = gen.nominal_checks(rows, offs)
+    upload = upload_report(ctx, mat)
     ctx.release(mat)
     return {"workload": "%d x %d FP32 Beta(0.5,0.5), 10 planted trends, %d individuals of "
                         "2-30 columns" % (rows, ncols, p.n),
+            "upload": upload,
+            "roofline_views": roofline_views(steps, k_ms, stg, w.X.nbytes, p.n),
             "launch_shape": f"{how}: L={L} W={W} P={P} staging={stg} blocks={blocks}",
             "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
             "roofline": alu_roofline(steps, k_ms, stg),
@@ -333,7 +477,7 @@ def bench_shard(ctx, args, w, offs, cols):
     sample = np.arange(0, p.n, max(1, p.n // 8))
     so, sc = gen.csr([cols[offs[i]:offs[i + 1]] for i in sample])
     om, on, _, _ = oracle.eval_population(X, so, sc, negative=True,
-                                          threads=max(1, min(16, os.cpu_count() or 1)))
+                                          threads=default_cpu_threads())
     if not (np.array_equal(out[0].cpu().numpy()[sample], om) and
             np.array_equal(out[1].cpu().numpy()[sample], on)):
         print("bench.py: GPU counts differ from the oracle (row slice)", file=sys.stderr)
@@ -521,8 +665,9 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times), to scale "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
-    ap.add_argument("--extras", type=str, default="batch,serve,ea,paper,shard",
-                    help="comma list of extra measurements: 'batch' (64 populations in one "
+    ap.add_argument("--extras", type=str, default="fp32,batch,serve,ea,paper,shard",
+                    help="comma list of extra measurements: 'fp32' (the FP32-tile kernel on "
+                         "the same workload), 'batch' (64 populations in one "
                          "batched launch vs 64 plain launches), 'serve' (Poisson requests from "
                          "16 runs over 4 resident matrices), 'ea' (the stand-in evolutionary "
                          "loop around the evaluation), 'paper' (436,444 x 310), 'shard' (one of 8 "
@@ -564,6 +709,7 @@ def main():
 
     ctx = ebic.Context(0)
     mat = ctx.upload(w.X)
+    upload = upload_report(ctx, mat)
     p = ctx.population(offsets=offs, cols=cols)
     out = ctx.outputs(mat, n, masks=False)
     stream = torch.cuda.current_stream()
@@ -595,7 +741,7 @@ def main():
     g_gpu = out[1].cpu().numpy()
     so, sc = gen.csr([cols[offs[i]:offs[i + 1]] for i in sample])
     om, on, _, _ = oracle.eval_population(w.X, so, sc, negative=True,
-                                          threads=max(1, min(16, os.cpu_count() or 1)))
+                                          threads=default_cpu_threads())
     if not (np.array_equal(m_gpu[sample], om) and np.array_equal(g_gpu[sample], on)):
         print("bench.py: GPU counts differ from the oracle", file=sys.stderr)
         sys.exit(3)
@@ -737,6 +883,8 @@ def main():
                      "oriented chain; early exit per group of tiles), counted by the measurement "
                      "variant of the kernel" % executed_steps)),
         },
+        "roofline_views": roofline_views(executed_steps, k_ms, stg, w.X.nbytes, n),
+        "upload": upload,
         "hbm_view": {
             "effective_gbs": 4.0 * checks / (k_ms * 1e-3) / 1e9,
             "effective_frac_of_peak": 4.0 * checks / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -762,6 +910,8 @@ def main():
     }
     ctx.release(mat)
     extras = {x for x in args.extras.split(",") if x}
+    if "fp32" in extras:
+        result["fp32_path"] = bench_fp32(ctx, args, w, offs, cols)
     if "batch" in extras:
         result["batched"] = bench_batched(ctx, args)
     if "serve" in extras:
@@ -775,7 +925,7 @@ def main():
     ctx.close()
 
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
+        threads = args.cpu_threads or default_cpu_threads()
         log(f"timing the CPU oracle with {threads} threads")
         result["cpu_baseline"] = cpu_baseline(w, offs, cols, threads)
         if threads > 1:

@@ -14,6 +14,8 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "../../include/ebic.h"
 #include "ebic_internal.h"
@@ -338,6 +340,59 @@ ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int3
     return d;
 }
 
+void upload_pinned(ebic_ctx *ctx, size_t bytes)
+{
+    // (called under ctx->mu)
+    if (ctx->up_pin_bytes < bytes) {
+        for (int b = 0; b < 2; ++b) {
+            if (ctx->up_done[b]) hip_check(hipEventSynchronize(ctx->up_done[b]), "hipEventSynchronize");
+            if (ctx->up_pin[b]) (void)hipHostFree(ctx->up_pin[b]);
+            ctx->up_pin[b] = nullptr;
+        }
+        ctx->up_pin_bytes = 0;
+        for (int b = 0; b < 2; ++b)
+            hip_check(hipHostMalloc(&ctx->up_pin[b], bytes, hipHostMallocDefault), "hipHostMalloc");
+        ctx->up_pin_bytes = bytes;
+    }
+    for (int b = 0; b < 2; ++b)
+        if (!ctx->up_done[b])
+            hip_check(hipEventCreateWithFlags(&ctx->up_done[b], hipEventDisableTiming), "hipEventCreate");
+}
+
+void pack_rows(const float *src, int64_t ld_src, bool col_major, int64_t r0, int64_t nr, int32_t cols, float *dst)
+{
+    // Row-major: rows r0 .. r0+nr of cols floats each -> dst[nr][cols].
+    // Column-major: column c's entries r0 .. r0+nr -> dst[c][nr].
+    const int64_t units = col_major ? cols : nr;
+    const size_t unit_bytes = (size_t)(col_major ? nr : cols) * sizeof(float);
+    const bool contiguous = col_major ? (ld_src == nr || cols == 1) : (ld_src == cols || nr == 1);
+    const size_t total = (size_t)units * unit_bytes;
+    unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    if (total < (4u << 20)) nt = 1;
+    auto work = [&](unsigned t) {
+        if (contiguous) {
+            const char *from = reinterpret_cast<const char *>(col_major ? src + r0 : src + r0 * ld_src);
+            const size_t lo = total * t / nt, hi = total * (t + 1) / nt;
+            std::memcpy(reinterpret_cast<char *>(dst) + lo, from + lo, hi - lo);
+            return;
+        }
+        const int64_t lo = units * t / nt, hi = units * (t + 1) / nt;
+        for (int64_t u = lo; u < hi; ++u) {
+            const float *from = col_major ? src + u * ld_src + r0 : src + (r0 + u) * ld_src;
+            std::memcpy(reinterpret_cast<char *>(dst) + (size_t)u * unit_bytes, from, unit_bytes);
+        }
+    };
+    if (nt == 1) {
+        work(0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &x : th) x.join();
+}
+
 void *stream_scratch(ebic_ctx *ctx, hipStream_t s, size_t bytes)
 {
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -457,6 +512,12 @@ ebic_status ebic_destroy(ebic_ctx *ctx)
             ctx->d_step_counter = nullptr;
             for (auto &kv : ctx->scratch) ctx_free(ctx, kv.second.ptr);
             ctx->scratch.clear();
+            for (int b = 0; b < 2; ++b) {
+                if (ctx->up_done[b]) (void)hipEventDestroy(ctx->up_done[b]);
+                if (ctx->up_pin[b]) (void)hipHostFree(ctx->up_pin[b]);
+                ctx->up_done[b] = nullptr;
+                ctx->up_pin[b] = nullptr;
+            }
         }
         delete ctx;
     });
@@ -517,38 +578,45 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
                 m.bytes += bytes;
             }
             m.value_bytes = m.bytes;
-            // Rows are laid out chunk by chunk through a bounded staging buffer.
+            // Rows are laid out chunk by chunk through a bounded device
+            // staging buffer. A host source is first packed (by several
+            // threads) into one of two pinned buffers, so each chunk crosses
+            // as one 1-D copy and the packing of a chunk overlaps the copy
+            // and layout of the previous one.
             const int64_t chunk_bytes = 64ll << 20;
             int64_t chunk = std::max<int64_t>(64, chunk_bytes / ((int64_t)cols * 4) / 64 * 64);
             chunk = std::min<int64_t>(chunk, (rows + 63) / 64 * 64);
-            if (!on_device) staging = static_cast<float *>(ctx_alloc(ctx, (size_t)chunk * cols * 4));
-            for (int64_t r0 = 0; r0 < rows; r0 += chunk) {
+            const size_t stage_bytes = (size_t)chunk * cols * 4;
+            if (!on_device) {
+                staging = static_cast<float *>(ctx_alloc(ctx, stage_bytes));
+                upload_pinned(ctx, stage_bytes);
+            }
+            int64_t ci = 0;
+            for (int64_t r0 = 0; r0 < rows; r0 += chunk, ++ci) {
                 const int64_t nr = std::min<int64_t>(chunk, rows - r0);
                 const float *dsrc;
                 int64_t dld;
                 if (on_device) {
                     dsrc = col_major ? src + r0 : src + r0 * ld_src;
                     dld = ld_src;
-                } else if (!col_major) {
-                    hip_check(hipMemcpy2DAsync(staging, (size_t)cols * 4, src + r0 * ld_src,
-                                               (size_t)ld_src * 4, (size_t)cols * 4, (size_t)nr,
-                                               hipMemcpyHostToDevice, s),
-                              "hipMemcpy2DAsync");
-                    dsrc = staging;
-                    dld = cols;
                 } else {
-                    hip_check(hipMemcpy2DAsync(staging, (size_t)nr * 4, src + r0, (size_t)ld_src * 4,
-                                               (size_t)nr * 4, (size_t)cols, hipMemcpyHostToDevice, s),
-                              "hipMemcpy2DAsync");
+                    const int b = (int)(ci & 1);
+                    // The copy that last read this pinned buffer has completed.
+                    hip_check(hipEventSynchronize(ctx->up_done[b]), "hipEventSynchronize");
+                    float *pin = static_cast<float *>(ctx->up_pin[b]);
+                    pack_rows(src, ld_src, col_major, r0, nr, cols, pin);
+                    hip_check(hipMemcpyAsync(staging, pin, (size_t)nr * cols * 4, hipMemcpyHostToDevice, s),
+                              "hipMemcpyAsync");
+                    hip_check(hipEventRecord(ctx->up_done[b], s), "hipEventRecord");
                     dsrc = staging;
-                    dld = nr;
+                    dld = col_major ? nr : cols;
                 }
+                // (the next chunk's copy into `staging` follows this kernel on the stream)
                 hip_check(launch_layout(dsrc, dld, col_major, nr, cols, r0, m.X, m.dev.ld,
                                         missing_sentinel, m.Xfill, missing_fill, s),
                           "layout kernel");
-                // The staging buffer is reused by the next chunk.
-                if (!on_device) hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
             }
+            if (!on_device) hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
             hip_check(launch_zero_pad(m.X, rows, m.dev.ld, cols, s), "zero-pad kernel");
             if (m.Xfill) hip_check(launch_zero_pad(m.Xfill, rows, m.dev.ld, cols, s), "zero-pad kernel");
             // Byte rank codes for matrices of at most 128 columns: four rows
@@ -608,6 +676,7 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
                 hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
             }
         } catch (...) {
+            (void)hipStreamSynchronize(s);  // nothing in flight reads what is freed
             ctx_free(ctx, staging);
             ctx_free(ctx, m.X);
             ctx_free(ctx, m.Xfill);

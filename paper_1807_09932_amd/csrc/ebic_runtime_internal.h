@@ -91,6 +91,11 @@ struct ebic_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
     unsigned long long *d_step_counter = nullptr;
     // Fault injection (tests of the error paths; see FaultPlan).
+    // Pinned host staging of uploads (two buffers used alternately, and the
+    // events of the copies that last read them; under mu).
+    void *up_pin[2] = {nullptr, nullptr};
+    hipEvent_t up_done[2] = {nullptr, nullptr};
+    size_t up_pin_bytes = 0;
     std::mutex fault_mu;
     ebic::FaultPlan fault;
     int64_t allocs_done = 0, launches_done = 0;
@@ -229,6 +234,13 @@ ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int3
 // At least `bytes` of device scratch private to stream `s` (grown on demand;
 // a grown buffer replaces the old one after the stream has drained).
 void *stream_scratch(ebic_ctx *ctx, hipStream_t s, size_t bytes);
+// The upload's two pinned host buffers, at least `bytes` each (under mu).
+void upload_pinned(ebic_ctx *ctx, size_t bytes);
+// Copy rows [r0, r0 + nr) of a host matrix (row-major with row stride
+// ld_src, or column-major with column stride ld_src) into dst, packed
+// (row-major: nr x cols; column-major: cols x nr), with a few threads.
+void pack_rows(const float *src, int64_t ld_src, bool col_major, int64_t r0, int64_t nr, int32_t cols,
+               float *dst);
 // Launch one evaluation with the context's diagnostics applied.
 hipError_t ctx_launch_eval(ebic_ctx *ctx, const ReqDesc &d, const LaunchCfg &cfg, hipStream_t s);
 
