@@ -40,8 +40,13 @@ BYTE_PEAK_TOPS = CMP_PEAK_TOPS * 4 / 2.5
 # 16-bit rank codes: the same five ops per two column steps cover two rows
 # per lane op: peak 2 / 2.5 x 39.3 = 31.5 T row-checks/s.
 HALF_PEAK_TOPS = CMP_PEAK_TOPS * 2 / 2.5
+# 10-bit rank codes: three rows per lane op: peak 3 / 2.5 x 39.3 = 47.2 T.
+T10_PEAK_TOPS = CMP_PEAK_TOPS * 3 / 2.5
 STAGE_BYTES = 3
 STAGE_HALVES = 4
+STAGE_T10 = 5
+SWAR_STAGES = (STAGE_BYTES, STAGE_HALVES, STAGE_T10)
+ROWS_PER_OP = {STAGE_BYTES: 4, STAGE_HALVES: 2, STAGE_T10: 3}
 
 
 def alu_roofline(steps, k_ms, staging):
@@ -49,8 +54,8 @@ def alu_roofline(steps, k_ms, staging):
     variant (compare instructions, or 64-row sub-tile column steps with byte
     codes) x 64 rows over the kernel time, against the peak of that staging."""
     ach = steps * 64 / (k_ms * 1e-3) / 1e12
-    if staging in (STAGE_BYTES, STAGE_HALVES):
-        peak = BYTE_PEAK_TOPS if staging == STAGE_BYTES else HALF_PEAK_TOPS
+    if staging in SWAR_STAGES:
+        peak = {STAGE_BYTES: BYTE_PEAK_TOPS, STAGE_HALVES: HALF_PEAK_TOPS, STAGE_T10: T10_PEAK_TOPS}[staging]
         return {"bound": "alu", "achieved": ach, "peak": peak, "unit": "T row-checks/s",
                 "frac": ach / peak}
     return {"bound": "alu", "achieved": ach, "peak": CMP_PEAK_TOPS, "unit": "T compare lane-ops/s",
@@ -164,7 +169,7 @@ def upload_report(ctx, mat):
     from paper_1807_09932_amd import ebic
     names = [n for n, b in (("fp32_fill_copy", ebic.SET_FILL_COPY), ("fp16", ebic.SET_FP16),
                             ("fp16_fill", ebic.SET_FP16_FILL), ("u8", ebic.SET_U8),
-                            ("u16", ebic.SET_U16)) if st["code_sets"] & b]
+                            ("u16", ebic.SET_U16), ("u10", ebic.SET_U10)) if st["code_sets"] & b]
     return {"upload_ms": st["upload_ms"], "resident_bytes": st["value_bytes"] + st["code_bytes"],
             "value_bytes": st["value_bytes"], "code_bytes": st["code_bytes"], "code_sets": names,
             "swar_tie_chunks": st["swar_tie_chunks"], "swar_chunks": st["swar_chunks"],
@@ -191,9 +196,9 @@ def roofline_views(executed_steps, k_ms, staging, matrix_bytes, n_ind):
             "unit": "T lane-compares/s", "frac": executed_steps * 2 * 64 / t / 1e12 / CMP_PEAK_TOPS,
             "note": "executed 64-row column steps x 2 compares x 64 lanes, as if each step were "
                     "two FP32 compares; above 1 for rank codes, whose one 32-bit lane operation "
-                    "compares four (u8) or two (u16) rows"},
+                    "compares four (u8), three (u10) or two (u16) rows"},
     }
-    if staging not in (STAGE_BYTES, STAGE_HALVES):
+    if staging not in SWAR_STAGES:
         views["fp32_compare_issue"]["note"] = ("executed 64-row column steps x 2 compares x 64 lanes "
                                                "over the kernel time")
     return views
@@ -848,9 +853,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {STAGE_BYTES: "u8", STAGE_HALVES: "u16", 2: "f16"}.get(stg, "f32"),
+        "dtype": {STAGE_BYTES: "u8", STAGE_HALVES: "u16", STAGE_T10: "u10", 2: "f16"}.get(stg, "f32"),
         "dtype_note": "the type the evaluation kernel compares: the rank codes it stages "
-                      "(u8: byte codes, four per 32-bit lane word; u16: two per word; f16: FP16 "
+                      "(u8: byte codes, four per 32-bit lane word; u10: 10-bit codes, three per "
+                      "word; u16: two per word; f16: FP16 "
                       "codes) or the FP32 values; the resident matrix and the code build are "
                       "FP32, and the counts are exact integers",
         "data": "synthetic",
@@ -876,8 +882,8 @@ def main():
                      "of one 64-row sub-tile; the first pair counts one step; early exit per "
                      "chunk of two lane words per lane), counted by the measurement variant of "
                      "the kernel; peak = 39.3e12 32-bit VALU lane ops/s x %d rows per lane op / "
-                     "2.5 ops per column step" % (executed_steps, 4 if stg == STAGE_BYTES else 2))
-                    if stg in (STAGE_BYTES, STAGE_HALVES) else
+                     "2.5 ops per column step" % (executed_steps, ROWS_PER_OP.get(stg, 2)))
+                    if stg in SWAR_STAGES else
                     ("FP32 compares executed per launch: %d wave-wide compare instructions x 64 "
                      "rows (first pair: 3 per 64-row tile, then 1 per column step of each row's "
                      "oriented chain; early exit per group of tiles), counted by the measurement "

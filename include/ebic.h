@@ -133,7 +133,8 @@ enum {
     EBIC_SET_FP16 = 2u,        /* FP16 rank codes of the values (missing = NaN) */
     EBIC_SET_FP16_FILL = 4u,   /* FP16 rank codes of the fill copy */
     EBIC_SET_U8 = 8u,          /* byte rank codes of the fill-substituted values */
-    EBIC_SET_U16 = 16u         /* 16-bit rank codes of the fill-substituted values */
+    EBIC_SET_U16 = 16u,        /* 16-bit rank codes of the fill-substituted values */
+    EBIC_SET_U10 = 32u         /* 10-bit rank codes (three per 32-bit word) of the same */
 };
 
 /*

@@ -61,7 +61,7 @@ struct GraphEntry {
 };
 
 using GraphKey = std::tuple<hipStream_t, int32_t, int32_t, int32_t, int64_t, int32_t, int32_t,
-                            int32_t, int64_t, bool>;
+                            int32_t, int64_t, bool, int32_t>;
 
 void check(hipError_t e, const char *what) { hip_check(e, what); }
 
@@ -112,6 +112,7 @@ struct Plan {
     std::vector<int64_t> first;
     std::vector<Item> items;
     std::vector<int32_t> stagings;  // per request
+    int32_t set = kBatchSetAll;     // the kernel instance (kBatchSet*)
     size_t tile_bytes = 0;
     int64_t total_ind = 0;
     int32_t grid = 0;
@@ -151,12 +152,14 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     c.W = std::max(1, std::min(16, c.W));
     c.P = std::max(1, c.P);
 
-    // Staging per request: the byte or 16-bit SWAR codes when the shape asks
-    // for either and the matrix has them for this mode (bytes: four
-    // sub-tiles; 16-bit codes: two); the
-    // FP16 rank codes when the shape asks for codes (or the FP32 tile does
-    // not fit) and they exist and fit; else the FP32 tile if it fits next to
-    // the counts, else direct reads.
+    // Staging per request. When the shape asks for SWAR codes, each request
+    // takes the kind its matrix has for its mode, each at its own number of
+    // sub-tiles: bytes (four), else the kind the shape names among the
+    // 10-bit (three) and 16-bit (two) codes, else the other of the two. Then
+    // the FP16 rank codes when the shape asks for codes (or the FP32 tile
+    // does not fit) and they exist and fit; else the FP32 tile if it fits
+    // next to the counts, else direct reads.
+    std::vector<int32_t> tiles_of;  // sub-tiles per chunk, per request
     for (int32_t q = 0; q < n_reqs; ++q) {
         const ebic_request &r = reqs[q];
         Matrix &m = ctx_matrix_mut(ctx, r.matrix);
@@ -166,36 +169,59 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
         const bool built_codes = (include ? m.dev.Cfill : m.dev.C) != nullptr;
         const bool have_codes = built_codes || (codes != CODES_EXISTING && codes_buildable(m, include));
         const bool have_bytes = m.dev.B && (include || m.dev.b_exclude);
-        const bool have_halves = m.dev.Hc && (include || m.dev.h_exclude);
+        const bool have_halves = m.dev.Hc ? (include || m.dev.h_exclude)
+                                          : codes != CODES_EXISTING && halves_buildable(m, include);
+        const bool have_t10 = m.dev.T10 && (include || m.dev.t_exclude);
         auto fits = [&](int32_t stg) {
-            return tile_lds_bytes(c.L, m.dev.cols, stg) + count_lds_bytes(c.P) <= lds_max;
+            return tile_lds_bytes(batch_tiles(stg, c.L), m.dev.cols, stg) + count_lds_bytes(c.P) <= lds_max;
         };
         int32_t staging = STAGE_DIRECT;
         const bool codes_ok = have_codes && c.L >= 2 && fits(STAGE_CODES);
-        const bool wants_swar = c.staging == STAGE_BYTES || c.staging == STAGE_HALVES;
+        const bool wants_swar = c.staging == STAGE_BYTES || c.staging == STAGE_HALVES || c.staging == STAGE_T10;
         const bool wants_codes = c.staging == STAGE_CODES || wants_swar;
-        if (wants_swar && c.L == 4 && have_bytes && fits(STAGE_BYTES)) staging = STAGE_BYTES;
-        else if (wants_swar && c.L == 2 && have_halves && fits(STAGE_HALVES)) staging = STAGE_HALVES;
+        const int32_t wide1 = c.staging == STAGE_HALVES ? STAGE_HALVES : STAGE_T10;
+        const int32_t wide2 = wide1 == STAGE_HALVES ? STAGE_T10 : STAGE_HALVES;
+        auto have = [&](int32_t stg) { return stg == STAGE_T10 ? have_t10 : have_halves; };
+        if (wants_swar && have_bytes && fits(STAGE_BYTES)) staging = STAGE_BYTES;
+        else if (wants_swar && have(wide1) && fits(wide1)) staging = wide1;
+        else if (wants_swar && have(wide2) && fits(wide2)) staging = wide2;
         else if (codes_ok && (wants_codes || !fits(STAGE_LDS))) staging = STAGE_CODES;
         else if (fits(STAGE_LDS)) staging = STAGE_LDS;
         if (staging == STAGE_CODES && !built_codes && codes == CODES_BUILD && r.n_ind > 0)
             build_fp16_codes(ctx, m, include);
+        if (staging == STAGE_HALVES && !m.Hc && codes == CODES_BUILD && r.n_ind > 0) build_half_codes(ctx, m);
         // (a report plans codes that are not built yet: its descriptors are
         // never launched)
-        const bool unbuilt = staging == STAGE_CODES && (include ? m.dev.Cfill : m.dev.C) == nullptr;
+        const bool unbuilt = (staging == STAGE_CODES && (include ? m.dev.Cfill : m.dev.C) == nullptr) ||
+                             (staging == STAGE_HALVES && !m.dev.Hc);
         ReqDesc d = make_desc(m, std::max(0, r.n_ind), r.d_offsets, r.d_cols, r.flags, r.d_matched,
                               r.d_negative, r.d_matched_mask, r.d_negative_mask,
                               unbuilt && (codes == CODES_REPORT || r.n_ind <= 0) ? STAGE_LDS : staging);
         d.head_base = p.first.back();
         p.stagings.push_back(staging);
-        p.tile_bytes = std::max(p.tile_bytes, tile_lds_bytes(c.L, m.dev.cols, staging));
+        tiles_of.push_back(batch_tiles(staging, c.L));
+        p.tile_bytes = std::max(p.tile_bytes, tile_lds_bytes(tiles_of.back(), m.dev.cols, staging));
         p.descs.push_back(d);
         p.first.push_back(p.first.back() + d.n);
     }
     p.total_ind = p.first.back();
+    // The kernel instance: one compiled for a single kind of SWAR codes when
+    // every live request stages that kind.
+    {
+        int32_t used = 0;
+        for (size_t q = 0; q < p.stagings.size(); ++q) {
+            if (p.descs[q].n <= 0) continue;
+            const int32_t stg = p.stagings[q];
+            used |= stg == STAGE_BYTES ? kBatchSetBytes
+                    : stg == STAGE_HALVES ? kBatchSetHalves
+                    : stg == STAGE_T10 ? kBatchSetT10
+                    : stg == STAGE_CODES ? kBatchSetCodes : kBatchSetValues;
+        }
+        p.set = used == kBatchSetBytes || used == kBatchSetHalves || used == kBatchSetT10 ? used : kBatchSetAll;
+    }
 
     const size_t lds = p.tile_bytes + count_lds_bytes(c.P);
-    int occ = batch_occupancy(c.L, c.W, lds);
+    int occ = batch_occupancy(c.L, p.set, c.W, lds);
     if (occ <= 0) occ = 1;
     p.grid = c.blocks > 0 ? c.blocks : ctx->cu_count * occ;
 
@@ -214,7 +240,8 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
         const ReqDesc &d = p.descs[q];
         if (d.n == 0) continue;
         const int64_t tiles = (d.rows + 63) / 64;
-        const int64_t chunks = (tiles + c.L - 1) / c.L;  // ranges start on a multiple of L tiles
+        const int32_t Lq = tiles_of[q];
+        const int64_t chunks = (tiles + Lq - 1) / Lq;  // ranges start on a multiple of Lq tiles
         const int32_t groups = (d.n + c.P - 1) / c.P;
         const double share = units > 0 ? target * (double)d.n * (double)tiles / units : 1.0;
         int64_t ranges = (int64_t)std::max(1.0, share / groups + 0.5);
@@ -227,8 +254,8 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
                 it.req = q;
                 it.i0 = i0;
                 it.np = np;
-                it.t0 = (int32_t)(r * chunks / ranges * c.L);
-                it.t1 = (int32_t)std::min<int64_t>(tiles, (r + 1) * chunks / ranges * c.L);
+                it.t0 = (int32_t)(r * chunks / ranges * Lq);
+                it.t1 = (int32_t)std::min<int64_t>(tiles, (r + 1) * chunks / ranges * Lq);
                 if (it.t1 <= it.t0) continue;
                 est.push_back({it, (double)np * (double)(it.t1 - it.t0)});
             }
@@ -262,7 +289,7 @@ static GraphSpec graph_spec(hipStream_t s, const Plan &p, bool count)
     g.cap_items = (int32_t)pow2(std::max<int64_t>(8192, (int64_t)p.items.size()));
     g.cap_ind = pow2(std::max<int64_t>(16384, p.total_ind));
     g.key = GraphKey{s, p.cfg.L, p.cfg.W, p.cfg.P, (int64_t)p.tile_bytes, p.grid, g.cap_req, g.cap_items,
-                     g.cap_ind, count};
+                     g.cap_ind, count, p.set};
     return g;
 }
 
@@ -297,7 +324,7 @@ static std::unique_ptr<GraphEntry> capture_graph(ebic_ctx *ctx, const GraphSpec 
                              reinterpret_cast<const ReqDesc *>(da + lay.descs),
                              reinterpret_cast<const int64_t *>(da + lay.first),
                              reinterpret_cast<const Item *>(da + lay.items), g->d_heads, p.cfg.L,
-                             p.cfg.W, p.cfg.P, p.tile_bytes, p.grid, prep_blocks, counter, cs);
+                             p.set, p.cfg.W, p.cfg.P, p.tile_bytes, p.grid, prep_blocks, counter, cs);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         check(e, "batch capture");

@@ -52,6 +52,7 @@ __host__ __device__ inline size_t tile_bytes_of(int32_t L, int32_t cols, int32_t
     if (staging == STAGE_DIRECT) return 0;
     if (staging == STAGE_BYTES) return (size_t)cols * L * kWave;  // one byte per row
     if (staging == STAGE_HALVES) return (size_t)cols * L * kWave * 2;
+    if (staging == STAGE_T10) return (size_t)cols * 256;  // one lane word (three sub-tiles)
     return (size_t)L * kWave * cols * (staging == STAGE_CODES ? sizeof(uint16_t) : sizeof(float));
 }
 
@@ -754,6 +755,16 @@ template <> struct Lanes<16> {
     static constexpr int SHF = 15;
     static constexpr int PARTS = 2;
 };
+// Three parts of ten bits (bits 30-31 unused; codes below 2^9): the same
+// arithmetic holds per part, and the sum D + E of the first pair carries
+// into bits 10, 20 and 30.
+template <> struct Lanes<10> {
+    static constexpr uint32_t H = 0x20080200u;
+    static constexpr uint32_t TWO = 0x40100400u;
+    static constexpr uint32_t MIR = 0x1ff7fdffu;
+    static constexpr int SHF = 9;
+    static constexpr int PARTS = 3;
+};
 
 
 #define BY_LOAD(t, w)                                                          \
@@ -1157,11 +1168,26 @@ __device__ __forceinline__ void half_masks2(uint32_t x, uint64_t &m0, uint64_t &
         : [x] "v"(x));
 }
 
+// Wave-wide masks of the three 64-row sub-tiles of a word of 10-bit parts:
+// x holds only the parts' top bits (9, 19, 29), which lie alone in bytes
+// 1, 2 and 3.
+__device__ __forceinline__ void t10_masks3(uint32_t x, uint64_t &m0, uint64_t &m1, uint64_t &m2)
+{
+    asm volatile(
+        "v_cmp_ne_u32_sdwa %[m0], %[x], 0 src0_sel:BYTE_1 src1_sel:DWORD\n\t"
+        "v_cmp_ne_u32_sdwa %[m1], %[x], 0 src0_sel:BYTE_2 src1_sel:DWORD\n\t"
+        "v_cmp_ne_u32_sdwa %[m2], %[x], 0 src0_sel:BYTE_3 src1_sel:DWORD\n\t"
+        "s_nop 1"
+        : [m0] "=s"(m0), [m1] "=s"(m1), [m2] "=s"(m2)
+        : [x] "v"(x));
+}
+
 // The sub-tile masks of a word (BITS-bit parts; the top bit of each part).
 template <int BITS>
 __device__ __forceinline__ void lane_masks(uint32_t x, uint64_t *m)
 {
     if constexpr (BITS == 8) byte_masks4(x, m[0], m[1], m[2], m[3]);
+    else if constexpr (BITS == 10) t10_masks3(x, m[0], m[1], m[2]);
     else half_masks2(x, m[0], m[1]);
 }
 
@@ -1185,6 +1211,19 @@ __device__ __forceinline__ int32_t lane_popc(uint32_t x)
             "s_bcnt1_i32_b64 %[d], %[a]\n\t"
             "s_add_u32 %[c], %[c], %[d]\n\t"
             "s_bcnt1_i32_b64 %[d], %[b]\n\t"
+            "s_add_u32 %[c], %[c], %[d]"
+            : [a] "=&s"(a), [b] "=&s"(b), [c] "=&s"(c), [d] "=&s"(d)
+            : [x] "v"(x)
+            : "scc");
+    } else if constexpr (BITS == 10) {
+        asm volatile(
+            "v_cmp_ne_u32_sdwa %[a], %[x], 0 src0_sel:BYTE_1 src1_sel:DWORD\n\t"
+            "v_cmp_ne_u32_sdwa %[b], %[x], 0 src0_sel:BYTE_2 src1_sel:DWORD\n\t"
+            "s_bcnt1_i32_b64 %[c], %[a]\n\t"
+            "v_cmp_ne_u32_sdwa %[a], %[x], 0 src0_sel:BYTE_3 src1_sel:DWORD\n\t"
+            "s_bcnt1_i32_b64 %[d], %[b]\n\t"
+            "s_add_u32 %[c], %[c], %[d]\n\t"
+            "s_bcnt1_i32_b64 %[d], %[a]\n\t"
             "s_add_u32 %[c], %[c], %[d]"
             : [a] "=&s"(a), [b] "=&s"(b), [c] "=&s"(c), [d] "=&s"(d)
             : [x] "v"(x)
@@ -1532,12 +1571,18 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
     // of column idx / pieces) through registers, and the pieces of the next
     // chunk are loaded while the current one is evaluated. Pieces past
     // 2 * blockDim are copied directly.
-    constexpr bool kSwar = STAGE == STAGE_BYTES || STAGE == STAGE_HALVES;
-    constexpr int BITS = STAGE == STAGE_HALVES ? 16 : 8;
-    constexpr int RB = BITS / 8;                      // bytes per row
-    constexpr int PARTS = 32 / BITS;                  // rows (sub-tiles) per lane word
+    constexpr bool kSwar = STAGE == STAGE_BYTES || STAGE == STAGE_HALVES || STAGE == STAGE_T10;
+    constexpr bool kT10 = STAGE == STAGE_T10;
+    constexpr int BITS = STAGE == STAGE_HALVES ? 16 : kT10 ? 10 : 8;
+    constexpr int PARTS = kT10 ? 3 : 32 / BITS;      // rows (sub-tiles) per lane word
     constexpr int NWORDS = L >= PARTS ? L / PARTS : 1;  // lane words per chunk
-    constexpr int PL = L * RB == 8 ? 5 : 4;          // log2 of the pieces per column
+    constexpr int CB = 256 * NWORDS;                  // bytes of one column per chunk
+    constexpr int PL = NWORDS == 2 ? 5 : 4;          // log2 of the 16-byte pieces per column
+    // A chunk starts on a multiple of L tiles: its bytes in a column, and
+    // the index of its tie flag (one per 512 rows; 10-bit codes: one per
+    // 192-row chunk).
+    auto chunk_at = [](int64_t tile) { return tile / L * CB; };
+    auto tie_at = [](int64_t tile) { return kT10 ? tile / 3 : (tile * kWave) >> 9; };
     const int btotal = kSwar ? d.cols << PL : 0;
     const int idx0 = threadIdx.x, idx1 = threadIdx.x + blockDim.x;
     const uint8_t *src0 = d.B + (int64_t)(idx0 >> PL) * d.ldb + 16 * (idx0 & ((1 << PL) - 1));
@@ -1546,10 +1591,10 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
     int32_t tie_pre = 1;  // the next chunk's tie flag, loaded with its bytes
     if constexpr (kSwar) {
         if (t0 < t1) {
-            const int64_t r0 = t0 * kWave * RB;
+            const int64_t r0 = chunk_at(t0);
             if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r0);
             if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r0);
-            tie_pre = d.T[(t0 * kWave) >> 9];
+            tie_pre = d.T[tie_at(t0)];
         }
     }
 
@@ -1590,7 +1635,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         uint32_t hvalid[NWORDS] = {};
         bool ties = true;
         if constexpr (kSwar) {
-            static_assert(STAGE == STAGE_HALVES ? (L == 2 || L == 4) : (L == 4 || L == 8),
+            static_assert(STAGE == STAGE_HALVES ? (L == 2 || L == 4) : kT10 ? L == 3 : (L == 4 || L == 8),
                           "one or two lane words per row of a chunk");
             ties = __builtin_amdgcn_readfirstlane(tie_pre) != 0;  // (uniform: one flag per chunk)
             // The L * 64 rows [row0, row0 + 64 L) of every column, in their
@@ -1600,7 +1645,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             if (idx0 < btotal) tile4[idx0] = pre0;
             if (idx1 < btotal) tile4[idx1] = pre1;
             for (int idx = idx1 + blockDim.x; idx < btotal; idx += blockDim.x)
-                tile4[idx] = *reinterpret_cast<const uint4 *>(d.B + (int64_t)(idx >> PL) * d.ldb + row0 * RB +
+                tile4[idx] = *reinterpret_cast<const uint4 *>(d.B + (int64_t)(idx >> PL) * d.ldb + chunk_at(tb) +
                                                               16 * (idx & ((1 << PL) - 1)));
             if (nl == L && row0 + L * kWave <= d.rows) {
 #pragma unroll
@@ -1613,10 +1658,10 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             }
             __syncthreads();
             if (tb + L < t1) {
-                const int64_t r1 = row0 + L * kWave;
-                if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r1 * RB);
-                if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r1 * RB);
-                tie_pre = d.T[r1 >> 9];
+                const int64_t r1 = chunk_at(tb + L);
+                if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r1);
+                if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r1);
+                tie_pre = d.T[tie_at(tb + L)];
             }
         }
         if constexpr (STAGE == STAGE_LDS) {
@@ -1846,7 +1891,8 @@ k_eval(ReqDesc d, const IndHead *__restrict__ heads, int32_t P, int32_t n_tiles,
     const int64_t t0 = (int64_t)rng * n_chunks / gridDim.x * L;
     const int64_t t1 = min<int64_t>(n_tiles, (int64_t)(rng + 1) * n_chunks / gridDim.x * L);
     uint64_t steps = 0;
-    run_item<L, NEG, STAGE, COUNT, STAGE == STAGE_HALVES>(d, heads, i0, np, t0, t1, tile, cnt, steps);
+    run_item<L, NEG, STAGE, COUNT, STAGE == STAGE_HALVES || STAGE == STAGE_T10>(d, heads, i0, np, t0, t1, tile,
+                                                                                 cnt, steps);
     if (COUNT && (threadIdx.x & (kWave - 1)) == 0 && steps)
         atomicAdd(step_counter, (unsigned long long)steps);
 }
@@ -1856,7 +1902,10 @@ k_eval(ReqDesc d, const IndHead *__restrict__ heads, int32_t P, int32_t n_tiles,
 // the batch header until none are left; each item carries its request
 // (matrix, population, flags, outputs).
 // ---------------------------------------------------------------------------
-template <int L, bool COUNT>
+// SET: the stagings this instance handles (kBatchSet* bits): a batch whose
+// requests all stage one kind of SWAR codes runs an instance compiled for
+// that kind alone, whose registers are not shared with the other paths.
+template <int L, int SET, bool COUNT>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 k_eval_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs, const Item *__restrict__ items,
              const IndHead *__restrict__ heads, int32_t tile_bytes, int32_t P,
@@ -1878,36 +1927,47 @@ k_eval_batch(BatchHeader *hdr, const ReqDesc *__restrict__ descs, const Item *__
         const Item it = items[id];
         const ReqDesc d = descs[it.req];
         const bool neg = (d.flags & kFlagNeg) != 0;
-        if constexpr (L == 4) {  // (byte codes in batches: four sub-tiles)
+        // SWAR codes in batches: one lane word per row group, at the number
+        // of sub-tiles of the codes (bytes 4, 10-bit codes 3, 16-bit codes
+        // 2; the planner cuts each request's tile ranges to it). The
+        // two-word sequences are left to plain launches: beside the other
+        // paths of a persistent kernel they would not fit its registers.
+        if constexpr ((SET & kBatchSetBytes) != 0) {
             if (d.flags & kFlagBytes) {
-                if (neg) run_item<L, true, STAGE_BYTES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
-                else run_item<L, false, STAGE_BYTES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                if (neg) run_item<4, true, STAGE_BYTES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                else run_item<4, false, STAGE_BYTES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
                 continue;
             }
         }
-        // 16-bit codes in batches: one lane word per row (L = 2). The
-        // two-word sequences would push the L = 4 instance, which holds the
-        // byte path, past its register budget into scratch.
-        if constexpr (L == 2) {
+        if constexpr ((SET & kBatchSetT10) != 0) {
+            if (d.flags & kFlagT10) {
+                if (neg) run_item<3, true, STAGE_T10, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                else run_item<3, false, STAGE_T10, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                continue;
+            }
+        }
+        if constexpr ((SET & kBatchSetHalves) != 0) {
             if (d.flags & kFlagHalves) {
-                if (neg) run_item<L, true, STAGE_HALVES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
-                else run_item<L, false, STAGE_HALVES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                if (neg) run_item<2, true, STAGE_HALVES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                else run_item<2, false, STAGE_HALVES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
                 continue;
             }
         }
-        if constexpr (L >= 2) {
+        if constexpr (L >= 2 && (SET & kBatchSetCodes)) {
             if (d.flags & kFlagCodes) {
                 if (neg) run_item<L, true, STAGE_CODES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
                 else run_item<L, false, STAGE_CODES, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
                 continue;
             }
         }
-        if ((d.flags & kFlagDirect) == 0) {
-            if (neg) run_item<L, true, STAGE_LDS, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
-            else run_item<L, false, STAGE_LDS, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
-        } else {
-            if (neg) run_item<L, true, STAGE_DIRECT, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
-            else run_item<L, false, STAGE_DIRECT, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+        if constexpr ((SET & kBatchSetValues) != 0) {
+            if ((d.flags & kFlagDirect) == 0) {
+                if (neg) run_item<L, true, STAGE_LDS, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                else run_item<L, false, STAGE_LDS, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+            } else {
+                if (neg) run_item<L, true, STAGE_DIRECT, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+                else run_item<L, false, STAGE_DIRECT, COUNT>(d, heads, it.i0, it.np, it.t0, it.t1, tile, cnt, steps);
+            }
         }
     }
     if (COUNT && (threadIdx.x & (kWave - 1)) == 0 && steps)
@@ -1952,6 +2012,10 @@ const void *eval_pick(int L, bool neg, int staging)
         if (L == 8) return neg ? eval_ptr<8, true, STAGE_BYTES, COUNT>() : eval_ptr<8, false, STAGE_BYTES, COUNT>();
         return nullptr;
     }
+    if (staging == STAGE_T10) {  // one lane word of three rows per chunk
+        if (L == 3) return neg ? eval_ptr<3, true, STAGE_T10, COUNT>() : eval_ptr<3, false, STAGE_T10, COUNT>();
+        return nullptr;
+    }
     if (staging == STAGE_HALVES) {  // one or two lane words of two rows per chunk
         if (L == 2) return neg ? eval_ptr<2, true, STAGE_HALVES, COUNT>() : eval_ptr<2, false, STAGE_HALVES, COUNT>();
         if (L == 4) return neg ? eval_ptr<4, true, STAGE_HALVES, COUNT>() : eval_ptr<4, false, STAGE_HALVES, COUNT>();
@@ -1969,12 +2033,23 @@ const void *eval_kernel(int L, uint32_t flags, int staging, bool count)
     return count ? eval_pick<true>(L, neg, staging) : eval_pick<false>(L, neg, staging);
 }
 
-const void *batch_kernel(int L, bool count)
+const void *batch_kernel(int L, int set, bool count)
 {
+    // Instances for one kind of SWAR codes (whatever L the other stagings
+    // would take), else the general one of each L.
+    if (set == kBatchSetBytes)
+        return count ? (const void *)&k_eval_batch<2, kBatchSetBytes, true>
+                     : (const void *)&k_eval_batch<2, kBatchSetBytes, false>;
+    if (set == kBatchSetHalves)
+        return count ? (const void *)&k_eval_batch<2, kBatchSetHalves, true>
+                     : (const void *)&k_eval_batch<2, kBatchSetHalves, false>;
+    if (set == kBatchSetT10)
+        return count ? (const void *)&k_eval_batch<2, kBatchSetT10, true>
+                     : (const void *)&k_eval_batch<2, kBatchSetT10, false>;
     switch (L) {
-    case 1: return count ? (const void *)&k_eval_batch<1, true> : (const void *)&k_eval_batch<1, false>;
-    case 2: return count ? (const void *)&k_eval_batch<2, true> : (const void *)&k_eval_batch<2, false>;
-    case 4: return count ? (const void *)&k_eval_batch<4, true> : (const void *)&k_eval_batch<4, false>;
+    case 1: return count ? (const void *)&k_eval_batch<1, kBatchSetAll, true> : (const void *)&k_eval_batch<1, kBatchSetAll, false>;
+    case 2: return count ? (const void *)&k_eval_batch<2, kBatchSetAll, true> : (const void *)&k_eval_batch<2, kBatchSetAll, false>;
+    case 4: return count ? (const void *)&k_eval_batch<4, kBatchSetAll, true> : (const void *)&k_eval_batch<4, kBatchSetAll, false>;
     default: return nullptr;
     }
 }
@@ -2007,9 +2082,9 @@ int eval_occupancy(const LaunchCfg &cfg, int32_t cols, uint32_t flags)
     return blocks;
 }
 
-int batch_occupancy(int32_t L, int32_t W, size_t lds)
+int batch_occupancy(int32_t L, int32_t set, int32_t W, size_t lds)
 {
-    const void *k = batch_kernel(L, false);
+    const void *k = batch_kernel(L, set, false);
     if (!k) return 0;
     int blocks = 0;
     if (set_lds(k, lds) != hipSuccess) return 0;
@@ -2086,7 +2161,7 @@ IndHead *noalloc_scratch(int device)
 }
 
 hipError_t launch_batch(BatchHeader *hdr, const ReqDesc *descs, const int64_t *first,
-                        const Item *items, IndHead *heads, int32_t L, int32_t W, int32_t P,
+                        const Item *items, IndHead *heads, int32_t L, int32_t set, int32_t W, int32_t P,
                         size_t tile_bytes, int32_t grid, int32_t prep_blocks,
                         unsigned long long *step_counter, hipStream_t s, hipEvent_t ev0,
                         hipEvent_t ev1)
@@ -2094,7 +2169,7 @@ hipError_t launch_batch(BatchHeader *hdr, const ReqDesc *descs, const int64_t *f
     hipLaunchKernelGGL(k_prep_batch, dim3(prep_blocks), dim3(256), 0, s, hdr, descs, first, heads);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const void *k = batch_kernel(L, step_counter != nullptr);
+    const void *k = batch_kernel(L, set, step_counter != nullptr);
     if (!k) return hipErrorInvalidValue;
     const size_t lds = tile_bytes + count_bytes_of(P);
     if ((e = set_lds(k, lds)) != hipSuccess) return e;

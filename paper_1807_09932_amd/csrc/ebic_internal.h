@@ -18,6 +18,7 @@ enum Staging : int32_t {
     STAGE_CODES = 2,   // the matrix's 16-bit rank codes staged into LDS (half the bytes)
     STAGE_BYTES = 3,   // 8-bit rank codes, four rows per 32-bit lane word (4 or 8 sub-tiles)
     STAGE_HALVES = 4,  // 16-bit rank codes, two rows per 32-bit lane word (4 sub-tiles)
+    STAGE_T10 = 5,     // 10-bit rank codes, three rows per 32-bit lane word (3 sub-tiles)
 };
 
 // Rank codes are kept for matrices of at most this many columns: a cell's
@@ -44,6 +45,16 @@ constexpr int32_t kMaxByteCols = 128;
 // half). A column occupies ldh bytes (rows rounded up to a multiple of 256,
 // two bytes each); exclude mode may use them only without missing cells.
 
+// 10-bit rank codes, for matrices of 129 to 512 columns: the same codes of
+// the fill-substituted values (0..511), three per 32-bit word in fields of
+// ten bits (bits 0-8, 10-18 and 20-28 hold the codes; bits 9, 19 and 29 are
+// the fields' top bits, 30-31 stay zero). Within each 192-row group the
+// word of lane l holds rows l, 64 + l and 128 + l (fields 0, 1, 2). A
+// column occupies ld10 bytes (256 per 192-row group); exclude mode may use
+// them only without missing cells. One tie flag per 192-row group.
+constexpr int32_t kMaxT10Cols = 512;
+constexpr int32_t kT10Rows = 192;  // rows per lane-word group
+
 // Request flags as the kernels see them (the low two bits are the ABI's
 // EBIC_NAN_INCLUDE and EBIC_NEG_TRENDS).
 constexpr uint32_t kFlagInclude = 1u;
@@ -53,6 +64,7 @@ constexpr uint32_t kFlagSubst = 1u << 9;   // direct reads replace NaN by the fi
 constexpr uint32_t kFlagCodes = 1u << 10;  // this request stages the rank codes
 constexpr uint32_t kFlagBytes = 1u << 11;  // this request stages the byte rank codes
 constexpr uint32_t kFlagHalves = 1u << 12; // this request stages the 16-bit rank codes
+constexpr uint32_t kFlagT10 = 1u << 13;    // this request stages the 10-bit rank codes
 
 // One launch shape of the evaluation kernels.
 struct LaunchCfg {
@@ -76,6 +88,10 @@ struct DevMatrix {
     const int32_t *Th = nullptr;   // their tie flags per 512 rows
     bool h_exclude = false;        // Hc also serves exclude mode (no missing cell)
     int64_t ldh = 0;               // bytes per column of Hc (multiple of 512)
+    const uint8_t *T10 = nullptr;  // 10-bit rank codes (three rows per word), or null
+    const int32_t *Tt = nullptr;   // their tie flags per 192-row group
+    bool t_exclude = false;        // T10 also serves exclude mode (no missing cell)
+    int64_t ld10 = 0;              // bytes per column of T10 (256 per 192 rows)
     bool b_exclude = false;        // B also serves exclude mode (no missing cell)
     int64_t ldb = 0;               // bytes per column of B (multiple of 256)
     int64_t ld = 0;                // multiple of 64
@@ -88,7 +104,7 @@ struct DevMatrix {
 struct ReqDesc {
     const float *X;            // the matrix to read (the fill copy when it serves include mode)
     const uint16_t *C;         // the rank codes to stage (kFlagCodes), or null
-    const uint8_t *B;          // the byte or 16-bit rank codes to stage (kFlagBytes, kFlagHalves)
+    const uint8_t *B;          // the byte, 16-bit or 10-bit rank codes to stage (kFlagBytes, kFlagHalves, kFlagT10)
     const int32_t *T;          // their per-512-row tie flags
     int64_t ldb;               // bytes per column of B
     int64_t ld;
@@ -148,7 +164,21 @@ size_t item_lds_bytes(int32_t L, int32_t cols, int32_t staging, int32_t P, bool 
 
 // Blocks per CU the plain evaluation kernel reaches with this shape (0 = cannot run).
 int eval_occupancy(const LaunchCfg &cfg, int32_t cols, uint32_t flags);
-int batch_occupancy(int32_t L, int32_t W, size_t lds_bytes);
+// Stagings a batched launch handles (the kernel instance is picked by the set
+// its requests use: one kind of SWAR codes alone, or all).
+constexpr int32_t kBatchSetBytes = 1;
+constexpr int32_t kBatchSetHalves = 2;
+constexpr int32_t kBatchSetCodes = 4;
+constexpr int32_t kBatchSetValues = 8;  // the FP32 tile or direct reads
+constexpr int32_t kBatchSetT10 = 16;
+constexpr int32_t kBatchSetAll = 31;
+// The sub-tiles per chunk of a request that stages `staging` in a batch
+// whose FP32/FP16 stagings take L: SWAR codes fix their own.
+inline int32_t batch_tiles(int32_t staging, int32_t L)
+{
+    return staging == STAGE_BYTES ? 4 : staging == STAGE_T10 ? 3 : staging == STAGE_HALVES ? 2 : L;
+}
+int batch_occupancy(int32_t L, int32_t set, int32_t W, size_t lds_bytes);
 
 // Plain evaluation: prep (validation, output initialisation, headers) then
 // the evaluation kernel over G groups x cfg.blocks tile ranges. ev0/ev1, if
@@ -171,7 +201,7 @@ IndHead *noalloc_scratch(int device);
 // prep_blocks x 256 threads validate every individual of every request;
 // then `grid` persistent blocks of W waves take items from the counter.
 hipError_t launch_batch(BatchHeader *hdr, const ReqDesc *descs, const int64_t *first,
-                        const Item *items, IndHead *heads, int32_t L, int32_t W, int32_t P,
+                        const Item *items, IndHead *heads, int32_t L, int32_t set, int32_t W, int32_t P,
                         size_t tile_bytes, int32_t grid, int32_t prep_blocks,
                         unsigned long long *step_counter, hipStream_t s,
                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
@@ -204,6 +234,12 @@ hipError_t launch_byte_codes(const float *X, int64_t rows, int64_t ld, int32_t c
 // column (a multiple of 512), in their interleaved order.
 hipError_t launch_half_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
                              uint8_t *Hc, int64_t ldh, int32_t *has_nan, int32_t *ties, hipStream_t s);
+
+// The same for 10-bit codes (cols <= kMaxT10Cols) into T10, ld10 bytes per
+// column (256 per 192-row group; T10 zeroed by the caller, the fields are
+// OR-ed in), and one tie flag per 192-row group.
+hipError_t launch_t10_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
+                            uint8_t *T10, int64_t ld10, int32_t *has_nan, int32_t *ties, hipStream_t s);
 
 // Zero rows [rows, ld) of every column of a column-major matrix.
 hipError_t launch_zero_pad(float *dst, int64_t rows, int64_t ld, int32_t cols, hipStream_t s);

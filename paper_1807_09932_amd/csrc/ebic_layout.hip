@@ -132,6 +132,49 @@ k_swar_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols
     if (live && tie) ties[r >> 9] = 1;
 }
 
+// 10-bit rank codes: the same counts, three rows per 32-bit word. Block b
+// holds rows [64 b, 64 b + 64), which are field b mod 3 of 192-row group
+// b / 3: each code is OR-ed into its word (the three blocks of a group
+// write disjoint fields of the same words). Flags a missing cell, and each
+// 192-row group with a row that holds two equal values.
+__global__ void __launch_bounds__(256)
+k_t10_codes(const float *__restrict__ X, int64_t rows, int64_t ld, int32_t cols, float fill,
+            uint32_t *__restrict__ out, int64_t ld_words, int32_t *__restrict__ has_nan,
+            int32_t *__restrict__ ties)
+{
+    extern __shared__ float t[];  // [cols][64]
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r = r0 + lane;
+    const bool live = r < rows;
+    bool missing = false;
+    for (int32_t c = wave; c < cols; c += 4) {
+        float v = live ? X[(int64_t)c * ld + r] : 0.f;
+        if (v != v) {
+            missing = true;
+            v = fill;
+        }
+        t[c * 64 + lane] = v;
+    }
+    if (missing) *has_nan = 1;
+    __syncthreads();
+    const int64_t group = blockIdx.x / 3;
+    const int field = blockIdx.x % 3;
+    bool tie = false;
+    for (int32_t c = wave; c < cols; c += 4) {
+        const float v = t[c * 64 + lane];
+        uint32_t n = 0, e = 0;
+        for (int32_t j = 0; j < cols; ++j) {
+            const float u = t[j * 64 + lane];
+            n += u < v ? 1u : 0u;
+            e += u == v ? 1u : 0u;
+        }
+        tie |= e > 1;
+        if (live && n) atomicOr(out + (int64_t)c * ld_words + group * 64 + lane, n << (10 * field));
+    }
+    if (live && tie) ties[group] = 1;
+}
+
 __global__ void k_zero_pad(float *__restrict__ dst, int64_t rows, int64_t ld, int32_t cols)
 {
     const int64_t pad = ld - rows;
@@ -178,6 +221,22 @@ hipError_t launch_half_codes(const float *X, int64_t rows, int64_t ld, int32_t c
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_swar_codes<uint16_t>, dim3((unsigned)(ldh / 2 / 64)), dim3(256), lds, s, X, rows,
                        ld, cols, fill, reinterpret_cast<uint16_t *>(Hc), ldh / 2, has_nan, ties);
+    return hipGetLastError();
+}
+
+hipError_t launch_t10_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
+                            uint8_t *T10, int64_t ld10, int32_t *has_nan, int32_t *ties, hipStream_t s)
+{
+    const int64_t groups = (rows + kT10Rows - 1) / kT10Rows;
+    if (cols > kMaxT10Cols || ld10 != groups * 256 || ld / 64 < (rows + 63) / 64) return hipErrorInvalidValue;
+    const size_t lds = (size_t)cols * 64 * sizeof(float);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t10_codes),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    // one block per 64 rows up to the last group's end; X is read only for
+    // rows below `rows`
+    hipLaunchKernelGGL(k_t10_codes, dim3((unsigned)(groups * 3)), dim3(256), lds, s, X, rows, ld, cols, fill,
+                       reinterpret_cast<uint32_t *>(T10), ld10 / 4, has_nan, ties);
     return hipGetLastError();
 }
 

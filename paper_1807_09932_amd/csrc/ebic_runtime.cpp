@@ -202,6 +202,54 @@ void build_fp16_codes(ebic_ctx *ctx, Matrix &m, bool include)
                    std::to_string(cbytes) + " bytes");
 }
 
+bool halves_buildable(const Matrix &m, bool include)
+{
+    return m.dev.cols > kMaxByteCols && m.dev.cols <= kMaxCodeCols && (include || m.has_missing == 0);
+}
+
+void build_half_codes(ebic_ctx *ctx, Matrix &m)
+{
+    if (m.Hc) return;
+    if (m.dev.cols <= kMaxByteCols || m.dev.cols > kMaxCodeCols)
+        fail(EBIC_EINVAL, "16-bit rank codes serve matrices of 129 to 384 columns");
+    DeviceGuard g(ctx->device);
+    const int64_t rows = m.dev.rows;
+    const int32_t cols = m.dev.cols;
+    const int64_t rows_pad = (rows + 255) / 256 * 256;
+    const int64_t ldh = rows_pad * 2;
+    const size_t hbytes = (size_t)ldh * cols;
+    const size_t tbytes = (size_t)((rows_pad + 511) / 512) * sizeof(int32_t);
+    uint8_t *Hc = static_cast<uint8_t *>(ctx_alloc(ctx, hbytes + 256 + tbytes));
+    int32_t *flag = reinterpret_cast<int32_t *>(Hc + hbytes);
+    int32_t *ties = reinterpret_cast<int32_t *>(Hc + hbytes + 256);
+    int32_t has_nan = 1;
+    hipStream_t s = nullptr;
+    try {
+        hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+        hip_check(hipMemsetAsync(flag, 0, 256 + tbytes, s), "hipMemsetAsync");
+        hip_check(launch_half_codes(m.X, rows, m.dev.ld, cols, m.dev.fill, Hc, ldh, flag, ties, s),
+                  "16-bit codes kernel");
+        hip_check(hipMemcpyAsync(&has_nan, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        hip_check(hipStreamDestroy(s), "hipStreamDestroy");
+        s = nullptr;
+    } catch (...) {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        ctx_free(ctx, Hc);
+        throw;
+    }
+    m.Hc = Hc;
+    m.dev.Hc = Hc;
+    m.dev.Th = ties;
+    m.dev.ldh = ldh;
+    m.dev.h_exclude = has_nan == 0;
+    m.bytes += hbytes + 256 + tbytes;
+    log_msg(2, "built 16-bit rank codes: " + std::to_string(hbytes) + " bytes");
+}
+
 // Launch shape for one population on one matrix.
 LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t flags, CodesMode codes)
 {
@@ -217,24 +265,37 @@ LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t f
     // built on first use; they are built below only if the plan stages them.
     const bool built_codes = (include ? m.dev.Cfill : m.dev.C) != nullptr;
     const bool have_codes = built_codes || (codes != CODES_EXISTING && codes_buildable(m, include));
-    const bool have_bytes = m.dev.B && ((flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
-    const bool have_halves = m.dev.Hc && ((flags & EBIC_NAN_INCLUDE) || m.dev.h_exclude);
+    const bool have_bytes = m.dev.B && (include || m.dev.b_exclude);
+    // (16-bit codes not built yet count as available where they can be
+    // built; they are built below if the plan stages them)
+    const bool have_halves = m.dev.Hc ? (include || m.dev.h_exclude)
+                                      : codes != CODES_EXISTING && halves_buildable(m, include);
+    const bool have_t10 = m.dev.T10 && (include || m.dev.t_exclude);
     // SWAR codes: bytes (up to 128 columns; one or two lane words per row,
-    // L = 4 or 8) or 16-bit codes (wider; one or two words, L = 2 or 4). A
-    // request without the one its shape asks for takes the other if the
-    // matrix has it, else the FP16 codes (or the FP32 tile) at the same
-    // shape; a tile that does not fit takes one word per row first.
-    if (cfg.staging == STAGE_BYTES && !have_bytes)
-        cfg.staging = have_halves ? STAGE_HALVES : (have_codes ? STAGE_CODES : STAGE_LDS);
-    if (cfg.staging == STAGE_HALVES && !have_halves)
-        cfg.staging = have_bytes ? STAGE_BYTES : (have_codes ? STAGE_CODES : STAGE_LDS);
+    // L = 4 or 8), 10-bit codes (up to 512 columns; one word, L = 3) or
+    // 16-bit codes (up to 384 columns; one or two words, L = 2 or 4). A
+    // request without the kind its shape asks for takes another kind the
+    // matrix has, else the FP16 codes (or the FP32 tile); a tile that does
+    // not fit takes one word per row first.
+    auto have_swar = [&](int32_t st) {
+        return st == STAGE_BYTES ? have_bytes : st == STAGE_HALVES ? have_halves : st == STAGE_T10 ? have_t10 : false;
+    };
+    const bool asked_swar = cfg.staging == STAGE_BYTES || cfg.staging == STAGE_HALVES || cfg.staging == STAGE_T10;
+    if (asked_swar && !have_swar(cfg.staging)) {
+        const int32_t order[3] = {STAGE_BYTES, STAGE_T10, STAGE_HALVES};
+        int32_t pick = -1;
+        for (int32_t st : order)
+            if (pick < 0 && have_swar(st)) pick = st;
+        cfg.staging = pick >= 0 ? pick : (have_codes ? STAGE_CODES : STAGE_LDS);
+    }
     if (cfg.staging == STAGE_BYTES) cfg.L = cfg.L >= 8 ? 8 : 4;
     if (cfg.staging == STAGE_HALVES) cfg.L = cfg.L >= 4 ? 4 : 2;
+    if (cfg.staging == STAGE_T10) cfg.L = 3;
     if (cfg.staging == STAGE_HALVES && cfg.L == 4 && !fits(cfg)) cfg.L = 2;
-    if (cfg.staging == STAGE_HALVES && !fits(cfg)) cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
     if (cfg.staging == STAGE_BYTES && cfg.L == 8 && !fits(cfg)) cfg.L = 4;
-    if (cfg.staging == STAGE_BYTES && !fits(cfg)) cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
-    if (cfg.staging != STAGE_BYTES) cfg.L = std::min(cfg.L, 4);
+    if ((cfg.staging == STAGE_HALVES || cfg.staging == STAGE_BYTES || cfg.staging == STAGE_T10) && !fits(cfg))
+        cfg.staging = have_codes ? STAGE_CODES : STAGE_LDS;
+    if (cfg.staging != STAGE_BYTES && cfg.staging != STAGE_T10) cfg.L = cfg.L == 3 ? 2 : std::min(cfg.L, 4);
     // Rank codes need codes for this mode and at least two sub-tiles.
     if (cfg.staging == STAGE_CODES && (!have_codes || cfg.L < 2)) cfg.staging = STAGE_LDS;
     // An FP32 tile that does not fit: the codes' tile (half the bytes) at the
@@ -270,7 +331,7 @@ LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t f
     // LDS beside a wide tile, which can leave room for a second block per
     // CU); that needs every block's tile range below 65,536 rows, so more
     // ranges are used where the matrix is taller.
-    cfg.cnt16 = cfg.staging == STAGE_HALVES;
+    cfg.cnt16 = cfg.staging == STAGE_HALVES || cfg.staging == STAGE_T10;
     derive_blocks();
     if (cfg.cnt16) {
         const int64_t min_ranges = (n_chunks * cfg.L * 64 + 65535 - 1) / 65535;
@@ -283,6 +344,7 @@ LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t f
         }
     }
     if (cfg.staging == STAGE_CODES && !built_codes && codes == CODES_BUILD) build_fp16_codes(ctx, m, include);
+    if (cfg.staging == STAGE_HALVES && !m.Hc && codes == CODES_BUILD) build_half_codes(ctx, m);
     return cfg;
 }
 
@@ -317,6 +379,14 @@ ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int3
         d.T = m.dev.Th;
         d.ldb = m.dev.ldh;
         d.flags |= kFlagHalves;
+    }
+    if (staging == STAGE_T10) {
+        if (!m.dev.T10 || !(include || m.dev.t_exclude))
+            fail(EBIC_EINVAL, "no 10-bit rank codes for this matrix and mode");
+        d.B = m.dev.T10;
+        d.T = m.dev.Tt;
+        d.ldb = m.dev.ld10;
+        d.flags |= kFlagT10;
     }
     if (staging == STAGE_DIRECT) {
         d.flags |= kFlagDirect;
@@ -500,6 +570,7 @@ ebic_status ebic_destroy(ebic_ctx *ctx)
                 ctx_free(ctx, kv.second.Cfill);
                 ctx_free(ctx, kv.second.B);
                 ctx_free(ctx, kv.second.Hc);
+                ctx_free(ctx, kv.second.T10);
             }
             ctx->matrices.clear();
             destroy_batch_state(ctx);
@@ -640,29 +711,34 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
                 hip_check(hipMemcpyAsync(&has_nan, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s),
                           "hipMemcpyAsync");
             }
-            // 16-bit codes for the wider matrices (two rows per 32-bit word).
+            // (16-bit codes, two rows per 32-bit word, are built on first use:
+            // the 10-bit codes serve the same widths with three.)
             int32_t has_nan_h = 1;
-            if (cols > kMaxByteCols && cols <= kMaxCodeCols) {
-                const int64_t rows_pad = (rows + 255) / 256 * 256;
-                m.dev.ldh = rows_pad * 2;
-                const size_t hbytes = (size_t)m.dev.ldh * cols;
-                const size_t tbytes = (size_t)((rows_pad + 511) / 512) * sizeof(int32_t);
-                m.Hc = static_cast<uint8_t *>(ctx_alloc(ctx, hbytes + 256 + tbytes));
-                m.bytes += hbytes + 256 + tbytes;
-                int32_t *flag = reinterpret_cast<int32_t *>(m.Hc + hbytes);
-                int32_t *ties = reinterpret_cast<int32_t *>(m.Hc + hbytes + 256);
-                hip_check(hipMemsetAsync(flag, 0, 256 + tbytes, s), "hipMemsetAsync");
-                hip_check(launch_half_codes(m.X, rows, m.dev.ld, cols, missing_fill, m.Hc, m.dev.ldh, flag, ties, s),
-                          "16-bit codes kernel");
-                hip_check(hipMemcpyAsync(&has_nan_h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s),
+            // 10-bit codes (three rows per 32-bit word) for 129..512 columns.
+            int32_t has_nan_t = 1;
+            if (cols > kMaxByteCols && cols <= kMaxT10Cols) {
+                const int64_t groups = (rows + kT10Rows - 1) / kT10Rows;
+                m.dev.ld10 = groups * 256;
+                const size_t tb = (size_t)m.dev.ld10 * cols;
+                const size_t fbytes = (size_t)groups * sizeof(int32_t);
+                m.T10 = static_cast<uint8_t *>(ctx_alloc(ctx, tb + 256 + fbytes));
+                m.bytes += tb + 256 + fbytes;
+                int32_t *flag = reinterpret_cast<int32_t *>(m.T10 + tb);
+                int32_t *ties = reinterpret_cast<int32_t *>(m.T10 + tb + 256);
+                hip_check(hipMemsetAsync(m.T10, 0, tb + 256 + fbytes, s), "hipMemsetAsync");
+                hip_check(launch_t10_codes(m.X, rows, m.dev.ld, cols, missing_fill, m.T10, m.dev.ld10, flag, ties, s),
+                          "10-bit codes kernel");
+                hip_check(hipMemcpyAsync(&has_nan_t, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s),
                           "hipMemcpyAsync");
-                m.dev.Th = ties;
+                m.dev.Tt = ties;
             }
             hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
             m.dev.b_exclude = m.B && has_nan == 0;
             m.dev.h_exclude = m.Hc && has_nan_h == 0;
+            m.dev.t_exclude = m.T10 && has_nan_t == 0;
             if (m.B) m.has_missing = has_nan != 0;
             if (m.Hc) m.has_missing = has_nan_h != 0;
+            if (m.T10) m.has_missing = has_nan_t != 0;
             // FP16 rank codes (half the bytes of a staged FP32 tile, missing
             // cells kept as NaN) serve exclude mode where the SWAR codes
             // cannot: on a matrix with missing cells. Other uses (a shape
@@ -684,6 +760,7 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             ctx_free(ctx, m.Cfill);
             ctx_free(ctx, m.B);
             ctx_free(ctx, m.Hc);
+            ctx_free(ctx, m.T10);
             throw;
         }
         ctx_free(ctx, staging);
@@ -693,6 +770,7 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
         m.dev.Cfill = m.Cfill;
         m.dev.B = m.B;
         m.dev.Hc = m.Hc;
+        m.dev.T10 = m.T10;
         m.upload_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         const int32_t id = ctx->next_matrix++;
         ctx->matrices[id] = m;
@@ -715,15 +793,17 @@ ebic_status ebic_matrix_get_stats(ebic_ctx *ctx, int32_t matrix, ebic_matrix_sta
         st.rows = m.dev.rows;
         st.cols = m.dev.cols;
         st.code_sets = (m.Xfill ? EBIC_SET_FILL_COPY : 0u) | (m.C ? EBIC_SET_FP16 : 0u) |
-                       (m.Cfill ? EBIC_SET_FP16_FILL : 0u) | (m.B ? EBIC_SET_U8 : 0u) | (m.Hc ? EBIC_SET_U16 : 0u);
+                       (m.Cfill ? EBIC_SET_FP16_FILL : 0u) | (m.B ? EBIC_SET_U8 : 0u) | (m.Hc ? EBIC_SET_U16 : 0u) |
+                       (m.T10 ? EBIC_SET_U10 : 0u);
         st.value_bytes = (int64_t)m.value_bytes;
         st.code_bytes = (int64_t)(m.bytes - m.value_bytes);
         st.has_missing = m.has_missing;
         st.upload_ms = m.upload_ms;
-        const int32_t *ties = m.B ? m.dev.T : m.Hc ? m.dev.Th : nullptr;
+        // (the tie flags of the default SWAR codes: bytes, else 10-bit codes)
+        const int32_t *ties = m.B ? m.dev.T : m.T10 ? m.dev.Tt : m.Hc ? m.dev.Th : nullptr;
         if (ties) {
             const int64_t rows_pad = m.B ? m.dev.ldb : (m.dev.rows + 255) / 256 * 256;
-            const int64_t n = (rows_pad + 511) / 512;
+            const int64_t n = m.B || !m.T10 ? (rows_pad + 511) / 512 : (m.dev.rows + kT10Rows - 1) / kT10Rows;
             std::vector<int32_t> h((size_t)n);
             hip_check(hipMemcpy(h.data(), ties, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy");
             st.swar_chunks = n;
@@ -763,6 +843,7 @@ ebic_status ebic_release_matrix(ebic_ctx *ctx, int32_t matrix)
         ctx_free(ctx, m.Cfill);
         ctx_free(ctx, m.B);
         ctx_free(ctx, m.Hc);
+        ctx_free(ctx, m.T10);
         ctx->matrices.erase(matrix);
         log_msg(2, "released matrix " + std::to_string(matrix));
     });

@@ -24,6 +24,7 @@ struct Matrix {
     uint16_t *Cfill = nullptr;  // rank codes of Xfill
     uint8_t *B = nullptr;       // byte rank codes (cols <= kMaxByteCols)
     uint8_t *Hc = nullptr;      // 16-bit rank codes (kMaxByteCols < cols <= kMaxCodeCols)
+    uint8_t *T10 = nullptr;     // 10-bit rank codes (kMaxByteCols < cols <= kMaxT10Cols)
     size_t bytes = 0;        // everything resident for this matrix
     size_t value_bytes = 0;  // X and Xfill
     float sentinel = 0.f;
@@ -224,6 +225,10 @@ bool codes_buildable(const Matrix &m, bool include);
 // Build them now (under ctx->mu): allocation, the codes kernel on a private
 // stream, and a wait for it.
 void build_fp16_codes(ebic_ctx *ctx, Matrix &m, bool include);
+// 16-bit SWAR codes (129..384 columns) are built on first use too: whether
+// they can serve a mode, and their build (under ctx->mu).
+bool halves_buildable(const Matrix &m, bool include);
+void build_half_codes(ebic_ctx *ctx, Matrix &m);
 LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t flags,
                     CodesMode codes = CODES_BUILD);
 // The kernels' view of one request; `staging` decides whether include mode

@@ -41,10 +41,11 @@ static TuneKey batch_key(int64_t total_ind, int64_t mean_rows, int32_t max_cols)
     return TuneKey{1, log2_bucket(mean_rows), log2_bucket(max_cols), log2_bucket(total_ind), 0};
 }
 
-// Defaults measured on MI355X for the 436,444 x 64 workload: the byte rank
+// Defaults measured on MI355X: for the 436,444 x 64 workload the byte rank
 // codes (four 64-row sub-tiles per lane word, two words per chunk) up to
-// 128 columns, sixteen waves per block, groups of 200 individuals; wider
-// matrices stage the 16-bit SWAR codes. A request without codes for its
+// 128 columns, sixteen waves per block, groups of 200 individuals; for
+// 129..512 columns (the 436,444 x 310 workload) the 10-bit codes, three
+// sub-tiles per lane word, groups of 400. A request without codes for its
 // mode falls back at launch.
 static int32_t default_L(int32_t cols) { return cols <= 64 ? 4 : (cols <= 128 ? 2 : 1); }
 
@@ -61,12 +62,12 @@ LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
         c.staging = STAGE_BYTES;
         c.L = 8;
         c.P = std::max(1, std::min(n, 200));
-    } else if (cols <= kMaxCodeCols) {
-        // 16-bit rank codes, one lane word of two rows per 128-row chunk
+    } else if (cols <= kMaxT10Cols) {
+        // 10-bit rank codes, one lane word of three rows per 192-row chunk
         // (cols x 256 bytes: two blocks per CU up to about 310 columns).
-        c.staging = STAGE_HALVES;
-        c.L = 2;
-        c.P = std::max(1, std::min(n, 200));
+        c.staging = STAGE_T10;
+        c.L = 3;
+        c.P = std::max(1, std::min(n, 400));
     }
     c.blocks = 0;
     return c;
@@ -82,9 +83,9 @@ LaunchCfg default_batch_cfg(int32_t max_cols)
     if (max_cols <= kMaxByteCols) {
         c.staging = STAGE_BYTES;
         c.L = 4;
-    } else if (max_cols <= kMaxCodeCols) {
-        c.staging = STAGE_HALVES;  // one lane word per row, large groups
-        c.L = 2;
+    } else if (max_cols <= kMaxT10Cols) {
+        c.staging = STAGE_T10;  // one lane word of three rows, large groups
+        c.L = 2;                // (the FP16 codes' sub-tiles, for requests without 10-bit codes)
         c.P = 1024;
     }
     c.blocks = 0;
@@ -227,10 +228,11 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
             ctx->override_cfg = LaunchCfg();
             return;
         }
-        if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 4 || tiles_per_wave == 8) ||
+        if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 3 || tiles_per_wave == 4 ||
+              tiles_per_wave == 8) ||
             waves_per_block < 1 || waves_per_block > 16 || individuals_per_group < 1 ||
             !(staging == STAGE_LDS || staging == STAGE_DIRECT || staging == STAGE_CODES ||
-              staging == STAGE_BYTES || staging == STAGE_HALVES) ||
+              staging == STAGE_BYTES || staging == STAGE_HALVES || staging == STAGE_T10) ||
             blocks < 0)
             fail(EBIC_EINVAL, "launch shape out of range");
         LaunchCfg c;
@@ -275,7 +277,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                           "hipMemcpy");
                 int64_t rows;
                 int32_t cols;
-                bool have_codes, have_bytes, have_halves;
+                bool have_codes, have_bytes, have_halves, have_t10;
                 {
                     std::lock_guard<std::mutex> lk(ctx->mu);
                     const Matrix &m = ctx_matrix(ctx, r.matrix);
@@ -284,23 +286,27 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                     have_codes = ((r.flags & EBIC_NAN_INCLUDE) ? m.dev.Cfill : m.dev.C) != nullptr;
                     have_bytes = m.dev.B && ((r.flags & EBIC_NAN_INCLUDE) || m.dev.b_exclude);
                     have_halves = m.dev.Hc && ((r.flags & EBIC_NAN_INCLUDE) || m.dev.h_exclude);
+                    have_t10 = m.dev.T10 && ((r.flags & EBIC_NAN_INCLUDE) || m.dev.t_exclude);
                 }
                 const TuneKey key = tune_key(rows, cols, r.n_ind, (int64_t)ends[1] - ends[0]);
                 if (!done.insert(key).second) continue;
                 LaunchCfg best;
                 float best_ms = INFINITY;
-                for (int L : {1, 2, 4, 8})
+                for (int L : {1, 2, 3, 4, 8})
                     for (int W : {4, 8, 16})
                         for (int P : {200, 400, 800, 1600})
                             for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT, (int)STAGE_CODES,
-                                            (int)STAGE_BYTES, (int)STAGE_HALVES}) {
+                                            (int)STAGE_BYTES, (int)STAGE_HALVES, (int)STAGE_T10}) {
+                                if ((L == 3) != (stg == STAGE_T10)) continue;  // 10-bit codes: three sub-tiles
+                                if (stg == STAGE_T10 && !have_t10) continue;
                                 LaunchCfg c;
                                 c.L = L;
                                 c.W = W;
                                 c.P = std::min(P, r.n_ind);
                                 c.staging = stg;
                                 if (stg != STAGE_DIRECT &&
-                                    item_lds_bytes(L, cols, stg, c.P) > ctx->lds_per_block)
+                                    item_lds_bytes(L, cols, stg, c.P,
+                                                   stg == STAGE_HALVES || stg == STAGE_T10) > ctx->lds_per_block)
                                     continue;
                                 if (stg == STAGE_CODES && (L < 2 || !have_codes)) continue;
                                 if (stg == STAGE_BYTES && (L < 4 || !have_bytes)) continue;
@@ -348,10 +354,10 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                         for (int W : {4, 8, 16})
                             for (int P : {128, 256, 512, 1024})
                                 for (int stg : {(int)STAGE_LDS, (int)STAGE_CODES, (int)STAGE_BYTES,
-                                                (int)STAGE_HALVES}) {
+                                                (int)STAGE_HALVES, (int)STAGE_T10}) {
                                 if (stg == STAGE_CODES && L < 2) continue;
-                                if (stg == STAGE_BYTES && L != 4) continue;  // batches: bytes at 4,
-                                if (stg == STAGE_HALVES && L != 2) continue; // 16-bit codes at 2 sub-tiles
+                                // (SWAR codes take their own sub-tiles in batches)
+                                if ((stg == STAGE_BYTES || stg == STAGE_HALVES || stg == STAGE_T10) && L != 2) continue;
                                 LaunchCfg c;
                                 c.L = L;
                                 c.W = W;

@@ -137,20 +137,16 @@ def test_batch_byte_codes(ctx, tiles):
         assert (L, W, P) == (tiles, 8, 128)
         for q, (m, _, include, _, _) in enumerate(jobs):
             k = mats.index(m)
-            # byte codes (four tiles only) on the 64- and 100-column matrices
-            # (the latter has missing cells, so exclude mode takes the FP16
-            # codes there; include mode has FP16 codes only with the fill
-            # copy kept, so it takes the FP32 tile); 16-bit codes on the
-            # 230-column one at two tiles (at four, exclude mode takes the
-            # FP16 codes and include mode, whose FP32 tile does not fit,
-            # direct reads)
+            # SWAR codes take their own number of sub-tiles whatever the
+            # batch's: byte codes on the 64- and 100-column matrices (the
+            # latter has missing cells, so exclude mode takes its FP16 codes
+            # there, at the batch's tiles); 10-bit codes on the 230-column one
             if k == 2:
-                expect = (ebic.STAGE_HALVES if tiles == 2 else
-                          ebic.STAGE_DIRECT if include else ebic.STAGE_CODES)
-            elif tiles == 4 and (k == 0 or include):
+                expect = ebic.STAGE_T10
+            elif k == 0 or include:
                 expect = ebic.STAGE_BYTES
             else:
-                expect = ebic.STAGE_LDS if include else ebic.STAGE_CODES
+                expect = ebic.STAGE_CODES
             assert stagings[q] == expect, (q, k, include, stagings[q])
     finally:
         ctx.set_launch_shape()

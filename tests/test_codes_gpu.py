@@ -1,7 +1,8 @@
 """Which rank-code sets a resident matrix holds: the upload builds the SWAR
-codes its default plan stages (bytes up to 128 columns, 16-bit codes up to
-384), plus the FP16 codes exclude mode needs when cells are missing; other
-FP16 code sets are built on first use, and results stay bit-exact."""
+codes its default plan stages (bytes up to 128 columns, 10-bit codes up to
+512), plus the FP16 codes exclude mode needs when cells are missing; the
+other code sets (FP16, 16-bit) are built on first use, and results stay
+bit-exact."""
 import numpy as np
 import pytest
 
@@ -19,7 +20,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("cols,swar", [(64, 8), (200, 16), (400, 0)])
+@pytest.mark.parametrize("cols,swar", [(64, 8), (200, 10), (400, 10), (600, 0)])
 def test_upload_builds_only_what_the_plan_stages(ctx, cols, swar):
     from paper_1807_09932_amd import ebic
     rows = 5_000
@@ -29,13 +30,35 @@ def test_upload_builds_only_what_the_plan_stages(ctx, cols, swar):
     st = ctx.stats(mat)
     ld = (rows + 63) // 64 * 64
     assert st["value_bytes"] == ld * cols * 4
-    want_sets = {8: ebic.SET_U8, 16: ebic.SET_U16, 0: 0}[swar]
+    want_sets = {8: ebic.SET_U8, 10: ebic.SET_U10, 0: 0}[swar]
     assert st["code_sets"] == want_sets, st
     assert st["has_missing"] == (0 if swar else -1)
     if swar == 8:
         ldb = (rows + 511) // 512 * 512
         assert st["code_bytes"] == ldb * cols + 256 + 4 * (ldb // 512)
+    if swar == 10:
+        groups = (rows + 191) // 192
+        assert st["code_bytes"] == groups * 256 * cols + 256 + 4 * groups
+        assert st["swar_chunks"] == groups
     ctx.release(mat)
+
+
+def test_16bit_codes_built_on_first_use(ctx):
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(5)
+    X = np.round(rng.standard_normal((3_001, 200)), 1).astype(np.float32)
+    offs, cols = gen.csr([rng.permutation(200)[: int(rng.integers(1, 25))].astype(np.int32) for _ in range(90)])
+    mat = ctx.upload(X)
+    assert not ctx.stats(mat)["code_sets"] & ebic.SET_U16
+    ctx.set_launch_shape(2, 8, 64, ebic.STAGE_HALVES, 0)
+    try:
+        assert ebic.ebic_plan_shape(ctx.handle, mat, 90)[3] == ebic.STAGE_HALVES
+        got = gpu_eval(ctx, mat, offs, cols)
+        assert_same(got, oracle_eval(X, offs, cols), "16-bit codes on first use")
+        assert ctx.stats(mat)["code_sets"] & ebic.SET_U16
+    finally:
+        ctx.set_launch_shape()
+        ctx.release(mat)
 
 
 def test_codes_built_on_first_use_and_exact(ctx):

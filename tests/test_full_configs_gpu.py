@@ -41,7 +41,7 @@ def test_batched_all_64_populations(ctx):
     outs = [ctx.outputs(mat, p.n, masks=q in with_masks) for q, p in enumerate(dev)]
     reqs = [ctx.request(mat, p, o) for p, o in zip(dev, outs)]
     L, W, P, stagings, _ = ebic.ebic_plan_batch_shape(ctx.handle, reqs)
-    assert (L, W, P) == (2, 16, 1024) and set(stagings) == {ebic.STAGE_HALVES}
+    assert (L, W, P) == (2, 16, 1024) and set(stagings) == {ebic.STAGE_T10}
     announce("batched 64 populations", sum(p.n for p in dev))
     ctx.eval_batch(reqs)
     torch.cuda.synchronize()
@@ -96,8 +96,9 @@ def test_methylation_include_mode_full(ctx):
     ctx.release(mat)
 
 
-@pytest.mark.parametrize("shape", [None, (2, 16, 400, 4)], ids=["default", "bench-autotuned"])
-def test_methylation_wide_full(ctx, shape):
+@pytest.mark.parametrize("shape,staging", [(None, 5), ((3, 16, 400, 5), 5), ((2, 16, 400, 4), 4)],
+                         ids=["default", "10-bit-P400", "16-bit"])
+def test_methylation_wide_full(ctx, shape, staging):
     from paper_1807_09932_amd import ebic
     w, pop = gen.methylation_wide()
     offs, cols = gen.csr(pop)
@@ -106,7 +107,7 @@ def test_methylation_wide_full(ctx, shape):
         if shape:
             ctx.set_launch_shape(*shape, 0)
         plan = ebic.ebic_plan_shape(ctx.handle, mat, offs.size - 1)
-        assert plan[3] == ebic.STAGE_HALVES
+        assert plan[3] == staging
         announce("methylation 436444x310", plan)
         got = gpu_eval(ctx, mat, offs, cols, negative=True, masks=True)
         want = oracle_eval(w.X, offs, cols, negative=True, masks=True)
