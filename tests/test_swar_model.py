@@ -1,9 +1,10 @@
-"""A CPU model of the SWAR rank-code arithmetic that the byte and 16-bit
-evaluation sequences run, checked against the oracle (no GPU).
+"""A CPU model of the SWAR rank-code arithmetic that the byte, 10-bit and
+16-bit evaluation sequences run, checked against the oracle (no GPU).
 
 The model restates, word by word in uint32 arithmetic, what the sequences
 compute on rank codes (per row, the number of cells of the row that are
-strictly smaller; codes below 2^(BITS-1), several rows per 32-bit word):
+strictly smaller; codes below 2^(BITS-1), 32 // BITS rows per 32-bit word,
+the 10-bit fields leaving bits 30-31 unused):
 
 * the first pair: D = (t1 | H) - t0 and E = (t0 | H) - t1, whose part top
   bits say t1 >= t0 and t0 >= t1 (no borrow crosses a part);
@@ -137,9 +138,10 @@ def _individuals(rng, cols, n):
     return inds
 
 
-@pytest.mark.parametrize("bits,cols", [(8, 64), (8, 128), (16, 200), (16, 310)])
+@pytest.mark.parametrize("bits,cols", [(8, 64), (8, 128), (16, 200), (16, 310), (10, 200), (10, 310),
+                                       (10, 512)])
 def test_tie_free_variant_needs_the_leading_run_dropped(bits, cols):
-    rows = 700 if bits == 8 else 350
+    rows = 700 if bits == 8 else 351
     X = _tie_free_matrix(rows, cols, 40 + cols)
     codes = rank_codes(X)
     assert int(codes.max()) < 2 ** (bits - 1)
@@ -170,6 +172,6 @@ def test_model_agrees_on_ties():
     from paper_1807_09932_amd import gen
     offs, cc = gen.csr([np.asarray(i, np.int32) for i in inds])
     om, on, _, _ = oracle.eval_population(X, offs, cc, negative=True)
-    for bits in (8, 16):
+    for bits in (8, 10, 16):
         for i, ind in enumerate(inds):
             assert swar_eval(codes, ind, bits, ties=True) == (int(om[i]), int(on[i])), (bits, ind)
