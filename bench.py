@@ -80,10 +80,10 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(launch_units):
+def traffic_from_profile(launch_units, name="k_eval_methylation_436444x64_traffic.json"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_eval_methylation_436444x64_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -234,9 +234,13 @@ def bench_batched(ctx, args):
     rows = w.X.shape[0]
     checks = sum(gen.nominal_checks(rows, o) for o, _ in packed)
     n_total = sum(p.n for p in dev)
-    log("batched: autotuning plain and batched shapes")
-    ctx.set_launch_shape(0, 0, 0, ebic.STAGE_LDS, 0)
-    ctx.autotune(reqs)
+    if args.batch_shape:
+        # a forced launch shape (profiling runs: no autotuning launches)
+        ctx.set_launch_shape(*[int(x) for x in args.batch_shape.split(",")], 0)
+    else:
+        log("batched: autotuning plain and batched shapes")
+        ctx.set_launch_shape(0, 0, 0, ebic.STAGE_LDS, 0)
+        ctx.autotune(reqs)
     stream = torch.cuda.current_stream()
 
     def batched():
@@ -284,6 +288,7 @@ def bench_batched(ctx, args):
     ebic.ebic_set_profiling(ctx.handle, 0)
     g_ms = l_ms / max(1, n_l)
     bL, bW, bP, b_stg, b_grid = ebic.ebic_plan_batch_shape(ctx.handle, reqs)
+    ctx.set_launch_shape()
     upload = upload_report(ctx, mat)
     ctx.release(mat)
     return {
@@ -298,7 +303,11 @@ def bench_batched(ctx, args):
         "executed_compares": b_steps,
         "launch_shape": "L=%d W=%d P=%d stagings=%s blocks=%d" % (bL, bW, bP, sorted(set(b_stg)),
                                                                   b_grid),
-        "roofline": alu_roofline(b_steps, g_ms, b_stg[0] if len(set(b_stg)) == 1 else None),
+        "roofline": {**alu_roofline(b_steps, g_ms, b_stg[0] if len(set(b_stg)) == 1 else None),
+                     "traffic": traffic_from_profile(1, "k_eval_batch_100000x256_traffic.json"),
+                     "traffic_note": "HBM bytes per launch of the persistent kernel (committed FETCH_SIZE / "
+                                     "WRITE_SIZE summary): each staged chunk is read once per group of P "
+                                     "individuals of each population, mostly from the Infinity Cache"},
         "timing": "median of %d synchronised calls; batched = one ebic_eval_batch (descriptor "
                   "copy + graph replay), plain = 64 ebic_eval_population calls" % reps,
         "upload": upload,
@@ -455,7 +464,8 @@ def bench_paper_shape(ctx, args):
             "roofline_views": roofline_views(steps, k_ms, stg, w.X.nbytes, p.n),
             "launch_shape": f"{how}: L={L} W={W} P={P} staging={stg} blocks={blocks}",
             "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
-            "roofline": alu_roofline(steps, k_ms, stg),
+            "roofline": {**alu_roofline(steps, k_ms, stg),
+                         "traffic": traffic_from_profile(1, "k_eval_methylation_wide_436444x310_traffic.json")},
             "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9}
 
 
@@ -661,6 +671,9 @@ def main():
     ap.add_argument("--rows", type=int, default=436444, help="(testing only) smaller matrix")
     ap.add_argument("--paper-shape", type=str, default="",
                     help="L,W,P,staging for the 'paper' extra instead of autotuning it")
+    ap.add_argument("--batch-shape", type=str, default="",
+                    help="L,W,P,staging for the 'batch' extra (both its batched and plain launches) "
+                         "instead of autotuning it")
     ap.add_argument("--shape", type=str, default="",
                     help="force the launch shape 'L,W,P[,S]' (64-row tiles per wave, waves per "
                          "block, individuals per group, staging: 0 FP32 tile, 1 direct, "

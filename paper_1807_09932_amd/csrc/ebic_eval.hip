@@ -1701,8 +1701,67 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         constexpr bool MASKS = decltype(masks_tag)::value;
         constexpr bool TIES = decltype(ties_tag)::value;  // (SWAR chunks only)
         // One individual (header hv) on the staged chunk.
+        // Lane 0 adds an individual's two counts to the block's LDS
+        // accumulators; no result is returned, so nothing waits for it.
+        auto add_counts = [&](int32_t ii, int32_t pm, int32_t pg) {
+            if (pm | pg) {
+                uint64_t save;
+                uint32_t va, vm, vg;
+                if constexpr (c16) {
+                    const uint32_t a = lds_addr(cnt + ii);
+                    const uint32_t both = (uint32_t)pm | ((uint32_t)pg << 16);
+                    asm volatile(
+                        "s_mov_b64 %[save], exec\n\t"
+                        "s_mov_b64 exec, 1\n\t"
+                        "v_mov_b32 %[va], %[a]\n\t"
+                        "v_mov_b32 %[vm], %[both]\n\t"
+                        "ds_add_u32 %[va], %[vm]\n\t"
+                        "s_mov_b64 exec, %[save]"
+                        : [save] "=&s"(save), [va] "=&v"(va), [vm] "=&v"(vm)
+                        : [a] "s"(a), [both] "s"(both)
+                        : "memory");
+                } else {
+                    const uint32_t a = lds_addr(cnt + 2 * ii);
+                    asm volatile(
+                        "s_mov_b64 %[save], exec\n\t"
+                        "s_mov_b64 exec, 1\n\t"
+                        "v_mov_b32 %[va], %[a]\n\t"
+                        "v_mov_b32 %[vm], %[pm]\n\t"
+                        "v_mov_b32 %[vg], %[pg]\n\t"
+                        "ds_add_u32 %[va], %[vm]\n\t"
+                        "ds_add_u32 %[va], %[vg] offset:4\n\t"
+                        "s_mov_b64 exec, %[save]"
+                        : [save] "=&s"(save), [va] "=&v"(va), [vm] "=&v"(vm), [vg] "=&v"(vg)
+                        : [a] "s"(a), [pm] "s"(pm), [pg] "s"(pg)
+                        : "memory");
+                }
+            }
+        };
         auto one = [&](const int4 (&hv)[3], int32_t ii) {
             const int32_t k = hv[0].x;
+            if constexpr (kSwar && !MASKS) {
+                // Counts only: the match words' parts are counted as they
+                // are made (no masks exist on this path).
+                if (k == 0) return;
+                const auto *tl = reinterpret_cast<const unsigned char *>(tile);
+                uint32_t mw[2] = {0, 0}, gw[2] = {0, 0};
+                bool any;
+                if constexpr (NWORDS == 2)
+                    any = eval_swar2<BITS, NEG, COUNT, TIES>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2], lane,
+                                                             hvalid[0], hvalid[NWORDS - 1], mw, gw, steps);
+                else
+                    any = eval_bytes<8, NEG, COUNT, BITS, TIES>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2],
+                                                                lane, hvalid[0], mw[0], gw[0], steps);
+                if (!any) return;
+                int32_t pm = 0, pg = 0;
+#pragma unroll
+                for (int h = 0; h < NWORDS; ++h) {
+                    pm += lane_popc<BITS>(mw[h]);
+                    if constexpr (NEG) pg += lane_popc<BITS>(gw[h]);
+                }
+                add_counts(ii, pm, pg);
+                return;
+            }
             uint64_t M[L], G[L];
             if (k == 0) {
 #pragma unroll
@@ -1778,40 +1837,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                         pg += __popcll(G[s]);
                     }
                 }
-                if (pm | pg) {
-                    // Lane 0 adds both counts to the block's LDS accumulators;
-                    // no result is returned, so nothing waits for it.
-                    uint64_t save;
-                    uint32_t va, vm, vg;
-                    if constexpr (c16) {
-                        const uint32_t a = lds_addr(cnt + ii);
-                        const uint32_t both = (uint32_t)pm | ((uint32_t)pg << 16);
-                        asm volatile(
-                            "s_mov_b64 %[save], exec\n\t"
-                            "s_mov_b64 exec, 1\n\t"
-                            "v_mov_b32 %[va], %[a]\n\t"
-                            "v_mov_b32 %[vm], %[both]\n\t"
-                            "ds_add_u32 %[va], %[vm]\n\t"
-                            "s_mov_b64 exec, %[save]"
-                            : [save] "=&s"(save), [va] "=&v"(va), [vm] "=&v"(vm)
-                            : [a] "s"(a), [both] "s"(both)
-                            : "memory");
-                    } else {
-                        const uint32_t a = lds_addr(cnt + 2 * ii);
-                        asm volatile(
-                            "s_mov_b64 %[save], exec\n\t"
-                            "s_mov_b64 exec, 1\n\t"
-                            "v_mov_b32 %[va], %[a]\n\t"
-                            "v_mov_b32 %[vm], %[pm]\n\t"
-                            "v_mov_b32 %[vg], %[pg]\n\t"
-                            "ds_add_u32 %[va], %[vm]\n\t"
-                            "ds_add_u32 %[va], %[vg] offset:4\n\t"
-                            "s_mov_b64 exec, %[save]"
-                            : [save] "=&s"(save), [va] "=&v"(va), [vm] "=&v"(vm), [vg] "=&v"(vg)
-                            : [a] "s"(a), [pm] "s"(pm), [pg] "s"(pg)
-                            : "memory");
-                    }
-                }
+                add_counts(ii, pm, pg);
             }
             if constexpr (MASKS) {
                 const int64_t i = i0 + ii;
