@@ -948,7 +948,7 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
 // skip the tie detection and the tie chain.
 // ---------------------------------------------------------------------------
 #define B2_LOAD(t, w)                                                          \
-    "v_lshl_add_u32 %[ad], %[" w "], 9, %[base]\n\t"                           \
+    "v_lshl_add_u32 %[ad], %[" w "], %[sh2], %[base]\n\t"                      \
     "ds_read_b32 %[" t "a], %[ad]\n\t"                                         \
     "ds_read_b32 %[" t "b], %[ad] offset:256\n\t"
 #define B2_PAIR(ta, tb, FMA, FMB, NFA, NFB, AOA, AOB, AIA, AIB)                \
@@ -997,7 +997,8 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
 #define B2_COLS                                                                \
     [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), \
         [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last), \
-        [hp] "s"(T::H + 1u), [H] "i"(T::H), [TWO] "i"(T::TWO), [SHF] "i"(T::SHF), [MIR] "i"(T::MIR)
+        [hp] "s"(T::H + 1u), [H] "i"(T::H), [TWO] "i"(T::TWO), [SHF] "i"(T::SHF), [MIR] "i"(T::MIR), \
+        [sh2] "i"(SH)
 // First pair of a word (X = a or b); the two words' operations alternate.
 // D: top bit of a part where t1 >= t0; E: where t0 >= t1 (tie test only).
 #define B2_F1(X) "v_or_b32_e32 %[D" X "], %[H], %[t1" X "]\n\t"
@@ -1020,7 +1021,10 @@ __device__ __forceinline__ void by_pos(uint32_t base, const int32_t (&w)[kWin], 
 // Both chains on both words through column min(last, 7); outputs per word
 // as in by_neg (tied = 0 without TIES). Waits count LDS operations; the
 // sequence starts and ends with lgkmcnt(0).
-template <int BITS, bool TIES>
+// SH: log2 of the bytes one staged column occupies (9: the two words of a
+// 512-byte column; 10: a pair of words of a 1024-byte column, the second
+// pair at base + 512).
+template <int BITS, bool TIES, int SH = 9>
 __device__ __forceinline__ void by2_neg(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hva,
                                         uint32_t hvb, uint32_t &alivea, uint32_t &aliveb, uint32_t &falla,
                                         uint32_t &fallb, uint32_t &tieda, uint32_t &tiedb)
@@ -1092,7 +1096,7 @@ __device__ __forceinline__ void by2_neg(uint32_t base, const int32_t (&w)[kWin],
 }
 
 // The >= chain alone on both words (fm = 0, nf = ~0).
-template <int BITS>
+template <int BITS, int SH = 9>
 __device__ __forceinline__ void by2_pos(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t hva,
                                         uint32_t hvb, uint32_t &alivea, uint32_t &aliveb)
 {
@@ -1141,6 +1145,380 @@ __device__ __forceinline__ void by2_pos(uint32_t base, const int32_t (&w)[kWin],
 #undef B2_AB
 #undef B2_FIRST_TIES
 #undef B2_FIRST_NOTIES
+
+// ---------------------------------------------------------------------------
+// Four lane words per chunk: byte codes in 1024-row chunks (four 256-row
+// groups; a staged column is 1024 bytes, word h at +256 h). All four words'
+// chains run in one instruction stream, each operation issued for the four
+// words in turn, with the arithmetic and the reference q of the two-word
+// sequences; one header, one set of column addresses and one set of exit
+// tests serve 1024 rows. These sequences take chunks whose rows are all in
+// range and hold no two equal values in a row (the top bits of every part
+// start set: Hs); other chunks run the two-word sequences on each pair of
+// words.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void by4_neg_full(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t (&alive)[4], uint32_t (&fall)[4])
+{
+    uint32_t t0a, t0b, t0c, t0d, t1a, t1b, t1c, t1d, ad, Da, Db, Dc, Dd, Ea, Eb, Ec, Ed, qa, qb, qc, qd, fma, fmb, fmc, fmd, nfa, nfb, nfc, nfd;
+    uint64_t tmp;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_lshl_add_u32 %[ad], %[w0], 10, %[base]\n\t"
+        "ds_read_b32 %[t0a], %[ad]\n\t"
+        "ds_read_b32 %[t0b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t0c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t0d], %[ad] offset:768\n\t"
+        "v_lshl_add_u32 %[ad], %[w1], 10, %[base]\n\t"
+        "ds_read_b32 %[t1a], %[ad]\n\t"
+        "ds_read_b32 %[t1b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t1c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t1d], %[ad] offset:768\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_or_b32_e32 %[Da], %[Hs], %[t1a]\n\t"
+        "v_or_b32_e32 %[Db], %[Hs], %[t1b]\n\t"
+        "v_or_b32_e32 %[Dc], %[Hs], %[t1c]\n\t"
+        "v_or_b32_e32 %[Dd], %[Hs], %[t1d]\n\t"
+        "v_sub_u32_e32 %[Da], %[Da], %[t0a]\n\t"
+        "v_sub_u32_e32 %[Db], %[Db], %[t0b]\n\t"
+        "v_sub_u32_e32 %[Dc], %[Dc], %[t0c]\n\t"
+        "v_sub_u32_e32 %[Dd], %[Dd], %[t0d]\n\t"
+        "v_bfi_b32 %[falla], %[Da], 0, %[Hs]\n\t"
+        "v_bfi_b32 %[fallb], %[Db], 0, %[Hs]\n\t"
+        "v_bfi_b32 %[fallc], %[Dc], 0, %[Hs]\n\t"
+        "v_bfi_b32 %[falld], %[Dd], 0, %[Hs]\n\t"
+        "v_lshrrev_b32_e32 %[Ea], 7, %[falla]\n\t"
+        "v_lshrrev_b32_e32 %[Eb], 7, %[fallb]\n\t"
+        "v_lshrrev_b32_e32 %[Ec], 7, %[fallc]\n\t"
+        "v_lshrrev_b32_e32 %[Ed], 7, %[falld]\n\t"
+        "v_sub_u32_e32 %[fma], %[falla], %[Ea]\n\t"
+        "v_sub_u32_e32 %[fmb], %[fallb], %[Eb]\n\t"
+        "v_sub_u32_e32 %[fmc], %[fallc], %[Ec]\n\t"
+        "v_sub_u32_e32 %[fmd], %[falld], %[Ed]\n\t"
+        "v_not_b32_e32 %[nfa], %[fma]\n\t"
+        "v_not_b32_e32 %[nfb], %[fmb]\n\t"
+        "v_not_b32_e32 %[nfc], %[fmc]\n\t"
+        "v_not_b32_e32 %[nfd], %[fmd]\n\t"
+        "v_xad_u32 %[qa], %[t1a], %[nfa], %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t1b], %[nfb], %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t1c], %[nfc], %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t1d], %[nfd], %[hp]\n\t"
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 6f\n\t"
+        "v_lshl_add_u32 %[ad], %[w2], 10, %[base]\n\t"
+        "ds_read_b32 %[t0a], %[ad]\n\t"
+        "ds_read_b32 %[t0b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t0c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t0d], %[ad] offset:768\n\t"
+        "v_lshl_add_u32 %[ad], %[w3], 10, %[base]\n\t"
+        "ds_read_b32 %[t1a], %[ad]\n\t"
+        "ds_read_b32 %[t1b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t1c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t1d], %[ad] offset:768\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_xad_u32 %[Da], %[t0a], %[fma], %[qa]\n\t"
+        "v_xad_u32 %[Db], %[t0b], %[fmb], %[qb]\n\t"
+        "v_xad_u32 %[Dc], %[t0c], %[fmc], %[qc]\n\t"
+        "v_xad_u32 %[Dd], %[t0d], %[fmd], %[qd]\n\t"
+        "v_xad_u32 %[qa], %[t0a], %[nfa], %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t0b], %[nfb], %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t0c], %[nfc], %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t0d], %[nfd], %[hp]\n\t"
+        "v_xad_u32 %[Ea], %[t1a], %[fma], %[qa]\n\t"
+        "v_xad_u32 %[Eb], %[t1b], %[fmb], %[qb]\n\t"
+        "v_xad_u32 %[Ec], %[t1c], %[fmc], %[qc]\n\t"
+        "v_xad_u32 %[Ed], %[t1d], %[fmd], %[qd]\n\t"
+        "v_xad_u32 %[qa], %[t1a], %[nfa], %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t1b], %[nfb], %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t1c], %[nfc], %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t1d], %[nfd], %[hp]\n\t"
+        "v_bitop3_b32 %[alivea], %[Hs], %[Da], %[Ea] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[aliveb], %[Hs], %[Db], %[Eb] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alivec], %[Hs], %[Dc], %[Ec] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alived], %[Hs], %[Dd], %[Ed] bitop3:0x80\n\t"
+        "s_cmp_le_i32 %[last], 3\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        "v_lshl_add_u32 %[ad], %[w4], 10, %[base]\n\t"
+        "ds_read_b32 %[t0a], %[ad]\n\t"
+        "ds_read_b32 %[t0b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t0c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t0d], %[ad] offset:768\n\t"
+        "v_lshl_add_u32 %[ad], %[w5], 10, %[base]\n\t"
+        "ds_read_b32 %[t1a], %[ad]\n\t"
+        "ds_read_b32 %[t1b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t1c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t1d], %[ad] offset:768\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_xad_u32 %[Da], %[t0a], %[fma], %[qa]\n\t"
+        "v_xad_u32 %[Db], %[t0b], %[fmb], %[qb]\n\t"
+        "v_xad_u32 %[Dc], %[t0c], %[fmc], %[qc]\n\t"
+        "v_xad_u32 %[Dd], %[t0d], %[fmd], %[qd]\n\t"
+        "v_xad_u32 %[qa], %[t0a], %[nfa], %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t0b], %[nfb], %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t0c], %[nfc], %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t0d], %[nfd], %[hp]\n\t"
+        "v_xad_u32 %[Ea], %[t1a], %[fma], %[qa]\n\t"
+        "v_xad_u32 %[Eb], %[t1b], %[fmb], %[qb]\n\t"
+        "v_xad_u32 %[Ec], %[t1c], %[fmc], %[qc]\n\t"
+        "v_xad_u32 %[Ed], %[t1d], %[fmd], %[qd]\n\t"
+        "v_xad_u32 %[qa], %[t1a], %[nfa], %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t1b], %[nfb], %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t1c], %[nfc], %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t1d], %[nfd], %[hp]\n\t"
+        "v_bitop3_b32 %[alivea], %[alivea], %[Da], %[Ea] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[aliveb], %[aliveb], %[Db], %[Eb] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alivec], %[alivec], %[Dc], %[Ec] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alived], %[alived], %[Dd], %[Ed] bitop3:0x80\n\t"
+        "v_or3_b32 %[Da], %[alivea], %[aliveb], %[alivec]\n\t"
+        "v_or_b32_e32 %[Da], %[Da], %[alived]\n\t"
+        "v_cmp_ne_u32_e64 %[tmp], 0, %[Da]\n\t"
+        "s_cmp_lg_u64 %[tmp], 0\n\t"
+        "s_cbranch_scc0 2f\n\t"
+        "s_cmp_le_i32 %[last], 5\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        "v_lshl_add_u32 %[ad], %[w6], 10, %[base]\n\t"
+        "ds_read_b32 %[t0a], %[ad]\n\t"
+        "ds_read_b32 %[t0b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t0c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t0d], %[ad] offset:768\n\t"
+        "v_lshl_add_u32 %[ad], %[w7], 10, %[base]\n\t"
+        "ds_read_b32 %[t1a], %[ad]\n\t"
+        "ds_read_b32 %[t1b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t1c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t1d], %[ad] offset:768\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_xad_u32 %[Da], %[t0a], %[fma], %[qa]\n\t"
+        "v_xad_u32 %[Db], %[t0b], %[fmb], %[qb]\n\t"
+        "v_xad_u32 %[Dc], %[t0c], %[fmc], %[qc]\n\t"
+        "v_xad_u32 %[Dd], %[t0d], %[fmd], %[qd]\n\t"
+        "v_xad_u32 %[qa], %[t0a], %[nfa], %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t0b], %[nfb], %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t0c], %[nfc], %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t0d], %[nfd], %[hp]\n\t"
+        "v_xad_u32 %[Ea], %[t1a], %[fma], %[qa]\n\t"
+        "v_xad_u32 %[Eb], %[t1b], %[fmb], %[qb]\n\t"
+        "v_xad_u32 %[Ec], %[t1c], %[fmc], %[qc]\n\t"
+        "v_xad_u32 %[Ed], %[t1d], %[fmd], %[qd]\n\t"
+        "v_bitop3_b32 %[alivea], %[alivea], %[Da], %[Ea] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[aliveb], %[aliveb], %[Db], %[Eb] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alivec], %[alivec], %[Dc], %[Ec] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alived], %[alived], %[Dd], %[Ed] bitop3:0x80\n\t"
+        "2:\n\t"
+        "s_branch 5f\n\t"
+        "6:\n\t"
+        "v_mov_b32_e32 %[alivea], %[Hs]\n\t"
+        "v_mov_b32_e32 %[aliveb], %[Hs]\n\t"
+        "v_mov_b32_e32 %[alivec], %[Hs]\n\t"
+        "v_mov_b32_e32 %[alived], %[Hs]\n\t"
+        "5:"
+        : [t0a] "=&v"(t0a),
+          [t0b] "=&v"(t0b),
+          [t0c] "=&v"(t0c),
+          [t0d] "=&v"(t0d),
+          [t1a] "=&v"(t1a),
+          [t1b] "=&v"(t1b),
+          [t1c] "=&v"(t1c),
+          [t1d] "=&v"(t1d),
+          [ad] "=&v"(ad),
+          [Da] "=&v"(Da),
+          [Db] "=&v"(Db),
+          [Dc] "=&v"(Dc),
+          [Dd] "=&v"(Dd),
+          [Ea] "=&v"(Ea),
+          [Eb] "=&v"(Eb),
+          [Ec] "=&v"(Ec),
+          [Ed] "=&v"(Ed),
+          [qa] "=&v"(qa),
+          [qb] "=&v"(qb),
+          [qc] "=&v"(qc),
+          [qd] "=&v"(qd),
+          [fma] "=&v"(fma),
+          [fmb] "=&v"(fmb),
+          [fmc] "=&v"(fmc),
+          [fmd] "=&v"(fmd),
+          [nfa] "=&v"(nfa),
+          [nfb] "=&v"(nfb),
+          [nfc] "=&v"(nfc),
+          [nfd] "=&v"(nfd),
+          [falla] "=&v"(fall[0]),
+          [fallb] "=&v"(fall[1]),
+          [fallc] "=&v"(fall[2]),
+          [falld] "=&v"(fall[3]),
+          [alivea] "=&v"(alive[0]),
+          [aliveb] "=&v"(alive[1]),
+          [alivec] "=&v"(alive[2]),
+          [alived] "=&v"(alive[3]),
+          [tmp] "=&s"(tmp)
+        : [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last), [Hs] "s"(0x80808080u), [hp] "s"(0x80808081u)
+        : "scc", "memory");
+}
+
+__device__ __forceinline__ void by4_pos_full(uint32_t base, const int32_t (&w)[kWin], int32_t last, uint32_t (&alive)[4])
+{
+    uint32_t t0a, t0b, t0c, t0d, t1a, t1b, t1c, t1d, ad, Da, Db, Dc, Dd, Ea, Eb, Ec, Ed, qa, qb, qc, qd;
+    uint64_t tmp;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_lshl_add_u32 %[ad], %[w0], 10, %[base]\n\t"
+        "ds_read_b32 %[t0a], %[ad]\n\t"
+        "ds_read_b32 %[t0b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t0c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t0d], %[ad] offset:768\n\t"
+        "v_lshl_add_u32 %[ad], %[w1], 10, %[base]\n\t"
+        "ds_read_b32 %[t1a], %[ad]\n\t"
+        "ds_read_b32 %[t1b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t1c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t1d], %[ad] offset:768\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_or_b32_e32 %[Da], %[Hs], %[t1a]\n\t"
+        "v_or_b32_e32 %[Db], %[Hs], %[t1b]\n\t"
+        "v_or_b32_e32 %[Dc], %[Hs], %[t1c]\n\t"
+        "v_or_b32_e32 %[Dd], %[Hs], %[t1d]\n\t"
+        "v_sub_u32_e32 %[Da], %[Da], %[t0a]\n\t"
+        "v_sub_u32_e32 %[Db], %[Db], %[t0b]\n\t"
+        "v_sub_u32_e32 %[Dc], %[Dc], %[t0c]\n\t"
+        "v_sub_u32_e32 %[Dd], %[Dd], %[t0d]\n\t"
+        "v_and_b32_e32 %[alivea], %[Hs], %[Da]\n\t"
+        "v_and_b32_e32 %[aliveb], %[Hs], %[Db]\n\t"
+        "v_and_b32_e32 %[alivec], %[Hs], %[Dc]\n\t"
+        "v_and_b32_e32 %[alived], %[Hs], %[Dd]\n\t"
+        "v_xad_u32 %[qa], %[t1a], -1, %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t1b], -1, %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t1c], -1, %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t1d], -1, %[hp]\n\t"
+        "s_cmp_lt_i32 %[last], 2\n\t"
+        "s_cbranch_scc1 6f\n\t"
+        "v_lshl_add_u32 %[ad], %[w2], 10, %[base]\n\t"
+        "ds_read_b32 %[t0a], %[ad]\n\t"
+        "ds_read_b32 %[t0b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t0c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t0d], %[ad] offset:768\n\t"
+        "v_lshl_add_u32 %[ad], %[w3], 10, %[base]\n\t"
+        "ds_read_b32 %[t1a], %[ad]\n\t"
+        "ds_read_b32 %[t1b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t1c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t1d], %[ad] offset:768\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_xad_u32 %[Da], %[t0a], 0, %[qa]\n\t"
+        "v_xad_u32 %[Db], %[t0b], 0, %[qb]\n\t"
+        "v_xad_u32 %[Dc], %[t0c], 0, %[qc]\n\t"
+        "v_xad_u32 %[Dd], %[t0d], 0, %[qd]\n\t"
+        "v_xad_u32 %[qa], %[t0a], -1, %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t0b], -1, %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t0c], -1, %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t0d], -1, %[hp]\n\t"
+        "v_xad_u32 %[Ea], %[t1a], 0, %[qa]\n\t"
+        "v_xad_u32 %[Eb], %[t1b], 0, %[qb]\n\t"
+        "v_xad_u32 %[Ec], %[t1c], 0, %[qc]\n\t"
+        "v_xad_u32 %[Ed], %[t1d], 0, %[qd]\n\t"
+        "v_xad_u32 %[qa], %[t1a], -1, %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t1b], -1, %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t1c], -1, %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t1d], -1, %[hp]\n\t"
+        "v_bitop3_b32 %[alivea], %[alivea], %[Da], %[Ea] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[aliveb], %[aliveb], %[Db], %[Eb] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alivec], %[alivec], %[Dc], %[Ec] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alived], %[alived], %[Dd], %[Ed] bitop3:0x80\n\t"
+        "s_cmp_le_i32 %[last], 3\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        "v_lshl_add_u32 %[ad], %[w4], 10, %[base]\n\t"
+        "ds_read_b32 %[t0a], %[ad]\n\t"
+        "ds_read_b32 %[t0b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t0c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t0d], %[ad] offset:768\n\t"
+        "v_lshl_add_u32 %[ad], %[w5], 10, %[base]\n\t"
+        "ds_read_b32 %[t1a], %[ad]\n\t"
+        "ds_read_b32 %[t1b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t1c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t1d], %[ad] offset:768\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_xad_u32 %[Da], %[t0a], 0, %[qa]\n\t"
+        "v_xad_u32 %[Db], %[t0b], 0, %[qb]\n\t"
+        "v_xad_u32 %[Dc], %[t0c], 0, %[qc]\n\t"
+        "v_xad_u32 %[Dd], %[t0d], 0, %[qd]\n\t"
+        "v_xad_u32 %[qa], %[t0a], -1, %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t0b], -1, %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t0c], -1, %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t0d], -1, %[hp]\n\t"
+        "v_xad_u32 %[Ea], %[t1a], 0, %[qa]\n\t"
+        "v_xad_u32 %[Eb], %[t1b], 0, %[qb]\n\t"
+        "v_xad_u32 %[Ec], %[t1c], 0, %[qc]\n\t"
+        "v_xad_u32 %[Ed], %[t1d], 0, %[qd]\n\t"
+        "v_xad_u32 %[qa], %[t1a], -1, %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t1b], -1, %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t1c], -1, %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t1d], -1, %[hp]\n\t"
+        "v_bitop3_b32 %[alivea], %[alivea], %[Da], %[Ea] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[aliveb], %[aliveb], %[Db], %[Eb] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alivec], %[alivec], %[Dc], %[Ec] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alived], %[alived], %[Dd], %[Ed] bitop3:0x80\n\t"
+        "v_or3_b32 %[Da], %[alivea], %[aliveb], %[alivec]\n\t"
+        "v_or_b32_e32 %[Da], %[Da], %[alived]\n\t"
+        "v_cmp_ne_u32_e64 %[tmp], 0, %[Da]\n\t"
+        "s_cmp_lg_u64 %[tmp], 0\n\t"
+        "s_cbranch_scc0 2f\n\t"
+        "s_cmp_le_i32 %[last], 5\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        "v_lshl_add_u32 %[ad], %[w6], 10, %[base]\n\t"
+        "ds_read_b32 %[t0a], %[ad]\n\t"
+        "ds_read_b32 %[t0b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t0c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t0d], %[ad] offset:768\n\t"
+        "v_lshl_add_u32 %[ad], %[w7], 10, %[base]\n\t"
+        "ds_read_b32 %[t1a], %[ad]\n\t"
+        "ds_read_b32 %[t1b], %[ad] offset:256\n\t"
+        "ds_read_b32 %[t1c], %[ad] offset:512\n\t"
+        "ds_read_b32 %[t1d], %[ad] offset:768\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_xad_u32 %[Da], %[t0a], 0, %[qa]\n\t"
+        "v_xad_u32 %[Db], %[t0b], 0, %[qb]\n\t"
+        "v_xad_u32 %[Dc], %[t0c], 0, %[qc]\n\t"
+        "v_xad_u32 %[Dd], %[t0d], 0, %[qd]\n\t"
+        "v_xad_u32 %[qa], %[t0a], -1, %[hp]\n\t"
+        "v_xad_u32 %[qb], %[t0b], -1, %[hp]\n\t"
+        "v_xad_u32 %[qc], %[t0c], -1, %[hp]\n\t"
+        "v_xad_u32 %[qd], %[t0d], -1, %[hp]\n\t"
+        "v_xad_u32 %[Ea], %[t1a], 0, %[qa]\n\t"
+        "v_xad_u32 %[Eb], %[t1b], 0, %[qb]\n\t"
+        "v_xad_u32 %[Ec], %[t1c], 0, %[qc]\n\t"
+        "v_xad_u32 %[Ed], %[t1d], 0, %[qd]\n\t"
+        "v_bitop3_b32 %[alivea], %[alivea], %[Da], %[Ea] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[aliveb], %[aliveb], %[Db], %[Eb] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alivec], %[alivec], %[Dc], %[Ec] bitop3:0x80\n\t"
+        "v_bitop3_b32 %[alived], %[alived], %[Dd], %[Ed] bitop3:0x80\n\t"
+        "2:\n\t"
+        "s_branch 5f\n\t"
+        "6:\n\t"
+        "5:"
+        : [t0a] "=&v"(t0a),
+          [t0b] "=&v"(t0b),
+          [t0c] "=&v"(t0c),
+          [t0d] "=&v"(t0d),
+          [t1a] "=&v"(t1a),
+          [t1b] "=&v"(t1b),
+          [t1c] "=&v"(t1c),
+          [t1d] "=&v"(t1d),
+          [ad] "=&v"(ad),
+          [Da] "=&v"(Da),
+          [Db] "=&v"(Db),
+          [Dc] "=&v"(Dc),
+          [Dd] "=&v"(Dd),
+          [Ea] "=&v"(Ea),
+          [Eb] "=&v"(Eb),
+          [Ec] "=&v"(Ec),
+          [Ed] "=&v"(Ed),
+          [qa] "=&v"(qa),
+          [qb] "=&v"(qb),
+          [qc] "=&v"(qc),
+          [qd] "=&v"(qd),
+          [alivea] "=&v"(alive[0]),
+          [aliveb] "=&v"(alive[1]),
+          [alivec] "=&v"(alive[2]),
+          [alived] "=&v"(alive[3]),
+          [tmp] "=&s"(tmp)
+        : [base] "v"(base), [w0] "s"(w[0]), [w1] "s"(w[1]), [w2] "s"(w[2]), [w3] "s"(w[3]), [w4] "s"(w[4]), [w5] "s"(w[5]), [w6] "s"(w[6]), [w7] "s"(w[7]), [last] "s"(last), [Hs] "s"(0x80808080u), [hp] "s"(0x80808081u)
+        : "scc", "memory");
+}
+
 
 // Wave-wide masks of the four sub-tiles: bit l of m[b] is bit 7 of byte b
 // of lane l's word (one SDWA compare per byte). The trailing wait states
@@ -1353,7 +1731,7 @@ __device__ __forceinline__ bool eval_bytes(const unsigned char *__restrict__ til
 // Plain-code twin of the two-word window (the measurement variant): both
 // words in lockstep with the same exits; one step per 64-row sub-tile and
 // column.
-template <int BITS, bool COUNT>
+template <int BITS, bool COUNT, int SH = 9>
 __device__ __forceinline__ void by2_window_ref(const unsigned char *__restrict__ base, const int32_t (&w)[kWin],
                                                int32_t last, const uint32_t (&fH)[2], const uint32_t (&nf)[2],
                                                uint32_t (&nx)[2], uint32_t (&alive)[2], uint64_t &steps)
@@ -1362,7 +1740,7 @@ __device__ __forceinline__ void by2_window_ref(const unsigned char *__restrict__
     for (int u = 2; u < kWin; ++u) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const uint32_t t = *reinterpret_cast<const uint32_t *>(base + (w[u] << 9) + 256 * h);
+            const uint32_t t = *reinterpret_cast<const uint32_t *>(base + (w[u] << SH) + 256 * h);
             alive[h] &= (t ^ fH[h]) + nx[h];
             nx[h] = (t ^ nf[h]) + 1u;
         }
@@ -1378,7 +1756,7 @@ __device__ __forceinline__ void by2_window_ref(const unsigned char *__restrict__
 // Sets, per word, mw (the top bits of the matching rows' parts) and gw
 // (those that match on their negative trend); returns false, leaving them
 // unset, when no row matches.
-template <int BITS, bool NEG, bool COUNT, bool TIES>
+template <int BITS, bool NEG, bool COUNT, bool TIES, int SH = 9>
 __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ tile, int32_t last,
                                            const int32_t *__restrict__ colidx,
                                            const int32_t *__restrict__ hbegin, const int4 &w03, const int4 &w47,
@@ -1390,7 +1768,7 @@ __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ til
     const unsigned char *base = tile + 4 * lane;
     const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
     auto rd = [&](int32_t col, int h) {
-        return *reinterpret_cast<const uint32_t *>(base + (col << 9) + 256 * h);
+        return *reinterpret_cast<const uint32_t *>(base + (col << SH) + 256 * h);
     };
     if (last == 0) {  // one column: every row in range counts
         mw[0] = hva;
@@ -1421,20 +1799,20 @@ __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ til
             nx[h] = (t1 ^ nf[h]) + 1u;
         }
         steps += 2 * NP;
-        if (last >= 2) by2_window_ref<BITS, COUNT>(base, w, last, fH, nf, nx, alive, steps);
+        if (last >= 2) by2_window_ref<BITS, COUNT, SH>(base, w, last, fH, nf, nx, alive, steps);
         if (NEG && last >= 2 && __ballot((tied[0] | tied[1]) != 0) != 0) {
             const uint32_t fH2[2] = {~0u, ~0u}, nf2[2] = {T::H, T::H};
             uint32_t nx2[2] = {(rd(w[1], 0) ^ T::H) + 1u, (rd(w[1], 1) ^ T::H) + 1u};
             steps += 2 * NP;
-            by2_window_ref<BITS, COUNT>(base, w, last, fH2, nf2, nx2, tied, steps);
+            by2_window_ref<BITS, COUNT, SH>(base, w, last, fH2, nf2, nx2, tied, steps);
         } else {
             tied[0] = tied[1] = 0;
         }
     } else {
         const uint32_t b = lds_addr(base);
         if constexpr (NEG)
-            by2_neg<BITS, TIES>(b, w, last, hva, hvb, alive[0], alive[1], fall[0], fall[1], tied[0], tied[1]);
-        else by2_pos<BITS>(b, w, last, hva, hvb, alive[0], alive[1]);
+            by2_neg<BITS, TIES, SH>(b, w, last, hva, hvb, alive[0], alive[1], fall[0], fall[1], tied[0], tied[1]);
+        else by2_pos<BITS, SH>(b, w, last, hva, hvb, alive[0], alive[1]);
     }
     // No row of either word left on either chain: nothing matches, and the
     // columns past the window (rarely reached: few rows survive eight
@@ -1447,10 +1825,10 @@ __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ til
         for (int h = 0; h < 2; ++h) {
             if constexpr (NEG) {
                 const uint32_t fm = fall[h] - (fall[h] >> T::SHF);
-                by_tail<9, COUNT, NP>(base + 256 * h, c, w, last, fm | T::H, ~fm, alive[h], steps);
-                by_tail<9, COUNT, NP>(base + 256 * h, c, w, last, ~0u, T::H, tied[h], steps);
+                by_tail<SH, COUNT, NP>(base + 256 * h, c, w, last, fm | T::H, ~fm, alive[h], steps);
+                by_tail<SH, COUNT, NP>(base + 256 * h, c, w, last, ~0u, T::H, tied[h], steps);
             } else {
-                by_tail<9, COUNT, NP>(base + 256 * h, c, w, last, T::H, ~0u, alive[h], steps);
+                by_tail<SH, COUNT, NP>(base + 256 * h, c, w, last, T::H, ~0u, alive[h], steps);
             }
         }
         if (__ballot((alive[0] | alive[1] | tied[0] | tied[1]) != 0) == 0) return false;
@@ -1459,6 +1837,116 @@ __device__ __forceinline__ bool eval_swar2(const unsigned char *__restrict__ til
     mw[1] = alive[1] | tied[1];
 #pragma unroll
     for (int h = 0; h < 2; ++h) gw[h] = NEG ? (alive[h] & fall[h]) | (tied[h] & ~alive[h]) : 0u;
+    return true;
+}
+
+// Plain-code twin of the four-word window (the measurement variant): all
+// four words in lockstep with the same exits; one step per 64-row sub-tile
+// and column.
+template <bool COUNT>
+__device__ __forceinline__ void by4_window_ref(const unsigned char *__restrict__ base, const int32_t (&w)[kWin],
+                                               int32_t last, const uint32_t (&fH)[4], const uint32_t (&nf)[4],
+                                               uint32_t (&nx)[4], uint32_t (&alive)[4], uint64_t &steps)
+{
+#pragma unroll
+    for (int u = 2; u < kWin; ++u) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const uint32_t t = *reinterpret_cast<const uint32_t *>(base + (w[u] << 10) + 256 * h);
+            alive[h] &= (t ^ fH[h]) + nx[h];
+            nx[h] = (t ^ nf[h]) + 1u;
+        }
+        if (COUNT) steps += 16;
+        if (u == 3 && last <= 3) return;
+        if (u == 5 && (__ballot((alive[0] | alive[1] | alive[2] | alive[3]) != 0) == 0 || last <= 5)) return;
+    }
+}
+
+// One individual on a chunk of four lane words per row group (byte codes,
+// 1024 rows, 16 sub-tiles; a column is 1024 bytes). hv: the top bits of the
+// in-range rows of each word; full: every row of the chunk is in range.
+// Sets, per word, mw and gw as eval_swar2 does; returns false, leaving them
+// unset, when no row matches. Full tie-free chunks run the four-word
+// sequences; other chunks run the two-word ones on words (0, 1) and (2, 3).
+template <bool NEG, bool COUNT, bool TIES>
+__device__ __forceinline__ bool eval_swar4(const unsigned char *__restrict__ tile, int32_t last,
+                                           const int32_t *__restrict__ colidx,
+                                           const int32_t *__restrict__ hbegin, const int4 &w03, const int4 &w47,
+                                           int lane, const uint32_t (&hv)[4], bool full, uint32_t (&mw)[4],
+                                           uint32_t (&gw)[4], uint64_t &steps)
+{
+    using T = Lanes<8>;
+    if (last == 0) {  // one column: every row in range counts
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            mw[h] = hv[h];
+            gw[h] = 0;
+        }
+        if (COUNT) steps += 16;
+        return true;
+    }
+    if (!full || (NEG && TIES)) {
+        uint32_t m2[2] = {0, 0}, g2[2] = {0, 0}, m3[2] = {0, 0}, g3[2] = {0, 0};
+        const bool a = eval_swar2<8, NEG, COUNT, TIES, 10>(tile, last, colidx, hbegin, w03, w47, lane, hv[0], hv[1],
+                                                            m2, g2, steps);
+        const bool b = eval_swar2<8, NEG, COUNT, TIES, 10>(tile + 512, last, colidx, hbegin, w03, w47, lane, hv[2],
+                                                            hv[3], m3, g3, steps);
+        if (!a && !b) return false;
+        mw[0] = a ? m2[0] : 0u;
+        mw[1] = a ? m2[1] : 0u;
+        gw[0] = a ? g2[0] : 0u;
+        gw[1] = a ? g2[1] : 0u;
+        mw[2] = b ? m3[0] : 0u;
+        mw[3] = b ? m3[1] : 0u;
+        gw[2] = b ? g3[0] : 0u;
+        gw[3] = b ? g3[1] : 0u;
+        return true;
+    }
+    const unsigned char *base = tile + 4 * lane;
+    const int32_t w[kWin] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
+    uint32_t alive[4], fall[4] = {0, 0, 0, 0};
+    if constexpr (COUNT) {
+        uint32_t fH[4], nf[4], nx[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const uint32_t t0 = *reinterpret_cast<const uint32_t *>(base + (w[0] << 10) + 256 * h);
+            const uint32_t t1 = *reinterpret_cast<const uint32_t *>(base + (w[1] << 10) + 256 * h);
+            const uint32_t D = (t1 | T::H) - t0;
+            fH[h] = T::H;
+            nf[h] = ~0u;
+            alive[h] = D & T::H;
+            if constexpr (NEG) {
+                fall[h] = ~D & T::H;
+                const uint32_t fm = fall[h] - (fall[h] >> T::SHF);
+                fH[h] = fm | T::H;
+                nf[h] = ~fm;
+                alive[h] = T::H;
+            }
+            nx[h] = (t1 ^ nf[h]) + 1u;
+        }
+        steps += 16;
+        if (last >= 2) by4_window_ref<COUNT>(base, w, last, fH, nf, nx, alive, steps);
+    } else {
+        const uint32_t b = lds_addr(base);
+        if constexpr (NEG) by4_neg_full(b, w, last, alive, fall);
+        else by4_pos_full(b, w, last, alive);
+    }
+    if (__ballot((alive[0] | alive[1] | alive[2] | alive[3]) != 0) == 0) return false;
+    if (last >= kWin) {
+        // The columns past the window (the CSR start is read only here).
+        const int32_t *c = colidx + *hbegin;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const uint32_t fm = NEG ? fall[h] - (fall[h] >> T::SHF) : 0u;
+            by_tail<10, COUNT, 4>(base + 256 * h, c, w, last, fm | T::H, ~fm, alive[h], steps);
+        }
+        if (__ballot((alive[0] | alive[1] | alive[2] | alive[3]) != 0) == 0) return false;
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        mw[h] = alive[h];
+        gw[h] = NEG ? alive[h] & fall[h] : 0u;
+    }
     return true;
 }
 
@@ -1577,24 +2065,29 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
     constexpr int PARTS = kT10 ? 3 : 32 / BITS;      // rows (sub-tiles) per lane word
     constexpr int NWORDS = L >= PARTS ? L / PARTS : 1;  // lane words per chunk
     constexpr int CB = 256 * NWORDS;                  // bytes of one column per chunk
-    constexpr int PL = NWORDS == 2 ? 5 : 4;          // log2 of the 16-byte pieces per column
+    constexpr int PL = NWORDS == 4 ? 6 : NWORDS == 2 ? 5 : 4;  // log2 of the 16-byte pieces per column
     // A chunk starts on a multiple of L tiles: its bytes in a column, and
     // the index of its tie flag (one per 512 rows; 10-bit codes: one per
     // 192-row chunk).
-    auto chunk_at = [](int64_t tile) { return tile / L * CB; };
+    // (byte chunks of 16 sub-tiles may start on any multiple of 8 tiles)
+    auto chunk_at = [](int64_t tile) { return kT10 ? tile / L * CB : tile * kWave * (BITS / 8); };
     auto tie_at = [](int64_t tile) { return kT10 ? tile / 3 : (tile * kWave) >> 9; };
     const int btotal = kSwar ? d.cols << PL : 0;
     const int idx0 = threadIdx.x, idx1 = threadIdx.x + blockDim.x;
     const uint8_t *src0 = d.B + (int64_t)(idx0 >> PL) * d.ldb + 16 * (idx0 & ((1 << PL) - 1));
     const uint8_t *src1 = d.B + (int64_t)(idx1 >> PL) * d.ldb + 16 * (idx1 & ((1 << PL) - 1));
     uint4 pre0 = {0, 0, 0, 0}, pre1 = {0, 0, 0, 0};
+    // Pieces prefetched per thread (four-word chunks keep one, to leave
+    // registers to the four words' chains).
+    constexpr bool kPre1 = NWORDS != 4;
     int32_t tie_pre = 1;  // the next chunk's tie flag, loaded with its bytes
     if constexpr (kSwar) {
         if (t0 < t1) {
             const int64_t r0 = chunk_at(t0);
             if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r0);
-            if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r0);
+            if (kPre1 && idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r0);
             tie_pre = d.T[tie_at(t0)];
+            if (NWORDS == 4) tie_pre |= d.T[tie_at(t0) + 1];  // (1024 rows: two flags)
         }
     }
 
@@ -1634,23 +2127,25 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         // in range, and whether a row of the chunk holds two equal values.
         uint32_t hvalid[NWORDS] = {};
         bool ties = true;
+        bool full = true;  // every row of the chunk is in range
         if constexpr (kSwar) {
-            static_assert(STAGE == STAGE_HALVES ? (L == 2 || L == 4) : kT10 ? L == 3 : (L == 4 || L == 8),
-                          "one or two lane words per row of a chunk");
+            static_assert(STAGE == STAGE_HALVES ? (L == 2 || L == 4) : kT10 ? L == 3 : (L == 4 || L == 8 || L == 16),
+                          "one, two or four lane words per row of a chunk");
             ties = __builtin_amdgcn_readfirstlane(tie_pre) != 0;  // (uniform: one flag per chunk)
             // The L * 64 rows [row0, row0 + 64 L) of every column, in their
             // interleaved order; rows outside the item or the matrix are
             // left out of `hvalid` instead.
             uint4 *tile4 = reinterpret_cast<uint4 *>(tile);
             if (idx0 < btotal) tile4[idx0] = pre0;
-            if (idx1 < btotal) tile4[idx1] = pre1;
-            for (int idx = idx1 + blockDim.x; idx < btotal; idx += blockDim.x)
+            if (kPre1 && idx1 < btotal) tile4[idx1] = pre1;
+            for (int idx = kPre1 ? idx1 + blockDim.x : idx1; idx < btotal; idx += blockDim.x)
                 tile4[idx] = *reinterpret_cast<const uint4 *>(d.B + (int64_t)(idx >> PL) * d.ldb + chunk_at(tb) +
                                                               16 * (idx & ((1 << PL) - 1)));
             if (nl == L && row0 + L * kWave <= d.rows) {
 #pragma unroll
                 for (int h = 0; h < NWORDS; ++h) hvalid[h] = Lanes<BITS>::H;
             } else {
+                full = false;
 #pragma unroll
                 for (int s = 0; s < L; ++s)
                     if (s < nl && row0 + s * kWave + lane < d.rows)
@@ -1660,8 +2155,9 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             if (tb + L < t1) {
                 const int64_t r1 = chunk_at(tb + L);
                 if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r1);
-                if (idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r1);
+                if (kPre1 && idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r1);
                 tie_pre = d.T[tie_at(tb + L)];
+                if (NWORDS == 4) tie_pre |= d.T[tie_at(tb + L) + 1];
             }
         }
         if constexpr (STAGE == STAGE_LDS) {
@@ -1744,9 +2240,35 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                 // are made (no masks exist on this path).
                 if (k == 0) return;
                 const auto *tl = reinterpret_cast<const unsigned char *>(tile);
-                uint32_t mw[2] = {0, 0}, gw[2] = {0, 0};
+                if constexpr (NWORDS == 4) {
+                    if (!full || (NEG && TIES)) {
+                        // each pair of words on its own, counted as it ends
+                        // (fewer registers live than four words' results)
+                        int32_t pm = 0, pg = 0;
+#pragma unroll
+                        for (int half = 0; half < 2; ++half) {
+                            if (8 * half >= nl) break;  // (a half chunk at the end of a range)
+                            uint32_t m2[2] = {0, 0}, g2[2] = {0, 0};
+                            if (eval_swar2<8, NEG, COUNT, TIES, 10>(tl + 512 * half, k - 1, d.colidx, &hb[ii].begin,
+                                                                    hv[1], hv[2], lane, hvalid[2 * half],
+                                                                    hvalid[2 * half + 1], m2, g2, steps)) {
+#pragma unroll
+                                for (int h = 0; h < 2; ++h) {
+                                    pm += lane_popc<8>(m2[h]);
+                                    if constexpr (NEG) pg += lane_popc<8>(g2[h]);
+                                }
+                            }
+                        }
+                        add_counts(ii, pm, pg);
+                        return;
+                    }
+                }
+                uint32_t mw[NWORDS] = {}, gw[NWORDS] = {};
                 bool any;
-                if constexpr (NWORDS == 2)
+                if constexpr (NWORDS == 4)
+                    any = eval_swar4<NEG, COUNT, TIES>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2], lane,
+                                                       hvalid, true, mw, gw, steps);
+                else if constexpr (NWORDS == 2)
                     any = eval_swar2<BITS, NEG, COUNT, TIES>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2], lane,
                                                              hvalid[0], hvalid[NWORDS - 1], mw, gw, steps);
                 else
@@ -1778,7 +2300,9 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                     const auto *tl = reinterpret_cast<const unsigned char *>(tile);
                     uint32_t mw[2] = {0, 0}, gw[2] = {0, 0};
                     bool any;
-                    if constexpr (NWORDS == 2)
+                    if constexpr (NWORDS == 4)
+                        any = false;  // (never reached: four-word chunks take the count-only path above)
+                    else if constexpr (NWORDS == 2)
                         any = eval_swar2<BITS, NEG, COUNT, TIES>(tl, k - 1, d.colidx, &hb[ii].begin, hv[1], hv[2],
                                                                  lane, hvalid[0], hvalid[NWORDS - 1], mw, gw, steps);
                     else
@@ -1854,7 +2378,12 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         // The loop is compiled with and without the mask stores, and for
         // SWAR chunks with and without the tie chain (the chunk's flag,
         // decided once here rather than per individual).
-        if constexpr (kSwar) {
+        if constexpr (kSwar && NWORDS == 4) {
+            // (counts only: the planner stages four words per row group only
+            // for calls without masks, and the launch checks it)
+            if (ties) individuals(std::false_type{}, std::true_type{});
+            else individuals(std::false_type{}, std::false_type{});
+        } else if constexpr (kSwar) {
             if (d.mmask || d.nmask) {
                 if (ties) individuals(std::true_type{}, std::true_type{});
                 else individuals(std::true_type{}, std::false_type{});
@@ -1913,9 +2442,14 @@ k_eval(ReqDesc d, const IndHead *__restrict__ heads, int32_t P, int32_t n_tiles,
     if (np <= 0) return;
     // Tile ranges start on a multiple of L, so only the matrix's last chunk
     // can be partial.
-    const int64_t n_chunks = (n_tiles + L - 1) / L;
-    const int64_t t0 = (int64_t)rng * n_chunks / gridDim.x * L;
-    const int64_t t1 = min<int64_t>(n_tiles, (int64_t)(rng + 1) * n_chunks / gridDim.x * L);
+    // Ranges start on a multiple of RG tiles: L, except byte codes in chunks
+    // of 16 sub-tiles, whose ranges are cut in units of 8 (a range then ends
+    // with a half chunk when it holds an odd number of units, so that the
+    // ranges stay as even as with 8-sub-tile chunks).
+    constexpr int RG = (STAGE == STAGE_BYTES && L == 16) ? 8 : L;
+    const int64_t n_chunks = (n_tiles + RG - 1) / RG;
+    const int64_t t0 = (int64_t)rng * n_chunks / gridDim.x * RG;
+    const int64_t t1 = min<int64_t>(n_tiles, (int64_t)(rng + 1) * n_chunks / gridDim.x * RG);
     uint64_t steps = 0;
     run_item<L, NEG, STAGE, COUNT, STAGE == STAGE_HALVES || STAGE == STAGE_T10>(d, heads, i0, np, t0, t1, tile,
                                                                                  cnt, steps);
@@ -2036,6 +2570,7 @@ const void *eval_pick(int L, bool neg, int staging)
     if (staging == STAGE_BYTES) {  // one or two 256-row groups per chunk
         if (L == 4) return neg ? eval_ptr<4, true, STAGE_BYTES, COUNT>() : eval_ptr<4, false, STAGE_BYTES, COUNT>();
         if (L == 8) return neg ? eval_ptr<8, true, STAGE_BYTES, COUNT>() : eval_ptr<8, false, STAGE_BYTES, COUNT>();
+        if (L == 16) return neg ? eval_ptr<16, true, STAGE_BYTES, COUNT>() : eval_ptr<16, false, STAGE_BYTES, COUNT>();
         return nullptr;
     }
     if (staging == STAGE_T10) {  // one lane word of three rows per chunk
@@ -2123,6 +2658,8 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
                        hipEvent_t ev1)
 {
     if (d.n <= 0) return hipSuccess;
+    // Four words per row group make counts only (no mask outputs).
+    if (cfg.L == 16 && (d.mmask || d.nmask)) return hipErrorInvalidValue;
     {
         const int threads = 256;
         const int per_block = threads / kWave;  // one wave per individual

@@ -251,7 +251,7 @@ void build_half_codes(ebic_ctx *ctx, Matrix &m)
 }
 
 // Launch shape for one population on one matrix.
-LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t flags, CodesMode codes)
+LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t flags, CodesMode codes, bool masks)
 {
     LaunchCfg cfg;
     if (ctx->override_cfg.W > 0) cfg = ctx->override_cfg;
@@ -288,7 +288,9 @@ LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t f
             if (pick < 0 && have_swar(st)) pick = st;
         cfg.staging = pick >= 0 ? pick : (have_codes ? STAGE_CODES : STAGE_LDS);
     }
-    if (cfg.staging == STAGE_BYTES) cfg.L = cfg.L >= 8 ? 8 : 4;
+    // (four words per row group make counts only)
+    if (cfg.staging == STAGE_BYTES) cfg.L = cfg.L >= 16 && !masks ? 16 : cfg.L >= 8 ? 8 : 4;
+    if (cfg.staging == STAGE_BYTES && cfg.L == 16 && !fits(cfg)) cfg.L = 8;
     if (cfg.staging == STAGE_HALVES) cfg.L = cfg.L >= 4 ? 4 : 2;
     if (cfg.staging == STAGE_T10) cfg.L = 3;
     if (cfg.staging == STAGE_HALVES && cfg.L == 4 && !fits(cfg)) cfg.L = 2;
@@ -312,7 +314,8 @@ LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t f
     if (cfg.staging == STAGE_LDS && !fits(cfg)) cfg.staging = STAGE_DIRECT;
     while (!fits(cfg) && cfg.P > 64) cfg.P /= 2;
     const int64_t n_tiles = (m.dev.rows + 63) / 64;
-    const int64_t n_chunks = (n_tiles + cfg.L - 1) / cfg.L;
+    const int32_t granule = cfg.staging == STAGE_BYTES && cfg.L == 16 ? 8 : cfg.L;  // (as the kernel cuts ranges)
+    const int64_t n_chunks = (n_tiles + granule - 1) / granule;
     const int32_t groups = (n + cfg.P - 1) / cfg.P;
     const int32_t forced_blocks = cfg.blocks;
     auto derive_blocks = [&] {
@@ -695,7 +698,9 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             // exclude mode may use them only if no cell is missing.
             int32_t has_nan = 1;
             if (cols <= kMaxByteCols) {
-                m.dev.ldb = (rows + 511) / 512 * 512;  // whole chunks of two 256-row groups
+                // whole 512-row units plus one: a chunk of four 256-row groups
+                // may start at any multiple of 512 rows
+                m.dev.ldb = ((rows + 511) / 512 + 1) * 512;
                 // Layout: codes | missing flag (256 bytes) | tie flags.
                 const size_t bbytes = (size_t)m.dev.ldb * cols;
                 const size_t tbytes = (size_t)(m.dev.ldb / 512) * sizeof(int32_t);
@@ -802,7 +807,7 @@ ebic_status ebic_matrix_get_stats(ebic_ctx *ctx, int32_t matrix, ebic_matrix_sta
         // (the tie flags of the default SWAR codes: bytes, else 10-bit codes)
         const int32_t *ties = m.B ? m.dev.T : m.T10 ? m.dev.Tt : m.Hc ? m.dev.Th : nullptr;
         if (ties) {
-            const int64_t rows_pad = m.B ? m.dev.ldb : (m.dev.rows + 255) / 256 * 256;
+            const int64_t rows_pad = m.B ? (m.dev.rows + 511) / 512 * 512 : (m.dev.rows + 255) / 256 * 256;
             const int64_t n = m.B || !m.T10 ? (rows_pad + 511) / 512 : (m.dev.rows + kT10Rows - 1) / kT10Rows;
             std::vector<int32_t> h((size_t)n);
             hip_check(hipMemcpy(h.data(), ties, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost), "hipMemcpy");
@@ -868,7 +873,7 @@ ebic_status ebic_eval_population(ebic_ctx *ctx, int32_t matrix, int32_t n_ind,
             if (n_ind == 0) return;
             if (!d_offsets || !d_cols || !d_matched)
                 fail(EBIC_EINVAL, "d_offsets, d_cols and d_matched are required");
-            cfg = plan_eval(ctx, m, n_ind, -1, flags, CODES_BUILD);
+            cfg = plan_eval(ctx, m, n_ind, -1, flags, CODES_BUILD, d_matched_mask || d_negative_mask);
             d = make_desc(m, n_ind, d_offsets, d_cols, flags, d_matched, d_negative, d_matched_mask,
                           d_negative_mask, cfg.staging);
             hold.add_locked(matrix);
@@ -901,7 +906,8 @@ ebic_status ebic_eval_population_noalloc(ebic_ctx *ctx, int32_t matrix, int32_t 
             if (n_ind == 0) return;
             if (!d_offsets || !d_cols || !d_matched)
                 fail(EBIC_EINVAL, "d_offsets, d_cols and d_matched are required");
-            cfg = plan_eval(ctx, m, n_ind, -1, flags, CODES_EXISTING);  // (allocates nothing)
+            cfg = plan_eval(ctx, m, n_ind, -1, flags, CODES_EXISTING,  // (allocates nothing)
+                            d_matched_mask || d_negative_mask);
             d = make_desc(m, n_ind, d_offsets, d_cols, flags, d_matched, d_negative, d_matched_mask,
                           d_negative_mask, cfg.staging);
             hold.add_locked(matrix);

@@ -230,7 +230,7 @@ void build_fp16_codes(ebic_ctx *ctx, Matrix &m, bool include);
 bool halves_buildable(const Matrix &m, bool include);
 void build_half_codes(ebic_ctx *ctx, Matrix &m);
 LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t flags,
-                    CodesMode codes = CODES_BUILD);
+                    CodesMode codes = CODES_BUILD, bool masks = false);
 // The kernels' view of one request; `staging` decides whether include mode
 // reads the fill copy or substitutes on the fly.
 ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int32_t *cols,

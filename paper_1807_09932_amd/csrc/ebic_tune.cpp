@@ -229,7 +229,7 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
             return;
         }
         if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 3 || tiles_per_wave == 4 ||
-              tiles_per_wave == 8) ||
+              tiles_per_wave == 8 || tiles_per_wave == 16) ||
             waves_per_block < 1 || waves_per_block > 16 || individuals_per_group < 1 ||
             !(staging == STAGE_LDS || staging == STAGE_DIRECT || staging == STAGE_CODES ||
               staging == STAGE_BYTES || staging == STAGE_HALVES || staging == STAGE_T10) ||
@@ -292,7 +292,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                 if (!done.insert(key).second) continue;
                 LaunchCfg best;
                 float best_ms = INFINITY;
-                for (int L : {1, 2, 3, 4, 8})
+                for (int L : {1, 2, 3, 4, 8, 16})
                     for (int W : {4, 8, 16})
                         for (int P : {200, 400, 800, 1600})
                             for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT, (int)STAGE_CODES,
@@ -310,7 +310,8 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                                     continue;
                                 if (stg == STAGE_CODES && (L < 2 || !have_codes)) continue;
                                 if (stg == STAGE_BYTES && (L < 4 || !have_bytes)) continue;
-                                if (L == 8 && stg != STAGE_BYTES) continue;  // eight sub-tiles: byte codes only
+                                if (L >= 8 && stg != STAGE_BYTES) continue;  // eight or 16 sub-tiles: byte codes only
+                                if (L == 16 && (r.d_matched_mask || r.d_negative_mask)) continue;  // (counts only)
                                 if (stg == STAGE_HALVES && ((L != 2 && L != 4) || !have_halves)) continue;
                                 set_override(c);
                                 const float ms = time_ms(
