@@ -263,23 +263,28 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
  * Force the launch shape of later evaluations on this context (tests and
  * tuning experiments); waves_per_block = 0 restores the automatic choice.
  *   tiles_per_wave:        64-row tiles one wave evaluates together (1, 2, 4;
- *                          8 with the byte rank codes, plain evaluations only)
+ *                          3 or 6 with the 10-bit codes; 8 or 16 with the
+ *                          byte codes, 16 for counts only)
  *   waves_per_block:       1 .. 16
  *   individuals_per_group: individuals that share one block's staged tiles
  *   staging:               0 = column tiles staged in LDS, 1 = direct reads,
  *                          2 = the rank codes staged in LDS (2 or 4 sub-tiles;
  *                              include mode needs EBIC_KEEP_FILL_COPY),
- *                          3 = the byte rank codes staged in LDS (4 or 8
+ *                          3 = the byte rank codes staged in LDS (4, 8 or 16
  *                              sub-tiles; matrices of at most 128 columns;
  *                              exclude mode needs a matrix without missing
  *                              cells),
  *                          4 = the 16-bit rank codes staged in LDS (2 or 4
  *                              sub-tiles; 129 .. 384 columns; the same
- *                              condition for exclude mode); 3 and 4 select
- *                              whichever of the two the matrix has; without
- *                              codes for the request's mode the launch takes
- *                              another staging. Batches stage byte codes at
- *                              4 sub-tiles and 16-bit codes at 2 only.
+ *                              condition for exclude mode),
+ *                          5 = the 10-bit rank codes staged in LDS (3 or 6
+ *                              sub-tiles; 129 .. 512 columns; the same
+ *                              condition); 3, 4 and 5 select whichever kind
+ *                              the matrix has when it lacks the one asked
+ *                              for; without codes for the request's mode the
+ *                              launch takes another staging. Batches stage
+ *                              byte codes at 4 sub-tiles, 10-bit codes at 3
+ *                              and 16-bit codes at 2.
  *   blocks:                grid size per group, 0 = from occupancy
  * Shapes that do not fit the device are reduced at launch (fewer tiles per
  * wave, then direct reads). Results never depend on the shape.

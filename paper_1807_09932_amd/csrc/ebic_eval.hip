@@ -52,7 +52,7 @@ __host__ __device__ inline size_t tile_bytes_of(int32_t L, int32_t cols, int32_t
     if (staging == STAGE_DIRECT) return 0;
     if (staging == STAGE_BYTES) return (size_t)cols * L * kWave;  // one byte per row
     if (staging == STAGE_HALVES) return (size_t)cols * L * kWave * 2;
-    if (staging == STAGE_T10) return (size_t)cols * 256;  // one lane word (three sub-tiles)
+    if (staging == STAGE_T10) return (size_t)cols * 256 * (L >= 6 ? 2 : 1);  // one or two lane words
     return (size_t)L * kWave * cols * (staging == STAGE_CODES ? sizeof(uint16_t) : sizeof(float));
 }
 
@@ -2068,9 +2068,9 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
     constexpr int PL = NWORDS == 4 ? 6 : NWORDS == 2 ? 5 : 4;  // log2 of the 16-byte pieces per column
     // A chunk starts on a multiple of L tiles: its bytes in a column, and
     // the index of its tie flag (one per 512 rows; 10-bit codes: one per
-    // 192-row chunk).
+    // 192-row group, two groups in a chunk of two words).
     // (byte chunks of 16 sub-tiles may start on any multiple of 8 tiles)
-    auto chunk_at = [](int64_t tile) { return kT10 ? tile / L * CB : tile * kWave * (BITS / 8); };
+    auto chunk_at = [](int64_t tile) { return kT10 ? tile / 3 * 256 : tile * kWave * (BITS / 8); };
     auto tie_at = [](int64_t tile) { return kT10 ? tile / 3 : (tile * kWave) >> 9; };
     const int btotal = kSwar ? d.cols << PL : 0;
     const int idx0 = threadIdx.x, idx1 = threadIdx.x + blockDim.x;
@@ -2080,6 +2080,9 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
     // Pieces prefetched per thread (four-word chunks keep one, to leave
     // registers to the four words' chains).
     constexpr bool kPre1 = NWORDS != 4;
+    // Chunks that span two tie flags: 1024 rows of byte codes, two 192-row
+    // groups of 10-bit codes.
+    constexpr bool kTwoFlags = NWORDS == 4 || (kT10 && NWORDS == 2);
     int32_t tie_pre = 1;  // the next chunk's tie flag, loaded with its bytes
     if constexpr (kSwar) {
         if (t0 < t1) {
@@ -2087,7 +2090,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
             if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r0);
             if (kPre1 && idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r0);
             tie_pre = d.T[tie_at(t0)];
-            if (NWORDS == 4) tie_pre |= d.T[tie_at(t0) + 1];  // (1024 rows: two flags)
+            if (kTwoFlags) tie_pre |= d.T[tie_at(t0) + 1];  // (two flags per chunk)
         }
     }
 
@@ -2129,7 +2132,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
         bool ties = true;
         bool full = true;  // every row of the chunk is in range
         if constexpr (kSwar) {
-            static_assert(STAGE == STAGE_HALVES ? (L == 2 || L == 4) : kT10 ? L == 3 : (L == 4 || L == 8 || L == 16),
+            static_assert(STAGE == STAGE_HALVES ? (L == 2 || L == 4) : kT10 ? (L == 3 || L == 6) : (L == 4 || L == 8 || L == 16),
                           "one, two or four lane words per row of a chunk");
             ties = __builtin_amdgcn_readfirstlane(tie_pre) != 0;  // (uniform: one flag per chunk)
             // The L * 64 rows [row0, row0 + 64 L) of every column, in their
@@ -2157,7 +2160,7 @@ __device__ __forceinline__ void run_item(const ReqDesc &d, const IndHead *__rest
                 if (idx0 < btotal) pre0 = *reinterpret_cast<const uint4 *>(src0 + r1);
                 if (kPre1 && idx1 < btotal) pre1 = *reinterpret_cast<const uint4 *>(src1 + r1);
                 tie_pre = d.T[tie_at(tb + L)];
-                if (NWORDS == 4) tie_pre |= d.T[tie_at(tb + L) + 1];
+                if (kTwoFlags) tie_pre |= d.T[tie_at(tb + L) + 1];
             }
         }
         if constexpr (STAGE == STAGE_LDS) {
@@ -2573,8 +2576,9 @@ const void *eval_pick(int L, bool neg, int staging)
         if (L == 16) return neg ? eval_ptr<16, true, STAGE_BYTES, COUNT>() : eval_ptr<16, false, STAGE_BYTES, COUNT>();
         return nullptr;
     }
-    if (staging == STAGE_T10) {  // one lane word of three rows per chunk
+    if (staging == STAGE_T10) {  // one or two lane words of three rows per chunk
         if (L == 3) return neg ? eval_ptr<3, true, STAGE_T10, COUNT>() : eval_ptr<3, false, STAGE_T10, COUNT>();
+        if (L == 6) return neg ? eval_ptr<6, true, STAGE_T10, COUNT>() : eval_ptr<6, false, STAGE_T10, COUNT>();
         return nullptr;
     }
     if (staging == STAGE_HALVES) {  // one or two lane words of two rows per chunk

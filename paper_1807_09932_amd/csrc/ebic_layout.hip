@@ -228,7 +228,8 @@ hipError_t launch_t10_codes(const float *X, int64_t rows, int64_t ld, int32_t co
                             uint8_t *T10, int64_t ld10, int32_t *has_nan, int32_t *ties, hipStream_t s)
 {
     const int64_t groups = (rows + kT10Rows - 1) / kT10Rows;
-    if (cols > kMaxT10Cols || ld10 != groups * 256 || ld / 64 < (rows + 63) / 64) return hipErrorInvalidValue;
+    if (cols > kMaxT10Cols || ld10 < groups * 256 || ld10 % 256 != 0 || ld / 64 < (rows + 63) / 64)
+        return hipErrorInvalidValue;
     const size_t lds = (size_t)cols * 64 * sizeof(float);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t10_codes),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -271,8 +271,9 @@ LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t f
     const bool have_halves = m.dev.Hc ? (include || m.dev.h_exclude)
                                       : codes != CODES_EXISTING && halves_buildable(m, include);
     const bool have_t10 = m.dev.T10 && (include || m.dev.t_exclude);
-    // SWAR codes: bytes (up to 128 columns; one or two lane words per row,
-    // L = 4 or 8), 10-bit codes (up to 512 columns; one word, L = 3) or
+    // SWAR codes: bytes (up to 128 columns; one, two or four lane words per
+    // row, L = 4, 8 or 16), 10-bit codes (up to 512 columns; one or two
+    // words, L = 3 or 6) or
     // 16-bit codes (up to 384 columns; one or two words, L = 2 or 4). A
     // request without the kind its shape asks for takes another kind the
     // matrix has, else the FP16 codes (or the FP32 tile); a tile that does
@@ -292,7 +293,8 @@ LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t f
     if (cfg.staging == STAGE_BYTES) cfg.L = cfg.L >= 16 && !masks ? 16 : cfg.L >= 8 ? 8 : 4;
     if (cfg.staging == STAGE_BYTES && cfg.L == 16 && !fits(cfg)) cfg.L = 8;
     if (cfg.staging == STAGE_HALVES) cfg.L = cfg.L >= 4 ? 4 : 2;
-    if (cfg.staging == STAGE_T10) cfg.L = 3;
+    if (cfg.staging == STAGE_T10) cfg.L = cfg.L >= 6 ? 6 : 3;
+    if (cfg.staging == STAGE_T10 && cfg.L == 6 && !fits(cfg)) cfg.L = 3;
     if (cfg.staging == STAGE_HALVES && cfg.L == 4 && !fits(cfg)) cfg.L = 2;
     if (cfg.staging == STAGE_BYTES && cfg.L == 8 && !fits(cfg)) cfg.L = 4;
     if ((cfg.staging == STAGE_HALVES || cfg.staging == STAGE_BYTES || cfg.staging == STAGE_T10) && !fits(cfg))
@@ -722,7 +724,9 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             // 10-bit codes (three rows per 32-bit word) for 129..512 columns.
             int32_t has_nan_t = 1;
             if (cols > kMaxByteCols && cols <= kMaxT10Cols) {
-                const int64_t groups = (rows + kT10Rows - 1) / kT10Rows;
+                // an even number of 192-row groups: a chunk of two groups
+                // starts on an even one (the padding group stays zero)
+                const int64_t groups = (rows + 2 * kT10Rows - 1) / (2 * kT10Rows) * 2;
                 m.dev.ld10 = groups * 256;
                 const size_t tb = (size_t)m.dev.ld10 * cols;
                 const size_t fbytes = (size_t)groups * sizeof(int32_t);

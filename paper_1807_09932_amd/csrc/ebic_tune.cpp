@@ -229,7 +229,7 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
             return;
         }
         if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 3 || tiles_per_wave == 4 ||
-              tiles_per_wave == 8 || tiles_per_wave == 16) ||
+              tiles_per_wave == 6 || tiles_per_wave == 8 || tiles_per_wave == 16) ||
             waves_per_block < 1 || waves_per_block > 16 || individuals_per_group < 1 ||
             !(staging == STAGE_LDS || staging == STAGE_DIRECT || staging == STAGE_CODES ||
               staging == STAGE_BYTES || staging == STAGE_HALVES || staging == STAGE_T10) ||
@@ -292,12 +292,12 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                 if (!done.insert(key).second) continue;
                 LaunchCfg best;
                 float best_ms = INFINITY;
-                for (int L : {1, 2, 3, 4, 8, 16})
+                for (int L : {1, 2, 3, 4, 6, 8, 16})
                     for (int W : {4, 8, 16})
                         for (int P : {200, 400, 800, 1600})
                             for (int stg : {(int)STAGE_LDS, (int)STAGE_DIRECT, (int)STAGE_CODES,
                                             (int)STAGE_BYTES, (int)STAGE_HALVES, (int)STAGE_T10}) {
-                                if ((L == 3) != (stg == STAGE_T10)) continue;  // 10-bit codes: three sub-tiles
+                                if ((L == 3 || L == 6) != (stg == STAGE_T10)) continue;  // 10-bit codes: 3 or 6
                                 if (stg == STAGE_T10 && !have_t10) continue;
                                 LaunchCfg c;
                                 c.L = L;

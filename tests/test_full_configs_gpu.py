@@ -96,8 +96,9 @@ def test_methylation_include_mode_full(ctx):
     ctx.release(mat)
 
 
-@pytest.mark.parametrize("shape,staging", [(None, 5), ((3, 16, 400, 5), 5), ((2, 16, 400, 4), 4)],
-                         ids=["default", "10-bit-P400", "16-bit"])
+@pytest.mark.parametrize("shape,staging", [(None, 5), ((3, 16, 400, 5), 5), ((6, 16, 200, 5), 5),
+                                           ((2, 16, 400, 4), 4)],
+                         ids=["default", "10-bit-P400", "10-bit-two-words", "16-bit"])
 def test_methylation_wide_full(ctx, shape, staging):
     from paper_1807_09932_amd import ebic
     w, pop = gen.methylation_wide()

@@ -1,7 +1,8 @@
 """10-bit rank codes (three rows per 32-bit lane word, for matrices of 129 to
 512 columns) against the oracle, bit-exact, through the C ABI: tie-heavy,
 tie-free and missing-valued matrices, ragged row counts around the 192-row
-groups, several launch shapes, plain and batched launches."""
+groups and 384-row chunks, one and two lane words per chunk, several launch
+shapes, plain and batched launches."""
 import numpy as np
 import pytest
 
@@ -44,7 +45,8 @@ def _pop(rng, cols, n, kmax=30, dup=0.05, bad=0.02):
     return gen.csr(inds)
 
 
-SHAPES = [(3, 16, 200, 0), (3, 8, 64, 0), (3, 5, 33, 7), (3, 16, 400, 0), (3, 1, 5, 2)]
+SHAPES = [(3, 16, 200, 0), (3, 8, 64, 0), (3, 5, 33, 7), (3, 16, 400, 0), (3, 1, 5, 2),
+          (6, 16, 200, 0), (6, 8, 64, 0), (6, 5, 33, 7), (6, 16, 400, 3), (6, 2, 5, 0)]
 
 
 @pytest.mark.parametrize("cols", [129, 200, 310, 384, 512])
@@ -79,18 +81,19 @@ def test_t10_plain(ctx, cols, kind):
         ctx.release(mat)
 
 
-@pytest.mark.parametrize("rows", [1, 63, 64, 65, 191, 192, 193, 383, 385, 577])
-def test_t10_edge_rows(ctx, rows):
+@pytest.mark.parametrize("tiles", [3, 6])
+@pytest.mark.parametrize("rows", [1, 63, 64, 65, 191, 192, 193, 383, 384, 385, 577, 769])
+def test_t10_edge_rows(ctx, rows, tiles):
     from paper_1807_09932_amd import ebic
     X = _matrix("ties", rows, 150, rows)
     rng = np.random.default_rng(rows)
     offs, cc = _pop(rng, 150, 60, kmax=12, dup=0.2)
     mat = ctx.upload(X)
     try:
-        ctx.set_launch_shape(3, 4, 16, ebic.STAGE_T10, 0)
-        assert ebic.ebic_plan_shape(ctx.handle, mat, 60)[3] == ebic.STAGE_T10
+        ctx.set_launch_shape(tiles, 4, 16, ebic.STAGE_T10, 0)
+        assert tuple(ebic.ebic_plan_shape(ctx.handle, mat, 60)[::3]) == (tiles, ebic.STAGE_T10)
         for include in (False, True):
-            announce("t10 rows", rows, include)
+            announce("t10 rows", rows, tiles, include)
             got = gpu_eval(ctx, mat, offs, cc, include=include, negative=True, masks=True)
             assert_same(got, oracle_eval(X, offs, cc, include=include, negative=True, masks=True),
                         f"rows={rows} include={include}")
