@@ -80,15 +80,19 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(launch_units, name="k_eval_methylation_436444x64_traffic.json"):
+def traffic_from_profile(launch_units, name="k_eval_methylation_436444x64_traffic.json", shape=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel sources changed since the counters were taken."""
+    None when the kernel sources changed since the counters were taken, or
+    when `shape` (tiles per wave, waves per block, group size, staging) is
+    not the launch shape they were taken in."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_sources_sha") != kernel_sources_sha():
+        return None
+    if shape is not None and list(t.get("launch_shape") or []) != [int(v) for v in shape]:
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -304,7 +308,9 @@ def bench_batched(ctx, args):
         "launch_shape": "L=%d W=%d P=%d stagings=%s blocks=%d" % (bL, bW, bP, sorted(set(b_stg)),
                                                                   b_grid),
         "roofline": {**alu_roofline(b_steps, g_ms, b_stg[0] if len(set(b_stg)) == 1 else None),
-                     "traffic": traffic_from_profile(1, "k_eval_batch_100000x256_traffic.json"),
+                     "traffic": (traffic_from_profile(1, "k_eval_batch_100000x256_traffic.json",
+                                                      (bL, bW, bP, b_stg[0]))
+                                 if len(set(b_stg)) == 1 else None),
                      "traffic_note": "HBM bytes per launch of the persistent kernel (committed FETCH_SIZE / "
                                      "WRITE_SIZE summary): each staged chunk is read once per group of P "
                                      "individuals of each population, mostly from the Infinity Cache"},
@@ -465,7 +471,8 @@ def bench_paper_shape(ctx, args):
             "launch_shape": f"{how}: L={L} W={W} P={P} staging={stg} blocks={blocks}",
             "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
             "roofline": {**alu_roofline(steps, k_ms, stg),
-                         "traffic": traffic_from_profile(1, "k_eval_methylation_wide_436444x310_traffic.json")},
+                         "traffic": traffic_from_profile(1, "k_eval_methylation_wide_436444x310_traffic.json",
+                                                         (L, W, P, stg))},
             "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9}
 
 
@@ -881,7 +888,7 @@ def main():
         },
         "roofline": {
             **roof,
-            "traffic": traffic_from_profile(1),
+            "traffic": traffic_from_profile(1, shape=(L, W, P, stg)),
             "kernel": "k_eval",
             "launch_shape": shape_note,
             "kernel_ms": k_ms,
@@ -910,8 +917,8 @@ def main():
             "note": "gather-equivalent: 4 B per nominal check; the staged kernel reads the "
                     "matrix once, so this is not physical traffic",
             "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9,
-            "physical_gbs": (traffic_from_profile(1) / (k_ms * 1e-3) / 1e9
-                             if traffic_from_profile(1) else None),
+            "physical_gbs": (traffic_from_profile(1, shape=(L, W, P, stg)) / (k_ms * 1e-3) / 1e9
+                             if traffic_from_profile(1, shape=(L, W, P, stg)) else None),
             "copy_ceiling_gbs": copy_gbs,
             "physical_note": "HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE "
                              "summary over the measured kernel time; copy ceiling = a 1 GiB "

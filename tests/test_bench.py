@@ -65,7 +65,10 @@ def test_traffic_only_for_matching_kernel_sources(bench, tmp_path, monkeypatch):
     sha = bench.kernel_sources_sha()
     path = prof / "k_eval_methylation_436444x64_traffic.json"
     assert bench.traffic_from_profile(1) is None  # no summary
-    path.write_text(json.dumps({"kernel_sources_sha": sha, "hbm_bytes_per_launch": 1234.0}))
+    path.write_text(json.dumps({"kernel_sources_sha": sha, "hbm_bytes_per_launch": 1234.0,
+                                "launch_shape": [8, 16, 200, 3]}))
     assert bench.traffic_from_profile(1) == 1234.0
+    assert bench.traffic_from_profile(1, shape=(8, 16, 200, 3)) == 1234.0
+    assert bench.traffic_from_profile(1, shape=(16, 16, 200, 3)) is None  # another launch shape
     (csrc / bench.KERNEL_SOURCES[0]).write_text("// changed\n")
     assert bench.traffic_from_profile(1) is None  # the kernel changed since

@@ -34,11 +34,14 @@ def test_upload_builds_only_what_the_plan_stages(ctx, cols, swar):
     assert st["code_sets"] == want_sets, st
     assert st["has_missing"] == (0 if swar else -1)
     if swar == 8:
-        ldb = (rows + 511) // 512 * 512
+        # whole 512-row units plus one (a 1024-row chunk may start at any unit)
+        ldb = ((rows + 511) // 512 + 1) * 512
         assert st["code_bytes"] == ldb * cols + 256 + 4 * (ldb // 512)
+        assert st["swar_chunks"] == (rows + 511) // 512
     if swar == 10:
         groups = (rows + 191) // 192
-        assert st["code_bytes"] == groups * 256 * cols + 256 + 4 * groups
+        padded = (groups + 1) // 2 * 2  # (an even count: two-group chunks)
+        assert st["code_bytes"] == padded * 256 * cols + 256 + 4 * padded
         assert st["swar_chunks"] == groups
     ctx.release(mat)
 
