@@ -390,6 +390,7 @@ def bench_ea(ctx, args, w=None):
     gens = 40
     t_host = t_dev = 0.0
     checks = 0
+    offs0, cols0, _ = ea.population()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for g in range(gens):
@@ -406,6 +407,34 @@ def bench_ea(ctx, args, w=None):
         t_dev += t3 - t2
         checks += gen.nominal_checks(rows, offs)
     el = time.perf_counter() - t0
+    host_final = ea.population()
+
+    # The same run with breeding on the device (ebic_ea_breed): evaluation
+    # and breeding alternate on one stream, the population never leaves the
+    # device, and the host waits once at the end.
+    def device_run():
+        pop = ctx.population(offsets=offs0, cols=cols0)
+        m = ctx.outputs(mat, 800, negative=False)[0]
+        n, kmax = 800, ea.params.k_max
+        bufs = [(torch.empty(n + 1, dtype=torch.int32, device=ctx.device),
+                 torch.empty(n * kmax, dtype=torch.int32, device=ctx.device),
+                 torch.empty(1, dtype=torch.int32, device=ctx.device)) for _ in range(2)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for g in range(1, gens + 1):
+            ctx.eval(mat, pop, negative=True, out=(m, None, None, None))
+            pop, _ = ctx.breed(ea.params, g, pop, m, out=bufs[g & 1])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, pop
+
+    device_run()  # (scratch and allocator warm-up)
+    el_dev, pop_dev = device_run()
+    do = pop_dev.offsets.cpu().numpy()
+    same = (np.array_equal(do, host_final[0]) and
+            np.array_equal(pop_dev.cols.cpu().numpy()[: int(do[-1])], host_final[1]))
+    if not same:
+        print("bench.py: the device-bred run differs from the host-bred run", file=sys.stderr)
+        sys.exit(3)
     ctx.release(mat)
     ea.close()
     return {"workload": "stand-in evolutionary loop, 800 individuals of 2-30 columns per "
@@ -415,7 +444,14 @@ def bench_ea(ctx, args, w=None):
             "evaluation_ms_per_generation": t_dev * 1e3 / gens,
             "checks_per_s": checks / el,
             "evaluation": "population to the device, ebic_eval_population, matched counts back "
-                          "(synchronous)"}
+                          "(synchronous)",
+            "device_bred": {"ms_per_generation": el_dev * 1e3 / gens,
+                            "generations_per_s": gens / el_dev,
+                            "checks_per_s": checks / el_dev,
+                            "equal_to_host_bred": bool(same),
+                            "how": "ebic_eval_population then ebic_ea_breed per generation on one "
+                                   "stream, one synchronisation at the end; the final population "
+                                   "equals the host-bred run's column for column"}}
 
 
 def bench_paper_shape(ctx, args):

@@ -476,6 +476,31 @@ ebic_status ebic_ea_population(ebic_ea *ea, const int32_t **offsets, const int32
 ebic_status ebic_ea_step(ebic_ea *ea, const int32_t *matched, int32_t *best_index,
                          double *best_fitness);
 
+/*
+ * The same breeding on the device: the generation after (d_offsets,
+ * d_cols), a population of n_ind = params->pop_size individuals in device
+ * memory, from its matched counts d_matched (n_ind, device; -1 marks an
+ * invalid individual), written as CSR to d_next_offsets (n_ind + 1) and
+ * d_next_cols (capacity n_ind * k_max int32), all device memory of the
+ * context's device, caller-owned and borrowed until the stream work
+ * completes. `generation` is the index of the generation being bred (>= 1;
+ * generation 0 is the driver's random first one): with the driver's
+ * parameters and the same counts, generation g equals what the g-th
+ * ebic_ea_step produces, column for column. d_best (nullable, device)
+ * receives the index of the current generation's best individual.
+ * Asynchronous on hip_stream (evaluation and breeding can alternate on one
+ * stream without the population leaving the device); the input and output
+ * populations must not overlap. A parent longer than k_max is read as its
+ * first k_max columns; a parent without columns is replaced by a random
+ * individual. Errors: EBIC_EINVAL (parameters as for ebic_ea_create,
+ * n_ind != pop_size, generation < 1, a NULL required pointer), EBIC_ENOMEM,
+ * EBIC_EHIP; nothing is enqueued on error.
+ */
+ebic_status ebic_ea_breed(ebic_ctx *ctx, const ebic_ea_params *params, int64_t generation, int32_t n_ind,
+                          const int32_t *d_offsets, const int32_t *d_cols, const int32_t *d_matched,
+                          int32_t *d_next_offsets, int32_t *d_next_cols, int32_t *d_best,
+                          void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Ingest and export (host code).
  * ------------------------------------------------------------------------ */

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libebic.so")
 
 SOURCES = ["ebic_eval.hip", "ebic_layout.hip", "ebic_runtime.cpp", "ebic_tune.cpp", "ebic_batch.cpp",
-           "ebic_serve.cpp", "ebic_ea.cpp", "ebic_io.cpp"]
+           "ebic_serve.cpp", "ebic_ea.cpp", "ebic_breed.hip", "ebic_io.cpp"]
 
 ARCH = os.environ.get("EBIC_OFFLOAD_ARCH", "gfx950")
 

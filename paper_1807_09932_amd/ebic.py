@@ -51,7 +51,7 @@ EXPORTED = ["ebic_create", "ebic_destroy", "ebic_set_allocator", "ebic_last_erro
             "ebic_plan_shape", "ebic_plan_batch_shape", "ebic_server_request_bytes", "ebic_server_create",
             "ebic_server_destroy", "ebic_server_submit", "ebic_server_poll",
             "ebic_server_get_stats", "ebic_server_cancel", "ebic_server_set_paused", "ebic_ea_create", "ebic_ea_destroy", "ebic_ea_population",
-            "ebic_ea_step", "ebic_read_delimited", "ebic_free_text_matrix",
+            "ebic_ea_step", "ebic_ea_breed", "ebic_read_delimited", "ebic_free_text_matrix",
             "ebic_write_biclusters"]
 
 
@@ -155,6 +155,7 @@ def load_library(path: str = LIB_PATH):
         "ebic_ea_population": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I32),
                                      ctypes.POINTER(I64)]),
         "ebic_ea_step": (I32, [P, P, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]),
+        "ebic_ea_breed": (I32, [P, ctypes.POINTER(ebic_ea_params), ctypes.c_int64, I32, P, P, P, P, P, P, P]),
         "ebic_read_delimited": (I32, [ctypes.c_char_p, ctypes.c_char, I32, I32, I32,
                                       ctypes.POINTER(ebic_text_matrix)]),
         "ebic_free_text_matrix": (I32, [ctypes.POINTER(ebic_text_matrix)]),
@@ -359,6 +360,13 @@ def ebic_ea_population(ea: int) -> Tuple[int, int, int, int]:
     _check(load_library().ebic_ea_population(ea, ctypes.byref(o), ctypes.byref(c),
                                              ctypes.byref(n), ctypes.byref(g)))
     return o.value, c.value, n.value, g.value
+
+
+def ebic_ea_breed(ctx: int, params: "ebic_ea_params", generation: int, n_ind: int, d_offsets: int,
+                  d_cols: int, d_matched: int, d_next_offsets: int, d_next_cols: int,
+                  d_best: Optional[int] = None, stream: Optional[int] = None) -> None:
+    _check(load_library().ebic_ea_breed(ctx, ctypes.byref(params), generation, n_ind, d_offsets, d_cols,
+                                        d_matched, d_next_offsets, d_next_cols, d_best, stream))
 
 
 def ebic_ea_step(ea: int, matched: int) -> Tuple[int, float]:
@@ -625,6 +633,23 @@ class Context:
         if cols.numel() == 0:
             cols = torch.zeros(1, dtype=torch.int32, device=self.device)
         return Population(offsets, cols)
+
+    def breed(self, params: "ebic_ea_params", generation: int, pop: Population, matched: torch.Tensor,
+              stream=None, out=None):
+        """The next generation bred on the device (ebic_ea_breed) from `pop`
+        and its matched counts: returns (Population, best) where best is a
+        one-element device tensor holding the current generation's best
+        index. `out` = (offsets, cols, best) tensors to reuse (n + 1,
+        n * k_max, 1). Asynchronous on the stream."""
+        n = pop.n
+        if out is None:
+            out = (torch.empty(n + 1, dtype=torch.int32, device=self.device),
+                   torch.empty(max(1, n * params.k_max), dtype=torch.int32, device=self.device),
+                   torch.empty(1, dtype=torch.int32, device=self.device))
+        o, c, b = out
+        ebic_ea_breed(self.handle, params, generation, n, pop.offsets.data_ptr(), pop.cols.data_ptr(),
+                      matched.data_ptr(), o.data_ptr(), c.data_ptr(), b.data_ptr(), self.stream_handle(stream))
+        return Population(o, c), b
 
     def outputs(self, matrix: int, n: int, masks: bool = False, negative: bool = True):
         rows, _ = self.matrices[matrix]
