@@ -92,9 +92,13 @@ def traffic_from_profile(launch_units, name="k_eval_methylation_436444x64_traffi
         t = json.load(f)
     if t.get("kernel_sources_sha") != kernel_sources_sha():
         return None
-    if shape is not None and list(t.get("launch_shape") or []) != [int(v) for v in shape]:
-        return None
-    return t.get("hbm_bytes_per_launch")
+    if shape is None:
+        return t.get("hbm_bytes_per_launch")
+    want = [int(v) for v in shape]
+    for entry in [t] + list(t.get("other_shapes") or []):
+        if list(entry.get("launch_shape") or []) == want:
+            return entry.get("hbm_bytes_per_launch")
+    return None
 
 
 def cpu_baseline(w, offs, cols, threads, repeats=3):

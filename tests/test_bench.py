@@ -70,5 +70,11 @@ def test_traffic_only_for_matching_kernel_sources(bench, tmp_path, monkeypatch):
     assert bench.traffic_from_profile(1) == 1234.0
     assert bench.traffic_from_profile(1, shape=(8, 16, 200, 3)) == 1234.0
     assert bench.traffic_from_profile(1, shape=(16, 16, 200, 3)) is None  # another launch shape
+    path.write_text(json.dumps({"kernel_sources_sha": sha, "hbm_bytes_per_launch": 1234.0,
+                                "launch_shape": [8, 16, 200, 3],
+                                "other_shapes": [{"launch_shape": [16, 16, 200, 3],
+                                                  "hbm_bytes_per_launch": 999.0}]}))
+    assert bench.traffic_from_profile(1, shape=(16, 16, 200, 3)) == 999.0
+    assert bench.traffic_from_profile(1, shape=(4, 16, 200, 3)) is None
     (csrc / bench.KERNEL_SOURCES[0]).write_text("// changed\n")
     assert bench.traffic_from_profile(1) is None  # the kernel changed since
