@@ -41,14 +41,26 @@ struct Rng {
         z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
         return z ^ (z >> 31);
     }
-    // Uniform integer in [0, n) (n >= 1), by rejection (no modulo bias).
+    // Uniform integer in [0, n) (n >= 1) from the high 32 bits of a draw,
+    // by Lemire's multiply-and-shift with rejection ("Fast random integer
+    // generation in an interval", ACM TOMACS 2019): the product x n spans
+    // [0, n 2^32); its high word is the result, and draws whose low word
+    // falls below 2^32 mod n are redrawn, so every result has the same
+    // number of preimages. No 64-bit division (a long software routine on
+    // the GPU); the 32-bit remainder is taken only when a rejection is
+    // possible.
     __host__ __device__ uint32_t below(uint32_t n)
     {
-        const uint64_t lim = UINT64_MAX - UINT64_MAX % n;
-        uint64_t x;
-        do x = next();
-        while (x >= lim);
-        return (uint32_t)(x % n);
+        uint64_t m = (next() >> 32) * (uint64_t)n;
+        uint32_t lo = (uint32_t)m;
+        if (lo < n) {
+            const uint32_t t = (0u - n) % n;  // 2^32 mod n
+            while (lo < t) {
+                m = (next() >> 32) * (uint64_t)n;
+                lo = (uint32_t)m;
+            }
+        }
+        return (uint32_t)(m >> 32);
     }
     // Uniform in [0, 1) with 53 random bits.
     __host__ __device__ double uniform() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
@@ -72,13 +84,18 @@ __host__ __device__ inline double fitness(int32_t matched, int32_t k)
     return (double)matched * ldexp(1.0, k - 2);
 }
 
-// Rank order: higher fitness first, then the lower index.
-__host__ __device__ inline bool ranks_before(const double *f, int32_t a, int32_t b)
+// Rank order: higher fitness first, then the lower index (individual a
+// of fitness fa before individual b of fitness fb).
+__host__ __device__ inline bool ranks_before(double fa, int32_t a, double fb, int32_t b)
 {
-    return f[a] > f[b] || (f[a] == f[b] && a < b);
+    return fa > fb || (fa == fb && a < b);
 }
 
-__host__ __device__ inline bool contains(const int32_t *ind, int32_t len, int32_t c)
+// The functions below take the individual being built as any indexable
+// buffer (a host array, or a device thread's column of an interleaved LDS
+// array); the parents are plain arrays.
+template <class Buf>
+__host__ __device__ inline bool contains(const Buf &ind, int32_t len, int32_t c)
 {
     for (int32_t j = 0; j < len; ++j)
         if (ind[j] == c) return true;
@@ -86,7 +103,8 @@ __host__ __device__ inline bool contains(const int32_t *ind, int32_t len, int32_
 }
 
 // A column of [0, n_cols) not in ind[0, len) (callers ensure one exists).
-__host__ __device__ inline int32_t unused_column(Rng &rng, int32_t n_cols, const int32_t *ind, int32_t len)
+template <class Buf>
+__host__ __device__ inline int32_t unused_column(Rng &rng, int32_t n_cols, const Buf &ind, int32_t len)
 {
     int32_t c;
     do c = (int32_t)rng.below((uint32_t)n_cols);
@@ -96,7 +114,8 @@ __host__ __device__ inline int32_t unused_column(Rng &rng, int32_t n_cols, const
 
 // A random individual of distinct columns, k_min..k_max long, into out
 // (capacity k_max); returns its length.
-__host__ __device__ inline int32_t random_individual(const ebic_ea_params &p, Rng &rng, int32_t *out)
+template <class Buf>
+__host__ __device__ inline int32_t random_individual(const ebic_ea_params &p, Rng &rng, Buf &out)
 {
     const int32_t k = p.k_min + (int32_t)rng.below((uint32_t)(p.k_max - p.k_min + 1));
     int32_t len = 0;
@@ -110,7 +129,8 @@ __host__ __device__ inline int32_t random_individual(const ebic_ea_params &p, Rn
 // One mutation of ind[0, k) in place (capacity k_max); returns the new
 // length. The operation is drawn first; one that does not apply to this
 // individual falls through to substitution.
-__host__ __device__ inline int32_t mutate(const ebic_ea_params &p, Rng &rng, int32_t *ind, int32_t k)
+template <class Buf>
+__host__ __device__ inline int32_t mutate(const ebic_ea_params &p, Rng &rng, Buf &ind, int32_t k)
 {
     const bool can_insert = k < p.k_max && k < p.n_cols;
     const bool can_delete = k > p.k_min;
@@ -146,8 +166,9 @@ __host__ __device__ inline int32_t mutate(const ebic_ea_params &p, Rng &rng, int
 // One-point crossover: a prefix of a, then b from a random point on,
 // skipping columns already present, cut to k_max and topped up to k_min
 // with unused columns. Parents are at least one column long.
+template <class Buf>
 __host__ __device__ inline int32_t crossover(const ebic_ea_params &p, Rng &rng, const int32_t *a, int32_t ka,
-                                             const int32_t *b, int32_t kb, int32_t *child)
+                                             const int32_t *b, int32_t kb, Buf &child)
 {
     const uint32_t cut = ka > 1 ? 1 + rng.below((uint32_t)ka - 1) : 1;
     const uint32_t from = rng.below((uint32_t)kb);
@@ -176,9 +197,10 @@ __host__ __device__ inline int32_t parent_len(const ebic_ea_params &p, const int
 // winner of a second tournament, then with probability p_mutation one
 // mutation. Writes the child to `child` (capacity k_max), returns its
 // length.
+template <class Buf>
 __host__ __device__ inline int32_t breed_child(const ebic_ea_params &p, Rng &rng, int32_t n,
                                                const int32_t *offsets, const int32_t *cols, const double *f,
-                                               int32_t *child)
+                                               Buf &child)
 {
     auto tournament = [&]() -> int32_t {
         const int32_t a = (int32_t)rng.below((uint32_t)n), b = (int32_t)rng.below((uint32_t)n);
@@ -201,6 +223,15 @@ __host__ __device__ inline int32_t breed_child(const ebic_ea_params &p, Rng &rng
     if (rng.uniform() < p.p_mutation) len = mutate(p, rng, child, len);
     return len;
 }
+
+// Element j of one thread's buffer in an array interleaved over `stride`
+// threads (element j of thread t at j * stride + t: consecutive threads hit
+// consecutive LDS banks).
+struct Strided {
+    int32_t *base;
+    int32_t stride;
+    __host__ __device__ int32_t &operator[](int32_t j) const { return base[(int64_t)j * stride]; }
+};
 
 // Why a parameter set cannot drive a run (NULL if it can).
 inline const char *params_error(const ebic_ea_params &p)

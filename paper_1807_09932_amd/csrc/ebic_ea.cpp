@@ -51,7 +51,8 @@ ebic_status ebic_ea_create(const ebic_ea_params *params, ebic_ea **out)
         std::vector<int32_t> ind((size_t)p.k_max);
         for (int32_t i = 0; i < p.pop_size; ++i) {
             breed::Rng rng = breed::stream(p.seed, 0, p.pop_size, i);
-            const int32_t k = breed::random_individual(p, rng, ind.data());
+            int32_t *buf = ind.data();
+            const int32_t k = breed::random_individual(p, rng, buf);
             ea->cols.insert(ea->cols.end(), ind.begin(), ind.begin() + k);
             ea->offsets.push_back((int32_t)ea->cols.size());
         }
@@ -88,7 +89,8 @@ ebic_status ebic_ea_step(ebic_ea *ea, const int32_t *matched, int32_t *best_inde
         // Rank: fitness descending, index ascending on ties.
         std::vector<int32_t> order((size_t)n);
         std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return f[a] > f[b]; });
+        std::sort(order.begin(), order.end(),
+                  [&](int32_t a, int32_t b) { return breed::ranks_before(f[a], a, f[b], b); });
         ea->best = order[0];
         ea->best_fitness = f[order[0]];
         if (best_index) *best_index = ea->best;
@@ -104,7 +106,8 @@ ebic_status ebic_ea_step(ebic_ea *ea, const int32_t *matched, int32_t *best_inde
                 std::copy_n(ea->cols.begin() + ea->offsets[e], len, child.begin());
             } else {
                 breed::Rng rng = breed::stream(p.seed, g, n, c);
-                len = breed::breed_child(p, rng, n, ea->offsets.data(), ea->cols.data(), f.data(), child.data());
+                int32_t *buf = child.data();
+                len = breed::breed_child(p, rng, n, ea->offsets.data(), ea->cols.data(), f.data(), buf);
             }
             cols.insert(cols.end(), child.begin(), child.begin() + len);
             offs.push_back((int32_t)cols.size());

@@ -4,7 +4,9 @@ generation bred on the device equals the host's column for column, and
 the counts of the evolving population equal the oracle's. Also a loop that
 alternates evaluation and breeding on one stream with no host round trip,
 parameter corners (no elites, no crossover, always crossover, fixed
-length, k_max = n_cols, two individuals), caller-made populations with
+length, k_max = n_cols, two individuals; populations bred by one
+workgroup and, above 1,024 individuals, by the five-kernel path, with
+children built in LDS or, for k_max above 64, in global memory), caller-made populations with
 invalid and over-long individuals, and argument errors."""
 import numpy as np
 import pytest
@@ -109,6 +111,8 @@ def test_on_device_loop_matches_host_loop(ctx):
     (6, 33, 1, 6, 2, 0.8, 1.0),
     (10, 2, 1, 10, 1, 1.0, 1.0),
     (300, 1500, 2, 40, 20, 0.5, 0.9),
+    (100, 200, 2, 80, 5, 0.6, 0.9),
+    (120, 1100, 2, 80, 10, 0.6, 0.9),  # over 1,024 and k_max above 64: children in global memory
 ])
 def test_parameter_corners(ctx, n_cols, pop, k_min, k_max, elite, pc, pm):
     import torch
