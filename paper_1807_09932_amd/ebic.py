@@ -408,8 +408,12 @@ def read_delimited(path: str, delimiter: str = "", header: int = -1, row_names: 
         n = m.rows * m.cols
         flat = np.ctypeslib.as_array(m.values, shape=(n,)).copy() if n else np.zeros(0, np.float32)
         X = flat.reshape(m.cols, m.rows).T  # column-major view of (rows, cols)
-        rn = [m.row_names[i].decode() for i in range(m.rows)] if m.row_names else None
-        cn = [m.col_names[i].decode() for i in range(m.cols)] if m.col_names else None
+        # (names are bytes as written in the file; bytes that are not UTF-8
+        # are kept as escapes, so writing the names back gives the same bytes)
+        rn = ([m.row_names[i].decode("utf-8", "surrogateescape") for i in range(m.rows)]
+              if m.row_names else None)
+        cn = ([m.col_names[i].decode("utf-8", "surrogateescape") for i in range(m.cols)]
+              if m.col_names else None)
     finally:
         ebic_free_text_matrix(m)
     return X, rn, cn
@@ -431,7 +435,7 @@ def write_biclusters(path: str, rows: int, offsets: np.ndarray, cols: np.ndarray
     def names(v):
         if v is None:
             return None
-        arr = (ctypes.c_char_p * len(v))(*[str(x).encode() for x in v])
+        arr = (ctypes.c_char_p * len(v))(*[str(x).encode("utf-8", "surrogateescape") for x in v])
         return ctypes.cast(arr, ctypes.POINTER(ctypes.c_char_p)), arr
     rn, cn = names(row_names), names(col_names)
     ebic_write_biclusters(path, rows, n, offsets.ctypes.data, cols.ctypes.data if cols.size else None,

@@ -131,3 +131,20 @@ def test_export_matches_masks(tmp_path):
     assert cc == [cn[c] for c in cols[offs[5]:offs[6]]]
     with pytest.raises(ebic.EbicError):
         ebic.write_biclusters(p, rows, offs, cols, mm, [len(pop)])
+
+
+def test_names_that_are_not_utf8_round_trip(tmp_path):
+    """Row and column names are the file's bytes: names that are not UTF-8
+    are read (as escapes) and written back as the same bytes."""
+    p = tmp_path / "latin1.tsv"
+    p.write_bytes(b"gene\tca\xe9\tcb\nr\xf61\t1.5\t2\nr2\t3\t-4\n")
+    X, rn, cn = ebic.read_delimited(str(p), "\t")
+    assert X.shape == (2, 2) and X[0, 0] == np.float32(1.5) and X[1, 1] == np.float32(-4)
+    assert cn[0].encode("utf-8", "surrogateescape") == b"ca\xe9"
+    assert rn[0].encode("utf-8", "surrogateescape") == b"r\xf61"
+    offs, cols = gen.csr([np.array([0, 1], np.int32)])
+    mask = np.array([[3]], dtype=np.uint64).view(np.int64)
+    out = tmp_path / "out.txt"
+    ebic.write_biclusters(str(out), 2, offs, cols, mask, [0], row_names=rn, col_names=cn)
+    data = out.read_bytes()
+    assert b"r\xf61" in data and b"ca\xe9" in data
