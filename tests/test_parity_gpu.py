@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from paper_1807_09932_amd import gen
-from tests.gpu_common import announce, assert_same, gpu_eval, oracle_eval
+from tests.gpu_common import announce, assert_same, gpu_eval, oracle_eval, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -438,3 +438,61 @@ def test_halves_tall_ranges(ctx):
     finally:
         ctx.set_launch_shape()
         ctx.release(mat)
+
+
+@pytest.mark.parametrize("tiles", [3, 6])
+@pytest.mark.parametrize("ncols", [129, 300, 512])
+@pytest.mark.parametrize("rows", [1, 193, 385, 3001])
+def test_t10_special_values(ctx, ncols, rows, tiles):
+    """10-bit rank codes (three rows per lane word) on the special values
+    (+-inf, +-0, denormals, ties), both modes and trend settings, without
+    and with missing cells (exclude mode then stages something else), one
+    and two lane words per chunk."""
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(2100 + 7 * ncols + rows + tiles)
+    X = _special(rng, (rows, ncols))
+    Xn = X.copy()
+    Xn[rng.random(X.shape) < 0.04] = np.float32(np.nan)
+    offs, cols = _random_pop(rng, ncols, 120, 30, dup=0.1, bad=0.02)
+    for name, A in (("no missing", X), ("missing", Xn)):
+        mat = ctx.upload(A, fill=-0.0)
+        try:
+            ctx.set_launch_shape(tiles, 8, 64, ebic.STAGE_T10, 0)
+            plan = ebic.ebic_plan_shape(ctx.handle, mat, offs.size - 1, int(offs[-1]))
+            assert (plan[3] == ebic.STAGE_T10) == (not np.isnan(A).any())
+            for include in (False, True):
+                for negative in (False, True):
+                    announce("t10 special", rows, ncols, tiles, name, include, negative)
+                    got = gpu_eval(ctx, mat, offs, cols, include=include, negative=negative)
+                    want = oracle_eval(A, offs, cols, include=include, negative=negative, fill=-0.0)
+                    assert_same(got, want, f"t10 {rows}x{ncols} {name} include={include} "
+                                           f"negative={negative}")
+        finally:
+            ctx.set_launch_shape()
+            ctx.release(mat)
+
+
+def test_library_allocator_without_torch():
+    """A context that allocates with hipMalloc itself (no torch allocator
+    hook): upload, plain and batched evaluation, release and destroy, with
+    the oracle's counts."""
+    import torch
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(77)
+    X = _special(rng, (2_001, 96))
+    offs, cols = _random_pop(rng, 96, 200, 20, dup=0.05, bad=0.02)
+    c = ebic.Context(0, torch_allocator=False)
+    try:
+        mat = c.upload(X)
+        announce("own allocator")
+        got = gpu_eval(c, mat, offs, cols, negative=True, masks=True)
+        assert_same(got, oracle_eval(X, offs, cols, negative=True, masks=True), "own allocator plain")
+        p = c.population(offsets=offs, cols=cols)
+        o = c.outputs(mat, p.n)
+        c.eval_batch([c.request(mat, p, o)])
+        torch.cuda.synchronize()
+        want = oracle_eval(X, offs, cols, negative=True, masks=False)
+        assert np.array_equal(to_np(o[0]), want[0]) and np.array_equal(to_np(o[1]), want[1])
+        c.release(mat)
+    finally:
+        c.close()
