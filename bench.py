@@ -945,9 +945,10 @@ def main():
                       "cost GPU time)" % (wall_events * 1e3 / args.steps),
             "ops": (("row checks executed per launch: %d steps x 64 rows (one step = one column "
                      "of one 64-row sub-tile; the first pair counts one step; early exit per "
-                     "chunk of two lane words per lane), counted by the measurement variant of "
+                     "chunk of %d lane word(s) per lane), counted by the measurement variant of "
                      "the kernel; peak = 39.3e12 32-bit VALU lane ops/s x %d rows per lane op / "
-                     "2.5 ops per column step" % (executed_steps, ROWS_PER_OP.get(stg, 2)))
+                     "2.5 ops per column step" % (executed_steps, max(1, L // ROWS_PER_OP.get(stg, 2)),
+                                                  ROWS_PER_OP.get(stg, 2)))
                     if stg in SWAR_STAGES else
                     ("FP32 compares executed per launch: %d wave-wide compare instructions x 64 "
                      "rows (first pair: 3 per 64-row tile, then 1 per column step of each row's "
