@@ -373,8 +373,10 @@ ebic_status ebic_server_request_bytes(ebic_ctx *ctx, int32_t matrix, int32_t n_i
  * Start a server on `ctx`: a device arena of hbm_budget_bytes (from the
  * context's allocator; it bounds the bytes of all batches in flight),
  * `slots` streams (1..16, each with a pinned staging buffer and a completion
- * thread) and a scheduler thread that launches up to max_batch waiting
- * requests per slot as one ebic_eval_batch. The matrices stay owned by the
+ * thread) and a scheduler thread that launches waiting requests, in
+ * arrival order, as one ebic_eval_batch per idle slot: at most max_batch of
+ * them, and at most an equal share (rounded up) of those waiting per idle
+ * slot, so that a backlog is spread over the idle slots. The matrices stay owned by the
  * context and must outlive the requests that use them.
  */
 ebic_status ebic_server_create(ebic_ctx *ctx, int64_t hbm_budget_bytes, int32_t slots,

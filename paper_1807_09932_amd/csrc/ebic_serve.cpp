@@ -9,17 +9,20 @@
 //     requests' CSR inputs, then their outputs) from launch to completion,
 //     so the admitted bytes never exceed the budget;
 //   * stream slots, each with a pinned host buffer laid out like its device
-//     region, an event and a completion thread;
+//     region, an event and a thread of its own;
 //   * a scheduler thread. Whenever a slot is idle and requests are waiting,
-//     it takes the longest FIFO prefix (up to max_batch requests) whose bytes
-//     fit the largest free block, packs their CSR into the slot's pinned
-//     buffer, and enqueues on the slot's stream: one host-to-device copy, one
-//     ebic_eval_batch (a replayed graph), one device-to-host copy of all
-//     outputs, an event. Batches on different slots overlap on the device.
+//     it assigns the slot the longest FIFO prefix (up to max_batch requests,
+//     and up to an equal share of the waiting requests per idle slot) whose
+//     bytes fit the largest free block, with its region of the arena.
 //
-// The completion thread of a slot waits for its event, copies each
-// request's counts (and masks) to the caller's buffers, records the
-// latency, frees the region and hands the tags to ebic_server_poll.
+// The slot's thread packs the batch's CSR into its pinned buffer and
+// enqueues on its stream one host-to-device copy, one ebic_eval_batch (a
+// replayed graph; capturing a new one takes milliseconds, which then hold
+// up this slot alone), one device-to-host copy of all outputs and an event.
+// Batches on different slots overlap on the device. It then waits for the
+// event, copies each request's counts (and masks) to the caller's buffers,
+// records the latency, frees the region and hands the tags to
+// ebic_server_poll.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -139,10 +142,9 @@ struct Slot {
     size_t h_cap = 0;
     std::vector<std::unique_ptr<Req>> batch;
     size_t dev_off = 0, dev_bytes = 0, in_bytes = 0;
-    bool busy = false;      // owns a batch (from packing to completion)
-    bool launched = false;  // its batch is enqueued; the completer may wait
-    ebic_status launch_status = EBIC_OK;
-    std::thread completer;
+    bool busy = false;      // owns a batch (from assignment to completion)
+    bool assigned = false;  // a batch waits for this slot's thread to launch it
+    std::thread completer;  // launches the slot's batches and completes them
 };
 
 }  // namespace
@@ -159,7 +161,7 @@ struct ebic_server {
     std::vector<std::unique_ptr<Slot>> slots;
     std::mutex mu;
     std::condition_variable cv_sched;  // scheduler: new requests, an idle slot, freed memory
-    std::condition_variable cv_slot;   // completers: a batch was launched
+    std::condition_variable cv_slot;   // slot threads: a batch was assigned
     std::condition_variable cv_done;   // pollers: tags completed
     std::deque<std::unique_ptr<Req>> pending;
     std::deque<std::pair<uint64_t, ebic_status>> done;
@@ -282,11 +284,19 @@ void scheduler_main(ebic_server *srv)
             srv->cv_sched.wait(lk);
             continue;
         }
-        // The longest FIFO prefix that fits the largest free block.
+        // The longest FIFO prefix that fits the largest free block, and at
+        // most an equal share (rounded up) of the waiting requests for each
+        // idle slot: when several slots are idle, a backlog is spread over
+        // them, whose batches run side by side, instead of going whole to
+        // the first one as one long batch that every request in it waits
+        // for.
         const size_t room = srv->free_list->largest();
+        size_t n_idle = 0;
+        for (auto &sl : srv->slots) n_idle += sl->busy ? 0 : 1;
+        const size_t share = (srv->pending.size() + n_idle - 1) / std::max<size_t>(1, n_idle);
         size_t bytes = 0;
         size_t take = 0;
-        while (take < srv->pending.size() && (int32_t)take < srv->max_batch &&
+        while (take < srv->pending.size() && (int32_t)take < srv->max_batch && take < share &&
                bytes + srv->pending[take]->sz.total() <= room) {
             bytes += srv->pending[take]->sz.total();
             ++take;
@@ -313,13 +323,10 @@ void scheduler_main(ebic_server *srv)
         }
         ++srv->batches;
         srv->batched_requests += (int64_t)take;
-        lk.unlock();
-        const ebic_status st = launch_batch_on(srv, sl);
-        const double t_l = now_s();
-        for (auto &r : sl.batch) r->t_launched = t_l;
-        lk.lock();
-        sl.launch_status = st;
-        sl.launched = true;
+        // The slot's own thread packs and launches the batch: a launch that
+        // captures a new graph (milliseconds) then holds up that slot alone,
+        // not the scheduler and every other slot.
+        sl.assigned = true;
         srv->cv_slot.notify_all();
     }
 }
@@ -329,10 +336,13 @@ void completer_main(ebic_server *srv, Slot *sl)
     (void)hipSetDevice(srv->ctx->device);
     std::unique_lock<std::mutex> lk(srv->mu);
     while (true) {
-        srv->cv_slot.wait(lk, [&] { return sl->launched || srv->sched_done; });
-        if (!sl->launched) break;  // every request has completed
+        srv->cv_slot.wait(lk, [&] { return sl->assigned || srv->sched_done; });
+        if (!sl->assigned) break;  // every request has completed
+        sl->assigned = false;
         lk.unlock();
-        ebic_status st = sl->launch_status;
+        ebic_status st = launch_batch_on(srv, *sl);
+        const double t_l = now_s();
+        for (auto &r : sl->batch) r->t_launched = t_l;
         if (st == EBIC_OK && hipEventSynchronize(sl->done) != hipSuccess) st = EBIC_EHIP;
         // After a failed launch, let whatever was enqueued drain before the
         // pinned buffer is reused.
@@ -362,7 +372,6 @@ void completer_main(ebic_server *srv, Slot *sl)
         sl->batch.clear();
         srv->free_list->release(sl->dev_off, sl->dev_bytes);
         srv->reserved -= (int64_t)sl->dev_bytes;
-        sl->launched = false;
         sl->busy = false;
         srv->cv_sched.notify_all();
         srv->cv_done.notify_all();

@@ -36,10 +36,16 @@ def test_results_in_the_mix_equal_results_alone(served):
     reqs = gen.served_requests(0.2, rate_hz=1000.0, pool_size=6)[:150]
     announce("serve mix", len(reqs))
     with Server(ctx, hbm_budget_bytes=64 << 20, slots=3) as srv:
+        # the first 60 queue behind a pause (so that mixed batches certainly
+        # form when it ends); the rest arrive on the schedule
+        srv.pause(True)
         t0 = time.perf_counter()
         futs = []
         for i, r in enumerate(reqs):
-            while time.perf_counter() - t0 < r.t_arrival:
+            if i == 60:
+                srv.pause(False)
+                t0 = time.perf_counter() - r.t_arrival
+            while i >= 60 and time.perf_counter() - t0 < r.t_arrival:
                 time.sleep(1e-4)
             offs, cols = pools[r.matrix][r.pool_index]
             futs.append(srv.submit(r.run, mats[r.matrix], offs, cols, negative=bool(i % 2),
