@@ -156,3 +156,28 @@ def test_methylation_full_four_words(ctx):
     finally:
         ctx.set_launch_shape()
         ctx.release(mat)
+
+
+@pytest.mark.parametrize("rows", [1, 63, 64, 65, 511, 512, 513, 1023, 1024, 1025, 1537, 2049])
+@pytest.mark.parametrize("blocks", [0, 1, 3])
+def test_edge_rows_four_words(ctx, rows, blocks):
+    """Row counts around the 64-row sub-tiles, 512-row units and 1024-row
+    chunks, with ranges of one, three or as many blocks as the planner
+    picks (half chunks at range ends, a last chunk past the matrix)."""
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(rows * 7 + blocks)
+    X = rng.integers(0, 6, size=(rows, 64)).astype(np.float32)  # tie-heavy: both paths
+    X[: rows // 2] = _tie_free(rows // 2, 64, rows) if rows >= 2 else X[: rows // 2]
+    offs, cc = _pop(rng, 64, 90)
+    mat = ctx.upload(X)
+    try:
+        ctx.set_launch_shape(16, 8, 32, ebic.STAGE_BYTES, blocks)
+        assert ebic.ebic_plan_shape(ctx.handle, mat, offs.size - 1)[0] == 16
+        for negative in (True, False):
+            announce("four words rows", rows, blocks, negative)
+            got = gpu_eval(ctx, mat, offs, cc, negative=negative, masks=False)
+            assert_same(_counts(got), oracle_eval(X, offs, cc, negative=negative, masks=False),
+                        f"rows={rows} blocks={blocks} negative={negative}")
+    finally:
+        ctx.set_launch_shape()
+        ctx.release(mat)
