@@ -134,7 +134,9 @@ enum {
     EBIC_SET_FP16_FILL = 4u,   /* FP16 rank codes of the fill copy */
     EBIC_SET_U8 = 8u,          /* byte rank codes of the fill-substituted values */
     EBIC_SET_U16 = 16u,        /* 16-bit rank codes of the fill-substituted values */
-    EBIC_SET_U10 = 32u         /* 10-bit rank codes (three per 32-bit word) of the same */
+    EBIC_SET_U10 = 32u,        /* 10-bit rank codes (three per 32-bit word) of the same */
+    EBIC_SET_PAIRS = 64u,      /* pairwise order bitmaps of the values */
+    EBIC_SET_PAIRS_FILL = 128u /* pairwise order bitmaps of the fill-substituted values */
 };
 
 /*
@@ -285,6 +287,19 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
  *                              launch takes another staging. Batches stage
  *                              byte codes at 4 sub-tiles, 10-bit codes at 3
  *                              and 16-bit codes at 2.
+ *                          6 = the pairwise order bitmaps (one bit per row
+ *                              for every ordered pair of columns, built on
+ *                              first use: cols^2 x ceil(rows / 2048) x 256
+ *                              bytes plus 512 bytes per 2,048 rows, at most
+ *                              1,024 columns and 32 GiB); nothing staged,
+ *                              tiles_per_wave ignored, at most 64
+ *                              individuals per wave, and `blocks` is the
+ *                              number of 2,048-row chunks a wave walks (0:
+ *                              enough runs of chunks to fill the device);
+ *                              without them (too large, or the
+ *                              allocation-free entry point before they are
+ *                              built) the launch takes the rank codes the
+ *                              matrix has. Batches never use them.
  *   blocks:                grid size per group, 0 = from occupancy
  * Shapes that do not fit the device are reduced at launch (fewer tiles per
  * wave, then direct reads). Results never depend on the shape.

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libebic.so")
 
-SOURCES = ["ebic_eval.hip", "ebic_layout.hip", "ebic_runtime.cpp", "ebic_tune.cpp", "ebic_batch.cpp",
+SOURCES = ["ebic_eval.hip", "ebic_pairs.hip", "ebic_layout.hip", "ebic_runtime.cpp", "ebic_tune.cpp", "ebic_batch.cpp",
            "ebic_serve.cpp", "ebic_ea.cpp", "ebic_breed.hip", "ebic_io.cpp"]
 
 ARCH = os.environ.get("EBIC_OFFLOAD_ARCH", "gfx950")

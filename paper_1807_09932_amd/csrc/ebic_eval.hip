@@ -40,16 +40,15 @@
 #include <type_traits>
 
 #include "ebic_internal.h"
+#include "ebic_prep.h"
 
 namespace ebic {
 
 namespace {
 
-constexpr int32_t kInvalid = -1;
-
 __host__ __device__ inline size_t tile_bytes_of(int32_t L, int32_t cols, int32_t staging)
 {
-    if (staging == STAGE_DIRECT) return 0;
+    if (staging == STAGE_DIRECT || staging == STAGE_PAIRS) return 0;
     if (staging == STAGE_BYTES) return (size_t)cols * L * kWave;  // one byte per row
     if (staging == STAGE_HALVES) return (size_t)cols * L * kWave * 2;
     if (staging == STAGE_T10) return (size_t)cols * 256 * (L >= 6 ? 2 : 1);  // one or two lane words
@@ -66,58 +65,19 @@ __host__ __device__ inline size_t count_bytes_of(int32_t P, bool cnt16 = false)
 // ---------------------------------------------------------------------------
 // Prep: validation, output initialisation and the per-individual header.
 // ---------------------------------------------------------------------------
-// One wave per individual: the lanes check its columns together (one round
-// of independent loads for up to 64 columns), lane 0 initialises the
-// outputs, and lanes 0..15 write the 64-byte header word by word.
-//
-// A leading run of repeats of the first column is dropped from the header
-// (begin moves to the run's last entry, k shrinks by the same amount):
-// comparing a cell with itself always holds (x >= x and x <= x for any
-// present value; a missing one is excluded by the kept copy of the column
-// in exclude mode and takes the fill value in include mode), so
-// c, c, ..., c, rest follows exactly the rows of c, rest, on both chains.
-// The evaluation then never sees a first pair that compares a cell with
-// itself, which is what lets a chunk without two equal values in any row
-// skip the tie handling of the first pair (the SWAR sequences' tie-free
-// variants classify every row as rising or falling there).
+// One wave per individual (the scan of its columns, with the leading
+// repeats of the first column dropped, in ebic_prep.h): lane 0 initialises
+// the outputs, and lanes 0..15 write the 64-byte header word by word.
 __device__ __forceinline__ void prep_wave(const ReqDesc &d, int32_t i, IndHead *__restrict__ heads, int lane)
 {
-    const int32_t b = d.offsets[i], e = d.offsets[i + 1];
-    const bool span = b >= 0 && e > b;
-    bool bad = false;
-    int32_t first = 0;  // lane l: column l of the individual (first 64)
-    int32_t run = 0;    // entries b .. b + run hold the first column
-    if (span) {
-        const int32_t c0 = d.colidx[b];
-        run = e - b - 1;  // unless a different column follows
-        bool found = false;
-        for (int32_t jb = b; jb < e; jb += kWave) {  // (wave-uniform trip count)
-            const int32_t j = jb + lane;
-            const bool in = j < e;
-            const int32_t c = in ? d.colidx[j] : c0;
-            if (jb == b) first = c;
-            bad |= in && (c < 0 || c >= d.cols);
-            const uint64_t differ = __ballot(in && c != c0);
-            if (!found && differ != 0) {
-                found = true;
-                run = (jb - b) + (int32_t)__builtin_ctzll(differ) - 1;
-            }
-        }
-    }
-    const bool ok = span && __ballot(bad) == 0;
-    const int32_t bb = b + run;      // the header's CSR start
-    const int32_t k = ok ? e - bb : 0;
-    // lanes 8..15: window column lane - 8 from bb (clamped to the last column)
-    const int32_t src = run + min(lane - 8, e - bb - 1);
-    int32_t win = __shfl(first, (src >= 0 && src < kWave) ? src : 0);
-    if (span && lane >= 8 && lane < 16 && src >= kWave) win = d.colidx[b + src];
+    const PrepScan sc = prep_scan(d, i, lane);
     if (lane == 0) {
-        d.matched[i] = ok ? 0 : kInvalid;
-        if (d.negative) d.negative[i] = ok ? 0 : kInvalid;
+        d.matched[i] = sc.ok ? 0 : kInvalid;
+        if (d.negative) d.negative[i] = sc.ok ? 0 : kInvalid;
     }
     if (lane < 16) {
         // words: k, begin, 6 x 0, the window
-        const int32_t v = lane == 0 ? k : lane == 1 ? bb : (lane >= 8 && ok) ? win : 0;
+        const int32_t v = lane == 0 ? sc.k : lane == 1 ? sc.bb : (lane >= 8 && sc.ok) ? sc.win : 0;
         reinterpret_cast<int32_t *>(heads + d.head_base + i)[lane] = v;
     }
 }
@@ -2662,15 +2622,37 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
                        hipEvent_t ev1)
 {
     if (d.n <= 0) return hipSuccess;
-    // Four words per row group make counts only (no mask outputs).
-    if (cfg.L == 16 && (d.mmask || d.nmask)) return hipErrorInvalidValue;
-    {
+    if (cfg.staging == STAGE_PAIRS) {
+        hipError_t e = launch_prep_pairs(d, heads, s);
+        if (e != hipSuccess) return e;
+    } else {
         const int threads = 256;
         const int per_block = threads / kWave;  // one wave per individual
         hipLaunchKernelGGL(k_prep, dim3((d.n + per_block - 1) / per_block), dim3(threads), 0, s, d, heads);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (cfg.staging == STAGE_PAIRS) {
+        // (no tile and no LDS: a flat grid of chunk x group blocks)
+        const void *kp = pairs_kernel(d.flags, step_counter != nullptr);
+        const size_t lds = 0;
+        hipError_t e = set_lds(kp, lds);
+        if (e != hipSuccess) return e;
+        // (blocks: chunks per wave run; at most 64 individuals per wave)
+        if (cfg.blocks < 1 || cfg.P > 64 * cfg.W) return hipErrorInvalidValue;
+        ReqDesc dd = d;
+        const IndHead *hh = heads;
+        int32_t P = cfg.P, M = cfg.blocks, nt = (int32_t)((d.rows + 63) / 64);
+        unsigned long long *sc = step_counter;
+        void *params[] = {&dd, &hh, &P, &M, &nt, &sc};
+        if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
+        e = hipLaunchKernel(kp, dim3(pairs_grid(d.rows, d.n, cfg.P, M)), dim3(cfg.W * kWave), params, lds, s);
+        if (e != hipSuccess) return e;
+        if (ev1) e = hipEventRecord(ev1, s);
+        return e;
+    }
+    // Four words per row group make counts only (no mask outputs).
+    if (cfg.L == 16 && (d.mmask || d.nmask)) return hipErrorInvalidValue;
     const void *k = eval_kernel(cfg.L, d.flags, cfg.staging, step_counter != nullptr);
     if (!k) return hipErrorInvalidValue;
     const int32_t n_tiles = (int32_t)((d.rows + 63) / 64);

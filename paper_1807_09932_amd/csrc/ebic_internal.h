@@ -19,6 +19,7 @@ enum Staging : int32_t {
     STAGE_BYTES = 3,   // 8-bit rank codes, four rows per 32-bit lane word (4 or 8 sub-tiles)
     STAGE_HALVES = 4,  // 16-bit rank codes, two rows per 32-bit lane word (4 sub-tiles)
     STAGE_T10 = 5,     // 10-bit rank codes, three rows per 32-bit lane word (3 sub-tiles)
+    STAGE_PAIRS = 6,   // pairwise order bitmaps, 32 rows per lane word, nothing staged
 };
 
 // Rank codes are kept for matrices of at most this many columns: a cell's
@@ -65,6 +66,7 @@ constexpr uint32_t kFlagCodes = 1u << 10;  // this request stages the rank codes
 constexpr uint32_t kFlagBytes = 1u << 11;  // this request stages the byte rank codes
 constexpr uint32_t kFlagHalves = 1u << 12; // this request stages the 16-bit rank codes
 constexpr uint32_t kFlagT10 = 1u << 13;    // this request stages the 10-bit rank codes
+constexpr uint32_t kFlagPairs = 1u << 14;  // this request reads the pairwise order bitmaps
 
 // One launch shape of the evaluation kernels.
 struct LaunchCfg {
@@ -94,6 +96,9 @@ struct DevMatrix {
     int64_t ld10 = 0;              // bytes per column of T10 (256 per 192 rows)
     bool b_exclude = false;        // B also serves exclude mode (no missing cell)
     int64_t ldb = 0;               // bytes per column of B (multiple of 256)
+    const uint32_t *Gx = nullptr;  // pairwise order bitmaps of X (exclude mode), or null
+    const uint32_t *Gf = nullptr;  // of the fill-substituted values (include mode), or null
+    int64_t w32 = 0;               // 32-bit words per pair (whole 2048-row chunks)
     int64_t ld = 0;                // multiple of 64
     int64_t rows = 0;
     int32_t cols = 0;
@@ -104,7 +109,8 @@ struct DevMatrix {
 struct ReqDesc {
     const float *X;            // the matrix to read (the fill copy when it serves include mode)
     const uint16_t *C;         // the rank codes to stage (kFlagCodes), or null
-    const uint8_t *B;          // the byte, 16-bit or 10-bit rank codes to stage (kFlagBytes, kFlagHalves, kFlagT10)
+    const uint8_t *B;          // the byte, 16-bit or 10-bit rank codes to stage (kFlagBytes, kFlagHalves,
+                               // kFlagT10), or the pairwise order bitmaps (kFlagPairs; ldb = words per pair)
     const int32_t *T;          // their per-512-row tie flags
     int64_t ldb;               // bytes per column of B
     int64_t ld;
@@ -238,6 +244,22 @@ hipError_t launch_half_codes(const float *X, int64_t rows, int64_t ld, int32_t c
 // The same for 10-bit codes (cols <= kMaxT10Cols) into T10, ld10 bytes per
 // column (256 per 192-row group; T10 zeroed by the caller, the fields are
 // OR-ed in), and one tie flag per 192-row group.
+// Pairwise order bitmaps (ebic_pairs.hip): words per pair for `rows`, the
+// build of every pair's words from a column-major matrix (subst: NaN takes
+// `fill` first) with each 2,048-row chunk's list of tied pairs and NaN flag
+// in T (pair_tie_bytes, zeroed by the caller), the prep kernel writing the
+// pairs headers, the evaluation kernel for request flags (ReqDesc: B = the
+// words, T = the tie lists), and its grid.
+constexpr int32_t kMaxPairCols = 1024;
+constexpr int64_t kMaxPairBytes = 32ll << 30;
+int64_t pair_words(int64_t rows);
+int64_t pair_tie_bytes(int64_t rows);
+hipError_t launch_pair_bits(const float *X, int64_t rows, int64_t ld, int32_t cols, bool subst, float fill,
+                            uint32_t *G, int64_t w32, uint32_t *T, hipStream_t s);
+hipError_t launch_prep_pairs(const ReqDesc &d, IndHead *heads, hipStream_t s);
+const void *pairs_kernel(uint32_t flags, bool count);
+int64_t pair_chunks_per_slice(int64_t rows);
+unsigned pairs_grid(int64_t rows, int32_t n, int32_t P, int32_t M);
 hipError_t launch_t10_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
                             uint8_t *T10, int64_t ld10, int32_t *has_nan, int32_t *ties, hipStream_t s);
 

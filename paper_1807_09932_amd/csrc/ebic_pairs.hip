@@ -1,0 +1,449 @@
+// ebic_pairs.hip -- the predicate over pairwise order bitmaps.
+//
+// The trend relation of an individual (c_0, ..., c_{k-1}) on a row holds
+// when every consecutive pair does: x[r, c_j] >= x[r, c_{j-1}] for the
+// positive chain, x[r, c_{j-1}] >= x[r, c_j] for the reversed one (Methods,
+// "Handling missing values": the rows are counted by this relation). Both
+// chains are conjunctions over the individual's consecutive column pairs,
+// and there are only cols^2 ordered pairs. So the library can compare every
+// ordered pair of columns once per row, on first use, and keep the answers
+// as bitmaps:
+//
+//   G[a * cols + b] bit r  =  x[r, b] >= x[r, a]      (IEEE single: a NaN
+//                                                       on either side is 0)
+//
+// The diagonal pair (a, a) is then "x[r, a] is present". An individual's
+// positive chain on 32 rows is one AND per pair of one 32-bit word per
+// lane, its reversed chain the same over the reversed pairs, and a row
+// matched by both directions (constant along the individual) counts once,
+// as positive. The results are those of the comparisons themselves, bit for
+// bit: the bitmaps hold the compares' outcomes, ties and signed zeros
+// included.
+//
+// Layout: chunk by chunk (2,048 rows: one 32-bit word per lane of a wave),
+// and within a chunk pair by pair, pair (a, b) of chunk q at word
+// ((q * cols + a) * cols + b) * 64; bit i of a lane's word is row
+// 2048 q + 32 lane + i. Rows past the matrix are 0. A chunk's pairs span
+// cols^2 x 256 bytes, so a wave addresses them with 32-bit offsets from the
+// chunk's base. Include mode reads a second set built from the
+// fill-substituted values (the same set when no cell is missing).
+//
+// Behind the bitmaps, 512 bytes per chunk list its ties: word 0 counts the
+// entries, word 1 is non-zero if a NaN occurs in the chunk, and words
+// 64 .. 127 hold the byte offsets of both orders of each pair of different
+// columns with two equal values on some row (up to 32 pairs; a count past
+// 64 means more). Where a chunk has no NaN and a pair (a, b), a != b, is not
+// listed, every row has x_a, x_b present and distinct, so the reversed
+// pair's word is the complement of the pair's on the matrix's rows: the
+// reversed chain then needs no loads of its own.
+//
+// Evaluation: a wave per (individuals, run of chunks). A prep kernel writes each
+// individual's 64-byte pairs header: k, the CSR start, the byte offsets of
+// the pairs of its first eight columns (consecutive repeats left out: a
+// pair (c, c) is implied by the pairs next to it, and the first pair is of
+// two different columns), and the window's columns. Per individual and
+// chunk the wave loads the seven pairs, ANDs them, takes the reversed chain as their
+// complement where the chunk allows it (else loads the reversed pairs), and
+// follows the columns past the window eight at a time while any row is
+// left. No tile is staged: the words come through L2 and the Infinity
+// Cache, where the pairs shared by the individuals of a chunk are reused,
+// and the blocks of a chunk are placed on one XCD and walk its chunks
+// together. The counts of the wave's 2,048 rows are summed across lanes by
+// DPP (row shifts, then row broadcasts) into a lane of the wave's own, and
+// added to the outputs once per wave.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ebic_internal.h"
+#include "ebic_prep.h"
+
+namespace ebic {
+namespace {
+
+constexpr int kChunkRows = 2048;  // rows per wave step: 64 lanes x 32 rows
+constexpr int kChunkWords = 64;
+constexpr int kTieWords = 128;    // per chunk: count, NaN flag, ..., 64 listed offsets
+constexpr int kTieList = 64;      // (the list's first word)
+constexpr uint32_t kNoPair = 0xffffffffu;  // never a pair's offset (those are multiples of 256)
+
+// The pairs header (the IndHead storage, read differently).
+struct PairHead {
+    int32_t k;         // columns from begin (0: invalid)
+    int32_t begin;     // CSR start (the last leading repeat of the first column)
+    uint32_t fwd[7];   // byte offsets of the window's pairs of different columns (the last one repeated);
+                       // for k = 1, fwd[0] is the column's diagonal pair
+    uint32_t pad0;
+    uint32_t win[4];   // the window's eight columns, two per word (low half first)
+    uint32_t pad1[2];
+};
+static_assert(sizeof(PairHead) == sizeof(IndHead), "the pairs header reuses the header storage");
+
+__global__ void __launch_bounds__(256) k_prep_pairs(ReqDesc d, IndHead *__restrict__ heads)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int32_t i = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (i >= d.n) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const PrepScan sc = prep_scan(d, i, lane);
+    if (lane == 0) {
+        d.matched[i] = sc.ok ? 0 : kInvalid;
+        if (d.negative) d.negative[i] = sc.ok ? 0 : kInvalid;
+    }
+    uint32_t *hd = reinterpret_cast<uint32_t *>(heads + d.head_base + i);
+    // lane u < 7: window pair (u, u + 1); the pairs of different columns
+    // are packed to the front in order, the last one repeating after them
+    const uint32_t cb = (uint32_t)d.cols * 256u;
+    const uint32_t a = (uint32_t)__shfl(sc.win, 8 + min(lane, 7));
+    const uint32_t c = (uint32_t)__shfl(sc.win, 8 + min(lane + 1, 7));
+    const int q = (lane - 10) & 3;  // lanes 10..13: columns 2q, 2q + 1
+    const uint32_t pk = (uint32_t)__shfl(sc.win, 8 + 2 * q) | ((uint32_t)__shfl(sc.win, 9 + 2 * q) << 16);
+    const bool distinct = lane < 7 && a != c;
+    const uint64_t dm = __ballot(distinct);
+    const uint32_t off = a * cb + (c << 8);
+    const int nf = __popcll(dm);
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)a, 0);
+    // (one column: its diagonal pair, "present")
+    const uint32_t last = nf == 0 ? w0 * cb + (w0 << 8)
+                                  : (uint32_t)__builtin_amdgcn_readlane((int)off, 63 - __clzll(dm));
+    if (!sc.ok) {
+        if (lane < 16) hd[lane] = 0u;
+        return;
+    }
+    if (distinct) hd[2 + __popcll(dm & ((1ull << lane) - 1))] = off;
+    if (lane >= nf && lane < 7) hd[2 + lane] = last;
+    if (lane == 0) hd[0] = (uint32_t)sc.k;
+    if (lane == 1) hd[1] = (uint32_t)sc.bb;
+    if (lane == 9 || lane == 14 || lane == 15) hd[lane] = 0u;
+    if (lane >= 10 && lane < 14) hd[lane] = pk;
+}
+
+// Block (chunk, a) of one wave: for every b >= a, the words of pairs (a, b)
+// and (b, a) on the chunk's rows; lane l covers rows chunk*2048 + 32 l ...
+// + 31 (one 128-byte run of each column). Ties and NaN go to the chunk's
+// list (T, zeroed beforehand).
+__global__ void __launch_bounds__(64) k_pair_bits(const float *__restrict__ X, int64_t rows, int64_t ld,
+                                                  int32_t cols, int32_t subst, float fill,
+                                                  uint32_t *__restrict__ G, uint32_t *__restrict__ T)
+{
+    const int32_t a = (int32_t)blockIdx.y;
+    const int64_t chunk = blockIdx.x;
+    const int lane = (int)threadIdx.x;
+    const int64_t r0 = chunk * kChunkRows + 32 * lane;
+    // valid rows of this lane's 32 as a bit mask
+    const int64_t nvalid = rows - r0;
+    const uint32_t vmask = nvalid >= 32 ? 0xffffffffu : nvalid <= 0 ? 0u : ((1u << nvalid) - 1u);
+    auto load32 = [&](int32_t c, float (&v)[32]) {
+        if (r0 < ld) {
+            const float4 *p = reinterpret_cast<const float4 *>(X + (int64_t)c * ld + r0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float4 f = p[q];
+                v[4 * q] = f.x;
+                v[4 * q + 1] = f.y;
+                v[4 * q + 2] = f.z;
+                v[4 * q + 3] = f.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) v[i] = __builtin_nanf("");
+        }
+        if (subst) {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) v[i] = v[i] != v[i] ? fill : v[i];
+        }
+    };
+    uint32_t *tl = T + chunk * kTieWords;
+    const uint32_t cb = (uint32_t)cols * 256u;
+    float xa[32];
+    load32(a, xa);
+    for (int32_t b = a; b < cols; ++b) {
+        float xb[32];
+        load32(b, xb);
+        uint32_t ge = 0, le = 0;  // x_b >= x_a, x_a >= x_b
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            ge |= (xb[i] >= xa[i] ? 1u : 0u) << i;
+            le |= (xa[i] >= xb[i] ? 1u : 0u) << i;
+        }
+        G[((chunk * cols + a) * cols + b) * kChunkWords + lane] = ge & vmask;
+        if (b != a) G[((chunk * cols + b) * cols + a) * kChunkWords + lane] = le & vmask;
+        const uint32_t odd = (b == a ? ~ge : (ge & le)) & vmask;  // NaN rows; tied rows
+        if (__ballot(odd != 0) != 0 && lane == 0) {
+            if (b == a) {
+                atomicOr(tl + 1, 1u);
+            } else {
+                const uint32_t slot = atomicAdd(tl, 2u);
+                if (slot + 2 <= (uint32_t)kTieList) {
+                    tl[kTieList + slot] = (uint32_t)a * cb + ((uint32_t)b << 8);
+                    tl[kTieList + slot + 1] = (uint32_t)b * cb + ((uint32_t)a << 8);
+                }
+            }
+        }
+    }
+}
+
+// Sum over the wave's 64 lanes, returned to every lane: an inclusive scan
+// within each row of 16 lanes (row shifts by 1, 2, 4, 8), then row 0's
+// total added into row 1 and row 2's into row 3 (row broadcast of lane 15),
+// then lane 31's into rows 2 and 3 (row broadcast of lane 31): lane 63 holds
+// the sum.
+__device__ __forceinline__ uint32_t wave_total(uint32_t v)
+{
+    int s = (int)v;
+    s += __builtin_amdgcn_update_dpp(0, s, 0x111, 0xf, 0xf, true);   // row_shr:1
+    s += __builtin_amdgcn_update_dpp(0, s, 0x112, 0xf, 0xf, true);   // row_shr:2
+    s += __builtin_amdgcn_update_dpp(0, s, 0x114, 0xf, 0xf, true);   // row_shr:4
+    s += __builtin_amdgcn_update_dpp(0, s, 0x118, 0xf, 0xf, true);   // row_shr:8
+    s += __builtin_amdgcn_update_dpp(0, s, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    s += __builtin_amdgcn_update_dpp(0, s, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane(s, 63);
+}
+
+// Block b works on XCD slice x = b mod 8 (the chunks x, x + 8, x + 16, ...,
+// which on MI355X's round-robin placement of blocks over the eight XCDs all
+// run on one XCD and share its L2) and, with j = b / 8, on group j mod G of
+// at most P individuals and on the j / G-th run of M consecutive chunks of
+// the slice. Its waves take the group's individuals in turn (at most 64 per
+// wave) and walk the run chunk by chunk, all of them on the same chunk at
+// about the same time; each lane of a wave keeps the counts of one of the
+// wave's individuals, added to the outputs once at the end.
+template <bool NEG, bool COUNT>
+__global__ void __launch_bounds__(1024) k_eval_pairs(ReqDesc d, const IndHead *__restrict__ heads, int32_t P,
+                                                     int32_t M, int32_t n_tiles, unsigned long long *step_counter)
+{
+    const int32_t n_chunks = (n_tiles + 31) / 32;
+    const int32_t per_slice = (n_chunks + 7) / 8;
+    const int32_t G_groups = (d.n + P - 1) / P;
+    const uint32_t b = blockIdx.x, j = b / 8;
+    const int32_t slice = (int32_t)(b % 8);
+    const int32_t run = (int32_t)(j / G_groups), grp = (int32_t)(j % G_groups);
+    const int32_t m0 = run * M;
+    if (m0 >= per_slice) return;
+    const int32_t m1 = min(m0 + M, per_slice);
+    const int32_t i0 = grp * P;
+    const int32_t np = min(P, d.n - i0);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int W = blockDim.x / kWave;
+
+    const int32_t C = d.cols;
+    const uint32_t cb = (uint32_t)C * 256u;  // pairs (a, 0 .. C-1) of a chunk
+    const int voff = lane * 4;
+    const PairHead *hb = reinterpret_cast<const PairHead *>(heads + d.head_base + i0);
+    // mask words (as 32-bit halves, little-endian: the uint64 layout)
+    const int64_t words32 = 2 * ((d.rows + 63) / 64);
+    const bool masks = d.mmask || d.nmask;
+    uint32_t acc_m = 0, acc_g = 0;  // lane t: the wave's t-th individual
+    uint64_t steps = 0;
+
+    for (int32_t m = m0; m < m1; ++m) {
+        const int32_t chunk = 8 * m + slice;
+        if (chunk >= n_chunks) break;
+        const uint32_t *gchunk = reinterpret_cast<const uint32_t *>(d.B) + (int64_t)chunk * C * C * kChunkWords;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(gchunk), (short)0, C * C * 256, 0x00020000);
+        // pair (a, c) of the chunk, this lane's word: offset a * C * 256 + c * 256
+        auto ld = [&](uint32_t off) { return __builtin_amdgcn_raw_buffer_load_b32(rs, voff, (int)off, 0); };
+        // The chunk's ties: lane l holds listed offset l (kNoPair past the
+        // count); `dirty` when the list overflowed or a NaN occurs.
+        const uint32_t *tl = reinterpret_cast<const uint32_t *>(d.T) + (int64_t)chunk * kTieWords;
+        const uint32_t n_tied = __builtin_amdgcn_readfirstlane(tl[0]);
+        const bool dirty = n_tied > (uint32_t)kTieList || __builtin_amdgcn_readfirstlane(tl[1]) != 0;
+        const uint32_t tied = (uint32_t)lane < n_tied ? tl[kTieList + lane] : kNoPair;
+        const bool clean = n_tied == 0 && !dirty;
+        const int64_t nvalid = d.rows - ((int64_t)chunk * kChunkRows + 32 * lane);
+        const uint32_t vmask = nvalid >= 32 ? 0xffffffffu : nvalid <= 0 ? 0u : ((1u << nvalid) - 1u);
+        // may the reversed chain over these pair offsets be the complement?
+        auto untied = [&](const uint32_t *off, int n) {
+            if (clean) return true;
+            if (dirty) return false;
+            bool hit = false;
+            for (int t = 0; t < n; ++t) hit |= tied == off[t];
+            return __ballot(hit) == 0;
+        };
+        const int64_t word = (int64_t)chunk * kChunkWords + lane;
+        const bool store = word < words32;
+
+        // The reversed chain of the window from its columns (loads of the
+        // reversed pairs; (c, c): "present", implied by the pairs next to it).
+        auto slow_window = [&](const uint32_t (&wp)[4]) {
+            uint32_t q[7];
+#pragma unroll
+            for (int u = 0; u < 7; ++u) {
+                const uint32_t a = (wp[u >> 1] >> ((u & 1) * 16)) & 0xffffu;
+                const uint32_t c = (wp[(u + 1) >> 1] >> (((u + 1) & 1) * 16)) & 0xffffu;
+                q[u] = ld(c * cb + (a << 8));
+            }
+            return q[0] & q[1] & q[2] & q[3] & q[4] & q[5] & q[6];
+        };
+        // The columns past the window, eight at a time (the last one
+        // repeated past the end), while a row is left.
+        auto tail = [&](uint32_t &Pw, uint32_t &Nw, int32_t k, int32_t begin, uint32_t prev) {
+            const int32_t *cc = d.colidx + begin;
+            for (int32_t u = 8; u < k; u += 8) {
+                uint32_t cn[8], fo[8], pp[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) cn[e] = (uint32_t)__builtin_amdgcn_readfirstlane(cc[min(u + e, k - 1)]);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    fo[e] = (e == 0 ? prev : cn[e - 1]) * cb + (cn[e] << 8);
+                    pp[e] = ld(fo[e]);
+                }
+                Pw &= pp[0] & pp[1] & pp[2] & pp[3] & pp[4] & pp[5] & pp[6] & pp[7];
+                if (NEG) {
+                    if (untied(fo, 8)) {
+                        // (c, c) pairs: "present", all the chunk's rows
+                        uint32_t nq = 0;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) nq |= (e == 0 ? prev : cn[e - 1]) == cn[e] ? 0u : pp[e];
+                        Nw &= ~nq;
+                    } else {
+                        uint32_t qq[8];
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) qq[e] = ld(cn[e] * cb + ((e == 0 ? prev : cn[e - 1]) << 8));
+                        Nw &= qq[0] & qq[1] & qq[2] & qq[3] & qq[4] & qq[5] & qq[6] & qq[7];
+                    }
+                }
+                prev = cn[7];
+                if (COUNT) steps += (uint64_t)min(8, k - u);
+                if (__ballot((Pw | Nw) != 0) == 0) break;
+            }
+        };
+        // Masks and counts of the wave's t-th individual (ii).
+        auto finish = [&](uint32_t Pw, uint32_t Nw, int32_t ii, int32_t t) {
+            const uint32_t mw = Pw | Nw, gw = NEG ? (Nw & ~Pw) : 0u;
+            if (masks && store) {
+                if (d.mmask) reinterpret_cast<uint32_t *>(d.mmask)[(int64_t)(i0 + ii) * words32 + word] = mw;
+                if (d.nmask) reinterpret_cast<uint32_t *>(d.nmask)[(int64_t)(i0 + ii) * words32 + word] = gw;
+            }
+            if (__ballot(mw != 0) == 0) return;
+            const uint32_t both =
+                wave_total((uint32_t)__builtin_popcount(mw) | ((uint32_t)__builtin_popcount(gw) << 16));
+            if (lane == t) {
+                acc_m += both & 0xffffu;
+                if (NEG) acc_g += both >> 16;
+            }
+        };
+
+        // Two individuals at a time (ii and ii + W, the wave's t-th and
+        // (t + 1)-th): both windows' loads in flight together. The window
+        // needs no branch: an individual of one column has the diagonal
+        // pair in every slot (its reversed chain, whatever it gives, adds
+        // nothing: its rows are all positive), and an invalid one (k = 0)
+        // is zeroed after the loads.
+        int32_t t = 0;
+        for (int32_t ii = wave; ii < np; ii += 2 * W, t += 2) {
+            const bool two = ii + W < np;
+            const int4 *ha = reinterpret_cast<const int4 *>(hb + ii);
+            const int4 *hc = reinterpret_cast<const int4 *>(hb + (two ? ii + W : ii));
+            const int4 a0 = ha[0], a1 = ha[1], a2 = ha[2], a3 = ha[3];
+            const int4 b0 = hc[0], b1 = hc[1], b2 = hc[2], b3 = hc[3];
+            const int32_t ka = __builtin_amdgcn_readfirstlane(a0.x), kb = __builtin_amdgcn_readfirstlane(b0.x);
+            const uint32_t fa[7] = {(uint32_t)__builtin_amdgcn_readfirstlane(a0.z),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(a0.w),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(a1.x),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(a1.y),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(a1.z),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(a1.w),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(a2.x)};
+            const uint32_t fb[7] = {(uint32_t)__builtin_amdgcn_readfirstlane(b0.z),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(b0.w),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(b1.x),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(b1.y),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(b1.z),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(b1.w),
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(b2.x)};
+            uint32_t pa[7], pb[7];
+#pragma unroll
+            for (int u = 0; u < 7; ++u) {
+                pa[u] = ld(fa[u]);
+                pb[u] = ld(fb[u]);
+            }
+            uint32_t Pa = pa[0] & pa[1] & pa[2] & pa[3] & pa[4] & pa[5] & pa[6];
+            uint32_t Pb = pb[0] & pb[1] & pb[2] & pb[3] & pb[4] & pb[5] & pb[6];
+            uint32_t Na = 0, Nb = 0;
+            if (NEG) {
+                const uint32_t wa[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(a2.z),
+                                        (uint32_t)__builtin_amdgcn_readfirstlane(a2.w),
+                                        (uint32_t)__builtin_amdgcn_readfirstlane(a3.x),
+                                        (uint32_t)__builtin_amdgcn_readfirstlane(a3.y)};
+                const uint32_t wb[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(b2.z),
+                                        (uint32_t)__builtin_amdgcn_readfirstlane(b2.w),
+                                        (uint32_t)__builtin_amdgcn_readfirstlane(b3.x),
+                                        (uint32_t)__builtin_amdgcn_readfirstlane(b3.y)};
+                Na = untied(fa, 7) ? ~(pa[0] | pa[1] | pa[2] | pa[3] | pa[4] | pa[5] | pa[6]) & vmask
+                                   : slow_window(wa);
+                Nb = untied(fb, 7) ? ~(pb[0] | pb[1] | pb[2] | pb[3] | pb[4] | pb[5] | pb[6]) & vmask
+                                   : slow_window(wb);
+            }
+            if (ka == 0) Pa = Na = 0u;
+            if (kb == 0) Pb = Nb = 0u;
+            if (COUNT) steps += (ka > 1 ? 7 : ka) + (two ? (kb > 1 ? 7 : kb) : 0);
+            if (ka > 8 && __ballot((Pa | Na) != 0) != 0)
+                tail(Pa, Na, ka, __builtin_amdgcn_readfirstlane(a0.y),
+                     (uint32_t)__builtin_amdgcn_readfirstlane(a3.y) >> 16);
+            finish(Pa, Na, ii, t);
+            if (two) {
+                if (kb > 8 && __ballot((Pb | Nb) != 0) != 0)
+                    tail(Pb, Nb, kb, __builtin_amdgcn_readfirstlane(b0.y),
+                         (uint32_t)__builtin_amdgcn_readfirstlane(b3.y) >> 16);
+                finish(Pb, Nb, ii + W, t + 1);
+            }
+        }
+    }
+    // the wave's individuals wave + t W, t = lane
+    const int32_t ii = wave + lane * W;
+    if (ii < np) {
+        if (acc_m) atomicAdd(d.matched + i0 + ii, (int32_t)acc_m);
+        if (NEG && acc_g && d.negative) atomicAdd(d.negative + i0 + ii, (int32_t)acc_g);
+    }
+    if (COUNT && lane == 0 && steps) atomicAdd(step_counter, (unsigned long long)steps);
+}
+
+}  // namespace
+
+int64_t pair_words(int64_t rows) { return (rows + kChunkRows - 1) / kChunkRows * kChunkWords; }
+
+int64_t pair_tie_bytes(int64_t rows)
+{
+    return (rows + kChunkRows - 1) / kChunkRows * kTieWords * (int64_t)sizeof(uint32_t);
+}
+
+hipError_t launch_pair_bits(const float *X, int64_t rows, int64_t ld, int32_t cols, bool subst, float fill,
+                            uint32_t *G, int64_t w32, uint32_t *T, hipStream_t s)
+{
+    if (cols < 1 || cols > kMaxPairCols || w32 != pair_words(rows) || ld % 64 != 0) return hipErrorInvalidValue;
+    const int64_t chunks = w32 / kChunkWords;
+    if (chunks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pair_bits, dim3((unsigned)chunks, (unsigned)cols), dim3(64), 0, s, X, rows, ld, cols,
+                       subst ? 1 : 0, fill, G, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_pairs(const ReqDesc &d, IndHead *heads, hipStream_t s)
+{
+    const int threads = 256;
+    const int per_block = threads / kWave;  // one wave per individual
+    hipLaunchKernelGGL(k_prep_pairs, dim3((d.n + per_block - 1) / per_block), dim3(threads), 0, s, d, heads);
+    return hipGetLastError();
+}
+
+const void *pairs_kernel(uint32_t flags, bool count)
+{
+    const bool neg = (flags & kFlagNeg) != 0;
+    if (count) return neg ? (const void *)&k_eval_pairs<true, true> : (const void *)&k_eval_pairs<false, true>;
+    return neg ? (const void *)&k_eval_pairs<true, false> : (const void *)&k_eval_pairs<false, false>;
+}
+
+int64_t pair_chunks_per_slice(int64_t rows) { return ((rows + kChunkRows - 1) / kChunkRows + 7) / 8; }
+
+// Blocks of the pairs launch: 8 XCD slices x groups x runs of M chunks.
+unsigned pairs_grid(int64_t rows, int32_t n, int32_t P, int32_t M)
+{
+    const int64_t groups = (n + P - 1) / P;
+    const int64_t runs = (pair_chunks_per_slice(rows) + M - 1) / M;
+    return (unsigned)(8 * groups * runs);
+}
+
+}  // namespace ebic

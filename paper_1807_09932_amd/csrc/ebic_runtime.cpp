@@ -250,6 +250,72 @@ void build_half_codes(ebic_ctx *ctx, Matrix &m)
     log_msg(2, "built 16-bit rank codes: " + std::to_string(hbytes) + " bytes");
 }
 
+// The words of every pair, then each 2,048-row chunk's list of tied pairs.
+static int64_t pairs_word_bytes(const Matrix &m)
+{
+    return (int64_t)m.dev.cols * m.dev.cols * pair_words(m.dev.rows) * (int64_t)sizeof(uint32_t);
+}
+
+static int64_t pairs_mark_bytes(const Matrix &m) { return pair_tie_bytes(m.dev.rows); }
+
+static int64_t pairs_bytes(const Matrix &m) { return pairs_word_bytes(m) + pairs_mark_bytes(m); }
+
+static const uint32_t *pairs_marks(const Matrix &m, const uint32_t *G)
+{
+    return G + pairs_word_bytes(m) / (int64_t)sizeof(uint32_t);
+}
+
+bool pairs_buildable(const Matrix &m)
+{
+    return m.dev.cols <= kMaxPairCols && pairs_bytes(m) <= kMaxPairBytes;
+}
+
+// The bitmaps a mode reads: exclude mode those of X; include mode those of
+// the fill-substituted values, which are X's own when no cell is missing.
+static const uint32_t *pairs_for(const Matrix &m, bool include)
+{
+    if (!include) return m.Gx;
+    if (m.has_missing == 0) return m.Gx;
+    return m.Gf;
+}
+
+void build_pairs(ebic_ctx *ctx, Matrix &m, bool include)
+{
+    if (pairs_for(m, include)) return;
+    if (!pairs_buildable(m))
+        fail(EBIC_EINVAL, "pairwise order bitmaps serve matrices of at most " + std::to_string(kMaxPairCols) +
+                              " columns and " + std::to_string(kMaxPairBytes >> 30) + " GiB");
+    const bool subst = include && m.has_missing != 0;  // (unknown counts as missing)
+    DeviceGuard g(ctx->device);
+    const int64_t w32 = pair_words(m.dev.rows);
+    const size_t gbytes = (size_t)pairs_bytes(m);
+    uint32_t *G = static_cast<uint32_t *>(ctx_alloc(ctx, gbytes));
+    hipStream_t s = nullptr;
+    try {
+        hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+        uint32_t *F = const_cast<uint32_t *>(pairs_marks(m, G));
+        hip_check(hipMemsetAsync(F, 0, (size_t)pairs_mark_bytes(m), s), "hipMemsetAsync");
+        hip_check(launch_pair_bits(m.X, m.dev.rows, m.dev.ld, m.dev.cols, subst, m.dev.fill, G, w32, F, s),
+                  "pair bitmaps kernel");
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        hip_check(hipStreamDestroy(s), "hipStreamDestroy");
+        s = nullptr;
+    } catch (...) {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        ctx_free(ctx, G);
+        throw;
+    }
+    if (subst) m.Gf = G, m.dev.Gf = G;
+    else m.Gx = G, m.dev.Gx = G;
+    m.dev.w32 = w32;
+    m.bytes += gbytes;
+    log_msg(2, std::string("built pairwise order bitmaps") + (subst ? " of the fill-substituted values" : "") +
+                   ": " + std::to_string(gbytes) + " bytes");
+}
+
 // Launch shape for one population on one matrix.
 LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t flags, CodesMode codes, bool masks)
 {
@@ -281,6 +347,32 @@ LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t f
     auto have_swar = [&](int32_t st) {
         return st == STAGE_BYTES ? have_bytes : st == STAGE_HALVES ? have_halves : st == STAGE_T10 ? have_t10 : false;
     };
+    // Pairwise order bitmaps (built on first use where they fit): no tile,
+    // one wave per individual and 2,048-row chunk.
+    if (cfg.staging == STAGE_PAIRS) {
+        const bool have_pairs = pairs_for(m, include) != nullptr || (codes != CODES_EXISTING && pairs_buildable(m));
+        if (have_pairs) {
+            // (blocks: the chunks of an XCD slice one wave walks, 0 = as
+            // many runs of chunks as fill the device)
+            cfg.L = 1;
+            cfg.cnt16 = false;
+            cfg.P = std::max(1, std::min({cfg.P, 64 * cfg.W, std::max(1, n)}));
+            const int64_t per_slice = pair_chunks_per_slice(m.dev.rows);
+            if (cfg.blocks > 0) {
+                cfg.blocks = (int32_t)std::min<int64_t>(cfg.blocks, per_slice);
+            } else {
+                const int64_t groups = (std::max(1, n) + cfg.P - 1) / cfg.P;
+                const int64_t waves = 8 * groups * cfg.W;          // one run per slice
+                const int64_t target = (int64_t)ctx->cu_count * 32;  // resident waves at full occupancy
+                const int64_t runs = std::min<int64_t>(per_slice, std::max<int64_t>(1, (target + waves - 1) / waves));
+                cfg.blocks = (int32_t)((per_slice + runs - 1) / runs);
+            }
+            if (!pairs_for(m, include) && codes == CODES_BUILD) build_pairs(ctx, m, include);
+            return cfg;
+        }
+        cfg.staging = STAGE_BYTES;  // (falls through to the kinds the matrix has)
+        cfg.L = 8;
+    }
     const bool asked_swar = cfg.staging == STAGE_BYTES || cfg.staging == STAGE_HALVES || cfg.staging == STAGE_T10;
     if (asked_swar && !have_swar(cfg.staging)) {
         const int32_t order[3] = {STAGE_BYTES, STAGE_T10, STAGE_HALVES};
@@ -392,6 +484,14 @@ ReqDesc make_desc(const Matrix &m, int32_t n, const int32_t *offsets, const int3
         d.T = m.dev.Tt;
         d.ldb = m.dev.ld10;
         d.flags |= kFlagT10;
+    }
+    if (staging == STAGE_PAIRS) {
+        const uint32_t *G = pairs_for(m, include);
+        if (!G) fail(EBIC_EINVAL, "no pairwise order bitmaps for this matrix and mode");
+        d.B = reinterpret_cast<const uint8_t *>(G);
+        d.T = reinterpret_cast<const int32_t *>(pairs_marks(m, G));
+        d.ldb = m.dev.w32;
+        d.flags |= kFlagPairs;
     }
     if (staging == STAGE_DIRECT) {
         d.flags |= kFlagDirect;
@@ -576,6 +676,8 @@ ebic_status ebic_destroy(ebic_ctx *ctx)
                 ctx_free(ctx, kv.second.B);
                 ctx_free(ctx, kv.second.Hc);
                 ctx_free(ctx, kv.second.T10);
+                ctx_free(ctx, kv.second.Gx);
+                ctx_free(ctx, kv.second.Gf);
             }
             ctx->matrices.clear();
             destroy_batch_state(ctx);
@@ -770,6 +872,8 @@ ebic_status ebic_upload_matrix(ebic_ctx *ctx, const float *src, int64_t rows, in
             ctx_free(ctx, m.B);
             ctx_free(ctx, m.Hc);
             ctx_free(ctx, m.T10);
+            ctx_free(ctx, m.Gx);
+            ctx_free(ctx, m.Gf);
             throw;
         }
         ctx_free(ctx, staging);
@@ -803,7 +907,8 @@ ebic_status ebic_matrix_get_stats(ebic_ctx *ctx, int32_t matrix, ebic_matrix_sta
         st.cols = m.dev.cols;
         st.code_sets = (m.Xfill ? EBIC_SET_FILL_COPY : 0u) | (m.C ? EBIC_SET_FP16 : 0u) |
                        (m.Cfill ? EBIC_SET_FP16_FILL : 0u) | (m.B ? EBIC_SET_U8 : 0u) | (m.Hc ? EBIC_SET_U16 : 0u) |
-                       (m.T10 ? EBIC_SET_U10 : 0u);
+                       (m.T10 ? EBIC_SET_U10 : 0u) | (m.Gx ? EBIC_SET_PAIRS : 0u) |
+                       (m.Gf ? EBIC_SET_PAIRS_FILL : 0u);
         st.value_bytes = (int64_t)m.value_bytes;
         st.code_bytes = (int64_t)(m.bytes - m.value_bytes);
         st.has_missing = m.has_missing;
@@ -853,6 +958,8 @@ ebic_status ebic_release_matrix(ebic_ctx *ctx, int32_t matrix)
         ctx_free(ctx, m.B);
         ctx_free(ctx, m.Hc);
         ctx_free(ctx, m.T10);
+        ctx_free(ctx, m.Gx);
+        ctx_free(ctx, m.Gf);
         ctx->matrices.erase(matrix);
         log_msg(2, "released matrix " + std::to_string(matrix));
     });

@@ -25,6 +25,8 @@ struct Matrix {
     uint8_t *B = nullptr;       // byte rank codes (cols <= kMaxByteCols)
     uint8_t *Hc = nullptr;      // 16-bit rank codes (kMaxByteCols < cols <= kMaxCodeCols)
     uint8_t *T10 = nullptr;     // 10-bit rank codes (kMaxByteCols < cols <= kMaxT10Cols)
+    uint32_t *Gx = nullptr;     // pairwise order bitmaps of X (built on first use)
+    uint32_t *Gf = nullptr;     // of the fill-substituted values (include mode, cells missing)
     size_t bytes = 0;        // everything resident for this matrix
     size_t value_bytes = 0;  // X and Xfill
     float sentinel = 0.f;
@@ -229,6 +231,8 @@ void build_fp16_codes(ebic_ctx *ctx, Matrix &m, bool include);
 // they can serve a mode, and their build (under ctx->mu).
 bool halves_buildable(const Matrix &m, bool include);
 void build_half_codes(ebic_ctx *ctx, Matrix &m);
+bool pairs_buildable(const Matrix &m);
+void build_pairs(ebic_ctx *ctx, Matrix &m, bool include);
 LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t flags,
                     CodesMode codes = CODES_BUILD, bool masks = false);
 // The kernels' view of one request; `staging` decides whether include mode

@@ -158,7 +158,8 @@ static void read_cache(std::map<TuneKey, LaunchCfg> &out, const std::string &pat
             // file is skipped)
             const bool L_ok = c.L == 1 || c.L == 2 || c.L == 3 || c.L == 4 || c.L == 6 || c.L == 8 || c.L == 16;
             const bool stg_ok = c.staging == STAGE_LDS || c.staging == STAGE_DIRECT || c.staging == STAGE_CODES ||
-                                c.staging == STAGE_BYTES || c.staging == STAGE_HALVES || c.staging == STAGE_T10;
+                                c.staging == STAGE_BYTES || c.staging == STAGE_HALVES || c.staging == STAGE_T10 ||
+                                c.staging == STAGE_PAIRS;
             if ((k.kind == 0 || k.kind == 1) && L_ok && c.W >= 1 && c.W <= 16 && c.P >= 1 && stg_ok) out[k] = c;
         }
     }
@@ -283,7 +284,8 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
               tiles_per_wave == 6 || tiles_per_wave == 8 || tiles_per_wave == 16) ||
             waves_per_block < 1 || waves_per_block > 16 || individuals_per_group < 1 ||
             !(staging == STAGE_LDS || staging == STAGE_DIRECT || staging == STAGE_CODES ||
-              staging == STAGE_BYTES || staging == STAGE_HALVES || staging == STAGE_T10) ||
+              staging == STAGE_BYTES || staging == STAGE_HALVES || staging == STAGE_T10 ||
+              staging == STAGE_PAIRS) ||
             blocks < 0)
             fail(EBIC_EINVAL, "launch shape out of range");
         LaunchCfg c;

@@ -43,6 +43,7 @@ STAGE_CODES = 2   # FP16 rank codes staged in LDS (matrices of <= 384 columns)
 STAGE_BYTES = 3   # byte rank codes, four rows per lane word (<= 128 columns; 4 or 8 tiles per wave)
 STAGE_HALVES = 4  # 16-bit rank codes, two rows per lane word (129..384 columns; 2 or 4 tiles per wave)
 STAGE_T10 = 5     # 10-bit rank codes, three rows per lane word (129..512 columns; 3 tiles per wave)
+STAGE_PAIRS = 6   # pairwise order bitmaps, 32 rows per lane word (<= 1,024 columns; built on first use)
 
 EXPORTED = ["ebic_create", "ebic_destroy", "ebic_set_allocator", "ebic_last_error",
             "ebic_upload_matrix", "ebic_matrix_info", "ebic_matrix_get_stats", "ebic_release_matrix",
@@ -89,6 +90,7 @@ class ebic_matrix_stats(ctypes.Structure):
 
 
 SET_FILL_COPY, SET_FP16, SET_FP16_FILL, SET_U8, SET_U16, SET_U10 = 1, 2, 4, 8, 16, 32
+SET_PAIRS, SET_PAIRS_FILL = 64, 128
 
 
 class ebic_ea_params(ctypes.Structure):
