@@ -45,7 +45,13 @@ T10_PEAK_TOPS = CMP_PEAK_TOPS * 3 / 2.5
 STAGE_BYTES = 3
 STAGE_HALVES = 4
 STAGE_T10 = 5
+STAGE_PAIRS = 6
 SWAR_STAGES = (STAGE_BYTES, STAGE_HALVES, STAGE_T10)
+# The L2 the pair bitmaps come through: per XCD 16 channels x 128 B per
+# clock, eight XCDs at 2.4 GHz: 39.3 TB/s.
+L2_PEAK_GBS = 8 * 16 * 128 * 2.4e9 / 1e9
+PAIR_CHUNK_ROWS = 2048  # rows of one 32-bit word per lane of a wave
+PAIR_WORD_BYTES = 256   # one pair's words on one chunk (64 lanes x 4 B)
 ROWS_PER_OP = {STAGE_BYTES: 4, STAGE_HALVES: 2, STAGE_T10: 3}
 
 
@@ -62,11 +68,59 @@ def alu_roofline(steps, k_ms, staging):
             "frac": ach / CMP_PEAK_TOPS}
 
 
+def pair_window_pairs(offs, cols, ncols):
+    """The distinct ordered column pairs the pair-bitmap kernel reads for
+    every chunk: per individual, the pairs of different columns among its
+    first eight (after a leading run of repeats of the first column), or
+    the one column's diagonal pair."""
+    seen = set()
+    for i in range(offs.size - 1):
+        c = [int(v) for v in cols[offs[i]:offs[i + 1]]]
+        if not c or min(c) < 0 or max(c) >= ncols:
+            seen.add((0, 0))  # (an invalid individual's header reads pair 0)
+            continue
+        j = 0
+        while j + 1 < len(c) and c[j + 1] == c[0]:
+            j += 1
+        w = c[j:j + 8]
+        w += [w[-1]] * (8 - len(w))
+        pairs = {(w[u], w[u + 1]) for u in range(7) if w[u] != w[u + 1]}
+        seen |= pairs or {(w[0], w[0])}
+    return len(seen)
+
+
+def pairs_roofline(offs, cols, rows, ncols, steps, k_ms):
+    """The HBM roofline of the pair-bitmap kernel: its algorithmic bytes are
+    the words of the distinct window pairs on every 2,048-row chunk (each
+    read once per launch), the chunks' tie lists, the individuals' headers
+    and the counts, over the kernel time."""
+    n = offs.size - 1
+    chunks = -(-rows // PAIR_CHUNK_ROWS)
+    d = pair_window_pairs(offs, cols, ncols)
+    nbytes = d * PAIR_WORD_BYTES * chunks + 512 * chunks + 64 * n + 8 * n
+    t = k_ms * 1e-3
+    ach = nbytes / t / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "algorithmic_bytes": nbytes, "distinct_window_pairs": d, "chunks": chunks,
+            "l2_view": {"bytes": steps * PAIR_WORD_BYTES, "achieved": steps * PAIR_WORD_BYTES / t / 1e9,
+                        "peak": L2_PEAK_GBS, "unit": "GB/s",
+                        "frac": steps * PAIR_WORD_BYTES / t / 1e9 / L2_PEAK_GBS,
+                        "note": "pair-word loads executed (window and tail, counted by the "
+                                "measurement variant) x 256 B, against the L2's 16 channels x "
+                                "128 B per clock per XCD"}}
+
+
+def kernel_roofline(stg, steps, k_ms, offs, cols, rows, ncols):
+    if stg == STAGE_PAIRS:
+        return pairs_roofline(offs, cols, rows, ncols, steps, k_ms)
+    return alu_roofline(steps, k_ms, stg)
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("ebic_eval.hip", "ebic_chain.inc", "ebic_internal.h")
+KERNEL_SOURCES = ("ebic_eval.hip", "ebic_chain.inc", "ebic_internal.h", "ebic_pairs.hip", "ebic_prep.h")
 
 
 def kernel_sources_sha():
@@ -206,7 +260,17 @@ def roofline_views(executed_steps, k_ms, staging, matrix_bytes, n_ind):
                     "two FP32 compares; above 1 for rank codes, whose one 32-bit lane operation "
                     "compares four (u8), three (u10) or two (u16) rows"},
     }
-    if staging not in SWAR_STAGES:
+    if staging == STAGE_PAIRS:
+        # (a pair step ANDs one 32-bit word per lane: 2,048 rows of one
+        # column pair, the outcome of 2,048 FP32 compares made at the build)
+        views["fp32_compare_issue"] = {
+            "bound": "alu", "achieved": executed_steps * PAIR_CHUNK_ROWS / t / 1e12, "peak": CMP_PEAK_TOPS,
+            "unit": "T compare outcomes/s",
+            "frac": executed_steps * PAIR_CHUNK_ROWS / t / 1e12 / CMP_PEAK_TOPS,
+            "note": "executed pair steps x 2,048 rows: the FP32 compare outcomes the kernel "
+                    "combines, as if each were a lane compare; above 1 because the bitmaps hold "
+                    "32 outcomes per lane word"}
+    elif staging not in SWAR_STAGES:
         views["fp32_compare_issue"]["note"] = ("executed 64-row column steps x 2 compares x 64 lanes "
                                                "over the kernel time")
     return views
@@ -311,17 +375,33 @@ def bench_batched(ctx, args):
         "executed_compares": b_steps,
         "launch_shape": "L=%d W=%d P=%d stagings=%s blocks=%d" % (bL, bW, bP, sorted(set(b_stg)),
                                                                   b_grid),
-        "roofline": {**alu_roofline(b_steps, g_ms, b_stg[0] if len(set(b_stg)) == 1 else None),
-                     "traffic": (traffic_from_profile(1, "k_eval_batch_100000x256_traffic.json",
-                                                      (bL, bW, bP, b_stg[0]))
-                                 if len(set(b_stg)) == 1 else None),
-                     "traffic_note": "HBM bytes per launch of the persistent kernel (committed FETCH_SIZE / "
-                                     "WRITE_SIZE summary): each staged chunk is read once per group of P "
-                                     "individuals of each population, mostly from the Infinity Cache"},
+        "roofline": batched_roofline(b_steps, g_ms, b_stg, (bL, bW, bP), packed, rows, w.X.shape[1]),
         "timing": "median of %d synchronised calls; batched = one ebic_eval_batch (descriptor "
                   "copy + graph replay), plain = 64 ebic_eval_population calls" % reps,
         "upload": upload,
     }
+
+
+def batched_roofline(steps, g_ms, stagings, shape, packed, rows, ncols):
+    """The batched launch's roofline: on the pair bitmaps, their HBM roofline
+    over all populations together (the words of the distinct window pairs
+    of every population, once per chunk: the batch walks each chunk for all
+    of them); on rank codes, the compare-issue roofline."""
+    one = len(set(stagings)) == 1
+    if one and stagings[0] == STAGE_PAIRS:
+        offs = np.concatenate([[0]] + [o[1:] + sum(int(q[0][-1]) for q in packed[:i])
+                                       for i, (o, _) in enumerate(packed)]).astype(np.int64)
+        cols = np.concatenate([c[:int(o[-1])] for o, c in packed])
+        return {**pairs_roofline(offs, cols, rows, ncols, steps, g_ms),
+                "traffic": traffic_from_profile(1, "k_eval_pairs_batch_100000x256_traffic.json",
+                                                shape + (STAGE_PAIRS,)),
+                "time": "the graph replay (descriptor copy, prep, the persistent pairs kernel)"}
+    return {**alu_roofline(steps, g_ms, stagings[0] if one else None),
+            "traffic": (traffic_from_profile(1, "k_eval_batch_100000x256_traffic.json", shape + (stagings[0],))
+                        if one else None),
+            "traffic_note": "HBM bytes per launch of the persistent kernel (committed FETCH_SIZE / "
+                            "WRITE_SIZE summary): each staged chunk is read once per group of P "
+                            "individuals of each population, mostly from the Infinity Cache"}
 
 
 def bench_fp32(ctx, args, w, offs, cols):
@@ -510,7 +590,7 @@ def bench_paper_shape(ctx, args):
             "roofline_views": roofline_views(steps, k_ms, stg, w.X.nbytes, p.n),
             "launch_shape": f"{how}: L={L} W={W} P={P} staging={stg} blocks={blocks}",
             "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
-            "roofline": {**alu_roofline(steps, k_ms, stg),
+            "roofline": {**kernel_roofline(stg, steps, k_ms, offs, cols, rows, ncols),
                          "traffic": traffic_from_profile(1, "k_eval_methylation_wide_436444x310_traffic.json",
                                                          (L, W, P, stg))},
             "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9}
@@ -560,7 +640,7 @@ def bench_shard(ctx, args, w, offs, cols):
                         "%d individuals" % (step, rows, ncols, p.n),
             "launch_shape": f"L={L} W={W} P={P} staging={stg} blocks={blocks}",
             "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
-            "roofline": alu_roofline(steps, k_ms, stg)}
+            "roofline": kernel_roofline(stg, steps, k_ms, offs, cols, step, ncols)}
 
 
 def bench_served(ctx, args):
@@ -902,7 +982,7 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = checks / (wall / args.steps)
     k_ms = kernel_ms / max(1, launches)
-    roof = alu_roofline(executed_steps, k_ms, stg)
+    roof = kernel_roofline(stg, executed_steps, k_ms, offs, cols, rows, ncols)
 
     # End-to-end latency of one generation's evaluation as the host EA sees
     # it: CSR to the device, evaluation, counts back to the host.
@@ -927,12 +1007,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {STAGE_BYTES: "u8", STAGE_HALVES: "u16", STAGE_T10: "u10", 2: "f16"}.get(stg, "f32"),
-        "dtype_note": "the type the evaluation kernel compares: the rank codes it stages "
+        "dtype": {STAGE_BYTES: "u8", STAGE_HALVES: "u16", STAGE_T10: "u10", 2: "f16",
+                  STAGE_PAIRS: "u1"}.get(stg, "f32"),
+        "dtype_note": "the type the evaluation kernel works on: the FP32 compares' outcomes "
+                      "as bits (u1: the pairwise order bitmaps, 32 rows per 32-bit lane word, "
+                      "combined by AND), the rank codes it stages "
                       "(u8: byte codes, four per 32-bit lane word; u10: 10-bit codes, three per "
                       "word; u16: two per word; f16: FP16 "
-                      "codes) or the FP32 values; the resident matrix and the code build are "
-                      "FP32, and the counts are exact integers",
+                      "codes) or the FP32 values; the resident matrix and the bitmap and code "
+                      "builds are FP32 compares, and the counts are exact integers",
         "data": "synthetic",
         "config": {
             "workload": "methylation-shaped plain eval: %d x %d FP32 Beta(0.5,0.5), 10 planted "
@@ -943,7 +1026,7 @@ def main():
         "roofline": {
             **roof,
             "traffic": traffic_from_profile(1, shape=(L, W, P, stg)),
-            "kernel": "k_eval",
+            "kernel": "k_eval_pairs" if stg == STAGE_PAIRS else "k_eval",
             "launch_shape": shape_note,
             "kernel_ms": k_ms,
             "kernel_ms_cold_cache": cold_ms,
@@ -952,7 +1035,13 @@ def main():
                       "records around each evaluation kernel on its stream, over a second "
                       "pass of the same K steps (that pass took %.4f ms per step: the events "
                       "cost GPU time)" % (wall_events * 1e3 / args.steps),
-            "ops": (("row checks executed per launch: %d steps x 64 rows (one step = one column "
+            "ops": (("pair bitmaps: per 2,048-row chunk, the words (256 B) of each of the "
+                     "population's %d distinct window pairs, read once per launch, plus 512 B of "
+                     "tie list per chunk and 72 B per individual (header, counts); %d pair steps "
+                     "executed (a wave's AND of one pair word per lane over 2,048 rows, window "
+                     "and tail)" % (roof["distinct_window_pairs"], executed_steps))
+                    if stg == STAGE_PAIRS else
+                    ("row checks executed per launch: %d steps x 64 rows (one step = one column "
                      "of one 64-row sub-tile; the first pair counts one step; early exit per "
                      "chunk of %d lane word(s) per lane), counted by the measurement variant of "
                      "the kernel; peak = 39.3e12 32-bit VALU lane ops/s x %d rows per lane op / "

@@ -292,14 +292,13 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
  *                              first use: cols^2 x ceil(rows / 2048) x 256
  *                              bytes plus 512 bytes per 2,048 rows, at most
  *                              1,024 columns and 32 GiB); nothing staged,
- *                              tiles_per_wave ignored, at most 64
- *                              individuals per wave, and `blocks` is the
- *                              number of 2,048-row chunks a wave walks (0:
- *                              enough runs of chunks to fill the device);
- *                              without them (too large, or the
+ *                              tiles_per_wave and blocks ignored, at most
+ *                              64 individuals per wave (individuals_per_group
+ *                              0 with a shape of this staging: chosen from
+ *                              the work); without them (too large, or the
  *                              allocation-free entry point before they are
  *                              built) the launch takes the rank codes the
- *                              matrix has. Batches never use them.
+ *                              matrix has.
  *   blocks:                grid size per group, 0 = from occupancy
  * Shapes that do not fit the device are reduced at launch (fewer tiles per
  * wave, then direct reads). Results never depend on the shape.

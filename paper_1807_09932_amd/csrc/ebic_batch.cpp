@@ -33,14 +33,20 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Header, request descriptors, prefix sums of individuals, the pair
+// queues and segments (requests on pair bitmaps), then the items.
 struct ArenaLayout {
-    size_t hdr = 0, descs = 0, first = 0, items = 0, bytes = 0;
+    size_t hdr = 0, descs = 0, first = 0, pq = 0, segs = 0, seg_req = 0, seg_gstart = 0, items = 0, bytes = 0;
     ArenaLayout(int32_t n_req, int32_t n_items)
     {
         hdr = 0;
         descs = align256(sizeof(BatchHeader));
         first = align256(descs + sizeof(ReqDesc) * (size_t)n_req);
-        items = align256(first + sizeof(int64_t) * (size_t)(n_req + 1));
+        pq = align256(first + sizeof(int64_t) * (size_t)(n_req + 1));
+        segs = align256(pq + sizeof(PairQueues));
+        seg_req = align256(segs + sizeof(PairSeg) * (size_t)n_req);
+        seg_gstart = align256(seg_req + sizeof(int32_t) * (size_t)n_req);
+        items = align256(seg_gstart + sizeof(int32_t) * (size_t)n_req);
         bytes = align256(items + sizeof(Item) * (size_t)n_items);
     }
 };
@@ -60,8 +66,11 @@ struct GraphEntry {
     std::mutex mu;  // one replay at a time per graph (its pinned buffers alternate)
 };
 
+// (stream, L, W, P, tile bytes, grid, capacities, counting, kernel set,
+// which kernels run: 1 the tiled one, 2 the pairs one; the pairs kernel's
+// W, P and grid)
 using GraphKey = std::tuple<hipStream_t, int32_t, int32_t, int32_t, int64_t, int32_t, int32_t,
-                            int32_t, int64_t, bool, int32_t>;
+                            int32_t, int64_t, bool, int32_t, int32_t, int32_t, int32_t, int32_t>;
 
 void check(hipError_t e, const char *what) { hip_check(e, what); }
 
@@ -116,6 +125,13 @@ struct Plan {
     size_t tile_bytes = 0;
     int64_t total_ind = 0;
     int32_t grid = 0;
+    // Requests on the pair bitmaps: their kernel's shape and queues.
+    bool pairs_shape = false;   // the shape asks for the bitmaps
+    int32_t pW = 4, pP = 0, pgrid = 0;
+    PairQueues pq{};
+    std::vector<PairSeg> segs;
+    std::vector<int32_t> seg_req, seg_gstart;
+    bool any_pairs() const { return !segs.empty(); }
 };
 
 static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, bool count, CodesMode codes)
@@ -145,6 +161,16 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     int64_t total = 0;
     for (int32_t q = 0; q < n_reqs; ++q) total += std::max(0, reqs[q].n_ind);
     p.cfg = batch_cfg(ctx, total, mean_rows, max_cols, -1);
+    // (the bitmaps up to 512 columns, or up to 1,024 under a forced shape)
+    const int32_t pair_cols = ctx->override_cfg.W > 0 ? kMaxPairCols : kDefaultPairCols;
+    if (p.cfg.staging == STAGE_PAIRS) {
+        // The bitmaps' kernel takes this shape; requests that cannot read
+        // bitmaps take the rank codes' default shape.
+        p.pairs_shape = true;
+        p.pW = std::max(1, std::min(16, p.cfg.W));
+        p.pP = p.cfg.P;
+        p.cfg = default_batch_codes_cfg(max_cols);
+    }
     LaunchCfg &c = p.cfg;
     const size_t lds_max = ctx->lds_per_block - 256;  // room for the kernel's static LDS
     if (c.L == 8) c.L = 4;  // (batches stage at most four sub-tiles per chunk)
@@ -159,11 +185,40 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     // the FP16 rank codes when the shape asks for codes (or the FP32 tile
     // does not fit) and they exist and fit; else the FP32 tile if it fits
     // next to the counts, else direct reads.
-    std::vector<int32_t> tiles_of;  // sub-tiles per chunk, per request
+    std::vector<int32_t> tiles_of;  // sub-tiles per chunk, per request (0: on the pair bitmaps)
     for (int32_t q = 0; q < n_reqs; ++q) {
         const ebic_request &r = reqs[q];
         Matrix &m = ctx_matrix_mut(ctx, r.matrix);
         const bool include = (r.flags & EBIC_NAN_INCLUDE) != 0;
+        if (p.pairs_shape && r.n_ind > 0 && m.dev.cols <= pair_cols) {
+            // The pair bitmaps where they exist or can be built (a report
+            // plans them unbuilt: its descriptors are never launched).
+            bool have = pairs_for(m, include) != nullptr;
+            if (!have && codes != CODES_EXISTING && pairs_buildable(m) && !m.pairs_failed) {
+                have = true;
+                if (codes == CODES_BUILD) {
+                    try {
+                        build_pairs(ctx, m, include);
+                    } catch (const Error &e) {
+                        if (e.code != EBIC_ENOMEM) throw;
+                        m.pairs_failed = true;
+                        have = false;
+                        log_msg(1, std::string("pair bitmaps not built (") + e.what() + "): rank codes instead");
+                    }
+                }
+            }
+            if (have) {
+                const bool built = pairs_for(m, include) != nullptr;
+                ReqDesc d = make_desc(m, r.n_ind, r.d_offsets, r.d_cols, r.flags, r.d_matched, r.d_negative,
+                                      r.d_matched_mask, r.d_negative_mask, built ? STAGE_PAIRS : STAGE_LDS);
+                d.head_base = p.first.back();
+                p.stagings.push_back(STAGE_PAIRS);
+                tiles_of.push_back(0);
+                p.descs.push_back(d);
+                p.first.push_back(p.first.back() + d.n);
+                continue;
+            }
+        }
         // FP16 codes not resident yet count as available when they can be
         // built; they are built below if this request stages them.
         const bool built_codes = (include ? m.dev.Cfill : m.dev.C) != nullptr;
@@ -210,7 +265,7 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     {
         int32_t used = 0;
         for (size_t q = 0; q < p.stagings.size(); ++q) {
-            if (p.descs[q].n <= 0) continue;
+            if (p.descs[q].n <= 0 || p.stagings[q] == STAGE_PAIRS) continue;
             const int32_t stg = p.stagings[q];
             used |= stg == STAGE_BYTES ? kBatchSetBytes
                     : stg == STAGE_HALVES ? kBatchSetHalves
@@ -229,7 +284,8 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     // ranges so that the whole batch has about 8 items per resident block,
     // in proportion to each request's work (individuals x tiles).
     double units = 0;
-    for (auto &d : p.descs) units += (double)d.n * (double)((d.rows + 63) / 64);
+    for (int32_t q = 0; q < n_reqs; ++q)
+        if (tiles_of[q] > 0) units += (double)p.descs[q].n * (double)((p.descs[q].rows + 63) / 64);
     const double target = 8.0 * p.grid;
     struct Est {
         Item it;
@@ -238,7 +294,7 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     std::vector<Est> est;
     for (int32_t q = 0; q < n_reqs; ++q) {
         const ReqDesc &d = p.descs[q];
-        if (d.n == 0) continue;
+        if (d.n == 0 || tiles_of[q] == 0) continue;
         const int64_t tiles = (d.rows + 63) / 64;
         const int32_t Lq = tiles_of[q];
         const int64_t chunks = (tiles + Lq - 1) / Lq;  // ranges start on a multiple of Lq tiles
@@ -264,6 +320,65 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
     std::stable_sort(est.begin(), est.end(), [](const Est &a, const Est &b) { return a.cost > b.cost; });
     p.items.reserve(est.size());
     for (auto &e : est) p.items.push_back(e.it);
+
+    // The pair requests: segments by bitmap set (requests in order), groups
+    // of pP individuals, and per XCD slice the items of each segment (its
+    // chunks of that slice x its groups).
+    {
+        int64_t ind_chunks = 0;
+        for (int32_t q = 0; q < n_reqs; ++q)
+            if (p.stagings[q] == STAGE_PAIRS && p.descs[q].n > 0)
+                ind_chunks += (int64_t)p.descs[q].n * ((p.descs[q].rows + 2047) / 2048);
+        if (p.pairs_shape && ind_chunks > 0) {
+            if (p.pP <= 0) {
+                // individuals per wave: up to 8 where the work gives at least
+                // two waves per resident slot
+                const int64_t slots = (int64_t)ctx->cu_count * 32;
+                p.pP = (int32_t)(p.pW * std::max<int64_t>(1, std::min<int64_t>(8, ind_chunks / (2 * slots))));
+            }
+            p.pP = std::max(1, std::min(p.pP, 64 * p.pW));
+            std::vector<const uint8_t *> keys;
+            for (int32_t q = 0; q < n_reqs; ++q) {
+                const ReqDesc &d = p.descs[q];
+                if (p.stagings[q] != STAGE_PAIRS || d.n <= 0) continue;
+                size_t g = 0;
+                while (g < keys.size() && keys[g] != d.B) ++g;
+                if (g == keys.size()) {
+                    keys.push_back(d.B);
+                    PairSeg sg{};
+                    sg.n_chunks = (int32_t)((d.rows + 2047) / 2048);
+                    p.segs.push_back(sg);
+                }
+            }
+            // entries grouped by segment, requests in order within each
+            for (size_t g = 0; g < keys.size(); ++g) {
+                PairSeg &sg = p.segs[g];
+                sg.e0 = (int32_t)p.seg_req.size();
+                for (int32_t q = 0; q < n_reqs; ++q) {
+                    const ReqDesc &d = p.descs[q];
+                    if (p.stagings[q] != STAGE_PAIRS || d.n <= 0 || d.B != keys[g]) continue;
+                    p.seg_req.push_back(q);
+                    p.seg_gstart.push_back(sg.groups);
+                    sg.groups += (d.n + p.pP - 1) / p.pP;
+                    ++sg.n_req;
+                }
+            }
+            for (int x = 0; x < 8; ++x) {
+                int64_t k = 0;
+                for (auto &sg : p.segs) {
+                    sg.base[x] = (int32_t)k;
+                    const int64_t in_slice = sg.n_chunks > x ? (sg.n_chunks - x + 7) / 8 : 0;
+                    k += in_slice * sg.groups;
+                }
+                if (k > INT32_MAX) fail(EBIC_EINVAL, "batch too large for one launch");
+                p.pq.total[x] = (int32_t)k;
+            }
+            p.pq.n_seg = (int32_t)p.segs.size();
+            int occ = pairs_batch_occupancy(p.pW);
+            if (occ <= 0) occ = 1;
+            p.pgrid = std::max(8, ctx->cu_count * occ / 8 * 8);
+        }
+    }
     (void)count;
     return p;
 }
@@ -288,8 +403,9 @@ static GraphSpec graph_spec(hipStream_t s, const Plan &p, bool count)
     g.cap_req = (int32_t)pow2(std::max<int64_t>(64, (int64_t)p.descs.size()));
     g.cap_items = (int32_t)pow2(std::max<int64_t>(8192, (int64_t)p.items.size()));
     g.cap_ind = pow2(std::max<int64_t>(16384, p.total_ind));
+    const int32_t kernels = (p.items.empty() ? 0 : 1) | (p.any_pairs() ? 2 : 0);
     g.key = GraphKey{s, p.cfg.L, p.cfg.W, p.cfg.P, (int64_t)p.tile_bytes, p.grid, g.cap_req, g.cap_items,
-                     g.cap_ind, count, p.set};
+                     g.cap_ind, count, p.set, kernels, p.pW, p.pP, p.pgrid};
     return g;
 }
 
@@ -324,7 +440,15 @@ static std::unique_ptr<GraphEntry> capture_graph(ebic_ctx *ctx, const GraphSpec 
                              reinterpret_cast<const ReqDesc *>(da + lay.descs),
                              reinterpret_cast<const int64_t *>(da + lay.first),
                              reinterpret_cast<const Item *>(da + lay.items), g->d_heads, p.cfg.L,
-                             p.set, p.cfg.W, p.cfg.P, p.tile_bytes, p.grid, prep_blocks, counter, cs);
+                             p.set, p.cfg.W, p.cfg.P, p.tile_bytes, p.items.empty() ? 0 : p.grid, prep_blocks,
+                             counter, cs);
+        if (e == hipSuccess && p.any_pairs())
+            e = launch_pairs_batch(reinterpret_cast<PairQueues *>(da + lay.pq),
+                                   reinterpret_cast<const ReqDesc *>(da + lay.descs),
+                                   reinterpret_cast<const PairSeg *>(da + lay.segs),
+                                   reinterpret_cast<const int32_t *>(da + lay.seg_req),
+                                   reinterpret_cast<const int32_t *>(da + lay.seg_gstart), g->d_heads, p.pW, p.pP,
+                                   p.pgrid, counter, cs);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         check(e, "batch capture");
@@ -368,8 +492,13 @@ extern "C" ebic_status ebic_plan_batch_shape(ebic_ctx *ctx, const ebic_request *
         const Plan p = plan_batch(ctx, reqs, n_reqs, false, CODES_REPORT);
         if (tiles_per_wave) *tiles_per_wave = p.cfg.L;
         if (waves_per_block) *waves_per_block = p.cfg.W;
-        if (individuals_per_group) *individuals_per_group = p.cfg.P;
-        if (blocks) *blocks = p.grid;
+        // (a batch with no request on the tiled kernel reports the pairs
+        // kernel's shape)
+        const bool pairs_only = p.items.empty() && p.any_pairs();
+        if (tiles_per_wave && pairs_only) *tiles_per_wave = 1;
+        if (waves_per_block && pairs_only) *waves_per_block = p.pW;
+        if (individuals_per_group) *individuals_per_group = pairs_only ? p.pP : p.cfg.P;
+        if (blocks) *blocks = pairs_only ? p.pgrid : p.grid;
         if (stagings)
             for (int32_t q = 0; q < n_reqs; ++q) stagings[q] = p.stagings[q];
     });
@@ -394,7 +523,7 @@ extern "C" ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, 
             for (int32_t q = 0; q < n_reqs; ++q)
                 if (reqs[q].n_ind > 0) hold.add_locked(reqs[q].matrix);
         }
-        if (p.items.empty()) return;  // every population is empty
+        if (p.items.empty() && !p.any_pairs()) return;  // every population is empty
         const bool count = (prof_mode & 2) != 0;
         const GraphSpec spec = graph_spec(s, p, count);
         GraphEntry *g = nullptr;
@@ -436,6 +565,12 @@ extern "C" ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, 
         std::memcpy(h + cap.hdr, &bh, sizeof(bh));
         std::memcpy(h + cap.descs, p.descs.data(), sizeof(ReqDesc) * p.descs.size());
         std::memcpy(h + cap.first, p.first.data(), sizeof(int64_t) * p.first.size());
+        std::memcpy(h + cap.pq, &p.pq, sizeof(PairQueues));  // (counters zero)
+        if (!p.segs.empty()) {
+            std::memcpy(h + cap.segs, p.segs.data(), sizeof(PairSeg) * p.segs.size());
+            std::memcpy(h + cap.seg_req, p.seg_req.data(), sizeof(int32_t) * p.seg_req.size());
+            std::memcpy(h + cap.seg_gstart, p.seg_gstart.data(), sizeof(int32_t) * p.seg_gstart.size());
+        }
         std::memcpy(h + cap.items, p.items.data(), sizeof(Item) * p.items.size());
         const size_t used = cap.items + sizeof(Item) * p.items.size();
         check(hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy_node, g->d_arena, h, used,

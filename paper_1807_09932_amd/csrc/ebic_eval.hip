@@ -104,7 +104,10 @@ __global__ void __launch_bounds__(256) k_prep_batch(BatchHeader *hdr, const ReqD
             if (first[mid] <= g) lo = mid;
             else hi = mid - 1;
         }
-        prep_wave(descs[lo], (int32_t)(g - first[lo]), heads, threadIdx.x & (kWave - 1));
+        if (descs[lo].flags & kFlagPairs)
+            prep_pairs_wave(descs[lo], (int32_t)(g - first[lo]), heads, threadIdx.x & (kWave - 1));
+        else
+            prep_wave(descs[lo], (int32_t)(g - first[lo]), heads, threadIdx.x & (kWave - 1));
     }
 }
 
@@ -2638,15 +2641,15 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
         const size_t lds = 0;
         hipError_t e = set_lds(kp, lds);
         if (e != hipSuccess) return e;
-        // (blocks: chunks per wave run; at most 64 individuals per wave)
-        if (cfg.blocks < 1 || cfg.P > 64 * cfg.W) return hipErrorInvalidValue;
+        // (at most 64 individuals per wave)
+        if (cfg.P > 64 * cfg.W) return hipErrorInvalidValue;
         ReqDesc dd = d;
         const IndHead *hh = heads;
-        int32_t P = cfg.P, M = cfg.blocks, nt = (int32_t)((d.rows + 63) / 64);
+        int32_t P = cfg.P, nt = (int32_t)((d.rows + 63) / 64);
         unsigned long long *sc = step_counter;
-        void *params[] = {&dd, &hh, &P, &M, &nt, &sc};
+        void *params[] = {&dd, &hh, &P, &nt, &sc};
         if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-        e = hipLaunchKernel(kp, dim3(pairs_grid(d.rows, d.n, cfg.P, M)), dim3(cfg.W * kWave), params, lds, s);
+        e = hipLaunchKernel(kp, dim3(pairs_grid(d.rows, d.n, cfg.P)), dim3(cfg.W * kWave), params, lds, s);
         if (e != hipSuccess) return e;
         if (ev1) e = hipEventRecord(ev1, s);
         return e;
@@ -2718,6 +2721,7 @@ hipError_t launch_batch(BatchHeader *hdr, const ReqDesc *descs, const int64_t *f
     hipLaunchKernelGGL(k_prep_batch, dim3(prep_blocks), dim3(256), 0, s, hdr, descs, first, heads);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (grid <= 0) return hipSuccess;  // (no request on the tiled kernel)
     const void *k = batch_kernel(L, set, step_counter != nullptr);
     if (!k) return hipErrorInvalidValue;
     const size_t lds = tile_bytes + count_bytes_of(P);

@@ -251,6 +251,7 @@ hipError_t launch_half_codes(const float *X, int64_t rows, int64_t ld, int32_t c
 // pairs headers, the evaluation kernel for request flags (ReqDesc: B = the
 // words, T = the tie lists), and its grid.
 constexpr int32_t kMaxPairCols = 1024;
+constexpr int32_t kDefaultPairCols = 512;  // widths planned on the bitmaps unless a shape says otherwise
 constexpr int64_t kMaxPairBytes = 32ll << 30;
 int64_t pair_words(int64_t rows);
 int64_t pair_tie_bytes(int64_t rows);
@@ -258,8 +259,29 @@ hipError_t launch_pair_bits(const float *X, int64_t rows, int64_t ld, int32_t co
                             uint32_t *G, int64_t w32, uint32_t *T, hipStream_t s);
 hipError_t launch_prep_pairs(const ReqDesc &d, IndHead *heads, hipStream_t s);
 const void *pairs_kernel(uint32_t flags, bool count);
-int64_t pair_chunks_per_slice(int64_t rows);
-unsigned pairs_grid(int64_t rows, int32_t n, int32_t P, int32_t M);
+unsigned pairs_grid(int64_t rows, int32_t n, int32_t P);
+
+// The pair items of a batch: eight queues, one per XCD slice (a slice: the
+// chunks c with c mod 8 = x), each walking its chunks in order segment by
+// segment; a segment is the requests reading one set of bitmaps, listed in
+// the entries e0 .. e0 + n_req - 1 of seg_req (request index) and seg_gstart
+// (the request's first group within the segment, groups of P individuals).
+struct PairQueues {
+    uint32_t counter[8];  // next item per queue (zero in the copied arena)
+    int32_t total[8];     // items per queue
+    int32_t n_seg;
+    int32_t pad[7];
+};
+struct PairSeg {
+    int32_t e0, n_req;
+    int32_t groups;    // groups over the segment's requests
+    int32_t n_chunks;  // 2,048-row chunks of its matrix
+    int32_t base[8];   // the segment's first item in each queue
+};
+hipError_t launch_pairs_batch(PairQueues *pq, const ReqDesc *descs, const PairSeg *segs, const int32_t *seg_req,
+                              const int32_t *seg_gstart, const IndHead *heads, int32_t W, int32_t P, int32_t grid,
+                              unsigned long long *step_counter, hipStream_t s);
+int pairs_batch_occupancy(int32_t W);  // blocks per CU of the batched pairs kernel
 hipError_t launch_t10_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
                             uint8_t *T10, int64_t ld10, int32_t *has_nan, int32_t *ties, hipStream_t s);
 

@@ -37,20 +37,21 @@
 // pair's word is the complement of the pair's on the matrix's rows: the
 // reversed chain then needs no loads of its own.
 //
-// Evaluation: a wave per (individuals, run of chunks). A prep kernel writes each
-// individual's 64-byte pairs header: k, the CSR start, the byte offsets of
-// the pairs of its first eight columns (consecutive repeats left out: a
-// pair (c, c) is implied by the pairs next to it, and the first pair is of
-// two different columns), and the window's columns. Per individual and
-// chunk the wave loads the seven pairs, ANDs them, takes the reversed chain as their
-// complement where the chunk allows it (else loads the reversed pairs), and
-// follows the columns past the window eight at a time while any row is
-// left. No tile is staged: the words come through L2 and the Infinity
-// Cache, where the pairs shared by the individuals of a chunk are reused,
-// and the blocks of a chunk are placed on one XCD and walk its chunks
+// Evaluation: a block per (group of individuals, chunk), its waves taking
+// the group's individuals in turn. A prep kernel writes each individual's
+// 64-byte pairs header: k, the CSR start, the byte offsets of the pairs of
+// its first eight columns (consecutive repeats left out: a pair (c, c) is
+// implied by the pairs next to it, and the first pair is of two different
+// columns), and the window's columns. Per individual and chunk the wave
+// loads the seven pairs (two individuals' at a time), ANDs them, takes the
+// reversed chain as their complement where the chunk allows it (else loads
+// the reversed pairs), and follows the columns past the window eight at a
+// time while any row is left. No tile is staged: the words come through L2
+// and the Infinity Cache, where the pairs shared by the individuals of a
+// chunk are reused, and the blocks of a chunk are placed on one XCD and run
 // together. The counts of the wave's 2,048 rows are summed across lanes by
 // DPP (row shifts, then row broadcasts) into a lane of the wave's own, and
-// added to the outputs once per wave.
+// added to the outputs once per item.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -67,55 +68,11 @@ constexpr int kTieWords = 128;    // per chunk: count, NaN flag, ..., 64 listed 
 constexpr int kTieList = 64;      // (the list's first word)
 constexpr uint32_t kNoPair = 0xffffffffu;  // never a pair's offset (those are multiples of 256)
 
-// The pairs header (the IndHead storage, read differently).
-struct PairHead {
-    int32_t k;         // columns from begin (0: invalid)
-    int32_t begin;     // CSR start (the last leading repeat of the first column)
-    uint32_t fwd[7];   // byte offsets of the window's pairs of different columns (the last one repeated);
-                       // for k = 1, fwd[0] is the column's diagonal pair
-    uint32_t pad0;
-    uint32_t win[4];   // the window's eight columns, two per word (low half first)
-    uint32_t pad1[2];
-};
-static_assert(sizeof(PairHead) == sizeof(IndHead), "the pairs header reuses the header storage");
-
 __global__ void __launch_bounds__(256) k_prep_pairs(ReqDesc d, IndHead *__restrict__ heads)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int32_t i = blockIdx.x * (blockDim.x / kWave) + wave;
-    if (i >= d.n) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const PrepScan sc = prep_scan(d, i, lane);
-    if (lane == 0) {
-        d.matched[i] = sc.ok ? 0 : kInvalid;
-        if (d.negative) d.negative[i] = sc.ok ? 0 : kInvalid;
-    }
-    uint32_t *hd = reinterpret_cast<uint32_t *>(heads + d.head_base + i);
-    // lane u < 7: window pair (u, u + 1); the pairs of different columns
-    // are packed to the front in order, the last one repeating after them
-    const uint32_t cb = (uint32_t)d.cols * 256u;
-    const uint32_t a = (uint32_t)__shfl(sc.win, 8 + min(lane, 7));
-    const uint32_t c = (uint32_t)__shfl(sc.win, 8 + min(lane + 1, 7));
-    const int q = (lane - 10) & 3;  // lanes 10..13: columns 2q, 2q + 1
-    const uint32_t pk = (uint32_t)__shfl(sc.win, 8 + 2 * q) | ((uint32_t)__shfl(sc.win, 9 + 2 * q) << 16);
-    const bool distinct = lane < 7 && a != c;
-    const uint64_t dm = __ballot(distinct);
-    const uint32_t off = a * cb + (c << 8);
-    const int nf = __popcll(dm);
-    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)a, 0);
-    // (one column: its diagonal pair, "present")
-    const uint32_t last = nf == 0 ? w0 * cb + (w0 << 8)
-                                  : (uint32_t)__builtin_amdgcn_readlane((int)off, 63 - __clzll(dm));
-    if (!sc.ok) {
-        if (lane < 16) hd[lane] = 0u;
-        return;
-    }
-    if (distinct) hd[2 + __popcll(dm & ((1ull << lane) - 1))] = off;
-    if (lane >= nf && lane < 7) hd[2 + lane] = last;
-    if (lane == 0) hd[0] = (uint32_t)sc.k;
-    if (lane == 1) hd[1] = (uint32_t)sc.bb;
-    if (lane == 9 || lane == 14 || lane == 15) hd[lane] = 0u;
-    if (lane >= 10 && lane < 14) hd[lane] = pk;
+    if (i < d.n) prep_pairs_wave(d, i, heads, threadIdx.x & (kWave - 1));
 }
 
 // Block (chunk, a) of one wave: for every b >= a, the words of pairs (a, b)
@@ -200,33 +157,14 @@ __device__ __forceinline__ uint32_t wave_total(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane(s, 63);
 }
 
-// Block b works on XCD slice x = b mod 8 (the chunks x, x + 8, x + 16, ...,
-// which on MI355X's round-robin placement of blocks over the eight XCDs all
-// run on one XCD and share its L2) and, with j = b / 8, on group j mod G of
-// at most P individuals and on the j / G-th run of M consecutive chunks of
-// the slice. Its waves take the group's individuals in turn (at most 64 per
-// wave) and walk the run chunk by chunk, all of them on the same chunk at
-// about the same time; each lane of a wave keeps the counts of one of the
-// wave's individuals, added to the outputs once at the end.
+// One work item: individuals [i0, i0 + np) of a request on one 2,048-row
+// chunk, by the W waves of a block (the wave's individuals in turn, at most
+// 64 per wave); each lane of a wave keeps the counts of one of the wave's
+// individuals, added to the outputs at the end.
 template <bool NEG, bool COUNT>
-__global__ void __launch_bounds__(1024) k_eval_pairs(ReqDesc d, const IndHead *__restrict__ heads, int32_t P,
-                                                     int32_t M, int32_t n_tiles, unsigned long long *step_counter)
+__device__ __forceinline__ void pairs_item(const ReqDesc &d, const IndHead *__restrict__ heads, int32_t i0,
+                                           int32_t np, int32_t chunk, int lane, int wave, int W, uint64_t &steps)
 {
-    const int32_t n_chunks = (n_tiles + 31) / 32;
-    const int32_t per_slice = (n_chunks + 7) / 8;
-    const int32_t G_groups = (d.n + P - 1) / P;
-    const uint32_t b = blockIdx.x, j = b / 8;
-    const int32_t slice = (int32_t)(b % 8);
-    const int32_t run = (int32_t)(j / G_groups), grp = (int32_t)(j % G_groups);
-    const int32_t m0 = run * M;
-    if (m0 >= per_slice) return;
-    const int32_t m1 = min(m0 + M, per_slice);
-    const int32_t i0 = grp * P;
-    const int32_t np = min(P, d.n - i0);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int W = blockDim.x / kWave;
-
     const int32_t C = d.cols;
     const uint32_t cb = (uint32_t)C * 256u;  // pairs (a, 0 .. C-1) of a chunk
     const int voff = lane * 4;
@@ -235,11 +173,8 @@ __global__ void __launch_bounds__(1024) k_eval_pairs(ReqDesc d, const IndHead *_
     const int64_t words32 = 2 * ((d.rows + 63) / 64);
     const bool masks = d.mmask || d.nmask;
     uint32_t acc_m = 0, acc_g = 0;  // lane t: the wave's t-th individual
-    uint64_t steps = 0;
 
-    for (int32_t m = m0; m < m1; ++m) {
-        const int32_t chunk = 8 * m + slice;
-        if (chunk >= n_chunks) break;
+    {
         const uint32_t *gchunk = reinterpret_cast<const uint32_t *>(d.B) + (int64_t)chunk * C * C * kChunkWords;
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(gchunk), (short)0, C * C * 256, 0x00020000);
@@ -398,6 +333,82 @@ __global__ void __launch_bounds__(1024) k_eval_pairs(ReqDesc d, const IndHead *_
         if (acc_m) atomicAdd(d.matched + i0 + ii, (int32_t)acc_m);
         if (NEG && acc_g && d.negative) atomicAdd(d.negative + i0 + ii, (int32_t)acc_g);
     }
+}
+
+// The plain launch: block b works on XCD slice x = b mod 8 (the chunks x,
+// x + 8, x + 16, ..., which on MI355X's round-robin placement of blocks over
+// the eight XCDs all run on one XCD and share its L2) and, with j = b / 8,
+// on group j mod G of at most P individuals and on the slice's (j / G)-th
+// chunk: the blocks of a chunk are dispatched together.
+template <bool NEG, bool COUNT>
+__global__ void __launch_bounds__(1024) k_eval_pairs(ReqDesc d, const IndHead *__restrict__ heads, int32_t P,
+                                                     int32_t n_tiles, unsigned long long *step_counter)
+{
+    const int32_t n_chunks = (n_tiles + 31) / 32;
+    const int32_t G_groups = (d.n + P - 1) / P;
+    const uint32_t b = blockIdx.x, j = b / 8;
+    const int32_t chunk = (int32_t)(8 * (j / G_groups) + b % 8);
+    const int32_t grp = (int32_t)(j % G_groups);
+    if (chunk >= n_chunks) return;
+    const int32_t i0 = grp * P;
+    const int32_t np = min(P, d.n - i0);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    uint64_t steps = 0;
+    pairs_item<NEG, COUNT>(d, heads, i0, np, chunk, lane, wave, blockDim.x / kWave, steps);
+    if (COUNT && lane == 0 && steps) atomicAdd(step_counter, (unsigned long long)steps);
+}
+
+// The batched launch: persistent blocks take items from eight queues, one
+// per XCD slice (block b starts with queue b mod 8, then helps the others).
+// A queue walks its slice's chunks in order, segment by segment (the
+// requests that read one set of bitmaps), every group of every request of
+// the segment on a chunk before the next chunk: item k of slice x in
+// segment g is chunk 8 (l / groups) + x and group l mod groups (l = k minus
+// the segment's first item in the queue), the group found among the
+// segment's requests by their first groups.
+template <bool COUNT>
+__global__ void __launch_bounds__(1024) k_eval_pairs_batch(PairQueues *__restrict__ pq, const ReqDesc *__restrict__ descs,
+                                                           const PairSeg *__restrict__ segs,
+                                                           const int32_t *__restrict__ seg_req,
+                                                           const int32_t *__restrict__ seg_gstart,
+                                                           const IndHead *__restrict__ heads, int32_t P,
+                                                           unsigned long long *step_counter)
+{
+    __shared__ int32_t s_item;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int W = blockDim.x / kWave;
+    const int32_t n_seg = pq->n_seg;
+    uint64_t steps = 0;
+    for (int o = 0; o < 8; ++o) {
+        const int slice = (int)((blockIdx.x + o) % 8);
+        const int32_t total = pq->total[slice];
+        for (;;) {
+            if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(&pq->counter[slice], 1u);
+            __syncthreads();
+            const int32_t k = __builtin_amdgcn_readfirstlane(s_item);
+            __syncthreads();
+            if (k >= total) break;
+            int32_t g = 0;
+            while (g + 1 < n_seg && segs[g + 1].base[slice] <= k) ++g;
+            const int32_t local = k - segs[g].base[slice];
+            const int32_t groups = segs[g].groups;
+            const int32_t chunk = 8 * (local / groups) + slice;
+            const int32_t pos = local % groups;
+            int32_t lo = segs[g].e0, hi = segs[g].e0 + segs[g].n_req - 1;  // the last entry starting at or before pos
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (seg_gstart[mid] <= pos) lo = mid;
+                else hi = mid - 1;
+            }
+            const ReqDesc &d = descs[seg_req[lo]];
+            const int32_t i0 = (pos - seg_gstart[lo]) * P;
+            const int32_t np = min(P, d.n - i0);
+            if (d.flags & kFlagNeg) pairs_item<true, COUNT>(d, heads, i0, np, chunk, lane, wave, W, steps);
+            else pairs_item<false, COUNT>(d, heads, i0, np, chunk, lane, wave, W, steps);
+        }
+    }
     if (COUNT && lane == 0 && steps) atomicAdd(step_counter, (unsigned long long)steps);
 }
 
@@ -429,6 +440,34 @@ hipError_t launch_prep_pairs(const ReqDesc &d, IndHead *heads, hipStream_t s)
     return hipGetLastError();
 }
 
+static const void *pairs_batch_kernel(bool count)
+{
+    return count ? (const void *)&k_eval_pairs_batch<true> : (const void *)&k_eval_pairs_batch<false>;
+}
+
+int pairs_batch_occupancy(int32_t W)
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, pairs_batch_kernel(false), W * kWave, 0) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
+hipError_t launch_pairs_batch(PairQueues *pq, const ReqDesc *descs, const PairSeg *segs, const int32_t *seg_req,
+                              const int32_t *seg_gstart, const IndHead *heads, int32_t W, int32_t P, int32_t grid,
+                              unsigned long long *step_counter, hipStream_t s)
+{
+    if (W < 1 || W > 16 || P < 1 || P > 64 * W || grid < 1) return hipErrorInvalidValue;
+    const bool count = step_counter != nullptr;
+    if (count)
+        hipLaunchKernelGGL(k_eval_pairs_batch<true>, dim3(grid), dim3(W * kWave), 0, s, pq, descs, segs, seg_req,
+                           seg_gstart, heads, P, step_counter);
+    else
+        hipLaunchKernelGGL(k_eval_pairs_batch<false>, dim3(grid), dim3(W * kWave), 0, s, pq, descs, segs, seg_req,
+                           seg_gstart, heads, P, step_counter);
+    return hipGetLastError();
+}
+
 const void *pairs_kernel(uint32_t flags, bool count)
 {
     const bool neg = (flags & kFlagNeg) != 0;
@@ -436,14 +475,12 @@ const void *pairs_kernel(uint32_t flags, bool count)
     return neg ? (const void *)&k_eval_pairs<true, false> : (const void *)&k_eval_pairs<false, false>;
 }
 
-int64_t pair_chunks_per_slice(int64_t rows) { return ((rows + kChunkRows - 1) / kChunkRows + 7) / 8; }
-
-// Blocks of the pairs launch: 8 XCD slices x groups x runs of M chunks.
-unsigned pairs_grid(int64_t rows, int32_t n, int32_t P, int32_t M)
+// Blocks of the plain pairs launch: 8 XCD slices x groups x chunks per slice.
+unsigned pairs_grid(int64_t rows, int32_t n, int32_t P)
 {
     const int64_t groups = (n + P - 1) / P;
-    const int64_t runs = (pair_chunks_per_slice(rows) + M - 1) / M;
-    return (unsigned)(8 * groups * runs);
+    const int64_t per_slice = ((rows + kChunkRows - 1) / kChunkRows + 7) / 8;
+    return (unsigned)(8 * groups * per_slice);
 }
 
 }  // namespace ebic

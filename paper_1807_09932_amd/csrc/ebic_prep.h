@@ -71,4 +71,54 @@ __device__ __forceinline__ PrepScan prep_scan(const ReqDesc &d, int32_t i, int l
     return sc;
 }
 
+// The pairs header (the IndHead storage, read differently) of the
+// pairwise-order-bitmap kernels.
+struct PairHead {
+    int32_t k;         // columns from begin (0: invalid)
+    int32_t begin;     // CSR start (the last leading repeat of the first column)
+    uint32_t fwd[7];   // byte offsets of the window's pairs of different columns (the last one repeated);
+                       // for k = 1, fwd[0] is the column's diagonal pair
+    uint32_t pad0;
+    uint32_t win[4];   // the window's eight columns, two per word (low half first)
+    uint32_t pad1[2];
+};
+static_assert(sizeof(PairHead) == sizeof(IndHead), "the pairs header reuses the header storage");
+
+// One wave per individual: the scan, the outputs' initialisation, and the
+// pairs header. Lane u < 7 forms window pair (u, u + 1); the pairs of
+// different columns are packed to the front in order (a pair (c, c) is
+// implied by the pairs next to it), the last one repeating after them; an
+// individual of one column gets its diagonal pair ("present").
+__device__ __forceinline__ void prep_pairs_wave(const ReqDesc &d, int32_t i, IndHead *__restrict__ heads, int lane)
+{
+    const PrepScan sc = prep_scan(d, i, lane);
+    if (lane == 0) {
+        d.matched[i] = sc.ok ? 0 : kInvalid;
+        if (d.negative) d.negative[i] = sc.ok ? 0 : kInvalid;
+    }
+    uint32_t *hd = reinterpret_cast<uint32_t *>(heads + d.head_base + i);
+    const uint32_t cb = (uint32_t)d.cols * 256u;  // a pair (a, b)'s byte offset: a * cb + b * 256
+    const uint32_t a = (uint32_t)__shfl(sc.win, 8 + min(lane, 7));
+    const uint32_t c = (uint32_t)__shfl(sc.win, 8 + min(lane + 1, 7));
+    const int q = (lane - 10) & 3;  // lanes 10..13: columns 2q, 2q + 1
+    const uint32_t pk = (uint32_t)__shfl(sc.win, 8 + 2 * q) | ((uint32_t)__shfl(sc.win, 9 + 2 * q) << 16);
+    const bool distinct = lane < 7 && a != c;
+    const uint64_t dm = __ballot(distinct);
+    const uint32_t off = a * cb + (c << 8);
+    const int nf = __popcll(dm);
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)a, 0);
+    const uint32_t last = nf == 0 ? w0 * cb + (w0 << 8)
+                                  : (uint32_t)__builtin_amdgcn_readlane((int)off, 63 - __clzll(dm));
+    if (!sc.ok) {
+        if (lane < 16) hd[lane] = 0u;
+        return;
+    }
+    if (distinct) hd[2 + __popcll(dm & ((1ull << lane) - 1))] = off;
+    if (lane >= nf && lane < 7) hd[2 + lane] = last;
+    if (lane == 0) hd[0] = (uint32_t)sc.k;
+    if (lane == 1) hd[1] = (uint32_t)sc.bb;
+    if (lane == 9 || lane == 14 || lane == 15) hd[lane] = 0u;
+    if (lane >= 10 && lane < 14) hd[lane] = pk;
+}
+
 }  // namespace ebic

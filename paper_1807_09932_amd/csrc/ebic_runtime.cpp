@@ -272,7 +272,7 @@ bool pairs_buildable(const Matrix &m)
 
 // The bitmaps a mode reads: exclude mode those of X; include mode those of
 // the fill-substituted values, which are X's own when no cell is missing.
-static const uint32_t *pairs_for(const Matrix &m, bool include)
+const uint32_t *pairs_for(const Matrix &m, bool include)
 {
     if (!include) return m.Gx;
     if (m.has_missing == 0) return m.Gx;
@@ -323,6 +323,7 @@ LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t f
     if (ctx->override_cfg.W > 0) cfg = ctx->override_cfg;
     else cfg = tuned_cfg(ctx, m.dev.rows, m.dev.cols, n, nnz);
     const size_t lds_max = ctx->lds_per_block;
+    const int32_t asked_P = cfg.P;  // (pairs: 0 = chosen here)
     cfg.P = std::max(1, std::min(cfg.P, std::max(1, n)));
     auto lds = [&](const LaunchCfg &c) { return item_lds_bytes(c.L, m.dev.cols, c.staging, c.P); };
     auto fits = [&](const LaunchCfg &c) { return lds(c) <= lds_max; };
@@ -350,28 +351,39 @@ LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t f
     // Pairwise order bitmaps (built on first use where they fit): no tile,
     // one wave per individual and 2,048-row chunk.
     if (cfg.staging == STAGE_PAIRS) {
-        const bool have_pairs = pairs_for(m, include) != nullptr || (codes != CODES_EXISTING && pairs_buildable(m));
+        bool have_pairs = pairs_for(m, include) != nullptr;
+        if (!have_pairs && codes != CODES_EXISTING && pairs_buildable(m) && !m.pairs_failed) {
+            have_pairs = true;  // (a report counts them as buildable)
+            if (codes == CODES_BUILD) {
+                try {
+                    build_pairs(ctx, m, include);
+                } catch (const Error &e) {
+                    if (e.code != EBIC_ENOMEM) throw;
+                    m.pairs_failed = true;
+                    have_pairs = false;
+                    log_msg(1, std::string("pair bitmaps not built (") + e.what() + "): rank codes instead");
+                }
+            }
+        }
         if (have_pairs) {
-            // (blocks: the chunks of an XCD slice one wave walks, 0 = as
-            // many runs of chunks as fill the device)
             cfg.L = 1;
             cfg.cnt16 = false;
-            cfg.P = std::max(1, std::min({cfg.P, 64 * cfg.W, std::max(1, n)}));
-            const int64_t per_slice = pair_chunks_per_slice(m.dev.rows);
-            if (cfg.blocks > 0) {
-                cfg.blocks = (int32_t)std::min<int64_t>(cfg.blocks, per_slice);
-            } else {
-                const int64_t groups = (std::max(1, n) + cfg.P - 1) / cfg.P;
-                const int64_t waves = 8 * groups * cfg.W;          // one run per slice
-                const int64_t target = (int64_t)ctx->cu_count * 32;  // resident waves at full occupancy
-                const int64_t runs = std::min<int64_t>(per_slice, std::max<int64_t>(1, (target + waves - 1) / waves));
-                cfg.blocks = (int32_t)((per_slice + runs - 1) / runs);
+            if (asked_P <= 0) {
+                // Individuals per wave: up to 8 where the chunks and
+                // individuals give at least two waves per resident slot,
+                // fewer (down to one) on smaller work.
+                const int64_t chunks = pair_words(m.dev.rows) / 64;
+                const int64_t slots = (int64_t)ctx->cu_count * 32;
+                const int64_t per_wave = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)n * chunks / (2 * slots)));
+                cfg.P = (int32_t)(per_wave * cfg.W);
             }
-            if (!pairs_for(m, include) && codes == CODES_BUILD) build_pairs(ctx, m, include);
+            cfg.P = std::max(1, std::min({cfg.P, 64 * cfg.W, std::max(1, n)}));
+            cfg.blocks = (int32_t)(pair_words(m.dev.rows) / 64);  // (reported: the chunks)
             return cfg;
         }
-        cfg.staging = STAGE_BYTES;  // (falls through to the kinds the matrix has)
-        cfg.L = 8;
+        // without them: the shape planned for the rank codes
+        cfg = default_codes_cfg(m.dev.rows, m.dev.cols, n);
+        cfg.P = std::max(1, std::min(cfg.P, std::max(1, n)));
     }
     const bool asked_swar = cfg.staging == STAGE_BYTES || cfg.staging == STAGE_HALVES || cfg.staging == STAGE_T10;
     if (asked_swar && !have_swar(cfg.staging)) {

@@ -31,6 +31,7 @@ struct Matrix {
     size_t value_bytes = 0;  // X and Xfill
     float sentinel = 0.f;
     int32_t has_missing = -1;  // from the SWAR code build (-1: not built)
+    bool pairs_failed = false;  // a build of the pair bitmaps found no memory: not tried again
     double upload_ms = 0;
     // Holders that keep the matrix from being released (under ctx->mu):
     // calls between planning and enqueuing, and serving requests from
@@ -233,6 +234,7 @@ bool halves_buildable(const Matrix &m, bool include);
 void build_half_codes(ebic_ctx *ctx, Matrix &m);
 bool pairs_buildable(const Matrix &m);
 void build_pairs(ebic_ctx *ctx, Matrix &m, bool include);
+const uint32_t *pairs_for(const Matrix &m, bool include);  // the bitmaps a mode reads, or null
 LaunchCfg plan_eval(ebic_ctx *ctx, Matrix &m, int32_t n, int64_t nnz, uint32_t flags,
                     CodesMode codes = CODES_BUILD, bool masks = false);
 // The kernels' view of one request; `staging` decides whether include mode
@@ -259,7 +261,9 @@ LaunchCfg tuned_cfg(ebic_ctx *ctx, int64_t rows, int32_t cols, int32_t n, int64_
 LaunchCfg tuned_batch_cfg(ebic_ctx *ctx, int64_t total_ind, int64_t mean_rows, int32_t max_cols,
                           int64_t nnz);
 LaunchCfg default_batch_cfg(int32_t max_cols);
+LaunchCfg default_batch_codes_cfg(int32_t max_cols);  // (the shape without the pair bitmaps)
 LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n);
+LaunchCfg default_codes_cfg(int64_t rows, int32_t cols, int32_t n);  // (the shape without the pair bitmaps)
 void load_tune_cache(ebic_ctx *ctx, const std::string &path);
 
 // ebic_batch.cpp

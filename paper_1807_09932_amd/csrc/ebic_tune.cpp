@@ -51,6 +51,23 @@ static int32_t default_L(int32_t cols) { return cols <= 64 ? 4 : (cols <= 128 ? 
 
 LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
 {
+    // The pairwise order bitmaps up to 512 columns (cols / 32 times the
+    // FP32 matrix's bytes, built on first use): four waves per block, the
+    // individuals per wave chosen at planning (P = 0).
+    if (cols <= kDefaultPairCols) {
+        LaunchCfg c;
+        c.L = 1;
+        c.W = 4;
+        c.P = 0;
+        c.staging = STAGE_PAIRS;
+        c.blocks = 0;
+        return c;
+    }
+    return default_codes_cfg(rows, cols, n);
+}
+
+LaunchCfg default_codes_cfg(int64_t rows, int32_t cols, int32_t n)
+{
     (void)rows;
     LaunchCfg c;
     c.W = 16;
@@ -74,6 +91,20 @@ LaunchCfg default_cfg(int64_t rows, int32_t cols, int32_t n)
 }
 
 LaunchCfg default_batch_cfg(int32_t max_cols)
+{
+    // The pair bitmaps (as for one population) for the requests whose
+    // matrices take them; the others get the rank codes' shape at planning.
+    (void)max_cols;
+    LaunchCfg c;
+    c.L = 1;
+    c.W = 4;
+    c.P = 0;
+    c.staging = STAGE_PAIRS;
+    c.blocks = 0;
+    return c;
+}
+
+LaunchCfg default_batch_codes_cfg(int32_t max_cols)
 {
     LaunchCfg c;
     c.W = 16;
@@ -282,7 +313,8 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
         }
         if (!(tiles_per_wave == 1 || tiles_per_wave == 2 || tiles_per_wave == 3 || tiles_per_wave == 4 ||
               tiles_per_wave == 6 || tiles_per_wave == 8 || tiles_per_wave == 16) ||
-            waves_per_block < 1 || waves_per_block > 16 || individuals_per_group < 1 ||
+            waves_per_block < 1 || waves_per_block > 16 ||
+            (individuals_per_group < 1 && !(individuals_per_group == 0 && staging == STAGE_PAIRS)) ||
             !(staging == STAGE_LDS || staging == STAGE_DIRECT || staging == STAGE_CODES ||
               staging == STAGE_BYTES || staging == STAGE_HALVES || staging == STAGE_T10 ||
               staging == STAGE_PAIRS) ||
@@ -349,6 +381,22 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                                                 s) == EBIC_OK;
                 };
                 std::vector<std::pair<float, LaunchCfg>> timed;
+                // The pairwise order bitmaps (built by the first of these
+                // evaluations where they fit): waves per block and
+                // individuals per wave, one chunk per block.
+                if (cols <= kDefaultPairCols)
+                    for (int W : {2, 4, 8})
+                        for (int per_wave : {1, 2, 4, 8, 16}) {
+                            LaunchCfg c;
+                            c.L = 1;
+                            c.W = W;
+                            c.P = std::min(per_wave * W, r.n_ind);
+                            c.staging = STAGE_PAIRS;
+                            c.blocks = 1;
+                            set_override(c);
+                            const float ms = time_ms(eval_once, 3, s);
+                            if (std::isfinite(ms)) timed.emplace_back(ms, c);
+                        }
                 for (int L : {1, 2, 3, 4, 6, 8, 16})
                     for (int W : {4, 8, 16})
                         for (int P : {200, 400, 800, 1600})
@@ -376,7 +424,7 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                             }
                 LaunchCfg best = settle(timed, set_override, eval_once, s);
                 if (best.W > 0) {
-                    best.blocks = 0;  // re-derived from occupancy at launch
+                    best.blocks = 0;  // re-derived from occupancy at launch (pairs: one chunk per run)
                     std::lock_guard<std::mutex> lk(ctx->mu);
                     ctx->tuned[key] = best;
                 }
@@ -399,6 +447,18 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
                     const TuneKey key = batch_key(total, rows_sum / live, max_cols);
                     std::vector<std::pair<float, LaunchCfg>> timed;
                     auto batch_once = [&] { return ebic_eval_batch(ctx, sample, n_reqs, s) == EBIC_OK; };
+                    if (max_cols <= kDefaultPairCols)
+                        for (int W : {2, 4, 8})
+                            for (int per_wave : {1, 2, 4, 8, 16}) {
+                                LaunchCfg c;
+                                c.L = 1;
+                                c.W = W;
+                                c.P = per_wave * W;
+                                c.staging = STAGE_PAIRS;
+                                set_override(c);
+                                const float ms = time_ms(batch_once, 3, s);
+                                if (std::isfinite(ms)) timed.emplace_back(ms, c);
+                            }
                     for (int L : {1, 2, 4})
                         for (int W : {4, 8, 16})
                             for (int P : {128, 256, 512, 1024})

@@ -39,7 +39,8 @@ def test_autotune_plain_and_batch_then_cache(tmp_path):
         entries = json.load(open(cache))
         assert entries, "the cache holds the tuned shapes"
         tuned_plain = ebic.ebic_plan_shape(ctx.handle, mat, dev[0].n, int(packed[0][0][-1]))
-        assert tuned_plain[3] in (ebic.STAGE_BYTES, ebic.STAGE_CODES, ebic.STAGE_LDS, ebic.STAGE_DIRECT)
+        assert tuned_plain[3] in (ebic.STAGE_PAIRS, ebic.STAGE_BYTES, ebic.STAGE_CODES, ebic.STAGE_LDS,
+                                  ebic.STAGE_DIRECT)
         # every population, plain and batched, in the tuned shapes: bit-exact
         for (o, c), p in zip(packed, dev):
             m, g, _, _ = ctx.eval(mat, p, negative=True)

@@ -78,3 +78,16 @@ def test_traffic_only_for_matching_kernel_sources(bench, tmp_path, monkeypatch):
     assert bench.traffic_from_profile(1, shape=(4, 16, 200, 3)) is None
     (csrc / bench.KERNEL_SOURCES[0]).write_text("// changed\n")
     assert bench.traffic_from_profile(1) is None  # the kernel changed since
+
+
+def test_pair_window_pairs_counts_distinct_window_pairs():
+    import numpy as np
+    import bench
+    from paper_1807_09932_amd import gen
+    inds = [[1, 2, 3], [3, 3, 1], [5], [1, 2, 1, 2], [4, 4, 4],
+            [0, 1, 2, 3, 4, 5, 6, 7, 8, 9],   # past the window: (7, 8), (8, 9) not read per chunk
+            [6, 6, 7, 7, 6], [2, 99]]          # inner repeats; an invalid column: pair (0, 0)
+    offs, cols = gen.csr([np.asarray(i, np.int32) for i in inds])
+    want = {(1, 2), (2, 3), (3, 1), (5, 5), (2, 1), (4, 4),
+            (0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (5, 6), (6, 7), (7, 6), (0, 0)}
+    assert bench.pair_window_pairs(offs, cols, 10) == len(want)

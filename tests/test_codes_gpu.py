@@ -98,9 +98,14 @@ def test_missing_cells_get_fp16_codes_at_upload(ctx):
     st = ctx.stats(mat)
     assert st["has_missing"] == 1
     assert st["code_sets"] == ebic.SET_U8 | ebic.SET_FP16, st
-    # exclude mode stages the FP16 codes (the byte codes hold the fill value)
-    assert ebic.ebic_plan_shape(ctx.handle, mat, 100)[3] == ebic.STAGE_CODES
-    for include in (False, True):
-        got = gpu_eval(ctx, mat, offs, cols, include=include)
-        assert_same(got, oracle_eval(w.X, offs, cols, include=include), f"include={include}")
+    # a shape asking for byte codes: exclude mode stages the FP16 codes (the
+    # byte codes hold the fill value)
+    ctx.set_launch_shape(8, 16, 200, ebic.STAGE_BYTES, 0)
+    try:
+        assert ebic.ebic_plan_shape(ctx.handle, mat, 100)[3] == ebic.STAGE_CODES
+        for include in (False, True):
+            got = gpu_eval(ctx, mat, offs, cols, include=include)
+            assert_same(got, oracle_eval(w.X, offs, cols, include=include), f"include={include}")
+    finally:
+        ctx.set_launch_shape()
     ctx.release(mat)

@@ -41,7 +41,7 @@ def test_batched_all_64_populations(ctx):
     outs = [ctx.outputs(mat, p.n, masks=q in with_masks) for q, p in enumerate(dev)]
     reqs = [ctx.request(mat, p, o) for p, o in zip(dev, outs)]
     L, W, P, stagings, _ = ebic.ebic_plan_batch_shape(ctx.handle, reqs)
-    assert (L, W, P) == (2, 16, 1024) and set(stagings) == {ebic.STAGE_T10}
+    assert (L, W) == (1, 4) and set(stagings) == {ebic.STAGE_PAIRS}
     announce("batched 64 populations", sum(p.n for p in dev))
     ctx.eval_batch(reqs)
     torch.cuda.synchronize()
@@ -96,7 +96,7 @@ def test_methylation_include_mode_full(ctx):
     ctx.release(mat)
 
 
-@pytest.mark.parametrize("shape,staging", [(None, 5), ((3, 16, 400, 5), 5), ((6, 16, 200, 5), 5),
+@pytest.mark.parametrize("shape,staging", [(None, 6), ((3, 16, 400, 5), 5), ((6, 16, 200, 5), 5),
                                            ((2, 16, 400, 4), 4)],
                          ids=["default", "10-bit-P400", "10-bit-two-words", "16-bit"])
 def test_methylation_wide_full(ctx, shape, staging):

@@ -4,9 +4,10 @@ ABI: special values (signed zeros, infinities, NaN, ties), both missing-value
 modes with and without negative trends and masks, one-column, repeated-column
 and invalid individuals, individuals longer than the header's window, row
 counts around the 32-row words and 2,048-row chunks, widths past the codes'
-limits, several launch shapes, the methylation workloads at full size, and
-the fallbacks (too many columns, the allocation-free entry point before the
-bitmaps exist, batches)."""
+limits, several launch shapes, the methylation workloads at full size, the
+fallbacks (too many columns, the allocation-free entry point before the
+bitmaps exist), and batches: requests on several matrices and in both modes
+on the batched pairs kernel beside requests on the tiled one."""
 import numpy as np
 import pytest
 
@@ -234,7 +235,7 @@ def test_pairs_fallbacks(ctx):
         torch.cuda.synchronize()
         for out in outs:
             assert_same((out[0].cpu().numpy(), out[1].cpu().numpy(), None, None), want, "batch")
-        assert ebic.STAGE_PAIRS not in ebic.ebic_plan_batch_shape(ctx.handle, reqs)[3]
+        assert ebic.ebic_plan_batch_shape(ctx.handle, reqs)[3] == [ebic.STAGE_PAIRS] * 2
     finally:
         ctx.set_launch_shape()
         ctx.release(mat)
@@ -294,3 +295,57 @@ def test_pairs_sparse_ties(ctx, cols):
     finally:
         ctx.set_launch_shape()
         ctx.release(mat)
+
+
+def test_pairs_batched_mixed(ctx):
+    """One batch: requests on two matrices (64 columns with ties and NaN, 300
+    tie-free columns) in both modes, with and without negative trends and
+    masks, an empty population, invalid individuals, and requests on a
+    600-column matrix (past the default width: the tiled kernel) in the same
+    launch; then a smaller batch on the same stream (the captured graph
+    again). Each result equals the oracle's."""
+    import torch
+    from paper_1807_09932_amd import ebic
+    rng = np.random.default_rng(77)
+    Xa = rng.integers(0, 9, size=(9_001, 64)).astype(np.float32)
+    Xa[rng.random(Xa.shape) < 0.02] = np.float32(np.nan)
+    Xb = _tie_free(15_000, 300, 78)
+    Xc = rng.standard_normal((3_000, 600)).astype(np.float32)
+    mats = {k: ctx.upload(X, fill=0.75) for k, X in (("a", Xa), ("b", Xb), ("c", Xc))}
+    Xs = {"a": Xa, "b": Xb, "c": Xc}
+    jobs = []
+    for q in range(14):
+        key = "abc"[q % 3]
+        cols = Xs[key].shape[1]
+        n = 0 if q == 5 else int(rng.integers(20, 300))
+        offs, cc = _pop(rng, cols, n, kmax=24) if n else gen.csr([])
+        jobs.append((key, offs, cc, q % 2 == 1, q % 4 != 3, q % 5 == 0))
+    s = torch.cuda.Stream()
+    try:
+        for rnd, sub in enumerate((jobs, jobs[:6])):
+            reqs, outs, held = [], [], []
+            for key, offs, cc, include, negative, masks in sub:
+                pop = ctx.population(offsets=offs, cols=cc)
+                o = ctx.outputs(mats[key], pop.n, masks=masks, negative=True)
+                held.append(pop)
+                outs.append(o)
+                reqs.append(ctx.request(mats[key], pop, o, include=include, negative=negative))
+            stg = ebic.ebic_plan_batch_shape(ctx.handle, reqs)[3]
+            for (key, offs, *_), st in zip(sub, stg):
+                if offs.size > 1:
+                    assert (st == ebic.STAGE_PAIRS) == (key != "c"), (key, st)
+            announce("pairs batched mixed", rnd, len(sub))
+            ctx.eval_batch(reqs, stream=s)
+            s.synchronize()
+            for (key, offs, cc, include, negative, masks), o in zip(sub, outs):
+                got = tuple(t.cpu().numpy() if t is not None else None for t in o)
+                got = tuple(g.view(np.uint64) if g is not None and g.dtype == np.int64 else g for g in got)
+                want = oracle_eval(Xs[key], offs, cc, include=include, negative=negative, masks=masks, fill=0.75)
+                if not negative:
+                    got = (got[0], None, got[2], got[3])
+                if not masks:
+                    got = (got[0], got[1], None, None)
+                assert_same(got, want, f"round {rnd} matrix {key} include={include} negative={negative}")
+    finally:
+        for m in mats.values():
+            ctx.release(m)
