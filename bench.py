@@ -591,7 +591,9 @@ def bench_paper_shape(ctx, args):
             "launch_shape": f"{how}: L={L} W={W} P={P} staging={stg} blocks={blocks}",
             "kernel_ms": k_ms, "checks_per_s": checks / (k_ms * 1e-3),
             "roofline": {**kernel_roofline(stg, steps, k_ms, offs, cols, rows, ncols),
-                         "traffic": traffic_from_profile(1, "k_eval_methylation_wide_436444x310_traffic.json",
+                         "traffic": traffic_from_profile(1, "k_eval_pairs_methylation_wide_436444x310_traffic.json"
+                                                         if stg == STAGE_PAIRS else
+                                                         "k_eval_methylation_wide_436444x310_traffic.json",
                                                          (L, W, P, stg))},
             "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9}
 
@@ -983,6 +985,8 @@ def main():
     value = checks / (wall / args.steps)
     k_ms = kernel_ms / max(1, launches)
     roof = kernel_roofline(stg, executed_steps, k_ms, offs, cols, rows, ncols)
+    main_traffic = ("k_eval_pairs_methylation_436444x64_traffic.json" if stg == STAGE_PAIRS
+                    else "k_eval_methylation_436444x64_traffic.json")
 
     # End-to-end latency of one generation's evaluation as the host EA sees
     # it: CSR to the device, evaluation, counts back to the host.
@@ -1025,7 +1029,7 @@ def main():
         },
         "roofline": {
             **roof,
-            "traffic": traffic_from_profile(1, shape=(L, W, P, stg)),
+            "traffic": traffic_from_profile(1, main_traffic, shape=(L, W, P, stg)),
             "kernel": "k_eval_pairs" if stg == STAGE_PAIRS else "k_eval",
             "launch_shape": shape_note,
             "kernel_ms": k_ms,
@@ -1061,8 +1065,8 @@ def main():
             "note": "gather-equivalent: 4 B per nominal check; the staged kernel reads the "
                     "matrix once, so this is not physical traffic",
             "matrix_once_gbs": w.X.nbytes / (k_ms * 1e-3) / 1e9,
-            "physical_gbs": (traffic_from_profile(1, shape=(L, W, P, stg)) / (k_ms * 1e-3) / 1e9
-                             if traffic_from_profile(1, shape=(L, W, P, stg)) else None),
+            "physical_gbs": (traffic_from_profile(1, main_traffic, shape=(L, W, P, stg)) / (k_ms * 1e-3) / 1e9
+                             if traffic_from_profile(1, main_traffic, shape=(L, W, P, stg)) else None),
             "copy_ceiling_gbs": copy_gbs,
             "physical_note": "HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE "
                              "summary over the measured kernel time; copy ceiling = a 1 GiB "
