@@ -1,16 +1,23 @@
 // ebic_batch.cpp -- ebic_eval_batch: many populations (of uneven sizes, with
 // individuals of uneven lengths, over one or several resident matrices) in
-// one persistent launch, replayed from a captured HIP graph.
+// one replay of a captured HIP graph.
 //
-// The host planner turns the requests into work items (individual group x
-// tile range), ordered largest first, and writes a batch arena (header,
-// request descriptors, prefix sums of individuals, items) into pinned host
-// memory. A graph captured once per (stream, launch shape, capacity)
+// The host planner puts each request on the pair bitmaps where its matrix
+// has them (or can: they are built here on first use), else on the tiled
+// kernel's stagings. Tiled requests become work items (individual group x
+// tile range), ordered largest first, which the persistent tiled kernel's
+// blocks take from a device-side counter. Pair requests are grouped by the
+// bitmap set they read (a segment); per XCD slice of 2,048-row chunks, the
+// fixed-grid pairs kernel walks each segment's chunks in order, all of its
+// groups on a chunk before the next, with a static stride (no counter). The
+// planner writes a batch arena (header, request descriptors, prefix sums of
+// individuals, the pair lists and segments, the tiled items) into pinned
+// host memory. A graph captured once per (stream, launch shapes, capacity)
 // copies the arena to the device, runs the prep kernel (validation, output
-// initialisation, individual headers, zeroing the work counter) and the
-// persistent evaluation kernel, whose blocks take items from the counter.
-// The arena's device address is fixed per graph, so one graph serves every
-// batch that fits its capacity; only the copy size is updated per replay.
+// initialisation, the individual headers of each request's kind, zeroing
+// the work counter) and the kernels the batch needs. The arena's device
+// address is fixed per graph, so one graph serves every batch that fits its
+// capacity; only the copy size is updated per replay.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,8 +40,8 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Header, request descriptors, prefix sums of individuals, the pair
-// queues and segments (requests on pair bitmaps), then the items.
+// Header, request descriptors, prefix sums of individuals, the pair lists
+// and segments (requests on pair bitmaps), then the tiled items.
 struct ArenaLayout {
     size_t hdr = 0, descs = 0, first = 0, pq = 0, segs = 0, seg_req = 0, seg_gstart = 0, items = 0, bytes = 0;
     ArenaLayout(int32_t n_req, int32_t n_items)
@@ -68,7 +75,7 @@ struct GraphEntry {
 
 // (stream, L, W, P, tile bytes, grid, capacities, counting, kernel set,
 // which kernels run: 1 the tiled one, 2 the pairs one; the pairs kernel's
-// W, P and grid)
+// W, an unused field, and its grid; its group size travels in the arena)
 using GraphKey = std::tuple<hipStream_t, int32_t, int32_t, int32_t, int64_t, int32_t, int32_t,
                             int32_t, int64_t, bool, int32_t, int32_t, int32_t, int32_t, int32_t>;
 
@@ -125,7 +132,7 @@ struct Plan {
     size_t tile_bytes = 0;
     int64_t total_ind = 0;
     int32_t grid = 0;
-    // Requests on the pair bitmaps: their kernel's shape and queues.
+    // Requests on the pair bitmaps: their kernel's shape and item lists.
     bool pairs_shape = false;   // the shape asks for the bitmaps
     int32_t pW = 4, pP = 0, pgrid = 0;
     PairQueues pq{};
@@ -332,9 +339,10 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
         if (p.pairs_shape && ind_chunks > 0) {
             if (p.pP <= 0) {
                 // individuals per wave: up to 8 where the work gives at least
-                // two waves per resident slot
+                // two waves per resident slot, at least 2 (an item's lookup
+                // costs about what one individual's chunk does)
                 const int64_t slots = (int64_t)ctx->cu_count * 32;
-                p.pP = (int32_t)(p.pW * std::max<int64_t>(1, std::min<int64_t>(8, ind_chunks / (2 * slots))));
+                p.pP = (int32_t)(p.pW * std::max<int64_t>(2, std::min<int64_t>(8, ind_chunks / (2 * slots))));
             }
             p.pP = std::max(1, std::min(p.pP, 64 * p.pW));
             std::vector<const uint8_t *> keys;
@@ -374,6 +382,7 @@ static Plan plan_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs, 
                 p.pq.total[x] = (int32_t)k;
             }
             p.pq.n_seg = (int32_t)p.segs.size();
+            p.pq.P = p.pP;  // (in the arena: graphs do not depend on it)
             int occ = pairs_batch_occupancy(p.pW);
             if (occ <= 0) occ = 1;
             p.pgrid = std::max(8, ctx->cu_count * occ / 8 * 8);
@@ -403,15 +412,19 @@ static GraphSpec graph_spec(hipStream_t s, const Plan &p, bool count)
     g.cap_req = (int32_t)pow2(std::max<int64_t>(64, (int64_t)p.descs.size()));
     g.cap_items = (int32_t)pow2(std::max<int64_t>(8192, (int64_t)p.items.size()));
     g.cap_ind = pow2(std::max<int64_t>(16384, p.total_ind));
-    const int32_t kernels = (p.items.empty() ? 0 : 1) | (p.any_pairs() ? 2 : 0);
-    g.key = GraphKey{s, p.cfg.L, p.cfg.W, p.cfg.P, (int64_t)p.tile_bytes, p.grid, g.cap_req, g.cap_items,
-                     g.cap_ind, count, p.set, kernels, p.pW, p.pP, p.pgrid};
+    // (the shape of a kernel that does not run stays out of the key)
+    const bool tiled = !p.items.empty(), pairs = p.any_pairs();
+    const int32_t kernels = (tiled ? 1 : 0) | (pairs ? 2 : 0);
+    g.key = GraphKey{s, tiled ? p.cfg.L : 0, tiled ? p.cfg.W : 0, tiled ? p.cfg.P : 0,
+                     tiled ? (int64_t)p.tile_bytes : 0, tiled ? p.grid : 0, g.cap_req, g.cap_items, g.cap_ind,
+                     count, tiled ? p.set : 0, kernels, pairs ? p.pW : 0, 0, pairs ? p.pgrid : 0};
     return g;
 }
 
 // Capture a new graph for `spec`. Holds no context lock: the capture runs on
-// a stream of its own in thread-local capture mode, so evaluations on other
-// streams proceed meanwhile.
+// a stream of its own in relaxed capture mode, so evaluations, uploads and
+// builds of codes or bitmaps on other threads and streams proceed meanwhile
+// without being refused as unsafe during a capture.
 static std::unique_ptr<GraphEntry> capture_graph(ebic_ctx *ctx, const GraphSpec &spec, const Plan &p,
                                                  bool count)
 {
@@ -433,7 +446,7 @@ static std::unique_ptr<GraphEntry> capture_graph(ebic_ctx *ctx, const GraphSpec 
         const int prep_blocks = std::max(1, ctx->cu_count * 8);  // four waves each, one individual per wave
         unsigned long long *counter = count ? ctx->d_step_counter : nullptr;
         check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
-        check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        check(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
         hipError_t e = hipMemcpyAsync(da, g->h_arena[0], lay.bytes, hipMemcpyHostToDevice, cs);
         if (e == hipSuccess)
             e = launch_batch(reinterpret_cast<BatchHeader *>(da + lay.hdr),
@@ -443,11 +456,11 @@ static std::unique_ptr<GraphEntry> capture_graph(ebic_ctx *ctx, const GraphSpec 
                              p.set, p.cfg.W, p.cfg.P, p.tile_bytes, p.items.empty() ? 0 : p.grid, prep_blocks,
                              counter, cs);
         if (e == hipSuccess && p.any_pairs())
-            e = launch_pairs_batch(reinterpret_cast<PairQueues *>(da + lay.pq),
+            e = launch_pairs_batch(reinterpret_cast<const PairQueues *>(da + lay.pq),
                                    reinterpret_cast<const ReqDesc *>(da + lay.descs),
                                    reinterpret_cast<const PairSeg *>(da + lay.segs),
                                    reinterpret_cast<const int32_t *>(da + lay.seg_req),
-                                   reinterpret_cast<const int32_t *>(da + lay.seg_gstart), g->d_heads, p.pW, p.pP,
+                                   reinterpret_cast<const int32_t *>(da + lay.seg_gstart), g->d_heads, p.pW,
                                    p.pgrid, counter, cs);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -565,7 +578,7 @@ extern "C" ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, 
         std::memcpy(h + cap.hdr, &bh, sizeof(bh));
         std::memcpy(h + cap.descs, p.descs.data(), sizeof(ReqDesc) * p.descs.size());
         std::memcpy(h + cap.first, p.first.data(), sizeof(int64_t) * p.first.size());
-        std::memcpy(h + cap.pq, &p.pq, sizeof(PairQueues));  // (counters zero)
+        std::memcpy(h + cap.pq, &p.pq, sizeof(PairQueues));
         if (!p.segs.empty()) {
             std::memcpy(h + cap.segs, p.segs.data(), sizeof(PairSeg) * p.segs.size());
             std::memcpy(h + cap.seg_req, p.seg_req.data(), sizeof(int32_t) * p.seg_req.size());

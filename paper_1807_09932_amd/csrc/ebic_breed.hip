@@ -238,6 +238,7 @@ extern "C" ebic_status ebic_ea_breed(ebic_ctx *ctx, const ebic_ea_params *params
             hip_check(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_breed_small),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)small_lds),
                       "hipFuncSetAttribute");
+            clear_last_error();
             hipLaunchKernelGGL(k_breed_small, dim3(1), dim3(T), small_lds, s, p, generation, n, d_offsets, d_cols,
                                d_matched, n2, d_next_offsets, d_next_cols, d_best);
             hip_check(hipGetLastError(), "breeding kernel");
@@ -255,13 +256,18 @@ extern "C" ebic_status ebic_ea_breed(ebic_ctx *ctx, const ebic_ea_params *params
         int32_t *slots = reinterpret_cast<int32_t *>(base + f_bytes + o_bytes + l_bytes);
         fault_point_launch(ctx, "breeding launch");
         const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
+        clear_last_error();
         hipLaunchKernelGGL(k_breed_fitness, dim3(blocks), dim3(kThreads), 0, s, n, d_offsets, d_matched, f);
+        clear_last_error();
         hipLaunchKernelGGL(k_breed_order, dim3(blocks), dim3(kThreads), 0, s, n, f, ne, order, d_best);
         const int32_t in_lds = p.k_max <= kLdsMaxK ? 1 : 0;
+        clear_last_error();
         hipLaunchKernelGGL(k_breed_children, dim3(blocks), dim3(kThreads),
                            in_lds ? (size_t)kThreads * p.k_max * sizeof(int32_t) : 0, s, p, generation, n,
                            d_offsets, d_cols, f, order, slots, lens, in_lds);
+        clear_last_error();
         hipLaunchKernelGGL(k_breed_offsets, dim3(1), dim3(1024), 0, s, n, lens, d_next_offsets);
+        clear_last_error();
         hipLaunchKernelGGL(k_breed_compact, dim3(blocks), dim3(kThreads), 0, s, n, p.k_max, slots,
                            d_next_offsets, d_next_cols);
         hip_check(hipGetLastError(), "breeding kernels");

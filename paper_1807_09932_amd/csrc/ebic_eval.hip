@@ -2631,6 +2631,7 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
     } else {
         const int threads = 256;
         const int per_block = threads / kWave;  // one wave per individual
+        clear_last_error();
         hipLaunchKernelGGL(k_prep, dim3((d.n + per_block - 1) / per_block), dim3(threads), 0, s, d, heads);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -2718,6 +2719,7 @@ hipError_t launch_batch(BatchHeader *hdr, const ReqDesc *descs, const int64_t *f
                         unsigned long long *step_counter, hipStream_t s, hipEvent_t ev0,
                         hipEvent_t ev1)
 {
+    clear_last_error();
     hipLaunchKernelGGL(k_prep_batch, dim3(prep_blocks), dim3(256), 0, s, hdr, descs, first, heads);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -244,6 +244,11 @@ hipError_t launch_half_codes(const float *X, int64_t rows, int64_t ld, int32_t c
 // The same for 10-bit codes (cols <= kMaxT10Cols) into T10, ld10 bytes per
 // column (256 per 192-row group; T10 zeroed by the caller, the fields are
 // OR-ed in), and one tie flag per 192-row group.
+// Clears the calling thread's last HIP error before a launch, so that the
+// hipGetLastError() after it reports that launch's own error (not one an
+// earlier call left, such as an ignored error of a release path).
+inline void clear_last_error() { (void)hipGetLastError(); }
+
 // Pairwise order bitmaps (ebic_pairs.hip): words per pair for `rows`, the
 // build of every pair's words from a column-major matrix (subst: NaN takes
 // `fill` first) with each 2,048-row chunk's list of tied pairs and NaN flag
@@ -261,26 +266,26 @@ hipError_t launch_prep_pairs(const ReqDesc &d, IndHead *heads, hipStream_t s);
 const void *pairs_kernel(uint32_t flags, bool count);
 unsigned pairs_grid(int64_t rows, int32_t n, int32_t P);
 
-// The pair items of a batch: eight queues, one per XCD slice (a slice: the
+// The pair items of a batch: eight lists, one per XCD slice (a slice: the
 // chunks c with c mod 8 = x), each walking its chunks in order segment by
 // segment; a segment is the requests reading one set of bitmaps, listed in
 // the entries e0 .. e0 + n_req - 1 of seg_req (request index) and seg_gstart
 // (the request's first group within the segment, groups of P individuals).
 struct PairQueues {
-    uint32_t counter[8];  // next item per queue (zero in the copied arena)
-    int32_t total[8];     // items per queue
+    int32_t total[8];  // items per list
     int32_t n_seg;
-    int32_t pad[7];
+    int32_t P;         // individuals per group (at most 64 per wave)
+    int32_t pad[6];
 };
 struct PairSeg {
     int32_t e0, n_req;
     int32_t groups;    // groups over the segment's requests
     int32_t n_chunks;  // 2,048-row chunks of its matrix
-    int32_t base[8];   // the segment's first item in each queue
+    int32_t base[8];   // the segment's first item in each list
 };
-hipError_t launch_pairs_batch(PairQueues *pq, const ReqDesc *descs, const PairSeg *segs, const int32_t *seg_req,
-                              const int32_t *seg_gstart, const IndHead *heads, int32_t W, int32_t P, int32_t grid,
-                              unsigned long long *step_counter, hipStream_t s);
+hipError_t launch_pairs_batch(const PairQueues *pq, const ReqDesc *descs, const PairSeg *segs,
+                              const int32_t *seg_req, const int32_t *seg_gstart, const IndHead *heads, int32_t W,
+                              int32_t grid, unsigned long long *step_counter, hipStream_t s);
 int pairs_batch_occupancy(int32_t W);  // blocks per CU of the batched pairs kernel
 hipError_t launch_t10_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, float fill,
                             uint8_t *T10, int64_t ld10, int32_t *has_nan, int32_t *ties, hipStream_t s);

@@ -194,6 +194,7 @@ hipError_t launch_codes(const float *X, int64_t rows, int64_t ld, int32_t cols, 
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_codes),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    clear_last_error();
     hipLaunchKernelGGL(k_codes, dim3((unsigned)(ld / 64)), dim3(256), lds, s, X, rows, ld, cols, C);
     return hipGetLastError();
 }
@@ -206,6 +207,7 @@ hipError_t launch_byte_codes(const float *X, int64_t rows, int64_t ld, int32_t c
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_swar_codes<uint8_t>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    clear_last_error();
     hipLaunchKernelGGL(k_swar_codes<uint8_t>, dim3((unsigned)(ldb / 64)), dim3(256), lds, s, X, rows, ld,
                        cols, fill, B, ldb, has_nan, ties);
     return hipGetLastError();
@@ -219,6 +221,7 @@ hipError_t launch_half_codes(const float *X, int64_t rows, int64_t ld, int32_t c
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_swar_codes<uint16_t>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    clear_last_error();
     hipLaunchKernelGGL(k_swar_codes<uint16_t>, dim3((unsigned)(ldh / 2 / 64)), dim3(256), lds, s, X, rows,
                        ld, cols, fill, reinterpret_cast<uint16_t *>(Hc), ldh / 2, has_nan, ties);
     return hipGetLastError();
@@ -236,6 +239,7 @@ hipError_t launch_t10_codes(const float *X, int64_t rows, int64_t ld, int32_t co
     if (e != hipSuccess) return e;
     // one block per 64 rows up to the last group's end; X is read only for
     // rows below `rows`
+    clear_last_error();
     hipLaunchKernelGGL(k_t10_codes, dim3((unsigned)(groups * 3)), dim3(256), lds, s, X, rows, ld, cols, fill,
                        reinterpret_cast<uint32_t *>(T10), ld10 / 4, has_nan, ties);
     return hipGetLastError();
@@ -247,6 +251,7 @@ hipError_t launch_layout(const float *src, int64_t ld_src, bool src_col_major, i
 {
     if (nr <= 0) return hipSuccess;
     dim3 grid((unsigned)((nr + 63) / 64), (unsigned)((cols + 63) / 64));
+    clear_last_error();
     hipLaunchKernelGGL(k_layout, grid, dim3(256), 0, s, src, ld_src, (int32_t)src_col_major, nr,
                        cols, r0, dst, ld, sentinel, dst_fill, fill);
     return hipGetLastError();
@@ -257,6 +262,7 @@ hipError_t launch_zero_pad(float *dst, int64_t rows, int64_t ld, int32_t cols, h
     const int64_t total = (ld - rows) * cols;
     if (total <= 0) return hipSuccess;
     const int threads = 256;
+    clear_last_error();
     hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads),
                        0, s, dst, rows, ld, cols);
     return hipGetLastError();

@@ -359,55 +359,52 @@ __global__ void __launch_bounds__(1024) k_eval_pairs(ReqDesc d, const IndHead *_
     if (COUNT && lane == 0 && steps) atomicAdd(step_counter, (unsigned long long)steps);
 }
 
-// The batched launch: persistent blocks take items from eight queues, one
-// per XCD slice (block b starts with queue b mod 8, then helps the others).
-// A queue walks its slice's chunks in order, segment by segment (the
-// requests that read one set of bitmaps), every group of every request of
-// the segment on a chunk before the next chunk: item k of slice x in
-// segment g is chunk 8 (l / groups) + x and group l mod groups (l = k minus
-// the segment's first item in the queue), the group found among the
-// segment's requests by their first groups.
+// The batched launch: a fixed grid (a multiple of 8 blocks) over eight item
+// lists, one per XCD slice: block b walks list b mod 8 with a stride of
+// grid / 8 (items b / 8, b / 8 + grid / 8, ...), so the blocks of a slice
+// take its items in order, all of them near the same chunk at a time, with
+// no counter to contend for. A list walks its slice's chunks in order,
+// segment by segment (the requests that read one set of bitmaps), every
+// group of every request of the segment on a chunk before the next chunk:
+// item k of slice x in segment g is chunk 8 (l / groups) + x and group
+// l mod groups (l = k minus the segment's first item in the list), the
+// group found among the segment's requests by their first groups.
 template <bool COUNT>
-__global__ void __launch_bounds__(1024) k_eval_pairs_batch(PairQueues *__restrict__ pq, const ReqDesc *__restrict__ descs,
+__global__ void __launch_bounds__(1024) k_eval_pairs_batch(const PairQueues *__restrict__ pq,
+                                                           const ReqDesc *__restrict__ descs,
                                                            const PairSeg *__restrict__ segs,
                                                            const int32_t *__restrict__ seg_req,
                                                            const int32_t *__restrict__ seg_gstart,
-                                                           const IndHead *__restrict__ heads, int32_t P,
+                                                           const IndHead *__restrict__ heads,
                                                            unsigned long long *step_counter)
 {
-    __shared__ int32_t s_item;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int W = blockDim.x / kWave;
     const int32_t n_seg = pq->n_seg;
+    const int32_t P = min(pq->P, 64 * W);  // (the planner keeps it there)
+    const int slice = (int)(blockIdx.x % 8);
+    const int32_t stride = (int32_t)(gridDim.x / 8);
+    const int32_t total = pq->total[slice];
     uint64_t steps = 0;
-    for (int o = 0; o < 8; ++o) {
-        const int slice = (int)((blockIdx.x + o) % 8);
-        const int32_t total = pq->total[slice];
-        for (;;) {
-            if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(&pq->counter[slice], 1u);
-            __syncthreads();
-            const int32_t k = __builtin_amdgcn_readfirstlane(s_item);
-            __syncthreads();
-            if (k >= total) break;
-            int32_t g = 0;
-            while (g + 1 < n_seg && segs[g + 1].base[slice] <= k) ++g;
-            const int32_t local = k - segs[g].base[slice];
-            const int32_t groups = segs[g].groups;
-            const int32_t chunk = 8 * (local / groups) + slice;
-            const int32_t pos = local % groups;
-            int32_t lo = segs[g].e0, hi = segs[g].e0 + segs[g].n_req - 1;  // the last entry starting at or before pos
-            while (lo < hi) {
-                const int32_t mid = (lo + hi + 1) >> 1;
-                if (seg_gstart[mid] <= pos) lo = mid;
-                else hi = mid - 1;
-            }
-            const ReqDesc &d = descs[seg_req[lo]];
-            const int32_t i0 = (pos - seg_gstart[lo]) * P;
-            const int32_t np = min(P, d.n - i0);
-            if (d.flags & kFlagNeg) pairs_item<true, COUNT>(d, heads, i0, np, chunk, lane, wave, W, steps);
-            else pairs_item<false, COUNT>(d, heads, i0, np, chunk, lane, wave, W, steps);
+    int32_t g = 0;  // (items come in order: the segment only moves forward)
+    for (int32_t k = (int32_t)(blockIdx.x / 8); k < total; k += stride) {
+        while (g + 1 < n_seg && segs[g + 1].base[slice] <= k) ++g;
+        const int32_t local = k - segs[g].base[slice];
+        const int32_t groups = segs[g].groups;
+        const int32_t chunk = 8 * (local / groups) + slice;
+        const int32_t pos = local % groups;
+        int32_t lo = segs[g].e0, hi = segs[g].e0 + segs[g].n_req - 1;  // the last entry starting at or before pos
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (seg_gstart[mid] <= pos) lo = mid;
+            else hi = mid - 1;
         }
+        const ReqDesc &d = descs[seg_req[lo]];
+        const int32_t i0 = (pos - seg_gstart[lo]) * P;
+        const int32_t np = min(P, d.n - i0);
+        if (d.flags & kFlagNeg) pairs_item<true, COUNT>(d, heads, i0, np, chunk, lane, wave, W, steps);
+        else pairs_item<false, COUNT>(d, heads, i0, np, chunk, lane, wave, W, steps);
     }
     if (COUNT && lane == 0 && steps) atomicAdd(step_counter, (unsigned long long)steps);
 }
@@ -427,6 +424,7 @@ hipError_t launch_pair_bits(const float *X, int64_t rows, int64_t ld, int32_t co
     if (cols < 1 || cols > kMaxPairCols || w32 != pair_words(rows) || ld % 64 != 0) return hipErrorInvalidValue;
     const int64_t chunks = w32 / kChunkWords;
     if (chunks > 0x7fffffff) return hipErrorInvalidValue;
+    clear_last_error();
     hipLaunchKernelGGL(k_pair_bits, dim3((unsigned)chunks, (unsigned)cols), dim3(64), 0, s, X, rows, ld, cols,
                        subst ? 1 : 0, fill, G, T);
     return hipGetLastError();
@@ -436,6 +434,7 @@ hipError_t launch_prep_pairs(const ReqDesc &d, IndHead *heads, hipStream_t s)
 {
     const int threads = 256;
     const int per_block = threads / kWave;  // one wave per individual
+    clear_last_error();
     hipLaunchKernelGGL(k_prep_pairs, dim3((d.n + per_block - 1) / per_block), dim3(threads), 0, s, d, heads);
     return hipGetLastError();
 }
@@ -453,18 +452,19 @@ int pairs_batch_occupancy(int32_t W)
     return blocks;
 }
 
-hipError_t launch_pairs_batch(PairQueues *pq, const ReqDesc *descs, const PairSeg *segs, const int32_t *seg_req,
-                              const int32_t *seg_gstart, const IndHead *heads, int32_t W, int32_t P, int32_t grid,
-                              unsigned long long *step_counter, hipStream_t s)
+hipError_t launch_pairs_batch(const PairQueues *pq, const ReqDesc *descs, const PairSeg *segs,
+                              const int32_t *seg_req, const int32_t *seg_gstart, const IndHead *heads, int32_t W,
+                              int32_t grid, unsigned long long *step_counter, hipStream_t s)
 {
-    if (W < 1 || W > 16 || P < 1 || P > 64 * W || grid < 1) return hipErrorInvalidValue;
+    if (W < 1 || W > 16 || grid < 8 || grid % 8 != 0) return hipErrorInvalidValue;
     const bool count = step_counter != nullptr;
+    clear_last_error();
     if (count)
         hipLaunchKernelGGL(k_eval_pairs_batch<true>, dim3(grid), dim3(W * kWave), 0, s, pq, descs, segs, seg_req,
-                           seg_gstart, heads, P, step_counter);
+                           seg_gstart, heads, step_counter);
     else
         hipLaunchKernelGGL(k_eval_pairs_batch<false>, dim3(grid), dim3(W * kWave), 0, s, pq, descs, segs, seg_req,
-                           seg_gstart, heads, P, step_counter);
+                           seg_gstart, heads, step_counter);
     return hipGetLastError();
 }
 

@@ -89,3 +89,39 @@ def test_budget_refuses_oversized_and_serialises_tight(served):
         offs, cols = pools[j % 4][j % 6]
         assert_same((r.matched, r.negative, r.matched_mask, r.negative_mask),
                     _alone(ctx, mats[j % 4], offs, cols, masks=True), f"tight {j}")
+
+
+def test_graph_captures_stay_one_per_slot():
+    """Batches of any mix of population sizes over several matrices (all
+    on the pair bitmaps, whose group size travels in the batch's arena)
+    replay one captured graph per slot stream; every result equals the
+    request evaluated alone."""
+    import torch
+    from paper_1807_09932_amd.ebic import Context
+    from paper_1807_09932_amd.serve import Server
+    rng = np.random.default_rng(91)
+    with Context(0) as ctx:
+        Xs = [rng.standard_normal((r, c)).astype(np.float32) for r, c in ((3_000, 40), (9_000, 120), (20_000, 64))]
+        mats = [ctx.upload(X) for X in Xs]
+        jobs = []
+        for i in range(90):
+            j = i % 3
+            n = int(rng.integers(5, 400))
+            inds = [rng.permutation(Xs[j].shape[1])[: int(rng.integers(2, 20))].astype(np.int32) for _ in range(n)]
+            jobs.append((j, *gen.csr(inds)))
+        announce("serve graph captures", len(jobs))
+        with Server(ctx, hbm_budget_bytes=64 << 20, slots=2) as srv:
+            srv.pause(True)
+            futs = [srv.submit(i, mats[j], o, c, negative=True) for i, (j, o, c) in enumerate(jobs[:40])]
+            srv.pause(False)
+            futs += [srv.submit(i, mats[j], o, c, negative=True) for i, (j, o, c) in enumerate(jobs[40:])]
+            results = [f.result(timeout=60) for f in futs]
+            stats = srv.stats()
+        assert stats["graph_captures"] <= 2, stats
+        for i in (0, 17, 45, 89):
+            j, o, c = jobs[i]
+            alone = _alone(ctx, mats[j], o, c)
+            assert np.array_equal(results[i].matched, alone[0]) and np.array_equal(results[i].negative, alone[1])
+        torch.cuda.synchronize()
+        for m in mats:
+            ctx.release(m)
