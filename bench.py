@@ -102,6 +102,9 @@ def pairs_roofline(offs, cols, rows, ncols, steps, k_ms):
     ach = nbytes / t / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "algorithmic_bytes": nbytes, "distinct_window_pairs": d, "chunks": chunks,
+            "frac_basis": "the bytes this formulation must read per launch (the window pairs' words on every "
+                          "chunk); roofline_views.hbm_min_bytes gives the fraction on the method's own minimum, "
+                          "the FP32 matrix read once",
             "l2_view": {"bytes": steps * PAIR_WORD_BYTES, "achieved": steps * PAIR_WORD_BYTES / t / 1e9,
                         "peak": L2_PEAK_GBS, "unit": "GB/s",
                         "frac": steps * PAIR_WORD_BYTES / t / 1e9 / L2_PEAK_GBS,
