@@ -349,3 +349,50 @@ def test_pairs_batched_mixed(ctx):
     finally:
         for m in mats.values():
             ctx.release(m)
+
+
+def test_pairs_allocation_failure_falls_back():
+    """A failed allocation of the bitmaps (injected with EBIC_FAULT at each
+    allocation in turn) leaves the matrix on its rank codes: the call that
+    would have built them evaluates on the codes, later plans do not offer
+    the bitmaps again, and the counts are exact throughout."""
+    import os
+    import torch
+    from paper_1807_09932_amd import ebic
+    from paper_1807_09932_amd.ebic import Context
+    rng = np.random.default_rng(55)
+    X = rng.standard_normal((5_000, 48)).astype(np.float32)
+    offs, cc = _pop(rng, 48, 80, kmax=16)
+    want = oracle_eval(X, offs, cc, negative=True, masks=False)
+    fell_back = 0
+    for after in range(0, 8):
+        old = os.environ.pop("EBIC_FAULT", None)
+        os.environ["EBIC_FAULT"] = f"alloc:{after}"
+        try:
+            ctx = Context(0)
+        finally:
+            os.environ.pop("EBIC_FAULT", None)
+            if old is not None:
+                os.environ["EBIC_FAULT"] = old
+        try:
+            announce("pairs alloc fault", after)
+            try:
+                mat = ctx.upload(X)
+            except ebic.EbicError as e:
+                assert e.status == ebic.EBIC_ENOMEM
+                mat = ctx.upload(X)
+            for _ in range(2):
+                try:
+                    got = gpu_eval(ctx, mat, offs, cc, negative=True, masks=False)
+                except ebic.EbicError as e:  # (a failure of another allocation: the call fails whole)
+                    assert e.status == ebic.EBIC_ENOMEM
+                    got = gpu_eval(ctx, mat, offs, cc, negative=True, masks=False)
+                assert_same((got[0], got[1], None, None), want, f"alloc fault {after}")
+            if not ctx.stats(mat)["code_sets"] & ebic.SET_PAIRS:
+                fell_back += 1
+                assert ebic.ebic_plan_shape(ctx.handle, mat, offs.size - 1)[3] != ebic.STAGE_PAIRS
+            torch.cuda.synchronize()
+            ctx.release(mat)
+        finally:
+            ctx.close()
+    assert fell_back >= 1, "no injected failure reached the bitmap allocation"
