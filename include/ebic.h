@@ -291,7 +291,8 @@ ebic_status ebic_autotune(ebic_ctx *ctx, const ebic_request *sample, int32_t n_r
  *                              for every ordered pair of columns, built on
  *                              first use: cols^2 x ceil(rows / 2048) x 256
  *                              bytes plus 512 bytes per 2,048 rows, at most
- *                              1,024 columns and 32 GiB); nothing staged,
+ *                              1,024 columns, 1,073,725,440 rows and 32
+ *                              GiB); nothing staged,
  *                              tiles_per_wave and blocks ignored, at most
  *                              64 individuals per wave (individuals_per_group
  *                              0 with a shape of this staging: chosen from

@@ -2650,7 +2650,9 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
         unsigned long long *sc = step_counter;
         void *params[] = {&dd, &hh, &P, &nt, &sc};
         if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-        e = hipLaunchKernel(kp, dim3(pairs_grid(d.rows, d.n, cfg.P)), dim3(cfg.W * kWave), params, lds, s);
+        const dim3 grid = pairs_grid(d.rows, d.n, cfg.P);
+        if (grid.x > 0x7fffffffu || grid.y > 65535u) return hipErrorInvalidValue;
+        e = hipLaunchKernel(kp, grid, dim3(cfg.W * kWave), params, lds, s);
         if (e != hipSuccess) return e;
         if (ev1) e = hipEventRecord(ev1, s);
         return e;

@@ -256,6 +256,7 @@ inline void clear_last_error() { (void)hipGetLastError(); }
 // pairs headers, the evaluation kernel for request flags (ReqDesc: B = the
 // words, T = the tie lists), and its grid.
 constexpr int32_t kMaxPairCols = 1024;
+constexpr int64_t kMaxPairRows = 65535ll * 8 * 2048;  // (the plain launch's grid: chunks / 8 in y)
 constexpr int32_t kDefaultPairCols = 512;  // widths planned on the bitmaps unless a shape says otherwise
 constexpr int64_t kMaxPairBytes = 32ll << 30;
 int64_t pair_words(int64_t rows);
@@ -264,7 +265,7 @@ hipError_t launch_pair_bits(const float *X, int64_t rows, int64_t ld, int32_t co
                             uint32_t *G, int64_t w32, uint32_t *T, hipStream_t s);
 hipError_t launch_prep_pairs(const ReqDesc &d, IndHead *heads, hipStream_t s);
 const void *pairs_kernel(uint32_t flags, bool count);
-unsigned pairs_grid(int64_t rows, int32_t n, int32_t P);
+dim3 pairs_grid(int64_t rows, int32_t n, int32_t P);
 
 // The pair items of a batch: eight lists, one per XCD slice (a slice: the
 // chunks c with c mod 8 = x), each walking its chunks in order segment by

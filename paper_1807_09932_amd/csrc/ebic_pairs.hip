@@ -335,20 +335,20 @@ __device__ __forceinline__ void pairs_item(const ReqDesc &d, const IndHead *__re
     }
 }
 
-// The plain launch: block b works on XCD slice x = b mod 8 (the chunks x,
-// x + 8, x + 16, ..., which on MI355X's round-robin placement of blocks over
-// the eight XCDs all run on one XCD and share its L2) and, with j = b / 8,
-// on group j mod G of at most P individuals and on the slice's (j / G)-th
-// chunk: the blocks of a chunk are dispatched together.
+// The plain launch: a 2-D grid of (8 x groups, chunks / 8) blocks. Block
+// (x, y) works on chunk 8 y + x mod 8 and group x / 8: blocks are dispatched
+// x first, and with gridDim.x a multiple of 8 the linear block index is
+// x mod 8 modulo 8, so on MI355X's round-robin placement of blocks over the
+// eight XCDs the blocks of a chunk all run on one XCD and share its L2, and
+// the blocks of eight consecutive chunks (all their groups) are dispatched
+// together.
 template <bool NEG, bool COUNT>
 __global__ void __launch_bounds__(1024) k_eval_pairs(ReqDesc d, const IndHead *__restrict__ heads, int32_t P,
                                                      int32_t n_tiles, unsigned long long *step_counter)
 {
     const int32_t n_chunks = (n_tiles + 31) / 32;
-    const int32_t G_groups = (d.n + P - 1) / P;
-    const uint32_t b = blockIdx.x, j = b / 8;
-    const int32_t chunk = (int32_t)(8 * (j / G_groups) + b % 8);
-    const int32_t grp = (int32_t)(j % G_groups);
+    const int32_t chunk = (int32_t)(8 * blockIdx.y + (blockIdx.x & 7));
+    const int32_t grp = (int32_t)(blockIdx.x >> 3);
     if (chunk >= n_chunks) return;
     const int32_t i0 = grp * P;
     const int32_t np = min(P, d.n - i0);
@@ -475,12 +475,12 @@ const void *pairs_kernel(uint32_t flags, bool count)
     return neg ? (const void *)&k_eval_pairs<true, false> : (const void *)&k_eval_pairs<false, false>;
 }
 
-// Blocks of the plain pairs launch: 8 XCD slices x groups x chunks per slice.
-unsigned pairs_grid(int64_t rows, int32_t n, int32_t P)
+// The plain pairs launch's grid: (8 x groups, chunks / 8 rounded up).
+dim3 pairs_grid(int64_t rows, int32_t n, int32_t P)
 {
     const int64_t groups = (n + P - 1) / P;
     const int64_t per_slice = ((rows + kChunkRows - 1) / kChunkRows + 7) / 8;
-    return (unsigned)(8 * groups * per_slice);
+    return dim3((unsigned)(8 * groups), (unsigned)per_slice);
 }
 
 }  // namespace ebic

@@ -267,7 +267,7 @@ static const uint32_t *pairs_marks(const Matrix &m, const uint32_t *G)
 
 bool pairs_buildable(const Matrix &m)
 {
-    return m.dev.cols <= kMaxPairCols && pairs_bytes(m) <= kMaxPairBytes;
+    return m.dev.cols <= kMaxPairCols && m.dev.rows <= kMaxPairRows && pairs_bytes(m) <= kMaxPairBytes;
 }
 
 // The bitmaps a mode reads: exclude mode those of X; include mode those of
@@ -284,7 +284,8 @@ void build_pairs(ebic_ctx *ctx, Matrix &m, bool include)
     if (pairs_for(m, include)) return;
     if (!pairs_buildable(m))
         fail(EBIC_EINVAL, "pairwise order bitmaps serve matrices of at most " + std::to_string(kMaxPairCols) +
-                              " columns and " + std::to_string(kMaxPairBytes >> 30) + " GiB");
+                              " columns, " + std::to_string(kMaxPairRows) + " rows and " +
+                              std::to_string(kMaxPairBytes >> 30) + " GiB");
     const bool subst = include && m.has_missing != 0;  // (unknown counts as missing)
     DeviceGuard g(ctx->device);
     const int64_t w32 = pair_words(m.dev.rows);
