@@ -243,10 +243,12 @@ typedef struct ebic_request {
 /*
  * Evaluate many populations -- of uneven sizes, with individuals of uneven
  * lengths, from many concurrent EBIC runs, over one or several resident
- * matrices -- in one persistent launch replayed from a captured HIP graph.
- * Each request's outputs equal those of ebic_eval_population on the same
- * inputs. `reqs` is a host array of n_reqs entries (read before the call
- * returns). Asynchronous on `hip_stream`.
+ * matrices -- in one replay of a captured HIP graph: requests on matrices
+ * that take the pair bitmaps (staging 6, built here on first use) in one
+ * fixed-grid kernel, the others in one persistent tiled kernel. Each
+ * request's outputs equal those of ebic_eval_population on the same inputs.
+ * `reqs` is a host array of n_reqs entries (read before the call returns).
+ * Asynchronous on `hip_stream`.
  */
 ebic_status ebic_eval_batch(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs,
                             void *hip_stream);
@@ -313,7 +315,9 @@ ebic_status ebic_set_launch_shape(ebic_ctx *ctx, int32_t tiles_per_wave, int32_t
  * set, else the tuned one for its shape class, else the default, reduced to
  * what the device fits. Any output may be NULL. Staging: 0 = LDS, 1 = direct,
  * 2 = rank codes in LDS, 3 = byte rank codes in LDS, 4 = 16-bit rank codes in
- * LDS (the staging planned for exclude mode).
+ * LDS, 5 = 10-bit rank codes in LDS, 6 = the pair bitmaps (the staging
+ * planned for exclude mode; for staging 6, blocks reports the 2,048-row
+ * chunks).
  */
 ebic_status ebic_plan_shape(ebic_ctx *ctx, int32_t matrix, int32_t n_ind, int64_t nnz,
                             int32_t *tiles_per_wave, int32_t *waves_per_block,
@@ -323,8 +327,9 @@ ebic_status ebic_plan_shape(ebic_ctx *ctx, int32_t matrix, int32_t n_ind, int64_
  * The launch shape ebic_eval_batch would use now for `reqs` (the same
  * validation, no launch): tiles per wave, waves per block, individuals per
  * group, the grid size, and, if `stagings` is not NULL, the staging of each
- * request (n_reqs entries, numbered as for ebic_plan_shape). Any output may
- * be NULL.
+ * request (n_reqs entries, numbered as for ebic_plan_shape). The shape is
+ * the tiled kernel's when any request is on it, else the pairs kernel's.
+ * Any output may be NULL.
  */
 ebic_status ebic_plan_batch_shape(ebic_ctx *ctx, const ebic_request *reqs, int32_t n_reqs,
                                   int32_t *tiles_per_wave, int32_t *waves_per_block,
