@@ -2638,7 +2638,7 @@ hipError_t launch_eval(const ReqDesc &d, IndHead *heads, const LaunchCfg &cfg,
     }
     if (cfg.staging == STAGE_PAIRS) {
         // (no tile and no LDS: a flat grid of chunk x group blocks)
-        const void *kp = pairs_kernel(d.flags, step_counter != nullptr);
+        const void *kp = pairs_kernel(d.flags, step_counter != nullptr, cfg.P, cfg.W);
         const size_t lds = 0;
         hipError_t e = set_lds(kp, lds);
         if (e != hipSuccess) return e;

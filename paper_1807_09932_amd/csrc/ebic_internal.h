@@ -264,7 +264,7 @@ int64_t pair_tie_bytes(int64_t rows);
 hipError_t launch_pair_bits(const float *X, int64_t rows, int64_t ld, int32_t cols, bool subst, float fill,
                             uint32_t *G, int64_t w32, uint32_t *T, hipStream_t s);
 hipError_t launch_prep_pairs(const ReqDesc &d, IndHead *heads, hipStream_t s);
-const void *pairs_kernel(uint32_t flags, bool count);
+const void *pairs_kernel(uint32_t flags, bool count, int32_t P, int32_t W);
 dim3 pairs_grid(int64_t rows, int32_t n, int32_t P);
 
 // The pair items of a batch: eight lists, one per XCD slice (a slice: the

@@ -46,7 +46,10 @@
 // loads the seven pairs (two individuals' at a time), ANDs them, takes the
 // reversed chain as their complement where the chunk allows it (else loads
 // the reversed pairs), and follows the columns past the window eight at a
-// time while any row is left. No tile is staged: the words come through L2
+// time while any row is left. Where a wave takes many individuals per item
+// (the batched kernel, and plain launches of eight or more per wave), the
+// next two individuals' headers are loaded while the current pairs are in
+// flight. No tile is staged: the words come through L2
 // and the Infinity Cache, where the pairs shared by the individuals of a
 // chunk are reused, and the blocks of a chunk are placed on one XCD and run
 // together. The counts of the wave's 2,048 rows are summed across lanes by
@@ -67,6 +70,7 @@ constexpr int kChunkWords = 64;
 constexpr int kTieWords = 128;    // per chunk: count, NaN flag, ..., 64 listed offsets
 constexpr int kTieList = 64;      // (the list's first word)
 constexpr uint32_t kNoPair = 0xffffffffu;  // never a pair's offset (those are multiples of 256)
+constexpr int kPipeMin = 8;       // individuals per wave and item from which the headers are loaded ahead
 
 __global__ void __launch_bounds__(256) k_prep_pairs(ReqDesc d, IndHead *__restrict__ heads)
 {
@@ -157,11 +161,36 @@ __device__ __forceinline__ uint32_t wave_total(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane(s, 63);
 }
 
+// What the item loop takes from a pairs header up front (the CSR start and
+// the window's columns are read where they are needed: the reversed pairs'
+// loads and the columns past the window).
+struct PairScal {
+    int32_t k;
+    uint32_t f[7];
+};
+
+__device__ __forceinline__ PairScal pair_scal(const PairHead *h)
+{
+    const int4 *p = reinterpret_cast<const int4 *>(h);
+    const int4 x0 = p[0], x1 = p[1];
+    const uint32_t x2 = h->fwd[6];
+    PairScal s;
+    s.k = __builtin_amdgcn_readfirstlane(x0.x);
+    s.f[0] = (uint32_t)__builtin_amdgcn_readfirstlane(x0.z);
+    s.f[1] = (uint32_t)__builtin_amdgcn_readfirstlane(x0.w);
+    s.f[2] = (uint32_t)__builtin_amdgcn_readfirstlane(x1.x);
+    s.f[3] = (uint32_t)__builtin_amdgcn_readfirstlane(x1.y);
+    s.f[4] = (uint32_t)__builtin_amdgcn_readfirstlane(x1.z);
+    s.f[5] = (uint32_t)__builtin_amdgcn_readfirstlane(x1.w);
+    s.f[6] = (uint32_t)__builtin_amdgcn_readfirstlane((int)x2);
+    return s;
+}
+
 // One work item: individuals [i0, i0 + np) of a request on one 2,048-row
 // chunk, by the W waves of a block (the wave's individuals in turn, at most
 // 64 per wave); each lane of a wave keeps the counts of one of the wave's
 // individuals, added to the outputs at the end.
-template <bool NEG, bool COUNT>
+template <bool NEG, bool COUNT, bool PIPE>
 __device__ __forceinline__ void pairs_item(const ReqDesc &d, const IndHead *__restrict__ heads, int32_t i0,
                                            int32_t np, int32_t chunk, int lane, int wave, int W, uint64_t &steps)
 {
@@ -184,7 +213,8 @@ __device__ __forceinline__ void pairs_item(const ReqDesc &d, const IndHead *__re
         // count); `dirty` when the list overflowed or a NaN occurs.
         const uint32_t *tl = reinterpret_cast<const uint32_t *>(d.T) + (int64_t)chunk * kTieWords;
         const uint32_t n_tied = __builtin_amdgcn_readfirstlane(tl[0]);
-        const bool dirty = n_tied > (uint32_t)kTieList || __builtin_amdgcn_readfirstlane(tl[1]) != 0;
+        const uint32_t nan_flag = __builtin_amdgcn_readfirstlane(tl[1]);  // (read either way: no dependent load)
+        const bool dirty = (n_tied > (uint32_t)kTieList) | (nan_flag != 0);
         const uint32_t tied = (uint32_t)lane < n_tied ? tl[kTieList + lane] : kNoPair;
         const bool clean = n_tied == 0 && !dirty;
         const int64_t nvalid = d.rows - ((int64_t)chunk * kChunkRows + 32 * lane);
@@ -202,7 +232,11 @@ __device__ __forceinline__ void pairs_item(const ReqDesc &d, const IndHead *__re
 
         // The reversed chain of the window from its columns (loads of the
         // reversed pairs; (c, c): "present", implied by the pairs next to it).
-        auto slow_window = [&](const uint32_t (&wp)[4]) {
+        auto slow_window = [&](const PairHead *h) {
+            const uint32_t *hw = h->win;
+            uint32_t wp[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) wp[u] = (uint32_t)__builtin_amdgcn_readfirstlane((int)hw[u]);
             uint32_t q[7];
 #pragma unroll
             for (int u = 0; u < 7; ++u) {
@@ -214,8 +248,9 @@ __device__ __forceinline__ void pairs_item(const ReqDesc &d, const IndHead *__re
         };
         // The columns past the window, eight at a time (the last one
         // repeated past the end), while a row is left.
-        auto tail = [&](uint32_t &Pw, uint32_t &Nw, int32_t k, int32_t begin, uint32_t prev) {
-            const int32_t *cc = d.colidx + begin;
+        auto tail = [&](uint32_t &Pw, uint32_t &Nw, int32_t k, const PairHead *h) {
+            const int32_t *cc = d.colidx + __builtin_amdgcn_readfirstlane(h->begin);
+            uint32_t prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->win[3]) >> 16;  // the window's last column
             for (int32_t u = 8; u < k; u += 8) {
                 uint32_t cn[8], fo[8], pp[8];
 #pragma unroll
@@ -262,68 +297,60 @@ __device__ __forceinline__ void pairs_item(const ReqDesc &d, const IndHead *__re
         };
 
         // Two individuals at a time (ii and ii + W, the wave's t-th and
-        // (t + 1)-th): both windows' loads in flight together. The window
+        // (t + 1)-th): both windows' loads in flight together, and the
+        // next two individuals' headers loaded while they are. The window
         // needs no branch: an individual of one column has the diagonal
         // pair in every slot (its reversed chain, whatever it gives, adds
         // nothing: its rows are all positive), and an invalid one (k = 0)
         // is zeroed after the loads.
-        int32_t t = 0;
-        for (int32_t ii = wave; ii < np; ii += 2 * W, t += 2) {
-            const bool two = ii + W < np;
-            const int4 *ha = reinterpret_cast<const int4 *>(hb + ii);
-            const int4 *hc = reinterpret_cast<const int4 *>(hb + (two ? ii + W : ii));
-            const int4 a0 = ha[0], a1 = ha[1], a2 = ha[2], a3 = ha[3];
-            const int4 b0 = hc[0], b1 = hc[1], b2 = hc[2], b3 = hc[3];
-            const int32_t ka = __builtin_amdgcn_readfirstlane(a0.x), kb = __builtin_amdgcn_readfirstlane(b0.x);
-            const uint32_t fa[7] = {(uint32_t)__builtin_amdgcn_readfirstlane(a0.z),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(a0.w),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(a1.x),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(a1.y),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(a1.z),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(a1.w),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(a2.x)};
-            const uint32_t fb[7] = {(uint32_t)__builtin_amdgcn_readfirstlane(b0.z),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(b0.w),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(b1.x),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(b1.y),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(b1.z),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(b1.w),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(b2.x)};
-            uint32_t pa[7], pb[7];
+        int32_t ii = wave;
+        if (ii < np) {
+            int32_t t = 0;
+            PairScal A = pair_scal(hb + ii), B = pair_scal(hb + min(ii + W, np - 1));
+            for (;;) {
+                const bool two = ii + W < np;
+                uint32_t pa[7], pb[7];
 #pragma unroll
-            for (int u = 0; u < 7; ++u) {
-                pa[u] = ld(fa[u]);
-                pb[u] = ld(fb[u]);
-            }
-            uint32_t Pa = pa[0] & pa[1] & pa[2] & pa[3] & pa[4] & pa[5] & pa[6];
-            uint32_t Pb = pb[0] & pb[1] & pb[2] & pb[3] & pb[4] & pb[5] & pb[6];
-            uint32_t Na = 0, Nb = 0;
-            if (NEG) {
-                const uint32_t wa[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(a2.z),
-                                        (uint32_t)__builtin_amdgcn_readfirstlane(a2.w),
-                                        (uint32_t)__builtin_amdgcn_readfirstlane(a3.x),
-                                        (uint32_t)__builtin_amdgcn_readfirstlane(a3.y)};
-                const uint32_t wb[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(b2.z),
-                                        (uint32_t)__builtin_amdgcn_readfirstlane(b2.w),
-                                        (uint32_t)__builtin_amdgcn_readfirstlane(b3.x),
-                                        (uint32_t)__builtin_amdgcn_readfirstlane(b3.y)};
-                Na = untied(fa, 7) ? ~(pa[0] | pa[1] | pa[2] | pa[3] | pa[4] | pa[5] | pa[6]) & vmask
-                                   : slow_window(wa);
-                Nb = untied(fb, 7) ? ~(pb[0] | pb[1] | pb[2] | pb[3] | pb[4] | pb[5] | pb[6]) & vmask
-                                   : slow_window(wb);
-            }
-            if (ka == 0) Pa = Na = 0u;
-            if (kb == 0) Pb = Nb = 0u;
-            if (COUNT) steps += (ka > 1 ? 7 : ka) + (two ? (kb > 1 ? 7 : kb) : 0);
-            if (ka > 8 && __ballot((Pa | Na) != 0) != 0)
-                tail(Pa, Na, ka, __builtin_amdgcn_readfirstlane(a0.y),
-                     (uint32_t)__builtin_amdgcn_readfirstlane(a3.y) >> 16);
-            finish(Pa, Na, ii, t);
-            if (two) {
-                if (kb > 8 && __ballot((Pb | Nb) != 0) != 0)
-                    tail(Pb, Nb, kb, __builtin_amdgcn_readfirstlane(b0.y),
-                         (uint32_t)__builtin_amdgcn_readfirstlane(b3.y) >> 16);
-                finish(Pb, Nb, ii + W, t + 1);
+                for (int u = 0; u < 7; ++u) {
+                    pa[u] = ld(A.f[u]);
+                    pb[u] = ld(B.f[u]);
+                }
+                const int32_t jn = ii + 2 * W;
+                const bool more = jn < np;
+                PairScal An, Bn;
+                if (PIPE && more) {
+                    An = pair_scal(hb + jn);
+                    Bn = pair_scal(hb + min(jn + W, np - 1));
+                }
+                uint32_t Pa = pa[0] & pa[1] & pa[2] & pa[3] & pa[4] & pa[5] & pa[6];
+                uint32_t Pb = pb[0] & pb[1] & pb[2] & pb[3] & pb[4] & pb[5] & pb[6];
+                uint32_t Na = 0, Nb = 0;
+                if (NEG) {
+                    Na = untied(A.f, 7) ? ~(pa[0] | pa[1] | pa[2] | pa[3] | pa[4] | pa[5] | pa[6]) & vmask
+                                        : slow_window(hb + ii);
+                    Nb = untied(B.f, 7) ? ~(pb[0] | pb[1] | pb[2] | pb[3] | pb[4] | pb[5] | pb[6]) & vmask
+                                        : slow_window(hb + min(ii + W, np - 1));
+                }
+                if (A.k == 0) Pa = Na = 0u;
+                if (B.k == 0) Pb = Nb = 0u;
+                if (COUNT) steps += (A.k > 1 ? 7 : A.k) + (two ? (B.k > 1 ? 7 : B.k) : 0);
+                if (A.k > 8 && __ballot((Pa | Na) != 0) != 0) tail(Pa, Na, A.k, hb + ii);
+                finish(Pa, Na, ii, t);
+                if (two) {
+                    if (B.k > 8 && __ballot((Pb | Nb) != 0) != 0)
+                        tail(Pb, Nb, B.k, hb + ii + W);
+                    finish(Pb, Nb, ii + W, t + 1);
+                }
+                if (!more) break;
+                if (PIPE) {
+                    A = An;
+                    B = Bn;
+                } else {
+                    A = pair_scal(hb + jn);
+                    B = pair_scal(hb + min(jn + W, np - 1));
+                }
+                ii = jn;
+                t += 2;
             }
         }
     }
@@ -342,7 +369,7 @@ __device__ __forceinline__ void pairs_item(const ReqDesc &d, const IndHead *__re
 // eight XCDs the blocks of a chunk all run on one XCD and share its L2, and
 // the blocks of eight consecutive chunks (all their groups) are dispatched
 // together.
-template <bool NEG, bool COUNT>
+template <bool NEG, bool COUNT, bool PIPE>
 __global__ void __launch_bounds__(1024) k_eval_pairs(ReqDesc d, const IndHead *__restrict__ heads, int32_t P,
                                                      int32_t n_tiles, unsigned long long *step_counter)
 {
@@ -355,7 +382,7 @@ __global__ void __launch_bounds__(1024) k_eval_pairs(ReqDesc d, const IndHead *_
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     uint64_t steps = 0;
-    pairs_item<NEG, COUNT>(d, heads, i0, np, chunk, lane, wave, blockDim.x / kWave, steps);
+    pairs_item<NEG, COUNT, PIPE>(d, heads, i0, np, chunk, lane, wave, blockDim.x / kWave, steps);
     if (COUNT && lane == 0 && steps) atomicAdd(step_counter, (unsigned long long)steps);
 }
 
@@ -403,8 +430,8 @@ __global__ void __launch_bounds__(1024) k_eval_pairs_batch(const PairQueues *__r
         const ReqDesc &d = descs[seg_req[lo]];
         const int32_t i0 = (pos - seg_gstart[lo]) * P;
         const int32_t np = min(P, d.n - i0);
-        if (d.flags & kFlagNeg) pairs_item<true, COUNT>(d, heads, i0, np, chunk, lane, wave, W, steps);
-        else pairs_item<false, COUNT>(d, heads, i0, np, chunk, lane, wave, W, steps);
+        if (d.flags & kFlagNeg) pairs_item<true, COUNT, true>(d, heads, i0, np, chunk, lane, wave, W, steps);
+        else pairs_item<false, COUNT, true>(d, heads, i0, np, chunk, lane, wave, W, steps);
     }
     if (COUNT && lane == 0 && steps) atomicAdd(step_counter, (unsigned long long)steps);
 }
@@ -468,11 +495,19 @@ hipError_t launch_pairs_batch(const PairQueues *pq, const ReqDesc *descs, const 
     return hipGetLastError();
 }
 
-const void *pairs_kernel(uint32_t flags, bool count)
+const void *pairs_kernel(uint32_t flags, bool count, int32_t P, int32_t W)
 {
     const bool neg = (flags & kFlagNeg) != 0;
-    if (count) return neg ? (const void *)&k_eval_pairs<true, true> : (const void *)&k_eval_pairs<false, true>;
-    return neg ? (const void *)&k_eval_pairs<true, false> : (const void *)&k_eval_pairs<false, false>;
+    // Loading the next headers early pays once a wave takes four or more
+    // pairs of individuals per item; with fewer, the extra scalar registers
+    // cost more than the hidden latency.
+    const bool pipe = (P + W - 1) / W >= kPipeMin;
+    if (pipe) {
+        if (count) return neg ? (const void *)&k_eval_pairs<true, true, true> : (const void *)&k_eval_pairs<false, true, true>;
+        return neg ? (const void *)&k_eval_pairs<true, false, true> : (const void *)&k_eval_pairs<false, false, true>;
+    }
+    if (count) return neg ? (const void *)&k_eval_pairs<true, true, false> : (const void *)&k_eval_pairs<false, true, false>;
+    return neg ? (const void *)&k_eval_pairs<true, false, false> : (const void *)&k_eval_pairs<false, false, false>;
 }
 
 // The plain pairs launch's grid: (8 x groups, chunks / 8 rounded up).
