@@ -284,6 +284,11 @@ def roofline_views(executed_steps, k_ms, staging, matrix_bytes, n_ind):
                     "compares four (u8), three (u10) or two (u16) rows"},
     }
     if staging == STAGE_PAIRS:
+        views["hbm_min_bytes"]["note"] = (
+            "the method's minimum traffic (the FP32 matrix read once, two int32 counts per "
+            "individual written) over the kernel time; the bitmap kernel reads the words of the "
+            "population's window pairs instead (the roofline above), a different byte count: "
+            "this fraction is what the same time would give a kernel that read only the matrix")
         # (a pair step ANDs one 32-bit word per lane: 2,048 rows of one
         # column pair, the outcome of 2,048 FP32 compares made at the build)
         views["fp32_compare_issue"] = {
