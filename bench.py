@@ -420,10 +420,17 @@ def batched_roofline(steps, g_ms, stagings, shape, packed, rows, ncols):
         offs = np.concatenate([[0]] + [o[1:] + sum(int(q[0][-1]) for q in packed[:i])
                                        for i, (o, _) in enumerate(packed)]).astype(np.int64)
         cols = np.concatenate([c[:int(o[-1])] for o, c in packed])
-        return {**pairs_roofline(offs, cols, rows, ncols, steps, g_ms),
-                "traffic": traffic_from_profile(1, "k_eval_pairs_batch_100000x256_traffic.json",
-                                                shape + (STAGE_PAIRS,)),
-                "time": "the graph replay (descriptor copy, prep, the persistent pairs kernel)"}
+        tr = traffic_from_profile(1, "k_eval_pairs_batch_100000x256_traffic.json", shape + (STAGE_PAIRS,))
+        out = {**pairs_roofline(offs, cols, rows, ncols, steps, g_ms), "traffic": tr,
+               "time": "the graph replay (descriptor copy, prep, the persistent pairs kernel)"}
+        if tr:
+            # (each chunk's words of all the batch's pairs, ~16 MB at 256
+            # columns, outgrow an XCD's L2: words come in several times)
+            out["physical_gbs"] = tr / (g_ms * 1e-3) / 1e9
+            out["physical_frac"] = out["physical_gbs"] / HBM_PEAK_GBS
+            out["physical_note"] = ("the committed FETCH_SIZE + WRITE_SIZE bytes per launch over the "
+                                    "same graph time: L2 fills, from HBM or the Infinity Cache")
+        return out
     return {**alu_roofline(steps, g_ms, stagings[0] if one else None),
             "traffic": (traffic_from_profile(1, "k_eval_batch_100000x256_traffic.json", shape + (stagings[0],))
                         if one else None),
