@@ -79,16 +79,23 @@ __global__ void __launch_bounds__(256) k_prep_pairs(ReqDesc d, IndHead *__restri
     if (i < d.n) prep_pairs_wave(d, i, heads, threadIdx.x & (kWave - 1));
 }
 
-// Block (chunk, a) of one wave: for every b >= a, the words of pairs (a, b)
-// and (b, a) on the chunk's rows; lane l covers rows chunk*2048 + 32 l ...
-// + 31 (one 128-byte run of each column). Ties and NaN go to the chunk's
-// list (T, zeroed beforehand).
+// One wave per block: columns a0 = A t .. A t + A - 1 of one chunk against
+// every b >= a0, the words of pairs (a, b) and (b, a) on the chunk's rows;
+// lane l covers rows chunk*2048 + 32 l ... + 31 (one 128-byte run of each
+// column), and each column b is loaded once for the block's A columns. Ties
+// and NaN go to the chunk's list (T, zeroed beforehand). The grid is
+// (8 x ceil(cols / A), chunks / 8): block (x, y) takes chunk 8 y + x mod 8
+// and t = x / 8, so a chunk's blocks all run on one XCD, one after another,
+// and its columns stay in that XCD's L2 while they do.
+template <int A>
 __global__ void __launch_bounds__(64) k_pair_bits(const float *__restrict__ X, int64_t rows, int64_t ld,
                                                   int32_t cols, int32_t subst, float fill,
                                                   uint32_t *__restrict__ G, uint32_t *__restrict__ T)
 {
-    const int32_t a = (int32_t)blockIdx.y;
-    const int64_t chunk = blockIdx.x;
+    const int64_t n_chunks = (rows + kChunkRows - 1) / kChunkRows;
+    const int64_t chunk = 8 * (int64_t)blockIdx.y + (blockIdx.x & 7);
+    const int32_t a0 = A * (int32_t)(blockIdx.x >> 3);
+    if (chunk >= n_chunks || a0 >= cols) return;
     const int lane = (int)threadIdx.x;
     const int64_t r0 = chunk * kChunkRows + 32 * lane;
     // valid rows of this lane's 32 as a bit mask
@@ -116,11 +123,8 @@ __global__ void __launch_bounds__(64) k_pair_bits(const float *__restrict__ X, i
     };
     uint32_t *tl = T + chunk * kTieWords;
     const uint32_t cb = (uint32_t)cols * 256u;
-    float xa[32];
-    load32(a, xa);
-    for (int32_t b = a; b < cols; ++b) {
-        float xb[32];
-        load32(b, xb);
+    // the words of pairs (a, b) and (b, a), b >= a
+    auto emit = [&](int32_t a, const float (&xa)[32], int32_t b, const float (&xb)[32]) {
         uint32_t ge = 0, le = 0;  // x_b >= x_a, x_a >= x_b
 #pragma unroll
         for (int i = 0; i < 32; ++i) {
@@ -141,6 +145,16 @@ __global__ void __launch_bounds__(64) k_pair_bits(const float *__restrict__ X, i
                 }
             }
         }
+    };
+    float xa[A][32];
+#pragma unroll
+    for (int j = 0; j < A; ++j) load32(min(a0 + j, cols - 1), xa[j]);
+    for (int32_t b = a0; b < cols; ++b) {
+        float xb[32];
+        load32(b, xb);
+#pragma unroll
+        for (int j = 0; j < A; ++j)
+            if (b >= a0 + j) emit(a0 + j, xa[j], b, xb);
     }
 }
 
@@ -450,10 +464,17 @@ hipError_t launch_pair_bits(const float *X, int64_t rows, int64_t ld, int32_t co
 {
     if (cols < 1 || cols > kMaxPairCols || w32 != pair_words(rows) || ld % 64 != 0) return hipErrorInvalidValue;
     const int64_t chunks = w32 / kChunkWords;
-    if (chunks > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t per_slice = (chunks + 7) / 8;
+    if (per_slice > 65535) return hipErrorInvalidValue;
+    // Four columns per block past 128 columns (the loads of each b shared
+    // four ways), two below, where fewer blocks per chunk would be left.
+    const bool four = cols > 128;
+    const int A = four ? 4 : 2;
+    const dim3 grid((unsigned)(8 * ((cols + A - 1) / A)), (unsigned)per_slice);
+    const int sub = subst ? 1 : 0;
     clear_last_error();
-    hipLaunchKernelGGL(k_pair_bits, dim3((unsigned)chunks, (unsigned)cols), dim3(64), 0, s, X, rows, ld, cols,
-                       subst ? 1 : 0, fill, G, T);
+    if (four) hipLaunchKernelGGL(k_pair_bits<4>, grid, dim3(64), 0, s, X, rows, ld, cols, sub, fill, G, T);
+    else hipLaunchKernelGGL(k_pair_bits<2>, grid, dim3(64), 0, s, X, rows, ld, cols, sub, fill, G, T);
     return hipGetLastError();
 }
 
