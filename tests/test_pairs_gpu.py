@@ -3,8 +3,9 @@ columns, built on first use) against the oracle, bit-exact, through the C
 ABI: special values (signed zeros, infinities, NaN, ties), both missing-value
 modes with and without negative trends and masks, one-column, repeated-column
 and invalid individuals, individuals longer than the header's window, row
-counts around the 32-row words and 2,048-row chunks, widths past the codes'
-limits, several launch shapes, the methylation workloads at full size, the
+counts around the 32-row words and 2,048-row chunks, widths around the
+bitmap build's column blocking and past the codes' limits, several launch
+shapes, the methylation workloads at full size, the
 fallbacks (too many columns, the allocation-free entry point before the
 bitmaps exist), and batches: requests on several matrices and in both modes
 on the batched pairs kernel beside requests on the tiled one."""
@@ -151,6 +152,34 @@ def test_pairs_edge_rows(ctx, rows):
                 got = gpu_eval(ctx, mat, offs, cc, include=include, negative=negative, masks=True)
                 want = oracle_eval(X, offs, cc, include=include, negative=negative, masks=True, fill=1.5)
                 assert_same(got, want, f"rows={rows} include={include} negative={negative}")
+    finally:
+        ctx.set_launch_shape()
+        ctx.release(mat)
+
+
+@pytest.mark.parametrize("cols", [1, 2, 3, 129, 131])
+def test_pairs_build_widths(ctx, cols):
+    """Widths around the bitmap build's column blocking (two columns of a
+    chunk per block up to 128 columns, four past that): the last block of
+    a chunk holds fewer columns. The rows span nine chunks, one past a
+    multiple of eight, so most of the build grid's second row of blocks has
+    no chunk."""
+    from paper_1807_09932_amd import ebic
+    rows = 8 * 2048 + 77
+    X = _special(rows, cols, 1000 + cols)
+    rng = np.random.default_rng(cols + 11)
+    offs, cc = _pop(rng, cols, 60, kmax=min(30, 2 * cols))
+    mat = ctx.upload(X, fill=0.5)
+    try:
+        ctx.set_launch_shape(1, 4, 16, ebic.STAGE_PAIRS, 0)
+        for include in (False, True):
+            for negative in (True, False):
+                announce("pairs build widths", cols, include, negative)
+                got = gpu_eval(ctx, mat, offs, cc, include=include, negative=negative, masks=True)
+                want = oracle_eval(X, offs, cc, include=include, negative=negative, masks=True, fill=0.5)
+                assert_same(got, want, f"build widths cols={cols} include={include} negative={negative}")
+        st = ctx.stats(mat)
+        assert st["code_sets"] & ebic.SET_PAIRS and st["code_sets"] & ebic.SET_PAIRS_FILL, st
     finally:
         ctx.set_launch_shape()
         ctx.release(mat)
